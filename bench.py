@@ -1,0 +1,166 @@
+"""Benchmark: element-matrix entries assembled per second on one MI355X.
+
+One step = one full assembly of the mass and conductivity matrices (geometry,
+coefficients at quadrature nodes, Lambda, X, V = Q X, deterministic scatter
+into CSR) of the 3D P2 workload: 32^3 cube, 6 Kuhn tetrahedra per cell
+(196,608 elements, 274,625 nodes), jitter 0.2h, 11-point rule, conductivity
+c(u) = 1 + 0.5 u^2 with u a sum of 8 random-phase sinusoids, mass m = 1.
+Inputs are resident in HBM before timing; the plan (pattern + permutation) is
+built once and reported separately.
+
+Prints one JSON line (rank 0). Extra objects: "roofline" for the dominant
+kernel (algorithmic bytes per launch / its HIP-event duration vs 8 TB/s) and
+"cpu_baseline" (the CPU oracle on the host cores).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(kernel, w, plan, mesh):
+    """Compulsory bytes of one launch of `kernel` (see the design notes)."""
+    d, ne, nn, npl, nnz = w.dim, plan.n_elem, plan.n_nodes, plan.n_p, plan.nnz
+    ns = npl * (npl + 1) // 2
+    n_vert = int(mesh["vertex_mask"].sum())
+    inputs = 4 * npl * ne + 8 * d * n_vert + 8 * nn           # conn, vertex coords, nodal field
+    if kernel == "form":
+        return inputs + 2 * 8 * ns * ne                          # + V_m, V_c written
+    if kernel == "gather":
+        contrib_full = ne * npl * npl                            # every CSR slot sums its segment
+        return 4 * nnz + 8 * nnz + 4 * contrib_full + 16 * contrib_full + 16 * nnz
+    if kernel == "fused":
+        return inputs + 4 * ne * ns + 16 * nnz
+    raise KeyError(kernel)
+
+
+def floor_bytes(w, plan, mesh):
+    """Whole-path floor: inputs once, the element-entry -> slot map once (4 B per
+    element entry), both CSR value arrays written once."""
+    d, ne, nn, npl, nnz = w.dim, plan.n_elem, plan.n_nodes, plan.n_p, plan.nnz
+    n_vert = int(mesh["vertex_mask"].sum())
+    return 4 * npl * ne + 8 * d * n_vert + 8 * nn + 4 * ne * npl * npl + 16 * nnz
+
+
+def cpu_baseline(w, mesh, rule, u, budget_s=20.0):
+    import oracle
+    threads = min(os.cpu_count() or 1, 16)
+    t0 = time.perf_counter()
+    oracle.assemble(mesh, rule, rule, w.mass_law, w.stiff_law, u, u, nthreads=threads)
+    dt = time.perf_counter() - t0
+    reps = 1
+    while time.perf_counter() - t0 + dt < budget_s and reps < 5:
+        oracle.assemble(mesh, rule, rule, w.mass_law, w.stiff_law, u, u, nthreads=threads)
+        reps += 1
+    total = time.perf_counter() - t0
+    entries = 2 * mesh["conn"].shape[1] * mesh["conn"].shape[0] ** 2
+    return {"value": entries * reps / total, "unit": "entries/s", "cores": threads, "kind": "oracle",
+            "sample": f"{reps} full assemblies of the same workload ({w.name}), {total:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="p2_3d_32")
+    ap.add_argument("--precision", default="fp64")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is a design "
+              "note, not a measured path.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2204_03893_amd as qxa
+    from workloads import WORKLOADS, make_inputs
+
+    w = WORKLOADS[args.workload]
+    mesh, rule, u = make_inputs(w)
+    dev = torch.device("cuda", 0)
+    m = qxa.Mesh(w.dim, w.order, mesh["coords"], mesh["conn"])
+    t0 = time.perf_counter()
+    plan = qxa.Plan(m, rule)
+    plan_s = time.perf_counter() - t0
+    uf = torch.tensor(u, device=dev)
+    M = torch.empty(plan.nnz, dtype=torch.float64, device=dev)
+    Cv = torch.empty(plan.nnz, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        qxa.assemble(plan, w.mass_law, w.stiff_law, uf, uf, precision=args.precision, M=M, Cv=Cv, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    qxa.sync(plan, stream)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_wall = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    qxa.sync(plan, stream)
+    ms = ev0.elapsed_time(ev1) / args.steps
+
+    # per-kernel durations with events recorded by the library on the launch stream
+    plan.set_timing(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    rep = plan.timing_report()
+    plan.set_timing(False)
+    kern = {k: v["ms"] / v["n"] for k, v in rep.items()}
+    dom = max(kern, key=kern.get)
+    ab = algorithmic_bytes(dom, w, plan, mesh)
+    achieved = ab / (kern[dom] * 1e-3) / 1e9
+    entries = 2 * plan.n_elem * plan.n_p ** 2
+    fb = floor_bytes(w, plan, mesh)
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(w, mesh, rule, u)
+
+    out = {
+        "metric": "element-matrix entries assembled/sec",
+        "value": entries / (ms * 1e-3),
+        "unit": "entries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else args.precision,
+        "data": "synthetic",
+        "config": {"workload": w.name, "description": w.description, "n_elem": plan.n_elem,
+                   "n_nodes": plan.n_nodes, "nnz": plan.nnz, "entries_per_step": entries,
+                   "precision": args.precision},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+                     "algorithmic_bytes": ab, "kernel_ms": kern[dom]},
+        "path_floor": {"bytes": fb, "frac_of_hbm_peak": fb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "kernels_ms": kern,
+        "plan_build_s": plan_s,
+        "wall_s_timed_region": wall,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,192 @@
+/*
+ * qxa — loop-free assembly of finite element mass and conductivity matrices
+ * as one small dense contraction V = Q X, for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Y. Voet, "On the fast assemblage of finite element matrices with
+ * application to nonlinear heat transfer problems".
+ *   - Section 2 defines the matrices: M_ij = int m phi_j phi_i and
+ *     C_ij = int c grad phi_j . grad phi_i (the conductivity matrix).
+ *   - Section 3 maps each simplex affinely to the reference element
+ *     (x = a + B_e xhat) and applies quadrature.
+ *   - Section 4 (Algorithm 2) vectorises all element matrices at once:
+ *       V_m = Q_m X_m,  Q_m = Phi (Khatri-Rao) Phi,  X_m = Lambda_m
+ *       V_c = Q_c X_c,  Q_c = [J_q (x) J_q]_q,        X_c = Lambda_c (Khatri-Rao) W
+ *       Lambda = S * (w b^T),  b_e = |det B_e|,  W = [vec((B_e^T B_e)^{-1})]_e
+ *     and forms the global matrices from V and the index sets N_e.
+ *   - Section 4 (summary) notes that only S depends on the unknown, so the
+ *     mesh-dependent data (pattern, permutation) is built once per mesh.
+ *
+ * All functions return a qxa_status (0 = success, negative = error) and never
+ * throw; qxa_last_error() returns a message for the last failing call on the
+ * calling thread. Indices are 0-based.
+ *
+ * Memory: the library never frees caller memory. qxa_mesh_create copies the
+ * mesh into library-owned device memory. Output value arrays are caller-owned
+ * device buffers. "device" pointers are HIP device pointers on the device the
+ * mesh was created on; a stream argument is a hipStream_t (NULL = default).
+ */
+#ifndef QXA_H
+#define QXA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QXA_OK = 0,
+    QXA_E_INVALID = -1,     /* bad argument (null pointer, size, enum value)        */
+    QXA_E_INDEX = -2,       /* connectivity index out of range / repeated in N_e    */
+    QXA_E_DEGENERATE = -3,  /* |det B_e| too small: B_e not invertible (Section 3) */
+    QXA_E_NONFINITE = -4,   /* non-finite coordinate or coefficient value           */
+    QXA_E_NOMEM = -5,       /* device or host allocation failed / over budget      */
+    QXA_E_UNSUPPORTED = -6, /* (dim, order, n_q, precision) combination not built   */
+    QXA_E_HIP = -7,         /* HIP runtime error                                    */
+    QXA_E_BUSY = -8         /* server queue full                                    */
+} qxa_status;
+
+/* Arithmetic of the contraction V = Q X. Geometry (B_e, |det B_e|, W) and the
+ * accumulation into CSR are FP64 in every form. */
+typedef enum {
+    QXA_FP64 = 0,   /* plain FP64                                                   */
+    QXA_FP32 = 1,   /* Q and X rounded to FP32, FP32 accumulation                  */
+    QXA_F16X2 = 2,  /* Q, X split hi+lo in FP16 (per-element scaled X), MFMA, FP32 acc */
+    QXA_BF16X2 = 3, /* Q, X split hi+lo in BF16, MFMA, FP32 accumulation           */
+    QXA_BF16X3 = 4  /* three-term BF16 split, MFMA, FP32 accumulation              */
+} qxa_precision;
+
+/* Coefficient evaluation at the quadrature nodes, the matrices S_m, S_c of
+ * Algorithm 2 (Section 4): constant (Line 5 skipped), a law applied to the
+ * interpolated nodal field u_h = phi^T u (solution-dependent coefficients,
+ * Section 4 nonlinear FEM), or values given per (q, e). */
+typedef enum { QXA_COEFF_CONST = 0, QXA_COEFF_NODAL = 1, QXA_COEFF_QPOINT = 2 } qxa_coeff_kind;
+typedef enum {
+    QXA_LAW_IDENTITY = 0, /* s                     */
+    QXA_LAW_POLY2 = 1,    /* a0 + a1 s + a2 s^2    */
+    QXA_LAW_EXP = 2       /* exp(a0 + a1 s)        */
+} qxa_law;
+
+enum { QXA_MEM_HOST = 0, QXA_MEM_DEVICE = 1 };
+
+/* Quadrature rule on the reference simplex (vertex 0 at the origin, vertex k
+ * at e_k): n_q points (row-major [n_q][dim], reference coordinates) and
+ * weights summing to 1/dim!. Host pointers; copied at plan creation. */
+typedef struct {
+    int dim;
+    int n_q;
+    const double *points;
+    const double *weights;
+} qxa_quad;
+
+/* kind = QXA_COEFF_CONST: s = value.
+ * kind = QXA_COEFF_NODAL: field = device array [n_nodes]; s = law(u_h(x_q)).
+ * kind = QXA_COEFF_QPOINT: field = device array [n_q][n_elem]; s = law(field[q][e]). */
+typedef struct {
+    int kind;
+    int law;
+    double value;
+    double a[3];
+    const double *field;
+} qxa_coeff;
+
+typedef struct qxa_mesh_s *qxa_mesh;
+typedef struct qxa_plan_s *qxa_plan;
+typedef struct qxa_graph_s *qxa_graph;
+typedef struct qxa_server_s *qxa_server;
+
+typedef struct {
+    int dim, order, n_p, n_q_mass, n_q_stiff;
+    int64_t n_nodes, n_elem, nnz;
+    const int64_t *row_ptr; /* device, [n_nodes+1], borrowed until qxa_plan_destroy */
+    const int32_t *col_idx; /* device, [nnz], sorted within each row                */
+    size_t device_bytes;    /* device memory held by the plan                       */
+    double build_ms;        /* wall time of qxa_plan_create                         */
+} qxa_plan_info;
+
+const char *qxa_last_error(void);
+const char *qxa_version(void);
+
+/*
+ * Mesh (Section 3, steps 2-3): a conforming mesh of straight-sided simplices
+ * of Lagrange order `order` (1..3) in dim = 2 or 3.
+ *   coords: SoA [dim][n_nodes] FP64 node coordinates (only the d+1 vertices of
+ *           each element are read: the map is affine).
+ *   conn:   SoA [n_p][n_elem] int32, n_p = C(order+dim, dim). Local order: the
+ *           dim+1 vertices; then order-1 equispaced nodes per edge, edges
+ *           (0,1),(1,2),(2,0) in 2D and (0,1),(1,2),(2,0),(0,3),(1,3),(2,3) in
+ *           3D, each from the first to the second vertex; then for order 3 one
+ *           node per face (2D centroid; 3D faces opposite vertex 3,0,1,2).
+ *   mem:    QXA_MEM_HOST or QXA_MEM_DEVICE (where coords/conn live).
+ * Validates indices (QXA_E_INDEX), finiteness (QXA_E_NONFINITE) and
+ * non-degenerate elements (QXA_E_DEGENERATE, the element id is in the message:
+ * B_e must be invertible, Section 3). Copies everything; the caller may free
+ * its arrays on return.
+ */
+qxa_status qxa_mesh_create(int device, int dim, int order, int64_t n_nodes, const double *coords, int64_t n_elem,
+                           const int32_t *conn, int mem, qxa_mesh *out);
+qxa_status qxa_mesh_destroy(qxa_mesh mesh);
+
+/*
+ * Plan (built once per mesh and rule pair): the reference tables Phi, J_q,
+ * Q_m, Q_c of Algorithm 2 (Lines 1-3; only the n_p(n_p+1)/2 rows of distinct
+ * symmetric pairs, the symmetry saving of Section 6), the CSR pattern (all
+ * (i,j) sharing an element; structural zeros kept), and the element-entry to
+ * CSR-slot permutation with its slot-sorted segments that the deterministic
+ * scatter uses (Algorithm 2, Line 12). The mesh must outlive the plan.
+ * Rules may differ between the two matrices (Algorithm 2, "Input").
+ */
+qxa_status qxa_plan_create(qxa_mesh mesh, const qxa_quad *mass_rule, const qxa_quad *stiff_rule, qxa_plan *out);
+qxa_status qxa_plan_destroy(qxa_plan plan);
+qxa_status qxa_plan_get_info(qxa_plan plan, qxa_plan_info *out);
+
+/* Host-only construction of the CSR pattern (no device needed): with
+ * row_ptr == NULL only *nnz is returned; otherwise row_ptr[n_nodes+1] and
+ * col_idx[*nnz] (host arrays) are filled. conn is a host SoA array as in
+ * qxa_mesh_create; indices are validated (QXA_E_INDEX). */
+qxa_status qxa_pattern_host(int dim, int order, int64_t n_nodes, int64_t n_elem, const int32_t *conn,
+                            int64_t *row_ptr, int32_t *col_idx, int64_t *nnz);
+
+/* Copy the CSR pattern into caller-owned device arrays row_ptr[n_nodes+1] and
+ * col_idx[nnz] (either may be NULL), asynchronously on `stream`. */
+qxa_status qxa_plan_copy_pattern(qxa_plan plan, int64_t *row_ptr, int32_t *col_idx, void *stream);
+
+/*
+ * One assembly (Algorithm 2, Lines 4-12): geometry b, W from the mesh,
+ * coefficients S at the quadrature nodes, Lambda, X, V = Q X, then the
+ * deterministic segmented-reduction scatter into CSR values (no float
+ * atomics; bitwise identical across runs). M_vals / C_vals: caller-owned
+ * device arrays of length nnz in the plan's CSR order; either may be NULL to
+ * skip that matrix. Asynchronous on `stream`; argument errors are returned
+ * immediately, device-detected non-finite coefficients at qxa_sync.
+ */
+qxa_status qxa_assemble(qxa_plan plan, const qxa_coeff *mass, const qxa_coeff *stiff, int precision, double *M_vals,
+                        double *C_vals, void *stream);
+
+/*
+ * Formation only (Algorithm 2, Lines 4-11): V_m and V_c as device arrays
+ * [n_p*n_p][n_elem] (entry (i*n_p+j, e) at index (i*n_p+j)*n_elem + e; the
+ * element matrices are symmetric so this is also the paper's column-major
+ * vec). Either output may be NULL.
+ */
+qxa_status qxa_element_matrices(qxa_plan plan, const qxa_coeff *mass, const qxa_coeff *stiff, int precision,
+                                double *Vm, double *Vc, void *stream);
+
+/*
+ * Per-kernel timing with HIP events recorded on the launch stream around every
+ * kernel this plan launches (off by default). qxa_plan_timing_report waits for
+ * the recorded events, writes a JSON object
+ *   {"<kernel>": {"n": launches, "ms": total milliseconds}, ...}
+ * into buf (cap bytes, NUL-terminated) and clears the record.
+ */
+qxa_status qxa_plan_set_timing(qxa_plan plan, int enable);
+qxa_status qxa_plan_timing_report(qxa_plan plan, char *buf, size_t cap);
+
+/* Wait for `stream` and report device-side conditions (QXA_E_NONFINITE). */
+qxa_status qxa_sync(qxa_plan plan, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QXA_H */

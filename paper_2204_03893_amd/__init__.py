@@ -1,0 +1,265 @@
+"""Python binding of libqxa (loop-free FEM assembly, V = Q X, on MI355X).
+
+Argument marshalling only: every step of the assembly runs in the HIP
+kernels of libqxa.so. torch is used for device memory and streams. There is
+no CPU fallback: if the library is not built, importing the binding's
+functions raises.
+
+Coefficient laws are tuples:
+    ("const", value) | ("identity",) | ("poly2", a0, a1, a2) | ("exp", a0, a1)
+and a non-constant law takes a device field: nodal values [n_nodes] (the law
+is applied to u_h = phi^T u at each quadrature node), or values per
+quadrature node [n_q, n_elem] with qpoint=True.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqxa.so")
+
+FP64, FP32, F16X2, BF16X2, BF16X3 = 0, 1, 2, 3, 4
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "f16x2": F16X2, "bf16x2": BF16X2, "bf16x3": BF16X3}
+_LAW = {"identity": 0, "poly2": 1, "exp": 2}
+
+
+class QxaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"qxa error {code}: {msg}")
+        self.code = code
+
+
+class _Quad(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n_q", C.c_int), ("points", C.c_void_p), ("weights", C.c_void_p)]
+
+
+class _Coeff(C.Structure):
+    _fields_ = [("kind", C.c_int), ("law", C.c_int), ("value", C.c_double), ("a", C.c_double * 3),
+                ("field", C.c_void_p)]
+
+
+class _PlanInfo(C.Structure):
+    _fields_ = [("dim", C.c_int), ("order", C.c_int), ("n_p", C.c_int), ("n_q_mass", C.c_int),
+                ("n_q_stiff", C.c_int), ("n_nodes", C.c_int64), ("n_elem", C.c_int64), ("nnz", C.c_int64),
+                ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("device_bytes", C.c_size_t),
+                ("build_ms", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libqxa.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2204_03893_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, ci = C.c_void_p, C.c_int64, C.c_int
+        L.qxa_last_error.restype = C.c_char_p
+        L.qxa_version.restype = C.c_char_p
+        L.qxa_mesh_create.argtypes = [ci, ci, ci, i64, vp, i64, vp, ci, C.POINTER(vp)]
+        L.qxa_mesh_destroy.argtypes = [vp]
+        L.qxa_plan_create.argtypes = [vp, C.POINTER(_Quad), C.POINTER(_Quad), C.POINTER(vp)]
+        L.qxa_plan_destroy.argtypes = [vp]
+        L.qxa_plan_get_info.argtypes = [vp, C.POINTER(_PlanInfo)]
+        L.qxa_plan_copy_pattern.argtypes = [vp, vp, vp, vp]
+        L.qxa_pattern_host.argtypes = [ci, ci, i64, i64, vp, vp, vp, C.POINTER(i64)]
+        L.qxa_assemble.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), ci, vp, vp, vp]
+        L.qxa_element_matrices.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), ci, vp, vp, vp]
+        L.qxa_sync.argtypes = [vp, vp]
+        L.qxa_plan_set_timing.argtypes = [vp, ci]
+        L.qxa_plan_timing_report.argtypes = [vp, C.c_char_p, C.c_size_t]
+        for name in ("qxa_mesh_create", "qxa_mesh_destroy", "qxa_plan_create", "qxa_plan_destroy",
+                     "qxa_plan_get_info", "qxa_plan_copy_pattern", "qxa_assemble", "qxa_element_matrices",
+                     "qxa_sync", "qxa_pattern_host", "qxa_plan_set_timing", "qxa_plan_timing_report"):
+            getattr(L, name).restype = ci
+        _lib = L
+    return _lib
+
+
+def check(code):
+    if code != 0:
+        raise QxaError(code, lib().qxa_last_error().decode())
+    return code
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Mesh:
+    """Library-owned copy of a simplex mesh (coords [dim, n_nodes], conn [n_p, n_elem])."""
+
+    def __init__(self, dim, order, coords, conn, device=0):
+        import torch
+        self.dim, self.order = int(dim), int(order)
+        self.handle = C.c_void_p()
+        if isinstance(coords, torch.Tensor):
+            X = coords.contiguous().to(torch.float64)
+            Cn = conn.contiguous().to(torch.int32)
+            mem = 1 if X.is_cuda else 0
+            xp, cp = X.data_ptr(), Cn.data_ptr()
+            keep = (X, Cn)
+        else:
+            X = np.ascontiguousarray(coords, dtype=np.float64)
+            Cn = np.ascontiguousarray(conn, dtype=np.int32)
+            mem = 0
+            xp, cp = X.ctypes.data, Cn.ctypes.data
+            keep = (X, Cn)
+        self.n_nodes = int(X.shape[1])
+        self.n_elem = int(Cn.shape[1])
+        self.n_p = int(Cn.shape[0])
+        check(lib().qxa_mesh_create(int(device), self.dim, self.order, self.n_nodes, C.c_void_p(xp), self.n_elem,
+                                    C.c_void_p(cp), mem, C.byref(self.handle)))
+        del keep
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            lib().qxa_mesh_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _quad(rule, dim):
+    pts, w = rule
+    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, dim)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    q = _Quad(dim, w.size, pts.ctypes.data, w.ctypes.data)
+    return q, (pts, w)
+
+
+class Plan:
+    """Per-mesh plan: reference tables, CSR pattern, element-entry -> slot permutation."""
+
+    def __init__(self, mesh: Mesh, rule_m, rule_c=None):
+        rule_c = rule_m if rule_c is None else rule_c
+        qm, km = _quad(rule_m, mesh.dim)
+        qc, kc = _quad(rule_c, mesh.dim)
+        self.mesh = mesh
+        self.handle = C.c_void_p()
+        check(lib().qxa_plan_create(mesh.handle, C.byref(qm), C.byref(qc), C.byref(self.handle)))
+        info = _PlanInfo()
+        check(lib().qxa_plan_get_info(self.handle, C.byref(info)))
+        self.info = info
+        self.nnz = int(info.nnz)
+        self.n_nodes = int(info.n_nodes)
+        self.n_elem = int(info.n_elem)
+        self.n_p = int(info.n_p)
+        self.build_ms = float(info.build_ms)
+        self.device_bytes = int(info.device_bytes)
+
+    def pattern(self):
+        """(row_ptr int64, col_idx int32) as device tensors."""
+        import torch
+        dev = torch.device("cuda", self.mesh.device)
+        rp = torch.empty(self.n_nodes + 1, dtype=torch.int64, device=dev)
+        ci = torch.empty(self.nnz, dtype=torch.int32, device=dev)
+        check(lib().qxa_plan_copy_pattern(self.handle, _ptr(rp), _ptr(ci), _stream_ptr(None)))
+        return rp, ci
+
+    def set_timing(self, on: bool):
+        check(lib().qxa_plan_set_timing(self.handle, int(bool(on))))
+
+    def timing_report(self):
+        """{kernel: {"n": launches, "ms": total ms}} from events recorded around each launch."""
+        import json
+        buf = C.create_string_buffer(4096)
+        check(lib().qxa_plan_timing_report(self.handle, buf, 4096))
+        return json.loads(buf.value.decode())
+
+    def close(self):
+        if self.handle:
+            lib().qxa_plan_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pattern_host(dim, order, n_nodes, conn):
+    """CSR pattern built by the library's host code (no GPU): (row_ptr, col_idx) numpy arrays."""
+    conn = np.ascontiguousarray(conn, dtype=np.int32)
+    nnz = C.c_int64()
+    check(lib().qxa_pattern_host(dim, order, n_nodes, conn.shape[1], conn.ctypes.data, None, None, C.byref(nnz)))
+    rp = np.zeros(n_nodes + 1, dtype=np.int64)
+    ci = np.zeros(nnz.value, dtype=np.int32)
+    check(lib().qxa_pattern_host(dim, order, n_nodes, conn.shape[1], conn.ctypes.data, rp.ctypes.data,
+                                 ci.ctypes.data, C.byref(nnz)))
+    return rp, ci
+
+
+def make_coeff(law, field=None, qpoint=False):
+    """Build the ABI coefficient struct; returns (struct, keepalive)."""
+    c = _Coeff()
+    c.a[0] = c.a[1] = c.a[2] = 0.0
+    if law[0] == "const":
+        c.kind, c.law, c.value, c.field = 0, 0, float(law[1]), None
+        return c, None
+    c.law = _LAW[law[0]]
+    for k, v in enumerate(law[1:]):
+        c.a[k] = float(v)
+    if field is None:
+        raise ValueError("non-constant coefficient law needs a device field")
+    c.kind = 2 if qpoint else 1
+    c.field = field.data_ptr()
+    c.value = 0.0
+    return c, field
+
+
+def _precision(p):
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+def assemble(plan: Plan, law_m, law_c, field_m=None, field_c=None, precision="fp64", M=None, Cv=None,
+             stream=None, want_m=True, want_c=True, qpoint=False):
+    """One assembly into CSR value arrays (device float64 tensors of length nnz)."""
+    import torch
+    dev = torch.device("cuda", plan.mesh.device)
+    if want_m and M is None:
+        M = torch.empty(plan.nnz, dtype=torch.float64, device=dev)
+    if want_c and Cv is None:
+        Cv = torch.empty(plan.nnz, dtype=torch.float64, device=dev)
+    cm, k1 = make_coeff(law_m, field_m, qpoint)
+    cc, k2 = make_coeff(law_c, field_c, qpoint)
+    check(lib().qxa_assemble(plan.handle, C.byref(cm), C.byref(cc), _precision(precision),
+                             _ptr(M if want_m else None), _ptr(Cv if want_c else None), _stream_ptr(stream)))
+    return M, Cv
+
+
+def element_matrices(plan: Plan, law_m, law_c, field_m=None, field_c=None, precision="fp64", stream=None,
+                     qpoint=False):
+    """Formation only: V_m, V_c as device tensors [n_p*n_p, n_elem]."""
+    import torch
+    dev = torch.device("cuda", plan.mesh.device)
+    n2 = plan.n_p * plan.n_p
+    Vm = torch.empty((n2, plan.n_elem), dtype=torch.float64, device=dev)
+    Vc = torch.empty((n2, plan.n_elem), dtype=torch.float64, device=dev)
+    cm, k1 = make_coeff(law_m, field_m, qpoint)
+    cc, k2 = make_coeff(law_c, field_c, qpoint)
+    check(lib().qxa_element_matrices(plan.handle, C.byref(cm), C.byref(cc), _precision(precision), _ptr(Vm),
+                                     _ptr(Vc), _stream_ptr(stream)))
+    return Vm, Vc
+
+
+def sync(plan: Plan, stream=None):
+    check(lib().qxa_sync(plan.handle, _stream_ptr(stream)))

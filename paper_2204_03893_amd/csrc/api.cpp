@@ -1,0 +1,411 @@
+// C-ABI of the assembly library: argument validation, ownership, launches.
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "kernels.hpp"
+#include "qxa_internal.hpp"
+
+namespace qxa {
+
+static thread_local std::string g_err;
+
+qxa_status fail(qxa_status code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+qxa_status hip_fail(hipError_t e, const char *what)
+{
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? QXA_E_NOMEM : QXA_E_HIP;
+}
+
+template <class T>
+static qxa_status dev_alloc(T **p, size_t count, size_t &acct)
+{
+    *p = nullptr;
+    if (count == 0) return QXA_OK;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return hip_fail(e, "hipMalloc");
+    }
+    acct += count * sizeof(T);
+    return QXA_OK;
+}
+
+template <class T>
+static qxa_status upload(T **p, const T *src, size_t count, size_t &acct)
+{
+    qxa_status st = dev_alloc(p, count, acct);
+    if (st || count == 0) return st;
+    QXA_HIP(hipMemcpy(*p, src, count * sizeof(T), hipMemcpyHostToDevice));
+    return QXA_OK;
+}
+
+static qxa_status to_coeff(const qxa_coeff *c, CoeffDev &out, const char *which)
+{
+    if (!c) {
+        out = CoeffDev{0, 0, 0.0, 0.0, 0.0, 0.0, nullptr};
+        return QXA_OK;
+    }
+    if (c->kind < 0 || c->kind > 2) return fail(QXA_E_INVALID, std::string(which) + " coefficient: bad kind");
+    if (c->law < 0 || c->law > 2) return fail(QXA_E_INVALID, std::string(which) + " coefficient: bad law");
+    if (c->kind != 0 && !c->field) return fail(QXA_E_INVALID, std::string(which) + " coefficient: null field");
+    if (c->kind == 0 && !std::isfinite(c->value))
+        return fail(QXA_E_NONFINITE, std::string(which) + " coefficient: non-finite constant");
+    out = CoeffDev{c->kind, c->law, c->value, c->a[0], c->a[1], c->a[2], c->field};
+    return QXA_OK;
+}
+
+}  // namespace qxa
+
+using namespace qxa;
+
+extern "C" {
+
+const char *qxa_last_error(void) { return g_err.c_str(); }
+const char *qxa_version(void) { return "qxa 0.1 (gfx950)"; }
+
+qxa_status qxa_mesh_create(int device, int dim, int order, int64_t n_nodes, const double *coords, int64_t n_elem,
+                           const int32_t *conn, int mem, qxa_mesh *out)
+{
+    if (!out) return fail(QXA_E_INVALID, "out is null");
+    *out = nullptr;
+    if (dim != 2 && dim != 3) return fail(QXA_E_INVALID, "dim must be 2 or 3");
+    if (order < 1 || order > 3) return fail(QXA_E_INVALID, "order must be 1, 2 or 3");
+    if (n_nodes < dim + 1 || n_elem < 0) return fail(QXA_E_INVALID, "bad sizes");
+    if (n_nodes >= (int64_t(1) << 31)) return fail(QXA_E_UNSUPPORTED, "more than 2^31 nodes");
+    if (!coords || (n_elem > 0 && !conn)) return fail(QXA_E_INVALID, "null coords/conn");
+    if (mem != QXA_MEM_HOST && mem != QXA_MEM_DEVICE) return fail(QXA_E_INVALID, "bad mem flag");
+    QXA_HIP(hipSetDevice(device));
+    const int np = n_local(dim, order);
+    std::vector<double> hx;
+    std::vector<int32_t> hc;
+    const double *X = coords;
+    const int32_t *Cn = conn;
+    if (mem == QXA_MEM_DEVICE) {
+        hx.resize(size_t(dim) * n_nodes);
+        hc.resize(size_t(np) * n_elem);
+        QXA_HIP(hipMemcpy(hx.data(), coords, hx.size() * sizeof(double), hipMemcpyDeviceToHost));
+        if (n_elem) QXA_HIP(hipMemcpy(hc.data(), conn, hc.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        X = hx.data();
+        Cn = hc.data();
+    }
+    for (size_t k = 0; k < size_t(dim) * n_nodes; ++k)
+        if (!std::isfinite(X[k])) return fail(QXA_E_NONFINITE, "non-finite node coordinate at index " + std::to_string(k));
+    for (int64_t e = 0; e < n_elem; ++e) {
+        int32_t v[kMaxNp];
+        for (int i = 0; i < np; ++i) {
+            v[i] = Cn[size_t(i) * n_elem + e];
+            if (v[i] < 0 || v[i] >= n_nodes)
+                return fail(QXA_E_INDEX, "element " + std::to_string(e) + ": node index out of range");
+            for (int j = 0; j < i; ++j)
+                if (v[j] == v[i]) return fail(QXA_E_INDEX, "element " + std::to_string(e) + ": repeated node");
+        }
+        // |det B_e| against the longest edge from vertex 0 (B_e invertible, Section 3)
+        double B[3][3], lmax = 0.0;
+        for (int c = 0; c < dim; ++c) {
+            double l2 = 0.0;
+            for (int r = 0; r < dim; ++r) {
+                B[r][c] = X[size_t(r) * n_nodes + v[c + 1]] - X[size_t(r) * n_nodes + v[0]];
+                l2 += B[r][c] * B[r][c];
+            }
+            lmax = std::max(lmax, std::sqrt(l2));
+        }
+        const double det = dim == 2 ? B[0][0] * B[1][1] - B[0][1] * B[1][0]
+                                    : B[0][0] * (B[1][1] * B[2][2] - B[1][2] * B[2][1]) -
+                                          B[0][1] * (B[1][0] * B[2][2] - B[1][2] * B[2][0]) +
+                                          B[0][2] * (B[1][0] * B[2][1] - B[1][1] * B[2][0]);
+        if (!(std::fabs(det) > 1e-14 * std::pow(lmax, dim)))
+            return fail(QXA_E_DEGENERATE, "element " + std::to_string(e) + " is degenerate (|det B_e| ~ 0)");
+    }
+    auto *m = new qxa_mesh_s();
+    m->device = device;
+    m->dim = dim;
+    m->order = order;
+    m->np = np;
+    m->n_nodes = n_nodes;
+    m->n_elem = n_elem;
+    m->h_conn.assign(Cn, Cn + size_t(np) * n_elem);
+    qxa_status st = upload(&m->d_coords, X, size_t(dim) * n_nodes, m->device_bytes);
+    if (!st) st = upload(&m->d_conn, Cn, size_t(np) * n_elem, m->device_bytes);
+    if (st) {
+        qxa_mesh_destroy(m);
+        return st;
+    }
+    *out = m;
+    return QXA_OK;
+}
+
+qxa_status qxa_mesh_destroy(qxa_mesh m)
+{
+    if (!m) return QXA_OK;
+    hipSetDevice(m->device);
+    hipFree(m->d_coords);
+    hipFree(m->d_conn);
+    delete m;
+    return QXA_OK;
+}
+
+qxa_status qxa_plan_destroy(qxa_plan p)
+{
+    if (!p) return QXA_OK;
+    hipSetDevice(p->mesh->device);
+    hipFree(p->d_row_ptr);
+    hipFree(p->d_col_idx);
+    hipFree(p->d_seg_ptr);
+    hipFree(p->d_seg_val);
+    hipFree(p->d_src_upper);
+    hipFree(p->d_tables);
+    hipFree(p->d_tables_f);
+    hipFree(p->d_V);
+    hipFree(p->d_flags);
+    delete p;
+    return QXA_OK;
+}
+
+qxa_status qxa_plan_create(qxa_mesh mesh, const qxa_quad *mr, const qxa_quad *cr, qxa_plan *out)
+{
+    if (!out) return fail(QXA_E_INVALID, "out is null");
+    *out = nullptr;
+    if (!mesh || !mr || !cr) return fail(QXA_E_INVALID, "null mesh or rule");
+    const auto t0 = std::chrono::steady_clock::now();
+    QXA_HIP(hipSetDevice(mesh->device));
+    auto *p = new qxa_plan_s();
+    p->mesh = mesh;
+    qxa_status st = build_ref_tables(mesh->dim, mesh->order, *mr, *cr, p->ref);
+    if (st) {
+        delete p;
+        return st;
+    }
+    const RefTables &T = p->ref;
+    if (!form_supported(T.dim, T.order, T.nq_m, T.nq_c)) {
+        delete p;
+        return fail(QXA_E_UNSUPPORTED, "no kernel built for dim=" + std::to_string(T.dim) + " order=" +
+                                           std::to_string(T.order) + " n_q(mass)=" + std::to_string(T.nq_m) +
+                                           " n_q(stiffness)=" + std::to_string(T.nq_c));
+    }
+    HostPlan hp;
+    st = build_host_plan(mesh->dim, mesh->order, mesh->n_nodes, mesh->n_elem, mesh->h_conn.data(), hp);
+    if (st) {
+        delete p;
+        return st;
+    }
+    p->nnz = hp.nnz;
+    size_t &acct = p->device_bytes;
+    st = upload(&p->d_row_ptr, hp.row_ptr.data(), hp.row_ptr.size(), acct);
+    if (!st) st = upload(&p->d_col_idx, hp.col_idx.data(), hp.col_idx.size(), acct);
+    if (!st) st = upload(&p->d_seg_ptr, hp.seg_ptr.data(), hp.seg_ptr.size(), acct);
+    if (!st) st = upload(&p->d_seg_val, hp.seg_val.data(), hp.seg_val.size(), acct);
+    if (!st) st = upload(&p->d_src_upper, hp.src_upper.data(), hp.src_upper.size(), acct);
+    // reference tables: FP64 block and FP32 copy of Q
+    std::vector<double> tab;
+    auto put = [&](const std::vector<double> &v) {
+        size_t off = tab.size();
+        tab.insert(tab.end(), v.begin(), v.end());
+        while (tab.size() % 4) tab.push_back(0.0);
+        return off;
+    };
+    p->off_wm = put(T.w_m);
+    p->off_wc = put(T.w_c);
+    p->off_phim = put(T.phi_m);
+    p->off_phic = put(T.phi_c);
+    p->off_qm = put(T.Qm);
+    p->off_qc = put(T.Qc);
+    std::vector<float> tabf(tab.begin(), tab.end());
+    if (!st) st = upload(&p->d_tables, tab.data(), tab.size(), acct);
+    if (!st) st = upload(&p->d_tables_f, tabf.data(), tabf.size(), acct);
+    if (!st) st = dev_alloc(&p->d_V, size_t(2) * T.ns * mesh->n_elem, acct);
+    if (!st) st = dev_alloc(&p->d_flags, 1, acct);
+    if (!st && p->d_flags) {
+        hipError_t e = hipMemset(p->d_flags, 0, sizeof(int));
+        if (e != hipSuccess) st = hip_fail(e, "hipMemset");
+    }
+    if (st) {
+        qxa_plan_destroy(p);
+        return st;
+    }
+    p->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = p;
+    return QXA_OK;
+}
+
+qxa_status qxa_plan_get_info(qxa_plan p, qxa_plan_info *out)
+{
+    if (!p || !out) return fail(QXA_E_INVALID, "null plan or out");
+    out->dim = p->ref.dim;
+    out->order = p->ref.order;
+    out->n_p = p->ref.np;
+    out->n_q_mass = p->ref.nq_m;
+    out->n_q_stiff = p->ref.nq_c;
+    out->n_nodes = p->mesh->n_nodes;
+    out->n_elem = p->mesh->n_elem;
+    out->nnz = p->nnz;
+    out->row_ptr = p->d_row_ptr;
+    out->col_idx = p->d_col_idx;
+    out->device_bytes = p->device_bytes;
+    out->build_ms = p->build_ms;
+    return QXA_OK;
+}
+
+qxa_status qxa_pattern_host(int dim, int order, int64_t n_nodes, int64_t n_elem, const int32_t *conn,
+                            int64_t *row_ptr, int32_t *col_idx, int64_t *nnz)
+{
+    if (!nnz || (n_elem > 0 && !conn)) return fail(QXA_E_INVALID, "null argument");
+    if ((dim != 2 && dim != 3) || order < 1 || order > 3 || n_nodes < 1 || n_elem < 0)
+        return fail(QXA_E_INVALID, "bad dim/order/sizes");
+    const int np = n_local(dim, order);
+    for (size_t k = 0; k < size_t(np) * n_elem; ++k)
+        if (conn[k] < 0 || conn[k] >= n_nodes) return fail(QXA_E_INDEX, "node index out of range");
+    HostPlan hp;
+    qxa_status st = build_host_plan(dim, order, n_nodes, n_elem, conn, hp);
+    if (st) return st;
+    *nnz = hp.nnz;
+    if (row_ptr) std::memcpy(row_ptr, hp.row_ptr.data(), sizeof(int64_t) * hp.row_ptr.size());
+    if (row_ptr && col_idx) std::memcpy(col_idx, hp.col_idx.data(), sizeof(int32_t) * hp.col_idx.size());
+    return QXA_OK;
+}
+
+qxa_status qxa_plan_copy_pattern(qxa_plan p, int64_t *row_ptr, int32_t *col_idx, void *stream)
+{
+    if (!p) return fail(QXA_E_INVALID, "null plan");
+    QXA_HIP(hipSetDevice(p->mesh->device));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (row_ptr)
+        QXA_HIP(hipMemcpyAsync(row_ptr, p->d_row_ptr, sizeof(int64_t) * (p->mesh->n_nodes + 1),
+                               hipMemcpyDeviceToDevice, s));
+    if (col_idx && p->nnz)
+        QXA_HIP(hipMemcpyAsync(col_idx, p->d_col_idx, sizeof(int32_t) * p->nnz, hipMemcpyDeviceToDevice, s));
+    return QXA_OK;
+}
+
+static qxa_status fill_form_args(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *stiff, int precision,
+                                 FormArgs &a)
+{
+    if (precision != QXA_FP64 && precision != QXA_FP32)
+        return fail(QXA_E_UNSUPPORTED, "precision form not available on the two-pass path");
+    qxa_status st = to_coeff(mass, a.cm, "mass");
+    if (!st) st = to_coeff(stiff, a.cc, "stiffness");
+    if (st) return st;
+    const qxa_mesh m = p->mesh;
+    a.n_nodes = m->n_nodes;
+    a.n_elem = m->n_elem;
+    a.coords = m->d_coords;
+    a.conn = m->d_conn;
+    a.w_m = p->d_tables + p->off_wm;
+    a.w_c = p->d_tables + p->off_wc;
+    a.phi_m = p->d_tables + p->off_phim;
+    a.phi_c = p->d_tables + p->off_phic;
+    if (precision == QXA_FP32) {
+        a.Qm = p->d_tables_f + p->off_qm;
+        a.Qc = p->d_tables_f + p->off_qc;
+    } else {
+        a.Qm = p->d_tables + p->off_qm;
+        a.Qc = p->d_tables + p->off_qc;
+    }
+    a.flags = p->d_flags;
+    return QXA_OK;
+}
+
+qxa_status qxa_assemble(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *stiff, int precision, double *M_vals,
+                        double *C_vals, void *stream)
+{
+    if (!p) return fail(QXA_E_INVALID, "null plan");
+    FormArgs a{};
+    qxa_status st = fill_form_args(p, mass, stiff, precision, a);
+    if (st) return st;
+    if (!M_vals && !C_vals) return QXA_OK;
+    QXA_HIP(hipSetDevice(p->mesh->device));
+    const size_t ns = size_t(p->ref.ns), ne = size_t(p->mesh->n_elem);
+    a.Vm = M_vals ? p->d_V : nullptr;
+    a.Vc = C_vals ? p->d_V + ns * ne : nullptr;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    {
+        TimedLaunch tl(p, "form", s);
+        QXA_HIP(launch_form(a, p->ref.dim, p->ref.order, p->ref.nq_m, p->ref.nq_c, precision, s));
+    }
+    TimedLaunch tl(p, "gather", s);
+    GatherArgs g{p->nnz, p->d_src_upper, p->d_seg_ptr, p->d_seg_val, a.Vm, a.Vc, M_vals, C_vals};
+    QXA_HIP(launch_gather(g, s));
+    return QXA_OK;
+}
+
+qxa_status qxa_element_matrices(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *stiff, int precision, double *Vm,
+                                double *Vc, void *stream)
+{
+    if (!p) return fail(QXA_E_INVALID, "null plan");
+    FormArgs a{};
+    qxa_status st = fill_form_args(p, mass, stiff, precision, a);
+    if (st) return st;
+    if (!Vm && !Vc) return QXA_OK;
+    QXA_HIP(hipSetDevice(p->mesh->device));
+    const size_t ns = size_t(p->ref.ns), ne = size_t(p->mesh->n_elem);
+    a.Vm = Vm ? p->d_V : nullptr;
+    a.Vc = Vc ? p->d_V + ns * ne : nullptr;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    QXA_HIP(launch_form(a, p->ref.dim, p->ref.order, p->ref.nq_m, p->ref.nq_c, precision, s));
+    ExpandArgs x{p->mesh->n_elem, p->ref.np, a.Vm, a.Vc, Vm, Vc};
+    QXA_HIP(launch_expand(x, s));
+    return QXA_OK;
+}
+
+qxa_status qxa_plan_set_timing(qxa_plan p, int enable)
+{
+    if (!p) return fail(QXA_E_INVALID, "null plan");
+    p->timing = enable != 0;
+    return QXA_OK;
+}
+
+qxa_status qxa_plan_timing_report(qxa_plan p, char *buf, size_t cap)
+{
+    if (!p || !buf || cap == 0) return fail(QXA_E_INVALID, "null plan or buffer");
+    QXA_HIP(hipSetDevice(p->mesh->device));
+    std::vector<std::pair<std::string, std::pair<int, double>>> acc;
+    qxa_status st = QXA_OK;
+    for (auto &r : p->recs) {
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess && st == QXA_OK) st = hip_fail(e, "hipEventElapsedTime");
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+        size_t k = 0;
+        while (k < acc.size() && acc[k].first != r.name) ++k;
+        if (k == acc.size()) acc.push_back({r.name, {0, 0.0}});
+        acc[k].second.first += 1;
+        acc[k].second.second += ms;
+    }
+    p->recs.clear();
+    std::string out = "{";
+    for (size_t k = 0; k < acc.size(); ++k) {
+        char tmp[160];
+        std::snprintf(tmp, sizeof(tmp), "%s\"%s\": {\"n\": %d, \"ms\": %.6f}", k ? ", " : "", acc[k].first.c_str(),
+                      acc[k].second.first, acc[k].second.second);
+        out += tmp;
+    }
+    out += "}";
+    std::snprintf(buf, cap, "%s", out.c_str());
+    return st;
+}
+
+qxa_status qxa_sync(qxa_plan p, void *stream)
+{
+    if (!p) return fail(QXA_E_INVALID, "null plan");
+    QXA_HIP(hipSetDevice(p->mesh->device));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    QXA_HIP(hipStreamSynchronize(s));
+    int flag = 0;
+    QXA_HIP(hipMemcpy(&flag, p->d_flags, sizeof(int), hipMemcpyDeviceToHost));
+    if (flag) {
+        QXA_HIP(hipMemset(p->d_flags, 0, sizeof(int)));
+        return fail(QXA_E_NONFINITE, "non-finite coefficient value at a quadrature node");
+    }
+    return QXA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,127 @@
+// Host construction of the per-mesh assembly plan (Algorithm 2, Line 12:
+// "the set of indices of nonzero entries").
+//   1. node -> element lists (counting sort; ascending element id per node);
+//   2. CSR pattern: row i holds every j that shares an element with i
+//      (Section 3, step 2: compact support), sorted, structural zeros kept;
+//   3. the element-entry -> CSR-slot permutation for the distinct symmetric
+//      pairs of every element, and its inverse as slot-sorted segments; every
+//      segment lists contributions in ascending (element, pair) order, which
+//      fixes the summation order of the scatter once per mesh.
+#include <algorithm>
+#include <thread>
+
+#include "qxa_internal.hpp"
+
+namespace qxa {
+
+template <class F>
+static void parallel_for(int64_t n, F &&f)
+{
+    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (n < 4096 || nt == 1) {
+        f(int64_t(0), n);
+        return;
+    }
+    std::vector<std::thread> th;
+    int64_t chunk = (n + nt - 1) / nt;
+    for (unsigned t = 0; t < nt; ++t) {
+        int64_t lo = std::min<int64_t>(n, t * chunk), hi = std::min<int64_t>(n, lo + chunk);
+        if (lo < hi) th.emplace_back([&f, lo, hi] { f(lo, hi); });
+    }
+    for (auto &x : th) x.join();
+}
+
+qxa_status build_host_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, const int32_t *conn, HostPlan &hp)
+{
+    const int np = n_local(dim, order);
+    const int ns = n_sym(np);
+    if (uint64_t(ns) * uint64_t(n_elem) >= (uint64_t(1) << 32))
+        return fail(QXA_E_UNSUPPORTED, "mesh too large for 32-bit element-entry indices");
+    hp.n_nodes = n_nodes;
+    hp.n_elem = n_elem;
+    // 1. node -> element adjacency
+    std::vector<int64_t> astart(n_nodes + 1, 0);
+    for (int i = 0; i < np; ++i)
+        for (int64_t e = 0; e < n_elem; ++e) astart[conn[size_t(i) * n_elem + e] + 1]++;
+    for (int64_t v = 0; v < n_nodes; ++v) astart[v + 1] += astart[v];
+    std::vector<int32_t> aelem(astart[n_nodes]);
+    {
+        std::vector<int64_t> fill(astart.begin(), astart.end() - 1);
+        for (int64_t e = 0; e < n_elem; ++e)
+            for (int i = 0; i < np; ++i) aelem[fill[conn[size_t(i) * n_elem + e]]++] = int32_t(e);
+    }
+    // 2. pattern: count, then fill
+    hp.row_ptr.assign(n_nodes + 1, 0);
+    auto row_cols = [&](int64_t v, std::vector<int32_t> &buf) {
+        buf.clear();
+        for (int64_t p = astart[v]; p < astart[v + 1]; ++p) {
+            const int64_t e = aelem[p];
+            for (int j = 0; j < np; ++j) buf.push_back(conn[size_t(j) * n_elem + e]);
+        }
+        std::sort(buf.begin(), buf.end());
+        buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
+    };
+    parallel_for(n_nodes, [&](int64_t lo, int64_t hi) {
+        std::vector<int32_t> buf;
+        for (int64_t v = lo; v < hi; ++v) {
+            row_cols(v, buf);
+            hp.row_ptr[v + 1] = int64_t(buf.size());
+        }
+    });
+    for (int64_t v = 0; v < n_nodes; ++v) hp.row_ptr[v + 1] += hp.row_ptr[v];
+    hp.nnz = hp.row_ptr[n_nodes];
+    if (hp.nnz >= (int64_t(1) << 31)) return fail(QXA_E_UNSUPPORTED, "more than 2^31 nonzeros");
+    hp.col_idx.resize(hp.nnz);
+    parallel_for(n_nodes, [&](int64_t lo, int64_t hi) {
+        std::vector<int32_t> buf;
+        for (int64_t v = lo; v < hi; ++v) {
+            row_cols(v, buf);
+            std::copy(buf.begin(), buf.end(), hp.col_idx.begin() + hp.row_ptr[v]);
+        }
+    });
+    auto slot_of = [&](int32_t r, int32_t c) -> uint32_t {
+        const int32_t *b = hp.col_idx.data() + hp.row_ptr[r];
+        const int32_t *e = hp.col_idx.data() + hp.row_ptr[r + 1];
+        return uint32_t(std::lower_bound(b, e, c) - hp.col_idx.data());
+    };
+    // 3. permutation (upper-triangle slot of every distinct symmetric pair)
+    std::vector<int> pa, pb;
+    for (int a = 0; a < np; ++a)
+        for (int b = a; b < np; ++b) {
+            pa.push_back(a);
+            pb.push_back(b);
+        }
+    hp.perm_sym.resize(size_t(ns) * n_elem);
+    parallel_for(n_elem, [&](int64_t lo, int64_t hi) {
+        for (int64_t e = lo; e < hi; ++e)
+            for (int s = 0; s < ns; ++s) {
+                const int32_t i = conn[size_t(pa[s]) * n_elem + e], j = conn[size_t(pb[s]) * n_elem + e];
+                hp.perm_sym[size_t(s) * n_elem + e] = slot_of(std::min(i, j), std::max(i, j));
+            }
+    });
+    // inverse: slot-sorted segments (counting sort keyed by slot, stable in (e, s))
+    hp.seg_ptr.assign(hp.nnz + 1, 0);
+    for (size_t k = 0; k < hp.perm_sym.size(); ++k) hp.seg_ptr[hp.perm_sym[k] + 1]++;
+    for (int64_t t = 0; t < hp.nnz; ++t) hp.seg_ptr[t + 1] += hp.seg_ptr[t];
+    hp.seg_val.resize(hp.perm_sym.size());
+    {
+        std::vector<uint32_t> fill(hp.seg_ptr.begin(), hp.seg_ptr.end() - 1);
+        for (int64_t e = 0; e < n_elem; ++e)
+            for (int s = 0; s < ns; ++s) {
+                const uint32_t t = hp.perm_sym[size_t(s) * n_elem + e];
+                hp.seg_val[fill[t]++] = uint32_t(s) * uint32_t(n_elem) + uint32_t(e);
+            }
+    }
+    // lower-triangle slots read the segment of their transposed twin
+    hp.src_upper.resize(hp.nnz);
+    parallel_for(n_nodes, [&](int64_t lo, int64_t hi) {
+        for (int64_t r = lo; r < hi; ++r)
+            for (int64_t t = hp.row_ptr[r]; t < hp.row_ptr[r + 1]; ++t) {
+                const int32_t c = hp.col_idx[t];
+                hp.src_upper[t] = (c >= r) ? uint32_t(t) : slot_of(c, int32_t(r));
+            }
+    });
+    return QXA_OK;
+}
+
+}  // namespace qxa

@@ -1,0 +1,34 @@
+"""Shared test helpers (comparison metrics; no assembly arithmetic)."""
+import numpy as np
+
+
+def row_scaled_error(got, ref, row_ptr):
+    """max_ij |v_ij - o_ij| / max_k |o_ik| (entrywise relative error is undefined on cancelled zeros)."""
+    if ref.size == 0:
+        return 0.0
+    rmax = np.maximum.reduceat(np.abs(ref), row_ptr[:-1])
+    rmax = np.where(rmax == 0, 1.0, rmax)
+    rows = np.repeat(np.arange(row_ptr.size - 1), np.diff(row_ptr))
+    return float(np.max(np.abs(got - ref) / rmax[rows]))
+
+
+def sampled_rows_error(got_full, row_ptr_full, rows, sub_ptr, ref_vals):
+    """Row-scaled error on selected rows: got_full is the full CSR value array."""
+    err = 0.0
+    for k, r in enumerate(rows):
+        g = got_full[row_ptr_full[r]:row_ptr_full[r + 1]]
+        o = ref_vals[sub_ptr[k]:sub_ptr[k + 1]]
+        m = np.max(np.abs(o)) if o.size else 1.0
+        err = max(err, float(np.max(np.abs(g - o)) / (m if m > 0 else 1.0)))
+    return err
+
+
+def transpose_slots(row_ptr, col_idx):
+    """Index of slot (j,i) for every slot (i,j) of a structurally symmetric CSR."""
+    n = row_ptr.size - 1
+    rows = np.repeat(np.arange(n), np.diff(row_ptr))
+    key = rows.astype(np.int64) * n + col_idx
+    tkey = col_idx.astype(np.int64) * n + rows
+    order = np.argsort(key)
+    pos = np.searchsorted(key[order], tkey)
+    return order[pos]

@@ -1,0 +1,64 @@
+"""Host-side checks of the C-ABI library (no GPU needed)."""
+import ctypes
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2204_03893_amd as qxa
+from workloads import structured_mesh
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        txt = open(h).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*\b(qxa_[a-z0-9_]+)\s*\(", txt, re.M):
+            names.add(m.group(1))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared_symbols()
+    assert {"qxa_mesh_create", "qxa_plan_create", "qxa_assemble", "qxa_sync"} <= names
+    L = ctypes.CDLL(qxa.LIB_PATH)
+    missing = [n for n in sorted(names) if not hasattr(L, n)]
+    assert missing == []
+
+
+@pytest.mark.parametrize("dim,order,N", [(2, 1, 9), (2, 2, 5), (2, 3, 4), (3, 1, 4), (3, 2, 3), (3, 3, 2)])
+def test_host_pattern_matches_oracle(dim, order, N):
+    m = structured_mesh(dim, order, N, 0.1, seed=2)
+    rp, ci = qxa.pattern_host(dim, order, m["n_nodes"], m["conn"])
+    rpo, cio = oracle.pattern(m)
+    assert np.array_equal(rp, rpo)
+    assert np.array_equal(ci, cio)
+
+
+def test_host_pattern_relabelled_mesh():
+    m = structured_mesh(3, 2, 2)
+    sigma = np.random.default_rng(3).permutation(m["n_nodes"])
+    m["conn"] = sigma[m["conn"]].astype(np.int32)
+    rp, ci = qxa.pattern_host(3, 2, m["n_nodes"], m["conn"])
+    rpo, cio = oracle.pattern(m)
+    assert np.array_equal(rp, rpo) and np.array_equal(ci, cio)
+
+
+def test_host_pattern_rejects_bad_index():
+    m = structured_mesh(2, 1, 3)
+    c = m["conn"].copy()
+    c[1, 5] = m["n_nodes"]
+    with pytest.raises(qxa.QxaError) as ei:
+        qxa.pattern_host(2, 1, m["n_nodes"], c)
+    assert ei.value.code == -2
+
+
+def test_host_pattern_empty_mesh():
+    rp, ci = qxa.pattern_host(2, 1, 5, np.zeros((3, 0), dtype=np.int32))
+    assert ci.size == 0 and np.all(rp == 0)

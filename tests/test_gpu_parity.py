@@ -1,0 +1,200 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU oracle.
+
+Bar: CSR pattern bit-exact; FP64 values within 1e-12 row-scaled relative
+error; bitwise run-to-run determinism; bitwise symmetry. Reduced-precision
+forms are reported against the oracle with their own stated bound.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import row_scaled_error, sampled_rows_error, transpose_slots
+from workloads import WORKLOADS, make_inputs, rule, scaled, structured_mesh
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _qxa():
+    import paper_2204_03893_amd as qxa
+    return qxa
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _run(w, precision="fp64", reps=1, stream_id=0):
+    qxa = _qxa()
+    mesh, r, u = make_inputs(w, stream_id)
+    m = qxa.Mesh(w.dim, w.order, mesh["coords"], mesh["conn"])
+    plan = qxa.Plan(m, r)
+    uf = torch.tensor(u, device="cuda")
+    outs = []
+    for _ in range(reps):
+        M, Cv = qxa.assemble(plan, w.mass_law, w.stiff_law, uf, uf, precision=precision)
+        qxa.sync(plan)
+        outs.append((M.cpu().numpy(), Cv.cpu().numpy()))
+    rp, ci = plan.pattern()
+    return mesh, r, u, plan, rp.cpu().numpy(), ci.cpu().numpy(), outs
+
+
+SMALL = [("p1_2d_64", None), ("p2_3d_32", 6), ("p3_2d_1024", 24), ("p1_3d_96_heat", 10)]
+
+
+@pytest.mark.parametrize("name,N", SMALL)
+def test_fp64_parity_against_oracle(name, N):
+    w = WORKLOADS[name] if N is None else scaled(name, N)
+    _say("case", w.name)
+    mesh, r, u, plan, rp, ci, outs = _run(w, reps=3)
+    rpo, cio, Mo, Co = oracle.assemble(mesh, r, r, w.mass_law, w.stiff_law, u, u)
+    assert np.array_equal(rp, rpo) and np.array_equal(ci, cio)
+    M, Cv = outs[0]
+    assert row_scaled_error(M, Mo, rpo) <= 1e-12
+    assert row_scaled_error(Cv, Co, rpo) <= 1e-12
+    for M2, C2 in outs[1:]:                      # bitwise deterministic
+        assert np.array_equal(M2.view(np.uint64), M.view(np.uint64))
+        assert np.array_equal(C2.view(np.uint64), Cv.view(np.uint64))
+    t = transpose_slots(rp, ci)                  # bitwise symmetric
+    assert np.array_equal(M[t], M) and np.array_equal(Cv[t], Cv)
+
+
+def test_fp64_parity_full_p2_3d_32():
+    """The benchmark workload at full size, every value compared."""
+    w = WORKLOADS["p2_3d_32"]
+    _say("case", w.name, "full")
+    mesh, r, u, plan, rp, ci, outs = _run(w)
+    rpo, cio, Mo, Co = oracle.assemble(mesh, r, r, w.mass_law, w.stiff_law, u, u)
+    assert np.array_equal(rp, rpo) and np.array_equal(ci, cio)
+    assert row_scaled_error(outs[0][0], Mo, rpo) <= 1e-12
+    assert row_scaled_error(outs[0][1], Co, rpo) <= 1e-12
+
+
+@pytest.mark.parametrize("name", ["p3_2d_1024", "p1_3d_96_heat"])
+def test_fp64_full_size_sampled_rows(name):
+    """Full-size meshes: rows sampled uniformly plus the first/last rows, computed one by one by the oracle."""
+    w = WORKLOADS[name]
+    _say("case", w.name, "full sampled")
+    mesh, r, u, plan, rp, ci, outs = _run(w)
+    n = mesh["n_nodes"]
+    rows = np.unique(np.concatenate([[0, 1, n // 2, n - 1], np.random.default_rng(0).integers(0, n, 300)]))
+    sp, sc, sM, sC = oracle.assemble_rows(mesh, rows, r, r, w.mass_law, w.stiff_law, u, u)
+    for k, rr in enumerate(rows):
+        assert np.array_equal(ci[rp[rr]:rp[rr + 1]], sc[sp[k]:sp[k + 1]])
+    assert sampled_rows_error(outs[0][0], rp, rows, sp, sM) <= 1e-12
+    assert sampled_rows_error(outs[0][1], rp, rows, sp, sC) <= 1e-12
+    # properties at any size: mass total and zero stiffness row sums
+    M, Cv = outs[0]
+    if w.mass_law[0] == "const":
+        assert abs(M.sum() - 1.0) < 1e-10
+    rs = np.add.reduceat(Cv, rp[:-1])
+    rmax = np.maximum.reduceat(np.abs(Cv), rp[:-1])
+    assert np.all(np.abs(rs) <= 1e-12 * rmax)
+
+
+@pytest.mark.parametrize("name,N", [("p2_3d_32", 6), ("p1_3d_96_heat", 8)])
+def test_fp32_contraction_error(name, N):
+    w = scaled(name, N)
+    _say("case", w.name, "fp32")
+    mesh, r, u, plan, rp, ci, outs = _run(w, precision="fp32", reps=2)
+    rpo, cio, Mo, Co = oracle.assemble(mesh, r, r, w.mass_law, w.stiff_law, u, u)
+    em = row_scaled_error(outs[0][0], Mo, rpo)
+    ec = row_scaled_error(outs[0][1], Co, rpo)
+    _say("fp32 row-scaled error", em, ec)
+    assert em <= 1e-6 and ec <= 1e-6
+    assert np.array_equal(outs[0][0], outs[1][0])
+
+
+@pytest.mark.parametrize("dim,order,deg", [(2, 1, 2), (2, 2, 4), (2, 3, 6), (3, 1, 2), (3, 2, 4), (3, 3, 6)])
+def test_element_matrices_formation(dim, order, deg):
+    """Formation only (Lines 4-11) against the oracle's local matrices, all orders."""
+    qxa = _qxa()
+    _say("case formation", dim, order)
+    mesh = structured_mesh(dim, order, 3 if dim == 2 else 2, 0.2, seed=4)
+    r = rule(dim, deg)
+    u = np.sin(3 * mesh["coords"][0]) + 0.5 * mesh["coords"][1]
+    m = qxa.Mesh(dim, order, mesh["coords"], mesh["conn"])
+    plan = qxa.Plan(m, r)
+    uf = torch.tensor(u, device="cuda")
+    lm, lc = ("poly2", 1.0, 0.1, 0.0), ("exp", 0.0, 1.0)
+    Vm, Vc = qxa.element_matrices(plan, lm, lc, uf, uf)
+    qxa.sync(plan)
+    ne = mesh["conn"].shape[1]
+    Me, Ce = oracle.element_matrices(mesh, np.arange(ne), r, r, lm, lc, u, u)
+    n = Me.shape[1]
+    Vm = Vm.cpu().numpy().reshape(n, n, ne).transpose(2, 0, 1)
+    Vc = Vc.cpu().numpy().reshape(n, n, ne).transpose(2, 0, 1)
+    assert np.abs(Vm - Me).max() <= 1e-12 * np.abs(Me).max()
+    assert np.abs(Vc - Ce).max() <= 1e-12 * np.abs(Ce).max()
+
+
+def test_qpoint_coefficients_and_separate_rules():
+    """Coefficient values given per (q, e), and different rules for M and C (paper policy)."""
+    qxa = _qxa()
+    mesh = structured_mesh(3, 2, 3, 0.2, seed=9)
+    rm, rc = rule(3, 4), rule(3, 2)
+    ne = mesh["conn"].shape[1]
+    rng = np.random.default_rng(1)
+    sm = rng.uniform(0.5, 2.0, size=(rm[1].size, ne))
+    sc = rng.uniform(0.5, 2.0, size=(rc[1].size, ne))
+    m = qxa.Mesh(3, 2, mesh["coords"], mesh["conn"])
+    plan = qxa.Plan(m, rm, rc)
+    M, Cv = qxa.assemble(plan, ("identity",), ("identity",), torch.tensor(sm, device="cuda"),
+                         torch.tensor(sc, device="cuda"), qpoint=True)
+    qxa.sync(plan)
+    rpo, cio, Mo, Co = oracle.assemble(mesh, rm, rc, ("identity",), ("identity",), qpoint_m=sm, qpoint_c=sc)
+    assert row_scaled_error(M.cpu().numpy(), Mo, rpo) <= 1e-12
+    assert row_scaled_error(Cv.cpu().numpy(), Co, rpo) <= 1e-12
+
+
+def test_error_paths():
+    qxa = _qxa()
+    mesh = structured_mesh(2, 1, 4)
+    # out-of-range node index
+    c = mesh["conn"].copy()
+    c[2, 3] = -1
+    with pytest.raises(qxa.QxaError) as ei:
+        qxa.Mesh(2, 1, mesh["coords"], c)
+    assert ei.value.code == -2
+    # degenerate element
+    X = mesh["coords"].copy()
+    v = mesh["conn"][:, 0]
+    X[:, v[2]] = 2 * X[:, v[1]] - X[:, v[0]]
+    with pytest.raises(qxa.QxaError) as ei:
+        qxa.Mesh(2, 1, X, mesh["conn"])
+    assert ei.value.code == -3
+    # unsupported rule size
+    m = qxa.Mesh(2, 1, mesh["coords"], mesh["conn"])
+    with pytest.raises(qxa.QxaError) as ei:
+        qxa.Plan(m, rule(2, 4))
+    assert ei.value.code == -6
+    # non-finite coefficient detected on the device, reported at sync
+    plan = qxa.Plan(m, rule(2, 2))
+    u = torch.zeros(mesh["n_nodes"], dtype=torch.float64, device="cuda")
+    u[7] = float("nan")
+    qxa.assemble(plan, ("const", 1.0), ("poly2", 1.0, 0.0, 1.0), None, u)
+    with pytest.raises(qxa.QxaError) as ei:
+        qxa.sync(plan)
+    assert ei.value.code == -4
+    qxa.assemble(plan, ("const", 1.0), ("const", 1.0))
+    qxa.sync(plan)                                # flag was cleared
+
+
+def test_empty_and_single_element_meshes():
+    qxa = _qxa()
+    X = np.array([[0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+    m = qxa.Mesh(2, 1, X, np.zeros((3, 0), dtype=np.int32))
+    plan = qxa.Plan(m, rule(2, 2))
+    assert plan.nnz == 0
+    qxa.assemble(plan, ("const", 1.0), ("const", 1.0))
+    qxa.sync(plan)
+    m1 = qxa.Mesh(2, 1, X, np.array([[0], [1], [2]], dtype=np.int32))
+    p1 = qxa.Plan(m1, rule(2, 2))
+    M, Cv = qxa.assemble(p1, ("const", 1.0), ("const", 1.0))
+    qxa.sync(p1)
+    assert abs(M.sum().item() - 0.5) < 1e-15
+    assert np.allclose(Cv.cpu().numpy(), [1, -0.5, -0.5, -0.5, 0.5, 0, -0.5, 0, 0.5], atol=1e-15)
