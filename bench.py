@@ -27,18 +27,17 @@ HBM_PEAK_GBS = 8000.0
 
 
 def algorithmic_bytes(kernel, w, plan, mesh):
-    """Compulsory bytes of one launch of `kernel` (see the design notes)."""
-    d, ne, nn, npl, nnz = w.dim, plan.n_elem, plan.n_nodes, plan.n_p, plan.nnz
-    ns = npl * (npl + 1) // 2
-    n_vert = int(mesh["vertex_mask"].sum())
-    inputs = 4 * npl * ne + 8 * d * n_vert + 8 * nn           # conn, vertex coords, nodal field
-    if kernel == "form":
-        return inputs + 2 * 8 * ns * ne                          # + V_m, V_c written
-    if kernel == "gather":
-        contrib_full = ne * npl * npl                            # every CSR slot sums its segment
-        return 4 * nnz + 8 * nnz + 4 * contrib_full + 16 * contrib_full + 16 * nnz
+    """Algorithmic bytes of one launch of `kernel`.
+
+    fused: the path floor (inputs once, the element-entry -> slot map at 4 B
+    per element entry, both CSR value arrays written once): everything the
+    method must move, independent of how the kernel stages it.
+    fixup: the shared-slot partials read once and their slots written once.
+    """
     if kernel == "fused":
-        return inputs + 4 * ne * ns + 16 * nnz
+        return floor_bytes(w, plan, mesh)
+    if kernel == "fixup":
+        return 16 * plan.n_partials + 32 * plan.n_shared
     raise KeyError(kernel)
 
 
@@ -74,6 +73,8 @@ def main():
     ap.add_argument("--workload", default="p2_3d_32")
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (5 times) to calibrate HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is a design "
@@ -82,6 +83,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.rand(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 5}))
+        return
 
     import paper_2204_03893_amd as qxa
     from workloads import WORKLOADS, make_inputs

@@ -103,6 +103,9 @@ typedef struct {
     const int32_t *col_idx; /* device, [nnz], sorted within each row                */
     size_t device_bytes;    /* device memory held by the plan                       */
     double build_ms;        /* wall time of qxa_plan_create                         */
+    int64_t n_tiles;        /* element tiles of the fused kernel                    */
+    int64_t n_shared;       /* CSR upper slots shared between tiles                 */
+    int64_t n_partials;     /* partial sums written for shared slots                */
 } qxa_plan_info;
 
 const char *qxa_last_error(void);
@@ -147,6 +150,14 @@ qxa_status qxa_plan_get_info(qxa_plan plan, qxa_plan_info *out);
  * qxa_mesh_create; indices are validated (QXA_E_INDEX). */
 qxa_status qxa_pattern_host(int dim, int order, int64_t n_nodes, int64_t n_elem, const int32_t *conn,
                             int64_t *row_ptr, int32_t *col_idx, int64_t *nnz);
+
+/* Host-only build and structural self-check of the whole plan (pattern,
+ * permutation, tile decomposition of the fused kernel): every index in bounds,
+ * every CSR slot written exactly once. The same check runs inside
+ * qxa_plan_create. Optional outputs: number of tiles and of shared-slot
+ * partials. */
+qxa_status qxa_plan_check_host(int dim, int order, int64_t n_nodes, const double *coords, int64_t n_elem,
+                               const int32_t *conn, int64_t *n_tiles, int64_t *n_partials);
 
 /* Copy the CSR pattern into caller-owned device arrays row_ptr[n_nodes+1] and
  * col_idx[nnz] (either may be NULL), asynchronously on `stream`. */

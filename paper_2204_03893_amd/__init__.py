@@ -45,7 +45,8 @@ class _PlanInfo(C.Structure):
     _fields_ = [("dim", C.c_int), ("order", C.c_int), ("n_p", C.c_int), ("n_q_mass", C.c_int),
                 ("n_q_stiff", C.c_int), ("n_nodes", C.c_int64), ("n_elem", C.c_int64), ("nnz", C.c_int64),
                 ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("device_bytes", C.c_size_t),
-                ("build_ms", C.c_double)]
+                ("build_ms", C.c_double), ("n_tiles", C.c_int64), ("n_shared", C.c_int64),
+                ("n_partials", C.c_int64)]
 
 
 _lib = None
@@ -68,6 +69,7 @@ def lib():
         L.qxa_plan_get_info.argtypes = [vp, C.POINTER(_PlanInfo)]
         L.qxa_plan_copy_pattern.argtypes = [vp, vp, vp, vp]
         L.qxa_pattern_host.argtypes = [ci, ci, i64, i64, vp, vp, vp, C.POINTER(i64)]
+        L.qxa_plan_check_host.argtypes = [ci, ci, i64, vp, i64, vp, C.POINTER(i64), C.POINTER(i64)]
         L.qxa_assemble.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), ci, vp, vp, vp]
         L.qxa_element_matrices.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), ci, vp, vp, vp]
         L.qxa_sync.argtypes = [vp, vp]
@@ -75,7 +77,7 @@ def lib():
         L.qxa_plan_timing_report.argtypes = [vp, C.c_char_p, C.c_size_t]
         for name in ("qxa_mesh_create", "qxa_mesh_destroy", "qxa_plan_create", "qxa_plan_destroy",
                      "qxa_plan_get_info", "qxa_plan_copy_pattern", "qxa_assemble", "qxa_element_matrices",
-                     "qxa_sync", "qxa_pattern_host", "qxa_plan_set_timing", "qxa_plan_timing_report"):
+                     "qxa_sync", "qxa_pattern_host", "qxa_plan_check_host", "qxa_plan_set_timing", "qxa_plan_timing_report"):
             getattr(L, name).restype = ci
         _lib = L
     return _lib
@@ -164,6 +166,9 @@ class Plan:
         self.n_p = int(info.n_p)
         self.build_ms = float(info.build_ms)
         self.device_bytes = int(info.device_bytes)
+        self.n_tiles = int(info.n_tiles)
+        self.n_shared = int(info.n_shared)
+        self.n_partials = int(info.n_partials)
 
     def pattern(self):
         """(row_ptr int64, col_idx int32) as device tensors."""
@@ -206,6 +211,16 @@ def pattern_host(dim, order, n_nodes, conn):
     check(lib().qxa_pattern_host(dim, order, n_nodes, conn.shape[1], conn.ctypes.data, rp.ctypes.data,
                                  ci.ctypes.data, C.byref(nnz)))
     return rp, ci
+
+
+def plan_check_host(dim, order, coords, conn):
+    """Host-only plan build + structural self-check; returns (n_tiles, n_partials)."""
+    X = np.ascontiguousarray(coords, dtype=np.float64)
+    conn = np.ascontiguousarray(conn, dtype=np.int32)
+    nt, npart = C.c_int64(), C.c_int64()
+    check(lib().qxa_plan_check_host(dim, order, X.shape[1], X.ctypes.data, conn.shape[1], conn.ctypes.data,
+                                    C.byref(nt), C.byref(npart)))
+    return nt.value, npart.value
 
 
 def make_coeff(law, field=None, qpoint=False):

@@ -132,6 +132,7 @@ qxa_status qxa_mesh_create(int device, int dim, int order, int64_t n_nodes, cons
     m->n_nodes = n_nodes;
     m->n_elem = n_elem;
     m->h_conn.assign(Cn, Cn + size_t(np) * n_elem);
+    m->h_coords.assign(X, X + size_t(dim) * n_nodes);
     qxa_status st = upload(&m->d_coords, X, size_t(dim) * n_nodes, m->device_bytes);
     if (!st) st = upload(&m->d_conn, Cn, size_t(np) * n_elem, m->device_bytes);
     if (st) {
@@ -158,9 +159,18 @@ qxa_status qxa_plan_destroy(qxa_plan p)
     hipSetDevice(p->mesh->device);
     hipFree(p->d_row_ptr);
     hipFree(p->d_col_idx);
-    hipFree(p->d_seg_ptr);
-    hipFree(p->d_seg_val);
-    hipFree(p->d_src_upper);
+    hipFree(p->d_tconn);
+    hipFree(p->d_elem_order);
+    hipFree(p->d_rec);
+    hipFree(p->d_rec_ptr);
+    hipFree(p->d_ovf);
+    hipFree(p->d_ovf_ptr);
+    hipFree(p->d_fix_ptr);
+    hipFree(p->d_fix_target);
+    hipFree(p->d_fix_idx);
+    hipFree(p->d_part);
+    hipFree(p->d_qfrag);
+    hipFree(p->d_qfrag_f);
     hipFree(p->d_tables);
     hipFree(p->d_tables_f);
     hipFree(p->d_V);
@@ -197,12 +207,55 @@ qxa_status qxa_plan_create(qxa_mesh mesh, const qxa_quad *mr, const qxa_quad *cr
         return st;
     }
     p->nnz = hp.nnz;
+    TilePlan tp;
+    st = build_tile_plan(mesh->dim, mesh->order, mesh->n_nodes, mesh->n_elem, mesh->h_conn.data(),
+                         mesh->h_coords.data(), hp, tile_size(mesh->dim, mesh->order), tp);
+    if (!st) st = check_tile_plan(T.np, mesh->n_elem, hp, tp);
+    if (st) {
+        delete p;
+        return st;
+    }
+    p->tile_T = tp.T;
+    p->n_tiles = tp.n_tiles;
+    p->n_shared = tp.n_shared;
+    p->n_fix = int64_t(tp.fix_target.size());
+    p->n_partials = tp.n_partials;
     size_t &acct = p->device_bytes;
     st = upload(&p->d_row_ptr, hp.row_ptr.data(), hp.row_ptr.size(), acct);
     if (!st) st = upload(&p->d_col_idx, hp.col_idx.data(), hp.col_idx.size(), acct);
-    if (!st) st = upload(&p->d_seg_ptr, hp.seg_ptr.data(), hp.seg_ptr.size(), acct);
-    if (!st) st = upload(&p->d_seg_val, hp.seg_val.data(), hp.seg_val.size(), acct);
-    if (!st) st = upload(&p->d_src_upper, hp.src_upper.data(), hp.src_upper.size(), acct);
+    if (!st) st = upload(&p->d_tconn, tp.tconn.data(), tp.tconn.size(), acct);
+    if (!st) st = upload(&p->d_elem_order, tp.elem_order.data(), tp.elem_order.size(), acct);
+    if (!st) st = upload(&p->d_rec, tp.rec.data(), tp.rec.size(), acct);
+    if (!st) st = upload(&p->d_rec_ptr, tp.rec_ptr.data(), tp.rec_ptr.size(), acct);
+    if (!st) st = upload(&p->d_ovf, tp.ovf.data(), tp.ovf.size(), acct);
+    if (!st) st = upload(&p->d_ovf_ptr, tp.ovf_ptr.data(), tp.ovf_ptr.size(), acct);
+    if (!st) st = upload(&p->d_fix_ptr, tp.fix_ptr.data(), tp.fix_ptr.size(), acct);
+    if (!st) st = upload(&p->d_fix_target, tp.fix_target.data(), tp.fix_target.size(), acct);
+    if (!st) st = upload(&p->d_fix_idx, tp.fix_idx.data(), tp.fix_idx.size(), acct);
+    if (!st) st = dev_alloc(&p->d_part, size_t(2) * tp.n_partials, acct);
+    if (!st && fused_uses_mfma(T.dim, T.order)) {
+        // Q^T fragments [(KSM+KSC)][NB][64]: lane l of block (ks, nb) holds
+        // Q[s = 16 nb + l % 16][k = 4 ks + l / 16] (zero outside the table)
+        const int nb_ = (T.ns + 15) / 16, ksm = (T.nq_m + 3) / 4, kc = T.nq_c * T.ng, ksc = (kc + 3) / 4;
+        std::vector<double> qf(size_t(ksm + ksc) * nb_ * 64, 0.0);
+        for (int ks = 0; ks < ksm + ksc; ++ks)
+            for (int nb = 0; nb < nb_; ++nb)
+                for (int l = 0; l < 64; ++l) {
+                    const int s = 16 * nb + l % 16;
+                    double v = 0.0;
+                    if (ks < ksm) {
+                        const int k = 4 * ks + l / 16;
+                        if (s < T.ns && k < T.nq_m) v = T.Qm[size_t(s) * T.nq_m + k];
+                    } else {
+                        const int k = 4 * (ks - ksm) + l / 16;
+                        if (s < T.ns && k < kc) v = T.Qc[size_t(s) * kc + k];
+                    }
+                    qf[(size_t(ks) * nb_ + nb) * 64 + l] = v;
+                }
+        std::vector<float> qff(qf.begin(), qf.end());
+        st = upload(&p->d_qfrag, qf.data(), qf.size(), acct);
+        if (!st) st = upload(&p->d_qfrag_f, qff.data(), qff.size(), acct);
+    }
     // reference tables: FP64 block and FP32 copy of Q
     std::vector<double> tab;
     auto put = [&](const std::vector<double> &v) {
@@ -220,7 +273,6 @@ qxa_status qxa_plan_create(qxa_mesh mesh, const qxa_quad *mr, const qxa_quad *cr
     std::vector<float> tabf(tab.begin(), tab.end());
     if (!st) st = upload(&p->d_tables, tab.data(), tab.size(), acct);
     if (!st) st = upload(&p->d_tables_f, tabf.data(), tabf.size(), acct);
-    if (!st) st = dev_alloc(&p->d_V, size_t(2) * T.ns * mesh->n_elem, acct);
     if (!st) st = dev_alloc(&p->d_flags, 1, acct);
     if (!st && p->d_flags) {
         hipError_t e = hipMemset(p->d_flags, 0, sizeof(int));
@@ -250,6 +302,9 @@ qxa_status qxa_plan_get_info(qxa_plan p, qxa_plan_info *out)
     out->col_idx = p->d_col_idx;
     out->device_bytes = p->device_bytes;
     out->build_ms = p->build_ms;
+    out->n_tiles = p->n_tiles;
+    out->n_shared = p->n_shared;
+    out->n_partials = p->n_partials;
     return QXA_OK;
 }
 
@@ -271,6 +326,27 @@ qxa_status qxa_pattern_host(int dim, int order, int64_t n_nodes, int64_t n_elem,
     return QXA_OK;
 }
 
+qxa_status qxa_plan_check_host(int dim, int order, int64_t n_nodes, const double *coords, int64_t n_elem,
+                               const int32_t *conn, int64_t *n_tiles, int64_t *n_partials)
+{
+    if (!coords || (n_elem > 0 && !conn)) return fail(QXA_E_INVALID, "null argument");
+    if ((dim != 2 && dim != 3) || order < 1 || order > 3 || n_nodes < 1 || n_elem < 0)
+        return fail(QXA_E_INVALID, "bad dim/order/sizes");
+    const int np = n_local(dim, order);
+    for (size_t k = 0; k < size_t(np) * n_elem; ++k)
+        if (conn[k] < 0 || conn[k] >= n_nodes) return fail(QXA_E_INDEX, "node index out of range");
+    HostPlan hp;
+    qxa_status st = build_host_plan(dim, order, n_nodes, n_elem, conn, hp);
+    if (st) return st;
+    TilePlan tp;
+    st = build_tile_plan(dim, order, n_nodes, n_elem, conn, coords, hp, tile_size(dim, order), tp);
+    if (!st) st = check_tile_plan(np, n_elem, hp, tp);
+    if (st) return st;
+    if (n_tiles) *n_tiles = tp.n_tiles;
+    if (n_partials) *n_partials = tp.n_partials;
+    return QXA_OK;
+}
+
 qxa_status qxa_plan_copy_pattern(qxa_plan p, int64_t *row_ptr, int32_t *col_idx, void *stream)
 {
     if (!p) return fail(QXA_E_INVALID, "null plan");
@@ -284,31 +360,30 @@ qxa_status qxa_plan_copy_pattern(qxa_plan p, int64_t *row_ptr, int32_t *col_idx,
     return QXA_OK;
 }
 
-static qxa_status fill_form_args(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *stiff, int precision,
-                                 FormArgs &a)
+static qxa_status fill_inputs(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *stiff, int precision,
+                              FormInputs &in, const void **Qm, const void **Qc)
 {
     if (precision != QXA_FP64 && precision != QXA_FP32)
-        return fail(QXA_E_UNSUPPORTED, "precision form not available on the two-pass path");
-    qxa_status st = to_coeff(mass, a.cm, "mass");
-    if (!st) st = to_coeff(stiff, a.cc, "stiffness");
+        return fail(QXA_E_UNSUPPORTED, "precision form not built");
+    qxa_status st = to_coeff(mass, in.cm, "mass");
+    if (!st) st = to_coeff(stiff, in.cc, "stiffness");
     if (st) return st;
     const qxa_mesh m = p->mesh;
-    a.n_nodes = m->n_nodes;
-    a.n_elem = m->n_elem;
-    a.coords = m->d_coords;
-    a.conn = m->d_conn;
-    a.w_m = p->d_tables + p->off_wm;
-    a.w_c = p->d_tables + p->off_wc;
-    a.phi_m = p->d_tables + p->off_phim;
-    a.phi_c = p->d_tables + p->off_phic;
+    in.n_nodes = m->n_nodes;
+    in.n_elem = m->n_elem;
+    in.coords = m->d_coords;
+    in.w_m = p->d_tables + p->off_wm;
+    in.w_c = p->d_tables + p->off_wc;
+    in.phi_m = p->d_tables + p->off_phim;
+    in.phi_c = p->d_tables + p->off_phic;
+    in.flags = p->d_flags;
     if (precision == QXA_FP32) {
-        a.Qm = p->d_tables_f + p->off_qm;
-        a.Qc = p->d_tables_f + p->off_qc;
+        *Qm = p->d_tables_f + p->off_qm;
+        *Qc = p->d_tables_f + p->off_qc;
     } else {
-        a.Qm = p->d_tables + p->off_qm;
-        a.Qc = p->d_tables + p->off_qc;
+        *Qm = p->d_tables + p->off_qm;
+        *Qc = p->d_tables + p->off_qc;
     }
-    a.flags = p->d_flags;
     return QXA_OK;
 }
 
@@ -316,22 +391,30 @@ qxa_status qxa_assemble(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *stif
                         double *C_vals, void *stream)
 {
     if (!p) return fail(QXA_E_INVALID, "null plan");
-    FormArgs a{};
-    qxa_status st = fill_form_args(p, mass, stiff, precision, a);
+    FusedArgs a{};
+    qxa_status st = fill_inputs(p, mass, stiff, precision, a.in, &a.Qm, &a.Qc);
     if (st) return st;
     if (!M_vals && !C_vals) return QXA_OK;
     QXA_HIP(hipSetDevice(p->mesh->device));
-    const size_t ns = size_t(p->ref.ns), ne = size_t(p->mesh->n_elem);
-    a.Vm = M_vals ? p->d_V : nullptr;
-    a.Vc = C_vals ? p->d_V + ns * ne : nullptr;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    a.tconn = p->d_tconn;
+    a.elem_order = p->d_elem_order;
+    a.rec = reinterpret_cast<const uint4 *>(p->d_rec);
+    a.rec_ptr = p->d_rec_ptr;
+    a.ovf = p->d_ovf;
+    a.ovf_ptr = p->d_ovf_ptr;
+    a.M = M_vals;
+    a.C = C_vals;
+    a.Qfrag = precision == QXA_FP32 ? static_cast<const void *>(p->d_qfrag_f) : static_cast<const void *>(p->d_qfrag);
+    a.Mpart = p->d_part;
+    a.Cpart = p->d_part + p->n_partials;
     {
-        TimedLaunch tl(p, "form", s);
-        QXA_HIP(launch_form(a, p->ref.dim, p->ref.order, p->ref.nq_m, p->ref.nq_c, precision, s));
+        TimedLaunch tl(p, "fused", s);
+        QXA_HIP(launch_fused(a, p->n_tiles, p->ref.dim, p->ref.order, p->ref.nq_m, p->ref.nq_c, precision, s));
     }
-    TimedLaunch tl(p, "gather", s);
-    GatherArgs g{p->nnz, p->d_src_upper, p->d_seg_ptr, p->d_seg_val, a.Vm, a.Vc, M_vals, C_vals};
-    QXA_HIP(launch_gather(g, s));
+    TimedLaunch tl(p, "fixup", s);
+    FixupArgs f{p->n_fix, p->d_fix_ptr, p->d_fix_target, p->d_fix_idx, a.Mpart, a.Cpart, M_vals, C_vals};
+    QXA_HIP(launch_fixup(f, s));
     return QXA_OK;
 }
 
@@ -340,11 +423,16 @@ qxa_status qxa_element_matrices(qxa_plan p, const qxa_coeff *mass, const qxa_coe
 {
     if (!p) return fail(QXA_E_INVALID, "null plan");
     FormArgs a{};
-    qxa_status st = fill_form_args(p, mass, stiff, precision, a);
+    qxa_status st = fill_inputs(p, mass, stiff, precision, a.in, &a.Qm, &a.Qc);
     if (st) return st;
     if (!Vm && !Vc) return QXA_OK;
     QXA_HIP(hipSetDevice(p->mesh->device));
     const size_t ns = size_t(p->ref.ns), ne = size_t(p->mesh->n_elem);
+    if (!p->d_V && ne) {
+        st = dev_alloc(&p->d_V, 2 * ns * ne, p->device_bytes);
+        if (st) return st;
+    }
+    a.conn = p->mesh->d_conn;
     a.Vm = Vm ? p->d_V : nullptr;
     a.Vc = Vc ? p->d_V + ns * ne : nullptr;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);

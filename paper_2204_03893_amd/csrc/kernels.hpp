@@ -9,22 +9,59 @@
 
 namespace qxa {
 
+// (dim, order, n_q mass, n_q stiffness) combinations with compiled kernels:
+// one rule for both matrices (degree 2P), and the lower-degree stiffness rule
+// (degree 2P-2) that constant coefficients allow.
+#define QXA_FORM_CASES(X)                                                                                     \
+    X(2, 1, 3, 3) X(2, 2, 6, 6) X(2, 3, 12, 12) X(3, 1, 4, 4) X(3, 2, 11, 11) X(3, 3, 24, 24) X(2, 1, 3, 1)   \
+        X(2, 2, 6, 3) X(2, 3, 12, 6) X(3, 1, 4, 1) X(3, 2, 11, 4) X(3, 3, 24, 11)
+
+// Elements per tile of the fused kernels (both matrices staged in LDS,
+// 2 * NS * (T + 1) * 8 B). Vector-ALU variant (P1, 3D P3): one lane per
+// element. Matrix-core variant (2D P2/P3, 3D P2): 16 elements per wave, 8
+// waves per workgroup, Q^T fragments staged next to V.
+constexpr int tile_size(int D, int P)
+{
+    return (D == 3 && P == 3) ? 32 : (P >= 2) ? 128 : 256;
+}
+
+// Number of Q^T fragment values (mass then stiffness) of the matrix-core
+// variant: [(KSM + KSC)][NB][64], zero-padded.
+constexpr int64_t qfrag_count(int D, int P, int nqm, int nqc)
+{
+    const int np = D == 2 ? (P + 1) * (P + 2) / 2 : (P + 1) * (P + 2) * (P + 3) / 6;
+    const int ns = np * (np + 1) / 2, ng = D * (D + 1) / 2;
+    return int64_t((nqm + 3) / 4 + (nqc * ng + 3) / 4) * ((ns + 15) / 16) * 64;
+}
+bool fused_uses_mfma(int D, int P);
+
 struct FormArgs {
-    int64_t n_nodes, n_elem;
-    const double *coords;  // [dim][n_nodes]
-    const int32_t *conn;   // [np][n_elem]
-    CoeffDev cm, cc;
-    const double *w_m, *w_c;      // [nq]
-    const double *phi_m, *phi_c;  // [np][nq]
-    const void *Qm, *Qc;          // compute-type tables [ns][nqm], [ns][nqc][ng]
-    double *Vm, *Vc;              // [ns][n_elem] outputs (either may be null)
-    int *flags;
+    FormInputs in;
+    const int32_t *conn;  // [np][n_elem]
+    const void *Qm, *Qc;  // compute-type tables [ns][nqm], [ns][nqc][ng]
+    double *Vm, *Vc;      // [ns][n_elem] outputs (either may be null)
 };
 
-struct GatherArgs {
-    int64_t nnz;
-    const uint32_t *src_upper, *seg_ptr, *seg_val;
-    const double *Vm, *Vc;
+struct FusedArgs {
+    FormInputs in;
+    const int32_t *tconn;       // [np][n_elem], tile order
+    const int32_t *elem_order;  // tile position -> element id
+    const void *Qm, *Qc;
+    const void *Qfrag;          // Q^T in MFMA B-operand order (matrix-core variant)
+    const uint4 *rec;           // reduction records {target, c0|c1, c2|c3, c4|c5}
+    const int64_t *rec_ptr;     // [n_tiles + 1]
+    const uint16_t *ovf;        // overflow contribution lists
+    const int64_t *ovf_ptr;     // [n_tiles + 1]
+    double *M, *C;              // CSR values (either may be null)
+    double *Mpart, *Cpart;      // partials of slots shared between tiles
+};
+
+struct FixupArgs {
+    int64_t n_fix;
+    const int32_t *fix_ptr;     // [n_fix + 1] ranges of fix_idx
+    const int32_t *fix_target;  // [n_fix] CSR slot (ascending)
+    const int32_t *fix_idx;     // partial indices, ascending tile order per output
+    const double *Mpart, *Cpart;
     double *M, *C;
 };
 
@@ -37,7 +74,9 @@ struct ExpandArgs {
 
 bool form_supported(int D, int P, int nqm, int nqc);
 hipError_t launch_form(const FormArgs &a, int D, int P, int nqm, int nqc, int precision, hipStream_t st);
-hipError_t launch_gather(const GatherArgs &a, hipStream_t st);
 hipError_t launch_expand(const ExpandArgs &a, hipStream_t st);
+hipError_t launch_fused(const FusedArgs &a, int64_t n_tiles, int D, int P, int nqm, int nqc, int precision,
+                        hipStream_t st);
+hipError_t launch_fixup(const FixupArgs &a, hipStream_t st);
 
 }  // namespace qxa

@@ -4,9 +4,9 @@
 //   2. CSR pattern: row i holds every j that shares an element with i
 //      (Section 3, step 2: compact support), sorted, structural zeros kept;
 //   3. the element-entry -> CSR-slot permutation for the distinct symmetric
-//      pairs of every element, and its inverse as slot-sorted segments; every
-//      segment lists contributions in ascending (element, pair) order, which
-//      fixes the summation order of the scatter once per mesh.
+//      pairs of every element (upper-triangle slot), and the mirror map
+//      (i,j) -> (j,i); the tile plan turns these into the fixed summation
+//      order of the scatter.
 #include <algorithm>
 #include <thread>
 
@@ -99,27 +99,11 @@ qxa_status build_host_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
                 hp.perm_sym[size_t(s) * n_elem + e] = slot_of(std::min(i, j), std::max(i, j));
             }
     });
-    // inverse: slot-sorted segments (counting sort keyed by slot, stable in (e, s))
-    hp.seg_ptr.assign(hp.nnz + 1, 0);
-    for (size_t k = 0; k < hp.perm_sym.size(); ++k) hp.seg_ptr[hp.perm_sym[k] + 1]++;
-    for (int64_t t = 0; t < hp.nnz; ++t) hp.seg_ptr[t + 1] += hp.seg_ptr[t];
-    hp.seg_val.resize(hp.perm_sym.size());
-    {
-        std::vector<uint32_t> fill(hp.seg_ptr.begin(), hp.seg_ptr.end() - 1);
-        for (int64_t e = 0; e < n_elem; ++e)
-            for (int s = 0; s < ns; ++s) {
-                const uint32_t t = hp.perm_sym[size_t(s) * n_elem + e];
-                hp.seg_val[fill[t]++] = uint32_t(s) * uint32_t(n_elem) + uint32_t(e);
-            }
-    }
-    // lower-triangle slots read the segment of their transposed twin
-    hp.src_upper.resize(hp.nnz);
+    // mirror slot of every slot (the pattern is structurally symmetric)
+    hp.mirror.resize(hp.nnz);
     parallel_for(n_nodes, [&](int64_t lo, int64_t hi) {
         for (int64_t r = lo; r < hi; ++r)
-            for (int64_t t = hp.row_ptr[r]; t < hp.row_ptr[r + 1]; ++t) {
-                const int32_t c = hp.col_idx[t];
-                hp.src_upper[t] = (c >= r) ? uint32_t(t) : slot_of(c, int32_t(r));
-            }
+            for (int64_t t = hp.row_ptr[r]; t < hp.row_ptr[r + 1]; ++t) hp.mirror[t] = slot_of(hp.col_idx[t], int32_t(r));
     });
     return QXA_OK;
 }

@@ -60,15 +60,43 @@ struct HostPlan {
     // Element-entry -> CSR slot for every symmetric pair s of every element:
     // perm[s * n_elem + e] = slot of (min(i,j), max(i,j)) (upper triangle).
     std::vector<uint32_t> perm_sym;
-    // Segments over all CSR slots: slot t reads the contribution list of its
-    // upper-triangle twin src_upper[t]; seg_ptr over upper slots lists the
-    // V indices s*n_elem + e in ascending (e, s) order.
-    std::vector<uint32_t> seg_ptr;    // [nnz + 1], empty segments for lower slots
-    std::vector<uint32_t> seg_val;    // V indices
-    std::vector<uint32_t> src_upper;  // [nnz]
+    std::vector<uint32_t> mirror;     // [nnz]: slot of (j, i) for slot (i, j)
 };
 
 qxa_status build_host_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, const int32_t *conn, HostPlan &hp);
+
+// Tile decomposition for the fused kernel.
+struct TilePlan {
+    int T = 0;
+    int64_t n_tiles = 0;
+    std::vector<int32_t> elem_order;  // tile position -> element id (Morton order of centroids)
+    std::vector<int32_t> tconn;       // [np][n_elem] connectivity in tile order
+    // One 16-byte record per output of a tile: {target, c0|c1, c2|c3, c4|c5}.
+    // target >= 0: a CSR slot owned by the tile (upper and mirror entries are
+    // separate records with the same contributions); target < 0: partial
+    // -(p + 1) of an upper slot shared between tiles. c0..c5: padded LDS
+    // indices (s*(T+1) + local element) of the contributions in summation
+    // order, 0xFFFF = none; c5 = 0x8000 | off when there are more than 6: then
+    // c0..c4 are inline and ovf[ovf_ptr[tile] + off] = count, then the rest.
+    // Owned records come first in ascending CSR slot order (coalesced
+    // stores), then the tile's partials, numbered consecutively.
+    std::vector<uint32_t> rec;        // [4 * n_records]
+    std::vector<int64_t> rec_ptr;     // [n_tiles + 1] (in records)
+    std::vector<uint16_t> ovf;
+    std::vector<int64_t> ovf_ptr;     // [n_tiles + 1]
+    // fix-up outputs (upper and mirror entries of shared slots) in ascending
+    // CSR slot order: fix_ptr[k]..fix_ptr[k+1] index fix_idx, the partials of
+    // fix_target[k] in ascending tile order
+    std::vector<int32_t> fix_ptr;     // [n_fix + 1]
+    std::vector<int32_t> fix_target;  // [n_fix]
+    std::vector<int32_t> fix_idx;     // [2 * n_partials] (each partial read by upper and mirror)
+    int64_t n_shared = 0;
+    int64_t n_partials = 0;
+};
+
+qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, const int32_t *conn,
+                           const double *coords, const HostPlan &hp, int T, TilePlan &tp);
+qxa_status check_tile_plan(int np, int64_t n_elem, const HostPlan &hp, const TilePlan &tp);
 
 }  // namespace qxa
 
@@ -80,6 +108,7 @@ struct qxa_mesh_s {
     double *d_coords = nullptr;   // [dim][n_nodes]
     int32_t *d_conn = nullptr;    // [np][n_elem]
     std::vector<int32_t> h_conn;  // host copy for plan building
+    std::vector<double> h_coords; // host copy for plan building (element order)
     size_t device_bytes = 0;
 };
 
@@ -89,13 +118,23 @@ struct qxa_plan_s {
     int64_t nnz = 0;
     int64_t *d_row_ptr = nullptr;
     int32_t *d_col_idx = nullptr;
-    uint32_t *d_seg_ptr = nullptr;
-    uint32_t *d_seg_val = nullptr;
-    uint32_t *d_src_upper = nullptr;
+    // fused-path tile plan (device copies)
+    int tile_T = 0;
+    int64_t n_tiles = 0, n_shared = 0, n_partials = 0;
+    int32_t *d_tconn = nullptr, *d_elem_order = nullptr;
+    uint32_t *d_rec = nullptr;
+    int64_t *d_rec_ptr = nullptr;
+    uint16_t *d_ovf = nullptr;
+    int64_t *d_ovf_ptr = nullptr;
+    int32_t *d_fix_ptr = nullptr, *d_fix_target = nullptr, *d_fix_idx = nullptr;
+    int64_t n_fix = 0;
+    double *d_part = nullptr;     // [2][n_partials]
+    double *d_qfrag = nullptr;    // Q^T in MFMA operand order (FP64)
+    float *d_qfrag_f = nullptr;   // same, FP32
     double *d_tables = nullptr;   // device copy of w, Phi, Qm, Qc (FP64)
     float *d_tables_f = nullptr;  // FP32 copy
     size_t off_wm = 0, off_wc = 0, off_phim = 0, off_phic = 0, off_qm = 0, off_qc = 0;
-    double *d_V = nullptr;        // [2][ns][n_elem] element-matrix buffer (two-pass path)
+    double *d_V = nullptr;        // [2][ns][n_elem] formation-only buffer (allocated on first use)
     int *d_flags = nullptr;       // device status flags (non-finite)
     size_t device_bytes = 0;
     double build_ms = 0.0;

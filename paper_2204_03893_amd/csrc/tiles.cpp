@@ -1,0 +1,309 @@
+// Tile plan for the fused formation + scatter kernel (Algorithm 2, Lines
+// 4-12 in one pass over the mesh).
+//
+// Elements are ordered along a Morton curve of their centroids and cut into
+// tiles of T consecutive elements. One workgroup forms the element matrices
+// of a tile in LDS and reduces, for every CSR slot the tile touches, the
+// tile's contributions in a fixed order. A slot whose contributions all come
+// from one tile is written by that tile (upper slot and its mirror); a slot
+// touched by several tiles gets one partial per tile, and the fix-up kernel
+// sums the partials in ascending tile order. Every slot is written exactly
+// once, with no atomics, so results are bitwise reproducible.
+#include <algorithm>
+#include <array>
+#include <atomic>
+#include <cmath>
+#include <thread>
+
+#include "qxa_internal.hpp"
+
+namespace qxa {
+
+template <class F>
+static void parallel_for(int64_t n, F &&f)
+{
+    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (n < 64 || nt == 1) {
+        f(int64_t(0), n);
+        return;
+    }
+    std::vector<std::thread> th;
+    int64_t chunk = (n + nt - 1) / nt;
+    for (unsigned t = 0; t < nt; ++t) {
+        int64_t lo = std::min<int64_t>(n, t * chunk), hi = std::min<int64_t>(n, lo + chunk);
+        if (lo < hi) th.emplace_back([&f, lo, hi] { f(lo, hi); });
+    }
+    for (auto &x : th) x.join();
+}
+
+static uint64_t spread_bits(uint64_t x, int dim)
+{
+    // interleave: bit b of x goes to bit dim*b
+    uint64_t r = 0;
+    for (int b = 0; b < 21; ++b) r |= ((x >> b) & 1ull) << (dim * b);
+    return r;
+}
+
+qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, const int32_t *conn,
+                           const double *coords, const HostPlan &hp, int T, TilePlan &tp)
+{
+    const int np = n_local(dim, order), ns = n_sym(np);
+    if (int64_t(T + 1) * ns >= 0x8000) return fail(QXA_E_UNSUPPORTED, "tile too large for 15-bit LDS indices");
+    tp.T = T;
+    tp.n_tiles = (n_elem + T - 1) / T;
+    // 1. Morton order of element centroids (vertices only: the map is affine)
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int k = 0; k < dim; ++k)
+        for (int64_t v = 0; v < n_nodes; ++v) {
+            lo[k] = std::min(lo[k], coords[size_t(k) * n_nodes + v]);
+            hi[k] = std::max(hi[k], coords[size_t(k) * n_nodes + v]);
+        }
+    const int bits = dim == 2 ? 21 : 21;
+    const double scale = double((1u << bits) - 1);
+    std::vector<std::pair<uint64_t, int32_t>> key(n_elem);
+    parallel_for(n_elem, [&](int64_t a, int64_t b) {
+        for (int64_t e = a; e < b; ++e) {
+            uint64_t code = 0;
+            for (int k = 0; k < dim; ++k) {
+                double c = 0.0;
+                for (int i = 0; i <= dim; ++i) c += coords[size_t(k) * n_nodes + conn[size_t(i) * n_elem + e]];
+                c /= (dim + 1);
+                const double t = (hi[k] > lo[k]) ? (c - lo[k]) / (hi[k] - lo[k]) : 0.0;
+                const uint64_t q = uint64_t(std::min(scale, std::max(0.0, std::floor(t * scale))));
+                code |= spread_bits(q, dim) << k;
+            }
+            key[e] = {code, int32_t(e)};
+        }
+    });
+    std::sort(key.begin(), key.end());
+    tp.elem_order.resize(n_elem);
+    for (int64_t p = 0; p < n_elem; ++p) tp.elem_order[p] = key[p].second;
+    key.clear();
+    key.shrink_to_fit();
+    tp.tconn.resize(size_t(np) * n_elem);
+    parallel_for(n_elem, [&](int64_t a, int64_t b) {
+        for (int64_t p = a; p < b; ++p)
+            for (int i = 0; i < np; ++i)
+                tp.tconn[size_t(i) * n_elem + p] = conn[size_t(i) * n_elem + tp.elem_order[p]];
+    });
+    // 2. per tile: sorted (upper slot, local element, pair) triples
+    const int64_t nt = tp.n_tiles;
+    auto tile_entries = [&](int64_t t, std::vector<uint64_t> &buf) {
+        // key = slot (32 bits) | lds index (16 bits): lds index = s*T + local element
+        buf.clear();
+        const int64_t p0 = t * T, p1 = std::min<int64_t>(n_elem, p0 + T);
+        for (int64_t p = p0; p < p1; ++p) {
+            const int64_t e = tp.elem_order[p];
+            for (int s = 0; s < ns; ++s) {
+                const uint64_t slot = hp.perm_sym[size_t(s) * n_elem + e];
+                const uint64_t lds = uint64_t(s) * (T + 1) + uint64_t(p - p0);
+                // order within a slot: ascending local element, then pair
+                const uint64_t ord = uint64_t(p - p0) * ns + s;
+                buf.push_back((slot << 32) | (ord << 16) | lds);
+            }
+        }
+        std::sort(buf.begin(), buf.end());
+    };
+    // touches per upper slot
+    std::vector<std::atomic<uint32_t>> touch(hp.nnz);
+    for (auto &x : touch) x.store(0, std::memory_order_relaxed);
+    parallel_for(nt, [&](int64_t a, int64_t b) {
+        std::vector<uint64_t> buf;
+        for (int64_t t = a; t < b; ++t) {
+            tile_entries(t, buf);
+            for (size_t k = 0; k < buf.size(); ++k)
+                if (k == 0 || (buf[k] >> 32) != (buf[k - 1] >> 32)) touch[buf[k] >> 32].fetch_add(1);
+        }
+    });
+    // 3. records per tile: owned outputs (upper and mirror) sorted by CSR slot,
+    //    then the tile's partials of shared upper slots
+    std::vector<std::vector<uint32_t>> trec(nt);
+    std::vector<std::vector<uint16_t>> tovf(nt);
+    std::vector<std::vector<uint32_t>> tshared(nt);  // upper slot of each partial, in partial order
+    std::atomic<bool> ovf_too_long{false};
+    parallel_for(nt, [&](int64_t a, int64_t b) {
+        std::vector<uint64_t> buf;
+        std::vector<std::pair<uint32_t, std::array<uint16_t, 6>>> owned;
+        std::vector<std::array<uint16_t, 6>> shared;
+        for (int64_t t = a; t < b; ++t) {
+            tile_entries(t, buf);
+            auto &O = tovf[t];
+            O.clear();
+            owned.clear();
+            shared.clear();
+            tshared[t].clear();
+            size_t k = 0;
+            while (k < buf.size()) {
+                const uint32_t u = uint32_t(buf[k] >> 32);
+                size_t k1 = k;
+                while (k1 < buf.size() && uint32_t(buf[k1] >> 32) == u) ++k1;
+                const size_t n = k1 - k;
+                std::array<uint16_t, 6> c;
+                c.fill(0xffff);
+                if (n <= 6) {
+                    for (size_t q = 0; q < n; ++q) c[q] = uint16_t(buf[k + q] & 0xffff);
+                } else {
+                    for (size_t q = 0; q < 5; ++q) c[q] = uint16_t(buf[k + q] & 0xffff);
+                    if (O.size() >= 0x7fff) ovf_too_long = true;
+                    c[5] = uint16_t(0x8000u | (uint32_t(O.size()) & 0x7fffu));
+                    O.push_back(uint16_t(n - 5));
+                    for (size_t q = 5; q < n; ++q) O.push_back(uint16_t(buf[k + q] & 0xffff));
+                }
+                if (touch[u].load() == 1) {
+                    owned.push_back({u, c});
+                    if (hp.mirror[u] != u) owned.push_back({hp.mirror[u], c});
+                } else {
+                    shared.push_back(c);
+                    tshared[t].push_back(u);
+                }
+                k = k1;
+            }
+            std::sort(owned.begin(), owned.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
+            auto &R = trec[t];
+            R.clear();
+            auto put = [&](uint32_t tgt, const std::array<uint16_t, 6> &c) {
+                R.push_back(tgt);
+                R.push_back(uint32_t(c[0]) | (uint32_t(c[1]) << 16));
+                R.push_back(uint32_t(c[2]) | (uint32_t(c[3]) << 16));
+                R.push_back(uint32_t(c[4]) | (uint32_t(c[5]) << 16));
+            };
+            for (auto &o : owned) put(o.first, o.second);
+            for (auto &c : shared) put(0u, c);  // partial index filled below
+        }
+    });
+    if (ovf_too_long) return fail(QXA_E_UNSUPPORTED, "tile overflow list longer than 15-bit offsets");
+    // partials: consecutive per tile, in ascending tile order
+    tp.rec_ptr.assign(nt + 1, 0);
+    tp.ovf_ptr.assign(nt + 1, 0);
+    std::vector<int64_t> part_base(nt + 1, 0);
+    for (int64_t t = 0; t < nt; ++t) {
+        tp.rec_ptr[t + 1] = tp.rec_ptr[t] + int64_t(trec[t].size() / 4);
+        tp.ovf_ptr[t + 1] = tp.ovf_ptr[t] + int64_t(tovf[t].size());
+        part_base[t + 1] = part_base[t] + int64_t(tshared[t].size());
+        const size_t n_owned = trec[t].size() / 4 - tshared[t].size();
+        for (size_t r = 0; r < tshared[t].size(); ++r)
+            trec[t][4 * (n_owned + r)] = uint32_t(-(part_base[t] + int64_t(r)) - 1);
+    }
+    tp.n_partials = part_base[nt];
+    if (tp.n_partials >= (int64_t(1) << 31)) return fail(QXA_E_UNSUPPORTED, "too many partials");
+    tp.rec.resize(4 * size_t(tp.rec_ptr[nt]));
+    tp.ovf.resize(size_t(tp.ovf_ptr[nt]));
+    parallel_for(nt, [&](int64_t a, int64_t b) {
+        for (int64_t t = a; t < b; ++t) {
+            std::copy(trec[t].begin(), trec[t].end(), tp.rec.begin() + 4 * tp.rec_ptr[t]);
+            std::copy(tovf[t].begin(), tovf[t].end(), tp.ovf.begin() + tp.ovf_ptr[t]);
+        }
+    });
+    // 4. fix-up outputs: every shared upper slot and its mirror, in CSR order,
+    //    each listing its partials in ascending tile order
+    std::vector<int32_t> sh_id(hp.nnz, -1);
+    std::vector<uint32_t> sh_slot;
+    for (int64_t u = 0; u < hp.nnz; ++u)
+        if (touch[u].load() > 1) {
+            sh_id[u] = int32_t(sh_slot.size());
+            sh_slot.push_back(uint32_t(u));
+        }
+    tp.n_shared = int64_t(sh_slot.size());
+    std::vector<int32_t> sptr(sh_slot.size() + 1, 0);
+    for (size_t f = 0; f < sh_slot.size(); ++f) sptr[f + 1] = sptr[f] + int32_t(touch[sh_slot[f]].load());
+    std::vector<int32_t> slist(sptr.back());
+    {
+        std::vector<int32_t> fill(sptr.begin(), sptr.end() - 1);
+        for (int64_t t = 0; t < nt; ++t)
+            for (size_t r = 0; r < tshared[t].size(); ++r) slist[fill[sh_id[tshared[t][r]]]++] = int32_t(part_base[t] + r);
+    }
+    std::vector<std::pair<uint32_t, int32_t>> fout;  // (target slot, shared id)
+    for (size_t f = 0; f < sh_slot.size(); ++f) {
+        const uint32_t u = sh_slot[f];
+        fout.push_back({u, int32_t(f)});
+        if (hp.mirror[u] != u) fout.push_back({hp.mirror[u], int32_t(f)});
+    }
+    std::sort(fout.begin(), fout.end());
+    tp.fix_ptr.assign(1, 0);
+    tp.fix_target.clear();
+    tp.fix_idx.clear();
+    for (auto &o : fout) {
+        tp.fix_target.push_back(int32_t(o.first));
+        for (int32_t k = sptr[o.second]; k < sptr[o.second + 1]; ++k) tp.fix_idx.push_back(slist[k]);
+        tp.fix_ptr.push_back(int32_t(tp.fix_idx.size()));
+    }
+    return QXA_OK;
+}
+
+}  // namespace qxa
+
+namespace qxa {
+
+// Structural check of a tile plan against the pattern: every index the fused
+// and fix-up kernels use is in bounds, every CSR slot is written exactly once
+// (by one tile or by the fix-up), every partial is written by exactly one tile
+// and read by exactly one shared slot, and every element entry is reduced
+// exactly once. Runs on the host before the plan is used.
+qxa_status check_tile_plan(int np, int64_t n_elem, const HostPlan &hp, const TilePlan &tp)
+{
+    const int ns = n_sym(np);
+    const int64_t T = tp.T, TP = T + 1;
+    std::vector<uint8_t> slot_w(hp.nnz, 0), part_w(tp.n_partials, 0), used;
+    std::vector<uint32_t> part_r(tp.n_partials, 0);
+    if (int64_t(tp.rec_ptr.size()) != tp.n_tiles + 1 || tp.rec_ptr[0] != 0 ||
+        int64_t(tp.ovf_ptr.size()) != tp.n_tiles + 1 || int64_t(tp.rec.size()) != 4 * tp.rec_ptr[tp.n_tiles])
+        return fail(QXA_E_INVALID, "tile plan: bad sizes");
+    auto write_slot = [&](int64_t g) -> bool { return g >= 0 && g < hp.nnz && slot_w[g]++ == 0; };
+    for (int64_t t = 0; t < tp.n_tiles; ++t) {
+        const int64_t p0 = t * T, nloc = std::min<int64_t>(T, n_elem - p0);
+        used.assign(size_t(TP) * ns, 0);
+        const int64_t ob = tp.ovf_ptr[t], oe = tp.ovf_ptr[t + 1];
+        auto valid = [&](uint32_t c) { return c < uint32_t(TP * ns) && int64_t(c % TP) < nloc; };
+        for (int64_t r = tp.rec_ptr[t]; r < tp.rec_ptr[t + 1]; ++r) {
+            const uint32_t *R = &tp.rec[4 * r];
+            const uint32_t c[6] = {R[1] & 0xffffu, R[1] >> 16, R[2] & 0xffffu, R[2] >> 16, R[3] & 0xffffu, R[3] >> 16};
+            std::vector<uint32_t> list;
+            for (int q = 0; q < 5; ++q)
+                if (c[q] != 0xffffu) list.push_back(c[q]);
+            if (c[5] != 0xffffu) {
+                if (c[5] < 0x8000u) {
+                    list.push_back(c[5]);
+                } else {
+                    const int64_t off = ob + (c[5] & 0x7fffu);
+                    if (off >= oe || off + int64_t(tp.ovf[off]) >= oe)
+                        return fail(QXA_E_INVALID, "tile plan: overflow list out of range");
+                    for (int q = 1; q <= tp.ovf[off]; ++q) list.push_back(tp.ovf[off + q]);
+                }
+            }
+            if (list.empty()) return fail(QXA_E_INVALID, "tile plan: empty record");
+            for (uint32_t x : list) {
+                if (!valid(x)) return fail(QXA_E_INVALID, "tile plan: LDS index out of range");
+                used[x] = 1;
+            }
+            const int32_t g = int32_t(R[0]);
+            if (g >= 0) {
+                if (!write_slot(g)) return fail(QXA_E_INVALID, "tile plan: slot written twice");
+            } else {
+                const int64_t pi = -int64_t(g) - 1;
+                if (pi >= tp.n_partials || part_w[pi]++) return fail(QXA_E_INVALID, "tile plan: partial written twice");
+            }
+        }
+        for (int64_t k = 0; k < nloc; ++k)
+            for (int s = 0; s < ns; ++s)
+                if (!used[size_t(s) * TP + k]) return fail(QXA_E_INVALID, "tile plan: contribution never reduced");
+    }
+    const int64_t nfix = int64_t(tp.fix_target.size());
+    if (int64_t(tp.fix_ptr.size()) != nfix + 1) return fail(QXA_E_INVALID, "tile plan: bad fix-up sizes");
+    for (int64_t f = 0; f < nfix; ++f) {
+        if (tp.fix_ptr[f + 1] - tp.fix_ptr[f] < 2) return fail(QXA_E_INVALID, "tile plan: shared slot with < 2 tiles");
+        for (int32_t k = tp.fix_ptr[f]; k < tp.fix_ptr[f + 1]; ++k) {
+            const int32_t pi = tp.fix_idx[k];
+            if (pi < 0 || pi >= tp.n_partials) return fail(QXA_E_INVALID, "tile plan: bad partial index");
+            part_r[pi]++;
+        }
+        if (!write_slot(tp.fix_target[f])) return fail(QXA_E_INVALID, "tile plan: fix-up slot written twice");
+    }
+    for (int64_t k = 0; k < tp.n_partials; ++k)
+        if (part_w[k] != 1 || part_r[k] < 1 || part_r[k] > 2)
+            return fail(QXA_E_INVALID, "tile plan: partial not written once / read by its slot");
+    for (int64_t t = 0; t < hp.nnz; ++t)
+        if (slot_w[t] != 1) return fail(QXA_E_INVALID, "tile plan: CSR slot not written exactly once");
+    return QXA_OK;
+}
+
+}  // namespace qxa

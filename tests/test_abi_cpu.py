@@ -62,3 +62,22 @@ def test_host_pattern_rejects_bad_index():
 def test_host_pattern_empty_mesh():
     rp, ci = qxa.pattern_host(2, 1, 5, np.zeros((3, 0), dtype=np.int32))
     assert ci.size == 0 and np.all(rp == 0)
+
+
+@pytest.mark.parametrize("dim,order,N", [(2, 1, 64), (2, 1, 7), (2, 2, 9), (2, 3, 5), (3, 1, 5), (3, 2, 3),
+                                         (3, 3, 2), (3, 2, 32)])
+def test_tile_plan_selfcheck(dim, order, N):
+    """Fused-kernel plan: every index in bounds, every CSR slot written exactly once."""
+    m = structured_mesh(dim, order, N, 0.2, seed=3)
+    nt, npart = qxa.plan_check_host(dim, order, m["coords"], m["conn"])
+    assert nt >= 1 and npart >= 0
+
+
+def test_tile_plan_selfcheck_relabelled_and_shuffled():
+    m = structured_mesh(3, 2, 4, 0.2, seed=4)
+    rng = np.random.default_rng(5)
+    sigma = rng.permutation(m["n_nodes"])
+    conn = sigma[m["conn"]].astype(np.int32)[:, rng.permutation(m["conn"].shape[1])]
+    X = np.empty_like(m["coords"])
+    X[:, sigma] = m["coords"]
+    qxa.plan_check_host(3, 2, X, conn)
