@@ -194,6 +194,21 @@ qxa_status qxa_element_matrices(qxa_plan plan, const qxa_coeff *mass, const qxa_
 qxa_status qxa_plan_set_timing(qxa_plan plan, int enable);
 qxa_status qxa_plan_timing_report(qxa_plan plan, char *buf, size_t cap);
 
+/*
+ * Reassembly graph (Section 4, summary: only the coefficient matrix S depends
+ * on the unknown, so Q, W, b and the sparsity data are reused and only the
+ * launches are replayed). Captures one qxa_assemble with these arguments into
+ * a HIP graph: the coefficient field pointers and the output arrays are baked
+ * in, so the caller updates the field contents in place between replays (on
+ * the replay stream, or synchronised with it). Outputs are overwritten by
+ * every replay and are bitwise equal to a direct qxa_assemble of the same
+ * inputs. The graph borrows the plan and the buffers; destroy it first.
+ */
+qxa_status qxa_graph_create(qxa_plan plan, const qxa_coeff *mass, const qxa_coeff *stiff, int precision,
+                            double *M_vals, double *C_vals, qxa_graph *out);
+qxa_status qxa_graph_launch(qxa_graph graph, void *stream);
+qxa_status qxa_graph_destroy(qxa_graph graph);
+
 /* Wait for `stream` and report device-side conditions (QXA_E_NONFINITE). */
 qxa_status qxa_sync(qxa_plan plan, void *stream);
 

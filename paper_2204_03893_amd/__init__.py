@@ -74,10 +74,14 @@ def lib():
         L.qxa_element_matrices.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), ci, vp, vp, vp]
         L.qxa_sync.argtypes = [vp, vp]
         L.qxa_plan_set_timing.argtypes = [vp, ci]
+        L.qxa_graph_create.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), ci, vp, vp, C.POINTER(vp)]
+        L.qxa_graph_launch.argtypes = [vp, vp]
+        L.qxa_graph_destroy.argtypes = [vp]
         L.qxa_plan_timing_report.argtypes = [vp, C.c_char_p, C.c_size_t]
         for name in ("qxa_mesh_create", "qxa_mesh_destroy", "qxa_plan_create", "qxa_plan_destroy",
                      "qxa_plan_get_info", "qxa_plan_copy_pattern", "qxa_assemble", "qxa_element_matrices",
-                     "qxa_sync", "qxa_pattern_host", "qxa_plan_check_host", "qxa_plan_set_timing", "qxa_plan_timing_report"):
+                     "qxa_sync", "qxa_pattern_host", "qxa_plan_check_host", "qxa_plan_set_timing", "qxa_plan_timing_report", "qxa_graph_create", "qxa_graph_launch",
+                     "qxa_graph_destroy"):
             getattr(L, name).restype = ci
         _lib = L
     return _lib
@@ -274,6 +278,38 @@ def element_matrices(plan: Plan, law_m, law_c, field_m=None, field_c=None, preci
     check(lib().qxa_element_matrices(plan.handle, C.byref(cm), C.byref(cc), _precision(precision), _ptr(Vm),
                                      _ptr(Vc), _stream_ptr(stream)))
     return Vm, Vc
+
+
+class ReassemblyGraph:
+    """One assembly captured in a HIP graph; update the fields in place, then launch()."""
+
+    def __init__(self, plan: Plan, law_m, law_c, field_m=None, field_c=None, precision="fp64", M=None, Cv=None,
+                 qpoint=False):
+        import torch
+        dev = torch.device("cuda", plan.mesh.device)
+        self.plan = plan
+        self.M = M if M is not None else torch.empty(plan.nnz, dtype=torch.float64, device=dev)
+        self.Cv = Cv if Cv is not None else torch.empty(plan.nnz, dtype=torch.float64, device=dev)
+        cm, self._k1 = make_coeff(law_m, field_m, qpoint)
+        cc, self._k2 = make_coeff(law_c, field_c, qpoint)
+        self.handle = C.c_void_p()
+        check(lib().qxa_graph_create(plan.handle, C.byref(cm), C.byref(cc), _precision(precision), _ptr(self.M),
+                                     _ptr(self.Cv), C.byref(self.handle)))
+
+    def launch(self, stream=None):
+        check(lib().qxa_graph_launch(self.handle, _stream_ptr(stream)))
+        return self.M, self.Cv
+
+    def close(self):
+        if self.handle:
+            lib().qxa_graph_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def sync(plan: Plan, stream=None):

@@ -62,6 +62,112 @@ static qxa_status to_coeff(const qxa_coeff *c, CoeffDev &out, const char *which)
     return QXA_OK;
 }
 
+static uint16_t bf16_bits(float x)
+{
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+    return uint16_t(u >> 16);
+}
+static float bf16_value(uint16_t b)
+{
+    const uint32_t u = uint32_t(b) << 16;
+    float x;
+    std::memcpy(&x, &u, 4);
+    return x;
+}
+static uint16_t f16_bits(float x)
+{
+    const _Float16 h = _Float16(x);
+    uint16_t b;
+    std::memcpy(&b, &h, 2);
+    return b;
+}
+static float f16_value(uint16_t b)
+{
+    _Float16 h;
+    std::memcpy(&h, &b, 2);
+    return float(h);
+}
+
+// Q^T fragments in MFMA B-operand order for every precision form.
+//   FP64 / FP32 (16x16x4): [ks][nb][lane], lane l of block (ks, nb) holds
+//     Q[s = 16 nb + l % 16][k = 4 ks + l / 16];
+//   split forms (16x16x32): [component][ks][nb][lane][8], lane l holds
+//     Q[s = 16 nb + l % 16][k = 32 ks + 8 (l / 16) + t], t = 0..7, as the
+//     hi / lo (/ mid) terms of its 16-bit split.
+// Mass block first, then stiffness; zero outside the tables.
+static void build_qfrags(const RefTables &T, std::vector<uint8_t> (&out)[5], double (&f16_qinv)[2])
+{
+    const int nb_ = (T.ns + 15) / 16, kc = T.nq_c * T.ng;
+    // FP16 keeps 5 exponent bits: each table is scaled by 2^k so that its largest
+    // entry lies in [2^13, 2^14), keeping small products out of the subnormals
+    double f16_scale[2];
+    for (int blk = 0; blk < 2; ++blk) {
+        const std::vector<double> &Q = blk == 0 ? T.Qm : T.Qc;
+        double mx = 0.0;
+        for (double x : Q) mx = std::max(mx, std::fabs(x));
+        const int e = mx > 0.0 ? std::ilogb(mx) : 0;
+        f16_scale[blk] = std::ldexp(1.0, 13 - e);
+        f16_qinv[blk] = std::ldexp(1.0, e - 13);
+    }
+    auto qval = [&](int blk, int s, int k) -> double {
+        if (s >= T.ns) return 0.0;
+        if (blk == 0) return k < T.nq_m ? T.Qm[size_t(s) * T.nq_m + k] : 0.0;
+        return k < kc ? T.Qc[size_t(s) * kc + k] : 0.0;
+    };
+    const int K[2] = {T.nq_m, kc};
+    // plain forms
+    for (int f = 0; f < 2; ++f) {
+        std::vector<uint8_t> &o = out[f];
+        for (int blk = 0; blk < 2; ++blk) {
+            const int ks_n = (K[blk] + 3) / 4;
+            for (int ks = 0; ks < ks_n; ++ks)
+                for (int nb = 0; nb < nb_; ++nb)
+                    for (int l = 0; l < 64; ++l) {
+                        const double v = qval(blk, 16 * nb + l % 16, 4 * ks + l / 16);
+                        if (f == 0) {
+                            const uint8_t *b = reinterpret_cast<const uint8_t *>(&v);
+                            o.insert(o.end(), b, b + 8);
+                        } else {
+                            const float x = float(v);
+                            const uint8_t *b = reinterpret_cast<const uint8_t *>(&x);
+                            o.insert(o.end(), b, b + 4);
+                        }
+                    }
+        }
+        while (o.size() % 16) o.push_back(0);
+    }
+    // split forms: F16X2 (index 2), BF16X2 (3), BF16X3 (4)
+    for (int f = 2; f < 5; ++f) {
+        const int nc = f == 4 ? 3 : 2;
+        std::vector<uint8_t> &o = out[f];
+        for (int blk = 0; blk < 2; ++blk) {
+            const int ks_n = (K[blk] + 31) / 32;
+            for (int c = 0; c < nc; ++c)
+                for (int ks = 0; ks < ks_n; ++ks)
+                    for (int nb = 0; nb < nb_; ++nb)
+                        for (int l = 0; l < 64; ++l)
+                            for (int t = 0; t < 8; ++t) {
+                                double v = qval(blk, 16 * nb + l % 16, 32 * ks + 8 * (l / 16) + t);
+                                uint16_t comp[3];
+                                if (f == 2) {
+                                    v *= f16_scale[blk];
+                                    comp[0] = f16_bits(float(v));
+                                    comp[1] = f16_bits(float(v - double(f16_value(comp[0]))));
+                                } else {
+                                    comp[0] = bf16_bits(float(v));
+                                    const double r1 = v - double(bf16_value(comp[0]));
+                                    comp[1] = bf16_bits(float(r1));
+                                    comp[2] = bf16_bits(float(r1 - double(bf16_value(comp[1]))));
+                                }
+                                o.push_back(uint8_t(comp[c] & 0xff));
+                                o.push_back(uint8_t(comp[c] >> 8));
+                            }
+        }
+    }
+}
+
 }  // namespace qxa
 
 using namespace qxa;
@@ -169,8 +275,7 @@ qxa_status qxa_plan_destroy(qxa_plan p)
     hipFree(p->d_fix_target);
     hipFree(p->d_fix_idx);
     hipFree(p->d_part);
-    hipFree(p->d_qfrag);
-    hipFree(p->d_qfrag_f);
+    for (auto *q : p->d_qfrag) hipFree(q);
     hipFree(p->d_tables);
     hipFree(p->d_tables_f);
     hipFree(p->d_V);
@@ -234,27 +339,12 @@ qxa_status qxa_plan_create(qxa_mesh mesh, const qxa_quad *mr, const qxa_quad *cr
     if (!st) st = upload(&p->d_fix_idx, tp.fix_idx.data(), tp.fix_idx.size(), acct);
     if (!st) st = dev_alloc(&p->d_part, size_t(2) * tp.n_partials, acct);
     if (!st && fused_uses_mfma(T.dim, T.order)) {
-        // Q^T fragments [(KSM+KSC)][NB][64]: lane l of block (ks, nb) holds
-        // Q[s = 16 nb + l % 16][k = 4 ks + l / 16] (zero outside the table)
-        const int nb_ = (T.ns + 15) / 16, ksm = (T.nq_m + 3) / 4, kc = T.nq_c * T.ng, ksc = (kc + 3) / 4;
-        std::vector<double> qf(size_t(ksm + ksc) * nb_ * 64, 0.0);
-        for (int ks = 0; ks < ksm + ksc; ++ks)
-            for (int nb = 0; nb < nb_; ++nb)
-                for (int l = 0; l < 64; ++l) {
-                    const int s = 16 * nb + l % 16;
-                    double v = 0.0;
-                    if (ks < ksm) {
-                        const int k = 4 * ks + l / 16;
-                        if (s < T.ns && k < T.nq_m) v = T.Qm[size_t(s) * T.nq_m + k];
-                    } else {
-                        const int k = 4 * (ks - ksm) + l / 16;
-                        if (s < T.ns && k < kc) v = T.Qc[size_t(s) * kc + k];
-                    }
-                    qf[(size_t(ks) * nb_ + nb) * 64 + l] = v;
-                }
-        std::vector<float> qff(qf.begin(), qf.end());
-        st = upload(&p->d_qfrag, qf.data(), qf.size(), acct);
-        if (!st) st = upload(&p->d_qfrag_f, qff.data(), qff.size(), acct);
+        std::vector<uint8_t> frag[5];
+        build_qfrags(T, frag, p->f16_qinv);
+        for (int f = 0; f < 5 && !st; ++f) {
+            p->qfrag_vec16[f] = int64_t(frag[f].size() / 16);
+            st = upload(reinterpret_cast<uint8_t **>(&p->d_qfrag[f]), frag[f].data(), frag[f].size(), acct);
+        }
     }
     // reference tables: FP64 block and FP32 copy of Q
     std::vector<double> tab;
@@ -363,8 +453,11 @@ qxa_status qxa_plan_copy_pattern(qxa_plan p, int64_t *row_ptr, int32_t *col_idx,
 static qxa_status fill_inputs(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *stiff, int precision,
                               FormInputs &in, const void **Qm, const void **Qc)
 {
-    if (precision != QXA_FP64 && precision != QXA_FP32)
-        return fail(QXA_E_UNSUPPORTED, "precision form not built");
+    if (precision < QXA_FP64 || precision > QXA_BF16X3) return fail(QXA_E_INVALID, "unknown precision form");
+    if (precision > QXA_FP32 && !fused_uses_mfma(p->ref.dim, p->ref.order))
+        return fail(QXA_E_UNSUPPORTED,
+                    "split 16-bit forms run on the matrix cores, used for the dense contractions (2D P2/P3, 3D P2); "
+                    "use QXA_FP32 as the reduced-precision form here");
     qxa_status st = to_coeff(mass, in.cm, "mass");
     if (!st) st = to_coeff(stiff, in.cc, "stiffness");
     if (st) return st;
@@ -405,7 +498,10 @@ qxa_status qxa_assemble(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *stif
     a.ovf_ptr = p->d_ovf_ptr;
     a.M = M_vals;
     a.C = C_vals;
-    a.Qfrag = precision == QXA_FP32 ? static_cast<const void *>(p->d_qfrag_f) : static_cast<const void *>(p->d_qfrag);
+    a.Qfrag = p->d_qfrag[precision];
+    a.qfrag_vec16 = p->qfrag_vec16[precision];
+    a.qinv_m = precision == QXA_F16X2 ? p->f16_qinv[0] : 1.0;
+    a.qinv_c = precision == QXA_F16X2 ? p->f16_qinv[1] : 1.0;
     a.Mpart = p->d_part;
     a.Cpart = p->d_part + p->n_partials;
     {
@@ -422,6 +518,8 @@ qxa_status qxa_element_matrices(qxa_plan p, const qxa_coeff *mass, const qxa_coe
                                 double *Vc, void *stream)
 {
     if (!p) return fail(QXA_E_INVALID, "null plan");
+    if (precision != QXA_FP64 && precision != QXA_FP32)
+        return fail(QXA_E_UNSUPPORTED, "the formation-only entry point computes in FP64 or FP32");
     FormArgs a{};
     qxa_status st = fill_inputs(p, mass, stiff, precision, a.in, &a.Qm, &a.Qc);
     if (st) return st;
@@ -479,6 +577,74 @@ qxa_status qxa_plan_timing_report(qxa_plan p, char *buf, size_t cap)
     out += "}";
     std::snprintf(buf, cap, "%s", out.c_str());
     return st;
+}
+
+}  // extern "C"
+
+struct qxa_graph_s {
+    qxa_plan plan = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+qxa_status qxa_graph_create(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *stiff, int precision, double *M_vals,
+                            double *C_vals, qxa_graph *out)
+{
+    if (!out) return fail(QXA_E_INVALID, "out is null");
+    *out = nullptr;
+    if (!p) return fail(QXA_E_INVALID, "null plan");
+    QXA_HIP(hipSetDevice(p->mesh->device));
+    hipStream_t s = nullptr;
+    QXA_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    const bool timing = p->timing;
+    p->timing = false;  // no event nodes inside the graph
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    qxa_status st = e == hipSuccess ? QXA_OK : hip_fail(e, "hipStreamBeginCapture");
+    hipGraph_t g = nullptr;
+    if (!st) {
+        st = qxa_assemble(p, mass, stiff, precision, M_vals, C_vals, s);
+        const std::string msg = st ? std::string(qxa_last_error()) : std::string();
+        e = hipStreamEndCapture(s, &g);
+        if (!st && e != hipSuccess) st = hip_fail(e, "hipStreamEndCapture");
+        if (st && !msg.empty()) fail(st, msg);
+    }
+    p->timing = timing;
+    hipStreamDestroy(s);
+    if (st) {
+        if (g) hipGraphDestroy(g);
+        return st;
+    }
+    auto *gr = new qxa_graph_s();
+    gr->plan = p;
+    gr->graph = g;
+    e = hipGraphInstantiate(&gr->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(g);
+        delete gr;
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    *out = gr;
+    return QXA_OK;
+}
+
+qxa_status qxa_graph_launch(qxa_graph g, void *stream)
+{
+    if (!g) return fail(QXA_E_INVALID, "null graph");
+    QXA_HIP(hipSetDevice(g->plan->mesh->device));
+    QXA_HIP(hipGraphLaunch(g->exec, reinterpret_cast<hipStream_t>(stream)));
+    return QXA_OK;
+}
+
+qxa_status qxa_graph_destroy(qxa_graph g)
+{
+    if (!g) return QXA_OK;
+    hipSetDevice(g->plan->mesh->device);
+    if (g->exec) hipGraphExecDestroy(g->exec);
+    if (g->graph) hipGraphDestroy(g->graph);
+    delete g;
+    return QXA_OK;
 }
 
 qxa_status qxa_sync(qxa_plan p, void *stream)

@@ -25,14 +25,6 @@ constexpr int tile_size(int D, int P)
     return (D == 3 && P == 3) ? 32 : (P >= 2) ? 128 : 256;
 }
 
-// Number of Q^T fragment values (mass then stiffness) of the matrix-core
-// variant: [(KSM + KSC)][NB][64], zero-padded.
-constexpr int64_t qfrag_count(int D, int P, int nqm, int nqc)
-{
-    const int np = D == 2 ? (P + 1) * (P + 2) / 2 : (P + 1) * (P + 2) * (P + 3) / 6;
-    const int ns = np * (np + 1) / 2, ng = D * (D + 1) / 2;
-    return int64_t((nqm + 3) / 4 + (nqc * ng + 3) / 4) * ((ns + 15) / 16) * 64;
-}
 bool fused_uses_mfma(int D, int P);
 
 struct FormArgs {
@@ -48,6 +40,8 @@ struct FusedArgs {
     const int32_t *elem_order;  // tile position -> element id
     const void *Qm, *Qc;
     const void *Qfrag;          // Q^T in MFMA B-operand order (matrix-core variant)
+    int64_t qfrag_vec16;        // size of Qfrag in 16-byte units
+    double qinv_m, qinv_c;      // inverse power-of-two scales of the FP16 Q tables (1 otherwise)
     const uint4 *rec;           // reduction records {target, c0|c1, c2|c3, c4|c5}
     const int64_t *rec_ptr;     // [n_tiles + 1]
     const uint16_t *ovf;        // overflow contribution lists

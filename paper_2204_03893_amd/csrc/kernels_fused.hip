@@ -11,6 +11,7 @@
 // ascending tile order. No float atomics: results are bitwise reproducible.
 #include <algorithm>
 
+#include "../../include/qxa.h"
 #include "kernels.hpp"
 #include "kernels_common.hpp"
 
@@ -20,7 +21,8 @@ namespace qxa {
 // staged matrices in the plan's order and write the target slot or partial.
 // Empty inline slots hold the index of a zero kept in LDS, so the six reads
 // are issued unconditionally (adding +0.0 leaves every sum unchanged).
-__device__ __forceinline__ void reduce_record(const uint4 R, const double *sVm, const double *sVc, uint32_t zero,
+template <typename ST>
+__device__ __forceinline__ void reduce_record(const uint4 R, const ST *sVm, const ST *sVc, uint32_t zero,
                                               const uint16_t *__restrict__ ovf, double *__restrict__ M,
                                               double *__restrict__ C, double *__restrict__ Mpart,
                                               double *__restrict__ Cpart)
@@ -33,8 +35,8 @@ __device__ __forceinline__ void reduce_record(const uint4 R, const double *sVm, 
     double vm[6], vc[6];
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
-        vm[q] = sVm[c[q]];
-        vc[q] = sVc[c[q]];
+        vm[q] = double(sVm[c[q]]);
+        vc[q] = double(sVc[c[q]]);
     }
     double am = vm[0], ac = vc[0];
 #pragma unroll
@@ -46,8 +48,8 @@ __device__ __forceinline__ void reduce_record(const uint4 R, const double *sVm, 
         const uint16_t *o = ovf + (c5 & 0x7fffu);
         const uint32_t n = o[0];
         for (uint32_t q = 1; q <= n; ++q) {
-            am += sVm[o[q]];
-            ac += sVc[o[q]];
+            am += double(sVm[o[q]]);
+            ac += double(sVc[o[q]]);
         }
     }
     const int32_t t = int32_t(R.x);
@@ -74,8 +76,9 @@ __device__ __forceinline__ void prefetch_records(const uint4 *__restrict__ rec, 
 
 // All records of a tile: the prefetched batch first, then the rest in
 // groups of kPrefetch independent loads.
+template <typename ST>
 __device__ __forceinline__ void tile_reduce(const uint4 (&pf)[kPrefetch], const FusedArgs &a, int64_t tile,
-                                            const double *sVm, const double *sVc, uint32_t zero, int stride)
+                                            const ST *sVm, const ST *sVc, uint32_t zero, int stride)
 {
     const int64_t r0 = a.rec_ptr[tile], r1 = a.rec_ptr[tile + 1];
     const uint16_t *ovf = a.ovf + a.ovf_ptr[tile];
@@ -179,28 +182,196 @@ __device__ __forceinline__ double xc_at(const double *lc, const double *A, int k
     return k < NQC * NG ? lc[k / NG] * A[k % NG] : 0.0;
 }
 
+// Split-precision operands of the 16 x 16 x 32 MFMA (gfx950): a value is
+// carried as a sum of 16-bit terms (hi + lo, or hi + mid + lo) and the
+// contraction keeps the products of total order < 2 (3 terms) or < 3 (6
+// terms), accumulated in FP32.
+typedef __bf16 qxa_bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 qxa_h8 __attribute__((ext_vector_type(8)));
+
+template <int PF>
+struct Split;
+template <>
+struct Split<QXA_BF16X2> {
+    using vec = qxa_bf8;
+    using elem = __bf16;
+    static constexpr int NC = 2;  // components
+    static constexpr int NT = 3;  // products: hh, hl, lh
+    static constexpr int pa[3] = {0, 0, 1}, pb[3] = {0, 1, 0};
+    static constexpr bool scaled = false;
+    static __device__ __forceinline__ void split(float x, __bf16 *c)
+    {
+        c[0] = __bf16(x);
+        c[1] = __bf16(x - float(c[0]));
+    }
+    static __device__ __forceinline__ qxa_f4 mfma(vec a, vec b, qxa_f4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct Split<QXA_BF16X3> {
+    using vec = qxa_bf8;
+    using elem = __bf16;
+    static constexpr int NC = 3;
+    static constexpr int NT = 6;  // hh, hm, mh, hl, mm, lh
+    static constexpr int pa[6] = {0, 0, 1, 0, 1, 2}, pb[6] = {0, 1, 0, 2, 1, 0};
+    static constexpr bool scaled = false;
+    static __device__ __forceinline__ void split(float x, __bf16 *c)
+    {
+        c[0] = __bf16(x);
+        const float r = x - float(c[0]);
+        c[1] = __bf16(r);
+        c[2] = __bf16(r - float(c[1]));
+    }
+    static __device__ __forceinline__ qxa_f4 mfma(vec a, vec b, qxa_f4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct Split<QXA_F16X2> {
+    using vec = qxa_h8;
+    using elem = _Float16;
+    static constexpr int NC = 2;
+    static constexpr int NT = 3;
+    static constexpr int pa[3] = {0, 0, 1}, pb[3] = {0, 1, 0};
+    static constexpr bool scaled = true;  // FP16 range: X is scaled per element by a power of two
+    static __device__ __forceinline__ void split(float x, _Float16 *c)
+    {
+        c[0] = _Float16(x);
+        c[1] = _Float16(x - float(c[0]));
+    }
+    static __device__ __forceinline__ qxa_f4 mfma(vec a, vec b, qxa_f4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+};
+
+// Contraction of one 16-element group, plain FP64/FP32 operands (16x16x4 MFMA).
+// xat(k) is the k-th entry of this lane's element's X column (compile-time k).
+template <typename CT, int K, int NB, int NS, int T, typename ST, class XAt>
+__device__ __forceinline__ void contract_group_plain(const CT *sQ, XAt &&xat, ST *sV, int lane, int col0)
+{
+    using MF = Mfma<CT>;
+    constexpr int KS = (K + 3) / 4;
+    const int j = lane >> 4, c16 = lane & 15;
+    typename MF::acc_t acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[nb] = typename MF::acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        const CT x = CT(sel4(j, xat(4 * ks), xat(4 * ks + 1), xat(4 * ks + 2), xat(4 * ks + 3)));
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[nb] = MF::step(x, sQ[(ks * NB + nb) * 64 + lane], acc[nb]);
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        const int s = 16 * nb + c16;
+        if (s < NS)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sV[s * (T + 1) + col0 + MF::row(lane, r)] = ST(acc[nb][r]);
+    }
+}
+
+// Contraction of one 16-element group with split 16-bit operands
+// (16x16x32 MFMA). Q^T fragments: [component][ks][nb][lane] x 8 values.
+template <int PF, int K, int NB, int NS, int T, typename ST, class XAt>
+__device__ __forceinline__ void contract_group_split(const uint4 *sQ, XAt &&xat, ST *sV, int lane, int col0,
+                                                     double qinv)
+{
+    using SP = Split<PF>;
+    using elem_t = typename SP::elem;
+    constexpr int KS = (K + 31) / 32;
+    const int j = lane >> 4, c16 = lane & 15;
+    // this lane's X entries k = 32 ks + 8 j + t, t = 0..7
+    double xv[KS][8];
+    double amax = 0.0;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            xv[ks][t] = sel4(j, xat(32 * ks + t), xat(32 * ks + 8 + t), xat(32 * ks + 16 + t), xat(32 * ks + 24 + t));
+            amax = fmax(amax, fabs(xv[ks][t]));
+        }
+    double scale = 1.0, inv = 1.0;
+    if constexpr (SP::scaled) {
+        // element-wide max over the 4 lanes holding the element (lanes c16 + 16 j)
+        amax = fmax(amax, __shfl_xor(amax, 16));
+        amax = fmax(amax, __shfl_xor(amax, 32));
+        if (amax > 0.0) {
+            const int e = ilogb(amax);
+            scale = ldexp(1.0, -e);
+            inv = ldexp(1.0, e);
+        }
+    }
+    typename SP::vec xc[KS][SP::NC];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            elem_t c[SP::NC];
+            SP::split(float(xv[ks][t] * scale), c);
+#pragma unroll
+            for (int q = 0; q < SP::NC; ++q) xc[ks][q][t] = c[q];
+        }
+    qxa_f4 acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[nb] = qxa_f4{0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int tm = 0; tm < SP::NT; ++tm) {
+                const uint4 qv = sQ[((SP::pb[tm] * KS + ks) * NB + nb) * 64 + lane];
+                acc[nb] = SP::mfma(xc[ks][SP::pa[tm]], __builtin_bit_cast(typename SP::vec, qv), acc[nb]);
+            }
+    // undo the element scale and the table scale: row r of this lane is element 4 (lane/16) + r
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const double ir = SP::scaled ? __shfl(inv, 4 * j + r) * qinv : 1.0;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const int s = 16 * nb + c16;
+            if (s < NS) sV[s * (T + 1) + col0 + 4 * j + r] = ST(double(acc[nb][r]) * ir);
+        }
+    }
+}
+
+template <int PF>
+struct FormTraits {
+    using stage_t = float;  // reduced forms stage V in FP32; CSR accumulation stays FP64
+    using qplain_t = float;
+};
+template <>
+struct FormTraits<QXA_FP64> {
+    using stage_t = double;
+    using qplain_t = double;
+};
+
 // T = 16 * (waves per workgroup): one 16-element group per wave.
-template <int D, int P, int NQM, int NQC, typename CT, int T>
+template <int D, int P, int NQM, int NQC, int PF, int T>
 __global__ __launch_bounds__(4 * T) void fused_mfma_kernel(FusedArgs a, int64_t n_tiles)
 {
     using S = Shape<D, P>;
-    using MF = Mfma<CT>;
+    using ST = typename FormTraits<PF>::stage_t;
+    constexpr bool SPLIT = PF >= QXA_F16X2;
     constexpr int NB = (S::NS + 15) / 16;
-    constexpr int KSM = (NQM + 3) / 4;
-    constexpr int KSC = (NQC * S::NG + 3) / 4;
+    constexpr int KM = NQM, KC = NQC * S::NG;
     extern __shared__ __align__(16) unsigned char smem[];
-    double *sVm = reinterpret_cast<double *>(smem);                                // [NS][T + 1]
-    double *sVc = sVm + S::NS * (T + 1);                                           // [NS][T + 1]
-    CT *sQ = reinterpret_cast<CT *>(smem + 2 * sizeof(double) * S::NS * (T + 1));  // [(KSM+KSC)][NB][64]
+    ST *sVm = reinterpret_cast<ST *>(smem);  // [NS][T + 1]
+    ST *sVc = sVm + S::NS * (T + 1);         // [NS][T + 1]
+    unsigned char *sQraw = smem + ((2 * sizeof(ST) * S::NS * (T + 1) + 15) / 16) * 16;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int j = lane >> 4, c16 = lane & 15;
     const int64_t ne = a.in.n_elem;
-
     {   // operand-ordered Q^T fragments, once per workgroup
-        const CT *gq = reinterpret_cast<const CT *>(a.Qfrag);
-        for (int k = tid; k < (KSM + KSC) * NB * 64; k += blockDim.x) sQ[k] = gq[k];
+        const uint4 *gq = reinterpret_cast<const uint4 *>(a.Qfrag);
+        uint4 *dq = reinterpret_cast<uint4 *>(sQraw);
+        for (int64_t k = tid; k < a.qfrag_vec16; k += blockDim.x) dq[k] = gq[k];
     }
-    if (tid == 0) sVm[T] = sVc[T] = 0.0;  // zero kept in the (unused) padding column of row 0
+    if (tid == 0) sVm[T] = sVc[T] = ST(0);  // zero kept in the (unused) padding column of row 0
     const bool need_eid = a.in.cm.kind == 2 || a.in.cc.kind == 2;
     TileWalk walk(n_tiles);
     int32_t v[S::NP];
@@ -234,41 +405,20 @@ __global__ __launch_bounds__(4 * T) void fused_mfma_kernel(FusedArgs a, int64_t 
         }
         if (walk.valid(tnext)) load_conn(tnext);  // in flight during the contraction
         lds_barrier();  // Q^T fragments ready (first tile) / staged V of the previous tile consumed
-        typename MF::acc_t acc[NB];
-        // V_m^T block: X_m^T (16 x 4 per step) times Q_m^T fragments
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[nb] = typename MF::acc_t{0, 0, 0, 0};
-#pragma unroll
-        for (int ks = 0; ks < KSM; ++ks) {
-            const CT x = CT(sel4(j, xm_at<NQM>(lm, 4 * ks), xm_at<NQM>(lm, 4 * ks + 1), xm_at<NQM>(lm, 4 * ks + 2),
-                                 xm_at<NQM>(lm, 4 * ks + 3)));
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) acc[nb] = MF::step(x, sQ[(ks * NB + nb) * 64 + lane], acc[nb]);
-        }
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            const int s = 16 * nb + c16;
-            if (s < S::NS)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) sVm[s * (T + 1) + 16 * wave + MF::row(lane, r)] = double(acc[nb][r]);
-        }
-        // V_c^T block: X_c^T = (Lambda_c (.) W)^T times Q_c^T fragments
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[nb] = typename MF::acc_t{0, 0, 0, 0};
-        const CT *qc = sQ + KSM * NB * 64;
-#pragma unroll
-        for (int ks = 0; ks < KSC; ++ks) {
-            const CT x = CT(sel4(j, xc_at<NQC, S::NG>(lc, A, 4 * ks), xc_at<NQC, S::NG>(lc, A, 4 * ks + 1),
-                                 xc_at<NQC, S::NG>(lc, A, 4 * ks + 2), xc_at<NQC, S::NG>(lc, A, 4 * ks + 3)));
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) acc[nb] = MF::step(x, qc[(ks * NB + nb) * 64 + lane], acc[nb]);
-        }
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            const int s = 16 * nb + c16;
-            if (s < S::NS)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) sVc[s * (T + 1) + 16 * wave + MF::row(lane, r)] = double(acc[nb][r]);
+        // V_m^T = X_m^T Q_m^T with X_m = Lambda_m; V_c^T = X_c^T Q_c^T with X_c = Lambda_c (.) W
+        auto xm = [&](int k) { return xm_at<NQM>(lm, k); };
+        auto xc = [&](int k) { return xc_at<NQC, S::NG>(lc, A, k); };
+        if constexpr (!SPLIT) {
+            using CT = typename FormTraits<PF>::qplain_t;
+            const CT *q = reinterpret_cast<const CT *>(sQraw);
+            contract_group_plain<CT, KM, NB, S::NS, T, ST>(q, xm, sVm, lane, 16 * wave);
+            contract_group_plain<CT, KC, NB, S::NS, T, ST>(q + ((KM + 3) / 4) * NB * 64, xc, sVc, lane, 16 * wave);
+        } else {
+            const uint4 *q = reinterpret_cast<const uint4 *>(sQraw);
+            constexpr int NC = Split<PF>::NC;
+            contract_group_split<PF, KM, NB, S::NS, T, ST>(q, xm, sVm, lane, 16 * wave, a.qinv_m);
+            contract_group_split<PF, KC, NB, S::NS, T, ST>(q + NC * ((KM + 31) / 32) * NB * 64, xc, sVc, lane,
+                                                          16 * wave, a.qinv_c);
         }
         if (walk.valid(tnext)) gather_raw<D, P>(a.in, v, raw);  // in flight during the reduction
         lds_barrier();
@@ -310,6 +460,7 @@ static unsigned persistent_grid(K kernel, int block, size_t lds, int64_t n_tiles
     if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, lds) != hipSuccess || per_cu < 1)
         per_cu = 1;
+    (void)hipGetLastError();  // a failed occupancy query must not be reported as a launch error
     return unsigned(std::min<int64_t>(n_tiles, int64_t(cus) * per_cu));
 }
 
@@ -317,28 +468,38 @@ hipError_t launch_fused(const FusedArgs &a, int64_t n_tiles, int D, int P, int n
                         hipStream_t st)
 {
     if (n_tiles == 0) return hipSuccess;
-#define X(d, p, m, c)                                                                                          \
-    if (D == d && P == p && nqm == m && nqc == c) {                                                            \
-        constexpr int T = tile_size(d, p);                                                                     \
-        if constexpr (use_mfma<d, p>()) {                                                                      \
-            const size_t lds = 2 * size_t(T + 1) * Shape<d, p>::NS * sizeof(double) + qfrag_count(d, p, m, c) *    \
-                                   (precision == 1 ? sizeof(float) : sizeof(double));                          \
-            if (precision == 1) {                                                                              \
-                auto k = fused_mfma_kernel<d, p, m, c, float, T>;                                              \
-                k<<<persistent_grid(k, 4 * T, lds, n_tiles), 4 * T, lds, st>>>(a, n_tiles);                    \
-            } else {                                                                                           \
-                auto k = fused_mfma_kernel<d, p, m, c, double, T>;                                             \
-                k<<<persistent_grid(k, 4 * T, lds, n_tiles), 4 * T, lds, st>>>(a, n_tiles);                    \
-            }                                                                                                  \
-        } else {                                                                                               \
-            const size_t lds = 2 * size_t(T + 1) * Shape<d, p>::NS * sizeof(double);                            \
-            if (precision == 1) fused_kernel<d, p, m, c, float, T><<<unsigned(n_tiles), T, lds, st>>>(a);      \
-            else fused_kernel<d, p, m, c, double, T><<<unsigned(n_tiles), T, lds, st>>>(a);                    \
-        }                                                                                                      \
-        return hipGetLastError();                                                                              \
+#define QXA_LAUNCH_MFMA(d, p, m, c, PF)                                                                   \
+    {                                                                                                     \
+        constexpr int T = tile_size(d, p);                                                                \
+        using STg = typename FormTraits<PF>::stage_t;                                                     \
+        const size_t lds = ((2 * sizeof(STg) * Shape<d, p>::NS * (T + 1) + 15) / 16) * 16 +               \
+                           size_t(a.qfrag_vec16) * 16;                                                    \
+        auto k = fused_mfma_kernel<d, p, m, c, PF, T>;                                                    \
+        k<<<persistent_grid(k, 4 * T, lds, n_tiles), 4 * T, lds, st>>>(a, n_tiles);                       \
+    }
+#define X(d, p, m, c)                                                                                      \
+    if (D == d && P == p && nqm == m && nqc == c) {                                                        \
+        constexpr int T = tile_size(d, p);                                                                 \
+        if constexpr (use_mfma<d, p>()) {                                                                  \
+            switch (precision) {                                                                           \
+            case QXA_FP64: QXA_LAUNCH_MFMA(d, p, m, c, QXA_FP64) break;                                    \
+            case QXA_FP32: QXA_LAUNCH_MFMA(d, p, m, c, QXA_FP32) break;                                    \
+            case QXA_F16X2: QXA_LAUNCH_MFMA(d, p, m, c, QXA_F16X2) break;                                  \
+            case QXA_BF16X2: QXA_LAUNCH_MFMA(d, p, m, c, QXA_BF16X2) break;                                \
+            case QXA_BF16X3: QXA_LAUNCH_MFMA(d, p, m, c, QXA_BF16X3) break;                                \
+            default: return hipErrorInvalidValue;                                                          \
+            }                                                                                              \
+        } else {                                                                                           \
+            if (precision != QXA_FP64 && precision != QXA_FP32) return hipErrorInvalidValue;               \
+            const size_t lds = 2 * size_t(T + 1) * Shape<d, p>::NS * sizeof(double);                      \
+            if (precision == QXA_FP32) fused_kernel<d, p, m, c, float, T><<<unsigned(n_tiles), T, lds, st>>>(a); \
+            else fused_kernel<d, p, m, c, double, T><<<unsigned(n_tiles), T, lds, st>>>(a);                \
+        }                                                                                                  \
+        return hipGetLastError();                                                                          \
     }
     QXA_FORM_CASES(X)
 #undef X
+#undef QXA_LAUNCH_MFMA
     return hipErrorInvalidValue;
 }
 

@@ -129,8 +129,11 @@ struct qxa_plan_s {
     int32_t *d_fix_ptr = nullptr, *d_fix_target = nullptr, *d_fix_idx = nullptr;
     int64_t n_fix = 0;
     double *d_part = nullptr;     // [2][n_partials]
-    double *d_qfrag = nullptr;    // Q^T in MFMA operand order (FP64)
-    float *d_qfrag_f = nullptr;   // same, FP32
+    // Q^T in MFMA operand order, one block per precision form (FP64, FP32,
+    // F16X2, BF16X2, BF16X3), sizes in 16-byte units
+    void *d_qfrag[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    int64_t qfrag_vec16[5] = {0, 0, 0, 0, 0};
+    double f16_qinv[2] = {1.0, 1.0};  // FP16 tables are stored as Q * 2^k (mass, stiffness)
     double *d_tables = nullptr;   // device copy of w, Phi, Qm, Qc (FP64)
     float *d_tables_f = nullptr;  // FP32 copy
     size_t off_wm = 0, off_wc = 0, off_phim = 0, off_phic = 0, off_qm = 0, off_qc = 0;

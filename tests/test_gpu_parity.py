@@ -198,3 +198,36 @@ def test_empty_and_single_element_meshes():
     qxa.sync(p1)
     assert abs(M.sum().item() - 0.5) < 1e-15
     assert np.allclose(Cv.cpu().numpy(), [1, -0.5, -0.5, -0.5, 0.5, 0, -0.5, 0, 0.5], atol=1e-15)
+
+
+# Bounds from the arithmetic of each form (row-scaled, against the FP64 oracle):
+# FP32 and the three-term BF16 split carry ~24-bit operands, F16 hi+lo ~22 bits,
+# all with FP32 accumulation over K <= 96 terms; BF16 hi+lo carries ~16 bits.
+FORM_BOUNDS = {"fp32": 5e-6, "f16x2": 5e-6, "bf16x3": 5e-6, "bf16x2": 2e-4}
+
+
+@pytest.mark.parametrize("name,N", [("p2_3d_32", 6), ("p3_2d_1024", 24)])
+@pytest.mark.parametrize("form", ["fp32", "f16x2", "bf16x2", "bf16x3"])
+def test_reduced_precision_forms(name, N, form):
+    w = scaled(name, N)
+    _say("case", w.name, form)
+    mesh, r, u, plan, rp, ci, outs = _run(w, precision=form, reps=2)
+    rpo, cio, Mo, Co = oracle.assemble(mesh, r, r, w.mass_law, w.stiff_law, u, u)
+    assert np.array_equal(rp, rpo) and np.array_equal(ci, cio)
+    em = row_scaled_error(outs[0][0], Mo, rpo)
+    ec = row_scaled_error(outs[0][1], Co, rpo)
+    _say(f"{form} row-scaled error: mass {em:.3e} conductivity {ec:.3e}")
+    assert em <= FORM_BOUNDS[form] and ec <= FORM_BOUNDS[form]
+    assert np.array_equal(outs[0][0].view(np.uint64), outs[1][0].view(np.uint64))
+    assert np.array_equal(outs[0][1].view(np.uint64), outs[1][1].view(np.uint64))
+
+
+def test_split_forms_rejected_on_vector_alu_path():
+    qxa = _qxa()
+    w = scaled("p1_3d_96_heat", 3)
+    mesh, r, u = make_inputs(w)
+    plan = qxa.Plan(qxa.Mesh(w.dim, w.order, mesh["coords"], mesh["conn"]), r)
+    uf = torch.tensor(u, device="cuda")
+    with pytest.raises(qxa.QxaError) as ei:
+        qxa.assemble(plan, w.mass_law, w.stiff_law, uf, uf, precision="bf16x2")
+    assert ei.value.code == -6
