@@ -209,6 +209,90 @@ qxa_status qxa_graph_create(qxa_plan plan, const qxa_coeff *mass, const qxa_coef
 qxa_status qxa_graph_launch(qxa_graph graph, void *stream);
 qxa_status qxa_graph_destroy(qxa_graph graph);
 
+/*
+ * Serving: a continuous-batching assembly loop run by a worker thread of the
+ * library, for many independent jobs (mesh + rules + coefficients).
+ *
+ * - qxa_server_submit queues a job and returns a ticket at once (QXA_E_BUSY
+ *   when queue_capacity jobs are waiting).
+ * - Admission, in arrival order, takes an in-flight slot (max_inflight) and
+ *   the job's device buffers (both CSR value arrays, partial sums, a status
+ *   word) from a device-memory budget of hbm_budget_bytes, which also holds
+ *   the resident plans. The budget is one device allocation made at creation;
+ *   nothing in the serving loop allocates or frees device memory. A job that
+ *   does not fit waits until released results or evicted plans make room;
+ *   QXA_E_NOMEM only when it cannot fit even in an otherwise empty budget.
+ * - Plans (pattern, permutation, tiles, reference tables) stay resident in an
+ *   LRU cache keyed by mesh and rule pair: only S changes between assemblies
+ *   of one mesh (Section 4, summary), so a cache hit skips the plan build.
+ *   Plans of new meshes are built by a second thread while other jobs run.
+ *   Unreferenced plans are evicted (least recently used first) when the
+ *   budget is short or more than plan_cache_entries are resident.
+ * - Admitted jobs with fewer than batch_tile_limit element tiles that share a
+ *   kernel (dim, order, rules, precision QXA_FP64 or QXA_FP32) run together
+ *   in one persistent launch: a device job table maps each global tile to
+ *   (job, tile). Other jobs launch alone. Launches rotate over n_streams
+ *   streams (default priority) so that they overlap.
+ * - Each job's values are bitwise identical to qxa_assemble of the same job
+ *   alone: every CSR slot is summed by one thread in a fixed order, whatever
+ *   the batch.
+ * - qxa_server_poll returns completed jobs (including failed ones, with their
+ *   status). Every polled ticket must be released with qxa_server_release,
+ *   which returns its buffers to the budget. Results live on the device.
+ * Meshes must outlive the server; coefficient fields must stay valid and
+ * unchanged until the job completes. One server per device; all functions
+ * are thread-safe.
+ */
+typedef struct {
+    int device;
+    size_t hbm_budget_bytes;  /* plans + job buffers (0: 4 GiB)                       */
+    int max_inflight;         /* admitted, not yet completed jobs (0: 64)             */
+    int n_streams;            /* streams launches rotate over (0: 4)                  */
+    int64_t batch_tile_limit; /* jobs with fewer tiles are batched (0: 512)           */
+    int queue_capacity;       /* waiting jobs beyond which submit fails (0: 65536)    */
+    int plan_cache_entries;   /* resident plans kept (0: bounded by the budget only)  */
+} qxa_server_opts;
+
+typedef struct {
+    qxa_mesh mesh;
+    qxa_quad mass_rule, stiff_rule; /* host arrays, copied at submit                  */
+    qxa_coeff mass, stiff;          /* device fields read when the job runs           */
+    int precision;                  /* a qxa_precision                                */
+    uint64_t user_tag;              /* returned with the completion                   */
+} qxa_job;
+
+typedef struct {
+    uint64_t ticket, user_tag;
+    int status;               /* QXA_OK or the job's error                          */
+    int plan_cached;          /* 1: the plan was resident when the job arrived      */
+    int batched;              /* jobs in the launch that ran this one               */
+    int64_t n_nodes, nnz;
+    const double *M, *C;      /* device [nnz], valid until the ticket is released   */
+    const int64_t *row_ptr;   /* device [n_nodes+1], valid until released           */
+    const int32_t *col_idx;   /* device [nnz]                                       */
+    double queue_ms;          /* submit -> launch (host clock)                      */
+    double run_ms;            /* its launch on the device (HIP events)              */
+    double total_ms;          /* submit -> completion seen by the server            */
+    char message[160];        /* error text when status != QXA_OK                   */
+} qxa_completion;
+
+qxa_status qxa_server_create(const qxa_server_opts *opts, qxa_server *out);
+qxa_status qxa_server_submit(qxa_server server, const qxa_job *job, uint64_t *ticket);
+/* Up to `max` completions in completion order; *n_done = how many. */
+qxa_status qxa_server_poll(qxa_server server, qxa_completion *done, int max, int *n_done);
+/* Copies a completed job's values into caller device buffers (either may be NULL). */
+qxa_status qxa_server_copy_result(qxa_server server, uint64_t ticket, double *M_vals, double *C_vals, void *stream);
+qxa_status qxa_server_release(qxa_server server, uint64_t ticket);
+/* paused != 0: admit nothing (submissions still queue); 0: resume. */
+qxa_status qxa_server_pause(qxa_server server, int paused);
+/* counters: [0] submitted [1] completed [2] plan-cache hits [3] plan builds
+ * [4] evictions [5] launches [6] batched launches [7] most jobs in one launch
+ * [8] budget bytes in use [9] peak bytes in use [10] queued [11] in flight
+ * [12] budget bytes */
+qxa_status qxa_server_stats(qxa_server server, int64_t *counters, int n);
+/* Waits for launched work, drops jobs not yet launched, frees everything. */
+qxa_status qxa_server_destroy(qxa_server server);
+
 /* Wait for `stream` and report device-side conditions (QXA_E_NONFINITE). */
 qxa_status qxa_sync(qxa_plan plan, void *stream);
 

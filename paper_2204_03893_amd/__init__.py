@@ -49,6 +49,27 @@ class _PlanInfo(C.Structure):
                 ("n_partials", C.c_int64)]
 
 
+class _ServerOpts(C.Structure):
+    _fields_ = [("device", C.c_int), ("hbm_budget_bytes", C.c_size_t), ("max_inflight", C.c_int),
+                ("n_streams", C.c_int), ("batch_tile_limit", C.c_int64), ("queue_capacity", C.c_int),
+                ("plan_cache_entries", C.c_int)]
+
+
+class _Job(C.Structure):
+    _fields_ = [("mesh", C.c_void_p), ("mass_rule", _Quad), ("stiff_rule", _Quad), ("mass", _Coeff),
+                ("stiff", _Coeff), ("precision", C.c_int), ("user_tag", C.c_uint64)]
+
+
+class _Completion(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("user_tag", C.c_uint64), ("status", C.c_int), ("plan_cached", C.c_int),
+                ("batched", C.c_int), ("n_nodes", C.c_int64), ("nnz", C.c_int64), ("M", C.c_void_p),
+                ("C", C.c_void_p), ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("queue_ms", C.c_double),
+                ("run_ms", C.c_double), ("total_ms", C.c_double), ("message", C.c_char * 160)]
+
+
+SERVER_STATS = ("submitted", "completed", "plan_hits", "plan_builds", "evictions", "launches", "batched_launches",
+                "max_batch", "bytes_in_use", "peak_bytes", "queued", "in_flight", "budget_bytes")
+
 _lib = None
 
 
@@ -78,10 +99,19 @@ def lib():
         L.qxa_graph_launch.argtypes = [vp, vp]
         L.qxa_graph_destroy.argtypes = [vp]
         L.qxa_plan_timing_report.argtypes = [vp, C.c_char_p, C.c_size_t]
+        L.qxa_server_create.argtypes = [C.POINTER(_ServerOpts), C.POINTER(vp)]
+        L.qxa_server_submit.argtypes = [vp, C.POINTER(_Job), C.POINTER(C.c_uint64)]
+        L.qxa_server_poll.argtypes = [vp, C.POINTER(_Completion), ci, C.POINTER(ci)]
+        L.qxa_server_copy_result.argtypes = [vp, C.c_uint64, vp, vp, vp]
+        L.qxa_server_release.argtypes = [vp, C.c_uint64]
+        L.qxa_server_pause.argtypes = [vp, ci]
+        L.qxa_server_stats.argtypes = [vp, C.POINTER(i64), ci]
+        L.qxa_server_destroy.argtypes = [vp]
         for name in ("qxa_mesh_create", "qxa_mesh_destroy", "qxa_plan_create", "qxa_plan_destroy",
                      "qxa_plan_get_info", "qxa_plan_copy_pattern", "qxa_assemble", "qxa_element_matrices",
                      "qxa_sync", "qxa_pattern_host", "qxa_plan_check_host", "qxa_plan_set_timing", "qxa_plan_timing_report", "qxa_graph_create", "qxa_graph_launch",
-                     "qxa_graph_destroy"):
+                     "qxa_graph_destroy", "qxa_server_create", "qxa_server_submit", "qxa_server_poll",
+                     "qxa_server_copy_result", "qxa_server_release", "qxa_server_pause", "qxa_server_stats", "qxa_server_destroy"):
             getattr(L, name).restype = ci
         _lib = L
     return _lib
@@ -314,3 +344,97 @@ class ReassemblyGraph:
 
 def sync(plan: Plan, stream=None):
     check(lib().qxa_sync(plan.handle, _stream_ptr(stream)))
+
+
+class Server:
+    """Continuous-batching assembly server of the library (a worker thread in libqxa).
+
+    submit() returns a ticket; poll() returns completions (dicts); result()
+    copies a completed job's CSR values into new device tensors; every polled
+    ticket must be released. Coefficient fields are kept alive here until
+    their job completes.
+    """
+
+    def __init__(self, device=0, hbm_budget=4 << 30, max_inflight=64, n_streams=4, batch_tile_limit=512,
+                 queue_capacity=65536, plan_cache_entries=0):
+        o = _ServerOpts(int(device), int(hbm_budget), int(max_inflight), int(n_streams), int(batch_tile_limit),
+                        int(queue_capacity), int(plan_cache_entries))
+        self.device = device
+        self.handle = C.c_void_p()
+        check(lib().qxa_server_create(C.byref(o), C.byref(self.handle)))
+        self._keep = {}
+        self._nnz = {}
+
+    def submit(self, mesh: Mesh, rule_m, rule_c=None, law_m=("const", 1.0), law_c=("const", 1.0), field_m=None,
+               field_c=None, precision="fp64", tag=0, qpoint=False):
+        rule_c = rule_m if rule_c is None else rule_c
+        qm, km = _quad(rule_m, mesh.dim)
+        qc, kc = _quad(rule_c, mesh.dim)
+        cm, k1 = make_coeff(law_m, field_m, qpoint)
+        cc, k2 = make_coeff(law_c, field_c, qpoint)
+        job = _Job(mesh.handle, qm, qc, cm, cc, _precision(precision), int(tag))
+        t = C.c_uint64()
+        check(lib().qxa_server_submit(self.handle, C.byref(job), C.byref(t)))
+        self._keep[t.value] = (mesh, k1, k2)
+        return t.value
+
+    def poll(self, max_n=256):
+        buf = (_Completion * max_n)()
+        n = C.c_int()
+        check(lib().qxa_server_poll(self.handle, buf, max_n, C.byref(n)))
+        out = []
+        for c in buf[:n.value]:
+            self._keep.pop(c.ticket, None)
+            self._nnz[c.ticket] = int(c.nnz)
+            out.append({"ticket": c.ticket, "tag": c.user_tag, "status": c.status, "plan_cached": bool(c.plan_cached),
+                        "batched": c.batched, "n_nodes": c.n_nodes, "nnz": c.nnz, "queue_ms": c.queue_ms,
+                        "run_ms": c.run_ms, "total_ms": c.total_ms, "message": c.message.decode()})
+        return out
+
+    def result(self, ticket, stream=None):
+        """(M, C) of a completed job copied into new float64 device tensors (on `stream`)."""
+        import torch
+        nnz = self._nnz[ticket]
+        dev = torch.device("cuda", self.device)
+        M = torch.empty(nnz, dtype=torch.float64, device=dev)
+        Cv = torch.empty(nnz, dtype=torch.float64, device=dev)
+        check(lib().qxa_server_copy_result(self.handle, C.c_uint64(ticket), _ptr(M), _ptr(Cv), _stream_ptr(stream)))
+        return M, Cv
+
+    def release(self, ticket):
+        self._nnz.pop(ticket, None)
+        check(lib().qxa_server_release(self.handle, C.c_uint64(ticket)))
+
+    def pause(self, paused=True):
+        """Stop (True) or resume (False) admission; submissions keep queueing."""
+        check(lib().qxa_server_pause(self.handle, int(bool(paused))))
+
+    def wait(self, n, timeout_s=60.0):
+        """Poll until n completions have arrived (raises TimeoutError)."""
+        import time
+        out, t0 = [], time.perf_counter()
+        while len(out) < n:
+            got = self.poll()
+            out += got
+            if not got:
+                if time.perf_counter() - t0 > timeout_s:
+                    raise TimeoutError(f"{len(out)} of {n} jobs completed in {timeout_s} s: {self.stats()}")
+                time.sleep(0.0005)
+        return out
+
+    def stats(self):
+        v = (C.c_int64 * len(SERVER_STATS))()
+        check(lib().qxa_server_stats(self.handle, v, len(SERVER_STATS)))
+        return dict(zip(SERVER_STATS, list(v)))
+
+    def close(self):
+        if self.handle:
+            lib().qxa_server_destroy(self.handle)
+            self.handle = C.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,4 +1,5 @@
 // C-ABI of the assembly library: argument validation, ownership, launches.
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -45,6 +46,33 @@ static qxa_status upload(T **p, const T *src, size_t count, size_t &acct)
     if (st || count == 0) return st;
     QXA_HIP(hipMemcpy(*p, src, count * sizeof(T), hipMemcpyHostToDevice));
     return QXA_OK;
+}
+
+// Plan buffers: from the plan's arena when it has one, else hipMalloc.
+template <class T>
+static qxa_status plan_alloc(qxa_plan p, T **ptr, size_t count)
+{
+    if (!p->arena) return dev_alloc(ptr, count, p->device_bytes);
+    *ptr = nullptr;
+    if (count == 0) return QXA_OK;
+    *ptr = static_cast<T *>(p->arena->alloc(count * sizeof(T)));
+    if (!*ptr) return fail(QXA_E_NOMEM, "device memory budget exhausted");
+    p->device_bytes += DevArena::granule(count * sizeof(T));
+    return QXA_OK;
+}
+template <class T>
+static qxa_status plan_upload_buf(qxa_plan p, T **ptr, const T *src, size_t count)
+{
+    qxa_status st = plan_alloc(p, ptr, count);
+    if (st || count == 0) return st;
+    QXA_HIP(hipMemcpy(*ptr, src, count * sizeof(T), hipMemcpyHostToDevice));
+    return QXA_OK;
+}
+static void plan_free(qxa_plan p, void *ptr)
+{
+    if (!ptr) return;
+    if (p->arena) p->arena->release(ptr);
+    else hipFree(ptr);
 }
 
 static qxa_status to_coeff(const qxa_coeff *c, CoeffDev &out, const char *which)
@@ -230,7 +258,9 @@ qxa_status qxa_mesh_create(int device, int dim, int order, int64_t n_nodes, cons
         if (!(std::fabs(det) > 1e-14 * std::pow(lmax, dim)))
             return fail(QXA_E_DEGENERATE, "element " + std::to_string(e) + " is degenerate (|det B_e| ~ 0)");
     }
+    static std::atomic<uint64_t> serial{0};
     auto *m = new qxa_mesh_s();
+    m->serial = ++serial;
     m->device = device;
     m->dim = dim;
     m->order = order;
@@ -263,26 +293,115 @@ qxa_status qxa_plan_destroy(qxa_plan p)
 {
     if (!p) return QXA_OK;
     hipSetDevice(p->mesh->device);
-    hipFree(p->d_row_ptr);
-    hipFree(p->d_col_idx);
-    hipFree(p->d_tconn);
-    hipFree(p->d_elem_order);
-    hipFree(p->d_rec);
-    hipFree(p->d_rec_ptr);
-    hipFree(p->d_ovf);
-    hipFree(p->d_ovf_ptr);
-    hipFree(p->d_fix_ptr);
-    hipFree(p->d_fix_target);
-    hipFree(p->d_fix_idx);
-    hipFree(p->d_part);
-    for (auto *q : p->d_qfrag) hipFree(q);
-    hipFree(p->d_tables);
-    hipFree(p->d_tables_f);
-    hipFree(p->d_V);
-    hipFree(p->d_flags);
+    void *bufs[] = {p->d_row_ptr, p->d_col_idx, p->d_tconn, p->d_elem_order, p->d_rec, p->d_rec_ptr, p->d_ovf,
+                    p->d_ovf_ptr, p->d_fix_ptr, p->d_fix_target, p->d_fix_idx, p->d_part, p->d_qfrag[0],
+                    p->d_qfrag[1], p->d_qfrag[2], p->d_qfrag[3], p->d_qfrag[4], p->d_tables, p->d_tables_f,
+                    p->d_V, p->d_flags};
+    for (void *b : bufs) plan_free(p, b);
     delete p;
     return QXA_OK;
 }
+
+}  // extern "C"
+
+namespace qxa {
+
+qxa_status plan_stage(qxa_mesh mesh, const qxa_quad &mr, const qxa_quad &cr, PlanStaging &g)
+{
+    qxa_status st = build_ref_tables(mesh->dim, mesh->order, mr, cr, g.ref);
+    if (st) return st;
+    const RefTables &T = g.ref;
+    if (!form_supported(T.dim, T.order, T.nq_m, T.nq_c))
+        return fail(QXA_E_UNSUPPORTED, "no kernel built for dim=" + std::to_string(T.dim) + " order=" +
+                                           std::to_string(T.order) + " n_q(mass)=" + std::to_string(T.nq_m) +
+                                           " n_q(stiffness)=" + std::to_string(T.nq_c));
+    st = build_host_plan(mesh->dim, mesh->order, mesh->n_nodes, mesh->n_elem, mesh->h_conn.data(), g.hp);
+    if (st) return st;
+    st = build_tile_plan(mesh->dim, mesh->order, mesh->n_nodes, mesh->n_elem, mesh->h_conn.data(),
+                         mesh->h_coords.data(), g.hp, tile_size(mesh->dim, mesh->order), g.tp);
+    if (!st) st = check_tile_plan(T.np, mesh->n_elem, g.hp, g.tp);
+    if (st) return st;
+    g.mfma = fused_uses_mfma(T.dim, T.order);
+    if (g.mfma) build_qfrags(T, g.frag, g.f16_qinv);
+    // reference tables: FP64 block and an FP32 copy
+    auto put = [&](const std::vector<double> &v) {
+        size_t off = g.tab.size();
+        g.tab.insert(g.tab.end(), v.begin(), v.end());
+        while (g.tab.size() % 4) g.tab.push_back(0.0);
+        return off;
+    };
+    g.off_wm = put(T.w_m);
+    g.off_wc = put(T.w_c);
+    g.off_phim = put(T.phi_m);
+    g.off_phic = put(T.phi_c);
+    g.off_qm = put(T.Qm);
+    g.off_qc = put(T.Qc);
+    g.tabf.assign(g.tab.begin(), g.tab.end());
+    return QXA_OK;
+}
+
+qxa_status plan_upload(qxa_mesh mesh, const PlanStaging &g, DevArena *arena, bool own_scratch, qxa_plan *out)
+{
+    *out = nullptr;
+    QXA_HIP(hipSetDevice(mesh->device));
+    auto *p = new qxa_plan_s();
+    p->mesh = mesh;
+    p->arena = arena;
+    p->ref = g.ref;
+    const HostPlan &hp = g.hp;
+    const TilePlan &tp = g.tp;
+    p->nnz = hp.nnz;
+    p->tile_T = tp.T;
+    p->n_tiles = tp.n_tiles;
+    p->n_shared = tp.n_shared;
+    p->n_fix = int64_t(tp.fix_target.size());
+    p->n_partials = tp.n_partials;
+    qxa_status st = plan_upload_buf(p, &p->d_row_ptr, hp.row_ptr.data(), hp.row_ptr.size());
+    if (!st) st = plan_upload_buf(p, &p->d_col_idx, hp.col_idx.data(), hp.col_idx.size());
+    if (!st) st = plan_upload_buf(p, &p->d_tconn, tp.tconn.data(), tp.tconn.size());
+    if (!st) st = plan_upload_buf(p, &p->d_elem_order, tp.elem_order.data(), tp.elem_order.size());
+    if (!st) st = plan_upload_buf(p, &p->d_rec, tp.rec.data(), tp.rec.size());
+    if (!st) st = plan_upload_buf(p, &p->d_rec_ptr, tp.rec_ptr.data(), tp.rec_ptr.size());
+    if (!st) st = plan_upload_buf(p, &p->d_ovf, tp.ovf.data(), tp.ovf.size());
+    if (!st) st = plan_upload_buf(p, &p->d_ovf_ptr, tp.ovf_ptr.data(), tp.ovf_ptr.size());
+    if (!st) st = plan_upload_buf(p, &p->d_fix_ptr, tp.fix_ptr.data(), tp.fix_ptr.size());
+    if (!st) st = plan_upload_buf(p, &p->d_fix_target, tp.fix_target.data(), tp.fix_target.size());
+    if (!st) st = plan_upload_buf(p, &p->d_fix_idx, tp.fix_idx.data(), tp.fix_idx.size());
+    if (!st && own_scratch) st = plan_alloc(p, &p->d_part, size_t(2) * tp.n_partials);
+    if (g.mfma) {
+        p->f16_qinv[0] = g.f16_qinv[0];
+        p->f16_qinv[1] = g.f16_qinv[1];
+        for (int f = 0; f < 5 && !st; ++f) {
+            p->qfrag_vec16[f] = int64_t(g.frag[f].size() / 16);
+            st = plan_upload_buf(p, reinterpret_cast<uint8_t **>(&p->d_qfrag[f]), g.frag[f].data(), g.frag[f].size());
+        }
+    }
+    p->off_wm = g.off_wm;
+    p->off_wc = g.off_wc;
+    p->off_phim = g.off_phim;
+    p->off_phic = g.off_phic;
+    p->off_qm = g.off_qm;
+    p->off_qc = g.off_qc;
+    if (!st) st = plan_upload_buf(p, &p->d_tables, g.tab.data(), g.tab.size());
+    if (!st) st = plan_upload_buf(p, &p->d_tables_f, g.tabf.data(), g.tabf.size());
+    if (!st && own_scratch) {
+        st = plan_alloc(p, &p->d_flags, 1);
+        if (!st) {
+            hipError_t e = hipMemset(p->d_flags, 0, sizeof(int));
+            if (e != hipSuccess) st = hip_fail(e, "hipMemset");
+        }
+    }
+    if (st) {
+        qxa_plan_destroy(p);
+        return st;
+    }
+    *out = p;
+    return QXA_OK;
+}
+
+}  // namespace qxa
+
+extern "C" {
 
 qxa_status qxa_plan_create(qxa_mesh mesh, const qxa_quad *mr, const qxa_quad *cr, qxa_plan *out)
 {
@@ -291,89 +410,11 @@ qxa_status qxa_plan_create(qxa_mesh mesh, const qxa_quad *mr, const qxa_quad *cr
     if (!mesh || !mr || !cr) return fail(QXA_E_INVALID, "null mesh or rule");
     const auto t0 = std::chrono::steady_clock::now();
     QXA_HIP(hipSetDevice(mesh->device));
-    auto *p = new qxa_plan_s();
-    p->mesh = mesh;
-    qxa_status st = build_ref_tables(mesh->dim, mesh->order, *mr, *cr, p->ref);
-    if (st) {
-        delete p;
-        return st;
-    }
-    const RefTables &T = p->ref;
-    if (!form_supported(T.dim, T.order, T.nq_m, T.nq_c)) {
-        delete p;
-        return fail(QXA_E_UNSUPPORTED, "no kernel built for dim=" + std::to_string(T.dim) + " order=" +
-                                           std::to_string(T.order) + " n_q(mass)=" + std::to_string(T.nq_m) +
-                                           " n_q(stiffness)=" + std::to_string(T.nq_c));
-    }
-    HostPlan hp;
-    st = build_host_plan(mesh->dim, mesh->order, mesh->n_nodes, mesh->n_elem, mesh->h_conn.data(), hp);
-    if (st) {
-        delete p;
-        return st;
-    }
-    p->nnz = hp.nnz;
-    TilePlan tp;
-    st = build_tile_plan(mesh->dim, mesh->order, mesh->n_nodes, mesh->n_elem, mesh->h_conn.data(),
-                         mesh->h_coords.data(), hp, tile_size(mesh->dim, mesh->order), tp);
-    if (!st) st = check_tile_plan(T.np, mesh->n_elem, hp, tp);
-    if (st) {
-        delete p;
-        return st;
-    }
-    p->tile_T = tp.T;
-    p->n_tiles = tp.n_tiles;
-    p->n_shared = tp.n_shared;
-    p->n_fix = int64_t(tp.fix_target.size());
-    p->n_partials = tp.n_partials;
-    size_t &acct = p->device_bytes;
-    st = upload(&p->d_row_ptr, hp.row_ptr.data(), hp.row_ptr.size(), acct);
-    if (!st) st = upload(&p->d_col_idx, hp.col_idx.data(), hp.col_idx.size(), acct);
-    if (!st) st = upload(&p->d_tconn, tp.tconn.data(), tp.tconn.size(), acct);
-    if (!st) st = upload(&p->d_elem_order, tp.elem_order.data(), tp.elem_order.size(), acct);
-    if (!st) st = upload(&p->d_rec, tp.rec.data(), tp.rec.size(), acct);
-    if (!st) st = upload(&p->d_rec_ptr, tp.rec_ptr.data(), tp.rec_ptr.size(), acct);
-    if (!st) st = upload(&p->d_ovf, tp.ovf.data(), tp.ovf.size(), acct);
-    if (!st) st = upload(&p->d_ovf_ptr, tp.ovf_ptr.data(), tp.ovf_ptr.size(), acct);
-    if (!st) st = upload(&p->d_fix_ptr, tp.fix_ptr.data(), tp.fix_ptr.size(), acct);
-    if (!st) st = upload(&p->d_fix_target, tp.fix_target.data(), tp.fix_target.size(), acct);
-    if (!st) st = upload(&p->d_fix_idx, tp.fix_idx.data(), tp.fix_idx.size(), acct);
-    if (!st) st = dev_alloc(&p->d_part, size_t(2) * tp.n_partials, acct);
-    if (!st && fused_uses_mfma(T.dim, T.order)) {
-        std::vector<uint8_t> frag[5];
-        build_qfrags(T, frag, p->f16_qinv);
-        for (int f = 0; f < 5 && !st; ++f) {
-            p->qfrag_vec16[f] = int64_t(frag[f].size() / 16);
-            st = upload(reinterpret_cast<uint8_t **>(&p->d_qfrag[f]), frag[f].data(), frag[f].size(), acct);
-        }
-    }
-    // reference tables: FP64 block and FP32 copy of Q
-    std::vector<double> tab;
-    auto put = [&](const std::vector<double> &v) {
-        size_t off = tab.size();
-        tab.insert(tab.end(), v.begin(), v.end());
-        while (tab.size() % 4) tab.push_back(0.0);
-        return off;
-    };
-    p->off_wm = put(T.w_m);
-    p->off_wc = put(T.w_c);
-    p->off_phim = put(T.phi_m);
-    p->off_phic = put(T.phi_c);
-    p->off_qm = put(T.Qm);
-    p->off_qc = put(T.Qc);
-    std::vector<float> tabf(tab.begin(), tab.end());
-    if (!st) st = upload(&p->d_tables, tab.data(), tab.size(), acct);
-    if (!st) st = upload(&p->d_tables_f, tabf.data(), tabf.size(), acct);
-    if (!st) st = dev_alloc(&p->d_flags, 1, acct);
-    if (!st && p->d_flags) {
-        hipError_t e = hipMemset(p->d_flags, 0, sizeof(int));
-        if (e != hipSuccess) st = hip_fail(e, "hipMemset");
-    }
-    if (st) {
-        qxa_plan_destroy(p);
-        return st;
-    }
-    p->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    *out = p;
+    PlanStaging g;
+    qxa_status st = plan_stage(mesh, *mr, *cr, g);
+    if (!st) st = plan_upload(mesh, g, nullptr, true, out);
+    if (st) return st;
+    (*out)->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return QXA_OK;
 }
 
@@ -480,37 +521,59 @@ static qxa_status fill_inputs(qxa_plan p, const qxa_coeff *mass, const qxa_coeff
     return QXA_OK;
 }
 
-qxa_status qxa_assemble(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *stiff, int precision, double *M_vals,
-                        double *C_vals, void *stream)
+}  // extern "C"
+
+namespace qxa {
+
+qxa_status make_fused_args(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *stiff, int precision, double *M,
+                           double *C, double *part, int *flags, FusedArgs &a, FixupArgs &f)
 {
-    if (!p) return fail(QXA_E_INVALID, "null plan");
-    FusedArgs a{};
+    a = FusedArgs{};
     qxa_status st = fill_inputs(p, mass, stiff, precision, a.in, &a.Qm, &a.Qc);
     if (st) return st;
-    if (!M_vals && !C_vals) return QXA_OK;
-    QXA_HIP(hipSetDevice(p->mesh->device));
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    a.in.flags = flags;
     a.tconn = p->d_tconn;
     a.elem_order = p->d_elem_order;
     a.rec = reinterpret_cast<const uint4 *>(p->d_rec);
     a.rec_ptr = p->d_rec_ptr;
     a.ovf = p->d_ovf;
     a.ovf_ptr = p->d_ovf_ptr;
-    a.M = M_vals;
-    a.C = C_vals;
+    a.M = M;
+    a.C = C;
     a.Qfrag = p->d_qfrag[precision];
     a.qfrag_vec16 = p->qfrag_vec16[precision];
     a.qinv_m = precision == QXA_F16X2 ? p->f16_qinv[0] : 1.0;
     a.qinv_c = precision == QXA_F16X2 ? p->f16_qinv[1] : 1.0;
-    a.Mpart = p->d_part;
-    a.Cpart = p->d_part + p->n_partials;
+    a.Mpart = part;
+    a.Cpart = part ? part + p->n_partials : nullptr;
+    f = FixupArgs{p->n_fix, p->d_fix_ptr, p->d_fix_target, p->d_fix_idx, a.Mpart, a.Cpart, M, C};
+    return QXA_OK;
+}
+
+}  // namespace qxa
+
+extern "C" {
+
+qxa_status qxa_assemble(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *stiff, int precision, double *M_vals,
+                        double *C_vals, void *stream)
+{
+    if (!p) return fail(QXA_E_INVALID, "null plan");
+    if (!p->d_flags) return fail(QXA_E_INVALID, "plan is owned by a server");
+    FusedArgs a;
+    FixupArgs f;
+    qxa_status st = make_fused_args(p, mass, stiff, precision, M_vals, C_vals, p->d_part, p->d_flags, a, f);
+    if (st) return st;
+    if (!M_vals && !C_vals) return QXA_OK;
+    QXA_HIP(hipSetDevice(p->mesh->device));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     {
         TimedLaunch tl(p, "fused", s);
-        QXA_HIP(launch_fused(a, p->n_tiles, p->ref.dim, p->ref.order, p->ref.nq_m, p->ref.nq_c, precision, s));
+        const JobTable jt{a, nullptr, nullptr, 0, p->n_tiles};
+        QXA_HIP(launch_fused(jt, p->ref.dim, p->ref.order, p->ref.nq_m, p->ref.nq_c, precision, s));
     }
     TimedLaunch tl(p, "fixup", s);
-    FixupArgs f{p->n_fix, p->d_fix_ptr, p->d_fix_target, p->d_fix_idx, a.Mpart, a.Cpart, M_vals, C_vals};
-    QXA_HIP(launch_fixup(f, s));
+    const FixupTable ft{f, nullptr, nullptr, 0, p->n_fix};
+    QXA_HIP(launch_fixup(ft, s));
     return QXA_OK;
 }
 
@@ -527,7 +590,7 @@ qxa_status qxa_element_matrices(qxa_plan p, const qxa_coeff *mass, const qxa_coe
     QXA_HIP(hipSetDevice(p->mesh->device));
     const size_t ns = size_t(p->ref.ns), ne = size_t(p->mesh->n_elem);
     if (!p->d_V && ne) {
-        st = dev_alloc(&p->d_V, 2 * ns * ne, p->device_bytes);
+        st = plan_alloc(p, &p->d_V, 2 * ns * ne);
         if (st) return st;
     }
     a.conn = p->mesh->d_conn;

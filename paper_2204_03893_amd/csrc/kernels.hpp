@@ -5,6 +5,7 @@
 
 #include <cstdint>
 
+#include "../../include/qxa.h"
 #include "kernels_common.hpp"
 
 namespace qxa {
@@ -50,6 +51,19 @@ struct FusedArgs {
     double *Mpart, *Cpart;      // partials of slots shared between tiles
 };
 
+// Jobs of one launch: a single assembly is carried by value in `one`
+// (n_jobs == 0); a batch of assemblies that share a kernel (same shape,
+// rules and precision form) is a device array `jobs` with the running tile
+// count tile_end[j] (exclusive prefix). Workgroups map a global tile index
+// to (job, tile of the job).
+struct JobTable {
+    FusedArgs one;
+    const FusedArgs *jobs;
+    const int64_t *tile_end;
+    int n_jobs;
+    int64_t n_tiles;
+};
+
 struct FixupArgs {
     int64_t n_fix;
     const int32_t *fix_ptr;     // [n_fix + 1] ranges of fix_idx
@@ -57,6 +71,14 @@ struct FixupArgs {
     const int32_t *fix_idx;     // partial indices, ascending tile order per output
     const double *Mpart, *Cpart;
     double *M, *C;
+};
+
+struct FixupTable {
+    FixupArgs one;
+    const FixupArgs *jobs;
+    const int64_t *fix_end;  // running count of fix-up outputs (exclusive prefix)
+    int n_jobs;
+    int64_t n_fix;
 };
 
 struct ExpandArgs {
@@ -69,8 +91,12 @@ struct ExpandArgs {
 bool form_supported(int D, int P, int nqm, int nqc);
 hipError_t launch_form(const FormArgs &a, int D, int P, int nqm, int nqc, int precision, hipStream_t st);
 hipError_t launch_expand(const ExpandArgs &a, hipStream_t st);
-hipError_t launch_fused(const FusedArgs &a, int64_t n_tiles, int D, int P, int nqm, int nqc, int precision,
-                        hipStream_t st);
-hipError_t launch_fixup(const FixupArgs &a, hipStream_t st);
+hipError_t launch_fused(const JobTable &jt, int D, int P, int nqm, int nqc, int precision, hipStream_t st);
+hipError_t launch_fixup(const FixupTable &ft, hipStream_t st);
+
+// Argument blocks of one assembly with `plan` (validates the coefficients and
+// the precision form). part: [2][n_partials] partial sums; flags: one int.
+qxa_status make_fused_args(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *stiff, int precision, double *M,
+                           double *C, double *part, int *flags, FusedArgs &a, FixupArgs &f);
 
 }  // namespace qxa

@@ -98,15 +98,41 @@ __device__ __forceinline__ void tile_reduce(const uint4 (&pf)[kPrefetch], const 
     }
 }
 
-template <int D, int P, int NQM, int NQC, typename CT, int T>
-__global__ __launch_bounds__(T) void fused_kernel(FusedArgs a)
+// Job of global tile g (uniform across the workgroup) and the tile's index in
+// it; MULTI = false compiles the single-assembly launch (job carried by value).
+template <bool MULTI>
+__device__ __forceinline__ int job_of(const JobTable &jt, int64_t g, int64_t &local)
+{
+    if (!MULTI) {
+        local = g;
+        return -1;
+    }
+    int lo = 0, hi = jt.n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (jt.tile_end[mid] > g) hi = mid;
+        else lo = mid + 1;
+    }
+    local = g - (lo > 0 ? jt.tile_end[lo - 1] : 0);
+    return lo;
+}
+template <bool MULTI>
+__device__ __forceinline__ FusedArgs args_of(const JobTable &jt, int j)
+{
+    if constexpr (MULTI) return jt.jobs[j];
+    return jt.one;
+}
+
+template <int D, int P, int NQM, int NQC, typename CT, int T, bool MULTI>
+__global__ __launch_bounds__(T) void fused_kernel(JobTable jt)
 {
     using S = Shape<D, P>;
     extern __shared__ double sV[];  // [2][NS][T + 1] (row stride padded against bank conflicts)
     double *sVm = sV, *sVc = sV + S::NS * (T + 1);
     // the padding column of row 0 is never a contribution: keep a zero there
     if (threadIdx.x == 0) sVm[T] = sVc[T] = 0.0;
-    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    int64_t tile;
+    const FusedArgs a = args_of<MULTI>(jt, job_of<MULTI>(jt, xcd_tile(blockIdx.x, gridDim.x), tile));
     const int64_t p0 = tile * T;
     const int64_t ne = a.in.n_elem;
     const int lane = threadIdx.x;
@@ -351,8 +377,8 @@ struct FormTraits<QXA_FP64> {
 };
 
 // T = 16 * (waves per workgroup): one 16-element group per wave.
-template <int D, int P, int NQM, int NQC, int PF, int T>
-__global__ __launch_bounds__(4 * T) void fused_mfma_kernel(FusedArgs a, int64_t n_tiles)
+template <int D, int P, int NQM, int NQC, int PF, int T, bool MULTI>
+__global__ __launch_bounds__(4 * T) void fused_mfma_kernel(JobTable jt)
 {
     using S = Shape<D, P>;
     using ST = typename FormTraits<PF>::stage_t;
@@ -365,35 +391,44 @@ __global__ __launch_bounds__(4 * T) void fused_mfma_kernel(FusedArgs a, int64_t 
     unsigned char *sQraw = smem + ((2 * sizeof(ST) * S::NS * (T + 1) + 15) / 16) * 16;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int j = lane >> 4, c16 = lane & 15;
-    const int64_t ne = a.in.n_elem;
-    {   // operand-ordered Q^T fragments, once per workgroup
-        const uint4 *gq = reinterpret_cast<const uint4 *>(a.Qfrag);
+    {   // operand-ordered Q^T fragments, once per workgroup (shared by every job of the launch)
+        const FusedArgs a0 = args_of<MULTI>(jt, 0);
+        const uint4 *gq = reinterpret_cast<const uint4 *>(a0.Qfrag);
         uint4 *dq = reinterpret_cast<uint4 *>(sQraw);
-        for (int64_t k = tid; k < a.qfrag_vec16; k += blockDim.x) dq[k] = gq[k];
+        for (int64_t k = tid; k < a0.qfrag_vec16; k += blockDim.x) dq[k] = gq[k];
     }
     if (tid == 0) sVm[T] = sVc[T] = ST(0);  // zero kept in the (unused) padding column of row 0
-    const bool need_eid = a.in.cm.kind == 2 || a.in.cc.kind == 2;
-    TileWalk walk(n_tiles);
+    TileWalk walk(jt.n_tiles);
     int32_t v[S::NP];
     RawElem<D, P> raw;
-    auto load_conn = [&](int64_t tt) {
-        const int64_t pp = tt * T + 16 * wave + c16;
+    // connectivity and gathers of (global) tile g, for the lane's element
+    auto load_conn = [&](int64_t g) {
+        int64_t lt;
+        const FusedArgs b = args_of<MULTI>(jt, job_of<MULTI>(jt, g, lt));
+        const int64_t pp = lt * T + 16 * wave + c16;
 #pragma unroll
-        for (int i = 0; i < S::NP; ++i) v[i] = pp < ne ? a.tconn[i * ne + pp] : 0;
+        for (int i = 0; i < S::NP; ++i) v[i] = pp < b.in.n_elem ? b.tconn[i * b.in.n_elem + pp] : 0;
+    };
+    auto gather = [&](int64_t g) {
+        int64_t lt;
+        const FusedArgs b = args_of<MULTI>(jt, job_of<MULTI>(jt, g, lt));
+        gather_raw<D, P>(b.in, v, raw);
     };
     if (walk.valid(walk.t)) {
         load_conn(walk.t);
-        gather_raw<D, P>(a.in, v, raw);
+        gather(walk.t);
     }
-    for (int64_t tile = walk.t; walk.valid(tile); tile += walk.step) {
-        const int64_t tnext = tile + walk.step;
-        const int64_t p0 = tile * T;
-        const int64_t p = p0 + 16 * wave + c16;  // this lane's element (4 lanes per element)
+    for (int64_t g = walk.t; walk.valid(g); g += walk.step) {
+        const int64_t gnext = g + walk.step;
+        int64_t tile;
+        const FusedArgs a = args_of<MULTI>(jt, job_of<MULTI>(jt, g, tile));
+        const int64_t ne = a.in.n_elem;
+        const int64_t p = tile * T + 16 * wave + c16;  // this lane's element (4 lanes per element)
         uint4 pf[kPrefetch];
         prefetch_records(a.rec, a.rec_ptr[tile], a.rec_ptr[tile + 1], int(blockDim.x), pf);
         double A[S::NG], lm[NQM], lc[NQC];
         if (p < ne) {
-            const int64_t eid = need_eid ? int64_t(a.elem_order[p]) : p;
+            const int64_t eid = (a.in.cm.kind == 2 || a.in.cc.kind == 2) ? int64_t(a.elem_order[p]) : p;
             if (!setup_from_raw<D, P, NQM, NQC>(a.in, raw, v, eid, A, lm, lc) && j == 0) atomicOr(a.in.flags, 1);
         } else {
 #pragma unroll
@@ -403,7 +438,7 @@ __global__ __launch_bounds__(4 * T) void fused_mfma_kernel(FusedArgs a, int64_t 
 #pragma unroll
             for (int q = 0; q < NQC; ++q) lc[q] = 0.0;
         }
-        if (walk.valid(tnext)) load_conn(tnext);  // in flight during the contraction
+        if (walk.valid(gnext)) load_conn(gnext);  // in flight during the contraction
         lds_barrier();  // Q^T fragments ready (first tile) / staged V of the previous tile consumed
         // V_m^T = X_m^T Q_m^T with X_m = Lambda_m; V_c^T = X_c^T Q_c^T with X_c = Lambda_c (.) W
         auto xm = [&](int k) { return xm_at<NQM>(lm, k); };
@@ -420,7 +455,7 @@ __global__ __launch_bounds__(4 * T) void fused_mfma_kernel(FusedArgs a, int64_t 
             contract_group_split<PF, KC, NB, S::NS, T, ST>(q + NC * ((KM + 31) / 32) * NB * 64, xc, sVc, lane,
                                                           16 * wave, a.qinv_c);
         }
-        if (walk.valid(tnext)) gather_raw<D, P>(a.in, v, raw);  // in flight during the reduction
+        if (walk.valid(gnext)) gather(gnext);  // in flight during the reduction
         lds_barrier();
         tile_reduce(pf, a, tile, sVm, sVc, T, int(blockDim.x));
     }
@@ -428,10 +463,22 @@ __global__ __launch_bounds__(4 * T) void fused_mfma_kernel(FusedArgs a, int64_t 
 
 // Shared slots: each output (upper or mirror entry, ascending CSR order) sums
 // its partials in ascending tile order.
-__global__ __launch_bounds__(256) void fixup_kernel(FixupArgs a)
+__global__ __launch_bounds__(256) void fixup_kernel(FixupTable ft)
 {
-    const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (f >= a.n_fix) return;
+    int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (f >= ft.n_fix) return;
+    int jb = -1;
+    if (ft.n_jobs > 0) {
+        int lo = 0, hi = ft.n_jobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (ft.fix_end[mid] > f) hi = mid;
+            else lo = mid + 1;
+        }
+        f -= lo > 0 ? ft.fix_end[lo - 1] : 0;
+        jb = lo;
+    }
+    const FixupArgs a = jb < 0 ? ft.one : ft.jobs[jb];
     const int32_t lo = a.fix_ptr[f], hi = a.fix_ptr[f + 1];
     const int32_t t = a.fix_target[f];
     double m = 0.0, c = 0.0;
@@ -464,36 +511,47 @@ static unsigned persistent_grid(K kernel, int block, size_t lds, int64_t n_tiles
     return unsigned(std::min<int64_t>(n_tiles, int64_t(cus) * per_cu));
 }
 
-hipError_t launch_fused(const FusedArgs &a, int64_t n_tiles, int D, int P, int nqm, int nqc, int precision,
-                        hipStream_t st)
+hipError_t launch_fused(const JobTable &jt, int D, int P, int nqm, int nqc, int precision, hipStream_t st)
 {
+    const int64_t n_tiles = jt.n_tiles;
     if (n_tiles == 0) return hipSuccess;
-#define QXA_LAUNCH_MFMA(d, p, m, c, PF)                                                                   \
+    const FusedArgs &a = jt.one;  // the first job (Q^T fragment size is shared by all jobs)
+#define QXA_LAUNCH_MFMA(d, p, m, c, PF, MULTI)                                                            \
     {                                                                                                     \
         constexpr int T = tile_size(d, p);                                                                \
         using STg = typename FormTraits<PF>::stage_t;                                                     \
         const size_t lds = ((2 * sizeof(STg) * Shape<d, p>::NS * (T + 1) + 15) / 16) * 16 +               \
                            size_t(a.qfrag_vec16) * 16;                                                    \
-        auto k = fused_mfma_kernel<d, p, m, c, PF, T>;                                                    \
-        k<<<persistent_grid(k, 4 * T, lds, n_tiles), 4 * T, lds, st>>>(a, n_tiles);                       \
+        auto k = fused_mfma_kernel<d, p, m, c, PF, T, MULTI>;                                             \
+        k<<<persistent_grid(k, 4 * T, lds, n_tiles), 4 * T, lds, st>>>(jt);                               \
     }
 #define X(d, p, m, c)                                                                                      \
     if (D == d && P == p && nqm == m && nqc == c) {                                                        \
         constexpr int T = tile_size(d, p);                                                                 \
+        const bool multi = jt.n_jobs > 0;                                                                  \
+        if (multi && precision != QXA_FP64 && precision != QXA_FP32) return hipErrorInvalidValue;          \
         if constexpr (use_mfma<d, p>()) {                                                                  \
-            switch (precision) {                                                                           \
-            case QXA_FP64: QXA_LAUNCH_MFMA(d, p, m, c, QXA_FP64) break;                                    \
-            case QXA_FP32: QXA_LAUNCH_MFMA(d, p, m, c, QXA_FP32) break;                                    \
-            case QXA_F16X2: QXA_LAUNCH_MFMA(d, p, m, c, QXA_F16X2) break;                                  \
-            case QXA_BF16X2: QXA_LAUNCH_MFMA(d, p, m, c, QXA_BF16X2) break;                                \
-            case QXA_BF16X3: QXA_LAUNCH_MFMA(d, p, m, c, QXA_BF16X3) break;                                \
+            switch (precision * 2 + int(multi)) {                                                          \
+            case 2 * QXA_FP64: QXA_LAUNCH_MFMA(d, p, m, c, QXA_FP64, false) break;                         \
+            case 2 * QXA_FP64 + 1: QXA_LAUNCH_MFMA(d, p, m, c, QXA_FP64, true) break;                      \
+            case 2 * QXA_FP32: QXA_LAUNCH_MFMA(d, p, m, c, QXA_FP32, false) break;                         \
+            case 2 * QXA_FP32 + 1: QXA_LAUNCH_MFMA(d, p, m, c, QXA_FP32, true) break;                      \
+            case 2 * QXA_F16X2: QXA_LAUNCH_MFMA(d, p, m, c, QXA_F16X2, false) break;                       \
+            case 2 * QXA_BF16X2: QXA_LAUNCH_MFMA(d, p, m, c, QXA_BF16X2, false) break;                     \
+            case 2 * QXA_BF16X3: QXA_LAUNCH_MFMA(d, p, m, c, QXA_BF16X3, false) break;                     \
             default: return hipErrorInvalidValue;                                                          \
             }                                                                                              \
         } else {                                                                                           \
             if (precision != QXA_FP64 && precision != QXA_FP32) return hipErrorInvalidValue;               \
             const size_t lds = 2 * size_t(T + 1) * Shape<d, p>::NS * sizeof(double);                      \
-            if (precision == QXA_FP32) fused_kernel<d, p, m, c, float, T><<<unsigned(n_tiles), T, lds, st>>>(a); \
-            else fused_kernel<d, p, m, c, double, T><<<unsigned(n_tiles), T, lds, st>>>(a);                \
+            const unsigned grid = unsigned(n_tiles);                                                       \
+            if (precision == QXA_FP32) {                                                                   \
+                if (multi) fused_kernel<d, p, m, c, float, T, true><<<grid, T, lds, st>>>(jt);              \
+                else fused_kernel<d, p, m, c, float, T, false><<<grid, T, lds, st>>>(jt);                  \
+            } else {                                                                                       \
+                if (multi) fused_kernel<d, p, m, c, double, T, true><<<grid, T, lds, st>>>(jt);             \
+                else fused_kernel<d, p, m, c, double, T, false><<<grid, T, lds, st>>>(jt);                 \
+            }                                                                                              \
         }                                                                                                  \
         return hipGetLastError();                                                                          \
     }
@@ -503,10 +561,10 @@ hipError_t launch_fused(const FusedArgs &a, int64_t n_tiles, int D, int P, int n
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_fixup(const FixupArgs &a, hipStream_t st)
+hipError_t launch_fixup(const FixupTable &ft, hipStream_t st)
 {
-    if (a.n_fix == 0) return hipSuccess;
-    fixup_kernel<<<unsigned((a.n_fix + 255) / 256), 256, 0, st>>>(a);
+    if (ft.n_fix == 0) return hipSuccess;
+    fixup_kernel<<<unsigned((ft.n_fix + 255) / 256), 256, 0, st>>>(ft);
     return hipGetLastError();
 }
 

@@ -4,7 +4,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <utility>
 #include <vector>
 
@@ -98,10 +101,54 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
                            const double *coords, const HostPlan &hp, int T, TilePlan &tp);
 qxa_status check_tile_plan(int np, int64_t n_elem, const HostPlan &hp, const TilePlan &tp);
 
+// First-fit sub-allocator over one device allocation (256-byte granules,
+// free ranges coalesced). Thread-safe. Serves the server's resident plans and
+// job buffers so that their total never exceeds the budget it was given and
+// no allocation or free in the serving loop synchronises the device.
+class DevArena {
+public:
+    ~DevArena();
+    qxa_status init(size_t bytes);
+    void *alloc(size_t bytes);  // nullptr when no free range is large enough
+    void release(void *p);
+    size_t used() const { return used_; }
+    size_t peak() const { return peak_; }
+    size_t capacity() const { return cap_; }
+    static size_t granule(size_t bytes) { return (bytes + 255) & ~size_t(255); }
+
+private:
+    std::mutex mu_;
+    char *base_ = nullptr;
+    size_t cap_ = 0, used_ = 0, peak_ = 0;
+    std::map<size_t, size_t> free_;            // offset -> length
+    std::unordered_map<size_t, size_t> live_;  // offset -> length
+};
+
+// Everything of a plan that is computed on the host (reference tables, CSR
+// pattern, tile plan, operand-ordered Q^T), before any device allocation.
+struct PlanStaging {
+    RefTables ref;
+    HostPlan hp;
+    TilePlan tp;
+    bool mfma = false;
+    std::vector<uint8_t> frag[5];
+    double f16_qinv[2] = {1.0, 1.0};
+    std::vector<double> tab;
+    std::vector<float> tabf;
+    size_t off_wm = 0, off_wc = 0, off_phim = 0, off_phic = 0, off_qm = 0, off_qc = 0;
+};
+
+qxa_status plan_stage(qxa_mesh mesh, const qxa_quad &mr, const qxa_quad &cr, PlanStaging &out);
+// Uploads a staged plan. With an arena every buffer comes from it (QXA_E_NOMEM
+// when it is full) and the plan keeps no scratch of its own (own_scratch =
+// false: the caller brings partial-sum and flag buffers per assembly).
+qxa_status plan_upload(qxa_mesh mesh, const PlanStaging &stg, DevArena *arena, bool own_scratch, qxa_plan *out);
+
 }  // namespace qxa
 
 // Opaque handles ------------------------------------------------------------
 struct qxa_mesh_s {
+    uint64_t serial = 0;          // unique per mesh created in this process
     int device = 0;
     int dim = 0, order = 0, np = 0;
     int64_t n_nodes = 0, n_elem = 0;
@@ -114,6 +161,7 @@ struct qxa_mesh_s {
 
 struct qxa_plan_s {
     qxa_mesh mesh = nullptr;
+    qxa::DevArena *arena = nullptr;  // device buffers come from here when set
     qxa::RefTables ref;
     int64_t nnz = 0;
     int64_t *d_row_ptr = nullptr;
