@@ -65,6 +65,120 @@ def cpu_baseline(w, mesh, rule, u, budget_s=20.0):
             "sample": f"{reps} full assemblies of the same workload ({w.name}), {total:.1f} s"}
 
 
+def serving_pool(n_pool, max_elements, seed=2204):
+    """Heterogeneous request meshes: (dim, order) uniform over {2,3} x {1,2,3}, element count
+    log-uniform on [1e3, max_elements], interior vertices jittered by 0.2h; per mesh four smooth
+    random fields (16 random Fourier features), conductivity exp(g) or 1 + g^2, mass 1, and the
+    rule exact to degree 2P for both matrices."""
+    import numpy as np
+    from workloads import rule, structured_mesh
+    from workloads.fields import gaussian_random_field
+    rng = np.random.default_rng([seed, 5])
+    out = []
+    for k in range(n_pool):
+        dim = int(rng.integers(2, 4))
+        order = int(rng.integers(1, 4))
+        ne = float(np.exp(rng.uniform(np.log(1e3), np.log(max_elements))))
+        N = max(2, int(round((ne / 2) ** 0.5 if dim == 2 else (ne / 6) ** (1 / 3))))
+        m = structured_mesh(dim, order, N, 0.2, seed=[seed, 6, k])
+        fields = [gaussian_random_field(m["coords"], 16, np.random.default_rng([seed, 7, k, j]), length=0.1)
+                  for j in range(4)]
+        law = ("exp", 0.0, 1.0) if rng.uniform() < 0.5 else ("poly2", 1.0, 0.0, 1.0)
+        out.append({"mesh": m, "dim": dim, "order": order, "rule": rule(dim, 2 * order), "fields": fields,
+                    "law_c": law, "entries": 2 * m["conn"].shape[1] * m["conn"].shape[0] ** 2})
+    return out
+
+
+def serving(args):
+    """Serving run: a resident pool of meshes (plans cached by a warm-up pass), then requests
+    picking a mesh and a field at random, at saturation (all queued at once) and at Poisson
+    arrivals with 50% and 80% of the saturation rate. Latency = completion seen by the server
+    - scheduled arrival. Prints one JSON line."""
+    import numpy as np
+    import torch
+    import paper_2204_03893_amd as qxa
+    t0 = time.perf_counter()
+    pool = serving_pool(args.pool, args.max_elements)
+    gen_s = time.perf_counter() - t0
+    dev = torch.device("cuda", 0)
+    srv = qxa.Server(hbm_budget=32 << 30, max_inflight=64, n_streams=4, batch_tile_limit=512)
+    for p in pool:
+        m = p["mesh"]
+        p["obj"] = qxa.Mesh(p["dim"], p["order"], m["coords"], m["conn"])
+        p["dev_fields"] = [torch.tensor(f, device=dev) for f in p["fields"]]
+    # warm-up: one job per mesh builds every plan (cold-miss cost, reported separately)
+    t0 = time.perf_counter()
+    for k, p in enumerate(pool):
+        u = p["dev_fields"][0]
+        srv.submit(p["obj"], p["rule"], p["rule"], ("const", 1.0), p["law_c"], u, u, precision=args.precision, tag=k)
+    warm = srv.wait(len(pool), timeout_s=600)
+    warm_s = time.perf_counter() - t0
+    bad = [c for c in warm if c["status"] != 0]
+    if bad:
+        raise RuntimeError(f"serving warm-up failed: {bad[0]}")
+    for c in warm:
+        srv.release(c["ticket"])
+    rng = np.random.default_rng([2204, 8])
+
+    def run(rate):
+        n = args.requests
+        picks = rng.integers(0, len(pool), size=n)
+        fsel = rng.integers(0, 4, size=n)
+        gaps = rng.exponential(1.0 / rate, size=n) if rate else np.zeros(n)
+        sched = np.cumsum(gaps)
+        lat, waits, entries, done = [], [], 0, 0
+        paused = not rate
+        if paused:
+            srv.pause(True)
+        t_start = time.perf_counter()
+        submit_late = {}
+        i = 0
+        while done < n:
+            now = time.perf_counter() - t_start
+            while i < n and sched[i] <= now:
+                p = pool[picks[i]]
+                u = p["dev_fields"][fsel[i]]
+                t = srv.submit(p["obj"], p["rule"], p["rule"], ("const", 1.0), p["law_c"], u, u,
+                               precision=args.precision, tag=i)
+                submit_late[t] = (time.perf_counter() - t_start - sched[i]) * 1e3
+                i += 1
+                now = time.perf_counter() - t_start
+            if not rate and i == n and paused:
+                srv.pause(False)
+                paused = False
+                t_start_sat = time.perf_counter()
+            for c in srv.poll():
+                if c["status"] != 0:
+                    raise RuntimeError(f"serving request failed: {c}")
+                lat.append(submit_late.pop(c["ticket"]) + c["total_ms"])
+                waits.append(c["queue_ms"])
+                entries += pool[picks[c["tag"]]]["entries"]
+                srv.release(c["ticket"])
+                done += 1
+            if i == n and done < n:
+                time.sleep(0.0001)
+        span = time.perf_counter() - (t_start_sat if not rate else t_start)
+        lat = np.array(lat)
+        return {"offered_jobs_per_s": rate, "jobs": n, "makespan_s": span, "jobs_per_s": n / span,
+                "entries_per_s": entries / span, "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+                "mean_queue_ms": float(np.mean(waits))}
+
+    sat = run(0.0)
+    loads = [run(f * sat["jobs_per_s"]) for f in (0.5, 0.8)]
+    st = srv.stats()
+    srv.close()
+    sizes = [p["mesh"]["conn"].shape[1] for p in pool]
+    out = {"metric": "serving element-matrix entries assembled/sec", "value": sat["entries_per_s"],
+           "unit": "entries/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+           "dtype": "f64" if args.precision == "fp64" else args.precision, "vs_baseline": None,
+           "config": {"workload": "serving mix", "pool_meshes": len(pool), "elements_min": min(sizes),
+                      "elements_max": max(sizes), "requests_per_load": args.requests, "precision": args.precision},
+           "saturation": sat, "loads": loads, "warmup_plan_builds_s": warm_s, "pool_generation_s": gen_s,
+           "server": st}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +189,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) to calibrate HBM byte counters")
+    ap.add_argument("--mode", choices=("assemble", "serving"), default="assemble")
+    ap.add_argument("--requests", type=int, default=1000, help="serving: requests per offered load")
+    ap.add_argument("--pool", type=int, default=48, help="serving: resident meshes")
+    ap.add_argument("--max-elements", type=float, default=3e5, help="serving: largest mesh (elements)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is a design "
@@ -92,6 +210,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 5}))
+        return
+
+    if args.mode == "serving":
+        serving(args)
         return
 
     import paper_2204_03893_amd as qxa

@@ -13,7 +13,7 @@
  *       V_c = Q_c X_c,  Q_c = [J_q (x) J_q]_q,        X_c = Lambda_c (Khatri-Rao) W
  *       Lambda = S * (w b^T),  b_e = |det B_e|,  W = [vec((B_e^T B_e)^{-1})]_e
  *     and forms the global matrices from V and the index sets N_e.
- *   - Section 4 (summary) notes that only S depends on the unknown, so the
+ *   - Section 5 (summary) notes that only S depends on the unknown, so the
  *     mesh-dependent data (pattern, permutation) is built once per mesh.
  *
  * All functions return a qxa_status (0 = success, negative = error) and never
@@ -58,9 +58,9 @@ typedef enum {
 } qxa_precision;
 
 /* Coefficient evaluation at the quadrature nodes, the matrices S_m, S_c of
- * Algorithm 2 (Section 4): constant (Line 5 skipped), a law applied to the
+ * Algorithm 2 (Section 4): constant (no evaluation needed), a law applied to the
  * interpolated nodal field u_h = phi^T u (solution-dependent coefficients,
- * Section 4 nonlinear FEM), or values given per (q, e). */
+ * Section 5), or values given per (q, e). */
 typedef enum { QXA_COEFF_CONST = 0, QXA_COEFF_NODAL = 1, QXA_COEFF_QPOINT = 2 } qxa_coeff_kind;
 typedef enum {
     QXA_LAW_IDENTITY = 0, /* s                     */
@@ -133,11 +133,11 @@ qxa_status qxa_mesh_destroy(qxa_mesh mesh);
 
 /*
  * Plan (built once per mesh and rule pair): the reference tables Phi, J_q,
- * Q_m, Q_c of Algorithm 2 (Lines 1-3; only the n_p(n_p+1)/2 rows of distinct
- * symmetric pairs, the symmetry saving of Section 6), the CSR pattern (all
+ * Q_m, Q_c of Algorithm 2 (only the n_p(n_p+1)/2 rows of distinct
+ * symmetric pairs, the symmetry saving of Section 7), the CSR pattern (all
  * (i,j) sharing an element; structural zeros kept), and the element-entry to
  * CSR-slot permutation with its slot-sorted segments that the deterministic
- * scatter uses (Algorithm 2, Line 12). The mesh must outlive the plan.
+ * scatter uses (the global assembly of Algorithm 2). The mesh must outlive the plan.
  * Rules may differ between the two matrices (Algorithm 2, "Input").
  */
 qxa_status qxa_plan_create(qxa_mesh mesh, const qxa_quad *mass_rule, const qxa_quad *stiff_rule, qxa_plan *out);
@@ -164,7 +164,7 @@ qxa_status qxa_plan_check_host(int dim, int order, int64_t n_nodes, const double
 qxa_status qxa_plan_copy_pattern(qxa_plan plan, int64_t *row_ptr, int32_t *col_idx, void *stream);
 
 /*
- * One assembly (Algorithm 2, Lines 4-12): geometry b, W from the mesh,
+ * One assembly (Algorithm 2 after its reference tables): geometry b, W from the mesh,
  * coefficients S at the quadrature nodes, Lambda, X, V = Q X, then the
  * deterministic segmented-reduction scatter into CSR values (no float
  * atomics; bitwise identical across runs). M_vals / C_vals: caller-owned
@@ -176,7 +176,7 @@ qxa_status qxa_assemble(qxa_plan plan, const qxa_coeff *mass, const qxa_coeff *s
                         double *C_vals, void *stream);
 
 /*
- * Formation only (Algorithm 2, Lines 4-11): V_m and V_c as device arrays
+ * Formation only (the element matrices of Algorithm 2): V_m and V_c as device arrays
  * [n_p*n_p][n_elem] (entry (i*n_p+j, e) at index (i*n_p+j)*n_elem + e; the
  * element matrices are symmetric so this is also the paper's column-major
  * vec). Either output may be NULL.
@@ -195,7 +195,7 @@ qxa_status qxa_plan_set_timing(qxa_plan plan, int enable);
 qxa_status qxa_plan_timing_report(qxa_plan plan, char *buf, size_t cap);
 
 /*
- * Reassembly graph (Section 4, summary: only the coefficient matrix S depends
+ * Reassembly graph (Section 5, summary: only the coefficient matrix S depends
  * on the unknown, so Q, W, b and the sparsity data are reused and only the
  * launches are replayed). Captures one qxa_assemble with these arguments into
  * a HIP graph: the coefficient field pointers and the output arrays are baked
@@ -224,7 +224,7 @@ qxa_status qxa_graph_destroy(qxa_graph graph);
  *   QXA_E_NOMEM only when it cannot fit even in an otherwise empty budget.
  * - Plans (pattern, permutation, tiles, reference tables) stay resident in an
  *   LRU cache keyed by mesh and rule pair: only S changes between assemblies
- *   of one mesh (Section 4, summary), so a cache hit skips the plan build.
+ *   of one mesh (Section 5, summary), so a cache hit skips the plan build.
  *   Plans of new meshes are built by a second thread while other jobs run.
  *   Unreferenced plans are evicted (least recently used first) when the
  *   budget is short or more than plan_cache_entries are resident.

@@ -264,7 +264,7 @@ static int ref_setup(refdata *R, int dim, int P, int nq_m, const double *pts_m, 
 }
 
 /* Coefficient value at quadrature node q of element e (Section 3: m_q = m(F_e(xhat_q)),
- * Section 4: solution-dependent coefficients evaluated at u_h = phi^T u). */
+ * Section 5: solution-dependent coefficients evaluated at u_h = phi^T u). */
 static double coeff_at(const oracle_coeff *c, const double *phi_q, int n, const int32_t *conn,
                        int64_t n_e, int64_t e, int q)
 {

@@ -90,7 +90,7 @@ struct Shape {
     static constexpr int NG = D * (D + 1) / 2;
 };
 
-// Geometry (Line 4) and weighted coefficient columns (Lines 5-7) of one
+// Geometry (b_e, W) and weighted coefficient columns (S, Lambda) of one
 // element: b_e, vec(A_e), Lambda_m[:, e], Lambda_c[:, e]. `eid` is the element
 // index used for per-(q, e) coefficient arrays. Returns false when a
 // coefficient value is not finite.
@@ -217,7 +217,7 @@ __device__ __forceinline__ void geometry_from(const double (&x)[D + 1][D], doubl
     }
 }
 
-// Lines 4-7 from gathered inputs; v is still needed when the two nodal fields differ.
+// Geometry and Lambda columns from gathered inputs; v is still needed when the two nodal fields differ.
 template <int D, int P, int NQM, int NQC>
 __device__ __forceinline__ bool setup_from_raw(const FormInputs &in, const RawElem<D, P> &r, const int32_t *v,
                                                int64_t eid, double *A, double *lm, double *lc)
@@ -312,7 +312,7 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t n)
     return x * q + (x < r ? x : r) + i;
 }
 
-// V_m[:, e] = Q_m X_m[:, e] with X_m = Lambda_m (Lines 8, 10); store(s, value)
+// V_m[:, e] = Q_m X_m[:, e] with X_m = Lambda_m (Algorithm 2, mass matrix); store(s, value)
 // receives each symmetric-pair entry.
 template <int NS, int NQM, typename CT, class Store>
 __device__ __forceinline__ void contract_mass(const CT *__restrict__ Qm, const double *lm, Store &&store)
@@ -329,7 +329,7 @@ __device__ __forceinline__ void contract_mass(const CT *__restrict__ Qm, const d
     }
 }
 
-// V_c[:, e] = Q_c X_c[:, e] with X_c = Lambda_c (Khatri-Rao) W (Lines 9, 11).
+// V_c[:, e] = Q_c X_c[:, e] with X_c = Lambda_c (Khatri-Rao) W (Algorithm 2, conductivity matrix).
 template <int P, int NS, int NQC, int NG, typename CT, class Store>
 __device__ __forceinline__ void contract_stiff(const CT *__restrict__ Qc, const double *lc, const double *A,
                                                Store &&store)

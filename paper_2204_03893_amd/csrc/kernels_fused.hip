@@ -1,11 +1,12 @@
-// Fused assembly kernel: Algorithm 2, Lines 4-12 in one pass over the mesh.
+// Fused assembly kernel: all of Algorithm 2 after the reference tables, in one
+// pass over the mesh.
 //
 // One workgroup per tile of T consecutive elements (plan order), one lane per
 // element. Each lane computes its element's geometry and weighted coefficient
-// columns (Lines 4-7), then for each matrix in turn forms the element
-// matrix V = Q X (Lines 8-11, symmetric-pair rows only) into LDS, and the
+// columns (geometry, S, Lambda, W), then for each matrix in turn forms the element
+// matrix V = Q X (symmetric-pair rows only) into LDS, and the
 // workgroup reduces every CSR slot the tile touches over the tile's
-// contributions in the plan's fixed order (Line 12). Slots owned by the tile
+// contributions in the plan's fixed order (the global assembly). Slots owned by the tile
 // are written directly (upper entry and its mirror); slots shared with other
 // tiles are written as partials and summed by the fix-up kernel in
 // ascending tile order. No float atomics: results are bitwise reproducible.

@@ -1,4 +1,4 @@
-// Formation kernel (Algorithm 2, Lines 4-11) writing the symmetric element
+// Formation kernel (Algorithm 2 up to the element matrices) writing the symmetric element
 // matrices V_m, V_c to a buffer (the formation-only entry point), and the
 // expansion of the symmetric pairs to full n_p x n_p element matrices.
 #include "kernels.hpp"

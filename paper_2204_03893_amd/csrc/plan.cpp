@@ -1,4 +1,4 @@
-// Host construction of the per-mesh assembly plan (Algorithm 2, Line 12:
+// Host construction of the per-mesh assembly plan (the global assembly step of Algorithm 2:
 // "the set of indices of nonzero entries").
 //   1. node -> element lists (counting sort; ascending element id per node);
 //   2. CSR pattern: row i holds every j that shares an element with i

@@ -36,7 +36,7 @@ qxa_status hip_fail(hipError_t e, const char *what);
         if (_e != hipSuccess) return ::qxa::hip_fail(_e, #call); \
     } while (0)
 
-// Reference element tables (Algorithm 2, Lines 1-3) ---------------------
+// Reference element tables of Algorithm 2 (Phi, J_q, Q) ---------------------
 struct RefTables {
     int dim = 0, order = 0, np = 0, ns = 0, ng = 0;
     int nq_m = 0, nq_c = 0;

@@ -1,11 +1,11 @@
-// Reference-element tables of Algorithm 2, Lines 1-3 (Section 4):
+// Reference-element tables of Algorithm 2 (Section 4):
 //   Phi = [phi_1 .. phi_nq]  (basis values at the quadrature nodes),
 //   J_q  (reference basis gradients at node q),
 //   Q_m = Phi (.) Phi        (Khatri-Rao product, n_p^2 x n_q),
 //   Q_c = [J_1 (x) J_1, ..., J_nq (x) J_nq]  (n_p^2 x d^2 n_q).
 // Only the rows of distinct symmetric pairs (a <= b) are kept: V is the
 // vectorisation of a symmetric matrix, so the other rows are duplicates
-// (Section 6, first improvement). Q_c is further contracted against the
+// (Section 7, first improvement). Q_c is further contracted against the
 // symmetric W = vec(A_e): columns (q, a, b) and (q, b, a) are merged into one
 // column per a <= b, so X_c = Lambda_c (.) W keeps d(d+1)/2 rows per q.
 #include <cmath>

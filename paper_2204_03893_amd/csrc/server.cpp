@@ -1,6 +1,6 @@
 // Continuous-batching assembly server: arrival-order admission against
 // in-flight slots and a device-memory budget, a resident plan cache (only the
-// coefficients change between assemblies of one mesh, Section 4 summary),
+// coefficients change between assemblies of one mesh, Section 5 summary),
 // batched persistent launches over several streams, completion by events.
 #include <algorithm>
 #include <chrono>

@@ -1,5 +1,5 @@
-// Tile plan for the fused formation + scatter kernel (Algorithm 2, Lines
-// 4-12 in one pass over the mesh).
+// Tile plan for the fused formation + scatter kernel (Algorithm 2 after its
+// reference tables, in one pass over the mesh).
 //
 // Elements are ordered along a Morton curve of their centroids and cut into
 // tiles of T consecutive elements. One workgroup forms the element matrices

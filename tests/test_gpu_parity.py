@@ -111,7 +111,7 @@ def test_fp32_contraction_error(name, N):
 
 @pytest.mark.parametrize("dim,order,deg", [(2, 1, 2), (2, 2, 4), (2, 3, 6), (3, 1, 2), (3, 2, 4), (3, 3, 6)])
 def test_element_matrices_formation(dim, order, deg):
-    """Formation only (Lines 4-11) against the oracle's local matrices, all orders."""
+    """Formation only (element matrices of Algorithm 2, no global assembly) against the oracle's local matrices, all orders."""
     qxa = _qxa()
     _say("case formation", dim, order)
     mesh = structured_mesh(dim, order, 3 if dim == 2 else 2, 0.2, seed=4)

@@ -1,7 +1,7 @@
 """Seeded smooth fields sampled at mesh nodes (coefficient inputs).
 
 Solution-dependent coefficients are evaluated from the interpolated field
-u_h = phi^T u (Section 4, nonlinear FEM); the nodal vector u is the input.
+u_h = phi^T u (Section 5, nonlinear FEM); the nodal vector u is the input.
 Space-dependent coefficients k(x) = exp(g(x)) are handled the same way with a
 nodal sample of g. These generators only draw random numbers and evaluate
 sines/cosines at node coordinates; the coefficient maps themselves (1+a u^2,

@@ -1,6 +1,6 @@
 """Seeded structured simplex meshes standing in for the paper's unit-square meshes.
 
-The paper's experiments use Gmsh meshes of the unit square (Section 5,
+The paper's experiments use Gmsh meshes of the unit square (Section 6,
 Experiment 1) that are not available; these generators produce meshes of the
 same domain and element types with a chosen element count. Nothing here
 computes any part of the assembly method: only node positions, connectivity
