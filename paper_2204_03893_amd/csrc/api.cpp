@@ -3,6 +3,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -124,7 +125,13 @@ static float f16_value(uint16_t b)
 //   split forms (16x16x32): [component][ks][nb][lane][8], lane l holds
 //     Q[s = 16 nb + l % 16][k = 32 ks + 8 (l / 16) + t], t = 0..7, as the
 //     hi / lo (/ mid) terms of its 16-bit split.
-// Mass block first, then stiffness; zero outside the tables.
+// Mass block first (k = q), then conductivity. The conductivity columns are
+// ordered k = g * NQP + q (metric component g, node q, NQP = n_q rounded up
+// to 4 for the 16x16x4 forms and to 8 for the split forms), so the lanes that
+// hold one K slot of an element need the weighted coefficients of only a
+// subset of the quadrature nodes. Zero outside the tables.
+int qc_pad(int nq, bool split) { return split ? (nq + 7) / 8 * 8 : (nq + 3) / 4 * 4; }
+
 static void build_qfrags(const RefTables &T, std::vector<uint8_t> (&out)[5], double (&f16_qinv)[2])
 {
     const int nb_ = (T.ns + 15) / 16, kc = T.nq_c * T.ng;
@@ -139,21 +146,24 @@ static void build_qfrags(const RefTables &T, std::vector<uint8_t> (&out)[5], dou
         f16_scale[blk] = std::ldexp(1.0, 13 - e);
         f16_qinv[blk] = std::ldexp(1.0, e - 13);
     }
-    auto qval = [&](int blk, int s, int k) -> double {
+    // entry (s, k) of the mass (blk 0) or reordered conductivity (blk 1) block
+    auto qval = [&](int blk, int s, int k, bool split) -> double {
         if (s >= T.ns) return 0.0;
         if (blk == 0) return k < T.nq_m ? T.Qm[size_t(s) * T.nq_m + k] : 0.0;
-        return k < kc ? T.Qc[size_t(s) * kc + k] : 0.0;
+        const int nqp = qc_pad(T.nq_c, split), g = k / nqp, q = k % nqp;
+        if (g >= T.ng || q >= T.nq_c) return 0.0;
+        return T.Qc[size_t(s) * kc + size_t(q) * T.ng + g];
     };
-    const int K[2] = {T.nq_m, kc};
     // plain forms
     for (int f = 0; f < 2; ++f) {
         std::vector<uint8_t> &o = out[f];
         for (int blk = 0; blk < 2; ++blk) {
-            const int ks_n = (K[blk] + 3) / 4;
+            const int kb = blk == 0 ? T.nq_m : T.ng * qc_pad(T.nq_c, false);
+            const int ks_n = (kb + 3) / 4;
             for (int ks = 0; ks < ks_n; ++ks)
                 for (int nb = 0; nb < nb_; ++nb)
                     for (int l = 0; l < 64; ++l) {
-                        const double v = qval(blk, 16 * nb + l % 16, 4 * ks + l / 16);
+                        const double v = qval(blk, 16 * nb + l % 16, 4 * ks + l / 16, false);
                         if (f == 0) {
                             const uint8_t *b = reinterpret_cast<const uint8_t *>(&v);
                             o.insert(o.end(), b, b + 8);
@@ -171,13 +181,14 @@ static void build_qfrags(const RefTables &T, std::vector<uint8_t> (&out)[5], dou
         const int nc = f == 4 ? 3 : 2;
         std::vector<uint8_t> &o = out[f];
         for (int blk = 0; blk < 2; ++blk) {
-            const int ks_n = (K[blk] + 31) / 32;
+            const int kb = blk == 0 ? T.nq_m : T.ng * qc_pad(T.nq_c, true);
+            const int ks_n = (kb + 31) / 32;
             for (int c = 0; c < nc; ++c)
                 for (int ks = 0; ks < ks_n; ++ks)
                     for (int nb = 0; nb < nb_; ++nb)
                         for (int l = 0; l < 64; ++l)
                             for (int t = 0; t < 8; ++t) {
-                                double v = qval(blk, 16 * nb + l % 16, 32 * ks + 8 * (l / 16) + t);
+                                double v = qval(blk, 16 * nb + l % 16, 32 * ks + 8 * (l / 16) + t, true);
                                 uint16_t comp[3];
                                 if (f == 2) {
                                     v *= f16_scale[blk];
@@ -293,8 +304,8 @@ qxa_status qxa_plan_destroy(qxa_plan p)
 {
     if (!p) return QXA_OK;
     hipSetDevice(p->mesh->device);
-    void *bufs[] = {p->d_row_ptr, p->d_col_idx, p->d_tconn, p->d_elem_order, p->d_rec, p->d_rec_ptr, p->d_ovf,
-                    p->d_ovf_ptr, p->d_fix_ptr, p->d_fix_target, p->d_fix_idx, p->d_part, p->d_qfrag[0],
+    void *bufs[] = {p->d_row_ptr, p->d_col_idx, p->d_tconn, p->d_elem_order, p->d_rec, p->d_rec_ptr,
+                    p->d_part_ptr, p->d_fix_target, p->d_fix_src, p->d_sink, p->d_part, p->d_qfrag[0],
                     p->d_qfrag[1], p->d_qfrag[2], p->d_qfrag[3], p->d_qfrag[4], p->d_tables, p->d_tables_f,
                     p->d_V, p->d_flags};
     for (void *b : bufs) plan_free(p, b);
@@ -362,11 +373,10 @@ qxa_status plan_upload(qxa_mesh mesh, const PlanStaging &g, DevArena *arena, boo
     if (!st) st = plan_upload_buf(p, &p->d_elem_order, tp.elem_order.data(), tp.elem_order.size());
     if (!st) st = plan_upload_buf(p, &p->d_rec, tp.rec.data(), tp.rec.size());
     if (!st) st = plan_upload_buf(p, &p->d_rec_ptr, tp.rec_ptr.data(), tp.rec_ptr.size());
-    if (!st) st = plan_upload_buf(p, &p->d_ovf, tp.ovf.data(), tp.ovf.size());
-    if (!st) st = plan_upload_buf(p, &p->d_ovf_ptr, tp.ovf_ptr.data(), tp.ovf_ptr.size());
-    if (!st) st = plan_upload_buf(p, &p->d_fix_ptr, tp.fix_ptr.data(), tp.fix_ptr.size());
+    if (!st) st = plan_upload_buf(p, &p->d_part_ptr, tp.part_ptr.data(), tp.part_ptr.size());
     if (!st) st = plan_upload_buf(p, &p->d_fix_target, tp.fix_target.data(), tp.fix_target.size());
-    if (!st) st = plan_upload_buf(p, &p->d_fix_idx, tp.fix_idx.data(), tp.fix_idx.size());
+    if (!st) st = plan_upload_buf(p, &p->d_fix_src, tp.fix_src.data(), tp.fix_src.size());
+    if (!st) st = plan_alloc(p, &p->d_sink, size_t(kSinkDoubles));
     if (!st && own_scratch) st = plan_alloc(p, &p->d_part, size_t(2) * tp.n_partials);
     if (g.mfma) {
         p->f16_qinv[0] = g.f16_qinv[0];
@@ -536,8 +546,7 @@ qxa_status make_fused_args(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *s
     a.elem_order = p->d_elem_order;
     a.rec = reinterpret_cast<const uint4 *>(p->d_rec);
     a.rec_ptr = p->d_rec_ptr;
-    a.ovf = p->d_ovf;
-    a.ovf_ptr = p->d_ovf_ptr;
+    a.sink = p->d_sink;
     a.M = M;
     a.C = C;
     a.Qfrag = p->d_qfrag[precision];
@@ -546,7 +555,7 @@ qxa_status make_fused_args(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *s
     a.qinv_c = precision == QXA_F16X2 ? p->f16_qinv[1] : 1.0;
     a.Mpart = part;
     a.Cpart = part ? part + p->n_partials : nullptr;
-    f = FixupArgs{p->n_fix, p->d_fix_ptr, p->d_fix_target, p->d_fix_idx, a.Mpart, a.Cpart, M, C};
+    f = FixupArgs{p->n_fix, p->d_fix_target, p->d_fix_src, p->d_part_ptr, a.Mpart, a.Cpart, M, C};
     return QXA_OK;
 }
 
@@ -566,6 +575,11 @@ qxa_status qxa_assemble(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *stif
     if (!M_vals && !C_vals) return QXA_OK;
     QXA_HIP(hipSetDevice(p->mesh->device));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // launch errors are read back with hipGetLastError: drop one left behind by
+    // an unrelated earlier call on this thread so it is not blamed on the launch
+    const hipError_t stale = hipGetLastError();
+    if (stale != hipSuccess && std::getenv("QXA_DEBUG"))
+        std::fprintf(stderr, "qxa: cleared an earlier HIP error before launching: %s\n", hipGetErrorString(stale));
     {
         TimedLaunch tl(p, "fused", s);
         const JobTable jt{a, nullptr, nullptr, 0, p->n_tiles};

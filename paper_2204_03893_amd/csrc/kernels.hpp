@@ -23,7 +23,7 @@ namespace qxa {
 // waves per workgroup, Q^T fragments staged next to V.
 constexpr int tile_size(int D, int P)
 {
-    return (D == 3 && P == 3) ? 32 : (P >= 2) ? 128 : 256;
+    return (D == 3 && P == 3) ? 32 : (P >= 2) ? 64 : 256;
 }
 
 bool fused_uses_mfma(int D, int P);
@@ -45,8 +45,7 @@ struct FusedArgs {
     double qinv_m, qinv_c;      // inverse power-of-two scales of the FP16 Q tables (1 otherwise)
     const uint4 *rec;           // reduction records {target, c0|c1, c2|c3, c4|c5}
     const int64_t *rec_ptr;     // [n_tiles + 1]
-    const uint16_t *ovf;        // overflow contribution lists
-    const int64_t *ovf_ptr;     // [n_tiles + 1]
+    double *sink;               // write target of idle lanes (at least 1024 doubles)
     double *M, *C;              // CSR values (either may be null)
     double *Mpart, *Cpart;      // partials of slots shared between tiles
 };
@@ -66,9 +65,9 @@ struct JobTable {
 
 struct FixupArgs {
     int64_t n_fix;
-    const int32_t *fix_ptr;     // [n_fix + 1] ranges of fix_idx
     const int32_t *fix_target;  // [n_fix] CSR slot (ascending)
-    const int32_t *fix_idx;     // partial indices, ascending tile order per output
+    const int32_t *fix_src;     // [n_fix] shared slot whose partials are summed
+    const int64_t *part_ptr;    // [n_shared + 1] partial ranges, ascending tile order
     const double *Mpart, *Cpart;
     double *M, *C;
 };

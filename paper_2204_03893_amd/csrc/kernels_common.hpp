@@ -7,6 +7,18 @@
 
 namespace qxa {
 
+// Read-only tables shared by every lane (basis values, weights, Q). Read
+// through the constant address space, loads at uniform addresses go through
+// the scalar unit (and are batched) instead of one vector load and wait per
+// value. The tables are never written while a kernel runs.
+template <typename T>
+using table_ptr = const T __attribute__((address_space(4))) *;
+template <typename T>
+__device__ __forceinline__ table_ptr<T> uniform_table(const T *p)
+{
+    return (table_ptr<T>)(p);
+}
+
 struct CoeffDev {
     int kind;  // 0 const, 1 nodal, 2 per (q, e)
     int law;   // 0 identity, 1 poly2, 2 exp
@@ -116,12 +128,12 @@ __device__ __forceinline__ bool element_setup(const FormInputs &in, const int32_
         } else if (in.cm.kind == 1) {
             double uh = 0.0;  // u_h(xhat_q) = phi_q^T u_e
 #pragma unroll
-            for (int i = 0; i < NP; ++i) uh = fma(in.phi_m[i * NQM + q], um[i], uh);
+            for (int i = 0; i < NP; ++i) uh = fma(uniform_table(in.phi_m)[i * NQM + q], um[i], uh);
             s = apply_law(in.cm, uh);
         } else {
             s = apply_law(in.cm, in.cm.field[q * in.n_elem + eid]);
         }
-        lm[q] = in.w_m[q] * s * babs;
+        lm[q] = uniform_table(in.w_m)[q] * s * babs;
         ok &= isfinite(lm[q]);
     }
     double uc[NP];
@@ -142,12 +154,12 @@ __device__ __forceinline__ bool element_setup(const FormInputs &in, const int32_
         } else if (in.cc.kind == 1) {
             double uh = 0.0;
 #pragma unroll
-            for (int i = 0; i < NP; ++i) uh = fma(in.phi_c[i * NQC + q], uc[i], uh);
+            for (int i = 0; i < NP; ++i) uh = fma(uniform_table(in.phi_c)[i * NQC + q], uc[i], uh);
             s = apply_law(in.cc, uh);
         } else {
             s = apply_law(in.cc, in.cc.field[q * in.n_elem + eid]);
         }
-        lc[q] = in.w_c[q] * s * babs;
+        lc[q] = uniform_table(in.w_c)[q] * s * babs;
         ok &= isfinite(lc[q]);
     }
     return ok;
@@ -217,10 +229,12 @@ __device__ __forceinline__ void geometry_from(const double (&x)[D + 1][D], doubl
     }
 }
 
-// Geometry and Lambda columns from gathered inputs; v is still needed when the two nodal fields differ.
+// Geometry and Lambda columns from gathered inputs. When the two nodal fields
+// differ, the second one is read here through the element's connectivity
+// (tconn[i * ne + pos]); the gathered values hold the first.
 template <int D, int P, int NQM, int NQC>
-__device__ __forceinline__ bool setup_from_raw(const FormInputs &in, const RawElem<D, P> &r, const int32_t *v,
-                                               int64_t eid, double *A, double *lm, double *lc)
+__device__ __forceinline__ bool setup_from_raw(const FormInputs &in, const RawElem<D, P> &r, const int32_t *tconn,
+                                               int64_t pos, int64_t eid, double *A, double *lm, double *lc)
 {
     constexpr int NP = Shape<D, P>::NP;
     double babs;
@@ -234,12 +248,12 @@ __device__ __forceinline__ bool setup_from_raw(const FormInputs &in, const RawEl
         } else if (in.cm.kind == 1) {
             double uh = 0.0;
 #pragma unroll
-            for (int i = 0; i < NP; ++i) uh = fma(in.phi_m[i * NQM + q], r.u[i], uh);
+            for (int i = 0; i < NP; ++i) uh = fma(uniform_table(in.phi_m)[i * NQM + q], r.u[i], uh);
             s = apply_law(in.cm, uh);
         } else {
             s = apply_law(in.cm, in.cm.field[q * in.n_elem + eid]);
         }
-        lm[q] = in.w_m[q] * s * babs;
+        lm[q] = uniform_table(in.w_m)[q] * s * babs;
         ok &= isfinite(lm[q]);
     }
     double uc[NP];
@@ -249,7 +263,7 @@ __device__ __forceinline__ bool setup_from_raw(const FormInputs &in, const RawEl
             for (int i = 0; i < NP; ++i) uc[i] = r.u[i];
         } else {
 #pragma unroll
-            for (int i = 0; i < NP; ++i) uc[i] = in.cc.field[v[i]];
+            for (int i = 0; i < NP; ++i) uc[i] = in.cc.field[tconn[i * in.n_elem + pos]];
         }
     }
 #pragma unroll
@@ -260,12 +274,12 @@ __device__ __forceinline__ bool setup_from_raw(const FormInputs &in, const RawEl
         } else if (in.cc.kind == 1) {
             double uh = 0.0;
 #pragma unroll
-            for (int i = 0; i < NP; ++i) uh = fma(in.phi_c[i * NQC + q], uc[i], uh);
+            for (int i = 0; i < NP; ++i) uh = fma(uniform_table(in.phi_c)[i * NQC + q], uc[i], uh);
             s = apply_law(in.cc, uh);
         } else {
             s = apply_law(in.cc, in.cc.field[q * in.n_elem + eid]);
         }
-        lc[q] = in.w_c[q] * s * babs;
+        lc[q] = uniform_table(in.w_c)[q] * s * babs;
         ok &= isfinite(lc[q]);
     }
     return ok;
@@ -324,7 +338,7 @@ __device__ __forceinline__ void contract_mass(const CT *__restrict__ Qm, const d
     for (int s = 0; s < NS; ++s) {
         CT acc = CT(0);
 #pragma unroll
-        for (int q = 0; q < NQM; ++q) acc = fma(Qm[s * NQM + q], x[q], acc);
+        for (int q = 0; q < NQM; ++q) acc = fma(uniform_table(Qm)[s * NQM + q], x[q], acc);
         store(s, double(acc));
     }
 }
@@ -348,7 +362,7 @@ __device__ __forceinline__ void contract_stiff(const CT *__restrict__ Qc, const 
         for (int s = 0; s < NS; ++s) {
             CT acc = CT(0);
 #pragma unroll
-            for (int g = 0; g < NG; ++g) acc = fma(Qc[s * NQC * NG + g], x[g], acc);
+            for (int g = 0; g < NG; ++g) acc = fma(uniform_table(Qc)[s * NQC * NG + g], x[g], acc);
             store(s, double(acc));
         }
     } else if constexpr (FLAT) {
@@ -361,7 +375,7 @@ __device__ __forceinline__ void contract_stiff(const CT *__restrict__ Qc, const 
         for (int s = 0; s < NS; ++s) {
             CT acc = CT(0);
 #pragma unroll
-            for (int k = 0; k < NQC * NG; ++k) acc = fma(Qc[s * NQC * NG + k], x[k], acc);
+            for (int k = 0; k < NQC * NG; ++k) acc = fma(uniform_table(Qc)[s * NQC * NG + k], x[k], acc);
             store(s, double(acc));
         }
     } else {
@@ -378,7 +392,7 @@ __device__ __forceinline__ void contract_stiff(const CT *__restrict__ Qc, const 
             for (int q = 0; q < NQC; ++q) {
                 CT t = CT(0);
 #pragma unroll
-                for (int g = 0; g < NG; ++g) t = fma(Qc[(s * NQC + q) * NG + g], w[g], t);
+                for (int g = 0; g < NG; ++g) t = fma(uniform_table(Qc)[(s * NQC + q) * NG + g], w[g], t);
                 acc = fma(t, l[q], acc);
             }
             store(s, double(acc));

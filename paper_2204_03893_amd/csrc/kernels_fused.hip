@@ -18,48 +18,45 @@
 
 namespace qxa {
 
-// Reduction of one record: sum the contributions (padded LDS indices) of both
-// staged matrices in the plan's order and write the target slot or partial.
-// Empty inline slots hold the index of a zero kept in LDS, so the six reads
-// are issued unconditionally (adding +0.0 leaves every sum unchanged).
+// Sums of one record's contributions (padded LDS indices, plan order) to both
+// staged matrices. Absent contributions (0xFFFF) read the zero kept at index
+// `zero`, so the six reads are unconditional (adding +0.0 changes no sum).
 template <typename ST>
-__device__ __forceinline__ void reduce_record(const uint4 R, const ST *sVm, const ST *sVc, uint32_t zero,
-                                              const uint16_t *__restrict__ ovf, double *__restrict__ M,
-                                              double *__restrict__ C, double *__restrict__ Mpart,
-                                              double *__restrict__ Cpart)
+__device__ __forceinline__ void record_sums(const uint4 R, const ST *sVm, const ST *sVc, uint32_t zero, double &am,
+                                            double &ac)
 {
     uint32_t c[6] = {R.y & 0xffffu, R.y >> 16, R.z & 0xffffu, R.z >> 16, R.w & 0xffffu, R.w >> 16};
-    const bool more = c[5] >= 0x8000u && c[5] != 0xffffu;
-    const uint32_t c5 = c[5];
 #pragma unroll
-    for (int q = 1; q < 6; ++q) c[q] = (c[q] >= 0x8000u) ? zero : c[q];
+    for (int q = 1; q < 6; ++q) c[q] = c[q] == 0xffffu ? zero : c[q];
     double vm[6], vc[6];
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
         vm[q] = double(sVm[c[q]]);
         vc[q] = double(sVc[c[q]]);
     }
-    double am = vm[0], ac = vc[0];
+    am = vm[0];
+    ac = vc[0];
 #pragma unroll
     for (int q = 1; q < 6; ++q) {
         am += vm[q];
         ac += vc[q];
     }
-    if (more) {
-        const uint16_t *o = ovf + (c5 & 0x7fffu);
-        const uint32_t n = o[0];
-        for (uint32_t q = 1; q <= n; ++q) {
-            am += double(sVm[o[q]]);
-            ac += double(sVc[o[q]]);
-        }
-    }
+}
+
+// Reduction of one record into its CSR slot (target >= 0) or partial.
+template <typename ST>
+__device__ __forceinline__ void reduce_record(const uint4 R, const ST *sVm, const ST *sVc, uint32_t zero,
+                                              const FusedArgs &a)
+{
+    double am, ac;
+    record_sums(R, sVm, sVc, zero, am, ac);
     const int32_t t = int32_t(R.x);
     if (t >= 0) {
-        if (M) M[t] = am;
-        if (C) C[t] = ac;
+        if (a.M) a.M[t] = am;
+        if (a.C) a.C[t] = ac;
     } else {
-        if (M) Mpart[-int64_t(t) - 1] = am;
-        if (C) Cpart[-int64_t(t) - 1] = ac;
+        a.Mpart[-int64_t(t) - 1] = am;
+        a.Cpart[-int64_t(t) - 1] = ac;
     }
 }
 
@@ -75,17 +72,16 @@ __device__ __forceinline__ void prefetch_records(const uint4 *__restrict__ rec, 
     }
 }
 
-// All records of a tile: the prefetched batch first, then the rest in
-// groups of kPrefetch independent loads.
+// All records of a tile (one workgroup of `stride` threads): the prefetched
+// batch first, then the rest in groups of kPrefetch independent loads.
 template <typename ST>
 __device__ __forceinline__ void tile_reduce(const uint4 (&pf)[kPrefetch], const FusedArgs &a, int64_t tile,
                                             const ST *sVm, const ST *sVc, uint32_t zero, int stride)
 {
     const int64_t r0 = a.rec_ptr[tile], r1 = a.rec_ptr[tile + 1];
-    const uint16_t *ovf = a.ovf + a.ovf_ptr[tile];
 #pragma unroll
     for (int i = 0; i < kPrefetch; ++i)
-        if (r0 + threadIdx.x + int64_t(i) * stride < r1) reduce_record(pf[i], sVm, sVc, zero, ovf, a.M, a.C, a.Mpart, a.Cpart);
+        if (r0 + threadIdx.x + int64_t(i) * stride < r1) reduce_record(pf[i], sVm, sVc, zero, a);
     for (int64_t k0 = r0 + threadIdx.x + int64_t(kPrefetch) * stride; k0 < r1; k0 += int64_t(kPrefetch) * stride) {
         uint4 R[kPrefetch];
 #pragma unroll
@@ -95,7 +91,7 @@ __device__ __forceinline__ void tile_reduce(const uint4 (&pf)[kPrefetch], const 
         }
 #pragma unroll
         for (int i = 0; i < kPrefetch; ++i)
-            if (k0 + int64_t(i) * stride < r1) reduce_record(R[i], sVm, sVc, zero, ovf, a.M, a.C, a.Mpart, a.Cpart);
+            if (k0 + int64_t(i) * stride < r1) reduce_record(R[i], sVm, sVc, zero, a);
     }
 }
 
@@ -276,19 +272,20 @@ struct Split<QXA_F16X2> {
 };
 
 // Contraction of one 16-element group, plain FP64/FP32 operands (16x16x4 MFMA).
-// xat(k) is the k-th entry of this lane's element's X column (compile-time k).
-template <typename CT, int K, int NB, int NS, int T, typename ST, class XAt>
-__device__ __forceinline__ void contract_group_plain(const CT *sQ, XAt &&xat, ST *sV, int lane, int col0)
+// xk(ks) is this lane's A-operand entry of k-step ks: X[k = 4 ks + lane / 16]
+// of the lane's element (compile-time ks).
+template <typename CT, int K, int NB, int NS, int T, typename ST, class XK>
+__device__ __forceinline__ void contract_group_plain(const CT *sQ, XK &&xk, ST *sV, int lane, int col0)
 {
     using MF = Mfma<CT>;
     constexpr int KS = (K + 3) / 4;
-    const int j = lane >> 4, c16 = lane & 15;
+    const int c16 = lane & 15;
     typename MF::acc_t acc[NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[nb] = typename MF::acc_t{0, 0, 0, 0};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-        const CT x = CT(sel4(j, xat(4 * ks), xat(4 * ks + 1), xat(4 * ks + 2), xat(4 * ks + 3)));
+        const CT x = CT(xk(ks));
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[nb] = MF::step(x, sQ[(ks * NB + nb) * 64 + lane], acc[nb]);
     }
@@ -303,22 +300,22 @@ __device__ __forceinline__ void contract_group_plain(const CT *sQ, XAt &&xat, ST
 
 // Contraction of one 16-element group with split 16-bit operands
 // (16x16x32 MFMA). Q^T fragments: [component][ks][nb][lane] x 8 values.
-template <int PF, int K, int NB, int NS, int T, typename ST, class XAt>
-__device__ __forceinline__ void contract_group_split(const uint4 *sQ, XAt &&xat, ST *sV, int lane, int col0,
+// xv(ks, t) is this lane's entry X[k = 32 ks + 8 (lane / 16) + t] (compile-time ks, t).
+template <int PF, int K, int NB, int NS, int T, typename ST, class XV>
+__device__ __forceinline__ void contract_group_split(const uint4 *sQ, XV &&xvf, ST *sV, int lane, int col0,
                                                      double qinv)
 {
     using SP = Split<PF>;
     using elem_t = typename SP::elem;
     constexpr int KS = (K + 31) / 32;
     const int j = lane >> 4, c16 = lane & 15;
-    // this lane's X entries k = 32 ks + 8 j + t, t = 0..7
     double xv[KS][8];
     double amax = 0.0;
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
-            xv[ks][t] = sel4(j, xat(32 * ks + t), xat(32 * ks + 8 + t), xat(32 * ks + 16 + t), xat(32 * ks + 24 + t));
+            xv[ks][t] = xvf(ks, t);
             amax = fmax(amax, fabs(xv[ks][t]));
         }
     double scale = 1.0, inv = 1.0;
@@ -366,6 +363,91 @@ __device__ __forceinline__ void contract_group_split(const uint4 *sQ, XAt &&xat,
     }
 }
 
+// Quadrature nodes whose weighted coefficients a lane of an element needs on
+// the matrix cores, given the K order of the Q^T fragments (mass k = q;
+// conductivity k = g * NQP + q). Lane group j = lane / 16 holds
+//   16x16x4 forms: k = 4 ks + j         -> q = 4 m + j       (m < ceil(n_q / 4))
+//   split forms:   k = 32 ks + 8 j + t  -> mass q = 8 j + t, conductivity
+//                  q = (8 j) mod NQP + t (NQP in {8, 16}: the same q for every ks)
+template <int PF, int NQM, int NQC>
+struct LaneQ {
+    static constexpr bool SPLIT = PF >= QXA_F16X2;
+    static constexpr int NQP = SPLIT ? (NQC + 7) / 8 * 8 : (NQC + 3) / 4 * 4;
+    static_assert(!SPLIT || NQP == 8 || NQP == 16, "split forms need n_q <= 16");
+    static_assert(!SPLIT || NQM <= 32, "split forms need n_q(mass) <= 32");
+    static constexpr int MM = SPLIT ? 8 : (NQM + 3) / 4;  // mass nodes per lane
+    static constexpr int MC = SPLIT ? 8 : NQP / 4;        // conductivity nodes per lane
+    static __device__ __forceinline__ int qm(int j, int m) { return SPLIT ? 8 * j + m : 4 * m + j; }
+    static __device__ __forceinline__ int qc(int j, int m) { return SPLIT ? (8 * j) % NQP + m : 4 * m + j; }
+};
+
+// Per-lane setup on the matrix-core path: geometry (all lanes) and the
+// weighted coefficients Lambda of this lane's quadrature nodes only (zero for
+// nodes past n_q). Basis values and weights come from LDS, q-major
+// (sPhi[q * NP + i]). Returns false when a coefficient value is not finite.
+template <int D, int P, int NQM, int NQC, int PF>
+__device__ __forceinline__ bool lane_setup(const FormInputs &in, const RawElem<D, P> &r, const int32_t *tconn,
+                                           int64_t pos, int64_t eid, int j, const double *sPhiM,
+                                           const double *sPhiC, const double *sWM, const double *sWC, double *A,
+                                           double *lm, double *lc)
+{
+    using L = LaneQ<PF, NQM, NQC>;
+    constexpr int NP = Shape<D, P>::NP;
+    double babs;
+    geometry_from<D>(r.x, babs, A);
+    bool ok = true;
+#pragma unroll
+    for (int m = 0; m < L::MM; ++m) {
+        const int q = L::qm(j, m);
+        double v = 0.0;
+        if (q < NQM) {
+            double s;
+            if (in.cm.kind == 0) {
+                s = in.cm.value;
+            } else if (in.cm.kind == 1) {
+                double uh = 0.0;
+#pragma unroll
+                for (int i = 0; i < NP; ++i) uh = fma(sPhiM[q * NP + i], r.u[i], uh);
+                s = apply_law(in.cm, uh);
+            } else {
+                s = apply_law(in.cm, in.cm.field[q * in.n_elem + eid]);
+            }
+            v = sWM[q] * s * babs;
+        }
+        lm[m] = v;
+        ok &= isfinite(v);
+    }
+    const bool other = in.cc.kind == 1 && in.cm.kind == 1 && in.cc.field != in.cm.field;
+#pragma unroll
+    for (int m = 0; m < L::MC; ++m) {
+        const int q = L::qc(j, m);
+        double v = 0.0;
+        if (q < NQC) {
+            double s;
+            if (in.cc.kind == 0) {
+                s = in.cc.value;
+            } else if (in.cc.kind == 1) {
+                double uh = 0.0;
+                if (!other) {
+#pragma unroll
+                    for (int i = 0; i < NP; ++i) uh = fma(sPhiC[q * NP + i], r.u[i], uh);
+                } else {  // a second nodal field, read through the element's connectivity
+#pragma unroll
+                    for (int i = 0; i < NP; ++i)
+                        uh = fma(sPhiC[q * NP + i], in.cc.field[tconn[i * in.n_elem + pos]], uh);
+                }
+                s = apply_law(in.cc, uh);
+            } else {
+                s = apply_law(in.cc, in.cc.field[q * in.n_elem + eid]);
+            }
+            v = sWC[q] * s * babs;
+        }
+        lc[m] = v;
+        ok &= isfinite(v);
+    }
+    return ok;
+}
+
 template <int PF>
 struct FormTraits {
     using stage_t = float;  // reduced forms stage V in FP32; CSR accumulation stays FP64
@@ -377,93 +459,213 @@ struct FormTraits<QXA_FP64> {
     using qplain_t = double;
 };
 
-// T = 16 * (waves per workgroup): one 16-element group per wave.
+// Warp-specialised matrix-core kernel (persistent). The workgroup walks its
+// tiles with a two-buffer pipeline: waves 0-3 (producers, 16 elements each,
+// T = 64) gather, set up and contract tile i into LDS buffer i % 2 while waves
+// 4-11 (consumers) reduce tile i-1 from the other buffer; one LDS-only barrier
+// per tile separates the two. Producers issue only loads (the next tile's
+// gathers and connectivity), consumers only record loads and stores, so
+// neither role waits on the other's memory traffic. Consumers walk a tile's
+// records in chunks of kChunk rounds, loading chunk c+1 (or the next tile's
+// first chunk) before storing chunk c: every chunk issues the same number of
+// loads and stores (idle lanes read a valid record and write the sink), so
+// each wait covers only the records it needs, never the stores behind them.
+constexpr int kWsProducers = 256;
+constexpr int kWsConsumers = 512;
+constexpr int kWsThreads = kWsProducers + kWsConsumers;
+constexpr int kChunk = 8;
+
+// LDS of the kernel: staged V (two buffers, both matrices), Q^T fragments,
+// basis values and weights of both rules (q-major).
+template <int D, int P, int NQM, int NQC, int PF, int T>
+struct WsLds {
+    using ST = typename FormTraits<PF>::stage_t;
+    static constexpr int NP = Shape<D, P>::NP, NS = Shape<D, P>::NS;
+    static constexpr size_t v_bytes = ((4 * sizeof(ST) * NS * (T + 1) + 15) / 16) * 16;
+    static constexpr size_t tab_doubles = size_t(NQM + NQC) * NP + NQM + NQC;
+    static size_t bytes(int64_t qfrag_vec16) { return v_bytes + size_t(qfrag_vec16) * 16 + tab_doubles * 8; }
+};
+
 template <int D, int P, int NQM, int NQC, int PF, int T, bool MULTI>
-__global__ __launch_bounds__(4 * T) void fused_mfma_kernel(JobTable jt)
+__global__ __launch_bounds__(kWsThreads) void fused_ws_kernel(JobTable jt)
 {
+    static_assert(T == 16 * (kWsProducers / 64), "one 16-element group per producer wave");
     using S = Shape<D, P>;
     using ST = typename FormTraits<PF>::stage_t;
+    using L = LaneQ<PF, NQM, NQC>;
+    using LDS = WsLds<D, P, NQM, NQC, PF, T>;
     constexpr bool SPLIT = PF >= QXA_F16X2;
     constexpr int NB = (S::NS + 15) / 16;
-    constexpr int KM = NQM, KC = NQC * S::NG;
+    constexpr int KM = NQM, KC = L::NQP * S::NG;  // conductivity K order: k = g * NQP + q
+    constexpr int MAT = S::NS * (T + 1);         // one staged matrix [NS][T + 1]
+    constexpr int BUF = 2 * MAT;                 // one buffer: V_m then V_c
+    constexpr int NCT = kWsConsumers;
     extern __shared__ __align__(16) unsigned char smem[];
-    ST *sVm = reinterpret_cast<ST *>(smem);  // [NS][T + 1]
-    ST *sVc = sVm + S::NS * (T + 1);         // [NS][T + 1]
-    unsigned char *sQraw = smem + ((2 * sizeof(ST) * S::NS * (T + 1) + 15) / 16) * 16;
+    ST *sV = reinterpret_cast<ST *>(smem);  // [2 buffers][2 matrices][NS][T + 1]
+    unsigned char *sQraw = smem + LDS::v_bytes;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int j = lane >> 4, c16 = lane & 15;
-    {   // operand-ordered Q^T fragments, once per workgroup (shared by every job of the launch)
-        const FusedArgs a0 = args_of<MULTI>(jt, 0);
+    const FusedArgs a0 = args_of<MULTI>(jt, 0);  // tables are shared by every job of the launch
+    double *sPhiM = reinterpret_cast<double *>(sQraw + size_t(a0.qfrag_vec16) * 16);
+    double *sPhiC = sPhiM + NQM * S::NP, *sWM = sPhiC + NQC * S::NP, *sWC = sWM + NQM;
+    {
         const uint4 *gq = reinterpret_cast<const uint4 *>(a0.Qfrag);
         uint4 *dq = reinterpret_cast<uint4 *>(sQraw);
-        for (int64_t k = tid; k < a0.qfrag_vec16; k += blockDim.x) dq[k] = gq[k];
-    }
-    if (tid == 0) sVm[T] = sVc[T] = ST(0);  // zero kept in the (unused) padding column of row 0
-    TileWalk walk(jt.n_tiles);
-    int32_t v[S::NP];
-    RawElem<D, P> raw;
-    // connectivity and gathers of (global) tile g, for the lane's element
-    auto load_conn = [&](int64_t g) {
-        int64_t lt;
-        const FusedArgs b = args_of<MULTI>(jt, job_of<MULTI>(jt, g, lt));
-        const int64_t pp = lt * T + 16 * wave + c16;
-#pragma unroll
-        for (int i = 0; i < S::NP; ++i) v[i] = pp < b.in.n_elem ? b.tconn[i * b.in.n_elem + pp] : 0;
-    };
-    auto gather = [&](int64_t g) {
-        int64_t lt;
-        const FusedArgs b = args_of<MULTI>(jt, job_of<MULTI>(jt, g, lt));
-        gather_raw<D, P>(b.in, v, raw);
-    };
-    if (walk.valid(walk.t)) {
-        load_conn(walk.t);
-        gather(walk.t);
-    }
-    for (int64_t g = walk.t; walk.valid(g); g += walk.step) {
-        const int64_t gnext = g + walk.step;
-        int64_t tile;
-        const FusedArgs a = args_of<MULTI>(jt, job_of<MULTI>(jt, g, tile));
-        const int64_t ne = a.in.n_elem;
-        const int64_t p = tile * T + 16 * wave + c16;  // this lane's element (4 lanes per element)
-        uint4 pf[kPrefetch];
-        prefetch_records(a.rec, a.rec_ptr[tile], a.rec_ptr[tile + 1], int(blockDim.x), pf);
-        double A[S::NG], lm[NQM], lc[NQC];
-        if (p < ne) {
-            const int64_t eid = (a.in.cm.kind == 2 || a.in.cc.kind == 2) ? int64_t(a.elem_order[p]) : p;
-            if (!setup_from_raw<D, P, NQM, NQC>(a.in, raw, v, eid, A, lm, lc) && j == 0) atomicOr(a.in.flags, 1);
-        } else {
-#pragma unroll
-            for (int q = 0; q < S::NG; ++q) A[q] = 0.0;
-#pragma unroll
-            for (int q = 0; q < NQM; ++q) lm[q] = 0.0;
-#pragma unroll
-            for (int q = 0; q < NQC; ++q) lc[q] = 0.0;
+        for (int64_t k = tid; k < a0.qfrag_vec16; k += kWsThreads) dq[k] = gq[k];
+        for (int k = tid; k < NQM * S::NP; k += kWsThreads) {
+            const int q = k / S::NP, i = k % S::NP;
+            sPhiM[k] = a0.in.phi_m[i * NQM + q];
         }
-        if (walk.valid(gnext)) load_conn(gnext);  // in flight during the contraction
-        lds_barrier();  // Q^T fragments ready (first tile) / staged V of the previous tile consumed
-        // V_m^T = X_m^T Q_m^T with X_m = Lambda_m; V_c^T = X_c^T Q_c^T with X_c = Lambda_c (.) W
-        auto xm = [&](int k) { return xm_at<NQM>(lm, k); };
-        auto xc = [&](int k) { return xc_at<NQC, S::NG>(lc, A, k); };
-        if constexpr (!SPLIT) {
-            using CT = typename FormTraits<PF>::qplain_t;
-            const CT *q = reinterpret_cast<const CT *>(sQraw);
-            contract_group_plain<CT, KM, NB, S::NS, T, ST>(q, xm, sVm, lane, 16 * wave);
-            contract_group_plain<CT, KC, NB, S::NS, T, ST>(q + ((KM + 3) / 4) * NB * 64, xc, sVc, lane, 16 * wave);
-        } else {
-            const uint4 *q = reinterpret_cast<const uint4 *>(sQraw);
-            constexpr int NC = Split<PF>::NC;
-            contract_group_split<PF, KM, NB, S::NS, T, ST>(q, xm, sVm, lane, 16 * wave, a.qinv_m);
-            contract_group_split<PF, KC, NB, S::NS, T, ST>(q + NC * ((KM + 31) / 32) * NB * 64, xc, sVc, lane,
-                                                          16 * wave, a.qinv_c);
+        for (int k = tid; k < NQC * S::NP; k += kWsThreads) {
+            const int q = k / S::NP, i = k % S::NP;
+            sPhiC[k] = a0.in.phi_c[i * NQC + q];
         }
-        if (walk.valid(gnext)) gather(gnext);  // in flight during the reduction
-        lds_barrier();
-        tile_reduce(pf, a, tile, sVm, sVc, T, int(blockDim.x));
+        for (int k = tid; k < NQM; k += kWsThreads) sWM[k] = a0.in.w_m[k];
+        for (int k = tid; k < NQC; k += kWsThreads) sWC[k] = a0.in.w_c[k];
+    }
+    // a zero in the (never written) padding column of row 0 of each staged matrix
+    if (tid < 4) sV[(tid >> 1) * BUF + (tid & 1) * MAT + T] = ST(0);
+    const TileWalk walk(jt.n_tiles);
+    lds_barrier();
+    if (tid < kWsProducers) {
+        const int j = lane >> 4, c16 = lane & 15;
+        int32_t v[S::NP];
+        RawElem<D, P> raw;
+        auto load_conn = [&](int64_t g) {
+            int64_t lt;
+            const FusedArgs b = args_of<MULTI>(jt, job_of<MULTI>(jt, g, lt));
+            // lanes past the last element read the last element (unconditional loads keep
+            // the loads of one call in flight together)
+            const int64_t pp = min(lt * T + 16 * wave + c16, b.in.n_elem - 1);
+#pragma unroll
+            for (int i = 0; i < S::NP; ++i) v[i] = b.tconn[i * b.in.n_elem + pp];
+        };
+        auto gather = [&](int64_t g) {
+            int64_t lt;
+            const FusedArgs b = args_of<MULTI>(jt, job_of<MULTI>(jt, g, lt));
+            gather_raw<D, P>(b.in, v, raw);
+        };
+        int64_t g = walk.t;  // every workgroup of a persistent launch has at least one tile
+        load_conn(g);
+        gather(g);
+        if (walk.valid(g + walk.step)) load_conn(g + walk.step);
+        for (int it = 0; walk.valid(g); g += walk.step, ++it) {
+            int64_t tile;
+            const FusedArgs a = args_of<MULTI>(jt, job_of<MULTI>(jt, g, tile));
+            const int64_t ne = a.in.n_elem;
+            const int64_t p = tile * T + 16 * wave + c16;  // this lane's element (4 lanes per element)
+            double A[S::NG], lm[L::MM], lc[L::MC];
+            if (p < ne) {
+                const int64_t eid = (a.in.cm.kind == 2 || a.in.cc.kind == 2) ? int64_t(a.elem_order[p]) : p;
+                if (!lane_setup<D, P, NQM, NQC, PF>(a.in, raw, a.tconn, p, eid, j, sPhiM, sPhiC, sWM, sWC, A, lm,
+                                                    lc))
+                    atomicOr(a.in.flags, 1);
+            } else {
+#pragma unroll
+                for (int q = 0; q < S::NG; ++q) A[q] = 0.0;
+#pragma unroll
+                for (int m = 0; m < L::MM; ++m) lm[m] = 0.0;
+#pragma unroll
+                for (int m = 0; m < L::MC; ++m) lc[m] = 0.0;
+            }
+            const int64_t gn = g + walk.step;
+            if (walk.valid(gn)) {
+                gather(gn);  // its connectivity was loaded one tile ago
+                if (walk.valid(gn + walk.step)) load_conn(gn + walk.step);
+            }
+            ST *bVm = sV + (it & 1) * BUF, *bVc = bVm + MAT;
+            // V_m^T = X_m^T Q_m^T with X_m = Lambda_m; V_c^T = X_c^T Q_c^T with X_c = Lambda_c (.) W
+            if constexpr (!SPLIT) {
+                using CT = typename FormTraits<PF>::qplain_t;
+                const CT *q = reinterpret_cast<const CT *>(sQraw);
+                // k = 4 ks + j: mass node q = k, conductivity (g, q) = divmod(4 ks, NQP) + (0, j)
+                auto xm = [&](int ks) { return lm[ks]; };
+                auto xc = [&](int ks) { return lc[((4 * ks) % L::NQP) / 4] * A[(4 * ks) / L::NQP]; };
+                contract_group_plain<CT, KM, NB, S::NS, T, ST>(q, xm, bVm, lane, 16 * wave);
+                contract_group_plain<CT, KC, NB, S::NS, T, ST>(q + ((KM + 3) / 4) * NB * 64, xc, bVc, lane,
+                                                              16 * wave);
+            } else {
+                const uint4 *q = reinterpret_cast<const uint4 *>(sQraw);
+                constexpr int NC = Split<PF>::NC;
+                // k = 32 ks + 8 j + t: mass node q = k (one k-block), conductivity
+                // g = (32 ks + 8 j) / NQP and node (8 j) mod NQP + t
+                auto xm = [&](int ks, int t) { return ks == 0 ? lm[t] : 0.0; };
+                auto xc = [&](int ks, int t) {
+                    const int gg = (32 * ks + 8 * j) / L::NQP;
+                    double ag = 0.0;
+#pragma unroll
+                    for (int h = 0; h < S::NG; ++h) ag = gg == h ? A[h] : ag;
+                    return lc[t] * ag;
+                };
+                contract_group_split<PF, KM, NB, S::NS, T, ST>(q, xm, bVm, lane, 16 * wave, a.qinv_m);
+                contract_group_split<PF, KC, NB, S::NS, T, ST>(q + NC * ((KM + 31) / 32) * NB * 64, xc, bVc, lane,
+                                                              16 * wave, a.qinv_c);
+            }
+            lds_barrier();  // tile i staged; the consumers are done with buffer (i + 1) % 2
+        }
+    } else {
+        const int ct = tid - kWsProducers;
+        uint4 R[kChunk], Rn[kChunk];
+        // record of round q of chunk c: r0 + (c * kChunk + q) * NCT + ct, clamped to the tile
+        auto load_chunk = [&](const uint4 *rec, int64_t r0, int64_t r1, int64_t c, uint4 (&dst)[kChunk]) {
+#pragma unroll
+            for (int q = 0; q < kChunk; ++q) {
+                const int64_t k = r0 + (c * kChunk + q) * NCT + ct;
+                dst[q] = rec[k < r1 ? k : r1 - 1];
+            }
+        };
+        int64_t g = walk.t;
+        {
+            int64_t tile;
+            const FusedArgs a = args_of<MULTI>(jt, job_of<MULTI>(jt, g, tile));
+            load_chunk(a.rec, a.rec_ptr[tile], a.rec_ptr[tile + 1], 0, R);
+        }
+        lds_barrier();  // first tile staged
+        for (int it = 1;; ++it, g += walk.step) {
+            int64_t tile;
+            const FusedArgs a = args_of<MULTI>(jt, job_of<MULTI>(jt, g, tile));
+            const int64_t r0 = a.rec_ptr[tile], r1 = a.rec_ptr[tile + 1];
+            const int64_t nch = (r1 - r0 + int64_t(kChunk) * NCT - 1) / (int64_t(kChunk) * NCT);
+            const int64_t gn = g + walk.step;
+            const bool more = walk.valid(gn);
+            const uint4 *rec_n = a.rec;
+            int64_t r0n = r0, r1n = r1;
+            if (more) {
+                int64_t tn;
+                const FusedArgs an = args_of<MULTI>(jt, job_of<MULTI>(jt, gn, tn));
+                rec_n = an.rec;
+                r0n = an.rec_ptr[tn];
+                r1n = an.rec_ptr[tn + 1];
+            }
+            const ST *bVm = sV + ((it - 1) & 1) * BUF, *bVc = bVm + MAT;
+            double *sink_m = a.sink + ct, *sink_c = a.sink + NCT + ct;
+            for (int64_t c = 0; c < nch; ++c) {
+                // next chunk: the following one of this tile, else the next tile's first
+                const bool inner = c + 1 < nch;
+                load_chunk(inner ? a.rec : rec_n, inner ? r0 : r0n, inner ? r1 : r1n, inner ? c + 1 : 0, Rn);
+#pragma unroll
+                for (int q = 0; q < kChunk; ++q) {
+                    const int64_t k = r0 + (c * kChunk + q) * NCT + ct;
+                    double am, ac;
+                    record_sums(R[q], bVm, bVc, uint32_t(T), am, ac);
+                    const int32_t t = int32_t(R[q].x);
+                    const int64_t pi = -int64_t(t) - 1;
+                    double *dm = t >= 0 ? (a.M ? a.M + t : sink_m) : a.Mpart + pi;
+                    double *dc = t >= 0 ? (a.C ? a.C + t : sink_c) : a.Cpart + pi;
+                    const bool active = k < r1;
+                    *(active ? dm : sink_m) = am;
+                    *(active ? dc : sink_c) = ac;
+                }
+#pragma unroll
+                for (int q = 0; q < kChunk; ++q) R[q] = Rn[q];
+            }
+            if (!more) break;
+            lds_barrier();  // next tile staged; this buffer may be overwritten
+        }
     }
 }
 
 // Shared slots: each output (upper or mirror entry, ascending CSR order) sums
-// its partials in ascending tile order.
+// its slot's partials, which are stored contiguously in ascending tile order.
 __global__ __launch_bounds__(256) void fixup_kernel(FixupTable ft)
 {
     int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -480,13 +682,13 @@ __global__ __launch_bounds__(256) void fixup_kernel(FixupTable ft)
         jb = lo;
     }
     const FixupArgs a = jb < 0 ? ft.one : ft.jobs[jb];
-    const int32_t lo = a.fix_ptr[f], hi = a.fix_ptr[f + 1];
+    const int32_t k = a.fix_src[f];
+    const int64_t lo = a.part_ptr[k], hi = a.part_ptr[k + 1];
     const int32_t t = a.fix_target[f];
-    double m = 0.0, c = 0.0;
-    for (int32_t k = lo; k < hi; ++k) {
-        const int32_t pi = a.fix_idx[k];
-        if (a.M) m += a.Mpart[pi];
-        if (a.C) c += a.Cpart[pi];
+    double m = a.Mpart[lo], c = a.Cpart[lo];
+    for (int64_t q = lo + 1; q < hi; ++q) {
+        m += a.Mpart[q];
+        c += a.Cpart[q];
     }
     if (a.M) a.M[t] = m;
     if (a.C) a.C[t] = c;
@@ -520,11 +722,9 @@ hipError_t launch_fused(const JobTable &jt, int D, int P, int nqm, int nqc, int 
 #define QXA_LAUNCH_MFMA(d, p, m, c, PF, MULTI)                                                            \
     {                                                                                                     \
         constexpr int T = tile_size(d, p);                                                                \
-        using STg = typename FormTraits<PF>::stage_t;                                                     \
-        const size_t lds = ((2 * sizeof(STg) * Shape<d, p>::NS * (T + 1) + 15) / 16) * 16 +               \
-                           size_t(a.qfrag_vec16) * 16;                                                    \
-        auto k = fused_mfma_kernel<d, p, m, c, PF, T, MULTI>;                                             \
-        k<<<persistent_grid(k, 4 * T, lds, n_tiles), 4 * T, lds, st>>>(jt);                               \
+        const size_t lds = WsLds<d, p, m, c, PF, T>::bytes(a.qfrag_vec16);                              \
+        auto k = fused_ws_kernel<d, p, m, c, PF, T, MULTI>;                                               \
+        k<<<persistent_grid(k, kWsThreads, lds, n_tiles), kWsThreads, lds, st>>>(jt);                     \
     }
 #define X(d, p, m, c)                                                                                      \
     if (D == d && P == p && nqm == m && nqc == c) {                                                        \

@@ -17,6 +17,7 @@ namespace qxa {
 
 constexpr int kMaxNp = 20;  // P3 tetrahedra
 constexpr int kMaxNq = 64;
+constexpr int kSinkDoubles = 1024;
 
 inline int n_local(int dim, int order)
 {
@@ -77,22 +78,18 @@ struct TilePlan {
     // One 16-byte record per output of a tile: {target, c0|c1, c2|c3, c4|c5}.
     // target >= 0: a CSR slot owned by the tile (upper and mirror entries are
     // separate records with the same contributions); target < 0: partial
-    // -(p + 1) of an upper slot shared between tiles. c0..c5: padded LDS
-    // indices (s*(T+1) + local element) of the contributions in summation
-    // order, 0xFFFF = none; c5 = 0x8000 | off when there are more than 6: then
-    // c0..c4 are inline and ovf[ovf_ptr[tile] + off] = count, then the rest.
-    // Owned records come first in ascending CSR slot order (coalesced
-    // stores), then the tile's partials, numbered consecutively.
+    // -(p + 1). c0..c5: padded LDS indices (s*(T+1) + local element) of the
+    // contributions in summation order, 0xFFFF = none. Owned records come
+    // first in ascending CSR slot order (coalesced stores), then partials.
     std::vector<uint32_t> rec;        // [4 * n_records]
     std::vector<int64_t> rec_ptr;     // [n_tiles + 1] (in records)
-    std::vector<uint16_t> ovf;
-    std::vector<int64_t> ovf_ptr;     // [n_tiles + 1]
+    // Partials of shared upper slot k (CSR order) are part_ptr[k] ..
+    // part_ptr[k+1] - 1, in ascending tile order, then record order.
+    std::vector<int64_t> part_ptr;    // [n_shared + 1]
     // fix-up outputs (upper and mirror entries of shared slots) in ascending
-    // CSR slot order: fix_ptr[k]..fix_ptr[k+1] index fix_idx, the partials of
-    // fix_target[k] in ascending tile order
-    std::vector<int32_t> fix_ptr;     // [n_fix + 1]
+    // CSR slot order, each with the shared slot whose partials it sums
     std::vector<int32_t> fix_target;  // [n_fix]
-    std::vector<int32_t> fix_idx;     // [2 * n_partials] (each partial read by upper and mirror)
+    std::vector<int32_t> fix_src;     // [n_fix]
     int64_t n_shared = 0;
     int64_t n_partials = 0;
 };
@@ -172,10 +169,10 @@ struct qxa_plan_s {
     int32_t *d_tconn = nullptr, *d_elem_order = nullptr;
     uint32_t *d_rec = nullptr;
     int64_t *d_rec_ptr = nullptr;
-    uint16_t *d_ovf = nullptr;
-    int64_t *d_ovf_ptr = nullptr;
-    int32_t *d_fix_ptr = nullptr, *d_fix_target = nullptr, *d_fix_idx = nullptr;
+    int64_t *d_part_ptr = nullptr;
+    int32_t *d_fix_target = nullptr, *d_fix_src = nullptr;
     int64_t n_fix = 0;
+    double *d_sink = nullptr;     // write target of idle lanes (kSinkDoubles)
     double *d_part = nullptr;     // [2][n_partials]
     // Q^T in MFMA operand order, one block per precision form (FP64, FP32,
     // F16X2, BF16X2, BF16X3), sizes in 16-byte units

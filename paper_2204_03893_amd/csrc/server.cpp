@@ -368,6 +368,7 @@ static void launch_group(qxa_server s, std::vector<Job *> &g)
     const qxa_plan p0 = g[0]->entry->plan;
     const RefTables &R = p0->ref;
     const int prec = g[0]->spec.precision;
+    (void)hipGetLastError();  // launch errors are read back with hipGetLastError
     hipError_t e = hipEventRecord(sl.e0, st);
     const auto now = Clock::now();
     for (size_t k = 0; k < g.size(); ++k) {

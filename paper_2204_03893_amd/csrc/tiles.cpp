@@ -48,7 +48,7 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
                            const double *coords, const HostPlan &hp, int T, TilePlan &tp)
 {
     const int np = n_local(dim, order), ns = n_sym(np);
-    if (int64_t(T + 1) * ns >= 0x8000) return fail(QXA_E_UNSUPPORTED, "tile too large for 15-bit LDS indices");
+    if (int64_t(T + 1) * ns >= 0xffff) return fail(QXA_E_UNSUPPORTED, "tile too large for 16-bit LDS indices");
     tp.T = T;
     tp.n_tiles = (n_elem + T - 1) / T;
     // 1. Morton order of element centroids (vertices only: the map is affine)
@@ -104,63 +104,83 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
         }
         std::sort(buf.begin(), buf.end());
     };
-    // touches per upper slot
-    std::vector<std::atomic<uint32_t>> touch(hp.nnz);
-    for (auto &x : touch) x.store(0, std::memory_order_relaxed);
+    // Records hold at most 6 contributions. A slot is owned by a tile when
+    // that tile alone touches it with at most 6 contributions; otherwise
+    // (several tiles, or more than 6 contributions in one tile) every tile
+    // touching it writes ceil(k / 6) partials of its k contributions, and the
+    // fix-up sums them.
+    auto chunks = [](size_t k) { return uint32_t((k + 5) / 6); };
+    std::vector<std::atomic<uint32_t>> touch(hp.nnz), npart(hp.nnz);
+    std::vector<std::atomic<uint8_t>> big(hp.nnz);
+    for (int64_t u = 0; u < hp.nnz; ++u) {
+        touch[u].store(0, std::memory_order_relaxed);
+        npart[u].store(0, std::memory_order_relaxed);
+        big[u].store(0, std::memory_order_relaxed);
+    }
     parallel_for(nt, [&](int64_t a, int64_t b) {
         std::vector<uint64_t> buf;
         for (int64_t t = a; t < b; ++t) {
             tile_entries(t, buf);
-            for (size_t k = 0; k < buf.size(); ++k)
-                if (k == 0 || (buf[k] >> 32) != (buf[k - 1] >> 32)) touch[buf[k] >> 32].fetch_add(1);
-        }
-    });
-    // 3. records per tile: owned outputs (upper and mirror) sorted by CSR slot,
-    //    then the tile's partials of shared upper slots
-    std::vector<std::vector<uint32_t>> trec(nt);
-    std::vector<std::vector<uint16_t>> tovf(nt);
-    std::vector<std::vector<uint32_t>> tshared(nt);  // upper slot of each partial, in partial order
-    std::atomic<bool> ovf_too_long{false};
-    parallel_for(nt, [&](int64_t a, int64_t b) {
-        std::vector<uint64_t> buf;
-        std::vector<std::pair<uint32_t, std::array<uint16_t, 6>>> owned;
-        std::vector<std::array<uint16_t, 6>> shared;
-        for (int64_t t = a; t < b; ++t) {
-            tile_entries(t, buf);
-            auto &O = tovf[t];
-            O.clear();
-            owned.clear();
-            shared.clear();
-            tshared[t].clear();
             size_t k = 0;
             while (k < buf.size()) {
                 const uint32_t u = uint32_t(buf[k] >> 32);
                 size_t k1 = k;
                 while (k1 < buf.size() && uint32_t(buf[k1] >> 32) == u) ++k1;
-                const size_t n = k1 - k;
-                std::array<uint16_t, 6> c;
-                c.fill(0xffff);
-                if (n <= 6) {
-                    for (size_t q = 0; q < n; ++q) c[q] = uint16_t(buf[k + q] & 0xffff);
-                } else {
-                    for (size_t q = 0; q < 5; ++q) c[q] = uint16_t(buf[k + q] & 0xffff);
-                    if (O.size() >= 0x7fff) ovf_too_long = true;
-                    c[5] = uint16_t(0x8000u | (uint32_t(O.size()) & 0x7fffu));
-                    O.push_back(uint16_t(n - 5));
-                    for (size_t q = 5; q < n; ++q) O.push_back(uint16_t(buf[k + q] & 0xffff));
-                }
-                if (touch[u].load() == 1) {
-                    owned.push_back({u, c});
-                    if (hp.mirror[u] != u) owned.push_back({hp.mirror[u], c});
-                } else {
-                    shared.push_back(c);
-                    tshared[t].push_back(u);
+                touch[u].fetch_add(1, std::memory_order_relaxed);
+                npart[u].fetch_add(chunks(k1 - k), std::memory_order_relaxed);
+                if (k1 - k > 6) big[u].store(1, std::memory_order_relaxed);
+                k = k1;
+            }
+        }
+    });
+    // shared slots in CSR order; partials numbered by (slot, tile, chunk)
+    std::vector<int32_t> sh_id(hp.nnz, -1);
+    std::vector<uint32_t> sh_slot;
+    tp.part_ptr.assign(1, 0);
+    for (int64_t u = 0; u < hp.nnz; ++u)
+        if (touch[u].load() > 1 || big[u].load()) {
+            sh_id[u] = int32_t(sh_slot.size());
+            sh_slot.push_back(uint32_t(u));
+            tp.part_ptr.push_back(tp.part_ptr.back() + int64_t(npart[u].load()));
+        }
+    tp.n_shared = int64_t(sh_slot.size());
+    tp.n_partials = tp.part_ptr.back();
+    if (tp.n_partials >= (int64_t(1) << 31)) return fail(QXA_E_UNSUPPORTED, "too many partials");
+    // records per tile: owned outputs (upper and mirror) sorted by CSR slot,
+    // then the tile's partials; a partial's index is fixed in a second,
+    // sequential pass over the tiles in ascending order
+    std::vector<std::vector<uint32_t>> trec(nt);
+    std::vector<std::vector<std::pair<uint32_t, uint32_t>>> tpart(nt);  // (shared id, record position)
+    parallel_for(nt, [&](int64_t a, int64_t b) {
+        std::vector<uint64_t> buf;
+        std::vector<std::pair<uint32_t, std::array<uint16_t, 6>>> owned;
+        std::vector<std::pair<uint32_t, std::array<uint16_t, 6>>> shared;
+        for (int64_t t = a; t < b; ++t) {
+            tile_entries(t, buf);
+            owned.clear();
+            shared.clear();
+            size_t k = 0;
+            while (k < buf.size()) {
+                const uint32_t u = uint32_t(buf[k] >> 32);
+                size_t k1 = k;
+                while (k1 < buf.size() && uint32_t(buf[k1] >> 32) == u) ++k1;
+                for (size_t c0 = k; c0 < k1; c0 += 6) {
+                    std::array<uint16_t, 6> c;
+                    c.fill(0xffff);
+                    for (size_t q = c0; q < std::min(k1, c0 + 6); ++q) c[q - c0] = uint16_t(buf[q] & 0xffff);
+                    if (sh_id[u] < 0) {
+                        owned.push_back({u, c});
+                        if (hp.mirror[u] != u) owned.push_back({hp.mirror[u], c});
+                    } else {
+                        shared.push_back({uint32_t(sh_id[u]), c});
+                    }
                 }
                 k = k1;
             }
             std::sort(owned.begin(), owned.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
             auto &R = trec[t];
             R.clear();
+            tpart[t].clear();
             auto put = [&](uint32_t tgt, const std::array<uint16_t, 6> &c) {
                 R.push_back(tgt);
                 R.push_back(uint32_t(c[0]) | (uint32_t(c[1]) << 16));
@@ -168,50 +188,24 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
                 R.push_back(uint32_t(c[4]) | (uint32_t(c[5]) << 16));
             };
             for (auto &o : owned) put(o.first, o.second);
-            for (auto &c : shared) put(0u, c);  // partial index filled below
+            for (auto &sc : shared) {
+                tpart[t].push_back({sc.first, uint32_t(R.size() / 4)});
+                put(0u, sc.second);
+            }
         }
     });
-    if (ovf_too_long) return fail(QXA_E_UNSUPPORTED, "tile overflow list longer than 15-bit offsets");
-    // partials: consecutive per tile, in ascending tile order
-    tp.rec_ptr.assign(nt + 1, 0);
-    tp.ovf_ptr.assign(nt + 1, 0);
-    std::vector<int64_t> part_base(nt + 1, 0);
-    for (int64_t t = 0; t < nt; ++t) {
-        tp.rec_ptr[t + 1] = tp.rec_ptr[t] + int64_t(trec[t].size() / 4);
-        tp.ovf_ptr[t + 1] = tp.ovf_ptr[t] + int64_t(tovf[t].size());
-        part_base[t + 1] = part_base[t] + int64_t(tshared[t].size());
-        const size_t n_owned = trec[t].size() / 4 - tshared[t].size();
-        for (size_t r = 0; r < tshared[t].size(); ++r)
-            trec[t][4 * (n_owned + r)] = uint32_t(-(part_base[t] + int64_t(r)) - 1);
-    }
-    tp.n_partials = part_base[nt];
-    if (tp.n_partials >= (int64_t(1) << 31)) return fail(QXA_E_UNSUPPORTED, "too many partials");
-    tp.rec.resize(4 * size_t(tp.rec_ptr[nt]));
-    tp.ovf.resize(size_t(tp.ovf_ptr[nt]));
-    parallel_for(nt, [&](int64_t a, int64_t b) {
-        for (int64_t t = a; t < b; ++t) {
-            std::copy(trec[t].begin(), trec[t].end(), tp.rec.begin() + 4 * tp.rec_ptr[t]);
-            std::copy(tovf[t].begin(), tovf[t].end(), tp.ovf.begin() + tp.ovf_ptr[t]);
-        }
-    });
-    // 4. fix-up outputs: every shared upper slot and its mirror, in CSR order,
-    //    each listing its partials in ascending tile order
-    std::vector<int32_t> sh_id(hp.nnz, -1);
-    std::vector<uint32_t> sh_slot;
-    for (int64_t u = 0; u < hp.nnz; ++u)
-        if (touch[u].load() > 1) {
-            sh_id[u] = int32_t(sh_slot.size());
-            sh_slot.push_back(uint32_t(u));
-        }
-    tp.n_shared = int64_t(sh_slot.size());
-    std::vector<int32_t> sptr(sh_slot.size() + 1, 0);
-    for (size_t f = 0; f < sh_slot.size(); ++f) sptr[f + 1] = sptr[f] + int32_t(touch[sh_slot[f]].load());
-    std::vector<int32_t> slist(sptr.back());
     {
-        std::vector<int32_t> fill(sptr.begin(), sptr.end() - 1);
+        std::vector<int64_t> fill(tp.part_ptr.begin(), tp.part_ptr.end() - 1);
         for (int64_t t = 0; t < nt; ++t)
-            for (size_t r = 0; r < tshared[t].size(); ++r) slist[fill[sh_id[tshared[t][r]]]++] = int32_t(part_base[t] + r);
+            for (auto &pr : tpart[t]) trec[t][4 * size_t(pr.second)] = uint32_t(-(fill[pr.first]++) - 1);
     }
+    tp.rec_ptr.assign(nt + 1, 0);
+    for (int64_t t = 0; t < nt; ++t) tp.rec_ptr[t + 1] = tp.rec_ptr[t] + int64_t(trec[t].size() / 4);
+    tp.rec.resize(4 * size_t(tp.rec_ptr[nt]));
+    parallel_for(nt, [&](int64_t a, int64_t b) {
+        for (int64_t t = a; t < b; ++t) std::copy(trec[t].begin(), trec[t].end(), tp.rec.begin() + 4 * tp.rec_ptr[t]);
+    });
+    // fix-up outputs: every shared upper slot and its mirror, in CSR order
     std::vector<std::pair<uint32_t, int32_t>> fout;  // (target slot, shared id)
     for (size_t f = 0; f < sh_slot.size(); ++f) {
         const uint32_t u = sh_slot[f];
@@ -219,13 +213,11 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
         if (hp.mirror[u] != u) fout.push_back({hp.mirror[u], int32_t(f)});
     }
     std::sort(fout.begin(), fout.end());
-    tp.fix_ptr.assign(1, 0);
-    tp.fix_target.clear();
-    tp.fix_idx.clear();
-    for (auto &o : fout) {
-        tp.fix_target.push_back(int32_t(o.first));
-        for (int32_t k = sptr[o.second]; k < sptr[o.second + 1]; ++k) tp.fix_idx.push_back(slist[k]);
-        tp.fix_ptr.push_back(int32_t(tp.fix_idx.size()));
+    tp.fix_target.resize(fout.size());
+    tp.fix_src.resize(fout.size());
+    for (size_t f = 0; f < fout.size(); ++f) {
+        tp.fix_target[f] = int32_t(fout[f].first);
+        tp.fix_src[f] = fout[f].second;
     }
     return QXA_OK;
 }
@@ -237,44 +229,33 @@ namespace qxa {
 // Structural check of a tile plan against the pattern: every index the fused
 // and fix-up kernels use is in bounds, every CSR slot is written exactly once
 // (by one tile or by the fix-up), every partial is written by exactly one tile
-// and read by exactly one shared slot, and every element entry is reduced
+// and summed by exactly one shared slot, and every element entry is reduced
 // exactly once. Runs on the host before the plan is used.
 qxa_status check_tile_plan(int np, int64_t n_elem, const HostPlan &hp, const TilePlan &tp)
 {
     const int ns = n_sym(np);
     const int64_t T = tp.T, TP = T + 1;
     std::vector<uint8_t> slot_w(hp.nnz, 0), part_w(tp.n_partials, 0), used;
-    std::vector<uint32_t> part_r(tp.n_partials, 0);
     if (int64_t(tp.rec_ptr.size()) != tp.n_tiles + 1 || tp.rec_ptr[0] != 0 ||
-        int64_t(tp.ovf_ptr.size()) != tp.n_tiles + 1 || int64_t(tp.rec.size()) != 4 * tp.rec_ptr[tp.n_tiles])
+        int64_t(tp.rec.size()) != 4 * tp.rec_ptr[tp.n_tiles] || int64_t(tp.part_ptr.size()) != tp.n_shared + 1 ||
+        tp.part_ptr[0] != 0 || tp.part_ptr[tp.n_shared] != tp.n_partials)
         return fail(QXA_E_INVALID, "tile plan: bad sizes");
     auto write_slot = [&](int64_t g) -> bool { return g >= 0 && g < hp.nnz && slot_w[g]++ == 0; };
     for (int64_t t = 0; t < tp.n_tiles; ++t) {
         const int64_t p0 = t * T, nloc = std::min<int64_t>(T, n_elem - p0);
         used.assign(size_t(TP) * ns, 0);
-        const int64_t ob = tp.ovf_ptr[t], oe = tp.ovf_ptr[t + 1];
-        auto valid = [&](uint32_t c) { return c < uint32_t(TP * ns) && int64_t(c % TP) < nloc; };
         for (int64_t r = tp.rec_ptr[t]; r < tp.rec_ptr[t + 1]; ++r) {
             const uint32_t *R = &tp.rec[4 * r];
             const uint32_t c[6] = {R[1] & 0xffffu, R[1] >> 16, R[2] & 0xffffu, R[2] >> 16, R[3] & 0xffffu, R[3] >> 16};
-            std::vector<uint32_t> list;
-            for (int q = 0; q < 5; ++q)
-                if (c[q] != 0xffffu) list.push_back(c[q]);
-            if (c[5] != 0xffffu) {
-                if (c[5] < 0x8000u) {
-                    list.push_back(c[5]);
-                } else {
-                    const int64_t off = ob + (c[5] & 0x7fffu);
-                    if (off >= oe || off + int64_t(tp.ovf[off]) >= oe)
-                        return fail(QXA_E_INVALID, "tile plan: overflow list out of range");
-                    for (int q = 1; q <= tp.ovf[off]; ++q) list.push_back(tp.ovf[off + q]);
-                }
+            int n = 0;
+            for (int q = 0; q < 6; ++q) {
+                if (c[q] == 0xffffu) continue;
+                if (c[q] >= uint32_t(TP * ns) || int64_t(c[q] % TP) >= nloc)
+                    return fail(QXA_E_INVALID, "tile plan: LDS index out of range");
+                used[c[q]] = 1;
+                ++n;
             }
-            if (list.empty()) return fail(QXA_E_INVALID, "tile plan: empty record");
-            for (uint32_t x : list) {
-                if (!valid(x)) return fail(QXA_E_INVALID, "tile plan: LDS index out of range");
-                used[x] = 1;
-            }
+            if (n == 0) return fail(QXA_E_INVALID, "tile plan: empty record");
             const int32_t g = int32_t(R[0]);
             if (g >= 0) {
                 if (!write_slot(g)) return fail(QXA_E_INVALID, "tile plan: slot written twice");
@@ -287,20 +268,22 @@ qxa_status check_tile_plan(int np, int64_t n_elem, const HostPlan &hp, const Til
             for (int s = 0; s < ns; ++s)
                 if (!used[size_t(s) * TP + k]) return fail(QXA_E_INVALID, "tile plan: contribution never reduced");
     }
+    for (int64_t k = 0; k < tp.n_shared; ++k)
+        if (tp.part_ptr[k + 1] - tp.part_ptr[k] < 2) return fail(QXA_E_INVALID, "tile plan: shared slot with < 2 partials");
     const int64_t nfix = int64_t(tp.fix_target.size());
-    if (int64_t(tp.fix_ptr.size()) != nfix + 1) return fail(QXA_E_INVALID, "tile plan: bad fix-up sizes");
+    if (int64_t(tp.fix_src.size()) != nfix) return fail(QXA_E_INVALID, "tile plan: bad fix-up sizes");
+    std::vector<uint8_t> src_seen(tp.n_shared, 0);
     for (int64_t f = 0; f < nfix; ++f) {
-        if (tp.fix_ptr[f + 1] - tp.fix_ptr[f] < 2) return fail(QXA_E_INVALID, "tile plan: shared slot with < 2 tiles");
-        for (int32_t k = tp.fix_ptr[f]; k < tp.fix_ptr[f + 1]; ++k) {
-            const int32_t pi = tp.fix_idx[k];
-            if (pi < 0 || pi >= tp.n_partials) return fail(QXA_E_INVALID, "tile plan: bad partial index");
-            part_r[pi]++;
-        }
+        const int32_t k = tp.fix_src[f];
+        if (k < 0 || k >= tp.n_shared) return fail(QXA_E_INVALID, "tile plan: bad shared slot index");
+        src_seen[k] = 1;
+        if (f > 0 && tp.fix_target[f] <= tp.fix_target[f - 1]) return fail(QXA_E_INVALID, "tile plan: fix-up not sorted");
         if (!write_slot(tp.fix_target[f])) return fail(QXA_E_INVALID, "tile plan: fix-up slot written twice");
     }
     for (int64_t k = 0; k < tp.n_partials; ++k)
-        if (part_w[k] != 1 || part_r[k] < 1 || part_r[k] > 2)
-            return fail(QXA_E_INVALID, "tile plan: partial not written once / read by its slot");
+        if (part_w[k] != 1) return fail(QXA_E_INVALID, "tile plan: partial not written exactly once");
+    for (int64_t k = 0; k < tp.n_shared; ++k)
+        if (!src_seen[k]) return fail(QXA_E_INVALID, "tile plan: shared slot never summed");
     for (int64_t t = 0; t < hp.nnz; ++t)
         if (slot_w[t] != 1) return fail(QXA_E_INVALID, "tile plan: CSR slot not written exactly once");
     return QXA_OK;
