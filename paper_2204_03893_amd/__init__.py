@@ -364,6 +364,7 @@ class Server:
         check(lib().qxa_server_create(C.byref(o), C.byref(self.handle)))
         self._keep = {}
         self._nnz = {}
+        self._meshes = {}  # resident plans refer to their meshes: keep them until close()
 
     def submit(self, mesh: Mesh, rule_m, rule_c=None, law_m=("const", 1.0), law_c=("const", 1.0), field_m=None,
                field_c=None, precision="fp64", tag=0, qpoint=False):
@@ -375,7 +376,8 @@ class Server:
         job = _Job(mesh.handle, qm, qc, cm, cc, _precision(precision), int(tag))
         t = C.c_uint64()
         check(lib().qxa_server_submit(self.handle, C.byref(job), C.byref(t)))
-        self._keep[t.value] = (mesh, k1, k2)
+        self._keep[t.value] = (k1, k2)
+        self._meshes[id(mesh)] = mesh
         return t.value
 
     def poll(self, max_n=256):
@@ -432,6 +434,7 @@ class Server:
             lib().qxa_server_destroy(self.handle)
             self.handle = C.c_void_p()
             self._keep.clear()
+            self._meshes.clear()
 
     def __del__(self):
         try:

@@ -303,9 +303,9 @@ qxa_status qxa_mesh_destroy(qxa_mesh m)
 qxa_status qxa_plan_destroy(qxa_plan p)
 {
     if (!p) return QXA_OK;
-    hipSetDevice(p->mesh->device);
+    hipSetDevice(p->device);
     void *bufs[] = {p->d_row_ptr, p->d_col_idx, p->d_tconn, p->d_elem_order, p->d_rec, p->d_rec_ptr,
-                    p->d_part_ptr, p->d_fix_target, p->d_fix_src, p->d_sink, p->d_part, p->d_qfrag[0],
+                    p->d_part_ptr, p->d_fix_target, p->d_fix_mirror, p->d_sink, p->d_part, p->d_qfrag[0],
                     p->d_qfrag[1], p->d_qfrag[2], p->d_qfrag[3], p->d_qfrag[4], p->d_tables, p->d_tables_f,
                     p->d_V, p->d_flags};
     for (void *b : bufs) plan_free(p, b);
@@ -334,6 +334,8 @@ qxa_status plan_stage(qxa_mesh mesh, const qxa_quad &mr, const qxa_quad &cr, Pla
     if (st) return st;
     g.mfma = fused_uses_mfma(T.dim, T.order);
     if (g.mfma) build_qfrags(T, g.frag, g.f16_qinv);
+    if (!split_ok(T.dim, T.order, T.nq_m, T.nq_c))
+        for (int f = QXA_F16X2; f <= QXA_BF16X3; ++f) g.frag[f].clear();
     // reference tables: FP64 block and an FP32 copy
     auto put = [&](const std::vector<double> &v) {
         size_t off = g.tab.size();
@@ -357,6 +359,7 @@ qxa_status plan_upload(qxa_mesh mesh, const PlanStaging &g, DevArena *arena, boo
     QXA_HIP(hipSetDevice(mesh->device));
     auto *p = new qxa_plan_s();
     p->mesh = mesh;
+    p->device = mesh->device;
     p->arena = arena;
     p->ref = g.ref;
     const HostPlan &hp = g.hp;
@@ -375,7 +378,7 @@ qxa_status plan_upload(qxa_mesh mesh, const PlanStaging &g, DevArena *arena, boo
     if (!st) st = plan_upload_buf(p, &p->d_rec_ptr, tp.rec_ptr.data(), tp.rec_ptr.size());
     if (!st) st = plan_upload_buf(p, &p->d_part_ptr, tp.part_ptr.data(), tp.part_ptr.size());
     if (!st) st = plan_upload_buf(p, &p->d_fix_target, tp.fix_target.data(), tp.fix_target.size());
-    if (!st) st = plan_upload_buf(p, &p->d_fix_src, tp.fix_src.data(), tp.fix_src.size());
+    if (!st) st = plan_upload_buf(p, &p->d_fix_mirror, tp.fix_mirror.data(), tp.fix_mirror.size());
     if (!st) st = plan_alloc(p, &p->d_sink, size_t(kSinkDoubles));
     if (!st && own_scratch) st = plan_alloc(p, &p->d_part, size_t(2) * tp.n_partials);
     if (g.mfma) {
@@ -505,10 +508,10 @@ static qxa_status fill_inputs(qxa_plan p, const qxa_coeff *mass, const qxa_coeff
                               FormInputs &in, const void **Qm, const void **Qc)
 {
     if (precision < QXA_FP64 || precision > QXA_BF16X3) return fail(QXA_E_INVALID, "unknown precision form");
-    if (precision > QXA_FP32 && !fused_uses_mfma(p->ref.dim, p->ref.order))
+    if (precision > QXA_FP32 && !split_ok(p->ref.dim, p->ref.order, p->ref.nq_m, p->ref.nq_c))
         return fail(QXA_E_UNSUPPORTED,
-                    "split 16-bit forms run on the matrix cores, used for the dense contractions (2D P2/P3, 3D P2); "
-                    "use QXA_FP32 as the reduced-precision form here");
+                    "split 16-bit forms run on the matrix cores with Q staged on chip (2D P2/P3, 3D P2, at most 16 "
+                    "conductivity nodes); use QXA_FP32 as the reduced-precision form here");
     qxa_status st = to_coeff(mass, in.cm, "mass");
     if (!st) st = to_coeff(stiff, in.cc, "stiffness");
     if (st) return st;
@@ -553,9 +556,8 @@ qxa_status make_fused_args(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *s
     a.qfrag_vec16 = p->qfrag_vec16[precision];
     a.qinv_m = precision == QXA_F16X2 ? p->f16_qinv[0] : 1.0;
     a.qinv_c = precision == QXA_F16X2 ? p->f16_qinv[1] : 1.0;
-    a.Mpart = part;
-    a.Cpart = part ? part + p->n_partials : nullptr;
-    f = FixupArgs{p->n_fix, p->d_fix_target, p->d_fix_src, p->d_part_ptr, a.Mpart, a.Cpart, M, C};
+    a.part = part;
+    f = FixupArgs{p->n_fix, p->d_fix_target, p->d_fix_mirror, p->d_part_ptr, part, M, C};
     return QXA_OK;
 }
 
@@ -660,6 +662,7 @@ qxa_status qxa_plan_timing_report(qxa_plan p, char *buf, size_t cap)
 
 struct qxa_graph_s {
     qxa_plan plan = nullptr;
+    int device = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -695,6 +698,7 @@ qxa_status qxa_graph_create(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *
     }
     auto *gr = new qxa_graph_s();
     gr->plan = p;
+    gr->device = p->device;
     gr->graph = g;
     e = hipGraphInstantiate(&gr->exec, g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
@@ -709,7 +713,7 @@ qxa_status qxa_graph_create(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *
 qxa_status qxa_graph_launch(qxa_graph g, void *stream)
 {
     if (!g) return fail(QXA_E_INVALID, "null graph");
-    QXA_HIP(hipSetDevice(g->plan->mesh->device));
+    QXA_HIP(hipSetDevice(g->device));
     QXA_HIP(hipGraphLaunch(g->exec, reinterpret_cast<hipStream_t>(stream)));
     return QXA_OK;
 }
@@ -717,7 +721,7 @@ qxa_status qxa_graph_launch(qxa_graph g, void *stream)
 qxa_status qxa_graph_destroy(qxa_graph g)
 {
     if (!g) return QXA_OK;
-    hipSetDevice(g->plan->mesh->device);
+    hipSetDevice(g->device);
     if (g->exec) hipGraphExecDestroy(g->exec);
     if (g->graph) hipGraphDestroy(g->graph);
     delete g;

@@ -17,16 +17,24 @@ namespace qxa {
     X(2, 1, 3, 3) X(2, 2, 6, 6) X(2, 3, 12, 12) X(3, 1, 4, 4) X(3, 2, 11, 11) X(3, 3, 24, 24) X(2, 1, 3, 1)   \
         X(2, 2, 6, 3) X(2, 3, 12, 6) X(3, 1, 4, 1) X(3, 2, 11, 4) X(3, 3, 24, 11)
 
-// Elements per tile of the fused kernels (both matrices staged in LDS,
-// 2 * NS * (T + 1) * 8 B). Vector-ALU variant (P1, 3D P3): one lane per
-// element. Matrix-core variant (2D P2/P3, 3D P2): 16 elements per wave, 8
-// waves per workgroup, Q^T fragments staged next to V.
+// Elements per tile of the fused kernels. Vector-ALU variant (P1): one lane
+// per element. Matrix-core variant (P2, P3): 4 producer waves of 16 elements
+// (two LDS buffers of both matrices, 2 * 2 * NS * (T + 1) values, next to
+// Q^T); 3D P3 (NS = 210) keeps one 16-element group whose row blocks the
+// producer waves split.
 constexpr int tile_size(int D, int P)
 {
-    return (D == 3 && P == 3) ? 32 : (P >= 2) ? 64 : 256;
+    return (D == 3 && P == 3) ? 16 : (P >= 2) ? 64 : 256;
 }
 
 bool fused_uses_mfma(int D, int P);
+
+// Split 16-bit forms: Q^T staged in LDS (not the T = 16 shape) and at most 16
+// padded conductivity nodes and 32 mass nodes per element.
+constexpr bool split_ok(int D, int P, int nqm, int nqc)
+{
+    return P >= 2 && tile_size(D, P) != 16 && (nqc + 7) / 8 * 8 <= 16 && nqm <= 32;
+}
 
 struct FormArgs {
     FormInputs in;
@@ -47,7 +55,7 @@ struct FusedArgs {
     const int64_t *rec_ptr;     // [n_tiles + 1]
     double *sink;               // write target of idle lanes (at least 1024 doubles)
     double *M, *C;              // CSR values (either may be null)
-    double *Mpart, *Cpart;      // partials of slots shared between tiles
+    double *part;               // [n_partials][2] partials of shared slots (mass, conductivity)
 };
 
 // Jobs of one launch: a single assembly is carried by value in `one`
@@ -65,10 +73,10 @@ struct JobTable {
 
 struct FixupArgs {
     int64_t n_fix;
-    const int32_t *fix_target;  // [n_fix] CSR slot (ascending)
-    const int32_t *fix_src;     // [n_fix] shared slot whose partials are summed
-    const int64_t *part_ptr;    // [n_shared + 1] partial ranges, ascending tile order
-    const double *Mpart, *Cpart;
+    const int32_t *fix_target;  // [n_fix] shared upper slot (ascending)
+    const int32_t *fix_mirror;  // [n_fix] its mirror slot (== target on the diagonal)
+    const int64_t *part_ptr;    // [n_fix + 1] partial ranges, ascending tile order
+    const double *part;         // [n_partials][2]: (mass, conductivity) partial pairs
     double *M, *C;
 };
 

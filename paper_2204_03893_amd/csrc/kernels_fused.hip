@@ -11,6 +11,7 @@
 // tiles are written as partials and summed by the fix-up kernel in
 // ascending tile order. No float atomics: results are bitwise reproducible.
 #include <algorithm>
+#include <type_traits>
 
 #include "../../include/qxa.h"
 #include "kernels.hpp"
@@ -43,6 +44,28 @@ __device__ __forceinline__ void record_sums(const uint4 R, const ST *sVm, const 
     }
 }
 
+// The same for V_m and V_c staged interleaved, pair (V_m, V_c) of entry c at
+// sV[2 c], sV[2 c + 1]: one LDS read per contribution.
+template <typename ST>
+__device__ __forceinline__ void record_sums_pair(const uint4 R, const ST *sV, uint32_t zero, double &am, double &ac)
+{
+    using ST2 = typename std::conditional<sizeof(ST) == 8, double2, float2>::type;
+    const ST2 *v2 = reinterpret_cast<const ST2 *>(sV);
+    uint32_t c[6] = {R.y & 0xffffu, R.y >> 16, R.z & 0xffffu, R.z >> 16, R.w & 0xffffu, R.w >> 16};
+#pragma unroll
+    for (int q = 0; q < 6; ++q) c[q] = c[q] == 0xffffu ? zero : c[q];
+    ST2 v[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) v[q] = v2[c[q]];
+    am = double(v[0].x);
+    ac = double(v[0].y);
+#pragma unroll
+    for (int q = 1; q < 6; ++q) {
+        am += double(v[q].x);
+        ac += double(v[q].y);
+    }
+}
+
 // Reduction of one record into its CSR slot (target >= 0) or partial.
 template <typename ST>
 __device__ __forceinline__ void reduce_record(const uint4 R, const ST *sVm, const ST *sVc, uint32_t zero,
@@ -55,8 +78,8 @@ __device__ __forceinline__ void reduce_record(const uint4 R, const ST *sVm, cons
         if (a.M) a.M[t] = am;
         if (a.C) a.C[t] = ac;
     } else {
-        a.Mpart[-int64_t(t) - 1] = am;
-        a.Cpart[-int64_t(t) - 1] = ac;
+        a.part[2 * (-int64_t(t) - 1)] = am;
+        a.part[2 * (-int64_t(t) - 1) + 1] = ac;
     }
 }
 
@@ -274,34 +297,74 @@ struct Split<QXA_F16X2> {
 // Contraction of one 16-element group, plain FP64/FP32 operands (16x16x4 MFMA).
 // xk(ks) is this lane's A-operand entry of k-step ks: X[k = 4 ks + lane / 16]
 // of the lane's element (compile-time ks).
-template <typename CT, int K, int NB, int NS, int T, typename ST, class XK>
-__device__ __forceinline__ void contract_group_plain(const CT *sQ, XK &&xk, ST *sV, int lane, int col0)
+// NBW row blocks starting at nb0 (of NB) are computed; sQ may be LDS or global.
+template <typename CT, int K, int NB, int NS, int T, typename ST, int STRIDE, int NBW = NB, class XK>
+__device__ __forceinline__ void contract_group_plain(const CT *sQ, XK &&xk, ST *sV, int lane, int col0, int nb0 = 0)
 {
     using MF = Mfma<CT>;
     constexpr int KS = (K + 3) / 4;
     const int c16 = lane & 15;
-    typename MF::acc_t acc[NB];
+    typename MF::acc_t acc[NBW];
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) acc[nb] = typename MF::acc_t{0, 0, 0, 0};
+    for (int nb = 0; nb < NBW; ++nb) acc[nb] = typename MF::acc_t{0, 0, 0, 0};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
         const CT x = CT(xk(ks));
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[nb] = MF::step(x, sQ[(ks * NB + nb) * 64 + lane], acc[nb]);
+        for (int nb = 0; nb < NBW; ++nb)
+            if (NBW == NB || nb0 + nb < NB)
+                acc[nb] = MF::step(x, sQ[(ks * NB + nb0 + nb) * 64 + lane], acc[nb]);
     }
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-        const int s = 16 * nb + c16;
+    for (int nb = 0; nb < NBW; ++nb) {
+        const int s = 16 * (nb0 + nb) + c16;
         if (s < NS)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) sV[s * (T + 1) + col0 + MF::row(lane, r)] = ST(acc[nb][r]);
+            for (int r = 0; r < 4; ++r) sV[STRIDE * (s * (T + 1) + col0 + MF::row(lane, r))] = ST(acc[nb][r]);
+    }
+}
+
+// Conductivity contraction with Q^T read from global memory (shapes whose
+// Q^T does not fit in LDS). The K order k = g * NQP + q is walked as a rolled
+// loop over g with the NQP / 4 steps of one g unrolled, which bounds the
+// fragments in flight; lc[m] holds this lane's node q = 4 m + j.
+template <typename CT, int NQP, int NG, int NB, int NS, int T, typename ST, int STRIDE, int NBW>
+__device__ __forceinline__ void contract_group_gm(const CT *gQ, const double *lc, const double *A, ST *sV, int lane,
+                                                  int col0, int nb0)
+{
+    using MF = Mfma<CT>;
+    constexpr int MS = NQP / 4;
+    const int c16 = lane & 15;
+    typename MF::acc_t acc[NBW];
+#pragma unroll
+    for (int nb = 0; nb < NBW; ++nb) acc[nb] = typename MF::acc_t{0, 0, 0, 0};
+#pragma unroll 1
+    for (int g = 0; g < NG; ++g) {
+        double ag = A[0];
+#pragma unroll
+        for (int h = 1; h < NG; ++h) ag = g == h ? A[h] : ag;
+#pragma unroll
+        for (int m = 0; m < MS; ++m) {
+            const CT x = CT(lc[m] * ag);
+            const int ks = g * MS + m;
+#pragma unroll
+            for (int nb = 0; nb < NBW; ++nb)
+                if (nb0 + nb < NB) acc[nb] = MF::step(x, gQ[(ks * NB + nb0 + nb) * 64 + lane], acc[nb]);
+        }
+    }
+#pragma unroll
+    for (int nb = 0; nb < NBW; ++nb) {
+        const int s = 16 * (nb0 + nb) + c16;
+        if (s < NS)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sV[STRIDE * (s * (T + 1) + col0 + MF::row(lane, r))] = ST(acc[nb][r]);
     }
 }
 
 // Contraction of one 16-element group with split 16-bit operands
 // (16x16x32 MFMA). Q^T fragments: [component][ks][nb][lane] x 8 values.
 // xv(ks, t) is this lane's entry X[k = 32 ks + 8 (lane / 16) + t] (compile-time ks, t).
-template <int PF, int K, int NB, int NS, int T, typename ST, class XV>
+template <int PF, int K, int NB, int NS, int T, typename ST, int STRIDE, class XV>
 __device__ __forceinline__ void contract_group_split(const uint4 *sQ, XV &&xvf, ST *sV, int lane, int col0,
                                                      double qinv)
 {
@@ -358,7 +421,7 @@ __device__ __forceinline__ void contract_group_split(const uint4 *sQ, XV &&xvf, 
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
             const int s = 16 * nb + c16;
-            if (s < NS) sV[s * (T + 1) + col0 + 4 * j + r] = ST(double(acc[nb][r]) * ir);
+            if (s < NS) sV[STRIDE * (s * (T + 1) + col0 + 4 * j + r)] = ST(double(acc[nb][r]) * ir);
         }
     }
 }
@@ -471,59 +534,72 @@ struct FormTraits<QXA_FP64> {
 // loads and stores (idle lanes read a valid record and write the sink), so
 // each wait covers only the records it needs, never the stores behind them.
 constexpr int kWsProducers = 256;
-constexpr int kWsConsumers = 512;
-constexpr int kWsThreads = kWsProducers + kWsConsumers;
 constexpr int kChunk = 8;
+// consumer threads: 8 waves, or 4 for the T = 16 shape, whose producers need
+// the larger register budget of 8 waves per workgroup
+constexpr int ws_consumers(int T) { return T == 16 ? 256 : 512; }
+constexpr int ws_threads(int T) { return kWsProducers + ws_consumers(T); }
 
 // LDS of the kernel: staged V (two buffers, both matrices), Q^T fragments,
 // basis values and weights of both rules (q-major).
+// With T = 16 (wide shapes: 3D P3) the four producer waves share one
+// element group and split its row blocks, and Q^T (too large for LDS) is read
+// from global memory, where it stays cached.
 template <int D, int P, int NQM, int NQC, int PF, int T>
 struct WsLds {
     using ST = typename FormTraits<PF>::stage_t;
+    static constexpr bool QLDS = T != 16;
     static constexpr int NP = Shape<D, P>::NP, NS = Shape<D, P>::NS;
     static constexpr size_t v_bytes = ((4 * sizeof(ST) * NS * (T + 1) + 15) / 16) * 16;
     static constexpr size_t tab_doubles = size_t(NQM + NQC) * NP + NQM + NQC;
-    static size_t bytes(int64_t qfrag_vec16) { return v_bytes + size_t(qfrag_vec16) * 16 + tab_doubles * 8; }
+    static size_t bytes(int64_t qfrag_vec16)
+    {
+        return v_bytes + (QLDS ? size_t(qfrag_vec16) * 16 : 0) + tab_doubles * 8;
+    }
 };
 
 template <int D, int P, int NQM, int NQC, int PF, int T, bool MULTI>
-__global__ __launch_bounds__(kWsThreads) void fused_ws_kernel(JobTable jt)
+__global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
 {
-    static_assert(T == 16 * (kWsProducers / 64), "one 16-element group per producer wave");
+    static_assert(T == 16 * (kWsProducers / 64) || T == 16, "one 16-element group per producer wave, or one shared");
     using S = Shape<D, P>;
     using ST = typename FormTraits<PF>::stage_t;
     using L = LaneQ<PF, NQM, NQC>;
     using LDS = WsLds<D, P, NQM, NQC, PF, T>;
     constexpr bool SPLIT = PF >= QXA_F16X2;
+    constexpr bool QLDS = LDS::QLDS;  // else: T = 16, waves split the row blocks, Q^T from global memory
+    static_assert(QLDS || !SPLIT, "split forms need Q^T in LDS");
     constexpr int NB = (S::NS + 15) / 16;
+    constexpr int NBW = QLDS ? NB : (NB + 3) / 4;  // row blocks per producer wave
     constexpr int KM = NQM, KC = L::NQP * S::NG;  // conductivity K order: k = g * NQP + q
-    constexpr int MAT = S::NS * (T + 1);         // one staged matrix [NS][T + 1]
-    constexpr int BUF = 2 * MAT;                 // one buffer: V_m then V_c
-    constexpr int NCT = kWsConsumers;
+    constexpr int BUF = 2 * S::NS * (T + 1);     // one buffer: [NS][T + 1] pairs (V_m, V_c)
+    constexpr int NCT = ws_consumers(T);
+    constexpr int NTH = ws_threads(T);
     extern __shared__ __align__(16) unsigned char smem[];
-    ST *sV = reinterpret_cast<ST *>(smem);  // [2 buffers][2 matrices][NS][T + 1]
+    ST *sV = reinterpret_cast<ST *>(smem);  // [2 buffers][NS][T + 1][V_m, V_c]
     unsigned char *sQraw = smem + LDS::v_bytes;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const FusedArgs a0 = args_of<MULTI>(jt, 0);  // tables are shared by every job of the launch
-    double *sPhiM = reinterpret_cast<double *>(sQraw + size_t(a0.qfrag_vec16) * 16);
+    double *sPhiM = reinterpret_cast<double *>(sQraw + (QLDS ? size_t(a0.qfrag_vec16) * 16 : 0));
     double *sPhiC = sPhiM + NQM * S::NP, *sWM = sPhiC + NQC * S::NP, *sWC = sWM + NQM;
     {
         const uint4 *gq = reinterpret_cast<const uint4 *>(a0.Qfrag);
         uint4 *dq = reinterpret_cast<uint4 *>(sQraw);
-        for (int64_t k = tid; k < a0.qfrag_vec16; k += kWsThreads) dq[k] = gq[k];
-        for (int k = tid; k < NQM * S::NP; k += kWsThreads) {
+        if (QLDS)
+            for (int64_t k = tid; k < a0.qfrag_vec16; k += NTH) dq[k] = gq[k];
+        for (int k = tid; k < NQM * S::NP; k += NTH) {
             const int q = k / S::NP, i = k % S::NP;
             sPhiM[k] = a0.in.phi_m[i * NQM + q];
         }
-        for (int k = tid; k < NQC * S::NP; k += kWsThreads) {
+        for (int k = tid; k < NQC * S::NP; k += NTH) {
             const int q = k / S::NP, i = k % S::NP;
             sPhiC[k] = a0.in.phi_c[i * NQC + q];
         }
-        for (int k = tid; k < NQM; k += kWsThreads) sWM[k] = a0.in.w_m[k];
-        for (int k = tid; k < NQC; k += kWsThreads) sWC[k] = a0.in.w_c[k];
+        for (int k = tid; k < NQM; k += NTH) sWM[k] = a0.in.w_m[k];
+        for (int k = tid; k < NQC; k += NTH) sWC[k] = a0.in.w_c[k];
     }
-    // a zero in the (never written) padding column of row 0 of each staged matrix
-    if (tid < 4) sV[(tid >> 1) * BUF + (tid & 1) * MAT + T] = ST(0);
+    // a zero pair in the (never written) padding column of row 0 of each buffer
+    if (tid < 4) sV[(tid >> 1) * BUF + 2 * T + (tid & 1)] = ST(0);
     const TileWalk walk(jt.n_tiles);
     lds_barrier();
     if (tid < kWsProducers) {
@@ -535,7 +611,7 @@ __global__ __launch_bounds__(kWsThreads) void fused_ws_kernel(JobTable jt)
             const FusedArgs b = args_of<MULTI>(jt, job_of<MULTI>(jt, g, lt));
             // lanes past the last element read the last element (unconditional loads keep
             // the loads of one call in flight together)
-            const int64_t pp = min(lt * T + 16 * wave + c16, b.in.n_elem - 1);
+            const int64_t pp = min(lt * T + (QLDS ? 16 * wave : 0) + c16, b.in.n_elem - 1);
 #pragma unroll
             for (int i = 0; i < S::NP; ++i) v[i] = b.tconn[i * b.in.n_elem + pp];
         };
@@ -552,7 +628,7 @@ __global__ __launch_bounds__(kWsThreads) void fused_ws_kernel(JobTable jt)
             int64_t tile;
             const FusedArgs a = args_of<MULTI>(jt, job_of<MULTI>(jt, g, tile));
             const int64_t ne = a.in.n_elem;
-            const int64_t p = tile * T + 16 * wave + c16;  // this lane's element (4 lanes per element)
+            const int64_t p = tile * T + (QLDS ? 16 * wave : 0) + c16;  // this lane's element (4 lanes each)
             double A[S::NG], lm[L::MM], lc[L::MC];
             if (p < ne) {
                 const int64_t eid = (a.in.cm.kind == 2 || a.in.cc.kind == 2) ? int64_t(a.elem_order[p]) : p;
@@ -568,21 +644,26 @@ __global__ __launch_bounds__(kWsThreads) void fused_ws_kernel(JobTable jt)
                 for (int m = 0; m < L::MC; ++m) lc[m] = 0.0;
             }
             const int64_t gn = g + walk.step;
-            if (walk.valid(gn)) {
+            if (QLDS && walk.valid(gn)) {
                 gather(gn);  // its connectivity was loaded one tile ago
                 if (walk.valid(gn + walk.step)) load_conn(gn + walk.step);
             }
-            ST *bVm = sV + (it & 1) * BUF, *bVc = bVm + MAT;
+            ST *bVm = sV + (it & 1) * BUF, *bVc = bVm + 1;
             // V_m^T = X_m^T Q_m^T with X_m = Lambda_m; V_c^T = X_c^T Q_c^T with X_c = Lambda_c (.) W
             if constexpr (!SPLIT) {
                 using CT = typename FormTraits<PF>::qplain_t;
-                const CT *q = reinterpret_cast<const CT *>(sQraw);
+                const CT *q = reinterpret_cast<const CT *>(QLDS ? static_cast<const void *>(sQraw) : a.Qfrag);
                 // k = 4 ks + j: mass node q = k, conductivity (g, q) = divmod(4 ks, NQP) + (0, j)
                 auto xm = [&](int ks) { return lm[ks]; };
                 auto xc = [&](int ks) { return lc[((4 * ks) % L::NQP) / 4] * A[(4 * ks) / L::NQP]; };
-                contract_group_plain<CT, KM, NB, S::NS, T, ST>(q, xm, bVm, lane, 16 * wave);
-                contract_group_plain<CT, KC, NB, S::NS, T, ST>(q + ((KM + 3) / 4) * NB * 64, xc, bVc, lane,
-                                                              16 * wave);
+                const int col0 = QLDS ? 16 * wave : 0, nb0 = QLDS ? 0 : NBW * wave;
+                contract_group_plain<CT, KM, NB, S::NS, T, ST, 2, NBW>(q, xm, bVm, lane, col0, nb0);
+                if constexpr (QLDS)
+                    contract_group_plain<CT, KC, NB, S::NS, T, ST, 2, NBW>(q + ((KM + 3) / 4) * NB * 64, xc, bVc,
+                                                                          lane, col0, nb0);
+                else
+                    contract_group_gm<CT, L::NQP, S::NG, NB, S::NS, T, ST, 2, NBW>(q + ((KM + 3) / 4) * NB * 64, lc,
+                                                                                  A, bVc, lane, col0, nb0);
             } else {
                 const uint4 *q = reinterpret_cast<const uint4 *>(sQraw);
                 constexpr int NC = Split<PF>::NC;
@@ -596,9 +677,13 @@ __global__ __launch_bounds__(kWsThreads) void fused_ws_kernel(JobTable jt)
                     for (int h = 0; h < S::NG; ++h) ag = gg == h ? A[h] : ag;
                     return lc[t] * ag;
                 };
-                contract_group_split<PF, KM, NB, S::NS, T, ST>(q, xm, bVm, lane, 16 * wave, a.qinv_m);
-                contract_group_split<PF, KC, NB, S::NS, T, ST>(q + NC * ((KM + 31) / 32) * NB * 64, xc, bVc, lane,
-                                                              16 * wave, a.qinv_c);
+                contract_group_split<PF, KM, NB, S::NS, T, ST, 2>(q, xm, bVm, lane, 16 * wave, a.qinv_m);
+                contract_group_split<PF, KC, NB, S::NS, T, ST, 2>(q + NC * ((KM + 31) / 32) * NB * 64, xc, bVc,
+                                                                 lane, 16 * wave, a.qinv_c);
+            }
+            if (!QLDS && walk.valid(gn)) {  // registers are short here: gather after the contraction
+                gather(gn);
+                if (walk.valid(gn + walk.step)) load_conn(gn + walk.step);
             }
             lds_barrier();  // tile i staged; the consumers are done with buffer (i + 1) % 2
         }
@@ -636,7 +721,7 @@ __global__ __launch_bounds__(kWsThreads) void fused_ws_kernel(JobTable jt)
                 r0n = an.rec_ptr[tn];
                 r1n = an.rec_ptr[tn + 1];
             }
-            const ST *bVm = sV + ((it - 1) & 1) * BUF, *bVc = bVm + MAT;
+            const ST *bV = sV + ((it - 1) & 1) * BUF;
             double *sink_m = a.sink + ct, *sink_c = a.sink + NCT + ct;
             for (int64_t c = 0; c < nch; ++c) {
                 // next chunk: the following one of this tile, else the next tile's first
@@ -645,13 +730,15 @@ __global__ __launch_bounds__(kWsThreads) void fused_ws_kernel(JobTable jt)
 #pragma unroll
                 for (int q = 0; q < kChunk; ++q) {
                     const int64_t k = r0 + (c * kChunk + q) * NCT + ct;
-                    double am, ac;
-                    record_sums(R[q], bVm, bVc, uint32_t(T), am, ac);
-                    const int32_t t = int32_t(R[q].x);
-                    const int64_t pi = -int64_t(t) - 1;
-                    double *dm = t >= 0 ? (a.M ? a.M + t : sink_m) : a.Mpart + pi;
-                    double *dc = t >= 0 ? (a.C ? a.C + t : sink_c) : a.Cpart + pi;
                     const bool active = k < r1;
+                    // idle rounds read only the zero pair (a broadcast)
+                    const uint4 rq = active ? R[q] : make_uint4(0u, 0xffffffffu, 0xffffffffu, 0xffffffffu);
+                    double am, ac;
+                    record_sums_pair(rq, bV, uint32_t(T), am, ac);
+                    const int32_t t = int32_t(rq.x);
+                    const int64_t pi = -int64_t(t) - 1;
+                    double *dm = t >= 0 ? (a.M ? a.M + t : sink_m) : a.part + 2 * pi;
+                    double *dc = t >= 0 ? (a.C ? a.C + t : sink_c) : a.part + 2 * pi + 1;
                     *(active ? dm : sink_m) = am;
                     *(active ? dc : sink_c) = ac;
                 }
@@ -664,8 +751,8 @@ __global__ __launch_bounds__(kWsThreads) void fused_ws_kernel(JobTable jt)
     }
 }
 
-// Shared slots: each output (upper or mirror entry, ascending CSR order) sums
-// its slot's partials, which are stored contiguously in ascending tile order.
+// Shared slots: one thread per shared upper slot sums its partials (stored
+// contiguously, ascending tile order) and writes the slot and its mirror.
 __global__ __launch_bounds__(256) void fixup_kernel(FixupTable ft)
 {
     int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -682,25 +769,33 @@ __global__ __launch_bounds__(256) void fixup_kernel(FixupTable ft)
         jb = lo;
     }
     const FixupArgs a = jb < 0 ? ft.one : ft.jobs[jb];
-    const int32_t k = a.fix_src[f];
-    const int64_t lo = a.part_ptr[k], hi = a.part_ptr[k + 1];
-    const int32_t t = a.fix_target[f];
-    double m = a.Mpart[lo], c = a.Cpart[lo];
+    const int64_t lo = a.part_ptr[f], hi = a.part_ptr[f + 1];
+    const int32_t t = a.fix_target[f], tm = a.fix_mirror[f];
+    const double2 *pp = reinterpret_cast<const double2 *>(a.part);
+    const double2 first = pp[lo];
+    double m = first.x, c = first.y;
     for (int64_t q = lo + 1; q < hi; ++q) {
-        m += a.Mpart[q];
-        c += a.Cpart[q];
+        const double2 v = pp[q];
+        m += v.x;
+        c += v.y;
     }
-    if (a.M) a.M[t] = m;
-    if (a.C) a.C[t] = c;
+    if (a.M) {
+        a.M[t] = m;
+        a.M[tm] = m;
+    }
+    if (a.C) {
+        a.C[t] = c;
+        a.C[tm] = c;
+    }
 }
 
 template <int D, int P>
 constexpr bool use_mfma()
 {
-    return P >= 2 && !(D == 3 && P == 3);
+    return P >= 2;
 }
 
-bool fused_uses_mfma(int D, int P) { return P >= 2 && !(D == 3 && P == 3); }
+bool fused_uses_mfma(int D, int P) { return P >= 2; }
 
 // Resident workgroups for a persistent launch: CUs x workgroups per CU.
 template <class K>
@@ -724,7 +819,7 @@ hipError_t launch_fused(const JobTable &jt, int D, int P, int nqm, int nqc, int 
         constexpr int T = tile_size(d, p);                                                                \
         const size_t lds = WsLds<d, p, m, c, PF, T>::bytes(a.qfrag_vec16);                              \
         auto k = fused_ws_kernel<d, p, m, c, PF, T, MULTI>;                                               \
-        k<<<persistent_grid(k, kWsThreads, lds, n_tiles), kWsThreads, lds, st>>>(jt);                     \
+        k<<<persistent_grid(k, ws_threads(T), lds, n_tiles), ws_threads(T), lds, st>>>(jt);               \
     }
 #define X(d, p, m, c)                                                                                      \
     if (D == d && P == p && nqm == m && nqc == c) {                                                        \
@@ -737,9 +832,18 @@ hipError_t launch_fused(const JobTable &jt, int D, int P, int nqm, int nqc, int 
             case 2 * QXA_FP64 + 1: QXA_LAUNCH_MFMA(d, p, m, c, QXA_FP64, true) break;                      \
             case 2 * QXA_FP32: QXA_LAUNCH_MFMA(d, p, m, c, QXA_FP32, false) break;                         \
             case 2 * QXA_FP32 + 1: QXA_LAUNCH_MFMA(d, p, m, c, QXA_FP32, true) break;                      \
-            case 2 * QXA_F16X2: QXA_LAUNCH_MFMA(d, p, m, c, QXA_F16X2, false) break;                       \
-            case 2 * QXA_BF16X2: QXA_LAUNCH_MFMA(d, p, m, c, QXA_BF16X2, false) break;                     \
-            case 2 * QXA_BF16X3: QXA_LAUNCH_MFMA(d, p, m, c, QXA_BF16X3, false) break;                     \
+            case 2 * QXA_F16X2:                                                                                \
+                if constexpr (split_ok(d, p, m, c)) QXA_LAUNCH_MFMA(d, p, m, c, QXA_F16X2, false)              \
+                else return hipErrorInvalidValue;                                                              \
+                break;                                                                                         \
+            case 2 * QXA_BF16X2:                                                                               \
+                if constexpr (split_ok(d, p, m, c)) QXA_LAUNCH_MFMA(d, p, m, c, QXA_BF16X2, false)             \
+                else return hipErrorInvalidValue;                                                              \
+                break;                                                                                         \
+            case 2 * QXA_BF16X3:                                                                               \
+                if constexpr (split_ok(d, p, m, c)) QXA_LAUNCH_MFMA(d, p, m, c, QXA_BF16X3, false)             \
+                else return hipErrorInvalidValue;                                                              \
+                break;                                                                                         \
             default: return hipErrorInvalidValue;                                                          \
             }                                                                                              \
         } else {                                                                                           \

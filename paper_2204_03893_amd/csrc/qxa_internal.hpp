@@ -86,10 +86,9 @@ struct TilePlan {
     // Partials of shared upper slot k (CSR order) are part_ptr[k] ..
     // part_ptr[k+1] - 1, in ascending tile order, then record order.
     std::vector<int64_t> part_ptr;    // [n_shared + 1]
-    // fix-up outputs (upper and mirror entries of shared slots) in ascending
-    // CSR slot order, each with the shared slot whose partials it sums
-    std::vector<int32_t> fix_target;  // [n_fix]
-    std::vector<int32_t> fix_src;     // [n_fix]
+    // fix-up: shared upper slot k (ascending CSR order) and its mirror slot
+    std::vector<int32_t> fix_target;  // [n_shared]
+    std::vector<int32_t> fix_mirror;  // [n_shared]
     int64_t n_shared = 0;
     int64_t n_partials = 0;
 };
@@ -158,6 +157,7 @@ struct qxa_mesh_s {
 
 struct qxa_plan_s {
     qxa_mesh mesh = nullptr;
+    int device = 0;                  // destroy never reads the mesh (it may be gone)
     qxa::DevArena *arena = nullptr;  // device buffers come from here when set
     qxa::RefTables ref;
     int64_t nnz = 0;
@@ -170,7 +170,7 @@ struct qxa_plan_s {
     uint32_t *d_rec = nullptr;
     int64_t *d_rec_ptr = nullptr;
     int64_t *d_part_ptr = nullptr;
-    int32_t *d_fix_target = nullptr, *d_fix_src = nullptr;
+    int32_t *d_fix_target = nullptr, *d_fix_mirror = nullptr;
     int64_t n_fix = 0;
     double *d_sink = nullptr;     // write target of idle lanes (kSinkDoubles)
     double *d_part = nullptr;     // [2][n_partials]

@@ -205,19 +205,12 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
     parallel_for(nt, [&](int64_t a, int64_t b) {
         for (int64_t t = a; t < b; ++t) std::copy(trec[t].begin(), trec[t].end(), tp.rec.begin() + 4 * tp.rec_ptr[t]);
     });
-    // fix-up outputs: every shared upper slot and its mirror, in CSR order
-    std::vector<std::pair<uint32_t, int32_t>> fout;  // (target slot, shared id)
-    for (size_t f = 0; f < sh_slot.size(); ++f) {
-        const uint32_t u = sh_slot[f];
-        fout.push_back({u, int32_t(f)});
-        if (hp.mirror[u] != u) fout.push_back({hp.mirror[u], int32_t(f)});
-    }
-    std::sort(fout.begin(), fout.end());
-    tp.fix_target.resize(fout.size());
-    tp.fix_src.resize(fout.size());
-    for (size_t f = 0; f < fout.size(); ++f) {
-        tp.fix_target[f] = int32_t(fout[f].first);
-        tp.fix_src[f] = fout[f].second;
+    // fix-up: every shared upper slot (CSR order) and its mirror
+    tp.fix_target.resize(sh_slot.size());
+    tp.fix_mirror.resize(sh_slot.size());
+    for (size_t k = 0; k < sh_slot.size(); ++k) {
+        tp.fix_target[k] = int32_t(sh_slot[k]);
+        tp.fix_mirror[k] = int32_t(hp.mirror[sh_slot[k]]);
     }
     return QXA_OK;
 }
@@ -270,20 +263,18 @@ qxa_status check_tile_plan(int np, int64_t n_elem, const HostPlan &hp, const Til
     }
     for (int64_t k = 0; k < tp.n_shared; ++k)
         if (tp.part_ptr[k + 1] - tp.part_ptr[k] < 2) return fail(QXA_E_INVALID, "tile plan: shared slot with < 2 partials");
-    const int64_t nfix = int64_t(tp.fix_target.size());
-    if (int64_t(tp.fix_src.size()) != nfix) return fail(QXA_E_INVALID, "tile plan: bad fix-up sizes");
-    std::vector<uint8_t> src_seen(tp.n_shared, 0);
-    for (int64_t f = 0; f < nfix; ++f) {
-        const int32_t k = tp.fix_src[f];
-        if (k < 0 || k >= tp.n_shared) return fail(QXA_E_INVALID, "tile plan: bad shared slot index");
-        src_seen[k] = 1;
-        if (f > 0 && tp.fix_target[f] <= tp.fix_target[f - 1]) return fail(QXA_E_INVALID, "tile plan: fix-up not sorted");
-        if (!write_slot(tp.fix_target[f])) return fail(QXA_E_INVALID, "tile plan: fix-up slot written twice");
+    if (int64_t(tp.fix_target.size()) != tp.n_shared || int64_t(tp.fix_mirror.size()) != tp.n_shared)
+        return fail(QXA_E_INVALID, "tile plan: bad fix-up sizes");
+    for (int64_t k = 0; k < tp.n_shared; ++k) {
+        const int32_t u = tp.fix_target[k], m = tp.fix_mirror[k];
+        if (k > 0 && u <= tp.fix_target[k - 1]) return fail(QXA_E_INVALID, "tile plan: fix-up not sorted");
+        if (u < 0 || u >= hp.nnz || m < 0 || m >= hp.nnz || hp.mirror[u] != uint32_t(m))
+            return fail(QXA_E_INVALID, "tile plan: bad fix-up slot");
+        if (!write_slot(u)) return fail(QXA_E_INVALID, "tile plan: fix-up slot written twice");
+        if (m != u && !write_slot(m)) return fail(QXA_E_INVALID, "tile plan: fix-up mirror written twice");
     }
     for (int64_t k = 0; k < tp.n_partials; ++k)
         if (part_w[k] != 1) return fail(QXA_E_INVALID, "tile plan: partial not written exactly once");
-    for (int64_t k = 0; k < tp.n_shared; ++k)
-        if (!src_seen[k]) return fail(QXA_E_INVALID, "tile plan: shared slot never summed");
     for (int64_t t = 0; t < hp.nnz; ++t)
         if (slot_w[t] != 1) return fail(QXA_E_INVALID, "tile plan: CSR slot not written exactly once");
     return QXA_OK;

@@ -46,6 +46,41 @@ def _run(w, precision="fp64", reps=1, stream_id=0):
 SMALL = [("p1_2d_64", None), ("p2_3d_32", 6), ("p3_2d_1024", 24), ("p1_3d_96_heat", 10)]
 
 
+# every (dim, order) shape of the fused kernels, degree-2P rule for both
+# matrices, variable coefficients; meshes spanning several tiles plus a ragged tail
+SHAPES = [(2, 1, 23), (2, 2, 13), (2, 3, 9), (3, 1, 7), (3, 2, 5), (3, 3, 3)]
+
+
+@pytest.mark.parametrize("dim,order,N", SHAPES)
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fused_all_shapes_against_oracle(dim, order, N, precision):
+    qxa = _qxa()
+    from workloads.fields import gaussian_random_field
+    _say("case", dim, order, N, precision)
+    mesh = structured_mesh(dim, order, N, 0.2, seed=[7, dim, order])
+    u = gaussian_random_field(mesh["coords"], 16, np.random.default_rng([8, dim, order]), length=0.3)
+    r = rule(dim, 2 * order)
+    law_m, law_c = ("poly2", 1.0, 0.1, 0.0), ("exp", 0.0, 1.0)
+    m = qxa.Mesh(dim, order, mesh["coords"], mesh["conn"])
+    plan = qxa.Plan(m, r)
+    uf = torch.tensor(u, device="cuda")
+    M, Cv = qxa.assemble(plan, law_m, law_c, uf, uf, precision=precision)
+    M2, C2 = qxa.assemble(plan, law_m, law_c, uf, uf, precision=precision)
+    qxa.sync(plan)
+    rp, ci = plan.pattern()
+    rpo, cio, Mo, Co = oracle.assemble(mesh, r, r, law_m, law_c, u, u)
+    assert np.array_equal(rp.cpu().numpy(), rpo) and np.array_equal(ci.cpu().numpy(), cio)
+    tol = 1e-12 if precision == "fp64" else 5e-6
+    assert row_scaled_error(M.cpu().numpy(), Mo, rpo) <= tol
+    assert row_scaled_error(Cv.cpu().numpy(), Co, rpo) <= tol
+    assert torch.equal(M.view(torch.int64), M2.view(torch.int64))   # run-to-run bitwise
+    assert torch.equal(Cv.view(torch.int64), C2.view(torch.int64))
+    t = transpose_slots(rpo, cio)
+    Mh, Ch = M.cpu().numpy(), Cv.cpu().numpy()
+    assert np.array_equal(Mh, Mh[t]) and np.array_equal(Ch, Ch[t])  # bitwise symmetric
+    assert plan.n_tiles > 1
+
+
 @pytest.mark.parametrize("name,N", SMALL)
 def test_fp64_parity_against_oracle(name, N):
     w = WORKLOADS[name] if N is None else scaled(name, N)
