@@ -49,6 +49,32 @@ def floor_bytes(w, plan, mesh):
     return 4 * npl * ne + 8 * d * n_vert + 8 * nn + 4 * ne * npl * npl + 16 * nnz
 
 
+KERNEL_SOURCES = ("paper_2204_03893_amd/csrc/kernels_fused.hip", "paper_2204_03893_amd/csrc/kernels_common.hpp",
+                  "paper_2204_03893_amd/csrc/kernels.hpp")
+
+
+def measured_traffic(kernel, workload, precision):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    with the kernel sources as they are now (else None)."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    digest = h.hexdigest()[:16]
+    path = os.path.join(ROOT, "profiles", f"fused_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    pat = re.compile(r"traffic (\S+) (\S+) (\S+): bytes=(\d+) sources=([0-9a-f]+)")
+    for line in open(path):
+        m = pat.search(line)
+        if m and m.group(2) == workload and m.group(3) == precision and m.group(5) == digest and \
+                kernel == "fused" and m.group(1).startswith("fused"):
+            return int(m.group(4))
+    return None
+
+
 def cpu_baseline(w, mesh, rule, u, budget_s=20.0):
     import oracle
     threads = min(os.cpu_count() or 1, 16)
@@ -282,9 +308,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "description": w.description, "n_elem": plan.n_elem,
                    "n_nodes": plan.n_nodes, "nnz": plan.nnz, "entries_per_step": entries,
-                   "precision": args.precision},
+                   "precision": args.precision, "n_tiles": plan.n_tiles, "n_shared": plan.n_shared,
+                   "n_partials": plan.n_partials},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(dom, w.name, args.precision), "kernel": dom,
                      "algorithmic_bytes": ab, "kernel_ms": kern[dom]},
         "path_floor": {"bytes": fb, "frac_of_hbm_peak": fb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "kernels_ms": kern,

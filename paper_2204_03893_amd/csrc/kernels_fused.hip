@@ -20,15 +20,12 @@
 namespace qxa {
 
 // Sums of one record's contributions (padded LDS indices, plan order) to both
-// staged matrices. Absent contributions (0xFFFF) read the zero kept at index
-// `zero`, so the six reads are unconditional (adding +0.0 changes no sum).
+// staged matrices. Absent contributions index the zero kept at (pair 0,
+// column T), so the six reads are unconditional (adding +0.0 changes no sum).
 template <typename ST>
-__device__ __forceinline__ void record_sums(const uint4 R, const ST *sVm, const ST *sVc, uint32_t zero, double &am,
-                                            double &ac)
+__device__ __forceinline__ void record_sums(const uint4 R, const ST *sVm, const ST *sVc, double &am, double &ac)
 {
-    uint32_t c[6] = {R.y & 0xffffu, R.y >> 16, R.z & 0xffffu, R.z >> 16, R.w & 0xffffu, R.w >> 16};
-#pragma unroll
-    for (int q = 1; q < 6; ++q) c[q] = c[q] == 0xffffu ? zero : c[q];
+    const uint32_t c[6] = {R.y & 0xffffu, R.y >> 16, R.z & 0xffffu, R.z >> 16, R.w & 0xffffu, R.w >> 16};
     double vm[6], vc[6];
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
@@ -47,13 +44,11 @@ __device__ __forceinline__ void record_sums(const uint4 R, const ST *sVm, const 
 // The same for V_m and V_c staged interleaved, pair (V_m, V_c) of entry c at
 // sV[2 c], sV[2 c + 1]: one LDS read per contribution.
 template <typename ST>
-__device__ __forceinline__ void record_sums_pair(const uint4 R, const ST *sV, uint32_t zero, double &am, double &ac)
+__device__ __forceinline__ void record_sums_pair(const uint4 R, const ST *sV, double &am, double &ac)
 {
     using ST2 = typename std::conditional<sizeof(ST) == 8, double2, float2>::type;
     const ST2 *v2 = reinterpret_cast<const ST2 *>(sV);
-    uint32_t c[6] = {R.y & 0xffffu, R.y >> 16, R.z & 0xffffu, R.z >> 16, R.w & 0xffffu, R.w >> 16};
-#pragma unroll
-    for (int q = 0; q < 6; ++q) c[q] = c[q] == 0xffffu ? zero : c[q];
+    const uint32_t c[6] = {R.y & 0xffffu, R.y >> 16, R.z & 0xffffu, R.z >> 16, R.w & 0xffffu, R.w >> 16};
     ST2 v[6];
 #pragma unroll
     for (int q = 0; q < 6; ++q) v[q] = v2[c[q]];
@@ -68,11 +63,10 @@ __device__ __forceinline__ void record_sums_pair(const uint4 R, const ST *sV, ui
 
 // Reduction of one record into its CSR slot (target >= 0) or partial.
 template <typename ST>
-__device__ __forceinline__ void reduce_record(const uint4 R, const ST *sVm, const ST *sVc, uint32_t zero,
-                                              const FusedArgs &a)
+__device__ __forceinline__ void reduce_record(const uint4 R, const ST *sVm, const ST *sVc, const FusedArgs &a)
 {
     double am, ac;
-    record_sums(R, sVm, sVc, zero, am, ac);
+    record_sums(R, sVm, sVc, am, ac);
     const int32_t t = int32_t(R.x);
     if (t >= 0) {
         if (a.M) a.M[t] = am;
@@ -99,12 +93,12 @@ __device__ __forceinline__ void prefetch_records(const uint4 *__restrict__ rec, 
 // batch first, then the rest in groups of kPrefetch independent loads.
 template <typename ST>
 __device__ __forceinline__ void tile_reduce(const uint4 (&pf)[kPrefetch], const FusedArgs &a, int64_t tile,
-                                            const ST *sVm, const ST *sVc, uint32_t zero, int stride)
+                                            const ST *sVm, const ST *sVc, int stride)
 {
     const int64_t r0 = a.rec_ptr[tile], r1 = a.rec_ptr[tile + 1];
 #pragma unroll
     for (int i = 0; i < kPrefetch; ++i)
-        if (r0 + threadIdx.x + int64_t(i) * stride < r1) reduce_record(pf[i], sVm, sVc, zero, a);
+        if (r0 + threadIdx.x + int64_t(i) * stride < r1) reduce_record(pf[i], sVm, sVc, a);
     for (int64_t k0 = r0 + threadIdx.x + int64_t(kPrefetch) * stride; k0 < r1; k0 += int64_t(kPrefetch) * stride) {
         uint4 R[kPrefetch];
 #pragma unroll
@@ -114,7 +108,7 @@ __device__ __forceinline__ void tile_reduce(const uint4 (&pf)[kPrefetch], const 
         }
 #pragma unroll
         for (int i = 0; i < kPrefetch; ++i)
-            if (k0 + int64_t(i) * stride < r1) reduce_record(R[i], sVm, sVc, zero, a);
+            if (k0 + int64_t(i) * stride < r1) reduce_record(R[i], sVm, sVc, a);
     }
 }
 
@@ -174,7 +168,7 @@ __global__ __launch_bounds__(T) void fused_kernel(JobTable jt)
                                              [&](int s, double x) { sVc[s * (T + 1) + lane] = x; });
     }
     lds_barrier();
-    tile_reduce(pf, a, tile, sVm, sVc, T, T);
+    tile_reduce(pf, a, tile, sVm, sVc, T);
 }
 
 // ---------------------------------------------------------------------------
@@ -727,14 +721,17 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
                 // next chunk: the following one of this tile, else the next tile's first
                 const bool inner = c + 1 < nch;
                 load_chunk(inner ? a.rec : rec_n, inner ? r0 : r0n, inner ? r1 : r1n, inner ? c + 1 : 0, Rn);
+                const uint32_t none = uint32_t(T) | (uint32_t(T) << 16);  // absent contributions
 #pragma unroll
                 for (int q = 0; q < kChunk; ++q) {
-                    const int64_t k = r0 + (c * kChunk + q) * NCT + ct;
+                    const int64_t k0 = r0 + (c * kChunk + q) * NCT;
+                    if (k0 >= r1) continue;  // the whole round is past the tile's records (uniform)
+                    const int64_t k = k0 + ct;
                     const bool active = k < r1;
-                    // idle rounds read only the zero pair (a broadcast)
-                    const uint4 rq = active ? R[q] : make_uint4(0u, 0xffffffffu, 0xffffffffu, 0xffffffffu);
+                    // idle lanes read only the zero pair (a broadcast)
+                    const uint4 rq = active ? R[q] : make_uint4(0u, none, none, none);
                     double am, ac;
-                    record_sums_pair(rq, bV, uint32_t(T), am, ac);
+                    record_sums_pair(rq, bV, am, ac);
                     const int32_t t = int32_t(rq.x);
                     const int64_t pi = -int64_t(t) - 1;
                     double *dm = t >= 0 ? (a.M ? a.M + t : sink_m) : a.part + 2 * pi;

@@ -79,7 +79,8 @@ struct TilePlan {
     // target >= 0: a CSR slot owned by the tile (upper and mirror entries are
     // separate records with the same contributions); target < 0: partial
     // -(p + 1). c0..c5: padded LDS indices (s*(T+1) + local element) of the
-    // contributions in summation order, 0xFFFF = none. Owned records come
+    // contributions in summation order; T (pair 0, padding column, where the
+    // kernels keep a zero) = none. Owned records come
     // first in ascending CSR slot order (coalesced stores), then partials.
     std::vector<uint32_t> rec;        // [4 * n_records]
     std::vector<int64_t> rec_ptr;     // [n_tiles + 1] (in records)

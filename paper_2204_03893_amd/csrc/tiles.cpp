@@ -166,7 +166,7 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
                 while (k1 < buf.size() && uint32_t(buf[k1] >> 32) == u) ++k1;
                 for (size_t c0 = k; c0 < k1; c0 += 6) {
                     std::array<uint16_t, 6> c;
-                    c.fill(0xffff);
+                    c.fill(uint16_t(T));  // absent: the zero kept at (pair 0, column T)
                     for (size_t q = c0; q < std::min(k1, c0 + 6); ++q) c[q - c0] = uint16_t(buf[q] & 0xffff);
                     if (sh_id[u] < 0) {
                         owned.push_back({u, c});
@@ -242,7 +242,7 @@ qxa_status check_tile_plan(int np, int64_t n_elem, const HostPlan &hp, const Til
             const uint32_t c[6] = {R[1] & 0xffffu, R[1] >> 16, R[2] & 0xffffu, R[2] >> 16, R[3] & 0xffffu, R[3] >> 16};
             int n = 0;
             for (int q = 0; q < 6; ++q) {
-                if (c[q] == 0xffffu) continue;
+                if (c[q] == uint32_t(T)) continue;  // absent
                 if (c[q] >= uint32_t(TP * ns) || int64_t(c[q] % TP) >= nloc)
                     return fail(QXA_E_INVALID, "tile plan: LDS index out of range");
                 used[c[q]] = 1;
