@@ -205,6 +205,65 @@ def serving(args):
     print(json.dumps(out))
 
 
+def reassembly(args, n_steps=20):
+    """Reassembly loop (only the coefficients change): the heat workload by default
+    (p1_3d_96_heat, 5,308,416 elements). Each step updates the nodal field in place
+    (u += 0.05 * smooth increment, a device add on the same stream) and replays the
+    captured assembly graph; the same loop with direct assembly calls is timed beside it.
+    Prints one JSON line."""
+    import numpy as np
+    import torch
+    import paper_2204_03893_amd as qxa
+    from workloads import WORKLOADS, heat_increment, make_inputs
+    name = args.workload if args.workload != "p2_3d_32" else "p1_3d_96_heat"
+    w = WORKLOADS[name]
+    mesh, rule, u0 = make_inputs(w)
+    m = qxa.Mesh(w.dim, w.order, mesh["coords"], mesh["conn"])
+    t0 = time.perf_counter()
+    plan = qxa.Plan(m, rule)
+    plan_s = time.perf_counter() - t0
+    dev = torch.device("cuda", 0)
+    u = torch.tensor(u0, device=dev)
+    incs = [torch.tensor(heat_increment(w, mesh, s), device=dev) for s in range(1, n_steps + 1)]
+    stream = torch.cuda.current_stream()
+    g = qxa.ReassemblyGraph(plan, w.mass_law, w.stiff_law, u, u, precision=args.precision)
+    M = torch.empty(plan.nnz, dtype=torch.float64, device=dev)
+    Cv = torch.empty_like(M)
+
+    def loop(use_graph):
+        u.copy_(torch.tensor(u0, device=dev))
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for s in range(n_steps):
+            u.add_(incs[s])
+            if use_graph:
+                g.launch(stream)
+            else:
+                qxa.assemble(plan, w.mass_law, w.stiff_law, u, u, precision=args.precision, M=M, Cv=Cv,
+                             stream=stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        qxa.sync(plan, stream)
+        return ev0.elapsed_time(ev1) / n_steps
+
+    loop(True)
+    loop(False)  # warm-up
+    ms_graph = loop(True)
+    ms_direct = loop(False)
+    same = bool(torch.equal(g.M.view(torch.int64), M.view(torch.int64)) and
+                torch.equal(g.Cv.view(torch.int64), Cv.view(torch.int64)))
+    entries = 2 * plan.n_elem * plan.n_p ** 2
+    g.close()
+    out = {"metric": "element-matrix entries assembled/sec (reassembly loop)", "value": entries / (ms_graph * 1e-3),
+           "unit": "entries/s", "n_gpus": 1, "steps": n_steps, "ms_per_step": ms_graph, "higher_is_better": True,
+           "dtype": "f64" if args.precision == "fp64" else args.precision, "data": "synthetic", "vs_baseline": None,
+           "config": {"workload": w.name, "description": w.description, "n_elem": plan.n_elem, "nnz": plan.nnz,
+                      "precision": args.precision},
+           "ms_per_step_direct": ms_direct, "graph_equals_direct_bitwise": same, "plan_build_s": plan_s}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -215,7 +274,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) to calibrate HBM byte counters")
-    ap.add_argument("--mode", choices=("assemble", "serving"), default="assemble")
+    ap.add_argument("--mode", choices=("assemble", "serving", "reassembly"), default="assemble")
     ap.add_argument("--requests", type=int, default=1000, help="serving: requests per offered load")
     ap.add_argument("--pool", type=int, default=48, help="serving: resident meshes")
     ap.add_argument("--max-elements", type=float, default=3e5, help="serving: largest mesh (elements)")
@@ -240,6 +299,9 @@ def main():
 
     if args.mode == "serving":
         serving(args)
+        return
+    if args.mode == "reassembly":
+        reassembly(args)
         return
 
     import paper_2204_03893_amd as qxa
