@@ -716,7 +716,6 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
                 r1n = an.rec_ptr[tn + 1];
             }
             const ST *bV = sV + ((it - 1) & 1) * BUF;
-            double *sink_m = a.sink + ct, *sink_c = a.sink + NCT + ct;
             for (int64_t c = 0; c < nch; ++c) {
                 // next chunk: the following one of this tile, else the next tile's first
                 const bool inner = c + 1 < nch;
@@ -728,16 +727,19 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
                     if (k0 >= r1) continue;  // the whole round is past the tile's records (uniform)
                     const int64_t k = k0 + ct;
                     const bool active = k < r1;
-                    // idle lanes read only the zero pair (a broadcast)
+                    // idle lanes read only the zero pair (a broadcast) and store nothing
                     const uint4 rq = active ? R[q] : make_uint4(0u, none, none, none);
                     double am, ac;
                     record_sums_pair(rq, bV, am, ac);
                     const int32_t t = int32_t(rq.x);
-                    const int64_t pi = -int64_t(t) - 1;
-                    double *dm = t >= 0 ? (a.M ? a.M + t : sink_m) : a.part + 2 * pi;
-                    double *dc = t >= 0 ? (a.C ? a.C + t : sink_c) : a.part + 2 * pi + 1;
-                    *(active ? dm : sink_m) = am;
-                    *(active ? dc : sink_c) = ac;
+                    if (active) {
+                        if (t >= 0) {
+                            if (a.M) a.M[t] = am;
+                            if (a.C) a.C[t] = ac;
+                        } else {  // the (mass, conductivity) pair of a partial: one 16-byte store
+                            reinterpret_cast<double2 *>(a.part)[-int64_t(t) - 1] = make_double2(am, ac);
+                        }
+                    }
                 }
 #pragma unroll
                 for (int q = 0; q < kChunk; ++q) R[q] = Rn[q];
