@@ -319,32 +319,52 @@ __device__ __forceinline__ void contract_group_plain(const CT *sQ, XK &&xk, ST *
 }
 
 // Conductivity contraction with Q^T read from global memory (shapes whose
-// Q^T does not fit in LDS). The K order k = g * NQP + q is walked as a rolled
-// loop over g with the NQP / 4 steps of one g unrolled, which bounds the
-// fragments in flight; lc[m] holds this lane's node q = 4 m + j.
+// Q^T does not fit in LDS). The K order k = g * NQP + q is walked in chunks of
+// CH k-steps (CH divides NQP / 4, so a chunk has one g) in a rolled loop; the
+// fragments of chunk c + 1 are loaded while chunk c is multiplied. lc[m] holds
+// this lane's node q = 4 m + j.
 template <typename CT, int NQP, int NG, int NB, int NS, int T, typename ST, int STRIDE, int NBW>
 __device__ __forceinline__ void contract_group_gm(const CT *gQ, const double *lc, const double *A, ST *sV, int lane,
                                                   int col0, int nb0)
 {
     using MF = Mfma<CT>;
-    constexpr int MS = NQP / 4;
+    constexpr int MS = NQP / 4;                    // k-steps per metric component g
+    constexpr int CH = MS % 3 == 0 ? 3 : MS;       // k-steps per chunk
+    constexpr int CPG = MS / CH, NCH = NG * CPG;  // chunks per g, chunks
     const int c16 = lane & 15;
     typename MF::acc_t acc[NBW];
 #pragma unroll
     for (int nb = 0; nb < NBW; ++nb) acc[nb] = typename MF::acc_t{0, 0, 0, 0};
+    CT cur[CH][NBW], nxt[CH][NBW];
+    auto load = [&](int c, CT (&f)[CH][NBW]) {
+#pragma unroll
+        for (int t = 0; t < CH; ++t)
+#pragma unroll
+            for (int nb = 0; nb < NBW; ++nb)
+                f[t][nb] = nb0 + nb < NB ? gQ[((c * CH + t) * NB + nb0 + nb) * 64 + lane] : CT(0);
+    };
+    load(0, cur);
 #pragma unroll 1
-    for (int g = 0; g < NG; ++g) {
+    for (int c = 0; c < NCH; ++c) {
+        if (c + 1 < NCH) load(c + 1, nxt);
+        const int g = c / CPG, part = c % CPG;
         double ag = A[0];
 #pragma unroll
         for (int h = 1; h < NG; ++h) ag = g == h ? A[h] : ag;
 #pragma unroll
-        for (int m = 0; m < MS; ++m) {
-            const CT x = CT(lc[m] * ag);
-            const int ks = g * MS + m;
+        for (int t = 0; t < CH; ++t) {
+            double lv = lc[t];
+#pragma unroll
+            for (int h = 1; h < CPG; ++h) lv = part == h ? lc[h * CH + t] : lv;
+            const CT x = CT(lv * ag);
 #pragma unroll
             for (int nb = 0; nb < NBW; ++nb)
-                if (nb0 + nb < NB) acc[nb] = MF::step(x, gQ[(ks * NB + nb0 + nb) * 64 + lane], acc[nb]);
+                if (nb0 + nb < NB) acc[nb] = MF::step(x, cur[t][nb], acc[nb]);
         }
+#pragma unroll
+        for (int t = 0; t < CH; ++t)
+#pragma unroll
+            for (int nb = 0; nb < NBW; ++nb) cur[t][nb] = nxt[t][nb];
     }
 #pragma unroll
     for (int nb = 0; nb < NBW; ++nb) {
