@@ -125,12 +125,16 @@ static float f16_value(uint16_t b)
 //   split forms (16x16x32): [component][ks][nb][lane][8], lane l holds
 //     Q[s = 16 nb + l % 16][k = 32 ks + 8 (l / 16) + t], t = 0..7, as the
 //     hi / lo (/ mid) terms of its 16-bit split.
-// Mass block first (k = q), then conductivity. The conductivity columns are
-// ordered k = g * NQP + q (metric component g, node q, NQP = n_q rounded up
-// to 4 for the 16x16x4 forms and to 8 for the split forms), so the lanes that
-// hold one K slot of an element need the weighted coefficients of only a
-// subset of the quadrature nodes. Zero outside the tables.
-int qc_pad(int nq, bool split) { return split ? (nq + 7) / 8 * 8 : (nq + 3) / 4 * 4; }
+// Mass block first, then conductivity. The K order is chosen so that the four
+// lanes holding one element need the weighted coefficients of nodes
+// q = 4 m + j only (j = l / 16):
+//   16x16x4: mass k = q; conductivity k = g * NQP + q, NQP = n_q rounded up to 4;
+//   16x16x32: segment (ks, j) of 8 slots holds QPS = 8 / G groups of G slots,
+//     slot t = node q = 4 (QPS ks + t / G) + j, component t % G (G = 1 for the
+//     mass, d(d+1)/2 for the conductivity), unused slots zero.
+// Zero outside the tables.
+int qc_pad(int nq) { return (nq + 3) / 4 * 4; }
+int split_blocks(int nq, int G) { return ((nq + 3) / 4 + 8 / G - 1) / (8 / G); }
 
 static void build_qfrags(const RefTables &T, std::vector<uint8_t> (&out)[5], double (&f16_qinv)[2])
 {
@@ -146,24 +150,36 @@ static void build_qfrags(const RefTables &T, std::vector<uint8_t> (&out)[5], dou
         f16_scale[blk] = std::ldexp(1.0, 13 - e);
         f16_qinv[blk] = std::ldexp(1.0, e - 13);
     }
-    // entry (s, k) of the mass (blk 0) or reordered conductivity (blk 1) block
-    auto qval = [&](int blk, int s, int k, bool split) -> double {
+    // entry (s, q, g) of the mass (blk 0, g = 0) or conductivity (blk 1) table
+    auto qent = [&](int blk, int s, int q, int g) -> double {
         if (s >= T.ns) return 0.0;
-        if (blk == 0) return k < T.nq_m ? T.Qm[size_t(s) * T.nq_m + k] : 0.0;
-        const int nqp = qc_pad(T.nq_c, split), g = k / nqp, q = k % nqp;
-        if (g >= T.ng || q >= T.nq_c) return 0.0;
+        if (blk == 0) return q < T.nq_m && g == 0 ? T.Qm[size_t(s) * T.nq_m + q] : 0.0;
+        if (q >= T.nq_c || g >= T.ng) return 0.0;
         return T.Qc[size_t(s) * kc + size_t(q) * T.ng + g];
+    };
+    // entry (s, k) in the K order of the 16x16x4 forms
+    auto qval = [&](int blk, int s, int k) -> double {
+        if (blk == 0) return qent(0, s, k, 0);
+        const int nqp = qc_pad(T.nq_c);
+        return qent(1, s, k % nqp, k / nqp);
+    };
+    // entry (s, k) in the K order of the split forms
+    auto qval_split = [&](int blk, int s, int k) -> double {
+        const int G = blk == 0 ? 1 : T.ng, qps = 8 / G;
+        const int ks = k / 32, j = (k % 32) / 8, t = k % 8, u = t / G;
+        if (u >= qps) return 0.0;
+        return qent(blk, s, 4 * (qps * ks + u) + j, t % G);
     };
     // plain forms
     for (int f = 0; f < 2; ++f) {
         std::vector<uint8_t> &o = out[f];
         for (int blk = 0; blk < 2; ++blk) {
-            const int kb = blk == 0 ? T.nq_m : T.ng * qc_pad(T.nq_c, false);
+            const int kb = blk == 0 ? T.nq_m : T.ng * qc_pad(T.nq_c);
             const int ks_n = (kb + 3) / 4;
             for (int ks = 0; ks < ks_n; ++ks)
                 for (int nb = 0; nb < nb_; ++nb)
                     for (int l = 0; l < 64; ++l) {
-                        const double v = qval(blk, 16 * nb + l % 16, 4 * ks + l / 16, false);
+                        const double v = qval(blk, 16 * nb + l % 16, 4 * ks + l / 16);
                         if (f == 0) {
                             const uint8_t *b = reinterpret_cast<const uint8_t *>(&v);
                             o.insert(o.end(), b, b + 8);
@@ -181,14 +197,13 @@ static void build_qfrags(const RefTables &T, std::vector<uint8_t> (&out)[5], dou
         const int nc = f == 4 ? 3 : 2;
         std::vector<uint8_t> &o = out[f];
         for (int blk = 0; blk < 2; ++blk) {
-            const int kb = blk == 0 ? T.nq_m : T.ng * qc_pad(T.nq_c, true);
-            const int ks_n = (kb + 31) / 32;
+            const int ks_n = blk == 0 ? split_blocks(T.nq_m, 1) : split_blocks(T.nq_c, T.ng);
             for (int c = 0; c < nc; ++c)
                 for (int ks = 0; ks < ks_n; ++ks)
                     for (int nb = 0; nb < nb_; ++nb)
                         for (int l = 0; l < 64; ++l)
                             for (int t = 0; t < 8; ++t) {
-                                double v = qval(blk, 16 * nb + l % 16, 32 * ks + 8 * (l / 16) + t, true);
+                                double v = qval_split(blk, 16 * nb + l % 16, 32 * ks + 8 * (l / 16) + t);
                                 uint16_t comp[3];
                                 if (f == 2) {
                                     v *= f16_scale[blk];

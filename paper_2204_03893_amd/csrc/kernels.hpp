@@ -29,11 +29,10 @@ constexpr int tile_size(int D, int P)
 
 bool fused_uses_mfma(int D, int P);
 
-// Split 16-bit forms: Q^T staged in LDS (not the T = 16 shape) and at most 16
-// padded conductivity nodes and 32 mass nodes per element.
+// Split 16-bit forms: Q^T staged in LDS (not the T = 16 shape).
 constexpr bool split_ok(int D, int P, int nqm, int nqc)
 {
-    return P >= 2 && tile_size(D, P) != 16 && (nqc + 7) / 8 * 8 <= 16 && nqm <= 32;
+    return P >= 2 && tile_size(D, P) != 16 && nqm > 0 && nqc > 0;
 }
 
 struct FormArgs {

@@ -386,18 +386,15 @@ __device__ __forceinline__ void contract_group_split(const uint4 *sQ, XV &&xvf, 
     using elem_t = typename SP::elem;
     constexpr int KS = (K + 31) / 32;
     const int j = lane >> 4, c16 = lane & 15;
-    double xv[KS][8];
-    double amax = 0.0;
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            xv[ks][t] = xvf(ks, t);
-            amax = fmax(amax, fabs(xv[ks][t]));
-        }
     double scale = 1.0, inv = 1.0;
     if constexpr (SP::scaled) {
-        // element-wide max over the 4 lanes holding the element (lanes c16 + 16 j)
+        // element-wide max over the 4 lanes holding the element (lanes c16 + 16 j);
+        // the X entries are recomputed below rather than held
+        double amax = 0.0;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+            for (int t = 0; t < 8; ++t) amax = fmax(amax, fabs(xvf(ks, t)));
         amax = fmax(amax, __shfl_xor(amax, 16));
         amax = fmax(amax, __shfl_xor(amax, 32));
         if (amax > 0.0) {
@@ -406,28 +403,27 @@ __device__ __forceinline__ void contract_group_split(const uint4 *sQ, XV &&xvf, 
             inv = ldexp(1.0, e);
         }
     }
-    typename SP::vec xc[KS][SP::NC];
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            elem_t c[SP::NC];
-            SP::split(float(xv[ks][t] * scale), c);
-#pragma unroll
-            for (int q = 0; q < SP::NC; ++q) xc[ks][q][t] = c[q];
-        }
     qxa_f4 acc[NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[nb] = qxa_f4{0, 0, 0, 0};
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
+    for (int ks = 0; ks < KS; ++ks) {  // one 32-wide K block at a time: split, then multiply
+        typename SP::vec xc[SP::NC];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            elem_t c[SP::NC];
+            SP::split(float(xvf(ks, t) * scale), c);
+#pragma unroll
+            for (int q = 0; q < SP::NC; ++q) xc[q][t] = c[q];
+        }
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
             for (int tm = 0; tm < SP::NT; ++tm) {
                 const uint4 qv = sQ[((SP::pb[tm] * KS + ks) * NB + nb) * 64 + lane];
-                acc[nb] = SP::mfma(xc[ks][SP::pa[tm]], __builtin_bit_cast(typename SP::vec, qv), acc[nb]);
+                acc[nb] = SP::mfma(xc[SP::pa[tm]], __builtin_bit_cast(typename SP::vec, qv), acc[nb]);
             }
+    }
     // undo the element scale and the table scale: row r of this lane is element 4 (lane/16) + r
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -441,41 +437,42 @@ __device__ __forceinline__ void contract_group_split(const uint4 *sQ, XV &&xvf, 
 }
 
 // Quadrature nodes whose weighted coefficients a lane of an element needs on
-// the matrix cores, given the K order of the Q^T fragments (mass k = q;
-// conductivity k = g * NQP + q). Lane group j = lane / 16 holds
-//   16x16x4 forms: k = 4 ks + j         -> q = 4 m + j       (m < ceil(n_q / 4))
-//   split forms:   k = 32 ks + 8 j + t  -> mass q = 8 j + t, conductivity
-//                  q = (8 j) mod NQP + t (NQP in {8, 16}: the same q for every ks)
-template <int PF, int NQM, int NQC>
+// the matrix cores: lane group j = lane / 16 holds the nodes q = 4 m + j. The K
+// order of the Q^T fragments makes this so:
+//   16x16x4 forms (lane holds k = 4 ks + j): mass k = q; conductivity
+//     k = g * NQP + q with NQP = n_q rounded up to 4;
+//   split forms (lane holds k = 32 ks + 8 j + t, t < 8): each 8-slot segment
+//     holds QPS = 8 / G whole (node, component) groups of G slots, node
+//     q = 4 (QPS ks + t / G) + j, component t % G (G = 1 for the mass,
+//     d(d+1)/2 for the conductivity); the remaining slots are zero.
+template <int NQM, int NQC, int NG>
 struct LaneQ {
-    static constexpr bool SPLIT = PF >= QXA_F16X2;
-    static constexpr int NQP = SPLIT ? (NQC + 7) / 8 * 8 : (NQC + 3) / 4 * 4;
-    static_assert(!SPLIT || NQP == 8 || NQP == 16, "split forms need n_q <= 16");
-    static_assert(!SPLIT || NQM <= 32, "split forms need n_q(mass) <= 32");
-    static constexpr int MM = SPLIT ? 8 : (NQM + 3) / 4;  // mass nodes per lane
-    static constexpr int MC = SPLIT ? 8 : NQP / 4;        // conductivity nodes per lane
-    static __device__ __forceinline__ int qm(int j, int m) { return SPLIT ? 8 * j + m : 4 * m + j; }
-    static __device__ __forceinline__ int qc(int j, int m) { return SPLIT ? (8 * j) % NQP + m : 4 * m + j; }
+    static constexpr int NQP = (NQC + 3) / 4 * 4;
+    static constexpr int MM = (NQM + 3) / 4;  // mass nodes per lane
+    static constexpr int MC = NQP / 4;        // conductivity nodes per lane
+    static constexpr int QPSM = 8, QPSC = 8 / NG;
+    static constexpr int KSM = (MM + QPSM - 1) / QPSM, KSC = (MC + QPSC - 1) / QPSC;  // split K blocks
+    static __device__ __forceinline__ int q(int j, int m) { return 4 * m + j; }
 };
 
 // Per-lane setup on the matrix-core path: geometry (all lanes) and the
 // weighted coefficients Lambda of this lane's quadrature nodes only (zero for
 // nodes past n_q). Basis values and weights come from LDS, q-major
 // (sPhi[q * NP + i]). Returns false when a coefficient value is not finite.
-template <int D, int P, int NQM, int NQC, int PF>
+template <int D, int P, int NQM, int NQC>
 __device__ __forceinline__ bool lane_setup(const FormInputs &in, const RawElem<D, P> &r, const int32_t *tconn,
                                            int64_t pos, int64_t eid, int j, const double *sPhiM,
                                            const double *sPhiC, const double *sWM, const double *sWC, double *A,
                                            double *lm, double *lc)
 {
-    using L = LaneQ<PF, NQM, NQC>;
+    using L = LaneQ<NQM, NQC, Shape<D, P>::NG>;
     constexpr int NP = Shape<D, P>::NP;
     double babs;
     geometry_from<D>(r.x, babs, A);
     bool ok = true;
 #pragma unroll
     for (int m = 0; m < L::MM; ++m) {
-        const int q = L::qm(j, m);
+        const int q = L::q(j, m);
         double v = 0.0;
         if (q < NQM) {
             double s;
@@ -497,7 +494,7 @@ __device__ __forceinline__ bool lane_setup(const FormInputs &in, const RawElem<D
     const bool other = in.cc.kind == 1 && in.cm.kind == 1 && in.cc.field != in.cm.field;
 #pragma unroll
     for (int m = 0; m < L::MC; ++m) {
-        const int q = L::qc(j, m);
+        const int q = L::q(j, m);
         double v = 0.0;
         if (q < NQC) {
             double s;
@@ -578,7 +575,7 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
     static_assert(T == 16 * (kWsProducers / 64) || T == 16, "one 16-element group per producer wave, or one shared");
     using S = Shape<D, P>;
     using ST = typename FormTraits<PF>::stage_t;
-    using L = LaneQ<PF, NQM, NQC>;
+    using L = LaneQ<NQM, NQC, S::NG>;
     using LDS = WsLds<D, P, NQM, NQC, PF, T>;
     constexpr bool SPLIT = PF >= QXA_F16X2;
     constexpr bool QLDS = LDS::QLDS;  // else: T = 16, waves split the row blocks, Q^T from global memory
@@ -646,8 +643,7 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
             double A[S::NG], lm[L::MM], lc[L::MC];
             if (p < ne) {
                 const int64_t eid = (a.in.cm.kind == 2 || a.in.cc.kind == 2) ? int64_t(a.elem_order[p]) : p;
-                if (!lane_setup<D, P, NQM, NQC, PF>(a.in, raw, a.tconn, p, eid, j, sPhiM, sPhiC, sWM, sWC, A, lm,
-                                                    lc))
+                if (!lane_setup<D, P, NQM, NQC>(a.in, raw, a.tconn, p, eid, j, sPhiM, sPhiC, sWM, sWC, A, lm, lc))
                     atomicOr(a.in.flags, 1);
             } else {
 #pragma unroll
@@ -681,19 +677,18 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
             } else {
                 const uint4 *q = reinterpret_cast<const uint4 *>(sQraw);
                 constexpr int NC = Split<PF>::NC;
-                // k = 32 ks + 8 j + t: mass node q = k (one k-block), conductivity
-                // g = (32 ks + 8 j) / NQP and node (8 j) mod NQP + t
-                auto xm = [&](int ks, int t) { return ks == 0 ? lm[t] : 0.0; };
-                auto xc = [&](int ks, int t) {
-                    const int gg = (32 * ks + 8 * j) / L::NQP;
-                    double ag = 0.0;
-#pragma unroll
-                    for (int h = 0; h < S::NG; ++h) ag = gg == h ? A[h] : ag;
-                    return lc[t] * ag;
+                // k = 32 ks + 8 j + t holds node q = 4 m + j, m = QPS ks + t / G, component t % G
+                auto xm = [&](int ks, int t) {
+                    const int m = L::QPSM * ks + t;
+                    return m < L::MM ? lm[m] : 0.0;
                 };
-                contract_group_split<PF, KM, NB, S::NS, T, ST, 2>(q, xm, bVm, lane, 16 * wave, a.qinv_m);
-                contract_group_split<PF, KC, NB, S::NS, T, ST, 2>(q + NC * ((KM + 31) / 32) * NB * 64, xc, bVc,
-                                                                 lane, 16 * wave, a.qinv_c);
+                auto xc = [&](int ks, int t) {
+                    const int u = t / S::NG, g = t % S::NG, m = L::QPSC * ks + u;
+                    return u < L::QPSC && m < L::MC ? lc[m] * A[g] : 0.0;
+                };
+                contract_group_split<PF, 32 * L::KSM, NB, S::NS, T, ST, 2>(q, xm, bVm, lane, 16 * wave, a.qinv_m);
+                contract_group_split<PF, 32 * L::KSC, NB, S::NS, T, ST, 2>(q + NC * L::KSM * NB * 64, xc, bVc, lane,
+                                                                          16 * wave, a.qinv_c);
             }
             if (!QLDS && walk.valid(gn)) {  // registers are short here: gather after the contraction
                 gather(gn);
