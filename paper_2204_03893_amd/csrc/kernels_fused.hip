@@ -546,6 +546,10 @@ struct FormTraits<QXA_FP64> {
 // each wait covers only the records it needs, never the stores behind them.
 constexpr int kWsProducers = 256;
 constexpr int kChunk = 8;
+// record rounds per consumer chunk: all of a tile's records in one chunk, so
+// the next tile's are loaded a whole tile ahead (2D P3: up to 5,005 records
+// per 64-element tile on 512 consumer threads)
+constexpr int ws_chunk(int D, int P) { return D == 2 && P == 3 ? 10 : kChunk; }
 // consumer threads: 8 waves, or 4 for the T = 16 shape, whose producers need
 // the larger register budget of 8 waves per workgroup
 constexpr int ws_consumers(int T) { return T == 16 ? 256 : 512; }
@@ -585,6 +589,7 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
     constexpr int KM = NQM, KC = L::NQP * S::NG;  // conductivity K order: k = g * NQP + q
     constexpr int BUF = 2 * S::NS * (T + 1);     // one buffer: [NS][T + 1] pairs (V_m, V_c)
     constexpr int NCT = ws_consumers(T);
+    constexpr int CH = ws_chunk(D, P);
     constexpr int NTH = ws_threads(T);
     extern __shared__ __align__(16) unsigned char smem[];
     ST *sV = reinterpret_cast<ST *>(smem);  // [2 buffers][NS][T + 1][V_m, V_c]
@@ -698,12 +703,12 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
         }
     } else {
         const int ct = tid - kWsProducers;
-        uint4 R[kChunk], Rn[kChunk];
-        // record of round q of chunk c: r0 + (c * kChunk + q) * NCT + ct, clamped to the tile
-        auto load_chunk = [&](const uint4 *rec, int64_t r0, int64_t r1, int64_t c, uint4 (&dst)[kChunk]) {
+        uint4 R[CH], Rn[CH];
+        // record of round q of chunk c: r0 + (c * CH + q) * NCT + ct, clamped to the tile
+        auto load_chunk = [&](const uint4 *rec, int64_t r0, int64_t r1, int64_t c, uint4 (&dst)[CH]) {
 #pragma unroll
-            for (int q = 0; q < kChunk; ++q) {
-                const int64_t k = r0 + (c * kChunk + q) * NCT + ct;
+            for (int q = 0; q < CH; ++q) {
+                const int64_t k = r0 + (c * CH + q) * NCT + ct;
                 dst[q] = rec[k < r1 ? k : r1 - 1];
             }
         };
@@ -718,7 +723,7 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
             int64_t tile;
             const FusedArgs a = args_of<MULTI>(jt, job_of<MULTI>(jt, g, tile));
             const int64_t r0 = a.rec_ptr[tile], r1 = a.rec_ptr[tile + 1];
-            const int64_t nch = (r1 - r0 + int64_t(kChunk) * NCT - 1) / (int64_t(kChunk) * NCT);
+            const int64_t nch = (r1 - r0 + int64_t(CH) * NCT - 1) / (int64_t(CH) * NCT);
             const int64_t gn = g + walk.step;
             const bool more = walk.valid(gn);
             const uint4 *rec_n = a.rec;
@@ -737,8 +742,8 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
                 load_chunk(inner ? a.rec : rec_n, inner ? r0 : r0n, inner ? r1 : r1n, inner ? c + 1 : 0, Rn);
                 const uint32_t none = uint32_t(T) | (uint32_t(T) << 16);  // absent contributions
 #pragma unroll
-                for (int q = 0; q < kChunk; ++q) {
-                    const int64_t k0 = r0 + (c * kChunk + q) * NCT;
+                for (int q = 0; q < CH; ++q) {
+                    const int64_t k0 = r0 + (c * CH + q) * NCT;
                     if (k0 >= r1) continue;  // the whole round is past the tile's records (uniform)
                     const int64_t k = k0 + ct;
                     const bool active = k < r1;
@@ -757,7 +762,7 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
                     }
                 }
 #pragma unroll
-                for (int q = 0; q < kChunk; ++q) R[q] = Rn[q];
+                for (int q = 0; q < CH; ++q) R[q] = Rn[q];
             }
             if (!more) break;
             lds_barrier();  // next tile staged; this buffer may be overwritten
