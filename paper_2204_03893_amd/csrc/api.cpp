@@ -572,6 +572,10 @@ qxa_status make_fused_args(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *s
     a.qinv_m = precision == QXA_F16X2 ? p->f16_qinv[0] : 1.0;
     a.qinv_c = precision == QXA_F16X2 ? p->f16_qinv[1] : 1.0;
     a.part = part;
+    const int64_t lim = (int64_t(1) << 31) - 16;
+    a.buf_ok = 8 * p->nnz <= lim && 16 * p->n_partials <= lim;
+    a.bytes_vals = a.buf_ok ? uint32_t(8 * p->nnz) : 0u;
+    a.bytes_part = a.buf_ok ? uint32_t(16 * p->n_partials) : 0u;
     f = FixupArgs{p->n_fix, p->d_fix_target, p->d_fix_mirror, p->d_part_ptr, part, M, C};
     return QXA_OK;
 }
@@ -599,7 +603,7 @@ qxa_status qxa_assemble(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *stif
         std::fprintf(stderr, "qxa: cleared an earlier HIP error before launching: %s\n", hipGetErrorString(stale));
     {
         TimedLaunch tl(p, "fused", s);
-        const JobTable jt{a, nullptr, nullptr, 0, p->n_tiles};
+        const JobTable jt{a, nullptr, nullptr, 0, p->n_tiles, a.buf_ok};
         QXA_HIP(launch_fused(jt, p->ref.dim, p->ref.order, p->ref.nq_m, p->ref.nq_c, precision, s));
     }
     TimedLaunch tl(p, "fixup", s);

@@ -55,6 +55,9 @@ struct FusedArgs {
     double *sink;               // write target of idle lanes (at least 1024 doubles)
     double *M, *C;              // CSR values (either may be null)
     double *part;               // [n_partials][2] partials of shared slots (mass, conductivity)
+    uint32_t bytes_vals;        // 8 * nnz (buffer-store bound of M and C)
+    uint32_t bytes_part;        // 16 * n_partials (buffer-store bound of part)
+    int buf_ok;                 // both bounds below 2^31: the stores may go through buffer resources
 };
 
 // Jobs of one launch: a single assembly is carried by value in `one`
@@ -68,6 +71,7 @@ struct JobTable {
     const int64_t *tile_end;
     int n_jobs;
     int64_t n_tiles;
+    int buf_stores;  // every job has buf_ok
 };
 
 struct FixupArgs {

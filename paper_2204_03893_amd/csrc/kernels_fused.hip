@@ -124,16 +124,25 @@ __device__ __forceinline__ int job_of(const JobTable &jt, int64_t g, int64_t &lo
     int lo = 0, hi = jt.n_jobs - 1;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if (jt.tile_end[mid] > g) hi = mid;
+        if (uniform_table(jt.tile_end)[mid] > g) hi = mid;
         else lo = mid + 1;
     }
-    local = g - (lo > 0 ? jt.tile_end[lo - 1] : 0);
+    local = g - (lo > 0 ? uniform_table(jt.tile_end)[lo - 1] : 0);
     return lo;
 }
 template <bool MULTI>
 __device__ __forceinline__ FusedArgs args_of(const JobTable &jt, int j)
 {
-    if constexpr (MULTI) return jt.jobs[j];
+    if constexpr (MULTI) {
+        // word by word through the scalar path (j is uniform)
+        static_assert(sizeof(FusedArgs) % 8 == 0, "FusedArgs is copied in 8-byte words");
+        FusedArgs r;
+        const auto src = uniform_table(reinterpret_cast<const uint64_t *>(jt.jobs + j));
+        uint64_t *dst = reinterpret_cast<uint64_t *>(&r);
+#pragma unroll
+        for (size_t i = 0; i < sizeof(FusedArgs) / 8; ++i) dst[i] = src[i];
+        return r;
+    }
     return jt.one;
 }
 
@@ -202,6 +211,18 @@ struct Mfma<float> {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
 };
+
+typedef uint32_t qxa_u2 __attribute__((ext_vector_type(2)));
+typedef uint32_t qxa_u4 __attribute__((ext_vector_type(4)));
+
+// Raw buffer resource over [base, base + bytes) for stores: stride 0, word 3
+// as the gfx9 family takes it (32-bit data format, no swizzle, no index
+// range). A store whose offset is at or past `bytes` is dropped by the
+// hardware; bytes = 0 drops every store.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t store_rsrc(void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(base, 0, int(bytes), 0x00020000);
+}
 
 template <typename T>
 __device__ __forceinline__ T sel4(int j, T a0, T a1, T a2, T a3)
@@ -540,16 +561,17 @@ struct FormTraits<QXA_FP64> {
 // per tile separates the two. Producers issue only loads (the next tile's
 // gathers and connectivity), consumers only record loads and stores, so
 // neither role waits on the other's memory traffic. Consumers walk a tile's
-// records in chunks of kChunk rounds, loading chunk c+1 (or the next tile's
-// first chunk) before storing chunk c: every chunk issues the same number of
-// loads and stores (idle lanes read a valid record and write the sink), so
-// each wait covers only the records it needs, never the stores behind them.
+// records in chunks of CH rounds, loading chunk c+1 (or the next tile's
+// first chunk) before storing chunk c; every round issues at least two stores
+// (buffer stores that drop the lanes with nothing to write), so each wait for
+// records leaves the stores behind them in flight.
 constexpr int kWsProducers = 256;
-constexpr int kChunk = 8;
-// record rounds per consumer chunk: all of a tile's records in one chunk, so
-// the next tile's are loaded a whole tile ahead (2D P3: up to 5,005 records
-// per 64-element tile on 512 consumer threads)
-constexpr int ws_chunk(int D, int P) { return D == 2 && P == 3 ? 10 : kChunk; }
+// record rounds per consumer chunk, sized so that one chunk holds all of a
+// tile's records on Kuhn meshes (the next tile's are then loaded a whole tile
+// ahead): 2D P2 up to ~1,540 records per 64-element tile on 512 consumer
+// threads, 2D P3 ~5,010, 3D P2 ~2,940; 3D P3 (~4,080 per 16-element tile on
+// 256 threads) takes two chunks of 8
+constexpr int ws_chunk(int D, int P) { return D == 2 ? (P == 3 ? 10 : 3) : (P == 2 ? 6 : 8); }
 // consumer threads: 8 waves, or 4 for the T = 16 shape, whose producers need
 // the larger register budget of 8 waves per workgroup
 constexpr int ws_consumers(int T) { return T == 16 ? 256 : 512; }
@@ -587,7 +609,7 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
     constexpr int NB = (S::NS + 15) / 16;
     constexpr int NBW = QLDS ? NB : (NB + 3) / 4;  // row blocks per producer wave
     constexpr int KM = NQM, KC = L::NQP * S::NG;  // conductivity K order: k = g * NQP + q
-    constexpr int BUF = 2 * S::NS * (T + 1);     // one buffer: [NS][T + 1] pairs (V_m, V_c)
+    constexpr int BUF_ELEMS = 2 * S::NS * (T + 1);  // one buffer: [NS][T + 1] pairs (V_m, V_c)
     constexpr int NCT = ws_consumers(T);
     constexpr int CH = ws_chunk(D, P);
     constexpr int NTH = ws_threads(T);
@@ -615,7 +637,7 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
         for (int k = tid; k < NQC; k += NTH) sWC[k] = a0.in.w_c[k];
     }
     // a zero pair in the (never written) padding column of row 0 of each buffer
-    if (tid < 4) sV[(tid >> 1) * BUF + 2 * T + (tid & 1)] = ST(0);
+    if (tid < 4) sV[(tid >> 1) * BUF_ELEMS + 2 * T + (tid & 1)] = ST(0);
     const TileWalk walk(jt.n_tiles);
     lds_barrier();
     if (tid < kWsProducers) {
@@ -663,7 +685,7 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
                 gather(gn);  // its connectivity was loaded one tile ago
                 if (walk.valid(gn + walk.step)) load_conn(gn + walk.step);
             }
-            ST *bVm = sV + (it & 1) * BUF, *bVc = bVm + 1;
+            ST *bVm = sV + (it & 1) * BUF_ELEMS, *bVc = bVm + 1;
             // V_m^T = X_m^T Q_m^T with X_m = Lambda_m; V_c^T = X_c^T Q_c^T with X_c = Lambda_c (.) W
             if constexpr (!SPLIT) {
                 using CT = typename FormTraits<PF>::qplain_t;
@@ -712,61 +734,94 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
                 dst[q] = rec[k < r1 ? k : r1 - 1];
             }
         };
-        int64_t g = walk.t;
-        {
-            int64_t tile;
-            const FusedArgs a = args_of<MULTI>(jt, job_of<MULTI>(jt, g, tile));
-            load_chunk(a.rec, a.rec_ptr[tile], a.rec_ptr[tile + 1], 0, R);
-        }
-        lds_barrier();  // first tile staged
-        for (int it = 1;; ++it, g += walk.step) {
-            int64_t tile;
-            const FusedArgs a = args_of<MULTI>(jt, job_of<MULTI>(jt, g, tile));
-            const int64_t r0 = a.rec_ptr[tile], r1 = a.rec_ptr[tile + 1];
-            const int64_t nch = (r1 - r0 + int64_t(CH) * NCT - 1) / (int64_t(CH) * NCT);
-            const int64_t gn = g + walk.step;
-            const bool more = walk.valid(gn);
-            const uint4 *rec_n = a.rec;
-            int64_t r0n = r0, r1n = r1;
-            if (more) {
-                int64_t tn;
-                const FusedArgs an = args_of<MULTI>(jt, job_of<MULTI>(jt, gn, tn));
-                rec_n = an.rec;
-                r0n = an.rec_ptr[tn];
-                r1n = an.rec_ptr[tn + 1];
+        // tile ranges are uniform: read them through the scalar path, so that
+        // waiting for them never waits for this wave's outstanding stores
+        auto tile_range = [&](const FusedArgs &b, int64_t t, int64_t &r0, int64_t &r1) {
+            r0 = uniform_table(b.rec_ptr)[t];
+            r1 = uniform_table(b.rec_ptr)[t + 1];
+        };
+        // BUF: every round issues the mass and conductivity stores as buffer stores;
+        // a lane without an owned slot gives an offset past the end of the buffer,
+        // which the hardware drops. With at least two memory operations per round,
+        // the wait for the next chunk's records (loaded before this chunk's stores)
+        // leaves 2 * CH stores in flight instead of draining them all.
+        auto consume = [&](auto buf_tag) {
+            constexpr bool BUF = decltype(buf_tag)::value;
+            int64_t g = walk.t;
+            {
+                int64_t tile, r0, r1;
+                const FusedArgs a = args_of<MULTI>(jt, job_of<MULTI>(jt, g, tile));
+                tile_range(a, tile, r0, r1);
+                load_chunk(a.rec, r0, r1, 0, R);
             }
-            const ST *bV = sV + ((it - 1) & 1) * BUF;
-            for (int64_t c = 0; c < nch; ++c) {
-                // next chunk: the following one of this tile, else the next tile's first
-                const bool inner = c + 1 < nch;
-                load_chunk(inner ? a.rec : rec_n, inner ? r0 : r0n, inner ? r1 : r1n, inner ? c + 1 : 0, Rn);
-                const uint32_t none = uint32_t(T) | (uint32_t(T) << 16);  // absent contributions
+            lds_barrier();  // first tile staged
+            for (int it = 1;; ++it, g += walk.step) {
+                int64_t tile, r0, r1;
+                const FusedArgs a = args_of<MULTI>(jt, job_of<MULTI>(jt, g, tile));
+                tile_range(a, tile, r0, r1);
+                const int64_t nch = (r1 - r0 + int64_t(CH) * NCT - 1) / (int64_t(CH) * NCT);
+                const int64_t gn = g + walk.step;
+                const bool more = walk.valid(gn);
+                const uint4 *rec_n = a.rec;
+                int64_t r0n = r0, r1n = r1;
+                if (more) {
+                    int64_t tn;
+                    const FusedArgs an = args_of<MULTI>(jt, job_of<MULTI>(jt, gn, tn));
+                    rec_n = an.rec;
+                    tile_range(an, tn, r0n, r1n);
+                }
+                const ST *bV = sV + ((it - 1) & 1) * BUF_ELEMS;
+                const __amdgpu_buffer_rsrc_t rM = store_rsrc(a.M ? a.M : a.sink, a.M ? a.bytes_vals : 0u);
+                const __amdgpu_buffer_rsrc_t rC = store_rsrc(a.C ? a.C : a.sink, a.C ? a.bytes_vals : 0u);
+                for (int64_t c = 0; c < nch; ++c) {
+                    // next chunk: the following one of this tile, else the next tile's first
+                    const bool inner = c + 1 < nch;
+                    load_chunk(inner ? a.rec : rec_n, inner ? r0 : r0n, inner ? r1 : r1n, inner ? c + 1 : 0, Rn);
+                    const uint32_t none = uint32_t(T) | (uint32_t(T) << 16);  // absent contributions
 #pragma unroll
-                for (int q = 0; q < CH; ++q) {
-                    const int64_t k0 = r0 + (c * CH + q) * NCT;
-                    if (k0 >= r1) continue;  // the whole round is past the tile's records (uniform)
-                    const int64_t k = k0 + ct;
-                    const bool active = k < r1;
-                    // idle lanes read only the zero pair (a broadcast) and store nothing
-                    const uint4 rq = active ? R[q] : make_uint4(0u, none, none, none);
-                    double am, ac;
-                    record_sums_pair(rq, bV, am, ac);
-                    const int32_t t = int32_t(rq.x);
-                    if (active) {
-                        if (t >= 0) {
-                            if (a.M) a.M[t] = am;
-                            if (a.C) a.C[t] = ac;
-                        } else {  // the (mass, conductivity) pair of a partial: one 16-byte store
-                            reinterpret_cast<double2 *>(a.part)[-int64_t(t) - 1] = make_double2(am, ac);
+                    for (int q = 0; q < CH; ++q) {
+                        const int64_t k0 = r0 + (c * CH + q) * NCT;
+                        const int64_t k = k0 + ct;
+                        const bool active = k < r1;
+                        const int32_t t = int32_t(R[q].x);
+                        double am = 0.0, ac = 0.0;
+                        if constexpr (BUF) {
+                            // the whole round past the tile's records: no LDS reads (uniform)
+                            if (k0 < r1) {
+                                // idle lanes read only the zero pair (a broadcast)
+                                const uint4 rq = active ? R[q] : make_uint4(0u, none, none, none);
+                                record_sums_pair(rq, bV, am, ac);
+                            }
+                            const uint32_t ov = active && t >= 0 ? uint32_t(t) * 8u : 0x80000000u;
+                            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(qxa_u2, am), rM, ov, 0, 0);
+                            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(qxa_u2, ac), rC, ov, 0, 0);
+                            // partials sit at the end of the tile's records: a branch (skipped by
+                            // waves without one) adds stores but never removes the two above
+                            if (active && t < 0)
+                                reinterpret_cast<double2 *>(a.part)[-int64_t(t) - 1] = make_double2(am, ac);
+                        } else {
+                            if (k0 >= r1) continue;  // the whole round is past the tile's records (uniform)
+                            const uint4 rq = active ? R[q] : make_uint4(0u, none, none, none);
+                            record_sums_pair(rq, bV, am, ac);
+                            if (active) {
+                                if (t >= 0) {
+                                    if (a.M) a.M[t] = am;
+                                    if (a.C) a.C[t] = ac;
+                                } else {  // the (mass, conductivity) pair of a partial: one 16-byte store
+                                    reinterpret_cast<double2 *>(a.part)[-int64_t(t) - 1] = make_double2(am, ac);
+                                }
+                            }
                         }
                     }
-                }
 #pragma unroll
-                for (int q = 0; q < CH; ++q) R[q] = Rn[q];
+                    for (int q = 0; q < CH; ++q) R[q] = Rn[q];
+                }
+                if (!more) break;
+                lds_barrier();  // next tile staged; this buffer may be overwritten
             }
-            if (!more) break;
-            lds_barrier();  // next tile staged; this buffer may be overwritten
-        }
+        };
+        if (jt.buf_stores) consume(std::true_type{});
+        else consume(std::false_type{});
     }
 }
 

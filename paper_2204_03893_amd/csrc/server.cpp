@@ -379,7 +379,7 @@ static void launch_group(qxa_server s, std::vector<Job *> &g)
     if (e == hipSuccess) e = hipMemsetAsync(sl.d_flags, 0, sizeof(int) * g.size(), st);
     if (g.size() == 1) {
         const Job *j = g[0];
-        const JobTable jt{j->fa, nullptr, nullptr, 0, j->entry->plan->n_tiles};
+        const JobTable jt{j->fa, nullptr, nullptr, 0, j->entry->plan->n_tiles, j->fa.buf_ok};
         const FixupTable ft{j->xa, nullptr, nullptr, 0, j->entry->plan->n_fix};
         if (e == hipSuccess) e = launch_fused(jt, R.dim, R.order, R.nq_m, R.nq_c, prec, st);
         if (e == hipSuccess) e = launch_fixup(ft, st);
@@ -393,7 +393,9 @@ static void launch_group(qxa_server s, std::vector<Job *> &g)
         auto *hte = reinterpret_cast<int64_t *>(h + o_te);
         auto *hfe = reinterpret_cast<int64_t *>(h + o_fe);
         int64_t nt = 0, nf = 0;
+        int buf = 1;
         for (size_t k = 0; k < g.size(); ++k) {
+            buf &= g[k]->fa.buf_ok;
             hfa[k] = g[k]->fa;
             hxa[k] = g[k]->xa;
             nt += g[k]->entry->plan->n_tiles;
@@ -403,7 +405,7 @@ static void launch_group(qxa_server s, std::vector<Job *> &g)
         }
         if (e == hipSuccess) e = hipMemcpyAsync(d, h, o_fe + sizeof(int64_t) * g.size(), hipMemcpyHostToDevice, st);
         const JobTable jt{g[0]->fa, reinterpret_cast<const FusedArgs *>(d), reinterpret_cast<const int64_t *>(d + o_te),
-                          int(g.size()), nt};
+                          int(g.size()), nt, buf};
         const FixupTable ft{g[0]->xa, reinterpret_cast<const FixupArgs *>(d + o_fix),
                             reinterpret_cast<const int64_t *>(d + o_fe), int(g.size()), nf};
         if (e == hipSuccess) e = launch_fused(jt, R.dim, R.order, R.nq_m, R.nq_c, prec, st);
