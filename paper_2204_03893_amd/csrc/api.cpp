@@ -319,7 +319,7 @@ qxa_status qxa_plan_destroy(qxa_plan p)
 {
     if (!p) return QXA_OK;
     hipSetDevice(p->device);
-    void *bufs[] = {p->d_row_ptr, p->d_col_idx, p->d_tconn, p->d_elem_order, p->d_rec, p->d_rec_ptr,
+    void *bufs[] = {p->d_row_ptr, p->d_col_idx, p->d_tconn, p->d_elem_order, p->d_rec, p->d_rec_ptr, p->d_rec_mid,
                     p->d_part_ptr, p->d_fix_target, p->d_fix_mirror, p->d_sink, p->d_part, p->d_qfrag[0],
                     p->d_qfrag[1], p->d_qfrag[2], p->d_qfrag[3], p->d_qfrag[4], p->d_tables, p->d_tables_f,
                     p->d_V, p->d_flags};
@@ -344,7 +344,8 @@ qxa_status plan_stage(qxa_mesh mesh, const qxa_quad &mr, const qxa_quad &cr, Pla
     st = build_host_plan(mesh->dim, mesh->order, mesh->n_nodes, mesh->n_elem, mesh->h_conn.data(), g.hp);
     if (st) return st;
     st = build_tile_plan(mesh->dim, mesh->order, mesh->n_nodes, mesh->n_elem, mesh->h_conn.data(),
-                         mesh->h_coords.data(), g.hp, tile_size(mesh->dim, mesh->order), g.tp);
+                         mesh->h_coords.data(), g.hp, tile_size(mesh->dim, mesh->order),
+                         fused_uses_mfma(mesh->dim, mesh->order), g.tp);
     if (!st) st = check_tile_plan(T.np, mesh->n_elem, g.hp, g.tp);
     if (st) return st;
     g.mfma = fused_uses_mfma(T.dim, T.order);
@@ -391,6 +392,7 @@ qxa_status plan_upload(qxa_mesh mesh, const PlanStaging &g, DevArena *arena, boo
     if (!st) st = plan_upload_buf(p, &p->d_elem_order, tp.elem_order.data(), tp.elem_order.size());
     if (!st) st = plan_upload_buf(p, &p->d_rec, tp.rec.data(), tp.rec.size());
     if (!st) st = plan_upload_buf(p, &p->d_rec_ptr, tp.rec_ptr.data(), tp.rec_ptr.size());
+    if (!st) st = plan_upload_buf(p, &p->d_rec_mid, tp.rec_mid.data(), tp.rec_mid.size());
     if (!st) st = plan_upload_buf(p, &p->d_part_ptr, tp.part_ptr.data(), tp.part_ptr.size());
     if (!st) st = plan_upload_buf(p, &p->d_fix_target, tp.fix_target.data(), tp.fix_target.size());
     if (!st) st = plan_upload_buf(p, &p->d_fix_mirror, tp.fix_mirror.data(), tp.fix_mirror.size());
@@ -498,7 +500,8 @@ qxa_status qxa_plan_check_host(int dim, int order, int64_t n_nodes, const double
     qxa_status st = build_host_plan(dim, order, n_nodes, n_elem, conn, hp);
     if (st) return st;
     TilePlan tp;
-    st = build_tile_plan(dim, order, n_nodes, n_elem, conn, coords, hp, tile_size(dim, order), tp);
+    st = build_tile_plan(dim, order, n_nodes, n_elem, conn, coords, hp, tile_size(dim, order),
+                         fused_uses_mfma(dim, order), tp);
     if (!st) st = check_tile_plan(np, n_elem, hp, tp);
     if (st) return st;
     if (n_tiles) *n_tiles = tp.n_tiles;
@@ -564,6 +567,7 @@ qxa_status make_fused_args(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *s
     a.elem_order = p->d_elem_order;
     a.rec = reinterpret_cast<const uint4 *>(p->d_rec);
     a.rec_ptr = p->d_rec_ptr;
+    a.rec_mid = p->d_rec_mid;
     a.sink = p->d_sink;
     a.M = M;
     a.C = C;

@@ -50,8 +50,9 @@ struct FusedArgs {
     const void *Qfrag;          // Q^T in MFMA B-operand order (matrix-core variant)
     int64_t qfrag_vec16;        // size of Qfrag in 16-byte units
     double qinv_m, qinv_c;      // inverse power-of-two scales of the FP16 Q tables (1 otherwise)
-    const uint4 *rec;           // reduction records {target, c0|c1, c2|c3, c4|c5}
+    const uint4 *rec;           // output units: pairs {ta, a0|a1, tb, b0|b1}, then singles {t, c0|c1, c2|c3, c4|c5}
     const int64_t *rec_ptr;     // [n_tiles + 1]
+    const int64_t *rec_mid;     // [n_tiles] first single unit of each tile
     double *sink;               // write target of idle lanes (at least 1024 doubles)
     double *M, *C;              // CSR values (either may be null)
     double *part;               // [n_partials][2] partials of shared slots (mass, conductivity)

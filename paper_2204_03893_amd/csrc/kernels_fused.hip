@@ -61,6 +61,20 @@ __device__ __forceinline__ void record_sums_pair(const uint4 R, const ST *sV, do
     }
 }
 
+// The two outputs of a pair unit {ta, a0|a1, tb, b0|b1} from the same staging.
+template <typename ST>
+__device__ __forceinline__ void pair_sums(const uint4 U, const ST *sV, double &ama, double &aca, double &amb,
+                                          double &acb)
+{
+    using ST2 = typename std::conditional<sizeof(ST) == 8, double2, float2>::type;
+    const ST2 *v2 = reinterpret_cast<const ST2 *>(sV);
+    const ST2 a0 = v2[U.y & 0xffffu], a1 = v2[U.y >> 16], b0 = v2[U.w & 0xffffu], b1 = v2[U.w >> 16];
+    ama = double(a0.x) + double(a1.x);
+    aca = double(a0.y) + double(a1.y);
+    amb = double(b0.x) + double(b1.x);
+    acb = double(b0.y) + double(b1.y);
+}
+
 // Reduction of one record into its CSR slot (target >= 0) or partial.
 template <typename ST>
 __device__ __forceinline__ void reduce_record(const uint4 R, const ST *sVm, const ST *sVc, const FusedArgs &a)
@@ -566,12 +580,12 @@ struct FormTraits<QXA_FP64> {
 // (buffer stores that drop the lanes with nothing to write), so each wait for
 // records leaves the stores behind them in flight.
 constexpr int kWsProducers = 256;
-// record rounds per consumer chunk, sized so that one chunk holds all of a
-// tile's records on Kuhn meshes (the next tile's are then loaded a whole tile
-// ahead): 2D P2 up to ~1,540 records per 64-element tile on 512 consumer
-// threads, 2D P3 ~5,010, 3D P2 ~2,940; 3D P3 (~4,080 per 16-element tile on
-// 256 threads) takes two chunks of 8
-constexpr int ws_chunk(int D, int P) { return D == 2 ? (P == 3 ? 10 : 3) : (P == 2 ? 6 : 8); }
+// unit rounds per consumer chunk, sized so that one chunk holds all of a
+// tile's output units on Kuhn meshes (the next tile's are then loaded a whole
+// tile ahead): 2D P2 up to ~790 units per 64-element tile on 512 consumer
+// threads, 2D P3 ~2,520, 3D P2 ~1,700; 3D P3 (~2,100 per 16-element tile on
+// 256 threads) takes two chunks of 5
+constexpr int ws_chunk(int D, int P) { return D == 2 ? (P == 3 ? 5 : 2) : (P == 2 ? 4 : 5); }
 // consumer threads: 8 waves, or 4 for the T = 16 shape, whose producers need
 // the larger register budget of 8 waves per workgroup
 constexpr int ws_consumers(int T) { return T == 16 ? 256 : 512; }
@@ -725,8 +739,9 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
         }
     } else {
         const int ct = tid - kWsProducers;
+        const int cw = 64 * __builtin_amdgcn_readfirstlane(ct >> 6);  // this wave's first lane (uniform)
         uint4 R[CH], Rn[CH];
-        // record of round q of chunk c: r0 + (c * CH + q) * NCT + ct, clamped to the tile
+        // unit of round q of chunk c: r0 + (c * CH + q) * NCT + ct, clamped to the tile
         auto load_chunk = [&](const uint4 *rec, int64_t r0, int64_t r1, int64_t c, uint4 (&dst)[CH]) {
 #pragma unroll
             for (int q = 0; q < CH; ++q) {
@@ -740,11 +755,11 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
             r0 = uniform_table(b.rec_ptr)[t];
             r1 = uniform_table(b.rec_ptr)[t + 1];
         };
-        // BUF: every round issues the mass and conductivity stores as buffer stores;
-        // a lane without an owned slot gives an offset past the end of the buffer,
-        // which the hardware drops. With at least two memory operations per round,
-        // the wait for the next chunk's records (loaded before this chunk's stores)
-        // leaves 2 * CH stores in flight instead of draining them all.
+        // BUF: the mass and conductivity stores of every round's first outputs are
+        // buffer stores; a lane without an owned slot gives an offset past the end
+        // of the buffer, which the hardware drops. With at least two memory
+        // operations per round, the wait for the next chunk's units (loaded before
+        // this chunk's stores) leaves 2 * CH stores in flight instead of draining them.
         auto consume = [&](auto buf_tag) {
             constexpr bool BUF = decltype(buf_tag)::value;
             int64_t g = walk.t;
@@ -759,6 +774,7 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
                 int64_t tile, r0, r1;
                 const FusedArgs a = args_of<MULTI>(jt, job_of<MULTI>(jt, g, tile));
                 tile_range(a, tile, r0, r1);
+                const int64_t rm = uniform_table(a.rec_mid)[tile];  // pair units end here
                 const int64_t nch = (r1 - r0 + int64_t(CH) * NCT - 1) / (int64_t(CH) * NCT);
                 const int64_t gn = g + walk.step;
                 const bool more = walk.valid(gn);
@@ -773,6 +789,7 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
                 const ST *bV = sV + ((it - 1) & 1) * BUF_ELEMS;
                 const __amdgpu_buffer_rsrc_t rM = store_rsrc(a.M ? a.M : a.sink, a.M ? a.bytes_vals : 0u);
                 const __amdgpu_buffer_rsrc_t rC = store_rsrc(a.C ? a.C : a.sink, a.C ? a.bytes_vals : 0u);
+                double2 *part = reinterpret_cast<double2 *>(a.part);
                 for (int64_t c = 0; c < nch; ++c) {
                     // next chunk: the following one of this tile, else the next tile's first
                     const bool inner = c + 1 < nch;
@@ -781,34 +798,52 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
 #pragma unroll
                     for (int q = 0; q < CH; ++q) {
                         const int64_t k0 = r0 + (c * CH + q) * NCT;
-                        const int64_t k = k0 + ct;
-                        const bool active = k < r1;
-                        const int32_t t = int32_t(R[q].x);
-                        double am = 0.0, ac = 0.0;
-                        if constexpr (BUF) {
-                            // the whole round past the tile's records: no LDS reads (uniform)
-                            if (k0 < r1) {
-                                // idle lanes read only the zero pair (a broadcast)
-                                const uint4 rq = active ? R[q] : make_uint4(0u, none, none, none);
-                                record_sums_pair(rq, bV, am, ac);
+                        if (!BUF && k0 >= r1) continue;  // the whole round is past the tile's units (uniform)
+                        const int64_t k = k0 + ct, kw = k0 + cw;
+                        const bool active = k < r1, pair = k < rm;  // rm <= r1: a pair unit is active
+                        const uint4 U = R[q];
+                        const int32_t ta = int32_t(U.x), tb = int32_t(U.z);
+                        double ama = 0.0, aca = 0.0, amb = 0.0, acb = 0.0;
+                        if (k0 < r1) {  // (uniform) no LDS reads for a round past the tile's units
+                            if (kw + 63 < rm) {  // the wave's units are all pairs
+                                pair_sums(U, bV, ama, aca, amb, acb);
+                            } else if (kw >= rm) {  // all singles; idle lanes read the zero pair
+                                record_sums_pair(active ? U : make_uint4(0u, none, none, none), bV, ama, aca);
+                            } else if (pair) {  // the wave that holds the boundary
+                                pair_sums(U, bV, ama, aca, amb, acb);
+                            } else {
+                                record_sums_pair(active ? U : make_uint4(0u, none, none, none), bV, ama, aca);
                             }
-                            const uint32_t ov = active && t >= 0 ? uint32_t(t) * 8u : 0x80000000u;
-                            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(qxa_u2, am), rM, ov, 0, 0);
-                            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(qxa_u2, ac), rC, ov, 0, 0);
-                            // partials sit at the end of the tile's records: a branch (skipped by
-                            // waves without one) adds stores but never removes the two above
-                            if (active && t < 0)
-                                reinterpret_cast<double2 *>(a.part)[-int64_t(t) - 1] = make_double2(am, ac);
+                        }
+                        if constexpr (BUF) {
+                            const uint32_t drop = 0x80000000u;
+                            const uint32_t oa = active && ta >= 0 ? uint32_t(ta) * 8u : drop;
+                            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(qxa_u2, ama), rM, oa, 0, 0);
+                            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(qxa_u2, aca), rC, oa, 0, 0);
+                            if (kw < rm) {  // (uniform) second outputs of the wave's pair units
+                                const uint32_t ob = pair && tb >= 0 ? uint32_t(tb) * 8u : drop;
+                                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(qxa_u2, amb), rM, ob, 0, 0);
+                                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(qxa_u2, acb), rC, ob, 0, 0);
+                            }
+                            // partials sit at the end of each group: branches (skipped by waves
+                            // without one) add stores but never remove the two above
+                            if (active && ta < 0) part[-int64_t(ta) - 1] = make_double2(ama, aca);
+                            if (pair && tb < 0) part[-int64_t(tb) - 1] = make_double2(amb, acb);
                         } else {
-                            if (k0 >= r1) continue;  // the whole round is past the tile's records (uniform)
-                            const uint4 rq = active ? R[q] : make_uint4(0u, none, none, none);
-                            record_sums_pair(rq, bV, am, ac);
                             if (active) {
-                                if (t >= 0) {
-                                    if (a.M) a.M[t] = am;
-                                    if (a.C) a.C[t] = ac;
+                                if (ta >= 0) {
+                                    if (a.M) a.M[ta] = ama;
+                                    if (a.C) a.C[ta] = aca;
                                 } else {  // the (mass, conductivity) pair of a partial: one 16-byte store
-                                    reinterpret_cast<double2 *>(a.part)[-int64_t(t) - 1] = make_double2(am, ac);
+                                    part[-int64_t(ta) - 1] = make_double2(ama, aca);
+                                }
+                            }
+                            if (pair) {
+                                if (tb >= 0) {
+                                    if (a.M) a.M[tb] = amb;
+                                    if (a.C) a.C[tb] = acb;
+                                } else {
+                                    part[-int64_t(tb) - 1] = make_double2(amb, acb);
                                 }
                             }
                         }

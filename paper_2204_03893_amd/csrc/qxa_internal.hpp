@@ -75,15 +75,20 @@ struct TilePlan {
     int64_t n_tiles = 0;
     std::vector<int32_t> elem_order;  // tile position -> element id (Morton order of centroids)
     std::vector<int32_t> tconn;       // [np][n_elem] connectivity in tile order
-    // One 16-byte record per output of a tile: {target, c0|c1, c2|c3, c4|c5}.
-    // target >= 0: a CSR slot owned by the tile (upper and mirror entries are
-    // separate records with the same contributions); target < 0: partial
-    // -(p + 1). c0..c5: padded LDS indices (s*(T+1) + local element) of the
-    // contributions in summation order; T (pair 0, padding column, where the
-    // kernels keep a zero) = none. Owned records come
-    // first in ascending CSR slot order (coalesced stores), then partials.
-    std::vector<uint32_t> rec;        // [4 * n_records]
-    std::vector<int64_t> rec_ptr;     // [n_tiles + 1] (in records)
+    // A tile's outputs in 16-byte units. An output has a target (>= 0: a CSR
+    // slot owned by the tile, upper and mirror entries being separate outputs
+    // with the same contributions; < 0: partial -(p + 1)) and the padded LDS
+    // indices (s*(T+1) + local element) of its contributions in summation
+    // order; T (pair 0, padding column, where the kernels keep a zero) = none.
+    // Units rec_ptr[t] .. rec_mid[t] - 1 are pair units {target a, a0|a1,
+    // target b, b0|b1} of outputs with at most two contributions (output l of
+    // that group with output l + n/2, n = 2 (rec_mid - rec_ptr)); the rest are
+    // single units {target, c0|c1, c2|c3, c4|c5} (at most six). In each group
+    // owned outputs come first in ascending CSR slot order (coalesced stores),
+    // then partials. Without pair units (P1) rec_mid[t] = rec_ptr[t].
+    std::vector<uint32_t> rec;        // [4 * n_units]
+    std::vector<int64_t> rec_ptr;     // [n_tiles + 1] (in units)
+    std::vector<int64_t> rec_mid;     // [n_tiles] first single unit of the tile
     // Partials of shared upper slot k (CSR order) are part_ptr[k] ..
     // part_ptr[k+1] - 1, in ascending tile order, then record order.
     std::vector<int64_t> part_ptr;    // [n_shared + 1]
@@ -95,7 +100,7 @@ struct TilePlan {
 };
 
 qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, const int32_t *conn,
-                           const double *coords, const HostPlan &hp, int T, TilePlan &tp);
+                           const double *coords, const HostPlan &hp, int T, bool pair_units, TilePlan &tp);
 qxa_status check_tile_plan(int np, int64_t n_elem, const HostPlan &hp, const TilePlan &tp);
 
 // First-fit sub-allocator over one device allocation (256-byte granules,
@@ -170,6 +175,7 @@ struct qxa_plan_s {
     int32_t *d_tconn = nullptr, *d_elem_order = nullptr;
     uint32_t *d_rec = nullptr;
     int64_t *d_rec_ptr = nullptr;
+    int64_t *d_rec_mid = nullptr;
     int64_t *d_part_ptr = nullptr;
     int32_t *d_fix_target = nullptr, *d_fix_mirror = nullptr;
     int64_t n_fix = 0;

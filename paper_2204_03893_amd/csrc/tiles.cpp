@@ -45,7 +45,7 @@ static uint64_t spread_bits(uint64_t x, int dim)
 }
 
 qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, const int32_t *conn,
-                           const double *coords, const HostPlan &hp, int T, TilePlan &tp)
+                           const double *coords, const HostPlan &hp, int T, bool pair_units, TilePlan &tp)
 {
     const int np = n_local(dim, order), ns = n_sym(np);
     if (int64_t(T + 1) * ns >= 0xffff) return fail(QXA_E_UNSUPPORTED, "tile too large for 16-bit LDS indices");
@@ -150,11 +150,17 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
     // then the tile's partials; a partial's index is fixed in a second,
     // sequential pass over the tiles in ascending order
     std::vector<std::vector<uint32_t>> trec(nt);
-    std::vector<std::vector<std::pair<uint32_t, uint32_t>>> tpart(nt);  // (shared id, record position)
+    std::vector<int64_t> tshort(nt, 0);  // pair units at the start of each tile
+    std::vector<std::vector<std::pair<uint32_t, uint32_t>>> tpart(nt);  // (shared id, word of its target)
+    struct Out {
+        uint32_t tgt;  // CSR slot (owned) or shared id
+        bool shared;
+        int n;  // contributions
+        std::array<uint16_t, 6> c;
+    };
     parallel_for(nt, [&](int64_t a, int64_t b) {
         std::vector<uint64_t> buf;
-        std::vector<std::pair<uint32_t, std::array<uint16_t, 6>>> owned;
-        std::vector<std::pair<uint32_t, std::array<uint16_t, 6>>> shared;
+        std::vector<Out> owned, shared, S, L;
         for (int64_t t = a; t < b; ++t) {
             tile_entries(t, buf);
             owned.clear();
@@ -165,42 +171,71 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
                 size_t k1 = k;
                 while (k1 < buf.size() && uint32_t(buf[k1] >> 32) == u) ++k1;
                 for (size_t c0 = k; c0 < k1; c0 += 6) {
-                    std::array<uint16_t, 6> c;
-                    c.fill(uint16_t(T));  // absent: the zero kept at (pair 0, column T)
-                    for (size_t q = c0; q < std::min(k1, c0 + 6); ++q) c[q - c0] = uint16_t(buf[q] & 0xffff);
+                    Out o{0u, false, int(std::min(k1, c0 + 6) - c0), {}};
+                    o.c.fill(uint16_t(T));  // absent: the zero kept at (pair 0, column T)
+                    for (int q = 0; q < o.n; ++q) o.c[q] = uint16_t(buf[c0 + q] & 0xffff);
                     if (sh_id[u] < 0) {
-                        owned.push_back({u, c});
-                        if (hp.mirror[u] != u) owned.push_back({hp.mirror[u], c});
+                        o.tgt = u;
+                        owned.push_back(o);
+                        if (hp.mirror[u] != u) {
+                            o.tgt = hp.mirror[u];
+                            owned.push_back(o);
+                        }
                     } else {
-                        shared.push_back({uint32_t(sh_id[u]), c});
+                        o.tgt = uint32_t(sh_id[u]);
+                        o.shared = true;
+                        shared.push_back(o);
                     }
                 }
                 k = k1;
             }
-            std::sort(owned.begin(), owned.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
+            std::sort(owned.begin(), owned.end(), [](const Out &x, const Out &y) { return x.tgt < y.tgt; });
+            // outputs with at most two contributions go two to a unit, the rest one
+            // to a unit; owned outputs before partials in each group
+            S.clear();
+            L.clear();
+            for (const auto *grp : {&owned, &shared})
+                for (const Out &o : *grp) (pair_units && o.n <= 2 ? S : L).push_back(o);
+            if (S.size() % 2) {
+                L.insert(L.begin(), S.back());
+                S.pop_back();
+            }
             auto &R = trec[t];
             R.clear();
             tpart[t].clear();
-            auto put = [&](uint32_t tgt, const std::array<uint16_t, 6> &c) {
-                R.push_back(tgt);
-                R.push_back(uint32_t(c[0]) | (uint32_t(c[1]) << 16));
-                R.push_back(uint32_t(c[2]) | (uint32_t(c[3]) << 16));
-                R.push_back(uint32_t(c[4]) | (uint32_t(c[5]) << 16));
+            const size_t us = S.size() / 2;
+            tshort[t] = int64_t(us);
+            auto target = [&](const Out &o) {
+                if (o.shared) tpart[t].push_back({o.tgt, uint32_t(R.size())});
+                return o.shared ? 0u : o.tgt;
             };
-            for (auto &o : owned) put(o.first, o.second);
-            for (auto &sc : shared) {
-                tpart[t].push_back({sc.first, uint32_t(R.size() / 4)});
-                put(0u, sc.second);
+            auto pack = [](const Out &o, int q) { return uint32_t(o.c[q]) | (uint32_t(o.c[q + 1]) << 16); };
+            // unit l: outputs l and l + us, so that each store of a round covers consecutive outputs
+            for (size_t l = 0; l < us; ++l) {
+                R.push_back(target(S[l]));
+                R.push_back(pack(S[l], 0));
+                R.push_back(target(S[l + us]));
+                R.push_back(pack(S[l + us], 0));
+            }
+            for (const Out &o : L) {
+                R.push_back(target(o));
+                R.push_back(pack(o, 0));
+                R.push_back(pack(o, 2));
+                R.push_back(pack(o, 4));
             }
         }
     });
     {
         std::vector<int64_t> fill(tp.part_ptr.begin(), tp.part_ptr.end() - 1);
         for (int64_t t = 0; t < nt; ++t)
-            for (auto &pr : tpart[t]) trec[t][4 * size_t(pr.second)] = uint32_t(-(fill[pr.first]++) - 1);
+            for (auto &pr : tpart[t]) trec[t][pr.second] = uint32_t(-(fill[pr.first]++) - 1);
     }
     tp.rec_ptr.assign(nt + 1, 0);
-    for (int64_t t = 0; t < nt; ++t) tp.rec_ptr[t + 1] = tp.rec_ptr[t] + int64_t(trec[t].size() / 4);
+    tp.rec_mid.assign(nt, 0);
+    for (int64_t t = 0; t < nt; ++t) {
+        tp.rec_ptr[t + 1] = tp.rec_ptr[t] + int64_t(trec[t].size() / 4);
+        tp.rec_mid[t] = tp.rec_ptr[t] + tshort[t];
+    }
     tp.rec.resize(4 * size_t(tp.rec_ptr[nt]));
     parallel_for(nt, [&](int64_t a, int64_t b) {
         for (int64_t t = a; t < b; ++t) std::copy(trec[t].begin(), trec[t].end(), tp.rec.begin() + 4 * tp.rec_ptr[t]);
@@ -230,6 +265,7 @@ qxa_status check_tile_plan(int np, int64_t n_elem, const HostPlan &hp, const Til
     const int64_t T = tp.T, TP = T + 1;
     std::vector<uint8_t> slot_w(hp.nnz, 0), part_w(tp.n_partials, 0), used;
     if (int64_t(tp.rec_ptr.size()) != tp.n_tiles + 1 || tp.rec_ptr[0] != 0 ||
+        int64_t(tp.rec_mid.size()) != tp.n_tiles ||
         int64_t(tp.rec.size()) != 4 * tp.rec_ptr[tp.n_tiles] || int64_t(tp.part_ptr.size()) != tp.n_shared + 1 ||
         tp.part_ptr[0] != 0 || tp.part_ptr[tp.n_shared] != tp.n_partials)
         return fail(QXA_E_INVALID, "tile plan: bad sizes");
@@ -237,11 +273,12 @@ qxa_status check_tile_plan(int np, int64_t n_elem, const HostPlan &hp, const Til
     for (int64_t t = 0; t < tp.n_tiles; ++t) {
         const int64_t p0 = t * T, nloc = std::min<int64_t>(T, n_elem - p0);
         used.assign(size_t(TP) * ns, 0);
-        for (int64_t r = tp.rec_ptr[t]; r < tp.rec_ptr[t + 1]; ++r) {
-            const uint32_t *R = &tp.rec[4 * r];
-            const uint32_t c[6] = {R[1] & 0xffffu, R[1] >> 16, R[2] & 0xffffu, R[2] >> 16, R[3] & 0xffffu, R[3] >> 16};
+        if (tp.rec_mid[t] < tp.rec_ptr[t] || tp.rec_mid[t] > tp.rec_ptr[t + 1])
+            return fail(QXA_E_INVALID, "tile plan: bad pair-unit range");
+        // one output: target g and nc contribution indices
+        auto check_out = [&](int32_t g, const uint32_t *c, int nc) -> qxa_status {
             int n = 0;
-            for (int q = 0; q < 6; ++q) {
+            for (int q = 0; q < nc; ++q) {
                 if (c[q] == uint32_t(T)) continue;  // absent
                 if (c[q] >= uint32_t(TP * ns) || int64_t(c[q] % TP) >= nloc)
                     return fail(QXA_E_INVALID, "tile plan: LDS index out of range");
@@ -249,13 +286,26 @@ qxa_status check_tile_plan(int np, int64_t n_elem, const HostPlan &hp, const Til
                 ++n;
             }
             if (n == 0) return fail(QXA_E_INVALID, "tile plan: empty record");
-            const int32_t g = int32_t(R[0]);
             if (g >= 0) {
                 if (!write_slot(g)) return fail(QXA_E_INVALID, "tile plan: slot written twice");
             } else {
                 const int64_t pi = -int64_t(g) - 1;
                 if (pi >= tp.n_partials || part_w[pi]++) return fail(QXA_E_INVALID, "tile plan: partial written twice");
             }
+            return QXA_OK;
+        };
+        for (int64_t r = tp.rec_ptr[t]; r < tp.rec_ptr[t + 1]; ++r) {
+            const uint32_t *R = &tp.rec[4 * r];
+            qxa_status st;
+            if (r < tp.rec_mid[t]) {  // two outputs of at most two contributions
+                const uint32_t a[2] = {R[1] & 0xffffu, R[1] >> 16}, b[2] = {R[3] & 0xffffu, R[3] >> 16};
+                st = check_out(int32_t(R[0]), a, 2);
+                if (!st) st = check_out(int32_t(R[2]), b, 2);
+            } else {
+                const uint32_t c[6] = {R[1] & 0xffffu, R[1] >> 16, R[2] & 0xffffu, R[2] >> 16, R[3] & 0xffffu, R[3] >> 16};
+                st = check_out(int32_t(R[0]), c, 6);
+            }
+            if (st) return st;
         }
         for (int64_t k = 0; k < nloc; ++k)
             for (int s = 0; s < ns; ++s)
