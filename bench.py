@@ -371,7 +371,7 @@ def main():
         "config": {"workload": w.name, "description": w.description, "n_elem": plan.n_elem,
                    "n_nodes": plan.n_nodes, "nnz": plan.nnz, "entries_per_step": entries,
                    "precision": args.precision, "n_tiles": plan.n_tiles, "n_shared": plan.n_shared,
-                   "n_partials": plan.n_partials},
+                   "n_partials": plan.n_partials, "n_units": plan.n_units, "n_pair_units": plan.n_pair_units},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(dom, w.name, args.precision), "kernel": dom,

@@ -106,6 +106,8 @@ typedef struct {
     int64_t n_tiles;        /* element tiles of the fused kernel                    */
     int64_t n_shared;       /* CSR upper slots shared between tiles                 */
     int64_t n_partials;     /* partial sums written for shared slots                */
+    int64_t n_units;        /* 16-byte output units read by the fused kernel        */
+    int64_t n_pair_units;   /* of which pair units (two outputs each)               */
 } qxa_plan_info;
 
 const char *qxa_last_error(void);

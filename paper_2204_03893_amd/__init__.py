@@ -46,7 +46,7 @@ class _PlanInfo(C.Structure):
                 ("n_q_stiff", C.c_int), ("n_nodes", C.c_int64), ("n_elem", C.c_int64), ("nnz", C.c_int64),
                 ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("device_bytes", C.c_size_t),
                 ("build_ms", C.c_double), ("n_tiles", C.c_int64), ("n_shared", C.c_int64),
-                ("n_partials", C.c_int64)]
+                ("n_partials", C.c_int64), ("n_units", C.c_int64), ("n_pair_units", C.c_int64)]
 
 
 class _ServerOpts(C.Structure):
@@ -203,6 +203,8 @@ class Plan:
         self.n_tiles = int(info.n_tiles)
         self.n_shared = int(info.n_shared)
         self.n_partials = int(info.n_partials)
+        self.n_units = int(info.n_units)
+        self.n_pair_units = int(info.n_pair_units)
 
     def pattern(self):
         """(row_ptr int64, col_idx int32) as device tensors."""

@@ -386,6 +386,9 @@ qxa_status plan_upload(qxa_mesh mesh, const PlanStaging &g, DevArena *arena, boo
     p->n_shared = tp.n_shared;
     p->n_fix = int64_t(tp.fix_target.size());
     p->n_partials = tp.n_partials;
+    p->n_units = tp.rec_ptr.back();
+    p->n_pair_units = 0;
+    for (int64_t t = 0; t < tp.n_tiles; ++t) p->n_pair_units += tp.rec_mid[t] - tp.rec_ptr[t];
     qxa_status st = plan_upload_buf(p, &p->d_row_ptr, hp.row_ptr.data(), hp.row_ptr.size());
     if (!st) st = plan_upload_buf(p, &p->d_col_idx, hp.col_idx.data(), hp.col_idx.size());
     if (!st) st = plan_upload_buf(p, &p->d_tconn, tp.tconn.data(), tp.tconn.size());
@@ -466,6 +469,8 @@ qxa_status qxa_plan_get_info(qxa_plan p, qxa_plan_info *out)
     out->n_tiles = p->n_tiles;
     out->n_shared = p->n_shared;
     out->n_partials = p->n_partials;
+    out->n_units = p->n_units;
+    out->n_pair_units = p->n_pair_units;
     return QXA_OK;
 }
 

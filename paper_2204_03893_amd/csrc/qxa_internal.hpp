@@ -171,7 +171,7 @@ struct qxa_plan_s {
     int32_t *d_col_idx = nullptr;
     // fused-path tile plan (device copies)
     int tile_T = 0;
-    int64_t n_tiles = 0, n_shared = 0, n_partials = 0;
+    int64_t n_tiles = 0, n_shared = 0, n_partials = 0, n_units = 0, n_pair_units = 0;
     int32_t *d_tconn = nullptr, *d_elem_order = nullptr;
     uint32_t *d_rec = nullptr;
     int64_t *d_rec_ptr = nullptr;
