@@ -864,7 +864,9 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
 // contiguously, ascending tile order) and writes the slot and its mirror.
 __global__ __launch_bounds__(256) void fixup_kernel(FixupTable ft)
 {
-    int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    // XCD-aware: the blocks of one XCD take a contiguous range of shared slots,
+    // so that stores into the same CSR rows meet in the same L2
+    int64_t f = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (f >= ft.n_fix) return;
     int jb = -1;
     if (ft.n_jobs > 0) {
