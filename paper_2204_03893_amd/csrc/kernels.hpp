@@ -20,8 +20,8 @@ namespace qxa {
 // Elements per tile of the fused kernels. Vector-ALU variant (P1): one lane
 // per element. Matrix-core variant (P2, P3): 4 producer waves of 16 elements
 // (two LDS buffers of both matrices, 2 * 2 * NS * (T + 1) values, next to
-// Q^T); 3D P3 (NS = 210) keeps one 16-element group whose row blocks the
-// producer waves split.
+// Q^T); 3D P3 (NS = 210) keeps one 16-element group whose row blocks eight
+// producer waves split, two each.
 constexpr int tile_size(int D, int P)
 {
     return (D == 3 && P == 3) ? 16 : (P >= 2) ? 64 : 256;

@@ -570,8 +570,9 @@ struct FormTraits<QXA_FP64> {
 
 // Warp-specialised matrix-core kernel (persistent). The workgroup walks its
 // tiles with a two-buffer pipeline: waves 0-3 (producers, 16 elements each,
-// T = 64) gather, set up and contract tile i into LDS buffer i % 2 while waves
-// 4-11 (consumers) reduce tile i-1 from the other buffer; one LDS-only barrier
+// T = 64; waves 0-7 for T = 16, see WideProducer) gather, set up and contract
+// tile i into LDS buffer i % 2 while the other waves (consumers) reduce tile
+// i-1 from the other buffer; one LDS-only barrier
 // per tile separates the two. Producers issue only loads (the next tile's
 // gathers and connectivity), consumers only record loads and stores, so
 // neither role waits on the other's memory traffic. Consumers walk a tile's
@@ -579,23 +580,273 @@ struct FormTraits<QXA_FP64> {
 // first chunk) before storing chunk c; every round issues at least two stores
 // (buffer stores that drop the lanes with nothing to write), so each wait for
 // records leaves the stores behind them in flight.
-constexpr int kWsProducers = 256;
+// producer threads: 4 waves of one 16-element group each, or 8 waves for T = 16
+constexpr int ws_producers(int T) { return T == 16 ? 512 : 256; }
 // unit rounds per consumer chunk, sized so that one chunk holds all of a
 // tile's output units on Kuhn meshes (the next tile's are then loaded a whole
 // tile ahead): 2D P2 up to ~790 units per 64-element tile on 512 consumer
 // threads, 2D P3 ~2,520, 3D P2 ~1,700; 3D P3 (~2,100 per 16-element tile on
 // 256 threads) takes two chunks of 5
 constexpr int ws_chunk(int D, int P) { return D == 2 ? (P == 3 ? 5 : 2) : (P == 2 ? 4 : 5); }
-// consumer threads: 8 waves, or 4 for the T = 16 shape, whose producers need
-// the larger register budget of 8 waves per workgroup
+// consumer threads: 8 waves, or 4 for the T = 16 shape (12 waves in all, whose
+// register budget its producers need)
 constexpr int ws_consumers(int T) { return T == 16 ? 256 : 512; }
-constexpr int ws_threads(int T) { return kWsProducers + ws_consumers(T); }
+constexpr int ws_threads(int T) { return ws_producers(T) + ws_consumers(T); }
+
+// Producers of the T = 16 shape (3D P3: 210 symmetric rows, Q^T of 282 KB in
+// FP64, read from global memory where it stays cached), eight waves:
+// - the connectivity, vertex coordinates and nodal field of a tile are
+//   gathered by all producer lanes together, one value per lane (tile g + 2),
+//   and staged in LDS;
+// - the weighted coefficients Lambda (one (element, node) per lane and pass)
+//   and the metric W of each element are formed from the staged values
+//   (tile g + 1) and staged in LDS, so no coefficient is evaluated twice;
+// - each wave multiplies X^T (16 elements, read back from LDS) by the
+//   Q^T fragments of its row blocks nb = wave and wave + 8 (tile g), the
+//   fragments of the next chunk of k-steps being loaded during the current one.
+// Every stage works on a different tile, so one barrier per tile orders them;
+// two barriers before the loop fill the pipeline.
+template <int D, int P, int NQM, int NQC, int PF, int T, bool MULTI>
+struct WideProducer {
+    using S = Shape<D, P>;
+    using ST = typename FormTraits<PF>::stage_t;
+    using CT = typename FormTraits<PF>::qplain_t;
+    using MF = Mfma<CT>;
+    static constexpr int NPT = 512;                    // producer threads
+    static constexpr int NP = S::NP, NG = S::NG, NS = S::NS;
+    static constexpr int DC = (D + 1) * D;             // staged vertex coordinates per element
+    static constexpr int RAWN = DC + 2 * NP;           // + first and second nodal field
+    static constexpr int NITEM = DC + NP;              // gather items per element
+    static constexpr int NQL = NQM + NQC;              // staged Lambda per element
+    static constexpr int NQP = (NQC + 3) / 4 * 4;
+    static constexpr int KSM = (NQM + 3) / 4, MSC = NQP / 4;
+    static constexpr int NSTEP = KSM + NG * MSC;       // k-steps: mass, then conductivity (k = g NQP + q)
+    static constexpr int NB = (NS + 15) / 16;
+    static constexpr int CHS = 6;                      // k-steps per chunk
+    static constexpr int NCHK = (NSTEP + CHS - 1) / CHS;
+    static constexpr int BUF_ELEMS = 2 * NS * (T + 1);
+    static constexpr size_t lds_doubles = size_t(2) * T * (RAWN + NQL + NG);
+    static_assert(T == 16 && NITEM <= NPT / T, "one gather item per producer lane");
+    static_assert(NB <= 16, "two row blocks per producer wave");
+
+    const JobTable &jt;
+    const TileWalk &walk;
+    ST *sV;
+    const double *sPhiM, *sPhiC, *sWM, *sWC;
+    double *sRaw, *sLam, *sA;  // [2][T][RAWN], [2][T][NQL], [2][T][NG]
+    int tid, lane, wave, ge, gk;  // gather item of this lane: element ge, item gk
+
+    __device__ WideProducer(const JobTable &jt_, const TileWalk &w, ST *sV_, const double *pm, const double *pc,
+                            const double *wm, const double *wc, double *wide, int tid_)
+        : jt(jt_), walk(w), sV(sV_), sPhiM(pm), sPhiC(pc), sWM(wm), sWC(wc), sRaw(wide),
+          sLam(wide + 2 * T * RAWN), sA(wide + 2 * T * (RAWN + NQL)), tid(tid_), lane(tid_ & 63), wave(tid_ >> 6),
+          ge(tid_ % T), gk(tid_ / T)
+    {
+    }
+
+    // this lane's connectivity entry of tile g (node gk, or the vertex of coordinate item gk)
+    __device__ int32_t conn_of(int64_t g) const
+    {
+        int64_t lt;
+        const FusedArgs b = args_of<MULTI>(jt, job_of<MULTI>(jt, g, lt));
+        const int64_t p = min(lt * T + ge, b.in.n_elem - 1);
+        const int ci = gk < NP ? gk : (gk < NITEM ? (gk - NP) / D : 0);
+        return b.tconn[ci * b.in.n_elem + p];
+    }
+    __device__ void gather(int64_t g, int32_t node, double &d0, double &d1) const
+    {
+        int64_t lt;
+        const FusedArgs b = args_of<MULTI>(jt, job_of<MULTI>(jt, g, lt));
+        const CoeffDev &cm = b.in.cm, &cc = b.in.cc;
+        if (gk < NP) {
+            if (cm.kind == 1 || cc.kind == 1) d0 = (cm.kind == 1 ? cm.field : cc.field)[node];
+            if (cm.kind == 1 && cc.kind == 1 && cc.field != cm.field) d1 = cc.field[node];
+        } else if (gk < NITEM) {
+            d0 = b.in.coords[((gk - NP) % D) * b.in.n_nodes + node];
+        }
+    }
+    __device__ void put_raw(int buf, double d0, double d1) const
+    {
+        double *r = sRaw + (buf * T + ge) * RAWN;
+        if (gk < NP) {
+            r[DC + gk] = d0;
+            r[DC + NP + gk] = d1;
+        } else if (gk < NITEM) {
+            r[gk - NP] = d0;
+        }
+    }
+
+    // Lambda (and W) of tile g from its staged raw values, into buffer buf
+    __device__ void lambda(int64_t g, int buf) const
+    {
+        int64_t lt;
+        const FusedArgs b = args_of<MULTI>(jt, job_of<MULTI>(jt, g, lt));
+        const FormInputs &in = b.in;
+        const bool other = in.cc.kind == 1 && in.cm.kind == 1 && in.cc.field != in.cm.field;
+        bool ok = true;
+        for (int id = tid; id < T * (NQL + 1); id += NPT) {
+            const int e = id % T, which = id / T;
+            const int64_t p = lt * T + e;
+            const double *r = sRaw + (buf * T + e) * RAWN;
+            double x[D + 1][D];
+#pragma unroll
+            for (int v = 0; v <= D; ++v)
+#pragma unroll
+                for (int c = 0; c < D; ++c) x[v][c] = r[v * D + c];
+            double babs, A[NG];
+            geometry_from<D>(x, babs, A);
+            const bool live = p < in.n_elem;
+            if (which == NQL) {
+#pragma unroll
+                for (int gg = 0; gg < NG; ++gg) sA[(buf * T + e) * NG + gg] = live ? A[gg] : 0.0;
+                continue;
+            }
+            const bool mass = which < NQM;
+            const int q = mass ? which : which - NQM;
+            const CoeffDev &cf = mass ? in.cm : in.cc;
+            double v = 0.0;
+            if (live) {
+                double s;
+                if (cf.kind == 0) {
+                    s = cf.value;
+                } else if (cf.kind == 1) {
+                    const double *phi = mass ? sPhiM : sPhiC;
+                    const double *u = r + DC + (!mass && other ? NP : 0);
+                    double uh = 0.0;  // u_h(xhat_q) = phi_q^T u_e
+#pragma unroll
+                    for (int i = 0; i < NP; ++i) uh = fma(phi[q * NP + i], u[i], uh);
+                    s = apply_law(cf, uh);
+                } else {
+                    const int64_t eid = b.elem_order[p];
+                    s = apply_law(cf, cf.field[q * in.n_elem + eid]);
+                }
+                v = (mass ? sWM : sWC)[q] * s * babs;
+                ok &= isfinite(v);
+            }
+            sLam[(buf * T + e) * NQL + which] = v;
+        }
+        if (!ok) atomicOr(in.flags, 1);
+    }
+
+    // V_m^T = X_m^T Q_m^T and V_c^T = X_c^T Q_c^T of tile g (Lambda, W in buffer
+    // buf) for row blocks wave and wave + 8, into V buffer buf
+    __device__ void contract(const CT *gQ, int buf) const
+    {
+        const int j = lane >> 4, c16 = lane & 15;
+        const double *lam = sLam + (buf * T + c16) * NQL;
+        double lm[KSM], lc[MSC], A[NG];
+#pragma unroll
+        for (int m = 0; m < KSM; ++m) lm[m] = 4 * m + j < NQM ? lam[4 * m + j] : 0.0;
+#pragma unroll
+        for (int m = 0; m < MSC; ++m) lc[m] = 4 * m + j < NQC ? lam[NQM + 4 * m + j] : 0.0;
+#pragma unroll
+        for (int gg = 0; gg < NG; ++gg) A[gg] = sA[(buf * T + c16) * NG + gg];
+        // row blocks wave and wave + 8; a second block past the last one (waves 6
+        // and 7 of 14 blocks) repeats the last block and is not stored, which
+        // keeps the code free of branches and gives every SIMD four blocks
+        const int w = __builtin_amdgcn_readfirstlane(wave);
+        const int nb0 = w, nb1 = w + 8 < NB ? w + 8 : NB - 1;
+        typename MF::acc_t am[2], ac[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) am[u] = ac[u] = typename MF::acc_t{0, 0, 0, 0};
+        // fragments through a buffer resource: one lane offset per block, the
+        // k-step in the scalar offset
+        const __amdgpu_buffer_rsrc_t rq =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<CT *>(gQ), 0, int(sizeof(CT) * NSTEP * NB * 64), 0x00020000);
+        const int o0 = int(sizeof(CT)) * (nb0 * 64 + lane), o1 = int(sizeof(CT)) * (nb1 * 64 + lane);
+        auto ldq = [&](int off, int t) -> CT {
+            const int so = int(sizeof(CT)) * t * NB * 64;
+            if constexpr (sizeof(CT) == 8)
+                return __builtin_bit_cast(CT, __builtin_amdgcn_raw_buffer_load_b64(rq, off, so, 0));
+            else
+                return __builtin_bit_cast(CT, __builtin_amdgcn_raw_buffer_load_b32(rq, off, so, 0));
+        };
+        CT cur[CHS][2], nxt[CHS][2];
+        auto load = [&](int c, CT (&f)[CHS][2]) {
+#pragma unroll
+            for (int tt = 0; tt < CHS; ++tt) {
+                const int t = c * CHS + tt;
+                f[tt][0] = t < NSTEP ? ldq(o0, t) : CT(0);
+                f[tt][1] = t < NSTEP ? ldq(o1, t) : CT(0);
+            }
+        };
+        load(0, cur);
+#pragma unroll
+        for (int c = 0; c < NCHK; ++c) {
+            if (c + 1 < NCHK) load(c + 1, nxt);
+#pragma unroll
+            for (int tt = 0; tt < CHS; ++tt) {
+                const int t = c * CHS + tt;
+                if (t >= NSTEP) continue;
+                if (t < KSM) {  // mass: k = q
+                    const CT x = CT(lm[t]);
+                    am[0] = MF::step(x, cur[tt][0], am[0]);
+                    am[1] = MF::step(x, cur[tt][1], am[1]);
+                } else {  // conductivity: k = g NQP + q
+                    const int tc = t - KSM;
+                    const CT x = CT(lc[tc % MSC] * A[tc / MSC]);
+                    ac[0] = MF::step(x, cur[tt][0], ac[0]);
+                    ac[1] = MF::step(x, cur[tt][1], ac[1]);
+                }
+            }
+            if (c + 1 < NCHK) {
+#pragma unroll
+                for (int tt = 0; tt < CHS; ++tt) {
+                    cur[tt][0] = nxt[tt][0];
+                    cur[tt][1] = nxt[tt][1];
+                }
+            }
+        }
+        ST *bV = sV + buf * BUF_ELEMS;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int s = 16 * (u ? nb1 : nb0) + c16;
+            if (s < NS && (u == 0 || w + 8 < NB))
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int o = 2 * (s * (T + 1) + MF::row(lane, r));
+                    bV[o] = ST(am[u][r]);
+                    bV[o + 1] = ST(ac[u][r]);
+                }
+        }
+    }
+
+    __device__ void run(const CT *gQ) const
+    {
+        const int64_t step = walk.step;
+        int64_t g = walk.t;  // every workgroup of a persistent launch has at least one tile
+        int32_t cn;
+        {
+            const int32_t c0 = conn_of(g);
+            const int32_t c1 = walk.valid(g + step) ? conn_of(g + step) : 0;
+            double d0 = 0.0, d1 = 0.0, e0 = 0.0, e1 = 0.0;
+            gather(g, c0, d0, d1);
+            if (walk.valid(g + step)) gather(g + step, c1, e0, e1);
+            cn = walk.valid(g + 2 * step) ? conn_of(g + 2 * step) : 0;
+            put_raw(0, d0, d1);
+            lds_barrier();  // raw values of the first tile staged
+            lambda(g, 0);
+            if (walk.valid(g + step)) put_raw(1, e0, e1);
+            lds_barrier();  // Lambda of the first tile, raw values of the second staged
+        }
+        for (int it = 0; walk.valid(g); g += step, ++it) {
+            const int64_t g1 = g + step, g2 = g + 2 * step, g3 = g + 3 * step;
+            double r0 = 0.0, r1 = 0.0;
+            if (walk.valid(g2)) gather(g2, cn, r0, r1);  // its connectivity was loaded one tile ago
+            if (walk.valid(g3)) cn = conn_of(g3);
+            contract(gQ, it & 1);
+            if (walk.valid(g1)) lambda(g1, (it + 1) & 1);
+            if (walk.valid(g2)) put_raw(it & 1, r0, r1);
+            lds_barrier();  // tile g staged; buffers of tile g - 1 free
+        }
+    }
+};
+constexpr int kWidePrologueBarriers = 2;
 
 // LDS of the kernel: staged V (two buffers, both matrices), Q^T fragments,
-// basis values and weights of both rules (q-major).
-// With T = 16 (wide shapes: 3D P3) the four producer waves share one
-// element group and split its row blocks, and Q^T (too large for LDS) is read
-// from global memory, where it stays cached.
+// basis values and weights of both rules (q-major). With T = 16 (wide shapes:
+// 3D P3) Q^T (too large for LDS) is read from global memory, where it stays
+// cached, and the producers' staged raw values, Lambda and W follow.
 template <int D, int P, int NQM, int NQC, int PF, int T>
 struct WsLds {
     using ST = typename FormTraits<PF>::stage_t;
@@ -603,22 +854,25 @@ struct WsLds {
     static constexpr int NP = Shape<D, P>::NP, NS = Shape<D, P>::NS;
     static constexpr size_t v_bytes = ((4 * sizeof(ST) * NS * (T + 1) + 15) / 16) * 16;
     static constexpr size_t tab_doubles = size_t(NQM + NQC) * NP + NQM + NQC;
+    static constexpr size_t wide_doubles =
+        QLDS ? 0 : size_t(2) * T * ((D + 1) * D + 2 * NP + NQM + NQC + Shape<D, P>::NG);
     static size_t bytes(int64_t qfrag_vec16)
     {
-        return v_bytes + (QLDS ? size_t(qfrag_vec16) * 16 : 0) + tab_doubles * 8;
+        return v_bytes + (QLDS ? size_t(qfrag_vec16) * 16 : 0) + (tab_doubles + wide_doubles) * 8;
     }
 };
 
 template <int D, int P, int NQM, int NQC, int PF, int T, bool MULTI>
 __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
 {
-    static_assert(T == 16 * (kWsProducers / 64) || T == 16, "one 16-element group per producer wave, or one shared");
+    constexpr int NPT = ws_producers(T);
+    static_assert(T == 16 * (NPT / 64) || T == 16, "one 16-element group per producer wave, or T = 16");
     using S = Shape<D, P>;
     using ST = typename FormTraits<PF>::stage_t;
     using L = LaneQ<NQM, NQC, S::NG>;
     using LDS = WsLds<D, P, NQM, NQC, PF, T>;
     constexpr bool SPLIT = PF >= QXA_F16X2;
-    constexpr bool QLDS = LDS::QLDS;  // else: T = 16, waves split the row blocks, Q^T from global memory
+    constexpr bool QLDS = LDS::QLDS;  // else: T = 16, WideProducer, Q^T from global memory
     static_assert(QLDS || !SPLIT, "split forms need Q^T in LDS");
     constexpr int NB = (S::NS + 15) / 16;
     constexpr int NBW = QLDS ? NB : (NB + 3) / 4;  // row blocks per producer wave
@@ -654,7 +908,12 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
     if (tid < 4) sV[(tid >> 1) * BUF_ELEMS + 2 * T + (tid & 1)] = ST(0);
     const TileWalk walk(jt.n_tiles);
     lds_barrier();
-    if (tid < kWsProducers) {
+    if (tid < NPT) {
+      if constexpr (!QLDS) {
+        static_assert(WideProducer<D, P, NQM, NQC, PF, T, MULTI>::lds_doubles == LDS::wide_doubles, "LDS layout");
+        const WideProducer<D, P, NQM, NQC, PF, T, MULTI> wp(jt, walk, sV, sPhiM, sPhiC, sWM, sWC, sWC + NQC, tid);
+        wp.run(reinterpret_cast<const typename FormTraits<PF>::qplain_t *>(a0.Qfrag));
+      } else {
         const int j = lane >> 4, c16 = lane & 15;
         int32_t v[S::NP];
         RawElem<D, P> raw;
@@ -737,8 +996,9 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
             }
             lds_barrier();  // tile i staged; the consumers are done with buffer (i + 1) % 2
         }
+      }
     } else {
-        const int ct = tid - kWsProducers;
+        const int ct = tid - NPT;
         const int cw = 64 * __builtin_amdgcn_readfirstlane(ct >> 6);  // this wave's first lane (uniform)
         uint4 R[CH], Rn[CH];
         // unit of round q of chunk c: r0 + (c * CH + q) * NCT + ct, clamped to the tile
@@ -769,6 +1029,8 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
                 tile_range(a, tile, r0, r1);
                 load_chunk(a.rec, r0, r1, 0, R);
             }
+            if constexpr (!QLDS)  // the wide producers' pipeline fill
+                for (int k = 0; k < kWidePrologueBarriers; ++k) lds_barrier();
             lds_barrier();  // first tile staged
             for (int it = 1;; ++it, g += walk.step) {
                 int64_t tile, r0, r1;
