@@ -585,12 +585,10 @@ constexpr int ws_producers(int T) { return T == 16 ? 512 : 256; }
 // unit rounds per consumer chunk, sized so that one chunk holds all of a
 // tile's output units on Kuhn meshes (the next tile's are then loaded a whole
 // tile ahead): 2D P2 up to ~790 units per 64-element tile on 512 consumer
-// threads, 2D P3 ~2,520, 3D P2 ~1,700; 3D P3 (~2,100 per 16-element tile on
-// 256 threads) takes two chunks of 5
-constexpr int ws_chunk(int D, int P) { return D == 2 ? (P == 3 ? 5 : 2) : (P == 2 ? 4 : 5); }
-// consumer threads: 8 waves, or 4 for the T = 16 shape (12 waves in all, whose
-// register budget its producers need)
-constexpr int ws_consumers(int T) { return T == 16 ? 256 : 512; }
+// threads, 2D P3 ~2,520, 3D P2 ~1,700, 3D P3 ~2,100 per 16-element tile
+constexpr int ws_chunk(int D, int P) { return D == 2 ? (P == 3 ? 5 : 2) : 4; }
+// consumer threads: 8 waves
+constexpr int ws_consumers(int T) { return 512; }
 constexpr int ws_threads(int T) { return ws_producers(T) + ws_consumers(T); }
 
 // Producers of the T = 16 shape (3D P3: 210 symmetric rows, Q^T of 282 KB in
