@@ -581,8 +581,10 @@ qxa_status make_fused_args(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *s
     a.qinv_m = precision == QXA_F16X2 ? p->f16_qinv[0] : 1.0;
     a.qinv_c = precision == QXA_F16X2 ? p->f16_qinv[1] : 1.0;
     a.part = part;
+    // buffer stores address 31-bit byte offsets; larger arrays (or QXA_FLAT_STORES
+    // set, which tests use to cover that path on small meshes) take plain stores
     const int64_t lim = (int64_t(1) << 31) - 16;
-    a.buf_ok = 8 * p->nnz <= lim && 16 * p->n_partials <= lim;
+    a.buf_ok = 8 * p->nnz <= lim && 16 * p->n_partials <= lim && !std::getenv("QXA_FLAT_STORES");
     a.bytes_vals = a.buf_ok ? uint32_t(8 * p->nnz) : 0u;
     a.bytes_part = a.buf_ok ? uint32_t(16 * p->n_partials) : 0u;
     f = FixupArgs{p->n_fix, p->d_fix_target, p->d_fix_mirror, p->d_part_ptr, part, M, C};

@@ -266,3 +266,79 @@ def test_split_forms_rejected_on_vector_alu_path():
     with pytest.raises(qxa.QxaError) as ei:
         qxa.assemble(plan, w.mass_law, w.stiff_law, uf, uf, precision="bf16x2")
     assert ei.value.code == -6
+
+
+# shapes whose coefficient paths the cases above leave out: per-(q, e) values with a
+# lower-degree conductivity rule, two different nodal fields, one matrix only
+EXTRA_SHAPES = [(2, 3, 7), (3, 2, 4), (3, 3, 3)]
+
+
+@pytest.mark.parametrize("dim,order,N", EXTRA_SHAPES)
+def test_qpoint_values_with_lower_degree_stiffness_rule(dim, order, N):
+    qxa = _qxa()
+    _say("case qpoint", dim, order, N)
+    mesh = structured_mesh(dim, order, N, 0.2, seed=[11, dim, order])
+    rm, rc = rule(dim, 2 * order), rule(dim, 2 * order - 2)
+    ne = mesh["conn"].shape[1]
+    rng = np.random.default_rng([12, dim, order])
+    sm = rng.uniform(0.5, 2.0, size=(rm[1].size, ne))
+    sc = rng.uniform(-0.5, 0.5, size=(rc[1].size, ne))
+    m = qxa.Mesh(dim, order, mesh["coords"], mesh["conn"])
+    plan = qxa.Plan(m, rm, rc)
+    law_c = ("exp", 0.0, 1.0)
+    M, Cv = qxa.assemble(plan, ("identity",), law_c, torch.tensor(sm, device="cuda"),
+                         torch.tensor(sc, device="cuda"), qpoint=True)
+    qxa.sync(plan)
+    rpo, cio, Mo, Co = oracle.assemble(mesh, rm, rc, ("identity",), law_c, qpoint_m=sm, qpoint_c=sc)
+    assert row_scaled_error(M.cpu().numpy(), Mo, rpo) <= 1e-12
+    assert row_scaled_error(Cv.cpu().numpy(), Co, rpo) <= 1e-12
+
+
+@pytest.mark.parametrize("dim,order,N", EXTRA_SHAPES)
+def test_two_nodal_fields_and_single_matrix(dim, order, N):
+    qxa = _qxa()
+    from workloads.fields import gaussian_random_field
+    _say("case two fields", dim, order, N)
+    mesh = structured_mesh(dim, order, N, 0.2, seed=[13, dim, order])
+    um = gaussian_random_field(mesh["coords"], 16, np.random.default_rng([14, dim]), length=0.3)
+    uc = gaussian_random_field(mesh["coords"], 16, np.random.default_rng([15, dim]), length=0.2)
+    r = rule(dim, 2 * order)
+    law_m, law_c = ("poly2", 1.0, 0.2, 0.1), ("exp", 0.0, 1.0)
+    m = qxa.Mesh(dim, order, mesh["coords"], mesh["conn"])
+    plan = qxa.Plan(m, r)
+    fm, fc = torch.tensor(um, device="cuda"), torch.tensor(uc, device="cuda")
+    M, Cv = qxa.assemble(plan, law_m, law_c, fm, fc)
+    M1, _ = qxa.assemble(plan, law_m, law_c, fm, fc, want_c=False)
+    _, C1 = qxa.assemble(plan, law_m, law_c, fm, fc, want_m=False)
+    qxa.sync(plan)
+    rpo, cio, Mo, Co = oracle.assemble(mesh, r, r, law_m, law_c, um, uc)
+    assert row_scaled_error(M.cpu().numpy(), Mo, rpo) <= 1e-12
+    assert row_scaled_error(Cv.cpu().numpy(), Co, rpo) <= 1e-12
+    assert torch.equal(M.view(torch.int64), M1.view(torch.int64))
+    assert torch.equal(Cv.view(torch.int64), C1.view(torch.int64))
+
+
+@pytest.mark.parametrize("dim,order,N", [(2, 2, 9), (2, 3, 7), (3, 2, 4), (3, 3, 3)])
+def test_plain_store_path_equals_buffer_store_path(dim, order, N, monkeypatch):
+    """The consumers' plain-store path (arrays past 2^31 bytes) on a small mesh, forced
+    through QXA_FLAT_STORES: the same bits as the buffer-store path."""
+    qxa = _qxa()
+    from workloads.fields import gaussian_random_field
+    _say("case flat stores", dim, order, N)
+    mesh = structured_mesh(dim, order, N, 0.2, seed=[16, dim, order])
+    u = gaussian_random_field(mesh["coords"], 16, np.random.default_rng([17, dim]), length=0.3)
+    r = rule(dim, 2 * order)
+    m = qxa.Mesh(dim, order, mesh["coords"], mesh["conn"])
+    plan = qxa.Plan(m, r)
+    uf = torch.tensor(u, device="cuda")
+    law_m, law_c = ("poly2", 1.0, 0.1, 0.0), ("exp", 0.0, 1.0)
+    M, Cv = qxa.assemble(plan, law_m, law_c, uf, uf)
+    qxa.sync(plan)
+    monkeypatch.setenv("QXA_FLAT_STORES", "1")
+    M2, C2 = qxa.assemble(plan, law_m, law_c, uf, uf)
+    qxa.sync(plan)
+    monkeypatch.delenv("QXA_FLAT_STORES")
+    assert torch.equal(M.view(torch.int64), M2.view(torch.int64))
+    assert torch.equal(Cv.view(torch.int64), C2.view(torch.int64))
+    rpo, cio, Mo, Co = oracle.assemble(mesh, r, r, law_m, law_c, u, u)
+    assert row_scaled_error(M2.cpu().numpy(), Mo, rpo) <= 1e-12
