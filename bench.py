@@ -346,6 +346,28 @@ def main():
     plan.set_timing(False)
     kern = {k: v["ms"] / v["n"] for k, v in rep.items()}
     dom = max(kern, key=kern.get)
+
+    # single assemblies between events: warm, and after writing 1 GiB so that the
+    # 256 MB MALL holds none of the assembly's data (median, p10, p90 of the reps)
+    def single_reps(n, flush):
+        scratch = torch.empty(1 << 27, dtype=torch.float64, device=dev) if flush else None
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ts = []
+        for k in range(n):
+            if flush:
+                scratch.fill_(float(k))
+            a.record(stream)
+            step()
+            b.record(stream)
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+        del scratch
+        q = np.percentile(ts, [10, 50, 90])
+        return {"reps": n, "p10_ms": float(q[0]), "median_ms": float(q[1]), "p90_ms": float(q[2])}
+
+    n_single = max(1, min(50, args.steps))
+    single = {"warm": single_reps(n_single, False), "mall_flushed": single_reps(n_single, True)}
+    qxa.sync(plan, stream)
     ab = algorithmic_bytes(dom, w, plan, mesh)
     achieved = ab / (kern[dom] * 1e-3) / 1e9
     entries = 2 * plan.n_elem * plan.n_p ** 2
@@ -378,6 +400,7 @@ def main():
                      "algorithmic_bytes": ab, "kernel_ms": kern[dom]},
         "path_floor": {"bytes": fb, "frac_of_hbm_peak": fb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "kernels_ms": kern,
+        "single_assembly": single,
         "plan_build_s": plan_s,
         "wall_s_timed_region": wall,
         "cpu_baseline": cpu,
