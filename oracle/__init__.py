@@ -66,6 +66,9 @@ def _load():
         lib.oracle_element_matrices.argtypes = common + [C.c_int64, _I64, _D, _D]
         lib.oracle_qpoint_coeff.argtypes = [C.c_int, C.c_int, C.c_int64, _I32, C.c_int, _D, C.POINTER(_Coeff),
                                             C.c_int64, _I64, _D]
+        lib.oracle_mass_tensor_product.argtypes = [C.c_int, C.c_int, C.c_int64, _D, C.c_int64, _I32, C.c_int, _D,
+                                                   _D, C.POINTER(_Coeff), _D, _I64, _I32, _D, C.c_int,
+                                                   C.POINTER(C.c_int64)]
         _lib = lib
     return _lib
 
@@ -219,3 +222,23 @@ def qpoint_coeff(mesh, elems, rule, law, field=None):
     if rc:
         raise ValueError("oracle_qpoint_coeff failed")
     return out.reshape(-1, w.size)
+
+
+def mass_tensor_product(mesh, rule, law_dm, u, v, nthreads=0):
+    """The mass tensor of Section 5 (M_ijk = int m'(u_h) phi_i phi_j phi_k) contracted with
+    the nodal vector v in its second mode, in the CSR pattern: (row_ptr, col_idx, values).
+    law_dm is the law of m' applied to the interpolated field u."""
+    row_ptr, col_idx = pattern(mesh)
+    out = np.zeros(col_idx.size)
+    conn = np.ascontiguousarray(mesh["conn"], dtype=np.int32)
+    coords = np.ascontiguousarray(mesh["coords"], dtype=np.float64)
+    pts, w = (np.ascontiguousarray(a, dtype=np.float64) for a in rule)
+    c, keep = _coeff(law_dm, u)
+    vv = np.ascontiguousarray(v, dtype=np.float64)
+    bad = C.c_int64(-1)
+    rc = _load().oracle_mass_tensor_product(mesh["dim"], mesh["order"], coords.shape[1], coords.reshape(-1),
+                                            conn.shape[1], conn.reshape(-1), w.size, pts.reshape(-1), w,
+                                            C.byref(c), vv, row_ptr, col_idx, out, int(nthreads), C.byref(bad))
+    if rc:
+        raise ValueError(f"oracle mass_tensor_product failed ({rc}), element {bad.value}")
+    return row_ptr, col_idx, out

@@ -684,3 +684,91 @@ int oracle_qpoint_coeff(int dim, int P, int64_t n_e, const int32_t *conn, int nq
         for (int q = 0; q < nq; ++q) out[k * nq + q] = coeff_at(c, phi + (size_t)q * n, n, conn, n_e, elems[k], q);
     return 0;
 }
+
+/*
+ * Mass tensor of Section 5 contracted with a nodal vector v in its second mode:
+ *   M_ijk = sum_e sum_q w_q m'_q phi_i phi_j phi_k |det B_e|,
+ *   (M o_2 v)_ik = sum_j M_ijk v_j.
+ * Per element the local tensor (n_p^3 entries, phi_q (x) phi_q (x) phi_q weighted
+ * by lambda_q = w_q m'_q |det B_e|) is formed in full, then contracted with the
+ * element's entries of v; the local matrices are added into the CSR pattern like
+ * the mass matrix. cdm carries m' (kind 1: law of the interpolated nodal field).
+ */
+static int element_abs_det(const refdata *R, const double *coords, int64_t n_nodes, const int32_t *conn, int64_t n_e,
+                           int64_t e, double *adet)
+{
+    int d = R->dim;
+    double B[MAXD * MAXD], X[MAXD * MAXD];
+    int32_t v0 = conn[e];
+    double maxedge = 0.0;
+    for (int c = 0; c < d; ++c) {
+        int32_t vc = conn[(size_t)(c + 1) * n_e + e];
+        double len2 = 0.0;
+        for (int r = 0; r < d; ++r) {
+            double t = coords[(size_t)r * n_nodes + vc] - coords[(size_t)r * n_nodes + v0];
+            B[r * d + c] = t;
+            len2 += t * t;
+        }
+        if (len2 > maxedge) maxedge = len2;
+    }
+    for (int i = 0; i < d * d; ++i) X[i] = (i % (d + 1) == 0) ? 1.0 : 0.0;
+    double det = gauss_solve(d, B, d, X);
+    *adet = fabs(det);
+    return *adet > 1e-14 * pow(sqrt(maxedge), d) ? 0 : -3;
+}
+
+int oracle_mass_tensor_product(int dim, int P, int64_t n_nodes, const double *coords, int64_t n_e, const int32_t *conn,
+                               int nq, const double *pts, const double *w, const oracle_coeff *cdm, const double *v,
+                               const int64_t *row_ptr, const int32_t *col_idx, double *Tv, int nthreads,
+                               int64_t *bad_elem)
+{
+    refdata R;
+    if (ref_setup(&R, dim, P, nq, pts, w, nq, pts, w)) return -1;
+    int n = R.n;
+    double *Tbuf = (double *)malloc(sizeof(double) * (size_t)n_e * n * n);
+    double *dummy = (double *)malloc(sizeof(double) * (size_t)(row_ptr[n_nodes] + 1));
+    if (!Tbuf || !dummy) {
+        free(Tbuf);
+        free(dummy);
+        return -5;
+    }
+    int err = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(static)
+#endif
+    for (int64_t e = 0; e < n_e; ++e) {
+        double adet, Me[MAXP * MAXP * MAXP];
+        if (element_abs_det(&R, coords, n_nodes, conn, n_e, e, &adet)) {
+#ifdef _OPENMP
+#pragma omp critical
+#endif
+            {
+                if (!err || e < *bad_elem) *bad_elem = e;
+                err = -3;
+            }
+            continue;
+        }
+        for (int t = 0; t < n * n * n; ++t) Me[t] = 0.0;
+        for (int q = 0; q < nq; ++q) {
+            const double *ph = R.phi_m + (size_t)q * n;
+            double lam = w[q] * coeff_at(cdm, ph, n, conn, n_e, e, q) * adet;
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j)
+                    for (int k = 0; k < n; ++k) Me[(i * n + j) * n + k] += lam * ph[i] * ph[j] * ph[k];
+        }
+        double *T = Tbuf + (size_t)e * n * n;
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k) {
+                double s = 0.0;
+                for (int j = 0; j < n; ++j) s += Me[(i * n + j) * n + k] * v[conn[(size_t)j * n_e + e]];
+                T[i * n + k] = s;
+            }
+    }
+    if (!err)
+        err = assemble_rows(&R, coords, n_nodes, conn, n_e, cdm, cdm, n_nodes, NULL, row_ptr, col_idx, Tv, dummy, Tbuf,
+                            Tbuf, nthreads, bad_elem);
+    free(Tbuf);
+    free(dummy);
+    return err;
+}
