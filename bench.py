@@ -264,6 +264,90 @@ def reassembly(args, n_steps=20):
     print(json.dumps(out))
 
 
+def tangent(args):
+    """Mass tensor of the Newton Jacobian contracted with a nodal vector (Section 5):
+    M o_2 w with m(u) = 1 + 0.5 u^2 (m' = u), w = u - u_prev, on the workload's mesh.
+    One step = the per-node coefficient m'(u_h) w_h (qxa_coeff_product) plus the
+    mass-matrix assembly of that coefficient into the CSR pattern. Prints one JSON line."""
+    import numpy as np
+    import torch
+    import paper_2204_03893_amd as qxa
+    from workloads import WORKLOADS, make_inputs
+    w = WORKLOADS[args.workload]
+    mesh, rule, u0 = make_inputs(w)
+    _, _, u1 = make_inputs(w, stream=1)
+    dev = torch.device("cuda", 0)
+    m = qxa.Mesh(w.dim, w.order, mesh["coords"], mesh["conn"])
+    plan = qxa.Plan(m, rule)
+    u = torch.tensor(u0, device=dev)
+    wv = torch.tensor(u0 - u1, device=dev)
+    law_dm = ("poly2", 0.0, 1.0, 0.0)
+    stream = torch.cuda.current_stream()
+    T = torch.empty(plan.nnz, dtype=torch.float64, device=dev)
+    S = torch.empty((plan.n_q_mass, plan.n_elem), dtype=torch.float64, device=dev)
+
+    def step():
+        qxa.mass_tensor_product(plan, law_dm, u, wv, T=T, S=S, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    qxa.sync(plan, stream)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    qxa.sync(plan, stream)
+    ms = ev0.elapsed_time(ev1) / args.steps
+    # the coefficient kernel alone, then the assembly kernels' own events
+    ev0.record(stream)
+    for _ in range(args.steps):
+        qxa.coeff_product(plan, law_dm, u, wv, S=S, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    k_coeff = ev0.elapsed_time(ev1) / args.steps
+    plan.set_timing(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    rep = plan.timing_report()
+    plan.set_timing(False)
+    kern = {k: v["ms"] / v["n"] for k, v in rep.items()}
+    kern["coeff_product"] = k_coeff
+    ne, npl, nn, nq = plan.n_elem, plan.n_p, plan.n_nodes, plan.n_q_mass
+    n_vert = int(mesh["vertex_mask"].sum())
+    ab = {"coeff_product": 4 * npl * ne + 16 * nn + 8 * nq * ne,
+          "fused": 4 * npl * ne + 8 * w.dim * n_vert + 8 * nq * ne + 4 * ne * npl * npl + 8 * plan.nnz,
+          "fixup": 8 * plan.n_partials + 16 * plan.n_shared}
+    dom = max(kern, key=kern.get)
+    achieved = ab[dom] / (kern[dom] * 1e-3) / 1e9
+    entries = ne * npl ** 2
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        threads = min(os.cpu_count() or 1, 16)
+        t0 = time.perf_counter()
+        reps = 0
+        while reps < 3 and (reps == 0 or time.perf_counter() - t0 < 10):
+            oracle.mass_tensor_product(mesh, rule, law_dm, u0, u0 - u1, nthreads=threads)
+            reps += 1
+        tot = time.perf_counter() - t0
+        cpu = {"value": entries * reps / tot, "unit": "entries/s", "cores": threads, "kind": "oracle",
+               "sample": f"{reps} full tensor products of the same workload ({w.name}), {tot:.1f} s"}
+    out = {"metric": "mass-tensor product entries assembled/sec", "value": entries / (ms * 1e-3),
+           "unit": "entries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": w.name + " tensor product", "n_elem": ne, "nnz": plan.nnz,
+                      "law_dm": list(law_dm), "entries_per_step": entries},
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+                        "algorithmic_bytes": ab[dom], "kernel_ms": kern[dom]},
+           "kernels_ms": kern, "cpu_baseline": cpu}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -274,7 +358,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) to calibrate HBM byte counters")
-    ap.add_argument("--mode", choices=("assemble", "serving", "reassembly"), default="assemble")
+    ap.add_argument("--mode", choices=("assemble", "serving", "reassembly", "tangent"), default="assemble")
     ap.add_argument("--requests", type=int, default=1000, help="serving: requests per offered load")
     ap.add_argument("--pool", type=int, default=48, help="serving: resident meshes")
     ap.add_argument("--max-elements", type=float, default=3e5, help="serving: largest mesh (elements)")
@@ -302,6 +386,9 @@ def main():
         return
     if args.mode == "reassembly":
         reassembly(args)
+        return
+    if args.mode == "tangent":
+        tangent(args)
         return
 
     import paper_2204_03893_amd as qxa

@@ -187,6 +187,27 @@ qxa_status qxa_element_matrices(qxa_plan plan, const qxa_coeff *mass, const qxa_
                                 double *Vm, double *Vc, void *stream);
 
 /*
+ * Coefficient of the mass tensor contracted with a nodal vector (Section 5, the
+ * Newton Jacobian): the mass tensor M_ijk = int m'(u_h) phi_i phi_j phi_k
+ * contracted with v in its second mode, (M o_2 v)_ik = int m'(u_h) v_h phi_i phi_k,
+ * is the mass matrix of the coefficient s = m'(u_h) v_h; the local tensor
+ * (Phi (.) Phi (.) Phi) Lambda contracted with v_e equals (Phi (.) Phi)(Lambda * Phi^T v_e).
+ * This call evaluates s at the quadrature nodes of one of the plan's rules:
+ *   S[q][e] = law(u_h(xhat_q)) * v_h(xhat_q),  u = c->field, v nodal,
+ * for every element in mesh order. Passed to qxa_assemble as a QXA_COEFF_QPOINT
+ * mass coefficient with the identity law, S gives M o_2 v in the plan's CSR
+ * pattern (symmetric, as M is symmetric in all modes).
+ * rule: 0 = the plan's mass rule, 1 = its stiffness rule. c: kind
+ * QXA_COEFF_NODAL, its law that of m' (m = a0 + a1 s + a2 s^2 has m' = a1 + 2 a2 s,
+ * law poly2 (a1, 2 a2, 0)). v: device [n_nodes]. S: caller-owned device
+ * [n_q][n_elem], written asynchronously on `stream`. Errors: QXA_E_INVALID for
+ * null pointers, a bad rule index, another kind or a plan owned by a server; a
+ * non-finite s is reported by qxa_sync as QXA_E_NONFINITE. The conductivity
+ * tensor contracted in its second mode is not symmetric and is not provided.
+ */
+qxa_status qxa_coeff_product(qxa_plan plan, int rule, const qxa_coeff *c, const double *v, double *S, void *stream);
+
+/*
  * Per-kernel timing with HIP events recorded on the launch stream around every
  * kernel this plan launches (off by default). qxa_plan_timing_report waits for
  * the recorded events, writes a JSON object

@@ -93,6 +93,7 @@ def lib():
         L.qxa_plan_check_host.argtypes = [ci, ci, i64, vp, i64, vp, C.POINTER(i64), C.POINTER(i64)]
         L.qxa_assemble.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), ci, vp, vp, vp]
         L.qxa_element_matrices.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), ci, vp, vp, vp]
+        L.qxa_coeff_product.argtypes = [vp, ci, C.POINTER(_Coeff), vp, vp, vp]
         L.qxa_sync.argtypes = [vp, vp]
         L.qxa_plan_set_timing.argtypes = [vp, ci]
         L.qxa_graph_create.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), ci, vp, vp, C.POINTER(vp)]
@@ -198,6 +199,8 @@ class Plan:
         self.n_nodes = int(info.n_nodes)
         self.n_elem = int(info.n_elem)
         self.n_p = int(info.n_p)
+        self.n_q_mass = int(info.n_q_mass)
+        self.n_q_stiff = int(info.n_q_stiff)
         self.build_ms = float(info.build_ms)
         self.device_bytes = int(info.device_bytes)
         self.n_tiles = int(info.n_tiles)
@@ -295,6 +298,28 @@ def assemble(plan: Plan, law_m, law_c, field_m=None, field_c=None, precision="fp
     check(lib().qxa_assemble(plan.handle, C.byref(cm), C.byref(cc), _precision(precision),
                              _ptr(M if want_m else None), _ptr(Cv if want_c else None), _stream_ptr(stream)))
     return M, Cv
+
+
+def coeff_product(plan: Plan, law, u, v, rule="mass", S=None, stream=None):
+    """S[q][e] = law(u_h(x_q)) * v_h(x_q) at the quadrature nodes of the plan's mass (or
+    stiffness) rule: the coefficient of the mass tensor contracted with v (qxa_coeff_product)."""
+    import torch
+    which = {"mass": 0, "stiffness": 1}[rule]
+    nq = plan.n_q_mass if which == 0 else plan.n_q_stiff
+    if S is None:
+        S = torch.empty((nq, plan.n_elem), dtype=torch.float64, device=torch.device("cuda", plan.mesh.device))
+    c, keep = make_coeff(law, u)
+    check(lib().qxa_coeff_product(plan.handle, which, C.byref(c), _ptr(v), _ptr(S), _stream_ptr(stream)))
+    return S
+
+
+def mass_tensor_product(plan: Plan, law_dm, u, v, T=None, S=None, stream=None):
+    """The mass tensor of the Newton Jacobian (M_ijk = int m'(u_h) phi_i phi_j phi_k)
+    contracted with v in its second mode, in the plan's CSR pattern: the mass matrix of
+    the per-node coefficient law_dm(u_h) * v_h. Returns the value array (and S)."""
+    S = coeff_product(plan, law_dm, u, v, "mass", S=S, stream=stream)
+    T, _ = assemble(plan, ("identity",), ("const", 1.0), S, None, M=T, stream=stream, want_c=False, qpoint=True)
+    return T, S
 
 
 def element_matrices(plan: Plan, law_m, law_c, field_m=None, field_c=None, precision="fp64", stream=None,

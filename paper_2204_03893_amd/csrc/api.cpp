@@ -649,6 +649,28 @@ qxa_status qxa_element_matrices(qxa_plan p, const qxa_coeff *mass, const qxa_coe
     return QXA_OK;
 }
 
+qxa_status qxa_coeff_product(qxa_plan p, int rule, const qxa_coeff *c, const double *v, double *S, void *stream)
+{
+    if (!p || !c || !v || !S) return fail(QXA_E_INVALID, "null argument");
+    if (rule != 0 && rule != 1) return fail(QXA_E_INVALID, "rule: 0 (mass rule) or 1 (stiffness rule)");
+    if (!p->d_flags) return fail(QXA_E_INVALID, "plan is owned by a server");
+    if (c->kind != QXA_COEFF_NODAL) return fail(QXA_E_INVALID, "the first factor is a nodal field through a law");
+    CoeffProductArgs a{};
+    qxa_status st = to_coeff(c, a.c, "first factor");
+    if (st) return st;
+    if (p->mesh->n_elem == 0) return QXA_OK;
+    QXA_HIP(hipSetDevice(p->mesh->device));
+    a.n_elem = p->mesh->n_elem;
+    a.conn = p->mesh->d_conn;
+    a.phi = p->d_tables + (rule == 0 ? p->off_phim : p->off_phic);
+    a.v = v;
+    a.S = S;
+    a.flags = p->d_flags;
+    const int nq = rule == 0 ? p->ref.nq_m : p->ref.nq_c;
+    QXA_HIP(launch_coeff_product(a, p->ref.dim, p->ref.order, nq, reinterpret_cast<hipStream_t>(stream)));
+    return QXA_OK;
+}
+
 qxa_status qxa_plan_set_timing(qxa_plan p, int enable)
 {
     if (!p) return fail(QXA_E_INVALID, "null plan");

@@ -99,7 +99,18 @@ struct ExpandArgs {
     double *Vm, *Vc;        // [np*np][n_elem]
 };
 
+struct CoeffProductArgs {
+    int64_t n_elem;
+    const int32_t *conn;  // [np][n_elem]
+    const double *phi;    // [np][nq] basis values of the rule
+    CoeffDev c;           // law of the first factor; c.field = u [n_nodes]
+    const double *v;      // [n_nodes]
+    double *S;            // [nq][n_elem]
+    int *flags;
+};
+
 bool form_supported(int D, int P, int nqm, int nqc);
+hipError_t launch_coeff_product(const CoeffProductArgs &a, int D, int P, int nq, hipStream_t st);
 hipError_t launch_form(const FormArgs &a, int D, int P, int nqm, int nqc, int precision, hipStream_t st);
 hipError_t launch_expand(const ExpandArgs &a, hipStream_t st);
 hipError_t launch_fused(const JobTable &jt, int D, int P, int nqm, int nqc, int precision, hipStream_t st);

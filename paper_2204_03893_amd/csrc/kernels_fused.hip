@@ -185,10 +185,13 @@ __global__ __launch_bounds__(T) void fused_kernel(JobTable jt)
         for (int i = 0; i < S::NP; ++i) v[i] = a.tconn[i * ne + p];
         const int64_t eid = (a.in.cm.kind == 2 || a.in.cc.kind == 2) ? int64_t(a.elem_order[p]) : p;
         if (!element_setup<D, P, NQM, NQC>(a.in, v, eid, A, lm, lc)) atomicOr(a.in.flags, 1);
-        contract_mass<S::NS, NQM>(reinterpret_cast<const CT *>(a.Qm), lm,
-                                  [&](int s, double x) { sVm[s * (T + 1) + lane] = x; });
-        contract_stiff<P, S::NS, NQC, S::NG>(reinterpret_cast<const CT *>(a.Qc), lc, A,
-                                             [&](int s, double x) { sVc[s * (T + 1) + lane] = x; });
+        // a matrix that is not requested is not formed (its staged values are never stored)
+        if (a.M)
+            contract_mass<S::NS, NQM>(reinterpret_cast<const CT *>(a.Qm), lm,
+                                      [&](int s, double x) { sVm[s * (T + 1) + lane] = x; });
+        if (a.C)
+            contract_stiff<P, S::NS, NQC, S::NG>(reinterpret_cast<const CT *>(a.Qc), lc, A,
+                                                 [&](int s, double x) { sVc[s * (T + 1) + lane] = x; });
     }
     lds_barrier();
     tile_reduce(pf, a, tile, sVm, sVc, T);
@@ -343,63 +346,6 @@ __device__ __forceinline__ void contract_group_plain(const CT *sQ, XK &&xk, ST *
         for (int nb = 0; nb < NBW; ++nb)
             if (NBW == NB || nb0 + nb < NB)
                 acc[nb] = MF::step(x, sQ[(ks * NB + nb0 + nb) * 64 + lane], acc[nb]);
-    }
-#pragma unroll
-    for (int nb = 0; nb < NBW; ++nb) {
-        const int s = 16 * (nb0 + nb) + c16;
-        if (s < NS)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) sV[STRIDE * (s * (T + 1) + col0 + MF::row(lane, r))] = ST(acc[nb][r]);
-    }
-}
-
-// Conductivity contraction with Q^T read from global memory (shapes whose
-// Q^T does not fit in LDS). The K order k = g * NQP + q is walked in chunks of
-// CH k-steps (CH divides NQP / 4, so a chunk has one g) in a rolled loop; the
-// fragments of chunk c + 1 are loaded while chunk c is multiplied. lc[m] holds
-// this lane's node q = 4 m + j.
-template <typename CT, int NQP, int NG, int NB, int NS, int T, typename ST, int STRIDE, int NBW>
-__device__ __forceinline__ void contract_group_gm(const CT *gQ, const double *lc, const double *A, ST *sV, int lane,
-                                                  int col0, int nb0)
-{
-    using MF = Mfma<CT>;
-    constexpr int MS = NQP / 4;                    // k-steps per metric component g
-    constexpr int CH = MS % 3 == 0 ? 3 : MS;       // k-steps per chunk
-    constexpr int CPG = MS / CH, NCH = NG * CPG;  // chunks per g, chunks
-    const int c16 = lane & 15;
-    typename MF::acc_t acc[NBW];
-#pragma unroll
-    for (int nb = 0; nb < NBW; ++nb) acc[nb] = typename MF::acc_t{0, 0, 0, 0};
-    CT cur[CH][NBW], nxt[CH][NBW];
-    auto load = [&](int c, CT (&f)[CH][NBW]) {
-#pragma unroll
-        for (int t = 0; t < CH; ++t)
-#pragma unroll
-            for (int nb = 0; nb < NBW; ++nb)
-                f[t][nb] = nb0 + nb < NB ? gQ[((c * CH + t) * NB + nb0 + nb) * 64 + lane] : CT(0);
-    };
-    load(0, cur);
-#pragma unroll 1
-    for (int c = 0; c < NCH; ++c) {
-        if (c + 1 < NCH) load(c + 1, nxt);
-        const int g = c / CPG, part = c % CPG;
-        double ag = A[0];
-#pragma unroll
-        for (int h = 1; h < NG; ++h) ag = g == h ? A[h] : ag;
-#pragma unroll
-        for (int t = 0; t < CH; ++t) {
-            double lv = lc[t];
-#pragma unroll
-            for (int h = 1; h < CPG; ++h) lv = part == h ? lc[h * CH + t] : lv;
-            const CT x = CT(lv * ag);
-#pragma unroll
-            for (int nb = 0; nb < NBW; ++nb)
-                if (nb0 + nb < NB) acc[nb] = MF::step(x, cur[t][nb], acc[nb]);
-        }
-#pragma unroll
-        for (int t = 0; t < CH; ++t)
-#pragma unroll
-            for (int nb = 0; nb < NBW; ++nb) cur[t][nb] = nxt[t][nb];
     }
 #pragma unroll
     for (int nb = 0; nb < NBW; ++nb) {
@@ -873,7 +819,6 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
     constexpr bool QLDS = LDS::QLDS;  // else: T = 16, WideProducer, Q^T from global memory
     static_assert(QLDS || !SPLIT, "split forms need Q^T in LDS");
     constexpr int NB = (S::NS + 15) / 16;
-    constexpr int NBW = QLDS ? NB : (NB + 3) / 4;  // row blocks per producer wave
     constexpr int KM = NQM, KC = L::NQP * S::NG;  // conductivity K order: k = g * NQP + q
     constexpr int BUF_ELEMS = 2 * S::NS * (T + 1);  // one buffer: [NS][T + 1] pairs (V_m, V_c)
     constexpr int NCT = ws_consumers(T);
@@ -920,7 +865,7 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
             const FusedArgs b = args_of<MULTI>(jt, job_of<MULTI>(jt, g, lt));
             // lanes past the last element read the last element (unconditional loads keep
             // the loads of one call in flight together)
-            const int64_t pp = min(lt * T + (QLDS ? 16 * wave : 0) + c16, b.in.n_elem - 1);
+            const int64_t pp = min(lt * T + 16 * wave + c16, b.in.n_elem - 1);
 #pragma unroll
             for (int i = 0; i < S::NP; ++i) v[i] = b.tconn[i * b.in.n_elem + pp];
         };
@@ -937,7 +882,7 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
             int64_t tile;
             const FusedArgs a = args_of<MULTI>(jt, job_of<MULTI>(jt, g, tile));
             const int64_t ne = a.in.n_elem;
-            const int64_t p = tile * T + (QLDS ? 16 * wave : 0) + c16;  // this lane's element (4 lanes each)
+            const int64_t p = tile * T + 16 * wave + c16;  // this lane's element (4 lanes each)
             double A[S::NG], lm[L::MM], lc[L::MC];
             if (p < ne) {
                 const int64_t eid = (a.in.cm.kind == 2 || a.in.cc.kind == 2) ? int64_t(a.elem_order[p]) : p;
@@ -952,7 +897,7 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
                 for (int m = 0; m < L::MC; ++m) lc[m] = 0.0;
             }
             const int64_t gn = g + walk.step;
-            if (QLDS && walk.valid(gn)) {
+            if (walk.valid(gn)) {
                 gather(gn);  // its connectivity was loaded one tile ago
                 if (walk.valid(gn + walk.step)) load_conn(gn + walk.step);
             }
@@ -960,18 +905,15 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
             // V_m^T = X_m^T Q_m^T with X_m = Lambda_m; V_c^T = X_c^T Q_c^T with X_c = Lambda_c (.) W
             if constexpr (!SPLIT) {
                 using CT = typename FormTraits<PF>::qplain_t;
-                const CT *q = reinterpret_cast<const CT *>(QLDS ? static_cast<const void *>(sQraw) : a.Qfrag);
+                const CT *q = reinterpret_cast<const CT *>(sQraw);
                 // k = 4 ks + j: mass node q = k, conductivity (g, q) = divmod(4 ks, NQP) + (0, j)
                 auto xm = [&](int ks) { return lm[ks]; };
                 auto xc = [&](int ks) { return lc[((4 * ks) % L::NQP) / 4] * A[(4 * ks) / L::NQP]; };
-                const int col0 = QLDS ? 16 * wave : 0, nb0 = QLDS ? 0 : NBW * wave;
-                contract_group_plain<CT, KM, NB, S::NS, T, ST, 2, NBW>(q, xm, bVm, lane, col0, nb0);
-                if constexpr (QLDS)
-                    contract_group_plain<CT, KC, NB, S::NS, T, ST, 2, NBW>(q + ((KM + 3) / 4) * NB * 64, xc, bVc,
-                                                                          lane, col0, nb0);
-                else
-                    contract_group_gm<CT, L::NQP, S::NG, NB, S::NS, T, ST, 2, NBW>(q + ((KM + 3) / 4) * NB * 64, lc,
-                                                                                  A, bVc, lane, col0, nb0);
+                // a matrix that is not requested is not formed (its staged values are never stored)
+                if (a.M) contract_group_plain<CT, KM, NB, S::NS, T, ST, 2>(q, xm, bVm, lane, 16 * wave);
+                if (a.C)
+                    contract_group_plain<CT, KC, NB, S::NS, T, ST, 2>(q + ((KM + 3) / 4) * NB * 64, xc, bVc, lane,
+                                                                     16 * wave);
             } else {
                 const uint4 *q = reinterpret_cast<const uint4 *>(sQraw);
                 constexpr int NC = Split<PF>::NC;
@@ -984,13 +926,11 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
                     const int u = t / S::NG, g = t % S::NG, m = L::QPSC * ks + u;
                     return u < L::QPSC && m < L::MC ? lc[m] * A[g] : 0.0;
                 };
-                contract_group_split<PF, 32 * L::KSM, NB, S::NS, T, ST, 2>(q, xm, bVm, lane, 16 * wave, a.qinv_m);
-                contract_group_split<PF, 32 * L::KSC, NB, S::NS, T, ST, 2>(q + NC * L::KSM * NB * 64, xc, bVc, lane,
-                                                                          16 * wave, a.qinv_c);
-            }
-            if (!QLDS && walk.valid(gn)) {  // registers are short here: gather after the contraction
-                gather(gn);
-                if (walk.valid(gn + walk.step)) load_conn(gn + walk.step);
+                if (a.M)
+                    contract_group_split<PF, 32 * L::KSM, NB, S::NS, T, ST, 2>(q, xm, bVm, lane, 16 * wave, a.qinv_m);
+                if (a.C)
+                    contract_group_split<PF, 32 * L::KSC, NB, S::NS, T, ST, 2>(q + NC * L::KSM * NB * 64, xc, bVc,
+                                                                              lane, 16 * wave, a.qinv_c);
             }
             lds_barrier();  // tile i staged; the consumers are done with buffer (i + 1) % 2
         }

@@ -71,6 +71,58 @@ hipError_t launch_form(const FormArgs &a, int D, int P, int nqm, int nqc, int pr
     return hipErrorInvalidValue;
 }
 
+// Coefficient of the mass tensor contracted with v (Section 5): at every
+// quadrature node of the rule, s = law(u_h(xhat_q)) * v_h(xhat_q) with u_h and
+// v_h interpolated from the element's nodal values (one thread per element,
+// S[q][e] stored q-major so that a warp's stores are contiguous).
+template <int D, int P, int NQ>
+__global__ __launch_bounds__(256) void coeff_product_kernel(CoeffProductArgs a)
+{
+    using S = Shape<D, P>;
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= a.n_elem) return;
+    double u[S::NP], v[S::NP];
+#pragma unroll
+    for (int i = 0; i < S::NP; ++i) {
+        const int32_t node = a.conn[i * a.n_elem + e];
+        u[i] = a.c.field[node];
+        v[i] = a.v[node];
+    }
+    bool ok = true;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        double uh = 0.0, vh = 0.0;
+#pragma unroll
+        for (int i = 0; i < S::NP; ++i) {
+            const double ph = uniform_table(a.phi)[i * NQ + q];
+            uh = fma(ph, u[i], uh);
+            vh = fma(ph, v[i], vh);
+        }
+        const double s = apply_law(a.c, uh) * vh;
+        ok &= isfinite(s);
+        a.S[q * a.n_elem + e] = s;
+    }
+    if (!ok) atomicOr(a.flags, 1);
+}
+
+hipError_t launch_coeff_product(const CoeffProductArgs &a, int D, int P, int nq, hipStream_t st)
+{
+    if (a.n_elem == 0) return hipSuccess;
+    const dim3 block(256), grid(unsigned((a.n_elem + 255) / 256));
+#define X(d, p, m, c)                                                            \
+    if (D == d && P == p && nq == m) {                                          \
+        coeff_product_kernel<d, p, m><<<grid, block, 0, st>>>(a);                \
+        return hipGetLastError();                                                \
+    }                                                                            \
+    if (D == d && P == p && nq == c) {                                          \
+        coeff_product_kernel<d, p, c><<<grid, block, 0, st>>>(a);                \
+        return hipGetLastError();                                                \
+    }
+    QXA_FORM_CASES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_expand(const ExpandArgs &a, hipStream_t st)
 {
     if (a.n_elem == 0) return hipSuccess;
