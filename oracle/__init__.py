@@ -69,6 +69,7 @@ def _load():
         lib.oracle_mass_tensor_product.argtypes = [C.c_int, C.c_int, C.c_int64, _D, C.c_int64, _I32, C.c_int, _D,
                                                    _D, C.POINTER(_Coeff), _D, _I64, _I32, _D, C.c_int,
                                                    C.POINTER(C.c_int64)]
+        lib.oracle_cond_tensor_product.argtypes = lib.oracle_mass_tensor_product.argtypes
         _lib = lib
     return _lib
 
@@ -222,6 +223,29 @@ def qpoint_coeff(mesh, elems, rule, law, field=None):
     if rc:
         raise ValueError("oracle_qpoint_coeff failed")
     return out.reshape(-1, w.size)
+
+
+def _tensor_product(fn, mesh, rule, law, u, v, nthreads):
+    row_ptr, col_idx = pattern(mesh)
+    out = np.zeros(col_idx.size)
+    conn = np.ascontiguousarray(mesh["conn"], dtype=np.int32)
+    coords = np.ascontiguousarray(mesh["coords"], dtype=np.float64)
+    pts, w = (np.ascontiguousarray(a, dtype=np.float64) for a in rule)
+    c, keep = _coeff(law, u)
+    vv = np.ascontiguousarray(v, dtype=np.float64)
+    bad = C.c_int64(-1)
+    rc = getattr(_load(), fn)(mesh["dim"], mesh["order"], coords.shape[1], coords.reshape(-1), conn.shape[1],
+                              conn.reshape(-1), w.size, pts.reshape(-1), w, C.byref(c), vv, row_ptr, col_idx, out,
+                              int(nthreads), C.byref(bad))
+    if rc:
+        raise ValueError(f"oracle {fn} failed ({rc}), element {bad.value}")
+    return row_ptr, col_idx, out
+
+
+def cond_tensor_product(mesh, rule, law_dc, u, v, nthreads=0):
+    """The conductivity tensor of Section 5 (C_ijk = int c'(u_h) grad phi_i . grad phi_j phi_k)
+    contracted with v in its second mode, in the CSR pattern (row i, column k; not symmetric)."""
+    return _tensor_product("oracle_cond_tensor_product", mesh, rule, law_dc, u, v, nthreads)
 
 
 def mass_tensor_product(mesh, rule, law_dm, u, v, nthreads=0):

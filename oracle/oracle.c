@@ -772,3 +772,94 @@ int oracle_mass_tensor_product(int dim, int P, int64_t n_nodes, const double *co
     free(dummy);
     return err;
 }
+
+/*
+ * Conductivity tensor of Section 5 contracted with a nodal vector v in its second
+ * mode (the Newton Jacobian term):
+ *   C_ijk = sum_e sum_q w_q c'_q (J_q A_e J_q^T)_ij phi_k |det B_e|,
+ *   (C o_2 v)_ik = sum_j C_ijk v_j      (not symmetric in i, k).
+ * Per element the full local tensor (n_p^3 entries) is formed, then contracted with
+ * the element's entries of v; the local matrices (row i, column k) are added into
+ * the CSR pattern. cdc carries c' (kind 1: law of the interpolated nodal field).
+ */
+int oracle_cond_tensor_product(int dim, int P, int64_t n_nodes, const double *coords, int64_t n_e, const int32_t *conn,
+                               int nq, const double *pts, const double *w, const oracle_coeff *cdc, const double *v,
+                               const int64_t *row_ptr, const int32_t *col_idx, double *Tv, int nthreads,
+                               int64_t *bad_elem)
+{
+    refdata R;
+    if (ref_setup(&R, dim, P, nq, pts, w, nq, pts, w)) return -1;
+    int n = R.n, d = dim;
+    double *Tbuf = (double *)malloc(sizeof(double) * (size_t)n_e * n * n);
+    double *dummy = (double *)malloc(sizeof(double) * (size_t)(row_ptr[n_nodes] + 1));
+    if (!Tbuf || !dummy) {
+        free(Tbuf);
+        free(dummy);
+        return -5;
+    }
+    int err = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(static)
+#endif
+    for (int64_t e = 0; e < n_e; ++e) {
+        double B[MAXD * MAXD], Binv[MAXD * MAXD], A[MAXD * MAXD], Ce[MAXP * MAXP * MAXP];
+        int32_t v0 = conn[e];
+        double maxedge = 0.0;
+        for (int c = 0; c < d; ++c) {
+            int32_t vc = conn[(size_t)(c + 1) * n_e + e];
+            double len2 = 0.0;
+            for (int r = 0; r < d; ++r) {
+                double t = coords[(size_t)r * n_nodes + vc] - coords[(size_t)r * n_nodes + v0];
+                B[r * d + c] = t;
+                len2 += t * t;
+            }
+            if (len2 > maxedge) maxedge = len2;
+        }
+        for (int i = 0; i < d * d; ++i) Binv[i] = (i % (d + 1) == 0) ? 1.0 : 0.0;
+        double det = gauss_solve(d, B, d, Binv);
+        double adet = fabs(det);
+        if (!(adet > 1e-14 * pow(sqrt(maxedge), d))) {
+#ifdef _OPENMP
+#pragma omp critical
+#endif
+            {
+                if (!err || e < *bad_elem) *bad_elem = e;
+                err = -3;
+            }
+            continue;
+        }
+        for (int a = 0; a < d; ++a)
+            for (int b = 0; b < d; ++b) {
+                double s = 0.0;
+                for (int k = 0; k < d; ++k) s += Binv[a * d + k] * Binv[b * d + k];
+                A[a * d + b] = s;
+            }
+        for (int t = 0; t < n * n * n; ++t) Ce[t] = 0.0;
+        for (int q = 0; q < nq; ++q) {
+            const double *ph = R.phi_m + (size_t)q * n;
+            const double *Jq = R.dphi_m + (size_t)q * n * d;
+            double lam = w[q] * coeff_at(cdc, ph, n, conn, n_e, e, q) * adet;
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) {
+                    double g = 0.0;   /* (J_q A J_q^T)_ij */
+                    for (int a = 0; a < d; ++a)
+                        for (int b = 0; b < d; ++b) g += Jq[i * d + a] * A[a * d + b] * Jq[j * d + b];
+                    for (int k = 0; k < n; ++k) Ce[(i * n + j) * n + k] += lam * g * ph[k];
+                }
+        }
+        double *T = Tbuf + (size_t)e * n * n;
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k) {
+                double s = 0.0;
+                for (int j = 0; j < n; ++j) s += Ce[(i * n + j) * n + k] * v[conn[(size_t)j * n_e + e]];
+                T[i * n + k] = s;
+            }
+    }
+    if (!err)
+        err = assemble_rows(&R, coords, n_nodes, conn, n_e, cdc, cdc, n_nodes, NULL, row_ptr, col_idx, Tv, dummy, Tbuf,
+                            Tbuf, nthreads, bad_elem);
+    free(Tbuf);
+    free(dummy);
+    return err;
+}

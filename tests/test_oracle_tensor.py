@@ -88,3 +88,63 @@ def test_symmetric_and_linear_in_v():
     for i in range(n):
         A[i, ci[rp[i]:rp[i + 1]]] = T1[rp[i]:rp[i + 1]]
     assert np.abs(A - A.T).max() <= 1e-14 * np.abs(A).max()
+
+
+# ---- conductivity tensor C_ijk = int c'(u_h) grad phi_i . grad phi_j phi_k, second mode ----
+
+def _dense(rp, ci, vals, n):
+    A = np.zeros((n, n))
+    for i in range(n):
+        A[i, ci[rp[i]:rp[i + 1]]] = vals[rp[i]:rp[i + 1]]
+    return A
+
+
+@pytest.mark.parametrize("dim,order,N", [(2, 1, 3), (2, 2, 2), (2, 3, 1), (3, 1, 1), (3, 2, 1)])
+def test_cond_tensor_is_the_jacobian_of_C_u_times_u(dim, order, N):
+    """d/du_k (C(u) u)_i = sum_j C_ijk u_j + C_ik(u): with c quadratic, C(u) u is cubic in u,
+    so the Richardson-extrapolated central difference of the oracle's own conductivity
+    assembly is exact up to rounding."""
+    mesh = structured_mesh(dim, order, N, 0.2, seed=[51, dim, order])
+    u, _ = _fields(mesh, [52, dim, order])
+    n = u.size
+    r = rule(dim, 2 * order)
+    a0, a1, a2 = 1.0, 0.4, 0.3
+    law_c, law_dc = ("poly2", a0, a1, a2), ("poly2", a1, 2 * a2, 0.0)
+    rp, ci, T = oracle.cond_tensor_product(mesh, r, law_dc, u, u)
+    _, _, _, C0 = oracle.assemble(mesh, r, r, ("const", 1.0), law_c, None, u)
+
+    def g(x):
+        _, _, _, Cx = oracle.assemble(mesh, r, r, ("const", 1.0), law_c, None, x)
+        return _dense(rp, ci, Cx, n) @ x
+
+    J = np.zeros((n, n))
+    t = 1e-2
+    for k in range(n):
+        e = np.zeros(n)
+        e[k] = 1.0
+        d1 = (g(u + t * e) - g(u - t * e)) / (2 * t)
+        d2 = (g(u + t / 2 * e) - g(u - t / 2 * e)) / t
+        J[:, k] = (4 * d2 - d1) / 3
+    want = J - _dense(rp, ci, C0, n)
+    got = _dense(rp, ci, T, n)
+    assert np.abs(got - want).max() <= 1e-9 * np.abs(want).max()
+    assert np.abs(got - got.T).max() > 1e-6 * np.abs(got).max()      # not symmetric in general
+
+
+@pytest.mark.parametrize("dim,order,N", SHAPES)
+def test_cond_tensor_column_sums_vanish_and_constants(dim, order, N):
+    """sum_i grad phi_i = 0, so every column of C o_2 v sums to zero; a constant v has no gradient."""
+    mesh = structured_mesh(dim, order, N, 0.2, seed=[53, dim, order])
+    u, v = _fields(mesh, [54, dim, order])
+    r = rule(dim, 2 * order)
+    law = ("exp", 0.0, 0.7)
+    rp, ci, T = oracle.cond_tensor_product(mesh, r, law, u, v)
+    n = u.size
+    A = _dense(rp, ci, T, n)
+    assert np.abs(A.sum(axis=0)).max() <= 1e-12 * np.abs(A).max()
+    _, _, T1 = oracle.cond_tensor_product(mesh, r, law, u, np.full(n, 2.5))
+    assert np.abs(T1).max() <= 1e-12 * np.abs(T).max()
+    w = np.random.default_rng(55).uniform(-1, 1, size=n)
+    _, _, T2 = oracle.cond_tensor_product(mesh, r, law, u, w)
+    _, _, T3 = oracle.cond_tensor_product(mesh, r, law, u, v - 2 * w)
+    assert _rel(T3, T - 2 * T2) <= 1e-13
