@@ -202,10 +202,29 @@ qxa_status qxa_element_matrices(qxa_plan plan, const qxa_coeff *mass, const qxa_
  * law poly2 (a1, 2 a2, 0)). v: device [n_nodes]. S: caller-owned device
  * [n_q][n_elem], written asynchronously on `stream`. Errors: QXA_E_INVALID for
  * null pointers, a bad rule index, another kind or a plan owned by a server; a
- * non-finite s is reported by qxa_sync as QXA_E_NONFINITE. The conductivity
- * tensor contracted in its second mode is not symmetric and is not provided.
+ * non-finite s is reported by qxa_sync as QXA_E_NONFINITE.
  */
 qxa_status qxa_coeff_product(qxa_plan plan, int rule, const qxa_coeff *c, const double *v, double *S, void *stream);
+
+/*
+ * Conductivity tensor contracted with a nodal vector in its second mode (Section 5,
+ * the Newton Jacobian term): C_ijk = int c'(u_h) grad phi_i . grad phi_j phi_k,
+ *   (C o_2 v)_ik = sum_j C_ijk v_j = int c'(u_h) (grad phi_i . grad v_h) phi_k,
+ * written as CSR values in the plan's pattern (row i, column k; the result is not
+ * symmetric). Per element the local matrix is Q X with Q = [phi_q (x) J_q] and
+ * X[(q, c), e] = lambda_q (A_e J_q^T v_e)_c, lambda_q = w_q c'_q |det B_e|, on the
+ * plan's stiffness rule; it goes to a plan-owned buffer, and one thread per CSR slot
+ * sums the slot's element entries in ascending element order (deterministic).
+ * c: kind QXA_COEFF_NODAL with the law of c' (c = a0 + a1 s + a2 s^2 has
+ * c' = a1 + 2 a2 s). v: device [n_nodes]. T_vals: caller-owned device [nnz].
+ * The first call on a plan builds the slot -> entries map on the host and
+ * allocates 8 n_p^2 n_elem + 4 n_p^2 n_elem + 8 (nnz + 1) bytes of device memory,
+ * kept until qxa_plan_destroy; later calls allocate nothing. Asynchronous on
+ * `stream`. Errors: QXA_E_INVALID (null pointers, another kind, a plan owned by a
+ * server), QXA_E_UNSUPPORTED (n_p^2 n_elem >= 2^31), QXA_E_NOMEM; a non-finite
+ * c' value is reported by qxa_sync as QXA_E_NONFINITE.
+ */
+qxa_status qxa_cond_tensor_product(qxa_plan plan, const qxa_coeff *c, const double *v, double *T_vals, void *stream);
 
 /*
  * Per-kernel timing with HIP events recorded on the launch stream around every

@@ -94,6 +94,7 @@ def lib():
         L.qxa_assemble.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), ci, vp, vp, vp]
         L.qxa_element_matrices.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), ci, vp, vp, vp]
         L.qxa_coeff_product.argtypes = [vp, ci, C.POINTER(_Coeff), vp, vp, vp]
+        L.qxa_cond_tensor_product.argtypes = [vp, C.POINTER(_Coeff), vp, vp, vp]
         L.qxa_sync.argtypes = [vp, vp]
         L.qxa_plan_set_timing.argtypes = [vp, ci]
         L.qxa_graph_create.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), ci, vp, vp, C.POINTER(vp)]
@@ -320,6 +321,18 @@ def mass_tensor_product(plan: Plan, law_dm, u, v, T=None, S=None, stream=None):
     S = coeff_product(plan, law_dm, u, v, "mass", S=S, stream=stream)
     T, _ = assemble(plan, ("identity",), ("const", 1.0), S, None, M=T, stream=stream, want_c=False, qpoint=True)
     return T, S
+
+
+def cond_tensor_product(plan: Plan, law_dc, u, v, T=None, stream=None):
+    """The conductivity tensor of the Newton Jacobian (C_ijk = int c'(u_h) grad phi_i .
+    grad phi_j phi_k) contracted with v in its second mode, as values in the plan's CSR
+    pattern (row i, column k; not symmetric)."""
+    import torch
+    if T is None:
+        T = torch.empty(plan.nnz, dtype=torch.float64, device=torch.device("cuda", plan.mesh.device))
+    c, keep = make_coeff(law_dc, u)
+    check(lib().qxa_cond_tensor_product(plan.handle, C.byref(c), _ptr(v), _ptr(T), _stream_ptr(stream)))
+    return T
 
 
 def element_matrices(plan: Plan, law_m, law_c, field_m=None, field_c=None, precision="fp64", stream=None,

@@ -322,7 +322,7 @@ qxa_status qxa_plan_destroy(qxa_plan p)
     void *bufs[] = {p->d_row_ptr, p->d_col_idx, p->d_tconn, p->d_elem_order, p->d_rec, p->d_rec_ptr, p->d_rec_mid,
                     p->d_part_ptr, p->d_fix_target, p->d_fix_mirror, p->d_sink, p->d_part, p->d_qfrag[0],
                     p->d_qfrag[1], p->d_qfrag[2], p->d_qfrag[3], p->d_qfrag[4], p->d_tables, p->d_tables_f,
-                    p->d_V, p->d_flags};
+                    p->d_V, p->d_flags, p->d_T, p->d_ns_ptr, p->d_ns_items};
     for (void *b : bufs) plan_free(p, b);
     delete p;
     return QXA_OK;
@@ -365,6 +365,7 @@ qxa_status plan_stage(qxa_mesh mesh, const qxa_quad &mr, const qxa_quad &cr, Pla
     g.off_phic = put(T.phi_c);
     g.off_qm = put(T.Qm);
     g.off_qc = put(T.Qc);
+    g.off_dphic = put(T.dphi_c);
     g.tabf.assign(g.tab.begin(), g.tab.end());
     return QXA_OK;
 }
@@ -413,6 +414,7 @@ qxa_status plan_upload(qxa_mesh mesh, const PlanStaging &g, DevArena *arena, boo
     p->off_wc = g.off_wc;
     p->off_phim = g.off_phim;
     p->off_phic = g.off_phic;
+    p->off_dphic = g.off_dphic;
     p->off_qm = g.off_qm;
     p->off_qc = g.off_qc;
     if (!st) st = plan_upload_buf(p, &p->d_tables, g.tab.data(), g.tab.size());
@@ -668,6 +670,87 @@ qxa_status qxa_coeff_product(qxa_plan p, int rule, const qxa_coeff *c, const dou
     a.flags = p->d_flags;
     const int nq = rule == 0 ? p->ref.nq_m : p->ref.nq_c;
     QXA_HIP(launch_coeff_product(a, p->ref.dim, p->ref.order, nq, reinterpret_cast<hipStream_t>(stream)));
+    return QXA_OK;
+}
+
+}  // extern "C"
+
+namespace qxa {
+
+// Entries of every CSR slot (both triangles) for the nonsymmetric local matrices
+// T[(a*np + b) * n_elem + e]: the slot of (N_e(a), N_e(b)) is the upper slot of the
+// pair or its mirror. Counting sort in element order, so each slot lists its
+// entries by ascending element, then (a, b): a fixed summation order.
+static qxa_status build_slot_entries(qxa_plan p)
+{
+    const qxa_mesh m = p->mesh;
+    const int np = p->ref.np;
+    const int64_t ne = m->n_elem;
+    if (int64_t(np) * np * ne >= (int64_t(1) << 31))
+        return fail(QXA_E_UNSUPPORTED, "conductivity tensor product: more than 2^31 element entries");
+    HostPlan hp;
+    qxa_status st = build_host_plan(m->dim, m->order, m->n_nodes, ne, m->h_conn.data(), hp);
+    if (st) return st;
+    const int32_t *conn = m->h_conn.data();
+    auto slot = [&](int64_t e, int a, int b) -> uint32_t {
+        const int lo = std::min(a, b), hi = std::max(a, b);
+        const int s = lo * np - lo * (lo - 1) / 2 + (hi - lo);
+        const uint32_t up = hp.perm_sym[size_t(s) * ne + e];
+        return conn[size_t(a) * ne + e] <= conn[size_t(b) * ne + e] ? up : hp.mirror[up];
+    };
+    std::vector<int64_t> ptr(hp.nnz + 1, 0);
+    for (int64_t e = 0; e < ne; ++e)
+        for (int a = 0; a < np; ++a)
+            for (int b = 0; b < np; ++b) ++ptr[slot(e, a, b) + 1];
+    for (int64_t t = 0; t < hp.nnz; ++t) ptr[t + 1] += ptr[t];
+    std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+    std::vector<int32_t> items(static_cast<size_t>(ptr[hp.nnz]));
+    for (int64_t e = 0; e < ne; ++e)
+        for (int a = 0; a < np; ++a)
+            for (int b = 0; b < np; ++b) items[size_t(fill[slot(e, a, b)]++)] = int32_t((a * np + b) * ne + e);
+    st = plan_upload_buf(p, &p->d_ns_ptr, ptr.data(), ptr.size());
+    if (!st) st = plan_upload_buf(p, &p->d_ns_items, items.data(), items.size());
+    if (!st) st = plan_alloc(p, &p->d_T, size_t(np) * np * ne);
+    return st;
+}
+
+}  // namespace qxa
+
+extern "C" {
+
+qxa_status qxa_cond_tensor_product(qxa_plan p, const qxa_coeff *c, const double *v, double *T_vals, void *stream)
+{
+    if (!p || !c || !v || !T_vals) return fail(QXA_E_INVALID, "null argument");
+    if (!p->d_flags) return fail(QXA_E_INVALID, "plan is owned by a server");
+    if (c->kind != QXA_COEFF_NODAL) return fail(QXA_E_INVALID, "c' is a nodal field through a law");
+    CondTensorArgs a{};
+    qxa_status st = to_coeff(c, a.c, "c'");
+    if (st) return st;
+    if (p->mesh->n_elem == 0) return QXA_OK;
+    QXA_HIP(hipSetDevice(p->mesh->device));
+    if (!p->d_ns_ptr) {
+        st = build_slot_entries(p);
+        if (st) return st;
+    }
+    const qxa_mesh m = p->mesh;
+    a.n_nodes = m->n_nodes;
+    a.n_elem = m->n_elem;
+    a.coords = m->d_coords;
+    a.conn = m->d_conn;
+    a.w = p->d_tables + p->off_wc;
+    a.phi = p->d_tables + p->off_phic;
+    a.dphi = p->d_tables + p->off_dphic;
+    a.v = v;
+    a.T = p->d_T;
+    a.flags = p->d_flags;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    {
+        TimedLaunch tl(p, "cond_tensor_rows", s);
+        QXA_HIP(launch_cond_tensor(a, m->dim, m->order, p->ref.nq_c, s));
+    }
+    TimedLaunch tl(p, "slot_gather", s);
+    const SlotGatherArgs g{p->nnz, p->d_ns_ptr, p->d_ns_items, p->d_T, T_vals};
+    QXA_HIP(launch_slot_gather(g, s));
     return QXA_OK;
 }
 

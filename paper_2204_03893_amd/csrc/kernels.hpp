@@ -109,8 +109,31 @@ struct CoeffProductArgs {
     int *flags;
 };
 
+struct CondTensorArgs {
+    int64_t n_nodes, n_elem;
+    const double *coords;  // [dim][n_nodes]
+    const int32_t *conn;   // [np][n_elem]
+    const double *w;       // [nq] stiffness rule
+    const double *phi;     // [np][nq]
+    const double *dphi;    // [nq][np][dim]
+    CoeffDev c;            // law of c'; c.field = u [n_nodes]
+    const double *v;       // [n_nodes]
+    double *T;             // [np*np][n_elem] local matrices (row a, column b)
+    int *flags;
+};
+
+struct SlotGatherArgs {
+    int64_t n_slots;
+    const int64_t *ptr;    // [n_slots + 1]
+    const int32_t *items;  // indices into src
+    const double *src;
+    double *out;           // [n_slots]
+};
+
 bool form_supported(int D, int P, int nqm, int nqc);
 hipError_t launch_coeff_product(const CoeffProductArgs &a, int D, int P, int nq, hipStream_t st);
+hipError_t launch_cond_tensor(const CondTensorArgs &a, int D, int P, int nq, hipStream_t st);
+hipError_t launch_slot_gather(const SlotGatherArgs &a, hipStream_t st);
 hipError_t launch_form(const FormArgs &a, int D, int P, int nqm, int nqc, int precision, hipStream_t st);
 hipError_t launch_expand(const ExpandArgs &a, hipStream_t st);
 hipError_t launch_fused(const JobTable &jt, int D, int P, int nqm, int nqc, int precision, hipStream_t st);

@@ -123,6 +123,108 @@ hipError_t launch_coeff_product(const CoeffProductArgs &a, int D, int P, int nq,
     return hipErrorInvalidValue;
 }
 
+// Local matrices of the conductivity tensor contracted with v in its second mode
+// (Section 5): T_e[a][b] = sum_q w_q c'(u_h) |det B_e| (J_q[a] A_e J_q^T v_e) phi_b(xhat_q),
+// i.e. the columns of Q = [phi_q (x) J_q] weighted by X[(q, c), e] = lambda_q (A_e J_q^T v_e)_c.
+// One thread per (element, row a): blockIdx.y = a, elements along x (coalesced stores).
+template <int D, int P, int NQ>
+__global__ __launch_bounds__(256) void cond_tensor_rows_kernel(CondTensorArgs a)
+{
+    using S = Shape<D, P>;
+    constexpr int NP = S::NP;
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int ra = blockIdx.y;
+    if (e >= a.n_elem) return;
+    double x[D + 1][D];
+#pragma unroll
+    for (int k = 0; k <= D; ++k) {
+        const int32_t node = a.conn[k * a.n_elem + e];
+#pragma unroll
+        for (int c = 0; c < D; ++c) x[k][c] = a.coords[c * a.n_nodes + node];
+    }
+    double babs, Au[S::NG];
+    geometry_from<D>(x, babs, Au);
+    double A[D][D];
+    {
+        int g = 0;
+#pragma unroll
+        for (int r = 0; r < D; ++r)
+#pragma unroll
+            for (int c = r; c < D; ++c, ++g) A[r][c] = A[c][r] = Au[g];
+    }
+    double u[NP], v[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        const int32_t node = a.conn[i * a.n_elem + e];
+        u[i] = a.c.field[node];
+        v[i] = a.v[node];
+    }
+    double row[NP];
+#pragma unroll
+    for (int b = 0; b < NP; ++b) row[b] = 0.0;
+    bool ok = true;
+    for (int q = 0; q < NQ; ++q) {
+        const auto J = uniform_table(a.dphi) + size_t(q) * NP * D;
+        double uh = 0.0, gv[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) gv[c] = 0.0;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            uh = fma(uniform_table(a.phi)[i * NQ + q], u[i], uh);
+#pragma unroll
+            for (int c = 0; c < D; ++c) gv[c] = fma(J[i * D + c], v[i], gv[c]);  // J_q^T v_e
+        }
+        const double lam = uniform_table(a.w)[q] * apply_law(a.c, uh) * babs;
+        ok &= isfinite(lam);
+        double r = 0.0;  // J_q[a] A_e J_q^T v_e
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) t = fma(A[c][k], gv[k], t);
+            r = fma(J[ra * D + c], t, r);
+        }
+        const double f = lam * r;
+#pragma unroll
+        for (int b = 0; b < NP; ++b) row[b] = fma(f, uniform_table(a.phi)[b * NQ + q], row[b]);
+    }
+#pragma unroll
+    for (int b = 0; b < NP; ++b) a.T[(ra * NP + b) * a.n_elem + e] = row[b];
+    if (!ok) atomicOr(a.flags, 1);
+}
+
+hipError_t launch_cond_tensor(const CondTensorArgs &a, int D, int P, int nq, hipStream_t st)
+{
+    if (a.n_elem == 0) return hipSuccess;
+#define X(d, p, m, c)                                                                          \
+    if (D == d && P == p && nq == c) {                                                         \
+        const dim3 grid(unsigned((a.n_elem + 255) / 256), unsigned(Shape<d, p>::NP));         \
+        cond_tensor_rows_kernel<d, p, c><<<grid, 256, 0, st>>>(a);                            \
+        return hipGetLastError();                                                              \
+    }
+    QXA_FORM_CASES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+// out[t] = sum of src over the entries of slot t, in their stored order (deterministic).
+__global__ __launch_bounds__(256) void slot_gather_kernel(SlotGatherArgs a)
+{
+    const int64_t t = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (t >= a.n_slots) return;
+    const int64_t lo = a.ptr[t], hi = a.ptr[t + 1];
+    double s = 0.0;
+    for (int64_t k = lo; k < hi; ++k) s += a.src[a.items[k]];
+    a.out[t] = s;
+}
+
+hipError_t launch_slot_gather(const SlotGatherArgs &a, hipStream_t st)
+{
+    if (a.n_slots == 0) return hipSuccess;
+    slot_gather_kernel<<<unsigned((a.n_slots + 255) / 256), 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+
 hipError_t launch_expand(const ExpandArgs &a, hipStream_t st)
 {
     if (a.n_elem == 0) return hipSuccess;

@@ -147,12 +147,14 @@ qxa_status build_ref_tables(int dim, int order, const qxa_quad &mr, const qxa_qu
     }
     // stiffness rule: Phi (for u_h) and Q_c
     T.phi_c.assign(size_t(np) * T.nq_c, 0.0);
+    T.dphi_c.assign(size_t(T.nq_c) * np * dim, 0.0);
     T.Qc.assign(size_t(ns) * T.nq_c * ng, 0.0);
     std::vector<double> J0;
     T.stiff_const_grad = true;
     for (int q = 0; q < T.nq_c; ++q) {
         lagrange_eval(dim, order, cr.points + q * dim, phi, dphi);
         for (int i = 0; i < np; ++i) T.phi_c[size_t(i) * T.nq_c + q] = phi[i];
+        std::copy(dphi, dphi + np * dim, T.dphi_c.begin() + size_t(q) * np * dim);
         if (q == 0) J0.assign(dphi, dphi + np * dim);
         else
             for (int k = 0; k < np * dim; ++k)

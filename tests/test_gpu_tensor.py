@@ -60,3 +60,43 @@ def test_coeff_product_errors():
     with pytest.raises(qxa.QxaError) as ei:
         qxa.sync(plan)
     assert ei.value.code == -4
+
+
+@pytest.mark.parametrize("dim,order,N", SHAPES)
+def test_cond_tensor_product_against_oracle(dim, order, N):
+    import paper_2204_03893_amd as qxa
+    print("case cond", dim, order, N, flush=True)
+    mesh = structured_mesh(dim, order, N, 0.2, seed=[43, dim, order])
+    rng = np.random.default_rng([44, dim, order])
+    u = gaussian_random_field(mesh["coords"], 16, rng, length=0.3)
+    v = gaussian_random_field(mesh["coords"], 16, rng, length=0.2)
+    r = rule(dim, 2 * order)
+    law_dc = ("exp", 0.0, 0.5)
+    m = qxa.Mesh(dim, order, mesh["coords"], mesh["conn"])
+    plan = qxa.Plan(m, r)
+    uf, vf = torch.tensor(u, device="cuda"), torch.tensor(v, device="cuda")
+    T = qxa.cond_tensor_product(plan, law_dc, uf, vf)
+    T2 = qxa.cond_tensor_product(plan, law_dc, uf, vf)
+    qxa.sync(plan)
+    rp, ci = plan.pattern()
+    rpo, cio, To = oracle.cond_tensor_product(mesh, r, law_dc, u, v)
+    assert np.array_equal(rp.cpu().numpy(), rpo) and np.array_equal(ci.cpu().numpy(), cio)
+    assert row_scaled_error(T.cpu().numpy(), To, rpo) <= 1e-12
+    assert torch.equal(T.view(torch.int64), T2.view(torch.int64))
+
+
+def test_cond_tensor_product_errors():
+    import paper_2204_03893_amd as qxa
+    mesh = structured_mesh(2, 2, 3, 0.0)
+    m = qxa.Mesh(2, 2, mesh["coords"], mesh["conn"])
+    plan = qxa.Plan(m, rule(2, 4))
+    u = torch.zeros(mesh["n_nodes"], dtype=torch.float64, device="cuda")
+    with pytest.raises(qxa.QxaError) as ei:
+        qxa.cond_tensor_product(plan, ("const", 1.0), None, u)
+    assert ei.value.code == -1
+    bad = u.clone()
+    bad[5] = float("inf")
+    qxa.cond_tensor_product(plan, ("identity",), bad, u + 1.0)
+    with pytest.raises(qxa.QxaError) as ei:
+        qxa.sync(plan)
+    assert ei.value.code == -4
