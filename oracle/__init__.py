@@ -70,6 +70,8 @@ def _load():
                                                    _D, C.POINTER(_Coeff), _D, _I64, _I32, _D, C.c_int,
                                                    C.POINTER(C.c_int64)]
         lib.oracle_cond_tensor_product.argtypes = lib.oracle_mass_tensor_product.argtypes
+        lib.oracle_load_vector.argtypes = [C.c_int, C.c_int, C.c_int64, _D, C.c_int64, _I32, C.c_int, _D, _D,
+                                           C.POINTER(_Coeff), _D, C.POINTER(C.c_int64)]
         _lib = lib
     return _lib
 
@@ -266,3 +268,18 @@ def mass_tensor_product(mesh, rule, law_dm, u, v, nthreads=0):
     if rc:
         raise ValueError(f"oracle mass_tensor_product failed ({rc}), element {bad.value}")
     return row_ptr, col_idx, out
+
+
+def load_vector(mesh, rule, law_f, field=None, qpoint=None):
+    """Volume load vector F_i = int f phi_i over the mesh (float64 [n_nodes])."""
+    conn = np.ascontiguousarray(mesh["conn"], dtype=np.int32)
+    coords = np.ascontiguousarray(mesh["coords"], dtype=np.float64)
+    pts, w = (np.ascontiguousarray(a, dtype=np.float64) for a in rule)
+    c, keep = _coeff(law_f, field, qpoint)
+    F = np.zeros(coords.shape[1])
+    bad = C.c_int64(-1)
+    rc = _load().oracle_load_vector(mesh["dim"], mesh["order"], coords.shape[1], coords.reshape(-1), conn.shape[1],
+                                    conn.reshape(-1), w.size, pts.reshape(-1), w, C.byref(c), F, C.byref(bad))
+    if rc:
+        raise ValueError(f"oracle load_vector failed ({rc}), element {bad.value}")
+    return F

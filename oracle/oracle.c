@@ -863,3 +863,43 @@ int oracle_cond_tensor_product(int dim, int P, int64_t n_nodes, const double *co
     free(dummy);
     return err;
 }
+
+/*
+ * Volume load vector f_i = int f phi_i (Section 2), in the order of Algorithm 1:
+ * per element, per quadrature node of the rule, f_q w_q phi_i(xhat_q) |det B_e| is
+ * added into F[N_e(i)]; every entry is summed in ascending element order with
+ * compensation. cf: the coefficient f (constant, nodal field through a law, or
+ * values per (q, e)).
+ */
+int oracle_load_vector(int dim, int P, int64_t n_nodes, const double *coords, int64_t n_e, const int32_t *conn, int nq,
+                       const double *pts, const double *w, const oracle_coeff *cf, double *F, int64_t *bad_elem)
+{
+    refdata R;
+    if (ref_setup(&R, dim, P, nq, pts, w, nq, pts, w)) return -1;
+    int n = R.n;
+    double *comp = (double *)calloc((size_t)n_nodes, sizeof(double));
+    if (!comp) return -5;
+    for (int64_t i = 0; i < n_nodes; ++i) F[i] = 0.0;
+    for (int64_t e = 0; e < n_e; ++e) {
+        double adet;
+        if (element_abs_det(&R, coords, n_nodes, conn, n_e, e, &adet)) {
+            *bad_elem = e;
+            free(comp);
+            return -3;
+        }
+        double fe[MAXP];
+        for (int i = 0; i < n; ++i) fe[i] = 0.0;
+        for (int q = 0; q < nq; ++q) {
+            const double *ph = R.phi_m + (size_t)q * n;
+            double lam = w[q] * coeff_at(cf, ph, n, conn, n_e, e, q) * adet;
+            for (int i = 0; i < n; ++i) fe[i] += lam * ph[i];
+        }
+        for (int i = 0; i < n; ++i) {
+            int32_t node = conn[(size_t)i * n_e + e];
+            kadd(&F[node], &comp[node], fe[i]);
+        }
+    }
+    for (int64_t i = 0; i < n_nodes; ++i) F[i] += comp[i];
+    free(comp);
+    return 0;
+}
