@@ -227,6 +227,22 @@ qxa_status qxa_coeff_product(qxa_plan plan, int rule, const qxa_coeff *c, const 
 qxa_status qxa_cond_tensor_product(qxa_plan plan, const qxa_coeff *c, const double *v, double *T_vals, void *stream);
 
 /*
+ * Volume load vector (Section 2): F_i = int f phi_i, on the plan's mass rule, as
+ * the vector analogue of Algorithm 2: element vectors Phi Lambda_f with
+ * Lambda_f[q, e] = w_q f_qe |det B_e| (one thread per element, to a plan-owned
+ * buffer), then one thread per node sums the node's element entries in ascending
+ * element order (deterministic). f: any coefficient (constant, nodal field through
+ * a law, values per (q, e) in mesh element order). F: caller-owned device
+ * [n_nodes]. The first call on a plan builds the node -> entries map on the host
+ * and allocates 12 n_p n_elem + 8 (n_nodes + 1) bytes, kept until
+ * qxa_plan_destroy. Asynchronous on `stream`. Errors as qxa_assemble; a non-finite
+ * value is reported by qxa_sync as QXA_E_NONFINITE. (The reaction matrix of
+ * Section 2, A_ij = int a phi_j phi_i, is the mass matrix of the coefficient a:
+ * qxa_assemble with a as the mass coefficient.)
+ */
+qxa_status qxa_load_vector(qxa_plan plan, const qxa_coeff *f, double *F, void *stream);
+
+/*
  * Per-kernel timing with HIP events recorded on the launch stream around every
  * kernel this plan launches (off by default). qxa_plan_timing_report waits for
  * the recorded events, writes a JSON object

@@ -95,6 +95,7 @@ def lib():
         L.qxa_element_matrices.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), ci, vp, vp, vp]
         L.qxa_coeff_product.argtypes = [vp, ci, C.POINTER(_Coeff), vp, vp, vp]
         L.qxa_cond_tensor_product.argtypes = [vp, C.POINTER(_Coeff), vp, vp, vp]
+        L.qxa_load_vector.argtypes = [vp, C.POINTER(_Coeff), vp, vp]
         L.qxa_sync.argtypes = [vp, vp]
         L.qxa_plan_set_timing.argtypes = [vp, ci]
         L.qxa_graph_create.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), ci, vp, vp, C.POINTER(vp)]
@@ -333,6 +334,22 @@ def cond_tensor_product(plan: Plan, law_dc, u, v, T=None, stream=None):
     c, keep = make_coeff(law_dc, u)
     check(lib().qxa_cond_tensor_product(plan.handle, C.byref(c), _ptr(v), _ptr(T), _stream_ptr(stream)))
     return T
+
+
+def load_vector(plan: Plan, law_f, field=None, F=None, stream=None, qpoint=False):
+    """Volume load vector F_i = int f phi_i (device float64 [n_nodes]) on the plan's mass rule."""
+    import torch
+    if F is None:
+        F = torch.empty(plan.n_nodes, dtype=torch.float64, device=torch.device("cuda", plan.mesh.device))
+    c, keep = make_coeff(law_f, field, qpoint)
+    check(lib().qxa_load_vector(plan.handle, C.byref(c), _ptr(F), _stream_ptr(stream)))
+    return F
+
+
+def reaction_matrix(plan: Plan, law_a, field=None, A=None, stream=None, qpoint=False):
+    """Reaction matrix A_ij = int a phi_j phi_i: the mass matrix of the coefficient a."""
+    A, _ = assemble(plan, law_a, ("const", 1.0), field, None, M=A, stream=stream, want_c=False, qpoint=qpoint)
+    return A
 
 
 def element_matrices(plan: Plan, law_m, law_c, field_m=None, field_c=None, precision="fp64", stream=None,

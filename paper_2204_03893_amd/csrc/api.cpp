@@ -322,7 +322,7 @@ qxa_status qxa_plan_destroy(qxa_plan p)
     void *bufs[] = {p->d_row_ptr, p->d_col_idx, p->d_tconn, p->d_elem_order, p->d_rec, p->d_rec_ptr, p->d_rec_mid,
                     p->d_part_ptr, p->d_fix_target, p->d_fix_mirror, p->d_sink, p->d_part, p->d_qfrag[0],
                     p->d_qfrag[1], p->d_qfrag[2], p->d_qfrag[3], p->d_qfrag[4], p->d_tables, p->d_tables_f,
-                    p->d_V, p->d_flags, p->d_T, p->d_ns_ptr, p->d_ns_items};
+                    p->d_V, p->d_flags, p->d_T, p->d_ns_ptr, p->d_ns_items, p->d_Fe, p->d_nf_ptr, p->d_nf_items};
     for (void *b : bufs) plan_free(p, b);
     delete p;
     return QXA_OK;
@@ -714,9 +714,62 @@ static qxa_status build_slot_entries(qxa_plan p)
     return st;
 }
 
+// Element entries of every node (a * n_elem + e with N_e(a) = node), ascending element.
+static qxa_status build_node_entries(qxa_plan p)
+{
+    const qxa_mesh m = p->mesh;
+    const int np = p->ref.np;
+    const int64_t ne = m->n_elem, nn = m->n_nodes;
+    if (int64_t(np) * ne >= (int64_t(1) << 31)) return fail(QXA_E_UNSUPPORTED, "load vector: more than 2^31 entries");
+    const int32_t *conn = m->h_conn.data();
+    std::vector<int64_t> ptr(nn + 1, 0);
+    for (int64_t e = 0; e < ne; ++e)
+        for (int a = 0; a < np; ++a) ++ptr[conn[size_t(a) * ne + e] + 1];
+    for (int64_t i = 0; i < nn; ++i) ptr[i + 1] += ptr[i];
+    std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+    std::vector<int32_t> items(static_cast<size_t>(ptr[nn]));
+    for (int64_t e = 0; e < ne; ++e)
+        for (int a = 0; a < np; ++a) items[size_t(fill[conn[size_t(a) * ne + e]]++)] = int32_t(a * ne + e);
+    qxa_status st = plan_upload_buf(p, &p->d_nf_ptr, ptr.data(), ptr.size());
+    if (!st) st = plan_upload_buf(p, &p->d_nf_items, items.data(), items.size());
+    if (!st) st = plan_alloc(p, &p->d_Fe, size_t(np) * ne);
+    return st;
+}
+
 }  // namespace qxa
 
 extern "C" {
+
+qxa_status qxa_load_vector(qxa_plan p, const qxa_coeff *f, double *F, void *stream)
+{
+    if (!p || !f || !F) return fail(QXA_E_INVALID, "null argument");
+    if (!p->d_flags) return fail(QXA_E_INVALID, "plan is owned by a server");
+    LoadArgs a{};
+    const void *qm, *qc;
+    qxa_status st = fill_inputs(p, f, nullptr, QXA_FP64, a.in, &qm, &qc);
+    if (st) return st;
+    const qxa_mesh m = p->mesh;
+    QXA_HIP(hipSetDevice(m->device));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (m->n_elem == 0) {
+        QXA_HIP(hipMemsetAsync(F, 0, sizeof(double) * m->n_nodes, s));
+        return QXA_OK;
+    }
+    if (!p->d_nf_ptr) {
+        st = build_node_entries(p);
+        if (st) return st;
+    }
+    a.conn = m->d_conn;
+    a.Fe = p->d_Fe;
+    {
+        TimedLaunch tl(p, "load_elem", s);
+        QXA_HIP(launch_load(a, m->dim, m->order, p->ref.nq_m, s));
+    }
+    TimedLaunch tl(p, "slot_gather", s);
+    const SlotGatherArgs g{m->n_nodes, p->d_nf_ptr, p->d_nf_items, p->d_Fe, F};
+    QXA_HIP(launch_slot_gather(g, s));
+    return QXA_OK;
+}
 
 qxa_status qxa_cond_tensor_product(qxa_plan p, const qxa_coeff *c, const double *v, double *T_vals, void *stream)
 {

@@ -122,6 +122,12 @@ struct CondTensorArgs {
     int *flags;
 };
 
+struct LoadArgs {
+    FormInputs in;        // geometry, mass-rule tables; in.cm = the load coefficient f
+    const int32_t *conn;  // [np][n_elem]
+    double *Fe;           // [np][n_elem] element load vectors
+};
+
 struct SlotGatherArgs {
     int64_t n_slots;
     const int64_t *ptr;    // [n_slots + 1]
@@ -134,6 +140,7 @@ bool form_supported(int D, int P, int nqm, int nqc);
 hipError_t launch_coeff_product(const CoeffProductArgs &a, int D, int P, int nq, hipStream_t st);
 hipError_t launch_cond_tensor(const CondTensorArgs &a, int D, int P, int nq, hipStream_t st);
 hipError_t launch_slot_gather(const SlotGatherArgs &a, hipStream_t st);
+hipError_t launch_load(const LoadArgs &a, int D, int P, int nq, hipStream_t st);
 hipError_t launch_form(const FormArgs &a, int D, int P, int nqm, int nqc, int precision, hipStream_t st);
 hipError_t launch_expand(const ExpandArgs &a, hipStream_t st);
 hipError_t launch_fused(const JobTable &jt, int D, int P, int nqm, int nqc, int precision, hipStream_t st);

@@ -207,6 +207,72 @@ hipError_t launch_cond_tensor(const CondTensorArgs &a, int D, int P, int nq, hip
     return hipErrorInvalidValue;
 }
 
+// Element load vectors (Section 2, f_i = int f phi_i; the vector analogue of
+// Algorithm 2, V = Phi Lambda): Fe[a][e] = sum_q phi_a(xhat_q) w_q f_q |det B_e|, one
+// thread per element.
+template <int D, int P, int NQ>
+__global__ __launch_bounds__(256) void load_elem_kernel(LoadArgs a)
+{
+    using S = Shape<D, P>;
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t ne = a.in.n_elem;
+    if (e >= ne) return;
+    double x[D + 1][D];
+#pragma unroll
+    for (int k = 0; k <= D; ++k) {
+        const int32_t node = a.conn[k * ne + e];
+#pragma unroll
+        for (int c = 0; c < D; ++c) x[k][c] = a.in.coords[c * a.in.n_nodes + node];
+    }
+    double babs, A[S::NG];
+    geometry_from<D>(x, babs, A);
+    const CoeffDev &f = a.in.cm;
+    double u[S::NP];
+    if (f.kind == 1) {
+#pragma unroll
+        for (int i = 0; i < S::NP; ++i) u[i] = f.field[a.conn[i * ne + e]];
+    }
+    double fe[S::NP];
+#pragma unroll
+    for (int i = 0; i < S::NP; ++i) fe[i] = 0.0;
+    bool ok = true;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        double s;
+        if (f.kind == 0) {
+            s = f.value;
+        } else if (f.kind == 1) {
+            double uh = 0.0;
+#pragma unroll
+            for (int i = 0; i < S::NP; ++i) uh = fma(uniform_table(a.in.phi_m)[i * NQ + q], u[i], uh);
+            s = apply_law(f, uh);
+        } else {
+            s = apply_law(f, f.field[q * ne + e]);
+        }
+        const double lam = uniform_table(a.in.w_m)[q] * s * babs;
+        ok &= isfinite(lam);
+#pragma unroll
+        for (int i = 0; i < S::NP; ++i) fe[i] = fma(uniform_table(a.in.phi_m)[i * NQ + q], lam, fe[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < S::NP; ++i) a.Fe[i * ne + e] = fe[i];
+    if (!ok) atomicOr(a.in.flags, 1);
+}
+
+hipError_t launch_load(const LoadArgs &a, int D, int P, int nq, hipStream_t st)
+{
+    if (a.in.n_elem == 0) return hipSuccess;
+    const unsigned grid = unsigned((a.in.n_elem + 255) / 256);
+#define X(d, p, m, c)                                                  \
+    if (D == d && P == p && nq == m) {                                 \
+        load_elem_kernel<d, p, m><<<grid, 256, 0, st>>>(a);            \
+        return hipGetLastError();                                      \
+    }
+    QXA_FORM_CASES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
 // out[t] = sum of src over the entries of slot t, in their stored order (deterministic).
 __global__ __launch_bounds__(256) void slot_gather_kernel(SlotGatherArgs a)
 {
