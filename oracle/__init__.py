@@ -35,7 +35,7 @@ def build(force: bool = False) -> str:
 
 class _Coeff(C.Structure):
     _fields_ = [("kind", C.c_int), ("law", C.c_int), ("value", C.c_double),
-                ("a", C.c_double * 3), ("field", C.c_void_p)]
+                ("a", C.c_double * 3), ("field", C.c_void_p), ("tensor", C.c_void_p)]
 
 
 _lib = None
@@ -147,25 +147,30 @@ def pattern(mesh):
     return row_ptr, col_idx
 
 
-def _common(mesh, rule_m, rule_c, law_m, law_c, field_m, field_c, qpoint_m=None, qpoint_c=None):
+def _common(mesh, rule_m, rule_c, law_m, law_c, field_m, field_c, qpoint_m=None, qpoint_c=None, tensor_c=None):
     conn = np.ascontiguousarray(mesh["conn"], dtype=np.int32)
     coords = np.ascontiguousarray(mesh["coords"], dtype=np.float64)
     pm, wm = (np.ascontiguousarray(a, dtype=np.float64) for a in rule_m)
     pc, wc = (np.ascontiguousarray(a, dtype=np.float64) for a in rule_c)
     cm, km = _coeff(law_m, field_m, qpoint_m)
     cc, kc = _coeff(law_c, field_c, qpoint_c)
+    if tensor_c is not None:
+        kc = (kc, np.ascontiguousarray(tensor_c, dtype=np.float64))
+        cc.tensor = kc[1].ctypes.data
     args = [mesh["dim"], mesh["order"], coords.shape[1], coords.reshape(-1), conn.shape[1], conn.reshape(-1),
             wm.size, pm.reshape(-1), wm, wc.size, pc.reshape(-1), wc, C.byref(cm), C.byref(cc)]
     return args, (conn, coords, pm, wm, pc, wc, cm, cc, km, kc)
 
 
 def assemble(mesh, rule_m, rule_c, law_m, law_c, field_m=None, field_c=None, nthreads=0,
-             qpoint_m=None, qpoint_c=None):
-    """Full CSR assembly: returns (row_ptr int64, col_idx int32, M float64, C float64)."""
+             qpoint_m=None, qpoint_c=None, tensor_c=None):
+    """Full CSR assembly: returns (row_ptr int64, col_idx int32, M float64, C float64).
+    tensor_c: upper triangle (row-major) of a constant symmetric conductivity tensor K
+    (anisotropic conductivity c K), or None for the isotropic case."""
     row_ptr, col_idx = pattern(mesh)
     M = np.zeros(col_idx.size)
     Cv = np.zeros(col_idx.size)
-    args, keep = _common(mesh, rule_m, rule_c, law_m, law_c, field_m, field_c, qpoint_m, qpoint_c)
+    args, keep = _common(mesh, rule_m, rule_c, law_m, law_c, field_m, field_c, qpoint_m, qpoint_c, tensor_c)
     bad = C.c_int64(-1)
     rc = _load().oracle_assemble(*args, row_ptr, col_idx, M, Cv, int(nthreads), C.byref(bad))
     if rc:
@@ -227,13 +232,17 @@ def qpoint_coeff(mesh, elems, rule, law, field=None):
     return out.reshape(-1, w.size)
 
 
-def _tensor_product(fn, mesh, rule, law, u, v, nthreads):
+def _tensor_product(fn, mesh, rule, law, u, v, nthreads, tensor=None):
     row_ptr, col_idx = pattern(mesh)
     out = np.zeros(col_idx.size)
     conn = np.ascontiguousarray(mesh["conn"], dtype=np.int32)
     coords = np.ascontiguousarray(mesh["coords"], dtype=np.float64)
     pts, w = (np.ascontiguousarray(a, dtype=np.float64) for a in rule)
     c, keep = _coeff(law, u)
+    kt = None
+    if tensor is not None:
+        kt = np.ascontiguousarray(tensor, dtype=np.float64)
+        c.tensor = kt.ctypes.data
     vv = np.ascontiguousarray(v, dtype=np.float64)
     bad = C.c_int64(-1)
     rc = getattr(_load(), fn)(mesh["dim"], mesh["order"], coords.shape[1], coords.reshape(-1), conn.shape[1],
@@ -244,10 +253,10 @@ def _tensor_product(fn, mesh, rule, law, u, v, nthreads):
     return row_ptr, col_idx, out
 
 
-def cond_tensor_product(mesh, rule, law_dc, u, v, nthreads=0):
+def cond_tensor_product(mesh, rule, law_dc, u, v, nthreads=0, tensor=None):
     """The conductivity tensor of Section 5 (C_ijk = int c'(u_h) grad phi_i . grad phi_j phi_k)
     contracted with v in its second mode, in the CSR pattern (row i, column k; not symmetric)."""
-    return _tensor_product("oracle_cond_tensor_product", mesh, rule, law_dc, u, v, nthreads)
+    return _tensor_product("oracle_cond_tensor_product", mesh, rule, law_dc, u, v, nthreads, tensor)
 
 
 def mass_tensor_product(mesh, rule, law_dm, u, v, nthreads=0):

@@ -228,7 +228,29 @@ typedef struct {
     double value;        /* constant value (kind 0) */
     double a[3];
     const double *field; /* kind 1: [n_nodes]; kind 2: [n_q][n_e] */
+    const double *tensor; /* conductivity only: upper triangle (row-major) of a symmetric
+                             d x d tensor K (Section 7, anisotropic conductivity), or NULL */
 } oracle_coeff;
+
+/* A_e = B^{-1} K B^{-T} (K = identity when tensor is NULL), full d x d. */
+static void metric(int d, const double *Binv, const double *tensor, double *A)
+{
+    double K[MAXD * MAXD];
+    for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) K[a * d + b] = (a == b) ? 1.0 : 0.0;
+    if (tensor) {
+        int g = 0;
+        for (int a = 0; a < d; ++a)
+            for (int b = a; b < d; ++b, ++g) K[a * d + b] = K[b * d + a] = tensor[g];
+    }
+    for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) {
+            double s = 0.0;
+            for (int k = 0; k < d; ++k)
+                for (int l = 0; l < d; ++l) s += Binv[a * d + k] * K[k * d + l] * Binv[b * d + l];
+            A[a * d + b] = s;
+        }
+}
 
 static double apply_law(const oracle_coeff *c, double s)
 {
@@ -317,16 +339,20 @@ static int element_matrices(const refdata *R, const double *coords, int64_t n_no
     double adet = fabs(det);
     if (!(adet > 1e-14 * pow(maxedge, d))) return -3;
     if (g_fault == 1) adet = 1.0;           /* planted: dropped |det B_e| */
-    /* A_e = B^{-1} B^{-T} */
-    for (int a = 0; a < d; ++a)
-        for (int b = 0; b < d; ++b) {
-            double s = 0.0;
-            for (int k = 0; k < d; ++k) {
-                if (g_fault == 2) s += Binv[k * d + a] * Binv[k * d + b];   /* planted: B^{-T} B^{-1} */
-                else s += Binv[a * d + k] * Binv[b * d + k];
+    /* A_e = B^{-1} B^{-T}, or B^{-1} K B^{-T} for an anisotropic conductivity */
+    if (cc->tensor && g_fault != 2) {
+        metric(d, Binv, cc->tensor, A);
+    } else {
+        for (int a = 0; a < d; ++a)
+            for (int b = 0; b < d; ++b) {
+                double s = 0.0;
+                for (int k = 0; k < d; ++k) {
+                    if (g_fault == 2) s += Binv[k * d + a] * Binv[k * d + b];   /* planted: B^{-T} B^{-1} */
+                    else s += Binv[a * d + k] * Binv[b * d + k];
+                }
+                A[a * d + b] = s;
             }
-            A[a * d + b] = s;
-        }
+    }
     for (int i = 0; i < n * n; ++i) {
         Me[i] = 0.0;
         Ce[i] = 0.0;
@@ -829,12 +855,7 @@ int oracle_cond_tensor_product(int dim, int P, int64_t n_nodes, const double *co
             }
             continue;
         }
-        for (int a = 0; a < d; ++a)
-            for (int b = 0; b < d; ++b) {
-                double s = 0.0;
-                for (int k = 0; k < d; ++k) s += Binv[a * d + k] * Binv[b * d + k];
-                A[a * d + b] = s;
-            }
+        metric(d, Binv, cdc->tensor, A);
         for (int t = 0; t < n * n * n; ++t) Ce[t] = 0.0;
         for (int q = 0; q < nq; ++q) {
             const double *ph = R.phi_m + (size_t)q * n;
