@@ -82,13 +82,19 @@ typedef struct {
 
 /* kind = QXA_COEFF_CONST: s = value.
  * kind = QXA_COEFF_NODAL: field = device array [n_nodes]; s = law(u_h(x_q)).
- * kind = QXA_COEFF_QPOINT: field = device array [n_q][n_elem]; s = law(field[q][e]). */
+ * kind = QXA_COEFF_QPOINT: field = device array [n_q][n_elem]; s = law(field[q][e]).
+ * tensor (conductivity coefficients only, else NULL): host array of the upper
+ * triangle, row-major, of a constant symmetric d x d tensor K (2D: K00, K01, K11;
+ * 3D: K00, K01, K02, K11, K12, K22); the conductivity is then s K, the anisotropic
+ * case of Section 7 with A_qe = B_e^{-1} s_q K B_e^{-T}. NULL: isotropic (K = I).
+ * Read during the call (qxa_server_submit copies it). */
 typedef struct {
     int kind;
     int law;
     double value;
     double a[3];
     const double *field;
+    const double *tensor;
 } qxa_coeff;
 
 typedef struct qxa_mesh_s *qxa_mesh;

@@ -38,7 +38,7 @@ class _Quad(C.Structure):
 
 class _Coeff(C.Structure):
     _fields_ = [("kind", C.c_int), ("law", C.c_int), ("value", C.c_double), ("a", C.c_double * 3),
-                ("field", C.c_void_p)]
+                ("field", C.c_void_p), ("tensor", C.c_void_p)]
 
 
 class _PlanInfo(C.Structure):
@@ -264,13 +264,18 @@ def plan_check_host(dim, order, coords, conn):
     return nt.value, npart.value
 
 
-def make_coeff(law, field=None, qpoint=False):
-    """Build the ABI coefficient struct; returns (struct, keepalive)."""
+def make_coeff(law, field=None, qpoint=False, tensor=None):
+    """Build the ABI coefficient struct; returns (struct, keepalive). tensor: upper triangle
+    (row-major) of a constant symmetric conductivity tensor K, for conductivity coefficients."""
     c = _Coeff()
     c.a[0] = c.a[1] = c.a[2] = 0.0
+    kt = None
+    if tensor is not None:
+        kt = np.ascontiguousarray(tensor, dtype=np.float64)
+        c.tensor = kt.ctypes.data
     if law[0] == "const":
         c.kind, c.law, c.value, c.field = 0, 0, float(law[1]), None
-        return c, None
+        return c, kt
     c.law = _LAW[law[0]]
     for k, v in enumerate(law[1:]):
         c.a[k] = float(v)
@@ -279,7 +284,7 @@ def make_coeff(law, field=None, qpoint=False):
     c.kind = 2 if qpoint else 1
     c.field = field.data_ptr()
     c.value = 0.0
-    return c, field
+    return c, (field, kt)
 
 
 def _precision(p):
@@ -287,7 +292,7 @@ def _precision(p):
 
 
 def assemble(plan: Plan, law_m, law_c, field_m=None, field_c=None, precision="fp64", M=None, Cv=None,
-             stream=None, want_m=True, want_c=True, qpoint=False):
+             stream=None, want_m=True, want_c=True, qpoint=False, tensor=None):
     """One assembly into CSR value arrays (device float64 tensors of length nnz)."""
     import torch
     dev = torch.device("cuda", plan.mesh.device)
@@ -296,7 +301,7 @@ def assemble(plan: Plan, law_m, law_c, field_m=None, field_c=None, precision="fp
     if want_c and Cv is None:
         Cv = torch.empty(plan.nnz, dtype=torch.float64, device=dev)
     cm, k1 = make_coeff(law_m, field_m, qpoint)
-    cc, k2 = make_coeff(law_c, field_c, qpoint)
+    cc, k2 = make_coeff(law_c, field_c, qpoint, tensor)
     check(lib().qxa_assemble(plan.handle, C.byref(cm), C.byref(cc), _precision(precision),
                              _ptr(M if want_m else None), _ptr(Cv if want_c else None), _stream_ptr(stream)))
     return M, Cv
@@ -324,14 +329,14 @@ def mass_tensor_product(plan: Plan, law_dm, u, v, T=None, S=None, stream=None):
     return T, S
 
 
-def cond_tensor_product(plan: Plan, law_dc, u, v, T=None, stream=None):
+def cond_tensor_product(plan: Plan, law_dc, u, v, T=None, stream=None, tensor=None):
     """The conductivity tensor of the Newton Jacobian (C_ijk = int c'(u_h) grad phi_i .
     grad phi_j phi_k) contracted with v in its second mode, as values in the plan's CSR
     pattern (row i, column k; not symmetric)."""
     import torch
     if T is None:
         T = torch.empty(plan.nnz, dtype=torch.float64, device=torch.device("cuda", plan.mesh.device))
-    c, keep = make_coeff(law_dc, u)
+    c, keep = make_coeff(law_dc, u, tensor=tensor)
     check(lib().qxa_cond_tensor_product(plan.handle, C.byref(c), _ptr(v), _ptr(T), _stream_ptr(stream)))
     return T
 
@@ -424,12 +429,12 @@ class Server:
         self._meshes = {}  # resident plans refer to their meshes: keep them until close()
 
     def submit(self, mesh: Mesh, rule_m, rule_c=None, law_m=("const", 1.0), law_c=("const", 1.0), field_m=None,
-               field_c=None, precision="fp64", tag=0, qpoint=False):
+               field_c=None, precision="fp64", tag=0, qpoint=False, tensor=None):
         rule_c = rule_m if rule_c is None else rule_c
         qm, km = _quad(rule_m, mesh.dim)
         qc, kc = _quad(rule_c, mesh.dim)
         cm, k1 = make_coeff(law_m, field_m, qpoint)
-        cc, k2 = make_coeff(law_c, field_c, qpoint)
+        cc, k2 = make_coeff(law_c, field_c, qpoint, tensor)
         job = _Job(mesh.handle, qm, qc, cm, cc, _precision(precision), int(tag))
         t = C.c_uint64()
         check(lib().qxa_server_submit(self.handle, C.byref(job), C.byref(t)))

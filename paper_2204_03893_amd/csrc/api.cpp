@@ -91,6 +91,23 @@ static qxa_status to_coeff(const qxa_coeff *c, CoeffDev &out, const char *which)
     return QXA_OK;
 }
 
+// The conductivity tensor of a stiffness coefficient (host array, d(d+1)/2 upper
+// entries); the mass coefficient has none.
+static qxa_status to_tensor(const qxa_coeff *mass, const qxa_coeff *stiff, int dim, int &aniso, double (&K)[6])
+{
+    aniso = 0;
+    for (int g = 0; g < 6; ++g) K[g] = 0.0;
+    if (mass && mass->tensor) return fail(QXA_E_INVALID, "mass coefficient: a tensor applies to conductivity only");
+    if (!stiff || !stiff->tensor) return QXA_OK;
+    const int ng = dim * (dim + 1) / 2;
+    for (int g = 0; g < ng; ++g) {
+        if (!std::isfinite(stiff->tensor[g])) return fail(QXA_E_NONFINITE, "conductivity tensor: non-finite entry");
+        K[g] = stiff->tensor[g];
+    }
+    aniso = 1;
+    return QXA_OK;
+}
+
 static uint16_t bf16_bits(float x)
 {
     uint32_t u;
@@ -539,6 +556,7 @@ static qxa_status fill_inputs(qxa_plan p, const qxa_coeff *mass, const qxa_coeff
                     "conductivity nodes); use QXA_FP32 as the reduced-precision form here");
     qxa_status st = to_coeff(mass, in.cm, "mass");
     if (!st) st = to_coeff(stiff, in.cc, "stiffness");
+    if (!st) st = to_tensor(mass, stiff, p->ref.dim, in.aniso, in.K);
     if (st) return st;
     const qxa_mesh m = p->mesh;
     in.n_nodes = m->n_nodes;
@@ -657,6 +675,7 @@ qxa_status qxa_coeff_product(qxa_plan p, int rule, const qxa_coeff *c, const dou
     if (rule != 0 && rule != 1) return fail(QXA_E_INVALID, "rule: 0 (mass rule) or 1 (stiffness rule)");
     if (!p->d_flags) return fail(QXA_E_INVALID, "plan is owned by a server");
     if (c->kind != QXA_COEFF_NODAL) return fail(QXA_E_INVALID, "the first factor is a nodal field through a law");
+    if (c->tensor) return fail(QXA_E_INVALID, "the first factor has no tensor");
     CoeffProductArgs a{};
     qxa_status st = to_coeff(c, a.c, "first factor");
     if (st) return st;
@@ -778,6 +797,7 @@ qxa_status qxa_cond_tensor_product(qxa_plan p, const qxa_coeff *c, const double 
     if (c->kind != QXA_COEFF_NODAL) return fail(QXA_E_INVALID, "c' is a nodal field through a law");
     CondTensorArgs a{};
     qxa_status st = to_coeff(c, a.c, "c'");
+    if (!st) st = to_tensor(nullptr, c, p->ref.dim, a.aniso, a.K);
     if (st) return st;
     if (p->mesh->n_elem == 0) return QXA_OK;
     QXA_HIP(hipSetDevice(p->mesh->device));

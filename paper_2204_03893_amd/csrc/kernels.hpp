@@ -117,6 +117,8 @@ struct CondTensorArgs {
     const double *phi;     // [np][nq]
     const double *dphi;    // [nq][np][dim]
     CoeffDev c;            // law of c'; c.field = u [n_nodes]
+    int aniso;             // conductivity tensor K instead of the identity
+    double K[6];
     const double *v;       // [n_nodes]
     double *T;             // [np*np][n_elem] local matrices (row a, column b)
     int *flags;

@@ -33,13 +33,57 @@ __device__ __forceinline__ double apply_law(const CoeffDev &c, double s)
     return s;
 }
 
+// A = I K I^T from the inverse I = B_e^{-1}, as its d(d+1)/2 upper entries in
+// row-major order; K = identity unless aniso (K: upper triangle, row-major, of the
+// symmetric conductivity tensor, Section 7).
+template <int D>
+__device__ __forceinline__ void metric_from_inverse(const double (&I)[D][D], int aniso, const double *K, double *A)
+{
+    if (!aniso) {
+        int g = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int b = a; b < D; ++b, ++g) {
+                double s = I[a][0] * I[b][0];
+#pragma unroll
+                for (int k = 1; k < D; ++k) s += I[a][k] * I[b][k];
+                A[g] = s;
+            }
+        return;
+    }
+    double Kf[D][D];
+    {
+        int g = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int b = a; b < D; ++b, ++g) Kf[a][b] = Kf[b][a] = K[g];
+    }
+    int g = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = a; b < D; ++b, ++g) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                double t = 0.0;
+#pragma unroll
+                for (int l = 0; l < D; ++l) t = fma(Kf[k][l], I[b][l], t);
+                s = fma(I[a][k], t, s);
+            }
+            A[g] = s;
+        }
+}
+
 // Geometry of Section 3 (affine map x = a_0 + B_e xhat, B_e = [a_1-a_0, ..., a_d-a_0])
 // and Section 4 (b_e = |det B_e|, W column = vec(A_e), A_e = (B_e^T B_e)^{-1}
 // = B_e^{-1} B_e^{-T}), symmetric A_e stored as its d(d+1)/2 upper entries
 // in row-major order: 2D (00,01,11), 3D (00,01,02,11,12,22).
 template <int D>
 __device__ __forceinline__ void element_geometry(const double *__restrict__ xyz, int64_t n_nodes, const int32_t *v,
-                                                 double &babs, double *A)
+                                                 double &babs, double *A, int aniso = 0, const double *K = nullptr)
 {
     if constexpr (D == 2) {
         const double x0 = xyz[v[0]], y0 = xyz[n_nodes + v[0]];
@@ -48,11 +92,9 @@ __device__ __forceinline__ void element_geometry(const double *__restrict__ xyz,
         const double det = b00 * b11 - b01 * b10;
         const double r = 1.0 / det;
         // B^{-1} = adj(B) / det
-        const double i00 = b11 * r, i01 = -b01 * r, i10 = -b10 * r, i11 = b00 * r;
+        const double I[2][2] = {{b11 * r, -b01 * r}, {-b10 * r, b00 * r}};
         babs = fabs(det);
-        A[0] = i00 * i00 + i01 * i01;
-        A[1] = i00 * i10 + i01 * i11;
-        A[2] = i10 * i10 + i11 * i11;
+        metric_from_inverse<2>(I, aniso, K, A);
     } else {
         double B[3][3];
         const double x0 = xyz[v[0]], y0 = xyz[n_nodes + v[0]], z0 = xyz[2 * n_nodes + v[0]];
@@ -77,11 +119,7 @@ __device__ __forceinline__ void element_geometry(const double *__restrict__ xyz,
         // Binv[a][k] = cof[k][a] / det
         const double I[3][3] = {{c00 * r, c10 * r, c20 * r}, {c01 * r, c11 * r, c21 * r}, {c02 * r, c12 * r, c22 * r}};
         babs = fabs(det);
-        int g = 0;
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = a; b < 3; ++b, ++g) A[g] = I[a][0] * I[b][0] + I[a][1] * I[b][1] + I[a][2] * I[b][2];
+        metric_from_inverse<3>(I, aniso, K, A);
     }
 }
 
@@ -90,6 +128,8 @@ struct FormInputs {
     int64_t n_nodes, n_elem;
     const double *coords;  // [dim][n_nodes]
     CoeffDev cm, cc;
+    int aniso;    // conductivity tensor K (upper triangle, row-major) instead of the identity
+    double K[6];
     const double *w_m, *w_c;      // [nq]
     const double *phi_m, *phi_c;  // [np][nq]
     int *flags;
@@ -112,7 +152,7 @@ __device__ __forceinline__ bool element_setup(const FormInputs &in, const int32_
 {
     constexpr int NP = Shape<D, P>::NP;
     double babs;
-    element_geometry<D>(in.coords, in.n_nodes, v, babs, A);
+    element_geometry<D>(in.coords, in.n_nodes, v, babs, A, in.aniso, in.K);
     double um[NP];
     if (in.cm.kind == 1 || in.cc.kind == 1) {
         const double *f = in.cm.kind == 1 ? in.cm.field : in.cc.field;
@@ -190,18 +230,17 @@ __device__ __forceinline__ void gather_raw(const FormInputs &in, const int32_t *
 
 // Geometry from gathered vertex coordinates (same arithmetic as element_geometry).
 template <int D>
-__device__ __forceinline__ void geometry_from(const double (&x)[D + 1][D], double &babs, double *A)
+__device__ __forceinline__ void geometry_from(const double (&x)[D + 1][D], double &babs, double *A, int aniso = 0,
+                                              const double *K = nullptr)
 {
     if constexpr (D == 2) {
         const double b00 = x[1][0] - x[0][0], b10 = x[1][1] - x[0][1];
         const double b01 = x[2][0] - x[0][0], b11 = x[2][1] - x[0][1];
         const double det = b00 * b11 - b01 * b10;
         const double r = 1.0 / det;
-        const double i00 = b11 * r, i01 = -b01 * r, i10 = -b10 * r, i11 = b00 * r;
+        const double I[2][2] = {{b11 * r, -b01 * r}, {-b10 * r, b00 * r}};
         babs = fabs(det);
-        A[0] = i00 * i00 + i01 * i01;
-        A[1] = i00 * i10 + i01 * i11;
-        A[2] = i10 * i10 + i11 * i11;
+        metric_from_inverse<2>(I, aniso, K, A);
     } else {
         double B[3][3];
 #pragma unroll
@@ -221,11 +260,7 @@ __device__ __forceinline__ void geometry_from(const double (&x)[D + 1][D], doubl
         const double r = 1.0 / det;
         const double I[3][3] = {{c00 * r, c10 * r, c20 * r}, {c01 * r, c11 * r, c21 * r}, {c02 * r, c12 * r, c22 * r}};
         babs = fabs(det);
-        int g = 0;
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = a; b < 3; ++b, ++g) A[g] = I[a][0] * I[b][0] + I[a][1] * I[b][1] + I[a][2] * I[b][2];
+        metric_from_inverse<3>(I, aniso, K, A);
     }
 }
 
@@ -238,7 +273,7 @@ __device__ __forceinline__ bool setup_from_raw(const FormInputs &in, const RawEl
 {
     constexpr int NP = Shape<D, P>::NP;
     double babs;
-    geometry_from<D>(r.x, babs, A);
+    geometry_from<D>(r.x, babs, A, in.aniso, in.K);
     bool ok = true;
 #pragma unroll
     for (int q = 0; q < NQM; ++q) {

@@ -449,7 +449,7 @@ __device__ __forceinline__ bool lane_setup(const FormInputs &in, const RawElem<D
     using L = LaneQ<NQM, NQC, Shape<D, P>::NG>;
     constexpr int NP = Shape<D, P>::NP;
     double babs;
-    geometry_from<D>(r.x, babs, A);
+    geometry_from<D>(r.x, babs, A, in.aniso, in.K);
     bool ok = true;
 #pragma unroll
     for (int m = 0; m < L::MM; ++m) {
@@ -638,7 +638,7 @@ struct WideProducer {
 #pragma unroll
                 for (int c = 0; c < D; ++c) x[v][c] = r[v * D + c];
             double babs, A[NG];
-            geometry_from<D>(x, babs, A);
+            geometry_from<D>(x, babs, A, in.aniso, in.K);
             const bool live = p < in.n_elem;
             if (which == NQL) {
 #pragma unroll

@@ -143,7 +143,7 @@ __global__ __launch_bounds__(256) void cond_tensor_rows_kernel(CondTensorArgs a)
         for (int c = 0; c < D; ++c) x[k][c] = a.coords[c * a.n_nodes + node];
     }
     double babs, Au[S::NG];
-    geometry_from<D>(x, babs, Au);
+    geometry_from<D>(x, babs, Au, a.aniso, a.K);
     double A[D][D];
     {
         int g = 0;

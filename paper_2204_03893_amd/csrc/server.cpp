@@ -128,6 +128,7 @@ struct Job {
     uint64_t ticket = 0;
     qxa_job spec{};
     std::vector<double> mr_pts, mr_w, cr_pts, cr_w;
+    double tensor[6] = {0, 0, 0, 0, 0, 0};  // copy of the conductivity tensor, if any
     PlanKey key;
     CacheEntry *entry = nullptr;
     int plan_cached = -1;  // unknown until the first cache lookup
@@ -638,6 +639,11 @@ qxa_status qxa_server_submit(qxa_server s, const qxa_job *job, uint64_t *ticket)
     j->spec.mass_rule.weights = j->mr_w.data();
     j->spec.stiff_rule.points = j->cr_pts.data();
     j->spec.stiff_rule.weights = j->cr_w.data();
+    if (job->mass.tensor) return fail(QXA_E_INVALID, "mass coefficient: a tensor applies to conductivity only");
+    if (job->stiff.tensor) {
+        std::copy(job->stiff.tensor, job->stiff.tensor + m->dim * (m->dim + 1) / 2, j->tensor);
+        j->spec.stiff.tensor = j->tensor;
+    }
     j->key = PlanKey{m->serial, rule_words(j->spec.mass_rule, j->spec.stiff_rule)};
     j->t_submit = Clock::now();
     std::lock_guard<std::mutex> lk(s->mu);
