@@ -518,14 +518,14 @@ struct FormTraits<QXA_FP64> {
 // tiles with a two-buffer pipeline: waves 0-3 (producers, 16 elements each,
 // T = 64; waves 0-7 for T = 16, see WideProducer) gather, set up and contract
 // tile i into LDS buffer i % 2 while the other waves (consumers) reduce tile
-// i-1 from the other buffer; one LDS-only barrier
-// per tile separates the two. Producers issue only loads (the next tile's
-// gathers and connectivity), consumers only record loads and stores, so
-// neither role waits on the other's memory traffic. Consumers walk a tile's
-// records in chunks of CH rounds, loading chunk c+1 (or the next tile's
-// first chunk) before storing chunk c; every round issues at least two stores
-// (buffer stores that drop the lanes with nothing to write), so each wait for
-// records leaves the stores behind them in flight.
+// i-1 from the other buffer; one LDS-only barrier per tile separates the two.
+// Producers issue only loads (the next tile's gathers and connectivity),
+// consumers only output-unit loads and stores, so neither role waits on the
+// other's memory traffic. Consumers walk a tile's units in chunks of CH
+// rounds, loading chunk c+1 (or the next tile's first chunk) before storing
+// chunk c; every round issues at least two stores (buffer stores that drop the
+// lanes with nothing to write), so each wait for units leaves the stores
+// behind them in flight.
 // producer threads: 4 waves of one 16-element group each, or 8 waves for T = 16
 constexpr int ws_producers(int T) { return T == 16 ? 512 : 256; }
 // unit rounds per consumer chunk, sized so that one chunk holds all of a

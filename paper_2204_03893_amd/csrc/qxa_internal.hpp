@@ -91,7 +91,7 @@ struct TilePlan {
     std::vector<int64_t> rec_ptr;     // [n_tiles + 1] (in units)
     std::vector<int64_t> rec_mid;     // [n_tiles] first single unit of the tile
     // Partials of shared upper slot k (CSR order) are part_ptr[k] ..
-    // part_ptr[k+1] - 1, in ascending tile order, then record order.
+    // part_ptr[k+1] - 1, in ascending tile order, then unit order.
     std::vector<int64_t> part_ptr;    // [n_shared + 1]
     // fix-up: shared upper slot k (ascending CSR order) and its mirror slot
     std::vector<int32_t> fix_target;  // [n_shared]

@@ -146,7 +146,7 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
     tp.n_shared = int64_t(sh_slot.size());
     tp.n_partials = tp.part_ptr.back();
     if (tp.n_partials >= (int64_t(1) << 31)) return fail(QXA_E_UNSUPPORTED, "too many partials");
-    // records per tile: owned outputs (upper and mirror) sorted by CSR slot,
+    // output units per tile: owned outputs (upper and mirror) sorted by CSR slot,
     // then the tile's partials; a partial's index is fixed in a second,
     // sequential pass over the tiles in ascending order
     std::vector<std::vector<uint32_t>> trec(nt);
