@@ -58,6 +58,7 @@ def _load():
         common = [C.c_int, C.c_int, C.c_int64, _D, C.c_int64, _I32, C.c_int, _D, _D, C.c_int, _D, _D,
                   C.POINTER(_Coeff), C.POINTER(_Coeff)]
         lib.oracle_assemble.argtypes = common + [_I64, _I32, _D, _D, C.c_int, C.POINTER(C.c_int64)]
+        lib.oracle_assemble_iso.argtypes = common + [_I64, _I32, _D, _D, C.c_int, C.POINTER(C.c_int64)]
         lib.oracle_assemble_rows.argtypes = common + [C.c_int64, _I64, _I64, _I32, _D, _D, C.c_int,
                                                       C.POINTER(C.c_int64)]
         lib.oracle_rows_pattern.argtypes = [C.c_int, C.c_int, C.c_int64, C.c_int64, _I32, C.c_int64, _I64,
@@ -292,3 +293,17 @@ def load_vector(mesh, rule, law_f, field=None, qpoint=None):
     if rc:
         raise ValueError(f"oracle load_vector failed ({rc}), element {bad.value}")
     return F
+
+
+def assemble_iso(mesh, rule_m, rule_c, law_m, law_c, field_m=None, field_c=None, nthreads=0, tensor_c=None):
+    """Isoparametric assembly (the element map uses the P-order basis and every node's
+    position): returns (row_ptr, col_idx, M, C)."""
+    row_ptr, col_idx = pattern(mesh)
+    M = np.zeros(col_idx.size)
+    Cv = np.zeros(col_idx.size)
+    args, keep = _common(mesh, rule_m, rule_c, law_m, law_c, field_m, field_c, None, None, tensor_c)
+    bad = C.c_int64(-1)
+    rc = _load().oracle_assemble_iso(*args, row_ptr, col_idx, M, Cv, int(nthreads), C.byref(bad))
+    if rc:
+        raise ValueError(f"oracle assemble_iso failed ({rc}), element {bad.value}")
+    return row_ptr, col_idx, M, Cv

@@ -924,3 +924,94 @@ int oracle_load_vector(int dim, int P, int64_t n_nodes, const double *coords, in
     free(comp);
     return 0;
 }
+
+/*
+ * Isoparametric elements (Section 7, curved geometry): the element map uses the same
+ * Lagrange basis as the unknowns, x(xhat) = sum_i x_i phi_i(xhat), so B is evaluated per
+ * quadrature node, B_q = sum_i x_i grad phi_i(xhat_q)^T, with |det B_q| and
+ * A_q = B_q^{-1} B_q^{-T} per node (LU per node):
+ *   M_e = sum_q w_q m_q phi_q phi_q^T |det B_q|,  C_e = sum_q w_q c_q J_q A_q J_q^T |det B_q|.
+ * The local matrices are added into the CSR pattern like the affine ones.
+ */
+static int element_matrices_iso(const refdata *R, const double *coords, int64_t n_nodes, const int32_t *conn,
+                                int64_t n_e, int64_t e, const oracle_coeff *cm, const oracle_coeff *cc, double *Me,
+                                double *Ce)
+{
+    int d = R->dim, n = R->n;
+    for (int i = 0; i < n * n; ++i) Me[i] = Ce[i] = 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+        int nq = pass == 0 ? R->nq_m : R->nq_c;
+        const double *phi = pass == 0 ? R->phi_m : R->phi_c;
+        const double *dphi = pass == 0 ? R->dphi_m : R->dphi_c;
+        const double *w = pass == 0 ? R->w_m : R->w_c;
+        for (int q = 0; q < nq; ++q) {
+            const double *ph = phi + (size_t)q * n, *Jq = dphi + (size_t)q * n * d;
+            double B[MAXD * MAXD], Binv[MAXD * MAXD], A[MAXD * MAXD];
+            for (int r = 0; r < d; ++r)
+                for (int c = 0; c < d; ++c) {
+                    double s = 0.0;
+                    for (int i = 0; i < n; ++i) s += coords[(size_t)r * n_nodes + conn[(size_t)i * n_e + e]] * Jq[i * d + c];
+                    B[r * d + c] = s;
+                }
+            for (int i = 0; i < d * d; ++i) Binv[i] = (i % (d + 1) == 0) ? 1.0 : 0.0;
+            double adet = fabs(gauss_solve(d, B, d, Binv));
+            if (!(adet > 0.0)) return -3;
+            if (pass == 0) {
+                double lam = w[q] * coeff_at(cm, ph, n, conn, n_e, e, q) * adet;
+                for (int i = 0; i < n; ++i)
+                    for (int j = 0; j < n; ++j) Me[i * n + j] += lam * ph[i] * ph[j];
+            } else {
+                metric(d, Binv, cc->tensor, A);
+                double lam = w[q] * coeff_at(cc, ph, n, conn, n_e, e, q) * adet;
+                for (int i = 0; i < n; ++i)
+                    for (int j = 0; j < n; ++j) {
+                        double s = 0.0;
+                        for (int a = 0; a < d; ++a)
+                            for (int b = 0; b < d; ++b) s += Jq[i * d + a] * A[a * d + b] * Jq[j * d + b];
+                        Ce[i * n + j] += lam * s;
+                    }
+            }
+        }
+    }
+    return 0;
+}
+
+int oracle_assemble_iso(int dim, int P, int64_t n_nodes, const double *coords, int64_t n_e, const int32_t *conn,
+                        int nq_m, const double *pts_m, const double *w_m, int nq_c, const double *pts_c,
+                        const double *w_c, const oracle_coeff *cm, const oracle_coeff *cc, const int64_t *row_ptr,
+                        const int32_t *col_idx, double *Mv, double *Cv, int nthreads, int64_t *bad_elem)
+{
+    refdata R;
+    if (ref_setup(&R, dim, P, nq_m, pts_m, w_m, nq_c, pts_c, w_c)) return -1;
+    int n = R.n;
+    double *Mebuf = (double *)malloc(sizeof(double) * (size_t)n_e * n * n);
+    double *Cebuf = (double *)malloc(sizeof(double) * (size_t)n_e * n * n);
+    if (!Mebuf || !Cebuf) {
+        free(Mebuf);
+        free(Cebuf);
+        return -5;
+    }
+    int err = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(static)
+#endif
+    for (int64_t e = 0; e < n_e; ++e) {
+        if (element_matrices_iso(&R, coords, n_nodes, conn, n_e, e, cm, cc, Mebuf + (size_t)e * n * n,
+                                 Cebuf + (size_t)e * n * n)) {
+#ifdef _OPENMP
+#pragma omp critical
+#endif
+            {
+                if (!err || e < *bad_elem) *bad_elem = e;
+                err = -3;
+            }
+        }
+    }
+    if (!err)
+        err = assemble_rows(&R, coords, n_nodes, conn, n_e, cm, cc, n_nodes, NULL, row_ptr, col_idx, Mv, Cv, Mebuf,
+                            Cebuf, nthreads, bad_elem);
+    free(Mebuf);
+    free(Cebuf);
+    return err;
+}
