@@ -249,6 +249,24 @@ qxa_status qxa_cond_tensor_product(qxa_plan plan, const qxa_coeff *c, const doub
 qxa_status qxa_load_vector(qxa_plan plan, const qxa_coeff *f, double *F, void *stream);
 
 /*
+ * Isoparametric (curved) elements (Section 7): the element map uses the P-order
+ * basis and the positions of all of an element's nodes, x(xhat) = sum_i x_i phi_i(xhat),
+ * so B, |det B| and A = B^{-1} K B^{-T} are evaluated at every quadrature node (X_m and
+ * X_c per (q, e); Q_m and Q_c unchanged). Same coefficients, outputs and pattern as
+ * qxa_assemble, in FP64. Two passes: the local matrices of every element (one thread
+ * per (element, row)) to a plan-owned buffer, then one thread per CSR slot sums the
+ * slot's element entries in ascending element order (deterministic, bitwise
+ * symmetric). The first call on a plan builds the slot -> entries map (shared with
+ * qxa_cond_tensor_product: 4 n_p^2 n_elem + 8 (nnz + 1) bytes) and allocates
+ * 16 n_p^2 n_elem bytes of element matrices; later calls allocate nothing. Errors as
+ * qxa_assemble, plus QXA_E_UNSUPPORTED when n_p^2 n_elem >= 2^31; a non-finite
+ * coefficient, or a map with det B_q = 0 at a quadrature node, is reported by qxa_sync
+ * as QXA_E_NONFINITE.
+ */
+qxa_status qxa_assemble_iso(qxa_plan plan, const qxa_coeff *mass, const qxa_coeff *stiff, double *M_vals,
+                            double *C_vals, void *stream);
+
+/*
  * Per-kernel timing with HIP events recorded on the launch stream around every
  * kernel this plan launches (off by default). qxa_plan_timing_report waits for
  * the recorded events, writes a JSON object

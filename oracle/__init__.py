@@ -295,13 +295,14 @@ def load_vector(mesh, rule, law_f, field=None, qpoint=None):
     return F
 
 
-def assemble_iso(mesh, rule_m, rule_c, law_m, law_c, field_m=None, field_c=None, nthreads=0, tensor_c=None):
+def assemble_iso(mesh, rule_m, rule_c, law_m, law_c, field_m=None, field_c=None, nthreads=0, tensor_c=None,
+                 qpoint_m=None, qpoint_c=None):
     """Isoparametric assembly (the element map uses the P-order basis and every node's
     position): returns (row_ptr, col_idx, M, C)."""
     row_ptr, col_idx = pattern(mesh)
     M = np.zeros(col_idx.size)
     Cv = np.zeros(col_idx.size)
-    args, keep = _common(mesh, rule_m, rule_c, law_m, law_c, field_m, field_c, None, None, tensor_c)
+    args, keep = _common(mesh, rule_m, rule_c, law_m, law_c, field_m, field_c, qpoint_m, qpoint_c, tensor_c)
     bad = C.c_int64(-1)
     rc = _load().oracle_assemble_iso(*args, row_ptr, col_idx, M, Cv, int(nthreads), C.byref(bad))
     if rc:

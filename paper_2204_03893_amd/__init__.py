@@ -96,6 +96,7 @@ def lib():
         L.qxa_coeff_product.argtypes = [vp, ci, C.POINTER(_Coeff), vp, vp, vp]
         L.qxa_cond_tensor_product.argtypes = [vp, C.POINTER(_Coeff), vp, vp, vp]
         L.qxa_load_vector.argtypes = [vp, C.POINTER(_Coeff), vp, vp]
+        L.qxa_assemble_iso.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), vp, vp, vp]
         L.qxa_sync.argtypes = [vp, vp]
         L.qxa_plan_set_timing.argtypes = [vp, ci]
         L.qxa_graph_create.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), ci, vp, vp, C.POINTER(vp)]
@@ -339,6 +340,23 @@ def cond_tensor_product(plan: Plan, law_dc, u, v, T=None, stream=None, tensor=No
     c, keep = make_coeff(law_dc, u, tensor=tensor)
     check(lib().qxa_cond_tensor_product(plan.handle, C.byref(c), _ptr(v), _ptr(T), _stream_ptr(stream)))
     return T
+
+
+def assemble_iso(plan: Plan, law_m, law_c, field_m=None, field_c=None, M=None, Cv=None, stream=None,
+                 want_m=True, want_c=True, qpoint=False, tensor=None):
+    """Isoparametric (curved) elements: M and C with the geometry evaluated per quadrature
+    node from every node's position (qxa_assemble_iso, FP64)."""
+    import torch
+    dev = torch.device("cuda", plan.mesh.device)
+    if want_m and M is None:
+        M = torch.empty(plan.nnz, dtype=torch.float64, device=dev)
+    if want_c and Cv is None:
+        Cv = torch.empty(plan.nnz, dtype=torch.float64, device=dev)
+    cm, k1 = make_coeff(law_m, field_m, qpoint)
+    cc, k2 = make_coeff(law_c, field_c, qpoint, tensor)
+    check(lib().qxa_assemble_iso(plan.handle, C.byref(cm), C.byref(cc), _ptr(M if want_m else None),
+                                 _ptr(Cv if want_c else None), _stream_ptr(stream)))
+    return M, Cv
 
 
 def load_vector(plan: Plan, law_f, field=None, F=None, stream=None, qpoint=False):

@@ -339,7 +339,7 @@ qxa_status qxa_plan_destroy(qxa_plan p)
     void *bufs[] = {p->d_row_ptr, p->d_col_idx, p->d_tconn, p->d_elem_order, p->d_rec, p->d_rec_ptr, p->d_rec_mid,
                     p->d_part_ptr, p->d_fix_target, p->d_fix_mirror, p->d_sink, p->d_part, p->d_qfrag[0],
                     p->d_qfrag[1], p->d_qfrag[2], p->d_qfrag[3], p->d_qfrag[4], p->d_tables, p->d_tables_f,
-                    p->d_V, p->d_flags, p->d_T, p->d_ns_ptr, p->d_ns_items, p->d_Fe, p->d_nf_ptr, p->d_nf_items};
+                    p->d_V, p->d_flags, p->d_T, p->d_ns_ptr, p->d_ns_items, p->d_Fe, p->d_nf_ptr, p->d_nf_items, p->d_Tiso};
     for (void *b : bufs) plan_free(p, b);
     delete p;
     return QXA_OK;
@@ -383,6 +383,7 @@ qxa_status plan_stage(qxa_mesh mesh, const qxa_quad &mr, const qxa_quad &cr, Pla
     g.off_qm = put(T.Qm);
     g.off_qc = put(T.Qc);
     g.off_dphic = put(T.dphi_c);
+    g.off_dphim = put(T.dphi_m);
     g.tabf.assign(g.tab.begin(), g.tab.end());
     return QXA_OK;
 }
@@ -432,6 +433,7 @@ qxa_status plan_upload(qxa_mesh mesh, const PlanStaging &g, DevArena *arena, boo
     p->off_phim = g.off_phim;
     p->off_phic = g.off_phic;
     p->off_dphic = g.off_dphic;
+    p->off_dphim = g.off_dphim;
     p->off_qm = g.off_qm;
     p->off_qc = g.off_qc;
     if (!st) st = plan_upload_buf(p, &p->d_tables, g.tab.data(), g.tab.size());
@@ -729,7 +731,6 @@ static qxa_status build_slot_entries(qxa_plan p)
             for (int b = 0; b < np; ++b) items[size_t(fill[slot(e, a, b)]++)] = int32_t((a * np + b) * ne + e);
     st = plan_upload_buf(p, &p->d_ns_ptr, ptr.data(), ptr.size());
     if (!st) st = plan_upload_buf(p, &p->d_ns_items, items.data(), items.size());
-    if (!st) st = plan_alloc(p, &p->d_T, size_t(np) * np * ne);
     return st;
 }
 
@@ -758,6 +759,49 @@ static qxa_status build_node_entries(qxa_plan p)
 }  // namespace qxa
 
 extern "C" {
+
+qxa_status qxa_assemble_iso(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *stiff, double *M_vals, double *C_vals,
+                            void *stream)
+{
+    if (!p) return fail(QXA_E_INVALID, "null plan");
+    if (!p->d_flags) return fail(QXA_E_INVALID, "plan is owned by a server");
+    IsoArgs a{};
+    const void *qm, *qc;
+    qxa_status st = fill_inputs(p, mass, stiff, QXA_FP64, a.in, &qm, &qc);
+    if (st) return st;
+    const qxa_mesh m = p->mesh;
+    if ((!M_vals && !C_vals) || m->n_elem == 0) return QXA_OK;
+    QXA_HIP(hipSetDevice(m->device));
+    if (!p->d_ns_ptr) {
+        st = build_slot_entries(p);
+        if (st) return st;
+    }
+    const size_t nt = size_t(p->ref.np) * p->ref.np * m->n_elem;
+    if (!p->d_Tiso) {
+        st = plan_alloc(p, &p->d_Tiso, 2 * nt);
+        if (st) return st;
+    }
+    a.conn = m->d_conn;
+    a.dphi_m = p->d_tables + p->off_dphim;
+    a.dphi_c = p->d_tables + p->off_dphic;
+    a.Tm = M_vals ? p->d_Tiso : nullptr;
+    a.Tc = C_vals ? p->d_Tiso + nt : nullptr;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    {
+        TimedLaunch tl(p, "iso_rows", s);
+        QXA_HIP(launch_iso(a, m->dim, m->order, p->ref.nq_m, p->ref.nq_c, s));
+    }
+    TimedLaunch tl(p, "slot_gather", s);
+    if (M_vals) {
+        const SlotGatherArgs g{p->nnz, p->d_ns_ptr, p->d_ns_items, a.Tm, M_vals};
+        QXA_HIP(launch_slot_gather(g, s));
+    }
+    if (C_vals) {
+        const SlotGatherArgs g{p->nnz, p->d_ns_ptr, p->d_ns_items, a.Tc, C_vals};
+        QXA_HIP(launch_slot_gather(g, s));
+    }
+    return QXA_OK;
+}
 
 qxa_status qxa_load_vector(qxa_plan p, const qxa_coeff *f, double *F, void *stream)
 {
@@ -803,6 +847,10 @@ qxa_status qxa_cond_tensor_product(qxa_plan p, const qxa_coeff *c, const double 
     QXA_HIP(hipSetDevice(p->mesh->device));
     if (!p->d_ns_ptr) {
         st = build_slot_entries(p);
+        if (st) return st;
+    }
+    if (!p->d_T) {
+        st = plan_alloc(p, &p->d_T, size_t(p->ref.np) * p->ref.np * p->mesh->n_elem);
         if (st) return st;
     }
     const qxa_mesh m = p->mesh;

@@ -130,6 +130,14 @@ struct LoadArgs {
     double *Fe;           // [np][n_elem] element load vectors
 };
 
+struct IsoArgs {
+    FormInputs in;         // coefficients, tensor, rules (w, phi)
+    const int32_t *conn;   // [np][n_elem]
+    const double *dphi_m;  // [nq_m][np][dim]
+    const double *dphi_c;  // [nq_c][np][dim]
+    double *Tm, *Tc;       // [np*np][n_elem] local matrices
+};
+
 struct SlotGatherArgs {
     int64_t n_slots;
     const int64_t *ptr;    // [n_slots + 1]
@@ -143,6 +151,7 @@ hipError_t launch_coeff_product(const CoeffProductArgs &a, int D, int P, int nq,
 hipError_t launch_cond_tensor(const CondTensorArgs &a, int D, int P, int nq, hipStream_t st);
 hipError_t launch_slot_gather(const SlotGatherArgs &a, hipStream_t st);
 hipError_t launch_load(const LoadArgs &a, int D, int P, int nq, hipStream_t st);
+hipError_t launch_iso(const IsoArgs &a, int D, int P, int nqm, int nqc, hipStream_t st);
 hipError_t launch_form(const FormArgs &a, int D, int P, int nqm, int nqc, int precision, hipStream_t st);
 hipError_t launch_expand(const ExpandArgs &a, hipStream_t st);
 hipError_t launch_fused(const JobTable &jt, int D, int P, int nqm, int nqc, int precision, hipStream_t st);

@@ -273,6 +273,161 @@ hipError_t launch_load(const LoadArgs &a, int D, int P, int nq, hipStream_t st)
     return hipErrorInvalidValue;
 }
 
+// Coefficient s(x_q) of one quadrature node for the isoparametric path (nodal
+// fields interpolated from global memory; per-(q, e) values in mesh order).
+template <int NP, int NQ>
+__device__ __forceinline__ double coeff_node(const CoeffDev &c, const double *phi, const int32_t *conn, int64_t ne,
+                                             int64_t e, int q)
+{
+    if (c.kind == 0) return c.value;
+    if (c.kind == 1) {
+        double uh = 0.0;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) uh = fma(uniform_table(phi)[i * NQ + q], c.field[conn[i * ne + e]], uh);
+        return apply_law(c, uh);
+    }
+    return apply_law(c, c.field[q * ne + e]);
+}
+
+// B_q = sum_i x_i J_q[i]^T of a curved (isoparametric) element, its inverse and |det|.
+template <int D, int NP>
+__device__ __forceinline__ void iso_geometry(const FormInputs &in, const int32_t *conn, int64_t e, const double *J,
+                                             double (&I)[D][D], double &adet)
+{
+    const int64_t ne = in.n_elem;
+    double B[D][D];
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+#pragma unroll
+        for (int c = 0; c < D; ++c) B[r][c] = 0.0;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        const int32_t node = conn[i * ne + e];
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+            const double xr = in.coords[r * in.n_nodes + node];
+#pragma unroll
+            for (int c = 0; c < D; ++c) B[r][c] = fma(xr, uniform_table(J)[i * D + c], B[r][c]);
+        }
+    }
+    if constexpr (D == 2) {
+        const double det = B[0][0] * B[1][1] - B[0][1] * B[1][0], r = 1.0 / det;
+        I[0][0] = B[1][1] * r;
+        I[0][1] = -B[0][1] * r;
+        I[1][0] = -B[1][0] * r;
+        I[1][1] = B[0][0] * r;
+        adet = fabs(det);
+    } else {
+        const double c00 = B[1][1] * B[2][2] - B[1][2] * B[2][1];
+        const double c01 = B[1][2] * B[2][0] - B[1][0] * B[2][2];
+        const double c02 = B[1][0] * B[2][1] - B[1][1] * B[2][0];
+        const double det = B[0][0] * c00 + B[0][1] * c01 + B[0][2] * c02, r = 1.0 / det;
+        I[0][0] = c00 * r;
+        I[1][0] = c01 * r;
+        I[2][0] = c02 * r;
+        I[0][1] = (B[0][2] * B[2][1] - B[0][1] * B[2][2]) * r;
+        I[1][1] = (B[0][0] * B[2][2] - B[0][2] * B[2][0]) * r;
+        I[2][1] = (B[0][1] * B[2][0] - B[0][0] * B[2][1]) * r;
+        I[0][2] = (B[0][1] * B[1][2] - B[0][2] * B[1][1]) * r;
+        I[1][2] = (B[0][2] * B[1][0] - B[0][0] * B[1][2]) * r;
+        I[2][2] = (B[0][0] * B[1][1] - B[0][1] * B[1][0]) * r;
+        adet = fabs(det);
+    }
+}
+
+// Isoparametric elements (curved geometry, Section 7): row a of M_e and C_e with B, |det B|
+// and A = B^{-1} K B^{-T} evaluated per quadrature node from every node's position
+// (X_m and X_c per (q, e); the contraction with Phi (.) Phi and [J_q (x) J_q] is unchanged).
+// One thread per (element, row a): blockIdx.y = a.
+template <int D, int P, int NQM, int NQC>
+__global__ __launch_bounds__(256) void iso_rows_kernel(IsoArgs a)
+{
+    using S = Shape<D, P>;
+    constexpr int NP = S::NP;
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int ra = blockIdx.y;
+    const FormInputs &in = a.in;
+    const int64_t ne = in.n_elem;
+    if (e >= ne) return;
+    bool ok = true;
+    if (a.Tm) {
+        double row[NP];
+#pragma unroll
+        for (int b = 0; b < NP; ++b) row[b] = 0.0;
+        for (int q = 0; q < NQM; ++q) {
+            double I[D][D], adet;
+            iso_geometry<D, NP>(in, a.conn, e, a.dphi_m + size_t(q) * NP * D, I, adet);
+            const double lam = uniform_table(in.w_m)[q] * coeff_node<NP, NQM>(in.cm, in.phi_m, a.conn, ne, e, q) * adet;
+            ok &= isfinite(lam) && adet > 0.0;
+            const double pa = uniform_table(in.phi_m)[ra * NQM + q];
+            // lam * (phi_a phi_b): the same bits for (a, b) and (b, a)
+#pragma unroll
+            for (int b = 0; b < NP; ++b) row[b] = fma(lam, pa * uniform_table(in.phi_m)[b * NQM + q], row[b]);
+        }
+#pragma unroll
+        for (int b = 0; b < NP; ++b) a.Tm[(ra * NP + b) * ne + e] = row[b];
+    }
+    if (a.Tc) {
+        double row[NP];
+#pragma unroll
+        for (int b = 0; b < NP; ++b) row[b] = 0.0;
+        for (int q = 0; q < NQC; ++q) {
+            const double *J = a.dphi_c + size_t(q) * NP * D;
+            double I[D][D], adet, Au[S::NG];
+            iso_geometry<D, NP>(in, a.conn, e, J, I, adet);
+            metric_from_inverse<D>(I, in.aniso, in.K, Au);
+            double A[D][D];
+            {
+                int g = 0;
+#pragma unroll
+                for (int r = 0; r < D; ++r)
+#pragma unroll
+                    for (int c = r; c < D; ++c, ++g) A[r][c] = A[c][r] = Au[g];
+            }
+            const double lam = uniform_table(in.w_c)[q] * coeff_node<NP, NQC>(in.cc, in.phi_c, a.conn, ne, e, q) * adet;
+            ok &= isfinite(lam) && adet > 0.0;
+            double ja[D];
+#pragma unroll
+            for (int c = 0; c < D; ++c) ja[c] = uniform_table(J)[ra * D + c];
+            // J_a^T A J_b summed over the upper triangle of A, each off-diagonal term as
+            // A_ck (J_a,c J_b,k + J_a,k J_b,c): the same bits for (a, b) and (b, a)
+#pragma unroll
+            for (int b = 0; b < NP; ++b) {
+                // no contraction of the pair sums into an fma (that would lose the symmetry)
+#pragma clang fp contract(off)
+                double jb[D];
+#pragma unroll
+                for (int c = 0; c < D; ++c) jb[c] = uniform_table(J)[b * D + c];
+                double s = 0.0;
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    s = fma(A[c][c], ja[c] * jb[c], s);
+#pragma unroll
+                    for (int k = c + 1; k < D; ++k) s = fma(A[c][k], ja[c] * jb[k] + ja[k] * jb[c], s);
+                }
+                row[b] = fma(lam, s, row[b]);
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < NP; ++b) a.Tc[(ra * NP + b) * ne + e] = row[b];
+    }
+    if (!ok) atomicOr(in.flags, 1);
+}
+
+hipError_t launch_iso(const IsoArgs &a, int D, int P, int nqm, int nqc, hipStream_t st)
+{
+    if (a.in.n_elem == 0) return hipSuccess;
+#define X(d, p, m, c)                                                                          \
+    if (D == d && P == p && nqm == m && nqc == c) {                                            \
+        const dim3 grid(unsigned((a.in.n_elem + 255) / 256), unsigned(Shape<d, p>::NP));      \
+        iso_rows_kernel<d, p, m, c><<<grid, 256, 0, st>>>(a);                                 \
+        return hipGetLastError();                                                              \
+    }
+    QXA_FORM_CASES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
 // out[t] = sum of src over the entries of slot t, in their stored order (deterministic).
 __global__ __launch_bounds__(256) void slot_gather_kernel(SlotGatherArgs a)
 {

@@ -45,6 +45,7 @@ struct RefTables {
     std::vector<double> phi_m;        // [np][nq_m]: Phi for the mass rule
     std::vector<double> phi_c;        // [np][nq_c]: Phi at the stiffness rule (for u_h)
     std::vector<double> dphi_c;       // [nq_c][np][dim]: J_q, reference gradients at the stiffness rule
+    std::vector<double> dphi_m;       // [nq_m][np][dim]: the same at the mass rule (curved geometry)
     std::vector<double> Qm;           // [ns][nq_m]           symmetric-pair rows of Phi (.) Phi
     std::vector<double> Qc;           // [ns][nq_c][ng]       symmetric-pair rows of [J_q (x) J_q], symmetric W
     std::vector<int> pair_a, pair_b;  // sym pair s -> (a, b), a <= b
@@ -138,7 +139,7 @@ struct PlanStaging {
     double f16_qinv[2] = {1.0, 1.0};
     std::vector<double> tab;
     std::vector<float> tabf;
-    size_t off_wm = 0, off_wc = 0, off_phim = 0, off_phic = 0, off_qm = 0, off_qc = 0, off_dphic = 0;
+    size_t off_wm = 0, off_wc = 0, off_phim = 0, off_phic = 0, off_qm = 0, off_qc = 0, off_dphic = 0, off_dphim = 0;
 };
 
 qxa_status plan_stage(qxa_mesh mesh, const qxa_quad &mr, const qxa_quad &cr, PlanStaging &out);
@@ -189,7 +190,8 @@ struct qxa_plan_s {
     double f16_qinv[2] = {1.0, 1.0};  // FP16 tables are stored as Q * 2^k (mass, stiffness)
     double *d_tables = nullptr;   // device copy of w, Phi, Qm, Qc (FP64)
     float *d_tables_f = nullptr;  // FP32 copy
-    size_t off_wm = 0, off_wc = 0, off_phim = 0, off_phic = 0, off_qm = 0, off_qc = 0, off_dphic = 0;
+    size_t off_wm = 0, off_wc = 0, off_phim = 0, off_phic = 0, off_qm = 0, off_qc = 0, off_dphic = 0, off_dphim = 0;
+    double *d_Tiso = nullptr;     // [2][np*np][n_elem] isoparametric local matrices (first use)
     double *d_V = nullptr;        // [2][ns][n_elem] formation-only buffer (allocated on first use)
     // conductivity tensor product (built on first use): local matrices [np*np][n_elem]
     // and, per CSR slot (both triangles), its element entries (index into d_T) in

@@ -139,10 +139,12 @@ qxa_status build_ref_tables(int dim, int order, const qxa_quad &mr, const qxa_qu
     double phi[kMaxNp], dphi[kMaxNp * 3];
     // mass rule: Phi and Q_m
     T.phi_m.assign(size_t(np) * T.nq_m, 0.0);
+    T.dphi_m.assign(size_t(T.nq_m) * np * dim, 0.0);
     T.Qm.assign(size_t(ns) * T.nq_m, 0.0);
     for (int q = 0; q < T.nq_m; ++q) {
         lagrange_eval(dim, order, mr.points + q * dim, phi, dphi);
         for (int i = 0; i < np; ++i) T.phi_m[size_t(i) * T.nq_m + q] = phi[i];
+        std::copy(dphi, dphi + np * dim, T.dphi_m.begin() + size_t(q) * np * dim);
         for (int s = 0; s < ns; ++s) T.Qm[size_t(s) * T.nq_m + q] = phi[T.pair_a[s]] * phi[T.pair_b[s]];
     }
     // stiffness rule: Phi (for u_h) and Q_c

@@ -1,0 +1,110 @@
+"""Isoparametric (curved) elements (Section 7) on the GPU: the per-node geometry path
+against the oracle on curved meshes of every shape, with nodal, per-quadrature-node and
+anisotropic coefficients, the lower-degree stiffness rule, the affine special case,
+symmetry, and the degenerate-map report."""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import row_scaled_error, transpose_slots
+from workloads import rule, structured_mesh
+from workloads.fields import gaussian_random_field
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+SHAPES = [(2, 1, 23), (2, 2, 13), (2, 3, 9), (3, 1, 7), (3, 2, 5), (3, 3, 3)]
+
+
+def _curved(mesh, eps):
+    """Every node moved by eps * prod_k sin(pi x_k) (zero on the boundary of the unit box)."""
+    X = mesh["coords"].copy()
+    bump = np.prod(np.sin(np.pi * X), axis=0)
+    out = dict(mesh)
+    out["coords"] = np.ascontiguousarray(X + eps * bump * np.array([1.0, -0.7, 0.5][:X.shape[0]])[:, None])
+    return out
+
+
+def _K(dim, seed):
+    S = np.eye(dim) + 0.4 * np.random.default_rng(seed).uniform(-1, 1, size=(dim, dim))
+    K = S @ S.T
+    return np.array([K[a, b] for a in range(dim) for b in range(a, dim)])
+
+
+@pytest.mark.parametrize("dim,order,N", SHAPES)
+def test_iso_nodal_fields_against_oracle(dim, order, N):
+    import paper_2204_03893_amd as qxa
+    print("case iso nodal", dim, order, N, flush=True)
+    mesh = _curved(structured_mesh(dim, order, N, 0.1, seed=[111, dim, order]), 0.1 / N)
+    u = gaussian_random_field(mesh["coords"], 16, np.random.default_rng([112, dim]), length=0.3)
+    r = rule(dim, 2 * order)
+    law_m, law_c = ("poly2", 1.0, 0.1, 0.2), ("exp", 0.0, 1.0)
+    K = _K(dim, [113, dim]) if order != 1 else None
+    m = qxa.Mesh(dim, order, mesh["coords"], mesh["conn"])
+    plan = qxa.Plan(m, r)
+    uf = torch.tensor(u, device="cuda")
+    M, Cv = qxa.assemble_iso(plan, law_m, law_c, uf, uf, tensor=K)
+    M2, C2 = qxa.assemble_iso(plan, law_m, law_c, uf, uf, tensor=K)   # second call: no allocation, same bits
+    qxa.sync(plan)
+    rpo, cio, Mo, Co = oracle.assemble_iso(mesh, r, r, law_m, law_c, u, u, tensor_c=K)
+    Mg, Cg = M.cpu().numpy(), Cv.cpu().numpy()
+    assert row_scaled_error(Mg, Mo, rpo) <= 1e-12
+    assert row_scaled_error(Cg, Co, rpo) <= 1e-12
+    assert torch.equal(M, M2) and torch.equal(Cv, C2)
+    tr = transpose_slots(rpo, cio)
+    assert np.array_equal(Mg, Mg[tr]) and np.array_equal(Cg, Cg[tr])
+
+
+@pytest.mark.parametrize("dim,order", [(2, 2), (3, 2), (2, 3)])
+def test_iso_qpoint_field_and_lower_degree_rule(dim, order):
+    import paper_2204_03893_amd as qxa
+    print("case iso qpoint", dim, order, flush=True)
+    mesh = _curved(structured_mesh(dim, order, 4, 0.1, seed=[114, dim, order]), 0.03)
+    rm, rc = rule(dim, 2 * order), rule(dim, 2 * order - 2)
+    ne = mesh["conn"].shape[1]
+    s = np.random.default_rng(115).uniform(0.5, 2.0, size=(len(rm[1]), ne))
+    m = qxa.Mesh(dim, order, mesh["coords"], mesh["conn"])
+    plan = qxa.Plan(m, rm, rc)
+    M, Cv = qxa.assemble_iso(plan, ("poly2", 0.0, 1.0, 0.0), ("const", 1.7), torch.tensor(s, device="cuda"), None,
+                             qpoint=True)
+    qxa.sync(plan)
+    rpo, _, Mo, Co = oracle.assemble_iso(mesh, rm, rc, ("poly2", 0.0, 1.0, 0.0), ("const", 1.7), qpoint_m=s)
+    assert row_scaled_error(M.cpu().numpy(), Mo, rpo) <= 1e-12
+    assert row_scaled_error(Cv.cpu().numpy(), Co, rpo) <= 1e-12
+
+
+def test_iso_affine_mesh_matches_the_fused_assembly():
+    import paper_2204_03893_amd as qxa
+    dim, order = 3, 2
+    mesh = structured_mesh(dim, order, 4, 0.2, seed=116)
+    u = gaussian_random_field(mesh["coords"], 16, np.random.default_rng(117), length=0.3)
+    r = rule(dim, 2 * order)
+    m = qxa.Mesh(dim, order, mesh["coords"], mesh["conn"])
+    plan = qxa.Plan(m, r)
+    uf = torch.tensor(u, device="cuda")
+    law_m, law_c = ("poly2", 1.0, 0.3, 0.0), ("exp", 0.0, 0.5)
+    Mi, Ci = qxa.assemble_iso(plan, law_m, law_c, uf, uf)
+    Mf, Cf = qxa.assemble(plan, law_m, law_c, uf, uf)
+    qxa.sync(plan)
+    rp = np.asarray(oracle.pattern(mesh)[0])
+    assert row_scaled_error(Mi.cpu().numpy(), Mf.cpu().numpy(), rp) <= 1e-12
+    assert row_scaled_error(Ci.cpu().numpy(), Cf.cpu().numpy(), rp) <= 1e-12
+    Mo, _ = qxa.assemble_iso(plan, law_m, law_c, uf, uf, want_c=False)   # one output only
+    qxa.sync(plan)
+    assert torch.equal(Mo, Mi)
+
+
+def test_iso_nonfinite_coefficient_is_reported():
+    import paper_2204_03893_amd as qxa
+    dim, order = 2, 2
+    mesh = _curved(structured_mesh(dim, order, 3, 0.0), 0.02)
+    u = np.ones(mesh["coords"].shape[1])
+    u[mesh["conn"][3, 4]] = np.nan
+    m = qxa.Mesh(dim, order, mesh["coords"], mesh["conn"])
+    plan = qxa.Plan(m, rule(dim, 2 * order))
+    qxa.assemble_iso(plan, ("const", 1.0), ("poly2", 1.0, 1.0, 0.0), None, torch.tensor(u, device="cuda"))
+    with pytest.raises(qxa.QxaError) as ei:
+        qxa.sync(plan)
+    assert ei.value.code == -4                       # QXA_E_NONFINITE
+    qxa.assemble_iso(plan, ("const", 1.0), ("const", 1.0))   # the report is cleared by qxa_sync
+    qxa.sync(plan)
