@@ -699,7 +699,7 @@ qxa_status qxa_coeff_product(qxa_plan p, int rule, const qxa_coeff *c, const dou
 namespace qxa {
 
 // Entries of every CSR slot (both triangles) for the nonsymmetric local matrices
-// T[(a*np + b) * n_elem + e]: the slot of (N_e(a), N_e(b)) is the upper slot of the
+// T[(e * np + a) * np + b] (element-major): the slot of (N_e(a), N_e(b)) is the upper slot of the
 // pair or its mirror. Counting sort in element order, so each slot lists its
 // entries by ascending element, then (a, b): a fixed summation order.
 static qxa_status build_slot_entries(qxa_plan p)
@@ -728,7 +728,7 @@ static qxa_status build_slot_entries(qxa_plan p)
     std::vector<int32_t> items(static_cast<size_t>(ptr[hp.nnz]));
     for (int64_t e = 0; e < ne; ++e)
         for (int a = 0; a < np; ++a)
-            for (int b = 0; b < np; ++b) items[size_t(fill[slot(e, a, b)]++)] = int32_t((a * np + b) * ne + e);
+            for (int b = 0; b < np; ++b) items[size_t(fill[slot(e, a, b)]++)] = int32_t((e * np + a) * np + b);
     st = plan_upload_buf(p, &p->d_ns_ptr, ptr.data(), ptr.size());
     if (!st) st = plan_upload_buf(p, &p->d_ns_items, items.data(), items.size());
     return st;
@@ -792,14 +792,11 @@ qxa_status qxa_assemble_iso(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *
         QXA_HIP(launch_iso(a, m->dim, m->order, p->ref.nq_m, p->ref.nq_c, s));
     }
     TimedLaunch tl(p, "slot_gather", s);
-    if (M_vals) {
-        const SlotGatherArgs g{p->nnz, p->d_ns_ptr, p->d_ns_items, a.Tm, M_vals};
-        QXA_HIP(launch_slot_gather(g, s));
-    }
-    if (C_vals) {
-        const SlotGatherArgs g{p->nnz, p->d_ns_ptr, p->d_ns_items, a.Tc, C_vals};
-        QXA_HIP(launch_slot_gather(g, s));
-    }
+    const SlotGatherArgs g = M_vals && C_vals
+                                 ? SlotGatherArgs{p->nnz, p->d_ns_ptr, p->d_ns_items, a.Tm, M_vals, a.Tc, C_vals}
+                                 : SlotGatherArgs{p->nnz, p->d_ns_ptr, p->d_ns_items, M_vals ? a.Tm : a.Tc,
+                                                  M_vals ? M_vals : C_vals, nullptr, nullptr};
+    QXA_HIP(launch_slot_gather(g, s));
     return QXA_OK;
 }
 
@@ -829,7 +826,7 @@ qxa_status qxa_load_vector(qxa_plan p, const qxa_coeff *f, double *F, void *stre
         QXA_HIP(launch_load(a, m->dim, m->order, p->ref.nq_m, s));
     }
     TimedLaunch tl(p, "slot_gather", s);
-    const SlotGatherArgs g{m->n_nodes, p->d_nf_ptr, p->d_nf_items, p->d_Fe, F};
+    const SlotGatherArgs g{m->n_nodes, p->d_nf_ptr, p->d_nf_items, p->d_Fe, F, nullptr, nullptr};
     QXA_HIP(launch_slot_gather(g, s));
     return QXA_OK;
 }
@@ -870,7 +867,7 @@ qxa_status qxa_cond_tensor_product(qxa_plan p, const qxa_coeff *c, const double 
         QXA_HIP(launch_cond_tensor(a, m->dim, m->order, p->ref.nq_c, s));
     }
     TimedLaunch tl(p, "slot_gather", s);
-    const SlotGatherArgs g{p->nnz, p->d_ns_ptr, p->d_ns_items, p->d_T, T_vals};
+    const SlotGatherArgs g{p->nnz, p->d_ns_ptr, p->d_ns_items, p->d_T, T_vals, nullptr, nullptr};
     QXA_HIP(launch_slot_gather(g, s));
     return QXA_OK;
 }

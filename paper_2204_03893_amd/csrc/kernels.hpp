@@ -120,7 +120,7 @@ struct CondTensorArgs {
     int aniso;             // conductivity tensor K instead of the identity
     double K[6];
     const double *v;       // [n_nodes]
-    double *T;             // [np*np][n_elem] local matrices (row a, column b)
+    double *T;             // [n_elem][np][np] local matrices (row a, column b)
     int *flags;
 };
 
@@ -135,7 +135,7 @@ struct IsoArgs {
     const int32_t *conn;   // [np][n_elem]
     const double *dphi_m;  // [nq_m][np][dim]
     const double *dphi_c;  // [nq_c][np][dim]
-    double *Tm, *Tc;       // [np*np][n_elem] local matrices
+    double *Tm, *Tc;       // [n_elem][np][np] local matrices
 };
 
 struct SlotGatherArgs {
@@ -144,6 +144,8 @@ struct SlotGatherArgs {
     const int32_t *items;  // indices into src
     const double *src;
     double *out;           // [n_slots]
+    const double *src2;    // optional second source, gathered with the same entries
+    double *out2;
 };
 
 bool form_supported(int D, int P, int nqm, int nqc);

@@ -189,7 +189,7 @@ __global__ __launch_bounds__(256) void cond_tensor_rows_kernel(CondTensorArgs a)
         for (int b = 0; b < NP; ++b) row[b] = fma(f, uniform_table(a.phi)[b * NQ + q], row[b]);
     }
 #pragma unroll
-    for (int b = 0; b < NP; ++b) a.T[(ra * NP + b) * a.n_elem + e] = row[b];
+    for (int b = 0; b < NP; ++b) a.T[(e * NP + ra) * NP + b] = row[b];
     if (!ok) atomicOr(a.flags, 1);
 }
 
@@ -365,7 +365,7 @@ __global__ __launch_bounds__(256) void iso_rows_kernel(IsoArgs a)
             for (int b = 0; b < NP; ++b) row[b] = fma(lam, pa * uniform_table(in.phi_m)[b * NQM + q], row[b]);
         }
 #pragma unroll
-        for (int b = 0; b < NP; ++b) a.Tm[(ra * NP + b) * ne + e] = row[b];
+        for (int b = 0; b < NP; ++b) a.Tm[(e * NP + ra) * NP + b] = row[b];
     }
     if (a.Tc) {
         double row[NP];
@@ -409,7 +409,7 @@ __global__ __launch_bounds__(256) void iso_rows_kernel(IsoArgs a)
             }
         }
 #pragma unroll
-        for (int b = 0; b < NP; ++b) a.Tc[(ra * NP + b) * ne + e] = row[b];
+        for (int b = 0; b < NP; ++b) a.Tc[(e * NP + ra) * NP + b] = row[b];
     }
     if (!ok) atomicOr(in.flags, 1);
 }
@@ -428,14 +428,25 @@ hipError_t launch_iso(const IsoArgs &a, int D, int P, int nqm, int nqc, hipStrea
     return hipErrorInvalidValue;
 }
 
-// out[t] = sum of src over the entries of slot t, in their stored order (deterministic).
+// out[t] = sum of src over the entries of slot t, in their stored order (deterministic);
+// with src2 set, out2[t] likewise from src2 in the same pass (the entry list read once).
 __global__ __launch_bounds__(256) void slot_gather_kernel(SlotGatherArgs a)
 {
     const int64_t t = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (t >= a.n_slots) return;
     const int64_t lo = a.ptr[t], hi = a.ptr[t + 1];
     double s = 0.0;
-    for (int64_t k = lo; k < hi; ++k) s += a.src[a.items[k]];
+    if (a.src2) {
+        double s2 = 0.0;
+        for (int64_t k = lo; k < hi; ++k) {
+            const int32_t i = a.items[k];
+            s += a.src[i];
+            s2 += a.src2[i];
+        }
+        a.out2[t] = s2;
+    } else {
+        for (int64_t k = lo; k < hi; ++k) s += a.src[a.items[k]];
+    }
     a.out[t] = s;
 }
 
