@@ -7,7 +7,7 @@
 #include <cstring>
 #include <string>
 
-#include "kernels.hpp"
+#include "kernels_twopass.hpp"
 #include "qxa_internal.hpp"
 
 namespace qxa {

@@ -92,70 +92,8 @@ struct FixupTable {
     int64_t n_fix;
 };
 
-struct ExpandArgs {
-    int64_t n_elem;
-    int np;
-    const double *Sm, *Sc;  // [ns][n_elem]
-    double *Vm, *Vc;        // [np*np][n_elem]
-};
-
-struct CoeffProductArgs {
-    int64_t n_elem;
-    const int32_t *conn;  // [np][n_elem]
-    const double *phi;    // [np][nq] basis values of the rule
-    CoeffDev c;           // law of the first factor; c.field = u [n_nodes]
-    const double *v;      // [n_nodes]
-    double *S;            // [nq][n_elem]
-    int *flags;
-};
-
-struct CondTensorArgs {
-    int64_t n_nodes, n_elem;
-    const double *coords;  // [dim][n_nodes]
-    const int32_t *conn;   // [np][n_elem]
-    const double *w;       // [nq] stiffness rule
-    const double *phi;     // [np][nq]
-    const double *dphi;    // [nq][np][dim]
-    CoeffDev c;            // law of c'; c.field = u [n_nodes]
-    int aniso;             // conductivity tensor K instead of the identity
-    double K[6];
-    const double *v;       // [n_nodes]
-    double *T;             // [n_elem][np][np] local matrices (row a, column b)
-    int *flags;
-};
-
-struct LoadArgs {
-    FormInputs in;        // geometry, mass-rule tables; in.cm = the load coefficient f
-    const int32_t *conn;  // [np][n_elem]
-    double *Fe;           // [np][n_elem] element load vectors
-};
-
-struct IsoArgs {
-    FormInputs in;         // coefficients, tensor, rules (w, phi)
-    const int32_t *conn;   // [np][n_elem]
-    const double *dphi_m;  // [nq_m][np][dim]
-    const double *dphi_c;  // [nq_c][np][dim]
-    double *Tm, *Tc;       // [n_elem][np][np] local matrices
-};
-
-struct SlotGatherArgs {
-    int64_t n_slots;
-    const int64_t *ptr;    // [n_slots + 1]
-    const int32_t *items;  // indices into src
-    const double *src;
-    double *out;           // [n_slots]
-    const double *src2;    // optional second source, gathered with the same entries
-    double *out2;
-};
-
 bool form_supported(int D, int P, int nqm, int nqc);
-hipError_t launch_coeff_product(const CoeffProductArgs &a, int D, int P, int nq, hipStream_t st);
-hipError_t launch_cond_tensor(const CondTensorArgs &a, int D, int P, int nq, hipStream_t st);
-hipError_t launch_slot_gather(const SlotGatherArgs &a, hipStream_t st);
-hipError_t launch_load(const LoadArgs &a, int D, int P, int nq, hipStream_t st);
-hipError_t launch_iso(const IsoArgs &a, int D, int P, int nqm, int nqc, hipStream_t st);
 hipError_t launch_form(const FormArgs &a, int D, int P, int nqm, int nqc, int precision, hipStream_t st);
-hipError_t launch_expand(const ExpandArgs &a, hipStream_t st);
 hipError_t launch_fused(const JobTable &jt, int D, int P, int nqm, int nqc, int precision, hipStream_t st);
 hipError_t launch_fixup(const FixupTable &ft, hipStream_t st);
 

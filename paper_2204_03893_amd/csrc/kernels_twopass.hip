@@ -1,7 +1,7 @@
 // Formation kernel (Algorithm 2 up to the element matrices) writing the symmetric element
 // matrices V_m, V_c to a buffer (the formation-only entry point), and the
 // expansion of the symmetric pairs to full n_p x n_p element matrices.
-#include "kernels.hpp"
+#include "kernels_twopass.hpp"
 #include "kernels_common.hpp"
 
 namespace qxa {
