@@ -1,0 +1,77 @@
+"""The next items at the size of the benchmark workload (3D P2, 32^3 Kuhn cube, 196,608
+elements), every value compared with the oracle: the mass and conductivity tensor
+products, the load vector, anisotropic conductivity and isoparametric elements (on the
+same mesh with its nodes moved by a bump that vanishes on the boundary)."""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import row_scaled_error
+from workloads import WORKLOADS, make_inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import paper_2204_03893_amd as qxa
+    w = WORKLOADS["p2_3d_32"]
+    print("case next-items full size", w.name, flush=True)
+    mesh, r, u = make_inputs(w)
+    _, _, u1 = make_inputs(w, stream=1)
+    m = qxa.Mesh(w.dim, w.order, mesh["coords"], mesh["conn"])
+    plan = qxa.Plan(m, r)
+    return qxa, w, mesh, r, u, u - u1, plan
+
+
+def test_tensor_products_full_size(setup):
+    qxa, w, mesh, r, u, v, plan = setup
+    print("case tensor products full size", flush=True)
+    uf, vf = torch.tensor(u, device="cuda"), torch.tensor(v, device="cuda")
+    law = ("poly2", 0.0, 1.0, 0.0)
+    Tm, _ = qxa.mass_tensor_product(plan, law, uf, vf)
+    Tc = qxa.cond_tensor_product(plan, law, uf, vf)
+    qxa.sync(plan)
+    rpo, _, Tmo = oracle.mass_tensor_product(mesh, r, law, u, v)
+    assert row_scaled_error(Tm.cpu().numpy(), Tmo, rpo) <= 1e-12
+    _, _, Tco = oracle.cond_tensor_product(mesh, r, law, u, v)
+    assert row_scaled_error(Tc.cpu().numpy(), Tco, rpo) <= 1e-12
+
+
+def test_load_vector_full_size(setup):
+    qxa, w, mesh, r, u, v, plan = setup
+    print("case load vector full size", flush=True)
+    F = qxa.load_vector(plan, ("exp", 0.0, 1.0), torch.tensor(u, device="cuda"))
+    qxa.sync(plan)
+    Fo = oracle.load_vector(mesh, r, ("exp", 0.0, 1.0), u)
+    assert np.abs(F.cpu().numpy() - Fo).max() <= 1e-12 * np.abs(Fo).max()
+
+
+def test_anisotropic_full_size(setup):
+    qxa, w, mesh, r, u, v, plan = setup
+    print("case anisotropic full size", flush=True)
+    K = np.array([2.0, 0.3, -0.2, 1.0, 0.1, 0.5])
+    uf = torch.tensor(u, device="cuda")
+    M, Cv = qxa.assemble(plan, w.mass_law, w.stiff_law, uf, uf, tensor=K)
+    qxa.sync(plan)
+    rpo, _, Mo, Co = oracle.assemble(mesh, r, r, w.mass_law, w.stiff_law, u, u, tensor_c=K)
+    assert row_scaled_error(M.cpu().numpy(), Mo, rpo) <= 1e-12
+    assert row_scaled_error(Cv.cpu().numpy(), Co, rpo) <= 1e-12
+
+
+def test_isoparametric_full_size(setup):
+    qxa, w, mesh, r, u, v, _ = setup
+    print("case isoparametric full size", flush=True)
+    X = mesh["coords"]
+    bump = np.prod(np.sin(np.pi * X), axis=0)
+    curved = dict(mesh)
+    curved["coords"] = np.ascontiguousarray(X + (0.1 / w.N) * bump * np.array([1.0, -0.7, 0.5])[:, None])
+    m = qxa.Mesh(w.dim, w.order, curved["coords"], curved["conn"])
+    plan = qxa.Plan(m, r)
+    uf = torch.tensor(u, device="cuda")
+    M, Cv = qxa.assemble_iso(plan, w.mass_law, w.stiff_law, uf, uf)
+    qxa.sync(plan)
+    rpo, _, Mo, Co = oracle.assemble_iso(curved, r, r, w.mass_law, w.stiff_law, u, u)
+    assert row_scaled_error(M.cpu().numpy(), Mo, rpo) <= 1e-12
+    assert row_scaled_error(Cv.cpu().numpy(), Co, rpo) <= 1e-12
