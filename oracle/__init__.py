@@ -35,7 +35,8 @@ def build(force: bool = False) -> str:
 
 class _Coeff(C.Structure):
     _fields_ = [("kind", C.c_int), ("law", C.c_int), ("value", C.c_double),
-                ("a", C.c_double * 3), ("field", C.c_void_p), ("tensor", C.c_void_p)]
+                ("a", C.c_double * 3), ("field", C.c_void_p), ("tensor", C.c_void_p),
+                ("tensor_q", C.c_void_p)]
 
 
 _lib = None
@@ -148,7 +149,8 @@ def pattern(mesh):
     return row_ptr, col_idx
 
 
-def _common(mesh, rule_m, rule_c, law_m, law_c, field_m, field_c, qpoint_m=None, qpoint_c=None, tensor_c=None):
+def _common(mesh, rule_m, rule_c, law_m, law_c, field_m, field_c, qpoint_m=None, qpoint_c=None, tensor_c=None,
+            tensor_q=None):
     conn = np.ascontiguousarray(mesh["conn"], dtype=np.int32)
     coords = np.ascontiguousarray(mesh["coords"], dtype=np.float64)
     pm, wm = (np.ascontiguousarray(a, dtype=np.float64) for a in rule_m)
@@ -158,20 +160,25 @@ def _common(mesh, rule_m, rule_c, law_m, law_c, field_m, field_c, qpoint_m=None,
     if tensor_c is not None:
         kc = (kc, np.ascontiguousarray(tensor_c, dtype=np.float64))
         cc.tensor = kc[1].ctypes.data
+    if tensor_q is not None:
+        kc = (kc, np.ascontiguousarray(tensor_q, dtype=np.float64))
+        cc.tensor_q = kc[1].ctypes.data
     args = [mesh["dim"], mesh["order"], coords.shape[1], coords.reshape(-1), conn.shape[1], conn.reshape(-1),
             wm.size, pm.reshape(-1), wm, wc.size, pc.reshape(-1), wc, C.byref(cm), C.byref(cc)]
     return args, (conn, coords, pm, wm, pc, wc, cm, cc, km, kc)
 
 
 def assemble(mesh, rule_m, rule_c, law_m, law_c, field_m=None, field_c=None, nthreads=0,
-             qpoint_m=None, qpoint_c=None, tensor_c=None):
+             qpoint_m=None, qpoint_c=None, tensor_c=None, tensor_q=None):
     """Full CSR assembly: returns (row_ptr int64, col_idx int32, M float64, C float64).
     tensor_c: upper triangle (row-major) of a constant symmetric conductivity tensor K
-    (anisotropic conductivity c K), or None for the isotropic case."""
+    (anisotropic conductivity c K), or None for the isotropic case. tensor_q: instead,
+    a tensor per quadrature node of the conductivity rule, [n_q][d(d+1)/2][n_elem]."""
     row_ptr, col_idx = pattern(mesh)
     M = np.zeros(col_idx.size)
     Cv = np.zeros(col_idx.size)
-    args, keep = _common(mesh, rule_m, rule_c, law_m, law_c, field_m, field_c, qpoint_m, qpoint_c, tensor_c)
+    args, keep = _common(mesh, rule_m, rule_c, law_m, law_c, field_m, field_c, qpoint_m, qpoint_c, tensor_c,
+                         tensor_q)
     bad = C.c_int64(-1)
     rc = _load().oracle_assemble(*args, row_ptr, col_idx, M, Cv, int(nthreads), C.byref(bad))
     if rc:
@@ -296,13 +303,14 @@ def load_vector(mesh, rule, law_f, field=None, qpoint=None):
 
 
 def assemble_iso(mesh, rule_m, rule_c, law_m, law_c, field_m=None, field_c=None, nthreads=0, tensor_c=None,
-                 qpoint_m=None, qpoint_c=None):
+                 qpoint_m=None, qpoint_c=None, tensor_q=None):
     """Isoparametric assembly (the element map uses the P-order basis and every node's
     position): returns (row_ptr, col_idx, M, C)."""
     row_ptr, col_idx = pattern(mesh)
     M = np.zeros(col_idx.size)
     Cv = np.zeros(col_idx.size)
-    args, keep = _common(mesh, rule_m, rule_c, law_m, law_c, field_m, field_c, qpoint_m, qpoint_c, tensor_c)
+    args, keep = _common(mesh, rule_m, rule_c, law_m, law_c, field_m, field_c, qpoint_m, qpoint_c, tensor_c,
+                         tensor_q)
     bad = C.c_int64(-1)
     rc = _load().oracle_assemble_iso(*args, row_ptr, col_idx, M, Cv, int(nthreads), C.byref(bad))
     if rc:

@@ -230,7 +230,19 @@ typedef struct {
     const double *field; /* kind 1: [n_nodes]; kind 2: [n_q][n_e] */
     const double *tensor; /* conductivity only: upper triangle (row-major) of a symmetric
                              d x d tensor K (Section 7, anisotropic conductivity), or NULL */
+    const double *tensor_q; /* conductivity only: a symmetric tensor per quadrature node,
+                               [n_q][d(d+1)/2][n_e] upper triangles (Section 7, c_q varying
+                               over the domain), or NULL; exclusive with tensor */
 } oracle_coeff;
+
+/* Upper triangle of the conductivity tensor at node q of element e (NULL: identity). */
+static const double *tensor_at(const oracle_coeff *c, int d, int64_t n_e, int64_t e, int q, double *buf)
+{
+    if (!c->tensor_q) return c->tensor;
+    int ng = d * (d + 1) / 2;
+    for (int g = 0; g < ng; ++g) buf[g] = c->tensor_q[((size_t)q * ng + g) * n_e + e];
+    return buf;
+}
 
 /* A_e = B^{-1} K B^{-T} (K = identity when tensor is NULL), full d x d. */
 static void metric(int d, const double *Binv, const double *tensor, double *A)
@@ -372,6 +384,10 @@ static int element_matrices(const refdata *R, const double *coords, int64_t n_no
         const double *Jq = R->dphi_c + (size_t)q * n * d;
         double wq = R->w_c[q];
         double cq = coeff_at(cc, ph, n, conn, n_e, e, q);
+        if (cc->tensor_q) {   /* A_qe = B_e^{-1} K_qe B_e^{-T} per node */
+            double kq[6];
+            metric(d, Binv, tensor_at(cc, d, n_e, e, q, kq), A);
+        }
         double JA[MAXP * MAXD];
         for (int i = 0; i < n; ++i)
             for (int b = 0; b < d; ++b) {
@@ -961,7 +977,8 @@ static int element_matrices_iso(const refdata *R, const double *coords, int64_t 
                 for (int i = 0; i < n; ++i)
                     for (int j = 0; j < n; ++j) Me[i * n + j] += lam * ph[i] * ph[j];
             } else {
-                metric(d, Binv, cc->tensor, A);
+                double kq[6];
+                metric(d, Binv, tensor_at(cc, d, n_e, e, q, kq), A);
                 double lam = w[q] * coeff_at(cc, ph, n, conn, n_e, e, q) * adet;
                 for (int i = 0; i < n; ++i)
                     for (int j = 0; j < n; ++j) {
