@@ -87,7 +87,14 @@ typedef struct {
  * triangle, row-major, of a constant symmetric d x d tensor K (2D: K00, K01, K11;
  * 3D: K00, K01, K02, K11, K12, K22); the conductivity is then s K, the anisotropic
  * case of Section 7 with A_qe = B_e^{-1} s_q K B_e^{-T}. NULL: isotropic (K = I).
- * Read during the call (qxa_server_submit copies it). */
+ * Read during the call (qxa_server_submit copies it).
+ * tensor_q (conductivity coefficient of qxa_assemble_iso only, else NULL): device
+ * array [n_q][d(d+1)/2][n_elem] of upper triangles, row-major, of a symmetric tensor
+ * K_qe per node q of the stiffness rule and element e; the conductivity is then
+ * s_qe K_qe (Section 7 with c_q varying over the domain: A_qe = B^{-1} s_qe K_qe B^{-T},
+ * a metric per node, which the isoparametric path forms anyway and which covers
+ * straight-sided meshes exactly). Exclusive with tensor. Other entry points return
+ * QXA_E_UNSUPPORTED when it is set. */
 typedef struct {
     int kind;
     int law;
@@ -95,6 +102,7 @@ typedef struct {
     double a[3];
     const double *field;
     const double *tensor;
+    const double *tensor_q;
 } qxa_coeff;
 
 typedef struct qxa_mesh_s *qxa_mesh;
@@ -253,15 +261,17 @@ qxa_status qxa_load_vector(qxa_plan plan, const qxa_coeff *f, double *F, void *s
  * basis and the positions of all of an element's nodes, x(xhat) = sum_i x_i phi_i(xhat),
  * so B, |det B| and A = B^{-1} K B^{-T} are evaluated at every quadrature node (X_m and
  * X_c per (q, e); Q_m and Q_c unchanged). Same coefficients, outputs and pattern as
- * qxa_assemble, in FP64. Two passes: the local matrices of every element (one thread
- * per (element, row)) to a plan-owned buffer, then one thread per CSR slot sums the
- * slot's element entries in ascending element order (deterministic, bitwise
- * symmetric). The first call on a plan builds the slot -> entries map (shared with
- * qxa_cond_tensor_product: 4 n_p^2 n_elem + 8 (nnz + 1) bytes) and allocates
- * 16 n_p^2 n_elem bytes of element matrices; later calls allocate nothing. Errors as
- * qxa_assemble, plus QXA_E_UNSUPPORTED when n_p^2 n_elem >= 2^31; a non-finite
- * coefficient, or a map with det B_q = 0 at a quadrature node, is reported by qxa_sync
- * as QXA_E_NONFINITE.
+ * qxa_assemble, in FP64. Two passes: the local matrices of every element (X per
+ * quadrature node, then V = Q X, once per symmetric pair) to a plan-owned buffer, then
+ * one thread per CSR slot sums the slot's element entries in ascending element order
+ * (deterministic, bitwise symmetric). The first call on a plan builds the slot ->
+ * entries map (shared with qxa_cond_tensor_product: 4 n_p^2 n_elem + 8 (nnz + 1) bytes)
+ * and allocates 16 n_s n_elem bytes of local matrices (n_s = n_p (n_p + 1) / 2, n_elem
+ * rounded up to a multiple of 64); later calls allocate nothing. Errors as
+ * qxa_assemble, plus QXA_E_UNSUPPORTED when n_p^2 n_elem >= 2^31 and QXA_E_INVALID for
+ * tensor_q on the mass coefficient or with tensor; a non-finite coefficient or tensor
+ * entry, or a map with det B_q = 0 at a quadrature node, is reported by qxa_sync as
+ * QXA_E_NONFINITE. The stiffness coefficient may carry a per-node tensor (tensor_q).
  */
 qxa_status qxa_assemble_iso(qxa_plan plan, const qxa_coeff *mass, const qxa_coeff *stiff, double *M_vals,
                             double *C_vals, void *stream);

@@ -38,7 +38,7 @@ class _Quad(C.Structure):
 
 class _Coeff(C.Structure):
     _fields_ = [("kind", C.c_int), ("law", C.c_int), ("value", C.c_double), ("a", C.c_double * 3),
-                ("field", C.c_void_p), ("tensor", C.c_void_p)]
+                ("field", C.c_void_p), ("tensor", C.c_void_p), ("tensor_q", C.c_void_p)]
 
 
 class _PlanInfo(C.Structure):
@@ -265,15 +265,20 @@ def plan_check_host(dim, order, coords, conn):
     return nt.value, npart.value
 
 
-def make_coeff(law, field=None, qpoint=False, tensor=None):
+def make_coeff(law, field=None, qpoint=False, tensor=None, tensor_q=None):
     """Build the ABI coefficient struct; returns (struct, keepalive). tensor: upper triangle
-    (row-major) of a constant symmetric conductivity tensor K, for conductivity coefficients."""
+    (row-major) of a constant symmetric conductivity tensor K, for conductivity coefficients;
+    tensor_q: device float64 [n_q][d(d+1)/2][n_elem], a tensor per quadrature node
+    (isoparametric path only)."""
     c = _Coeff()
     c.a[0] = c.a[1] = c.a[2] = 0.0
     kt = None
     if tensor is not None:
         kt = np.ascontiguousarray(tensor, dtype=np.float64)
         c.tensor = kt.ctypes.data
+    if tensor_q is not None:
+        kt = (kt, tensor_q)
+        c.tensor_q = tensor_q.data_ptr()
     if law[0] == "const":
         c.kind, c.law, c.value, c.field = 0, 0, float(law[1]), None
         return c, kt
@@ -343,9 +348,10 @@ def cond_tensor_product(plan: Plan, law_dc, u, v, T=None, stream=None, tensor=No
 
 
 def assemble_iso(plan: Plan, law_m, law_c, field_m=None, field_c=None, M=None, Cv=None, stream=None,
-                 want_m=True, want_c=True, qpoint=False, tensor=None):
+                 want_m=True, want_c=True, qpoint=False, tensor=None, tensor_q=None):
     """Isoparametric (curved) elements: M and C with the geometry evaluated per quadrature
-    node from every node's position (qxa_assemble_iso, FP64)."""
+    node from every node's position (qxa_assemble_iso, FP64). tensor_q: optional device
+    conductivity tensor per quadrature node, float64 [n_q][d(d+1)/2][n_elem]."""
     import torch
     dev = torch.device("cuda", plan.mesh.device)
     if want_m and M is None:
@@ -353,7 +359,7 @@ def assemble_iso(plan: Plan, law_m, law_c, field_m=None, field_c=None, M=None, C
     if want_c and Cv is None:
         Cv = torch.empty(plan.nnz, dtype=torch.float64, device=dev)
     cm, k1 = make_coeff(law_m, field_m, qpoint)
-    cc, k2 = make_coeff(law_c, field_c, qpoint, tensor)
+    cc, k2 = make_coeff(law_c, field_c, qpoint, tensor, tensor_q)
     check(lib().qxa_assemble_iso(plan.handle, C.byref(cm), C.byref(cc), _ptr(M if want_m else None),
                                  _ptr(Cv if want_c else None), _stream_ptr(stream)))
     return M, Cv

@@ -87,6 +87,10 @@ static qxa_status to_coeff(const qxa_coeff *c, CoeffDev &out, const char *which)
     if (c->kind != 0 && !c->field) return fail(QXA_E_INVALID, std::string(which) + " coefficient: null field");
     if (c->kind == 0 && !std::isfinite(c->value))
         return fail(QXA_E_NONFINITE, std::string(which) + " coefficient: non-finite constant");
+    if (c->tensor_q)
+        return fail(QXA_E_UNSUPPORTED, std::string(which) +
+                                           " coefficient: a tensor per quadrature node is taken by the "
+                                           "isoparametric path (qxa_assemble_iso) only");
     out = CoeffDev{c->kind, c->law, c->value, c->a[0], c->a[1], c->a[2], c->field};
     return QXA_OK;
 }
@@ -766,9 +770,18 @@ qxa_status qxa_assemble_iso(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *
     if (!p) return fail(QXA_E_INVALID, "null plan");
     if (!p->d_flags) return fail(QXA_E_INVALID, "plan is owned by a server");
     IsoArgs a{};
+    if (mass && mass->tensor_q) return fail(QXA_E_INVALID, "mass coefficient: a tensor applies to conductivity only");
+    if (stiff && stiff->tensor_q && stiff->tensor)
+        return fail(QXA_E_INVALID, "conductivity: give either a constant tensor or one per quadrature node");
+    qxa_coeff sc{};
+    if (stiff) {
+        sc = *stiff;
+        sc.tensor_q = nullptr;  // validated with the rest; passed to the kernel below
+    }
     const void *qm, *qc;
-    qxa_status st = fill_inputs(p, mass, stiff, QXA_FP64, a.in, &qm, &qc);
+    qxa_status st = fill_inputs(p, mass, stiff ? &sc : nullptr, QXA_FP64, a.in, &qm, &qc);
     if (st) return st;
+    a.Kq = stiff ? stiff->tensor_q : nullptr;
     const qxa_mesh m = p->mesh;
     if ((!M_vals && !C_vals) || m->n_elem == 0) return QXA_OK;
     QXA_HIP(hipSetDevice(m->device));
@@ -776,12 +789,15 @@ qxa_status qxa_assemble_iso(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *
         st = build_slot_entries(p);
         if (st) return st;
     }
-    const size_t nt = size_t(p->ref.np) * p->ref.np * m->n_elem;
+    // symmetric local matrices once per pair, pair-major per block of kIsoElems elements
+    const size_t nt = size_t(p->ref.ns) * ((m->n_elem + kIsoElems - 1) / kIsoElems) * kIsoElems;
     if (!p->d_Tiso) {
         st = plan_alloc(p, &p->d_Tiso, 2 * nt);
         if (st) return st;
     }
     a.conn = m->d_conn;
+    a.Qm = static_cast<const double *>(qm);
+    a.Qc = static_cast<const double *>(qc);
     a.dphi_m = p->d_tables + p->off_dphim;
     a.dphi_c = p->d_tables + p->off_dphic;
     a.Tm = M_vals ? p->d_Tiso : nullptr;
@@ -793,9 +809,10 @@ qxa_status qxa_assemble_iso(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *
     }
     TimedLaunch tl(p, "slot_gather", s);
     const SlotGatherArgs g = M_vals && C_vals
-                                 ? SlotGatherArgs{p->nnz, p->d_ns_ptr, p->d_ns_items, a.Tm, M_vals, a.Tc, C_vals}
+                                 ? SlotGatherArgs{p->nnz, p->d_ns_ptr, p->d_ns_items, a.Tm, M_vals, a.Tc, C_vals,
+                                                  p->ref.np}
                                  : SlotGatherArgs{p->nnz, p->d_ns_ptr, p->d_ns_items, M_vals ? a.Tm : a.Tc,
-                                                  M_vals ? M_vals : C_vals, nullptr, nullptr};
+                                                  M_vals ? M_vals : C_vals, nullptr, nullptr, p->ref.np};
     QXA_HIP(launch_slot_gather(g, s));
     return QXA_OK;
 }
@@ -826,7 +843,7 @@ qxa_status qxa_load_vector(qxa_plan p, const qxa_coeff *f, double *F, void *stre
         QXA_HIP(launch_load(a, m->dim, m->order, p->ref.nq_m, s));
     }
     TimedLaunch tl(p, "slot_gather", s);
-    const SlotGatherArgs g{m->n_nodes, p->d_nf_ptr, p->d_nf_items, p->d_Fe, F, nullptr, nullptr};
+    const SlotGatherArgs g{m->n_nodes, p->d_nf_ptr, p->d_nf_items, p->d_Fe, F, nullptr, nullptr, 0};
     QXA_HIP(launch_slot_gather(g, s));
     return QXA_OK;
 }
@@ -867,7 +884,7 @@ qxa_status qxa_cond_tensor_product(qxa_plan p, const qxa_coeff *c, const double 
         QXA_HIP(launch_cond_tensor(a, m->dim, m->order, p->ref.nq_c, s));
     }
     TimedLaunch tl(p, "slot_gather", s);
-    const SlotGatherArgs g{p->nnz, p->d_ns_ptr, p->d_ns_items, p->d_T, T_vals, nullptr, nullptr};
+    const SlotGatherArgs g{p->nnz, p->d_ns_ptr, p->d_ns_items, p->d_T, T_vals, nullptr, nullptr, 0};
     QXA_HIP(launch_slot_gather(g, s));
     return QXA_OK;
 }

@@ -273,43 +273,10 @@ hipError_t launch_load(const LoadArgs &a, int D, int P, int nq, hipStream_t st)
     return hipErrorInvalidValue;
 }
 
-// Coefficient s(x_q) of one quadrature node for the isoparametric path (nodal
-// fields interpolated from global memory; per-(q, e) values in mesh order).
-template <int NP, int NQ>
-__device__ __forceinline__ double coeff_node(const CoeffDev &c, const double *phi, const int32_t *conn, int64_t ne,
-                                             int64_t e, int q)
+// Inverse and |det| of a d x d matrix (adjugate over the determinant).
+template <int D>
+__device__ __forceinline__ void inverse_abs_det(const double (&B)[D][D], double (&I)[D][D], double &adet)
 {
-    if (c.kind == 0) return c.value;
-    if (c.kind == 1) {
-        double uh = 0.0;
-#pragma unroll
-        for (int i = 0; i < NP; ++i) uh = fma(uniform_table(phi)[i * NQ + q], c.field[conn[i * ne + e]], uh);
-        return apply_law(c, uh);
-    }
-    return apply_law(c, c.field[q * ne + e]);
-}
-
-// B_q = sum_i x_i J_q[i]^T of a curved (isoparametric) element, its inverse and |det|.
-template <int D, int NP>
-__device__ __forceinline__ void iso_geometry(const FormInputs &in, const int32_t *conn, int64_t e, const double *J,
-                                             double (&I)[D][D], double &adet)
-{
-    const int64_t ne = in.n_elem;
-    double B[D][D];
-#pragma unroll
-    for (int r = 0; r < D; ++r)
-#pragma unroll
-        for (int c = 0; c < D; ++c) B[r][c] = 0.0;
-#pragma unroll
-    for (int i = 0; i < NP; ++i) {
-        const int32_t node = conn[i * ne + e];
-#pragma unroll
-        for (int r = 0; r < D; ++r) {
-            const double xr = in.coords[r * in.n_nodes + node];
-#pragma unroll
-            for (int c = 0; c < D; ++c) B[r][c] = fma(xr, uniform_table(J)[i * D + c], B[r][c]);
-        }
-    }
     if constexpr (D == 2) {
         const double det = B[0][0] * B[1][1] - B[0][1] * B[1][0], r = 1.0 / det;
         I[0][0] = B[1][1] * r;
@@ -335,93 +302,155 @@ __device__ __forceinline__ void iso_geometry(const FormInputs &in, const int32_t
     }
 }
 
-// Isoparametric elements (curved geometry, Section 7): row a of M_e and C_e with B, |det B|
-// and A = B^{-1} K B^{-T} evaluated per quadrature node from every node's position
-// (X_m and X_c per (q, e); the contraction with Phi (.) Phi and [J_q (x) J_q] is unchanged).
-// One thread per (element, row a): blockIdx.y = a.
+// Isoparametric elements (curved geometry, Section 7): M_e and C_e with B, |det B| and
+// A = B^{-1} K B^{-T} evaluated per quadrature node from every node's position, so X
+// holds one column per (q, e): X_m[q] = w_q m_q |det B_q| and X_c[(q, g)] = w_q c_q
+// |det B_q| A_q[g]; the contraction V = Q X with the plan's Q_m and Q_c (symmetric pair
+// rows) is unchanged. A block takes 64 elements, one per lane, in three phases through
+// LDS: the elements' node positions and nodal fields (one wave per local node), X (one
+// wave per quadrature node: B_q, |det B_q|, the coefficient, A_q), then V (one wave per
+// pair a <= b, Q read as wave-uniform scalars), stored once per pair in a pair-major
+// layout [block][pair][64] so that the lanes of a wave write 512 contiguous bytes.
+
+template <int D, int P, int NQM, int NQC>
+constexpr size_t iso_lds_doubles()
+{
+    using S = Shape<D, P>;
+    return size_t(kIsoElems) * (S::NP * D + 2 * S::NP + NQM + NQC * S::NG);
+}
+
 template <int D, int P, int NQM, int NQC>
 __global__ __launch_bounds__(256) void iso_rows_kernel(IsoArgs a)
 {
     using S = Shape<D, P>;
-    constexpr int NP = S::NP;
-    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int ra = blockIdx.y;
+    constexpr int NP = S::NP, NG = S::NG, NS = S::NS, E = kIsoElems;
+    extern __shared__ double iso_lds[];
+    double *sCrd = iso_lds;              // [NP * D][E] node positions
+    double *sUm = sCrd + NP * D * E;     // [NP][E] nodal field of the mass coefficient
+    double *sUc = sUm + NP * E;          // [NP][E] nodal field of the conductivity coefficient
+    double *sXm = sUc + NP * E;          // [NQM][E]
+    double *sXc = sXm + NQM * E;         // [NQC * NG][E]
     const FormInputs &in = a.in;
-    const int64_t ne = in.n_elem;
-    if (e >= ne) return;
-    bool ok = true;
-    if (a.Tm) {
-        double row[NP];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const int nw = int(blockDim.x >> 6);
+    const int64_t ne = in.n_elem, e = int64_t(blockIdx.x) * E + lane;
+    const bool live = e < ne;
+    for (int i = wave; i < NP; i += nw) {
+        const int32_t node = live ? a.conn[i * ne + e] : 0;
 #pragma unroll
-        for (int b = 0; b < NP; ++b) row[b] = 0.0;
-        for (int q = 0; q < NQM; ++q) {
-            double I[D][D], adet;
-            iso_geometry<D, NP>(in, a.conn, e, a.dphi_m + size_t(q) * NP * D, I, adet);
-            const double lam = uniform_table(in.w_m)[q] * coeff_node<NP, NQM>(in.cm, in.phi_m, a.conn, ne, e, q) * adet;
-            ok &= isfinite(lam) && adet > 0.0;
-            const double pa = uniform_table(in.phi_m)[ra * NQM + q];
-            // lam * (phi_a phi_b): the same bits for (a, b) and (b, a)
-#pragma unroll
-            for (int b = 0; b < NP; ++b) row[b] = fma(lam, pa * uniform_table(in.phi_m)[b * NQM + q], row[b]);
-        }
-#pragma unroll
-        for (int b = 0; b < NP; ++b) a.Tm[(e * NP + ra) * NP + b] = row[b];
+        for (int r = 0; r < D; ++r) sCrd[(i * D + r) * E + lane] = live ? in.coords[r * in.n_nodes + node] : 0.0;
+        sUm[i * E + lane] = live && in.cm.kind == 1 ? in.cm.field[node] : 0.0;
+        sUc[i * E + lane] = live && in.cc.kind == 1 ? in.cc.field[node] : 0.0;
     }
-    if (a.Tc) {
-        double row[NP];
+    __syncthreads();
+    bool ok = true;
+    for (int qq = wave; qq < NQM + NQC; qq += nw) {
+        const bool mass = qq < NQM;
+        const int q = mass ? qq : qq - NQM;
+        if (mass ? !a.Tm : !a.Tc) continue;  // never read
+        const auto J = uniform_table((mass ? a.dphi_m : a.dphi_c) + size_t(q) * NP * D);
+        double B[D][D];
 #pragma unroll
-        for (int b = 0; b < NP; ++b) row[b] = 0.0;
-        for (int q = 0; q < NQC; ++q) {
-            const double *J = a.dphi_c + size_t(q) * NP * D;
-            double I[D][D], adet, Au[S::NG];
-            iso_geometry<D, NP>(in, a.conn, e, J, I, adet);
-            metric_from_inverse<D>(I, in.aniso, in.K, Au);
-            double A[D][D];
-            {
-                int g = 0;
+        for (int r = 0; r < D; ++r)
 #pragma unroll
-                for (int r = 0; r < D; ++r)
+            for (int c = 0; c < D; ++c) B[r][c] = 0.0;
 #pragma unroll
-                    for (int c = r; c < D; ++c, ++g) A[r][c] = A[c][r] = Au[g];
+        for (int i = 0; i < NP; ++i)
+#pragma unroll
+            for (int r = 0; r < D; ++r) {
+                const double xr = sCrd[(i * D + r) * E + lane];
+#pragma unroll
+                for (int c = 0; c < D; ++c) B[r][c] = fma(xr, J[i * D + c], B[r][c]);
             }
-            const double lam = uniform_table(in.w_c)[q] * coeff_node<NP, NQC>(in.cc, in.phi_c, a.conn, ne, e, q) * adet;
-            ok &= isfinite(lam) && adet > 0.0;
-            double ja[D];
+        double I[D][D], adet;
+        inverse_abs_det<D>(B, I, adet);
+        const CoeffDev &cf = mass ? in.cm : in.cc;
+        double sv = cf.value;
+        if (cf.kind == 1) {
+            const auto phi = uniform_table(mass ? in.phi_m : in.phi_c);
+            const double *u = mass ? sUm : sUc;
+            double uh = 0.0;  // u_h(xhat_q) = phi_q^T u_e
 #pragma unroll
-            for (int c = 0; c < D; ++c) ja[c] = uniform_table(J)[ra * D + c];
-            // J_a^T A J_b summed over the upper triangle of A, each off-diagonal term as
-            // A_ck (J_a,c J_b,k + J_a,k J_b,c): the same bits for (a, b) and (b, a)
+            for (int i = 0; i < NP; ++i) uh = fma(phi[i * (mass ? NQM : NQC) + q], u[i * E + lane], uh);
+            sv = apply_law(cf, uh);
+        } else if (cf.kind == 2) {
+            sv = live ? apply_law(cf, cf.field[q * ne + e]) : 0.0;
+        }
+        const double lam = uniform_table(mass ? in.w_m : in.w_c)[q] * sv * adet;
+        if (mass) {
+            if (live) {
+                ok &= isfinite(lam) && adet > 0.0;
+                sXm[q * E + lane] = lam;
+            }
+        } else {
+            double Au[NG];
+            if (a.Kq) {  // K_qe: a tensor per quadrature node
+                double Kl[NG];
 #pragma unroll
-            for (int b = 0; b < NP; ++b) {
-                // no contraction of the pair sums into an fma (that would lose the symmetry)
-#pragma clang fp contract(off)
-                double jb[D];
-#pragma unroll
-                for (int c = 0; c < D; ++c) jb[c] = uniform_table(J)[b * D + c];
-                double s = 0.0;
-#pragma unroll
-                for (int c = 0; c < D; ++c) {
-                    s = fma(A[c][c], ja[c] * jb[c], s);
-#pragma unroll
-                    for (int k = c + 1; k < D; ++k) s = fma(A[c][k], ja[c] * jb[k] + ja[k] * jb[c], s);
+                for (int g = 0; g < NG; ++g) {
+                    Kl[g] = live ? a.Kq[(int64_t(q) * NG + g) * ne + e] : 0.0;
+                    ok &= isfinite(Kl[g]);
                 }
-                row[b] = fma(lam, s, row[b]);
+                metric_from_inverse<D>(I, 1, Kl, Au);
+            } else {
+                metric_from_inverse<D>(I, in.aniso, in.K, Au);
+            }
+            if (live) {
+                ok &= isfinite(lam) && adet > 0.0;
+#pragma unroll
+                for (int g = 0; g < NG; ++g) sXc[(q * NG + g) * E + lane] = lam * Au[g];
             }
         }
-#pragma unroll
-        for (int b = 0; b < NP; ++b) a.Tc[(e * NP + ra) * NP + b] = row[b];
     }
     if (!ok) atomicOr(in.flags, 1);
+    __syncthreads();
+    if (!live) return;
+    // PB pairs per pass: each X value read from LDS serves PB rows of Q
+    constexpr int PB = 4;
+    for (int sp0 = wave * PB; sp0 < NS; sp0 += nw * PB) {
+        int spj[PB];
+#pragma unroll
+        for (int j = 0; j < PB; ++j) spj[j] = min(sp0 + j, NS - 1);
+        if (a.Tm) {
+            double v[PB];
+#pragma unroll
+            for (int j = 0; j < PB; ++j) v[j] = 0.0;
+#pragma unroll
+            for (int q = 0; q < NQM; ++q) {
+                const double x = sXm[q * E + lane];
+#pragma unroll
+                for (int j = 0; j < PB; ++j) v[j] = fma(uniform_table(a.Qm)[spj[j] * NQM + q], x, v[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < PB; ++j)
+                if (sp0 + j < NS) a.Tm[(size_t(blockIdx.x) * NS + sp0 + j) * E + lane] = v[j];
+        }
+        if (a.Tc) {
+            double v[PB];
+#pragma unroll
+            for (int j = 0; j < PB; ++j) v[j] = 0.0;
+#pragma unroll 6
+            for (int k = 0; k < NQC * NG; ++k) {
+                const double x = sXc[k * E + lane];
+#pragma unroll
+                for (int j = 0; j < PB; ++j) v[j] = fma(uniform_table(a.Qc)[spj[j] * (NQC * NG) + k], x, v[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < PB; ++j)
+                if (sp0 + j < NS) a.Tc[(size_t(blockIdx.x) * NS + sp0 + j) * E + lane] = v[j];
+        }
+    }
 }
 
 hipError_t launch_iso(const IsoArgs &a, int D, int P, int nqm, int nqc, hipStream_t st)
 {
     if (a.in.n_elem == 0) return hipSuccess;
-#define X(d, p, m, c)                                                                          \
-    if (D == d && P == p && nqm == m && nqc == c) {                                            \
-        const dim3 grid(unsigned((a.in.n_elem + 255) / 256), unsigned(Shape<d, p>::NP));      \
-        iso_rows_kernel<d, p, m, c><<<grid, 256, 0, st>>>(a);                                 \
-        return hipGetLastError();                                                              \
+    const unsigned blocks = unsigned((a.in.n_elem + kIsoElems - 1) / kIsoElems);
+#define X(d, p, m, c)                                                                                  \
+    if (D == d && P == p && nqm == m && nqc == c) {                                                    \
+        iso_rows_kernel<d, p, m, c><<<blocks, 256, iso_lds_doubles<d, p, m, c>() * sizeof(double), st>>>(a); \
+        return hipGetLastError();                                                                      \
     }
     QXA_FORM_CASES(X)
 #undef X
@@ -436,7 +465,20 @@ __global__ __launch_bounds__(256) void slot_gather_kernel(SlotGatherArgs a)
     if (t >= a.n_slots) return;
     const int64_t lo = a.ptr[t], hi = a.ptr[t + 1];
     double s = 0.0;
-    if (a.src2) {
+    if (a.sym_np) {  // entry (e, a, b) of a symmetric local matrix stored once per pair
+        const int np = a.sym_np, ns = np * (np + 1) / 2;
+        double s2 = 0.0;
+        for (int64_t k = lo; k < hi; ++k) {
+            const int32_t it = a.items[k];
+            const int32_t eb = it / np, b = it - eb * np, e = eb / np, ea = eb - e * np;
+            const int lo_ = min(ea, b), hi_ = max(ea, b);
+            const int sp = lo_ * np - lo_ * (lo_ - 1) / 2 + (hi_ - lo_);
+            const size_t i = (size_t(e / kIsoElems) * ns + sp) * kIsoElems + (e % kIsoElems);
+            s += a.src[i];
+            if (a.src2) s2 += a.src2[i];
+        }
+        if (a.src2) a.out2[t] = s2;
+    } else if (a.src2) {
         double s2 = 0.0;
         for (int64_t k = lo; k < hi; ++k) {
             const int32_t i = a.items[k];

@@ -50,7 +50,10 @@ struct IsoArgs {
     const int32_t *conn;   // [np][n_elem]
     const double *dphi_m;  // [nq_m][np][dim]
     const double *dphi_c;  // [nq_c][np][dim]
-    double *Tm, *Tc;       // [n_elem][np][np] local matrices
+    const double *Qm;      // [ns][nq_m] FP64 mass table (symmetric pair rows)
+    const double *Qc;      // [ns][nq_c][ng] FP64 conductivity table
+    const double *Kq;      // [nq_c][ng][n_elem] conductivity tensor per node (or null)
+    double *Tm, *Tc;       // [n_elem / 64][ns][64] symmetric local matrices, pair-major per block
 };
 
 struct SlotGatherArgs {
@@ -61,7 +64,12 @@ struct SlotGatherArgs {
     double *out;           // [n_slots]
     const double *src2;    // optional second source, gathered with the same entries
     double *out2;
+    int sym_np;            // > 0: items (e * np + a) * np + b address a symmetric local matrix
+                           // stored once per pair, [n_elem / 64][ns][64] (isoparametric path)
 };
+
+// Elements per block of the isoparametric kernel and of its pair-major layout.
+constexpr int kIsoElems = 64;
 
 hipError_t launch_expand(const ExpandArgs &a, hipStream_t st);
 hipError_t launch_coeff_product(const CoeffProductArgs &a, int D, int P, int nq, hipStream_t st);

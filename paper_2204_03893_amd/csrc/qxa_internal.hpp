@@ -191,7 +191,7 @@ struct qxa_plan_s {
     double *d_tables = nullptr;   // device copy of w, Phi, Qm, Qc (FP64)
     float *d_tables_f = nullptr;  // FP32 copy
     size_t off_wm = 0, off_wc = 0, off_phim = 0, off_phic = 0, off_qm = 0, off_qc = 0, off_dphic = 0, off_dphim = 0;
-    double *d_Tiso = nullptr;     // [2][n_elem][np][np] isoparametric local matrices (first use)
+    double *d_Tiso = nullptr;     // [2][n_elem / 64][ns][64] isoparametric local matrices (pair-major) (first use)
     double *d_V = nullptr;        // [2][ns][n_elem] formation-only buffer (allocated on first use)
     // conductivity tensor product (built on first use): local matrices [n_elem][np][np]
     // and, per CSR slot (both triangles), its element entries (index into d_T) in

@@ -640,6 +640,8 @@ qxa_status qxa_server_submit(qxa_server s, const qxa_job *job, uint64_t *ticket)
     j->spec.stiff_rule.points = j->cr_pts.data();
     j->spec.stiff_rule.weights = j->cr_w.data();
     if (job->mass.tensor) return fail(QXA_E_INVALID, "mass coefficient: a tensor applies to conductivity only");
+    if (job->mass.tensor_q || job->stiff.tensor_q)
+        return fail(QXA_E_UNSUPPORTED, "a tensor per quadrature node is taken by qxa_assemble_iso only");
     if (job->stiff.tensor) {
         std::copy(job->stiff.tensor, job->stiff.tensor + m->dim * (m->dim + 1) / 2, j->tensor);
         j->spec.stiff.tensor = j->tensor;

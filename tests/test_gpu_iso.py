@@ -108,3 +108,67 @@ def test_iso_nonfinite_coefficient_is_reported():
     assert ei.value.code == -4                       # QXA_E_NONFINITE
     qxa.assemble_iso(plan, ("const", 1.0), ("const", 1.0))   # the report is cleared by qxa_sync
     qxa.sync(plan)
+
+
+def _Kq(dim, nq, ne, seed):
+    rng = np.random.default_rng(seed)
+    ng = dim * (dim + 1) // 2
+    S = np.eye(dim)[None, None] + 0.3 * rng.uniform(-1, 1, size=(nq, ne, dim, dim))
+    K = np.einsum("qeab,qecb->qeac", S, S)                       # SPD per (q, e)
+    iu = np.triu_indices(dim)
+    return np.ascontiguousarray(K[:, :, iu[0], iu[1]].transpose(0, 2, 1)).reshape(nq, ng, ne)
+
+
+@pytest.mark.parametrize("dim,order,N", SHAPES)
+def test_iso_per_node_tensor_against_oracle(dim, order, N):
+    import paper_2204_03893_amd as qxa
+    print("case iso per-node tensor", dim, order, N, flush=True)
+    base = structured_mesh(dim, order, N, 0.1, seed=[121, dim, order])
+    r = rule(dim, 2 * order)
+    ne = base["conn"].shape[1]
+    Kq = _Kq(dim, r[1].size, ne, [122, dim, order])
+    u = gaussian_random_field(base["coords"], 16, np.random.default_rng([123, dim]), length=0.3)
+    law_c = ("exp", 0.0, 0.5)
+    Kd = torch.tensor(Kq, device="cuda")
+    uf = torch.tensor(u, device="cuda")
+    for curved in (False, True):
+        mesh = _curved(base, 0.1 / N) if curved else base
+        m = qxa.Mesh(dim, order, mesh["coords"], mesh["conn"])
+        plan = qxa.Plan(m, r)
+        M, Cv = qxa.assemble_iso(plan, ("const", 1.0), law_c, None, uf, tensor_q=Kd)
+        qxa.sync(plan)
+        fn = oracle.assemble_iso if curved else oracle.assemble    # straight sides: the affine oracle
+        rpo, cio, Mo, Co = fn(mesh, r, r, ("const", 1.0), law_c, None, u, tensor_q=Kq)
+        assert row_scaled_error(M.cpu().numpy(), Mo, rpo) <= 1e-12
+        Cg = Cv.cpu().numpy()
+        assert row_scaled_error(Cg, Co, rpo) <= 1e-12
+        tr = transpose_slots(rpo, cio)
+        assert np.array_equal(Cg, Cg[tr])
+
+
+def test_per_node_tensor_errors():
+    import paper_2204_03893_amd as qxa
+    dim, order = 2, 2
+    mesh = structured_mesh(dim, order, 3, 0.0)
+    r = rule(dim, 2 * order)
+    m = qxa.Mesh(dim, order, mesh["coords"], mesh["conn"])
+    plan = qxa.Plan(m, r)
+    Kd = torch.tensor(_Kq(dim, r[1].size, mesh["conn"].shape[1], 124), device="cuda")
+    with pytest.raises(qxa.QxaError) as ei:                       # the fused path does not take it
+        cc, k = qxa.make_coeff(("const", 1.0), tensor_q=Kd)
+        qxa.check(qxa.lib().qxa_assemble(plan.handle, None, qxa.C.byref(cc), 0, None, None, None))
+    assert ei.value.code == -6
+    with pytest.raises(qxa.QxaError) as ei:                       # constant and per-node tensor together
+        qxa.assemble_iso(plan, ("const", 1.0), ("const", 1.0), tensor=np.array([1.0, 0.0, 1.0]), tensor_q=Kd)
+    assert ei.value.code == -1
+    with pytest.raises(qxa.QxaError) as ei:                       # not on the mass coefficient
+        cm, k = qxa.make_coeff(("const", 1.0), tensor_q=Kd)
+        M = torch.empty(plan.nnz, dtype=torch.float64, device="cuda")
+        qxa.check(qxa.lib().qxa_assemble_iso(plan.handle, qxa.C.byref(cm), None, M.data_ptr(), None, None))
+    assert ei.value.code == -1
+    Kn = Kd.clone()
+    Kn[0, 0, 2] = float("nan")
+    qxa.assemble_iso(plan, ("const", 1.0), ("const", 1.0), tensor_q=Kn)
+    with pytest.raises(qxa.QxaError) as ei:                       # a non-finite entry is reported
+        qxa.sync(plan)
+    assert ei.value.code == -4
