@@ -343,7 +343,8 @@ qxa_status qxa_plan_destroy(qxa_plan p)
     void *bufs[] = {p->d_row_ptr, p->d_col_idx, p->d_tconn, p->d_elem_order, p->d_rec, p->d_rec_ptr, p->d_rec_mid,
                     p->d_part_ptr, p->d_fix_target, p->d_fix_mirror, p->d_sink, p->d_part, p->d_qfrag[0],
                     p->d_qfrag[1], p->d_qfrag[2], p->d_qfrag[3], p->d_qfrag[4], p->d_tables, p->d_tables_f,
-                    p->d_V, p->d_flags, p->d_T, p->d_ns_ptr, p->d_ns_items, p->d_Fe, p->d_nf_ptr, p->d_nf_items, p->d_Tiso};
+                    p->d_V, p->d_flags, p->d_T, p->d_ns_ptr, p->d_ns_items, p->d_Fe, p->d_nf_ptr, p->d_nf_items, p->d_Tiso,
+                    p->d_nu_ptr, p->d_nu_items, p->d_nu_pos, p->d_nu_mirror};
     for (void *b : bufs) plan_free(p, b);
     delete p;
     return QXA_OK;
@@ -738,6 +739,48 @@ static qxa_status build_slot_entries(qxa_plan p)
     return st;
 }
 
+// Entries of every upper CSR slot for symmetric local matrices stored once per pair,
+// pair-major per block of kIsoElems elements: index (e / 64 * ns + s) * 64 + e % 64.
+// Counting sort in element order (a fixed summation order); each upper slot also
+// records its own and its mirror's position.
+static qxa_status build_upper_entries(qxa_plan p)
+{
+    const qxa_mesh m = p->mesh;
+    const int ns = p->ref.ns;
+    const int64_t ne = m->n_elem, ne_pad = (ne + kIsoElems - 1) / kIsoElems * kIsoElems;
+    if (int64_t(ns) * ne_pad >= (int64_t(1) << 31))
+        return fail(QXA_E_UNSUPPORTED, "isoparametric assembly: more than 2^31 element entries");
+    HostPlan hp;
+    qxa_status st = build_host_plan(m->dim, m->order, m->n_nodes, ne, m->h_conn.data(), hp);
+    if (st) return st;
+    std::vector<int64_t> cnt(hp.nnz, 0);
+    for (size_t k = 0; k < hp.perm_sym.size(); ++k) ++cnt[hp.perm_sym[k]];
+    std::vector<int32_t> pos, mir;
+    std::vector<int64_t> up_of(hp.nnz, -1);
+    for (int64_t t = 0; t < hp.nnz; ++t)
+        if (cnt[t]) {
+            up_of[t] = int64_t(pos.size());
+            pos.push_back(int32_t(t));
+            mir.push_back(int32_t(hp.mirror[t]));
+        }
+    const int64_t n_up = int64_t(pos.size());
+    std::vector<int64_t> ptr(n_up + 1, 0);
+    for (int64_t u = 0; u < n_up; ++u) ptr[u + 1] = ptr[u] + cnt[pos[u]];
+    std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+    std::vector<int32_t> items(static_cast<size_t>(ptr[n_up]));
+    for (int64_t e = 0; e < ne; ++e)
+        for (int s = 0; s < ns; ++s) {
+            const int64_t u = up_of[hp.perm_sym[size_t(s) * ne + e]];
+            items[size_t(fill[u]++)] = int32_t((e / kIsoElems * ns + s) * kIsoElems + e % kIsoElems);
+        }
+    st = plan_upload_buf(p, &p->d_nu_ptr, ptr.data(), ptr.size());
+    if (!st) st = plan_upload_buf(p, &p->d_nu_items, items.data(), items.size());
+    if (!st) st = plan_upload_buf(p, &p->d_nu_pos, pos.data(), pos.size());
+    if (!st) st = plan_upload_buf(p, &p->d_nu_mirror, mir.data(), mir.size());
+    if (!st) p->n_up = n_up;
+    return st;
+}
+
 // Element entries of every node (a * n_elem + e with N_e(a) = node), ascending element.
 static qxa_status build_node_entries(qxa_plan p)
 {
@@ -785,8 +828,8 @@ qxa_status qxa_assemble_iso(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *
     const qxa_mesh m = p->mesh;
     if ((!M_vals && !C_vals) || m->n_elem == 0) return QXA_OK;
     QXA_HIP(hipSetDevice(m->device));
-    if (!p->d_ns_ptr) {
-        st = build_slot_entries(p);
+    if (!p->d_nu_ptr) {
+        st = build_upper_entries(p);
         if (st) return st;
     }
     // symmetric local matrices once per pair, pair-major per block of kIsoElems elements
@@ -807,13 +850,10 @@ qxa_status qxa_assemble_iso(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *
         TimedLaunch tl(p, "iso_rows", s);
         QXA_HIP(launch_iso(a, m->dim, m->order, p->ref.nq_m, p->ref.nq_c, s));
     }
-    TimedLaunch tl(p, "slot_gather", s);
-    const SlotGatherArgs g = M_vals && C_vals
-                                 ? SlotGatherArgs{p->nnz, p->d_ns_ptr, p->d_ns_items, a.Tm, M_vals, a.Tc, C_vals,
-                                                  p->ref.np}
-                                 : SlotGatherArgs{p->nnz, p->d_ns_ptr, p->d_ns_items, M_vals ? a.Tm : a.Tc,
-                                                  M_vals ? M_vals : C_vals, nullptr, nullptr, p->ref.np};
-    QXA_HIP(launch_slot_gather(g, s));
+    TimedLaunch tl(p, "upper_gather", s);
+    const UpperGatherArgs g{p->n_up, p->d_nu_ptr, p->d_nu_items, p->d_nu_pos, p->d_nu_mirror, a.Tm, a.Tc,
+                            M_vals, C_vals};
+    QXA_HIP(launch_upper_gather(g, s));
     return QXA_OK;
 }
 
@@ -843,7 +883,7 @@ qxa_status qxa_load_vector(qxa_plan p, const qxa_coeff *f, double *F, void *stre
         QXA_HIP(launch_load(a, m->dim, m->order, p->ref.nq_m, s));
     }
     TimedLaunch tl(p, "slot_gather", s);
-    const SlotGatherArgs g{m->n_nodes, p->d_nf_ptr, p->d_nf_items, p->d_Fe, F, nullptr, nullptr, 0};
+    const SlotGatherArgs g{m->n_nodes, p->d_nf_ptr, p->d_nf_items, p->d_Fe, F};
     QXA_HIP(launch_slot_gather(g, s));
     return QXA_OK;
 }
@@ -884,7 +924,7 @@ qxa_status qxa_cond_tensor_product(qxa_plan p, const qxa_coeff *c, const double 
         QXA_HIP(launch_cond_tensor(a, m->dim, m->order, p->ref.nq_c, s));
     }
     TimedLaunch tl(p, "slot_gather", s);
-    const SlotGatherArgs g{p->nnz, p->d_ns_ptr, p->d_ns_items, p->d_T, T_vals, nullptr, nullptr, 0};
+    const SlotGatherArgs g{p->nnz, p->d_ns_ptr, p->d_ns_items, p->d_T, T_vals};
     QXA_HIP(launch_slot_gather(g, s));
     return QXA_OK;
 }

@@ -457,39 +457,44 @@ hipError_t launch_iso(const IsoArgs &a, int D, int P, int nqm, int nqc, hipStrea
     return hipErrorInvalidValue;
 }
 
-// out[t] = sum of src over the entries of slot t, in their stored order (deterministic);
-// with src2 set, out2[t] likewise from src2 in the same pass (the entry list read once).
+// out[t] = sum of src over the entries of slot t, in their stored order (deterministic).
 __global__ __launch_bounds__(256) void slot_gather_kernel(SlotGatherArgs a)
 {
     const int64_t t = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (t >= a.n_slots) return;
     const int64_t lo = a.ptr[t], hi = a.ptr[t + 1];
     double s = 0.0;
-    if (a.sym_np) {  // entry (e, a, b) of a symmetric local matrix stored once per pair
-        const int np = a.sym_np, ns = np * (np + 1) / 2;
-        double s2 = 0.0;
-        for (int64_t k = lo; k < hi; ++k) {
-            const int32_t it = a.items[k];
-            const int32_t eb = it / np, b = it - eb * np, e = eb / np, ea = eb - e * np;
-            const int lo_ = min(ea, b), hi_ = max(ea, b);
-            const int sp = lo_ * np - lo_ * (lo_ - 1) / 2 + (hi_ - lo_);
-            const size_t i = (size_t(e / kIsoElems) * ns + sp) * kIsoElems + (e % kIsoElems);
-            s += a.src[i];
-            if (a.src2) s2 += a.src2[i];
-        }
-        if (a.src2) a.out2[t] = s2;
-    } else if (a.src2) {
-        double s2 = 0.0;
-        for (int64_t k = lo; k < hi; ++k) {
-            const int32_t i = a.items[k];
-            s += a.src[i];
-            s2 += a.src2[i];
-        }
-        a.out2[t] = s2;
-    } else {
-        for (int64_t k = lo; k < hi; ++k) s += a.src[a.items[k]];
-    }
+    for (int64_t k = lo; k < hi; ++k) s += a.src[a.items[k]];
     a.out[t] = s;
+}
+
+__global__ __launch_bounds__(256) void upper_gather_kernel(UpperGatherArgs a)
+{
+    const int64_t u = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (u >= a.n_up) return;
+    const int64_t lo = a.ptr[u], hi = a.ptr[u + 1];
+    const int32_t t = a.pos[u], tm = a.mirror[u];
+    double sm = 0.0, sc = 0.0;
+    for (int64_t k = lo; k < hi; ++k) {
+        const int32_t i = a.items[k];
+        if (a.srcM) sm += a.srcM[i];
+        if (a.srcC) sc += a.srcC[i];
+    }
+    if (a.M) {
+        a.M[t] = sm;
+        a.M[tm] = sm;
+    }
+    if (a.C) {
+        a.C[t] = sc;
+        a.C[tm] = sc;
+    }
+}
+
+hipError_t launch_upper_gather(const UpperGatherArgs &a, hipStream_t st)
+{
+    if (a.n_up == 0) return hipSuccess;
+    upper_gather_kernel<<<unsigned((a.n_up + 255) / 256), 256, 0, st>>>(a);
+    return hipGetLastError();
 }
 
 hipError_t launch_slot_gather(const SlotGatherArgs &a, hipStream_t st)

@@ -62,10 +62,18 @@ struct SlotGatherArgs {
     const int32_t *items;  // indices into src
     const double *src;
     double *out;           // [n_slots]
-    const double *src2;    // optional second source, gathered with the same entries
-    double *out2;
-    int sym_np;            // > 0: items (e * np + a) * np + b address a symmetric local matrix
-                           // stored once per pair, [n_elem / 64][ns][64] (isoparametric path)
+};
+
+// Symmetric local matrices: one thread per upper CSR slot sums its entries and writes
+// the slot and its mirror (M and C in one pass; either may be null).
+struct UpperGatherArgs {
+    int64_t n_up;
+    const int64_t *ptr;      // [n_up + 1]
+    const int32_t *items;    // indices into srcM / srcC
+    const int32_t *pos;      // [n_up] CSR position of the upper slot
+    const int32_t *mirror;   // [n_up] CSR position of its mirror
+    const double *srcM, *srcC;
+    double *M, *C;
 };
 
 // Elements per block of the isoparametric kernel and of its pair-major layout.
@@ -75,6 +83,7 @@ hipError_t launch_expand(const ExpandArgs &a, hipStream_t st);
 hipError_t launch_coeff_product(const CoeffProductArgs &a, int D, int P, int nq, hipStream_t st);
 hipError_t launch_cond_tensor(const CondTensorArgs &a, int D, int P, int nq, hipStream_t st);
 hipError_t launch_slot_gather(const SlotGatherArgs &a, hipStream_t st);
+hipError_t launch_upper_gather(const UpperGatherArgs &a, hipStream_t st);
 hipError_t launch_load(const LoadArgs &a, int D, int P, int nq, hipStream_t st);
 hipError_t launch_iso(const IsoArgs &a, int D, int P, int nqm, int nqc, hipStream_t st);
 

@@ -199,6 +199,13 @@ struct qxa_plan_s {
     double *d_T = nullptr;
     int64_t *d_ns_ptr = nullptr;  // [nnz + 1]
     int32_t *d_ns_items = nullptr;
+    // isoparametric path (built on first use): per upper CSR slot, its position, its
+    // mirror's position and its element-pair entries (index into the pair-major local
+    // matrices) in ascending element order
+    int64_t n_up = 0;
+    int64_t *d_nu_ptr = nullptr;  // [n_up + 1]
+    int32_t *d_nu_items = nullptr;
+    int32_t *d_nu_pos = nullptr, *d_nu_mirror = nullptr;
     // load vector (built on first use): element vectors [np][n_elem] and, per node,
     // its element entries in ascending element order
     double *d_Fe = nullptr;
