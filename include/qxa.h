@@ -80,6 +80,14 @@ typedef struct {
     const double *weights;
 } qxa_quad;
 
+/* A built-in symmetric rule on the reference simplex exact for polynomials of degree
+ * `degree` (the lowest built-in degree >= the one asked for: 1, 2, 4 or 6; dim 2 or 3).
+ * Points and weights were solved from the orbit moment equations in high precision;
+ * they satisfy every moment of that degree to rounding. The tables are library-owned
+ * with static lifetime (host memory). Errors: QXA_E_INVALID (null out, dim not 2 or 3),
+ * QXA_E_UNSUPPORTED (degree above 6). Host only; needs no GPU. */
+qxa_status qxa_quad_builtin(int dim, int degree, qxa_quad *out);
+
 /* kind = QXA_COEFF_CONST: s = value.
  * kind = QXA_COEFF_NODAL: field = device array [n_nodes]; s = law(u_h(x_q)).
  * kind = QXA_COEFF_QPOINT: field = device array [n_q][n_elem]; s = law(field[q][e]).

@@ -89,6 +89,7 @@ def lib():
         L.qxa_plan_destroy.argtypes = [vp]
         L.qxa_plan_get_info.argtypes = [vp, C.POINTER(_PlanInfo)]
         L.qxa_plan_copy_pattern.argtypes = [vp, vp, vp, vp]
+        L.qxa_quad_builtin.argtypes = [C.c_int, C.c_int, C.POINTER(_Quad)]
         L.qxa_pattern_host.argtypes = [ci, ci, i64, i64, vp, vp, vp, C.POINTER(i64)]
         L.qxa_plan_check_host.argtypes = [ci, ci, i64, vp, i64, vp, C.POINTER(i64), C.POINTER(i64)]
         L.qxa_assemble.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), ci, vp, vp, vp]
@@ -241,6 +242,16 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def quad_builtin(dim: int, degree: int):
+    """The library's built-in symmetric rule of at least this degree: (points [n_q, dim],
+    weights [n_q]) as new numpy arrays (qxa_quad_builtin)."""
+    q = _Quad()
+    check(lib().qxa_quad_builtin(int(dim), int(degree), C.byref(q)))
+    pts = np.ctypeslib.as_array(C.cast(q.points, C.POINTER(C.c_double)), shape=(q.n_q * q.dim,)).copy()
+    wts = np.ctypeslib.as_array(C.cast(q.weights, C.POINTER(C.c_double)), shape=(q.n_q,)).copy()
+    return pts.reshape(q.n_q, q.dim), wts
 
 
 def pattern_host(dim, order, n_nodes, conn):

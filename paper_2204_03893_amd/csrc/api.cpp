@@ -540,6 +540,20 @@ qxa_status qxa_plan_check_host(int dim, int order, int64_t n_nodes, const double
     return QXA_OK;
 }
 
+qxa_status qxa_quad_builtin(int dim, int degree, qxa_quad *out)
+{
+    if (!out) return fail(QXA_E_INVALID, "null output");
+    if (dim != 2 && dim != 3) return fail(QXA_E_INVALID, "dim must be 2 or 3");
+    const BuiltinRule *best = nullptr;
+    for (int k = 0; k < k_n_builtin_rules; ++k) {
+        const BuiltinRule &r = k_builtin_rules[k];
+        if (r.dim == dim && r.degree >= degree && (!best || r.degree < best->degree)) best = &r;
+    }
+    if (!best) return fail(QXA_E_UNSUPPORTED, "no built-in rule of that degree (at most 6)");
+    *out = qxa_quad{dim, best->n_q, best->points, best->weights};
+    return QXA_OK;
+}
+
 qxa_status qxa_plan_copy_pattern(qxa_plan p, int64_t *row_ptr, int32_t *col_idx, void *stream)
 {
     if (!p) return fail(QXA_E_INVALID, "null plan");

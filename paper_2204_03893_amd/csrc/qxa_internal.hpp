@@ -38,6 +38,14 @@ qxa_status hip_fail(hipError_t e, const char *what);
     } while (0)
 
 // Reference element tables of Algorithm 2 (Phi, J_q, Q) ---------------------
+// Built-in symmetric quadrature rules (rules_builtin.cpp, generated).
+struct BuiltinRule {
+    int dim, degree, n_q;
+    const double *points, *weights;
+};
+extern const BuiltinRule k_builtin_rules[];
+extern const int k_n_builtin_rules;
+
 struct RefTables {
     int dim = 0, order = 0, np = 0, ns = 0, ng = 0;
     int nq_m = 0, nq_c = 0;

@@ -81,3 +81,33 @@ def test_tile_plan_selfcheck_relabelled_and_shuffled():
     X = np.empty_like(m["coords"])
     X[:, sigma] = m["coords"]
     qxa.plan_check_host(3, 2, X, conn)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("degree", [1, 2, 3, 4, 5, 6])
+def test_builtin_rules(dim, degree):
+    """qxa_quad_builtin: the same doubles as the input module's rules, and every monomial
+    moment of its degree on the reference simplex (int x^alpha = alpha! / (|alpha| + d)!)."""
+    import itertools
+    import math
+    from workloads import rule
+    from workloads.quadrature import rule_degree
+    P, W = qxa.quad_builtin(dim, degree)
+    Pr, Wr = rule(dim, degree)
+    assert np.array_equal(P, Pr) and np.array_equal(W, Wr)
+    deg = rule_degree(dim, degree)
+    for alpha in itertools.product(range(deg + 1), repeat=dim):
+        if sum(alpha) > deg:
+            continue
+        exact = math.prod(math.factorial(a) for a in alpha) / math.factorial(sum(alpha) + dim)
+        got = float(np.sum(W * np.prod(P ** np.array(alpha), axis=1)))
+        assert abs(got - exact) <= 1e-15
+
+
+def test_builtin_rule_errors():
+    with pytest.raises(qxa.QxaError) as ei:
+        qxa.quad_builtin(2, 7)
+    assert ei.value.code == -6
+    with pytest.raises(qxa.QxaError) as ei:
+        qxa.quad_builtin(4, 2)
+    assert ei.value.code == -1
