@@ -24,6 +24,8 @@
  * mesh into library-owned device memory. Output value arrays are caller-owned
  * device buffers. "device" pointers are HIP device pointers on the device the
  * mesh was created on; a stream argument is a hipStream_t (NULL = default).
+ * An array argument whose length is zero (no elements, no nodes, nnz = 0) may
+ * be NULL.
  */
 #ifndef QXA_H
 #define QXA_H

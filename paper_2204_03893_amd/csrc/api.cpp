@@ -76,7 +76,9 @@ static void plan_free(qxa_plan p, void *ptr)
     else hipFree(ptr);
 }
 
-static qxa_status to_coeff(const qxa_coeff *c, CoeffDev &out, const char *which)
+// n_nodes, n_elem: the field's length for the nodal and per-(q, e) kinds (a field of
+// zero length may be null).
+static qxa_status to_coeff(const qxa_coeff *c, CoeffDev &out, const char *which, int64_t n_nodes, int64_t n_elem)
 {
     if (!c) {
         out = CoeffDev{0, 0, 0.0, 0.0, 0.0, 0.0, nullptr};
@@ -84,7 +86,8 @@ static qxa_status to_coeff(const qxa_coeff *c, CoeffDev &out, const char *which)
     }
     if (c->kind < 0 || c->kind > 2) return fail(QXA_E_INVALID, std::string(which) + " coefficient: bad kind");
     if (c->law < 0 || c->law > 2) return fail(QXA_E_INVALID, std::string(which) + " coefficient: bad law");
-    if (c->kind != 0 && !c->field) return fail(QXA_E_INVALID, std::string(which) + " coefficient: null field");
+    if (c->kind != 0 && !c->field && (c->kind == 1 ? n_nodes : n_elem) > 0)
+        return fail(QXA_E_INVALID, std::string(which) + " coefficient: null field");
     if (c->kind == 0 && !std::isfinite(c->value))
         return fail(QXA_E_NONFINITE, std::string(which) + " coefficient: non-finite constant");
     if (c->tensor_q)
@@ -575,8 +578,9 @@ static qxa_status fill_inputs(qxa_plan p, const qxa_coeff *mass, const qxa_coeff
         return fail(QXA_E_UNSUPPORTED,
                     "split 16-bit forms run on the matrix cores with Q staged on chip (2D P2/P3, 3D P2, at most 16 "
                     "conductivity nodes); use QXA_FP32 as the reduced-precision form here");
-    qxa_status st = to_coeff(mass, in.cm, "mass");
-    if (!st) st = to_coeff(stiff, in.cc, "stiffness");
+    const int64_t nn = p->mesh->n_nodes, ne = p->mesh->n_elem;
+    qxa_status st = to_coeff(mass, in.cm, "mass", nn, ne);
+    if (!st) st = to_coeff(stiff, in.cc, "stiffness", nn, ne);
     if (!st) st = to_tensor(mass, stiff, p->ref.dim, in.aniso, in.K);
     if (st) return st;
     const qxa_mesh m = p->mesh;
@@ -692,13 +696,15 @@ qxa_status qxa_element_matrices(qxa_plan p, const qxa_coeff *mass, const qxa_coe
 
 qxa_status qxa_coeff_product(qxa_plan p, int rule, const qxa_coeff *c, const double *v, double *S, void *stream)
 {
-    if (!p || !c || !v || !S) return fail(QXA_E_INVALID, "null argument");
+    if (!p || !c) return fail(QXA_E_INVALID, "null argument");
+    // arrays of zero length may be null
+    if ((!v && p->mesh->n_nodes) || (!S && p->mesh->n_elem)) return fail(QXA_E_INVALID, "null argument");
     if (rule != 0 && rule != 1) return fail(QXA_E_INVALID, "rule: 0 (mass rule) or 1 (stiffness rule)");
     if (!p->d_flags) return fail(QXA_E_INVALID, "plan is owned by a server");
     if (c->kind != QXA_COEFF_NODAL) return fail(QXA_E_INVALID, "the first factor is a nodal field through a law");
     if (c->tensor) return fail(QXA_E_INVALID, "the first factor has no tensor");
     CoeffProductArgs a{};
-    qxa_status st = to_coeff(c, a.c, "first factor");
+    qxa_status st = to_coeff(c, a.c, "first factor", p->mesh->n_nodes, p->mesh->n_elem);
     if (st) return st;
     if (p->mesh->n_elem == 0) return QXA_OK;
     QXA_HIP(hipSetDevice(p->mesh->device));
@@ -873,7 +879,7 @@ qxa_status qxa_assemble_iso(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *
 
 qxa_status qxa_load_vector(qxa_plan p, const qxa_coeff *f, double *F, void *stream)
 {
-    if (!p || !f || !F) return fail(QXA_E_INVALID, "null argument");
+    if (!p || !f || (!F && p->mesh->n_nodes)) return fail(QXA_E_INVALID, "null argument");
     if (!p->d_flags) return fail(QXA_E_INVALID, "plan is owned by a server");
     LoadArgs a{};
     const void *qm, *qc;
@@ -883,7 +889,7 @@ qxa_status qxa_load_vector(qxa_plan p, const qxa_coeff *f, double *F, void *stre
     QXA_HIP(hipSetDevice(m->device));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (m->n_elem == 0) {
-        QXA_HIP(hipMemsetAsync(F, 0, sizeof(double) * m->n_nodes, s));
+        if (m->n_nodes) QXA_HIP(hipMemsetAsync(F, 0, sizeof(double) * m->n_nodes, s));
         return QXA_OK;
     }
     if (!p->d_nf_ptr) {
@@ -904,11 +910,12 @@ qxa_status qxa_load_vector(qxa_plan p, const qxa_coeff *f, double *F, void *stre
 
 qxa_status qxa_cond_tensor_product(qxa_plan p, const qxa_coeff *c, const double *v, double *T_vals, void *stream)
 {
-    if (!p || !c || !v || !T_vals) return fail(QXA_E_INVALID, "null argument");
+    if (!p || !c) return fail(QXA_E_INVALID, "null argument");
+    if ((!v && p->mesh->n_nodes) || (!T_vals && p->nnz)) return fail(QXA_E_INVALID, "null argument");
     if (!p->d_flags) return fail(QXA_E_INVALID, "plan is owned by a server");
     if (c->kind != QXA_COEFF_NODAL) return fail(QXA_E_INVALID, "c' is a nodal field through a law");
     CondTensorArgs a{};
-    qxa_status st = to_coeff(c, a.c, "c'");
+    qxa_status st = to_coeff(c, a.c, "c'", p->mesh->n_nodes, p->mesh->n_elem);
     if (!st) st = to_tensor(nullptr, c, p->ref.dim, a.aniso, a.K);
     if (st) return st;
     if (p->mesh->n_elem == 0) return QXA_OK;
