@@ -126,81 +126,131 @@ hipError_t launch_coeff_product(const CoeffProductArgs &a, int D, int P, int nq,
 // Local matrices of the conductivity tensor contracted with v in its second mode
 // (Section 5): T_e[a][b] = sum_q w_q c'(u_h) |det B_e| (J_q[a] A_e J_q^T v_e) phi_b(xhat_q),
 // i.e. the columns of Q = [phi_q (x) J_q] weighted by X[(q, c), e] = lambda_q (A_e J_q^T v_e)_c.
-// One thread per (element, row a): blockIdx.y = a, elements along x (coalesced stores).
+// A block takes 64 elements, one per lane, through LDS: the nodal values of u and v (one
+// wave per local node) and the geometry; X (one wave per quadrature node, the reference
+// tables as wave-uniform scalars); then, per chunk of kCtRows rows, row a of every element
+// (one wave per row: r_a(q) = J_q[a] . X[q, :], then T[a][b] = sum_q phi_b(q) r_a(q)) into
+// an LDS stage that the block copies out as contiguous row segments of the element-major
+// output [n_elem][n_p][n_p].
+constexpr int kCtElems = 64, kCtRows = 4;
+
+template <int D, int P, int NQ>
+constexpr size_t ct_lds_doubles()
+{
+    using S = Shape<D, P>;
+    return size_t(kCtElems) * (2 * S::NP + S::NG + 1 + NQ * D) + size_t(kCtElems) * (kCtRows * S::NP + 1);
+}
+
 template <int D, int P, int NQ>
 __global__ __launch_bounds__(256) void cond_tensor_rows_kernel(CondTensorArgs a)
 {
     using S = Shape<D, P>;
-    constexpr int NP = S::NP;
-    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int ra = blockIdx.y;
-    if (e >= a.n_elem) return;
-    double x[D + 1][D];
-#pragma unroll
-    for (int k = 0; k <= D; ++k) {
-        const int32_t node = a.conn[k * a.n_elem + e];
-#pragma unroll
-        for (int c = 0; c < D; ++c) x[k][c] = a.coords[c * a.n_nodes + node];
+    constexpr int NP = S::NP, NG = S::NG, E = kCtElems, STR = kCtRows * NP + 1;
+    extern __shared__ double ct_lds[];
+    double *sU = ct_lds;          // [NP][E] u at the element's nodes
+    double *sV = sU + NP * E;     // [NP][E] v at the element's nodes
+    double *sA = sV + NP * E;     // [NG][E] A_e
+    double *sB = sA + NG * E;     // [E] |det B_e|
+    double *sX = sB + E;          // [NQ * D][E] X
+    double *sT = sX + NQ * D * E; // [E][STR] rows of the current chunk
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const int nw = int(blockDim.x >> 6);
+    const int64_t ne = a.n_elem, e0 = int64_t(blockIdx.x) * E, e = e0 + lane;
+    const bool live = e < ne;
+    for (int i = wave; i < NP; i += nw) {
+        const int32_t node = live ? a.conn[i * ne + e] : 0;
+        sU[i * E + lane] = live ? a.c.field[node] : 0.0;
+        sV[i * E + lane] = live ? a.v[node] : 0.0;
     }
-    double babs, Au[S::NG];
-    geometry_from<D>(x, babs, Au, a.aniso, a.K);
-    double A[D][D];
-    {
-        int g = 0;
+    if (wave == 0) {
+        double x[D + 1][D];
 #pragma unroll
-        for (int r = 0; r < D; ++r)
+        for (int k = 0; k <= D; ++k) {
+            const int32_t node = live ? a.conn[k * ne + e] : 0;
 #pragma unroll
-            for (int c = r; c < D; ++c, ++g) A[r][c] = A[c][r] = Au[g];
+            for (int c = 0; c < D; ++c) x[k][c] = live ? a.coords[c * a.n_nodes + node] : (c + 1 == k ? 1.0 : 0.0);
+        }
+        double babs, Au[NG];
+        geometry_from<D>(x, babs, Au, a.aniso, a.K);
+#pragma unroll
+        for (int g = 0; g < NG; ++g) sA[g * E + lane] = Au[g];
+        sB[lane] = babs;
     }
-    double u[NP], v[NP];
-#pragma unroll
-    for (int i = 0; i < NP; ++i) {
-        const int32_t node = a.conn[i * a.n_elem + e];
-        u[i] = a.c.field[node];
-        v[i] = a.v[node];
-    }
-    double row[NP];
-#pragma unroll
-    for (int b = 0; b < NP; ++b) row[b] = 0.0;
+    __syncthreads();
     bool ok = true;
-    for (int q = 0; q < NQ; ++q) {
-        const auto J = uniform_table(a.dphi) + size_t(q) * NP * D;
+    for (int q = wave; q < NQ; q += nw) {
+        const auto J = uniform_table(a.dphi + size_t(q) * NP * D);
+        const auto phi = uniform_table(a.phi);
         double uh = 0.0, gv[D];
 #pragma unroll
         for (int c = 0; c < D; ++c) gv[c] = 0.0;
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
-            uh = fma(uniform_table(a.phi)[i * NQ + q], u[i], uh);
+            const double vi = sV[i * E + lane];
+            uh = fma(phi[i * NQ + q], sU[i * E + lane], uh);
 #pragma unroll
-            for (int c = 0; c < D; ++c) gv[c] = fma(J[i * D + c], v[i], gv[c]);  // J_q^T v_e
+            for (int c = 0; c < D; ++c) gv[c] = fma(J[i * D + c], vi, gv[c]);  // J_q^T v_e
         }
-        const double lam = uniform_table(a.w)[q] * apply_law(a.c, uh) * babs;
-        ok &= isfinite(lam);
-        double r = 0.0;  // J_q[a] A_e J_q^T v_e
+        const double lam = uniform_table(a.w)[q] * apply_law(a.c, uh) * sB[lane];
+        if (live) ok &= isfinite(lam);
+        double A[D][D];
+        {
+            int g = 0;
+#pragma unroll
+            for (int r = 0; r < D; ++r)
+#pragma unroll
+                for (int c = r; c < D; ++c, ++g) A[r][c] = A[c][r] = sA[g * E + lane];
+        }
 #pragma unroll
         for (int c = 0; c < D; ++c) {
             double t = 0.0;
 #pragma unroll
             for (int k = 0; k < D; ++k) t = fma(A[c][k], gv[k], t);
-            r = fma(J[ra * D + c], t, r);
+            sX[(q * D + c) * E + lane] = lam * t;
         }
-        const double f = lam * r;
-#pragma unroll
-        for (int b = 0; b < NP; ++b) row[b] = fma(f, uniform_table(a.phi)[b * NQ + q], row[b]);
     }
-#pragma unroll
-    for (int b = 0; b < NP; ++b) a.T[(e * NP + ra) * NP + b] = row[b];
     if (!ok) atomicOr(a.flags, 1);
+    __syncthreads();
+    for (int a0 = 0; a0 < NP; a0 += kCtRows) {
+        const int rows = min(kCtRows, NP - a0);
+        for (int ar = wave; ar < rows; ar += nw) {
+            const int ra = a0 + ar;
+            double r[NQ];  // r_a(q) = J_q[a] . X[q, :]
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const auto J = uniform_table(a.dphi + size_t(q) * NP * D);
+                double t = 0.0;
+#pragma unroll
+                for (int c = 0; c < D; ++c) t = fma(J[ra * D + c], sX[(q * D + c) * E + lane], t);
+                r[q] = t;
+            }
+#pragma unroll 1
+            for (int b = 0; b < NP; ++b) {
+                double t = 0.0;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) t = fma(uniform_table(a.phi)[b * NQ + q], r[q], t);
+                sT[lane * STR + ar * NP + b] = t;
+            }
+        }
+        __syncthreads();
+        const int seg = rows * NP;  // element el's rows a0 .. a0 + rows - 1: contiguous in T
+        for (int idx = threadIdx.x; idx < E * seg; idx += blockDim.x) {
+            const int el = idx / seg, off = idx - el * seg;
+            if (e0 + el < ne) a.T[(e0 + el) * (NP * NP) + a0 * NP + off] = sT[el * STR + off];
+        }
+        __syncthreads();
+    }
 }
 
 hipError_t launch_cond_tensor(const CondTensorArgs &a, int D, int P, int nq, hipStream_t st)
 {
     if (a.n_elem == 0) return hipSuccess;
-#define X(d, p, m, c)                                                                          \
-    if (D == d && P == p && nq == c) {                                                         \
-        const dim3 grid(unsigned((a.n_elem + 255) / 256), unsigned(Shape<d, p>::NP));         \
-        cond_tensor_rows_kernel<d, p, c><<<grid, 256, 0, st>>>(a);                            \
-        return hipGetLastError();                                                              \
+    const unsigned blocks = unsigned((a.n_elem + kCtElems - 1) / kCtElems);
+#define X(d, p, m, c)                                                                                   \
+    if (D == d && P == p && nq == c) {                                                                  \
+        cond_tensor_rows_kernel<d, p, c><<<blocks, 256, ct_lds_doubles<d, p, c>() * sizeof(double), st>>>(a); \
+        return hipGetLastError();                                                                       \
     }
     QXA_FORM_CASES(X)
 #undef X
