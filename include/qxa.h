@@ -26,6 +26,12 @@
  * mesh was created on; a stream argument is a hipStream_t (NULL = default).
  * An array argument whose length is zero (no elements, no nodes, nnz = 0) may
  * be NULL.
+ *
+ * Concurrency: a plan owns the scratch its launches use (shared-slot partial
+ * sums, the local matrices of the two-pass entry points, the device flag read
+ * by qxa_sync), so work queued with one plan must be ordered: one stream, or
+ * streams synchronised by the caller. Calls with different plans may overlap.
+ * The server (qxa_server_*) keeps its own plans and is thread-safe.
  */
 #ifndef QXA_H
 #define QXA_H
