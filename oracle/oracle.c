@@ -15,6 +15,12 @@
  * quadrature nodes, then the addition of each local matrix into the global
  * matrix at the rows/columns of its node set N_e.
  *
+ * Beyond these, with the same loops: the tensors of the Newton Jacobian of
+ * Section 5 contracted with a vector (the full local n_p^3 tensor formed, then
+ * contracted), the volume load vector of Section 2, an anisotropic conductivity
+ * (a constant tensor, or one per quadrature node, Section 7) and isoparametric
+ * elements (B, |det B| and A per quadrature node from every node, Section 7).
+ *
  * Deliberately different from any fast implementation:
  *   - the reference Lagrange basis is obtained by solving the monomial
  *     Vandermonde system on the reference nodes (not closed formulas);
