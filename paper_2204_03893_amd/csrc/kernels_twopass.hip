@@ -514,7 +514,19 @@ __global__ __launch_bounds__(256) void slot_gather_kernel(SlotGatherArgs a)
     if (t >= a.n_slots) return;
     const int64_t lo = a.ptr[t], hi = a.ptr[t + 1];
     double s = 0.0;
-    for (int64_t k = lo; k < hi; ++k) s += a.src[a.items[k]];
+    // four entries per step: their index and value loads are issued before the adds, which
+    // then run in the stored order (the same sum as one entry at a time)
+    for (int64_t k = lo; k < hi; k += 4) {
+        int32_t i[4];
+        double v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) i[j] = a.items[min(k + j, hi - 1)];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = a.src[i[j]];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (k + j < hi) s += v[j];
+    }
     a.out[t] = s;
 }
 
