@@ -75,6 +75,14 @@ static void plan_free(qxa_plan p, void *ptr)
     if (p->arena) p->arena->release(ptr);
     else hipFree(ptr);
 }
+// Frees the buffers a lazily built map consists of and clears their pointers, so that
+// a build that failed part-way is redone on the next call instead of being used.
+template <class... T>
+static void plan_drop(qxa_plan p, T **...ptrs)
+{
+    (plan_free(p, *ptrs), ...);
+    ((*ptrs = nullptr), ...);
+}
 
 // n_nodes, n_elem: the field's length for the nodal and per-(q, e) kinds (a field of
 // zero length may be null).
@@ -756,6 +764,7 @@ static qxa_status build_slot_entries(qxa_plan p)
             for (int b = 0; b < np; ++b) items[size_t(fill[slot(e, a, b)]++)] = int32_t((e * np + a) * np + b);
     st = plan_upload_buf(p, &p->d_ns_ptr, ptr.data(), ptr.size());
     if (!st) st = plan_upload_buf(p, &p->d_ns_items, items.data(), items.size());
+    if (st) plan_drop(p, &p->d_ns_ptr, &p->d_ns_items);
     return st;
 }
 
@@ -797,7 +806,8 @@ static qxa_status build_upper_entries(qxa_plan p)
     if (!st) st = plan_upload_buf(p, &p->d_nu_items, items.data(), items.size());
     if (!st) st = plan_upload_buf(p, &p->d_nu_pos, pos.data(), pos.size());
     if (!st) st = plan_upload_buf(p, &p->d_nu_mirror, mir.data(), mir.size());
-    if (!st) p->n_up = n_up;
+    if (st) plan_drop(p, &p->d_nu_ptr, &p->d_nu_items, &p->d_nu_pos, &p->d_nu_mirror);
+    else p->n_up = n_up;
     return st;
 }
 
@@ -820,6 +830,7 @@ static qxa_status build_node_entries(qxa_plan p)
     qxa_status st = plan_upload_buf(p, &p->d_nf_ptr, ptr.data(), ptr.size());
     if (!st) st = plan_upload_buf(p, &p->d_nf_items, items.data(), items.size());
     if (!st) st = plan_alloc(p, &p->d_Fe, size_t(np) * ne);
+    if (st) plan_drop(p, &p->d_nf_ptr, &p->d_nf_items, &p->d_Fe);
     return st;
 }
 

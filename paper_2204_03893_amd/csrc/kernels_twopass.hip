@@ -530,6 +530,7 @@ __global__ __launch_bounds__(256) void slot_gather_kernel(SlotGatherArgs a)
     a.out[t] = s;
 }
 
+template <bool HM, bool HC>
 __global__ __launch_bounds__(256) void upper_gather_kernel(UpperGatherArgs a)
 {
     const int64_t u = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
@@ -537,16 +538,28 @@ __global__ __launch_bounds__(256) void upper_gather_kernel(UpperGatherArgs a)
     const int64_t lo = a.ptr[u], hi = a.ptr[u + 1];
     const int32_t t = a.pos[u], tm = a.mirror[u];
     double sm = 0.0, sc = 0.0;
-    for (int64_t k = lo; k < hi; ++k) {
-        const int32_t i = a.items[k];
-        if (a.srcM) sm += a.srcM[i];
-        if (a.srcC) sc += a.srcC[i];
+    for (int64_t k = lo; k < hi; k += 4) {  // four entries per step, summed in the stored order
+        int32_t i[4];
+        double vm[4], vc[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) i[j] = a.items[min(k + j, hi - 1)];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if constexpr (HM) vm[j] = a.srcM[i[j]];
+            if constexpr (HC) vc[j] = a.srcC[i[j]];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (k + j < hi) {
+                if constexpr (HM) sm += vm[j];
+                if constexpr (HC) sc += vc[j];
+            }
     }
-    if (a.M) {
+    if constexpr (HM) {
         a.M[t] = sm;
         a.M[tm] = sm;
     }
-    if (a.C) {
+    if constexpr (HC) {
         a.C[t] = sc;
         a.C[tm] = sc;
     }
@@ -554,8 +567,11 @@ __global__ __launch_bounds__(256) void upper_gather_kernel(UpperGatherArgs a)
 
 hipError_t launch_upper_gather(const UpperGatherArgs &a, hipStream_t st)
 {
-    if (a.n_up == 0) return hipSuccess;
-    upper_gather_kernel<<<unsigned((a.n_up + 255) / 256), 256, 0, st>>>(a);
+    if (a.n_up == 0 || (!a.M && !a.C)) return hipSuccess;
+    const unsigned blocks = unsigned((a.n_up + 255) / 256);
+    if (a.M && a.C) upper_gather_kernel<true, true><<<blocks, 256, 0, st>>>(a);
+    else if (a.M) upper_gather_kernel<true, false><<<blocks, 256, 0, st>>>(a);
+    else upper_gather_kernel<false, true><<<blocks, 256, 0, st>>>(a);
     return hipGetLastError();
 }
 
