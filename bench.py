@@ -127,7 +127,7 @@ def serving(args):
     pool = serving_pool(args.pool, args.max_elements)
     gen_s = time.perf_counter() - t0
     dev = torch.device("cuda", 0)
-    srv = qxa.Server(hbm_budget=32 << 30, max_inflight=64, n_streams=4, batch_tile_limit=512)
+    srv = qxa.Server(hbm_budget=int(args.budget_gib) << 30, max_inflight=64, n_streams=4, batch_tile_limit=512)
     for p in pool:
         m = p["mesh"]
         p["obj"] = qxa.Mesh(p["dim"], p["order"], m["coords"], m["conn"])
@@ -199,7 +199,8 @@ def serving(args):
            "unit": "entries/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
            "dtype": "f64" if args.precision == "fp64" else args.precision, "vs_baseline": None,
            "config": {"workload": "serving mix", "pool_meshes": len(pool), "elements_min": min(sizes),
-                      "elements_max": max(sizes), "requests_per_load": args.requests, "precision": args.precision},
+                      "elements_max": max(sizes), "requests_per_load": args.requests, "precision": args.precision,
+                      "budget_gib": args.budget_gib},
            "saturation": sat, "loads": loads, "warmup_plan_builds_s": warm_s, "pool_generation_s": gen_s,
            "server": st}
     print(json.dumps(out))
@@ -415,9 +416,10 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) to calibrate HBM byte counters")
     ap.add_argument("--mode", choices=("assemble", "serving", "reassembly", "tangent"), default="assemble")
-    ap.add_argument("--requests", type=int, default=1000, help="serving: requests per offered load")
+    ap.add_argument("--requests", type=int, default=10000, help="serving: requests per offered load")
     ap.add_argument("--pool", type=int, default=48, help="serving: resident meshes")
-    ap.add_argument("--max-elements", type=float, default=3e5, help="serving: largest mesh (elements)")
+    ap.add_argument("--max-elements", type=float, default=1e6, help="serving: largest mesh (elements)")
+    ap.add_argument("--budget-gib", type=int, default=160, help="serving: device memory budget of the server (GiB)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is a design "
