@@ -90,8 +90,9 @@ def test_iso_affine_mesh_matches_the_fused_assembly():
     assert row_scaled_error(Mi.cpu().numpy(), Mf.cpu().numpy(), rp) <= 1e-12
     assert row_scaled_error(Ci.cpu().numpy(), Cf.cpu().numpy(), rp) <= 1e-12
     Mo, _ = qxa.assemble_iso(plan, law_m, law_c, uf, uf, want_c=False)   # one output only
+    _, Co = qxa.assemble_iso(plan, law_m, law_c, uf, uf, want_m=False)
     qxa.sync(plan)
-    assert torch.equal(Mo, Mi)
+    assert torch.equal(Mo, Mi) and torch.equal(Co, Ci)
 
 
 def test_iso_nonfinite_coefficient_is_reported():
