@@ -405,6 +405,59 @@ def tangent(args):
     print(json.dumps(out))
 
 
+def paper_sweep(args):
+    """Paper-shaped stand-in for Experiment 1 (Section 6.1): the unit square, P1 and P2
+    triangles, constant coefficients, the fewest-point rules exact for them (P1: mass 3
+    points, conductivity 1; P2: mass 6 points, conductivity 3), mesh sizes close to the
+    paper's six meshes. Times the mass matrix alone, the conductivity matrix alone and both
+    (formation + scatter into CSR, plan built beforehand). Context for the paper's tables,
+    not a target. Prints one JSON line."""
+    import torch
+    import paper_2204_03893_amd as qxa
+    from workloads import rule, structured_mesh
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream()
+    rules = {1: (rule(2, 2), rule(2, 1)), 2: (rule(2, 4), rule(2, 2))}
+    rows = []
+    for order in (1, 2):
+        for N in (23, 46, 92, 183, 368, 736):
+            mesh = structured_mesh(2, order, N, 0.0)
+            m = qxa.Mesh(2, order, mesh["coords"], mesh["conn"])
+            t0 = time.perf_counter()
+            plan = qxa.Plan(m, *rules[order])
+            build_s = time.perf_counter() - t0
+            M = torch.empty(plan.nnz, dtype=torch.float64, device=dev)
+            Cv = torch.empty_like(M)
+            res = {"order": order, "N": N, "n_elem": plan.n_elem, "n_nodes": plan.n_nodes, "nnz": plan.nnz,
+                   "plan_build_s": build_s}
+            for name, wm, wc in (("mass_ms", True, False), ("cond_ms", False, True), ("both_ms", True, True)):
+                def once():
+                    qxa.assemble(plan, ("const", 1.0), ("const", 1.0), M=M, Cv=Cv, stream=stream,
+                                 want_m=wm, want_c=wc)
+                for _ in range(5):
+                    once()
+                torch.cuda.synchronize()
+                ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                ev0.record(stream)
+                for _ in range(args.steps):
+                    once()
+                ev1.record(stream)
+                torch.cuda.synchronize()
+                res[name] = ev0.elapsed_time(ev1) / args.steps
+            qxa.sync(plan, stream)
+            res["entries_per_s_both"] = 2 * plan.n_elem * plan.n_p ** 2 / (res["both_ms"] * 1e-3)
+            rows.append(res)
+            print(json.dumps(res), file=sys.stderr, flush=True)
+            del plan, m
+    big = [r for r in rows if r["order"] == 2 and r["N"] == 736][0]
+    out = {"metric": "element-matrix entries assembled/sec (paper-shaped sweep, context)",
+           "value": big["entries_per_s_both"], "unit": "entries/s", "n_gpus": 1, "steps": args.steps,
+           "higher_is_better": True, "dtype": "f64", "data": "synthetic", "vs_baseline": None,
+           "config": {"workload": "unit square, 2D P1/P2, constant coefficients, N = 23..736"},
+           "p2_736_mass_matrix_ms": big["mass_ms"], "rows": rows}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -415,7 +468,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) to calibrate HBM byte counters")
-    ap.add_argument("--mode", choices=("assemble", "serving", "reassembly", "tangent"), default="assemble")
+    ap.add_argument("--mode", choices=("assemble", "serving", "reassembly", "tangent", "paper"), default="assemble")
     ap.add_argument("--requests", type=int, default=10000, help="serving: requests per offered load")
     ap.add_argument("--pool", type=int, default=48, help="serving: resident meshes")
     ap.add_argument("--max-elements", type=float, default=1e6, help="serving: largest mesh (elements)")
@@ -447,6 +500,9 @@ def main():
         return
     if args.mode == "tangent":
         tangent(args)
+        return
+    if args.mode == "paper":
+        paper_sweep(args)
         return
 
     import paper_2204_03893_amd as qxa
