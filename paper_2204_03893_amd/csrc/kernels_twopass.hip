@@ -1,6 +1,11 @@
-// Formation kernel (Algorithm 2 up to the element matrices) writing the symmetric element
-// matrices V_m, V_c to a buffer (the formation-only entry point), and the
-// expansion of the symmetric pairs to full n_p x n_p element matrices.
+// Kernels that write local values to HBM and then gather them:
+//  - formation (Algorithm 2 up to the element matrices) of the symmetric V_m, V_c for
+//    the formation-only entry point, and their expansion to full n_p x n_p matrices;
+//  - the per-node coefficient of the mass tensor contracted with a vector and the local
+//    matrices of the conductivity tensor contracted with a vector (Section 5);
+//  - element load vectors (Section 2);
+//  - isoparametric local matrices with a per-node geometry and tensor (Section 7);
+//  - the deterministic gathers into CSR slots, nodes, or upper slots and their mirrors.
 #include "kernels_twopass.hpp"
 #include "kernels_common.hpp"
 
