@@ -111,3 +111,11 @@ def test_builtin_rule_errors():
     with pytest.raises(qxa.QxaError) as ei:
         qxa.quad_builtin(4, 2)
     assert ei.value.code == -1
+
+
+def test_builtin_rule_tables_are_generated():
+    """csrc/rules_builtin.cpp is exactly what paper_2204_03893_amd/gen_rules.py writes."""
+    from paper_2204_03893_amd import gen_rules
+    path = os.path.join(os.path.dirname(qxa.__file__), "csrc", "rules_builtin.cpp")
+    with open(path) as f:
+        assert f.read() == gen_rules.render()
