@@ -6,9 +6,10 @@ def row_scaled_error(got, ref, row_ptr):
     """max_ij |v_ij - o_ij| / max_k |o_ik| (entrywise relative error is undefined on cancelled zeros)."""
     if ref.size == 0:
         return 0.0
-    rmax = np.maximum.reduceat(np.abs(ref), row_ptr[:-1])
-    rmax = np.where(rmax == 0, 1.0, rmax)
     rows = np.repeat(np.arange(row_ptr.size - 1), np.diff(row_ptr))
+    rmax = np.zeros(row_ptr.size - 1)
+    np.maximum.at(rmax, rows, np.abs(ref))          # rows without entries keep 0
+    rmax = np.where(rmax == 0, 1.0, rmax)
     return float(np.max(np.abs(got - ref) / rmax[rows]))
 
 
