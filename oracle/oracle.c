@@ -969,12 +969,19 @@ static int element_matrices_iso(const refdata *R, const double *coords, int64_t 
         for (int q = 0; q < nq; ++q) {
             const double *ph = phi + (size_t)q * n, *Jq = dphi + (size_t)q * n * d;
             double B[MAXD * MAXD], Binv[MAXD * MAXD], A[MAXD * MAXD];
-            for (int r = 0; r < d; ++r)
+            /* B_q = sum_i (x_i - x_0) grad phi_i(xhat_q)^T: the gradients sum to zero, so
+             * subtracting vertex 0 changes nothing exactly and keeps the sum free of the
+             * cancellation of absolute coordinates on small elements (Section 3 builds B_e
+             * from the same differences a_k - a_0) */
+            for (int r = 0; r < d; ++r) {
+                const double x0 = coords[(size_t)r * n_nodes + conn[e]];
                 for (int c = 0; c < d; ++c) {
                     double s = 0.0;
-                    for (int i = 0; i < n; ++i) s += coords[(size_t)r * n_nodes + conn[(size_t)i * n_e + e]] * Jq[i * d + c];
+                    for (int i = 0; i < n; ++i)
+                        s += (coords[(size_t)r * n_nodes + conn[(size_t)i * n_e + e]] - x0) * Jq[i * d + c];
                     B[r * d + c] = s;
                 }
+            }
             for (int i = 0; i < d * d; ++i) Binv[i] = (i % (d + 1) == 0) ? 1.0 : 0.0;
             double adet = fabs(gauss_solve(d, B, d, Binv));
             if (!(adet > 0.0)) return -3;
