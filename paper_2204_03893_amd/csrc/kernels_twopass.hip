@@ -414,7 +414,9 @@ __global__ __launch_bounds__(256) void iso_rows_kernel(IsoArgs a)
         for (int i = 0; i < NP; ++i)
 #pragma unroll
             for (int r = 0; r < D; ++r) {
-                const double xr = sCrd[(i * D + r) * E + lane];
+                // x_i - x_0: the gradients sum to zero, so this is B_q exactly, without the
+                // cancellation of absolute coordinates on small elements
+                const double xr = sCrd[(i * D + r) * E + lane] - sCrd[r * E + lane];
 #pragma unroll
                 for (int c = 0; c < D; ++c) B[r][c] = fma(xr, J[i * D + c], B[r][c]);
             }
