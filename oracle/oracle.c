@@ -891,11 +891,15 @@ int oracle_cond_tensor_product(int dim, int P, int64_t n_nodes, const double *co
                     for (int k = 0; k < n; ++k) Ce[(i * n + j) * n + k] += lam * g * ph[k];
                 }
         }
+        /* contracted with v_j - v_0: the same in exact arithmetic (sum_j grad phi_j = 0, so
+         * sum_j C_ijk = 0) and without the cancellation of |v| against its small variation
+         * over an element */
         double *T = Tbuf + (size_t)e * n * n;
+        const double vbase = v[conn[e]];
         for (int i = 0; i < n; ++i)
             for (int k = 0; k < n; ++k) {
                 double s = 0.0;
-                for (int j = 0; j < n; ++j) s += Ce[(i * n + j) * n + k] * v[conn[(size_t)j * n_e + e]];
+                for (int j = 0; j < n; ++j) s += Ce[(i * n + j) * n + k] * (v[conn[(size_t)j * n_e + e]] - vbase);
                 T[i * n + k] = s;
             }
     }
