@@ -192,7 +192,7 @@ __global__ __launch_bounds__(256) void cond_tensor_rows_kernel(CondTensorArgs a)
         for (int c = 0; c < D; ++c) gv[c] = 0.0;
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
-            const double vi = sV[i * E + lane];
+            const double vi = sV[i * E + lane] - sV[lane];  // v_i - v_0 (the gradients sum to zero)
             uh = fma(phi[i * NQ + q], sU[i * E + lane], uh);
 #pragma unroll
             for (int c = 0; c < D; ++c) gv[c] = fma(J[i * D + c], vi, gv[c]);  // J_q^T v_e

@@ -35,17 +35,10 @@ def test_tensor_products_full_size_p3(setup):
     Tm, _ = qxa.mass_tensor_product(plan, law, uf, vf)
     qxa.sync(plan)
     rpo, _, Tco = oracle.cond_tensor_product(mesh, r, law, u, v)
-    # T_ik = int c'(u_h) phi_k grad phi_i . grad v_h: the gradient of a smooth v on cells of
-    # size h = 1/1024 cancels (sum_i grad phi_i = 0), so rounding scales with |C| |c'| |v|,
-    # not with the entries of T (a row where grad v_h ~ 0 has entries ~ h^2); the bound is
-    # taken relative to that scale, from the oracle's unit-coefficient conductivity matrix
-    _, _, _, C1 = oracle.assemble(mesh, r, r, ("const", 1.0), ("const", 1.0))
-    scale = np.abs(C1).max() * 1.5 * np.abs(u).max() * np.abs(v).max()
-    err = np.abs(Tc.cpu().numpy() - Tco).max()
-    print("conductivity tensor product: max abs error", err, "scale", scale, "max |T|", np.abs(Tco).max(),
-          flush=True)
-    assert err <= 1e-12 * scale
-    del Tco, C1
+    err = row_scaled_error(Tc.cpu().numpy(), Tco, rpo)
+    print("conductivity tensor product: row-scaled error", err, flush=True)
+    assert err <= 1e-12
+    del Tco
     _, _, Tmo = oracle.mass_tensor_product(mesh, r, law, u, v)
     assert row_scaled_error(Tm.cpu().numpy(), Tmo, rpo) <= 1e-12
 
