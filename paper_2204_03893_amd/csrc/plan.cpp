@@ -1,5 +1,5 @@
-// Host construction of the per-mesh assembly plan (the global assembly step of Algorithm 2:
-// "the set of indices of nonzero entries").
+// Host construction of the per-mesh assembly plan (the global assembly step of Algorithm 2,
+// where the sparsity pattern is fixed once per mesh).
 //   1. node -> element lists (counting sort; ascending element id per node);
 //   2. CSR pattern: row i holds every j that shares an element with i
 //      (Section 3, step 2: compact support), sorted, structural zeros kept;
