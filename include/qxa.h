@@ -389,8 +389,15 @@ qxa_status qxa_server_create(const qxa_server_opts *opts, qxa_server *out);
 qxa_status qxa_server_submit(qxa_server server, const qxa_job *job, uint64_t *ticket);
 /* Up to `max` completions in completion order; *n_done = how many. */
 qxa_status qxa_server_poll(qxa_server server, qxa_completion *done, int max, int *n_done);
-/* Copies a completed job's values into caller device buffers (either may be NULL). */
+/* Copies a completed job's values into caller device buffers (either may be NULL),
+ * asynchronously on `stream`; an event recorded there after the copies is kept with
+ * the ticket. */
 qxa_status qxa_server_copy_result(qxa_server server, uint64_t ticket, double *M_vals, double *C_vals, void *stream);
+/* Returns a polled job's buffers to the budget. It first waits for every copy that
+ * qxa_server_copy_result queued for this ticket, so the copied values are never
+ * those of a later job that reuses the buffer; no synchronisation of the copy stream
+ * is needed before it. The job's device pointers (qxa_completion.M, .C) are invalid
+ * afterwards. */
 qxa_status qxa_server_release(qxa_server server, uint64_t ticket);
 /* paused != 0: admit nothing (submissions still queue); 0: resume. */
 qxa_status qxa_server_pause(qxa_server server, int paused);

@@ -139,6 +139,38 @@ def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+def _n_local(dim, order):
+    n = 1
+    for k in range(1, dim + 1):
+        n = n * (order + k) // k
+    return n
+
+
+def _dev_arg(t, name, numel, device, dtype="float64"):
+    """Checks a tensor handed to the kernels as a raw device pointer: a contiguous torch
+    tensor of `dtype` on cuda:`device` with exactly `numel` elements (ValueError otherwise).
+    Nothing is launched before every argument of a call has passed."""
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch tensor on cuda:{device}, got {type(t).__name__}")
+    want = getattr(torch, dtype)
+    if t.dtype != want:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {want}")
+    if not t.is_cuda or t.device.index != device:
+        raise ValueError(f"{name}: on {t.device}, expected cuda:{device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: not contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name}: {t.numel()} elements, expected {numel}")
+    return t
+
+
+def _field_len(n_nodes, n_q, n_elem, qpoint):
+    return n_q * n_elem if qpoint else n_nodes
+
+
 class Mesh:
     """Library-owned copy of a simplex mesh (coords [dim, n_nodes], conn [n_p, n_elem])."""
 
@@ -158,6 +190,11 @@ class Mesh:
             mem = 0
             xp, cp = X.ctypes.data, Cn.ctypes.data
             keep = (X, Cn)
+        if X.ndim != 2 or X.shape[0] != self.dim or Cn.ndim != 2:
+            raise ValueError(f"coords must be [dim={self.dim}, n_nodes] and conn [n_p, n_elem]")
+        if Cn.shape[0] != _n_local(self.dim, self.order):
+            raise ValueError(f"conn has {Cn.shape[0]} rows; a P{self.order} simplex in {self.dim}D has "
+                             f"{_n_local(self.dim, self.order)} nodes")
         self.n_nodes = int(X.shape[1])
         self.n_elem = int(Cn.shape[1])
         self.n_p = int(Cn.shape[0])
@@ -276,11 +313,19 @@ def plan_check_host(dim, order, coords, conn):
     return nt.value, npart.value
 
 
-def make_coeff(law, field=None, qpoint=False, tensor=None, tensor_q=None):
+def make_coeff(law, field=None, qpoint=False, tensor=None, tensor_q=None, sizes=None, name="coefficient"):
     """Build the ABI coefficient struct; returns (struct, keepalive). tensor: upper triangle
     (row-major) of a constant symmetric conductivity tensor K, for conductivity coefficients;
     tensor_q: device float64 [n_q][d(d+1)/2][n_elem], a tensor per quadrature node
-    (isoparametric path only)."""
+    (isoparametric path only). sizes = (dim, n_nodes, n_q, n_elem, device) checks the
+    device arrays against the plan they are used with."""
+    if sizes is not None:
+        dim, n_nodes, n_q, n_elem, device = sizes
+        if law[0] != "const":
+            _dev_arg(field, f"{name} field", _field_len(n_nodes, n_q, n_elem, qpoint), device)
+        _dev_arg(tensor_q, f"{name} tensor_q", n_q * (dim * (dim + 1) // 2) * n_elem, device)
+        if tensor is not None and np.asarray(tensor).size != dim * (dim + 1) // 2:
+            raise ValueError(f"{name} tensor: expected the {dim * (dim + 1) // 2} upper-triangle entries")
     c = _Coeff()
     c.a[0] = c.a[1] = c.a[2] = 0.0
     kt = None
@@ -308,17 +353,26 @@ def _precision(p):
     return PRECISIONS[p] if isinstance(p, str) else int(p)
 
 
+def _sizes(plan, which):
+    """(dim, n_nodes, n_q, n_elem, device) of a plan for coefficients on its mass
+    ("mass") or stiffness ("stiff") rule."""
+    nq = plan.n_q_mass if which == "mass" else plan.n_q_stiff
+    return (plan.mesh.dim, plan.n_nodes, nq, plan.n_elem, plan.mesh.device)
+
+
 def assemble(plan: Plan, law_m, law_c, field_m=None, field_c=None, precision="fp64", M=None, Cv=None,
              stream=None, want_m=True, want_c=True, qpoint=False, tensor=None):
     """One assembly into CSR value arrays (device float64 tensors of length nnz)."""
     import torch
     dev = torch.device("cuda", plan.mesh.device)
+    _dev_arg(M, "M", plan.nnz, plan.mesh.device)
+    _dev_arg(Cv, "Cv", plan.nnz, plan.mesh.device)
+    cm, k1 = make_coeff(law_m, field_m, qpoint, sizes=_sizes(plan, "mass"), name="mass")
+    cc, k2 = make_coeff(law_c, field_c, qpoint, tensor, sizes=_sizes(plan, "stiff"), name="conductivity")
     if want_m and M is None:
         M = torch.empty(plan.nnz, dtype=torch.float64, device=dev)
     if want_c and Cv is None:
         Cv = torch.empty(plan.nnz, dtype=torch.float64, device=dev)
-    cm, k1 = make_coeff(law_m, field_m, qpoint)
-    cc, k2 = make_coeff(law_c, field_c, qpoint, tensor)
     check(lib().qxa_assemble(plan.handle, C.byref(cm), C.byref(cc), _precision(precision),
                              _ptr(M if want_m else None), _ptr(Cv if want_c else None), _stream_ptr(stream)))
     return M, Cv
@@ -330,9 +384,13 @@ def coeff_product(plan: Plan, law, u, v, rule="mass", S=None, stream=None):
     import torch
     which = {"mass": 0, "stiffness": 1}[rule]
     nq = plan.n_q_mass if which == 0 else plan.n_q_stiff
+    sz = _sizes(plan, "mass" if which == 0 else "stiff")
+    _dev_arg(u, "u", plan.n_nodes, plan.mesh.device)
+    _dev_arg(v, "v", plan.n_nodes, plan.mesh.device)
+    _dev_arg(S, "S", nq * plan.n_elem, plan.mesh.device)
     if S is None:
         S = torch.empty((nq, plan.n_elem), dtype=torch.float64, device=torch.device("cuda", plan.mesh.device))
-    c, keep = make_coeff(law, u)
+    c, keep = make_coeff(law, u, sizes=sz, name="law")
     check(lib().qxa_coeff_product(plan.handle, which, C.byref(c), _ptr(v), _ptr(S), _stream_ptr(stream)))
     return S
 
@@ -351,9 +409,12 @@ def cond_tensor_product(plan: Plan, law_dc, u, v, T=None, stream=None, tensor=No
     grad phi_j phi_k) contracted with v in its second mode, as values in the plan's CSR
     pattern (row i, column k; not symmetric)."""
     import torch
+    _dev_arg(u, "u", plan.n_nodes, plan.mesh.device)
+    _dev_arg(v, "v", plan.n_nodes, plan.mesh.device)
+    _dev_arg(T, "T", plan.nnz, plan.mesh.device)
     if T is None:
         T = torch.empty(plan.nnz, dtype=torch.float64, device=torch.device("cuda", plan.mesh.device))
-    c, keep = make_coeff(law_dc, u, tensor=tensor)
+    c, keep = make_coeff(law_dc, u, tensor=tensor, sizes=_sizes(plan, "stiff"), name="law")
     check(lib().qxa_cond_tensor_product(plan.handle, C.byref(c), _ptr(v), _ptr(T), _stream_ptr(stream)))
     return T
 
@@ -365,12 +426,14 @@ def assemble_iso(plan: Plan, law_m, law_c, field_m=None, field_c=None, M=None, C
     conductivity tensor per quadrature node, float64 [n_q][d(d+1)/2][n_elem]."""
     import torch
     dev = torch.device("cuda", plan.mesh.device)
+    _dev_arg(M, "M", plan.nnz, plan.mesh.device)
+    _dev_arg(Cv, "Cv", plan.nnz, plan.mesh.device)
+    cm, k1 = make_coeff(law_m, field_m, qpoint, sizes=_sizes(plan, "mass"), name="mass")
+    cc, k2 = make_coeff(law_c, field_c, qpoint, tensor, tensor_q, sizes=_sizes(plan, "stiff"), name="conductivity")
     if want_m and M is None:
         M = torch.empty(plan.nnz, dtype=torch.float64, device=dev)
     if want_c and Cv is None:
         Cv = torch.empty(plan.nnz, dtype=torch.float64, device=dev)
-    cm, k1 = make_coeff(law_m, field_m, qpoint)
-    cc, k2 = make_coeff(law_c, field_c, qpoint, tensor, tensor_q)
     check(lib().qxa_assemble_iso(plan.handle, C.byref(cm), C.byref(cc), _ptr(M if want_m else None),
                                  _ptr(Cv if want_c else None), _stream_ptr(stream)))
     return M, Cv
@@ -379,9 +442,10 @@ def assemble_iso(plan: Plan, law_m, law_c, field_m=None, field_c=None, M=None, C
 def load_vector(plan: Plan, law_f, field=None, F=None, stream=None, qpoint=False):
     """Volume load vector F_i = int f phi_i (device float64 [n_nodes]) on the plan's mass rule."""
     import torch
+    _dev_arg(F, "F", plan.n_nodes, plan.mesh.device)
+    c, keep = make_coeff(law_f, field, qpoint, sizes=_sizes(plan, "mass"), name="load")
     if F is None:
         F = torch.empty(plan.n_nodes, dtype=torch.float64, device=torch.device("cuda", plan.mesh.device))
-    c, keep = make_coeff(law_f, field, qpoint)
     check(lib().qxa_load_vector(plan.handle, C.byref(c), _ptr(F), _stream_ptr(stream)))
     return F
 
@@ -400,8 +464,8 @@ def element_matrices(plan: Plan, law_m, law_c, field_m=None, field_c=None, preci
     n2 = plan.n_p * plan.n_p
     Vm = torch.empty((n2, plan.n_elem), dtype=torch.float64, device=dev)
     Vc = torch.empty((n2, plan.n_elem), dtype=torch.float64, device=dev)
-    cm, k1 = make_coeff(law_m, field_m, qpoint)
-    cc, k2 = make_coeff(law_c, field_c, qpoint)
+    cm, k1 = make_coeff(law_m, field_m, qpoint, sizes=_sizes(plan, "mass"), name="mass")
+    cc, k2 = make_coeff(law_c, field_c, qpoint, sizes=_sizes(plan, "stiff"), name="conductivity")
     check(lib().qxa_element_matrices(plan.handle, C.byref(cm), C.byref(cc), _precision(precision), _ptr(Vm),
                                      _ptr(Vc), _stream_ptr(stream)))
     return Vm, Vc
@@ -415,10 +479,12 @@ class ReassemblyGraph:
         import torch
         dev = torch.device("cuda", plan.mesh.device)
         self.plan = plan
+        _dev_arg(M, "M", plan.nnz, plan.mesh.device)
+        _dev_arg(Cv, "Cv", plan.nnz, plan.mesh.device)
+        cm, self._k1 = make_coeff(law_m, field_m, qpoint, sizes=_sizes(plan, "mass"), name="mass")
+        cc, self._k2 = make_coeff(law_c, field_c, qpoint, sizes=_sizes(plan, "stiff"), name="conductivity")
         self.M = M if M is not None else torch.empty(plan.nnz, dtype=torch.float64, device=dev)
         self.Cv = Cv if Cv is not None else torch.empty(plan.nnz, dtype=torch.float64, device=dev)
-        cm, self._k1 = make_coeff(law_m, field_m, qpoint)
-        cc, self._k2 = make_coeff(law_c, field_c, qpoint)
         self.handle = C.c_void_p()
         check(lib().qxa_graph_create(plan.handle, C.byref(cm), C.byref(cc), _precision(precision), _ptr(self.M),
                                      _ptr(self.Cv), C.byref(self.handle)))
@@ -468,8 +534,12 @@ class Server:
         rule_c = rule_m if rule_c is None else rule_c
         qm, km = _quad(rule_m, mesh.dim)
         qc, kc = _quad(rule_c, mesh.dim)
-        cm, k1 = make_coeff(law_m, field_m, qpoint)
-        cc, k2 = make_coeff(law_c, field_c, qpoint, tensor)
+        if mesh.device != self.device:
+            raise ValueError(f"mesh on device {mesh.device}, server on {self.device}")
+        cm, k1 = make_coeff(law_m, field_m, qpoint, sizes=(mesh.dim, mesh.n_nodes, qm.n_q, mesh.n_elem, self.device),
+                            name="mass")
+        cc, k2 = make_coeff(law_c, field_c, qpoint, tensor,
+                            sizes=(mesh.dim, mesh.n_nodes, qc.n_q, mesh.n_elem, self.device), name="conductivity")
         job = _Job(mesh.handle, qm, qc, cm, cc, _precision(precision), int(tag))
         t = C.c_uint64()
         check(lib().qxa_server_submit(self.handle, C.byref(job), C.byref(t)))

@@ -142,6 +142,9 @@ struct Job {
     int batched = 0;
     double run_ms = 0.0;
     bool polled = false;
+    // copies of the result queued by qxa_server_copy_result on callers' streams:
+    // release waits for them before the buffer returns to the budget
+    std::vector<hipEvent_t> copies;
 };
 
 // Device and pinned host tables of one launch; held until its end event.
@@ -551,6 +554,11 @@ static void server_free(qxa_server s)
 {
     hipSetDevice(s->o.device);
     for (hipStream_t st : s->streams) hipStreamSynchronize(st);
+    for (auto &kv : s->jobs)
+        for (hipEvent_t ev : kv.second->copies) {
+            hipEventSynchronize(ev);
+            hipEventDestroy(ev);
+        }
     for (auto &kv : s->cache)
         if (kv.second->plan) qxa_plan_destroy(kv.second->plan);
     s->cache.clear();
@@ -714,16 +722,54 @@ qxa_status qxa_server_copy_result(qxa_server s, uint64_t ticket, double *M_vals,
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (M_vals && nnz) QXA_HIP(hipMemcpyAsync(M_vals, M, sizeof(double) * nnz, hipMemcpyDeviceToDevice, st));
     if (C_vals && nnz) QXA_HIP(hipMemcpyAsync(C_vals, C, sizeof(double) * nnz, hipMemcpyDeviceToDevice, st));
+    if ((M_vals || C_vals) && nnz) {
+        // the job's buffer may be reused only after these copies have read it
+        hipEvent_t ev;
+        QXA_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        hipError_t e = hipEventRecord(ev, st);
+        if (e != hipSuccess) {
+            hipEventDestroy(ev);
+            return hip_fail(e, "hipEventRecord");
+        }
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto f = s->jobs.find(ticket);
+        if (f == s->jobs.end()) {  // released by another thread meanwhile: wait here instead
+            hipEventSynchronize(ev);
+            hipEventDestroy(ev);
+        } else {
+            f->second->copies.push_back(ev);
+        }
+    }
     return QXA_OK;
 }
 
 qxa_status qxa_server_release(qxa_server s, uint64_t ticket)
 {
     if (!s) return fail(QXA_E_INVALID, "null server");
+    std::vector<hipEvent_t> copies;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto f = s->jobs.find(ticket);
+        if (f == s->jobs.end() || !f->second->polled) return fail(QXA_E_INVALID, "ticket not completed or unknown");
+        copies.swap(f->second->copies);
+    }
+    // queued copies of the result must have read the buffer before it can serve another job
+    hipError_t werr = hipSuccess;
+    for (hipEvent_t ev : copies) {
+        const hipError_t e = hipEventSynchronize(ev);
+        if (werr == hipSuccess) werr = e;
+        hipEventDestroy(ev);
+    }
     std::lock_guard<std::mutex> lk(s->mu);
     auto f = s->jobs.find(ticket);
-    if (f == s->jobs.end() || !f->second->polled) return fail(QXA_E_INVALID, "ticket not completed or unknown");
+    if (f == s->jobs.end()) return fail(QXA_E_INVALID, "ticket released twice");
     Job *j = f->second.get();
+    for (hipEvent_t ev : j->copies) {  // copies queued while this call waited
+        hipEventSynchronize(ev);
+        hipEventDestroy(ev);
+    }
+    j->copies.clear();
+    if (werr != hipSuccess) return hip_fail(werr, "hipEventSynchronize (result copy)");
     if (j->buf) {
         s->arena.release(j->buf);
         --s->holders;

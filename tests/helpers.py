@@ -1,6 +1,13 @@
 """Shared test helpers (comparison metrics; no assembly arithmetic)."""
 import numpy as np
 
+# Row-scaled error bounds of the reduced-precision contraction forms against the FP64
+# oracle. FP32, F16 hi+lo (with per-element power-of-two scaling of X) and the
+# three-term BF16 split carry 22-24-bit operands with FP32 accumulation; measured
+# 2-5e-7 on the 3D P2 and 2D P3 workloads, so each is held to the 1e-6 target.
+# The two-term BF16 split carries ~16 bits (measured 1.2-1.5e-5): its own bound.
+FORM_BOUNDS = {"fp32": 1e-6, "f16x2": 1e-6, "bf16x3": 1e-6, "bf16x2": 5e-5}
+
 
 def row_scaled_error(got, ref, row_ptr):
     """max_ij |v_ij - o_ij| / max_k |o_ik| (entrywise relative error is undefined on cancelled zeros)."""
@@ -33,3 +40,21 @@ def transpose_slots(row_ptr, col_idx):
     order = np.argsort(key)
     pos = np.searchsorted(key[order], tkey)
     return order[pos]
+
+
+def frobenius_error(got, ref):
+    """||got - ref||_F / ||ref||_F."""
+    n = float(np.linalg.norm(ref))
+    return float(np.linalg.norm(got - ref)) / (n if n > 0 else 1.0)
+
+
+_INPUTS = {}
+
+
+def workload_inputs(name):
+    """make_inputs of a named full-size workload, generated once per test process (the
+    2D P3 one takes tens of seconds)."""
+    from workloads import WORKLOADS, make_inputs
+    if name not in _INPUTS:
+        _INPUTS[name] = make_inputs(WORKLOADS[name])
+    return _INPUTS[name]

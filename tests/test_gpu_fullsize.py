@@ -1,0 +1,76 @@
+"""Every value of the main assembly at the full size of the largest workloads, against
+the oracle: the 2D P3 workload (1024^2 cells, 2,097,152 elements, 9,443,329 rows, nnz
+160,462,849) in FP64 and in each reduced-precision contraction form, and the 3D P1 heat
+workload (96^3 cells, 5,308,416 elements, nnz 13,465,441) in FP64 and FP32. Each form's
+row-scaled and Frobenius errors are printed as FORM_ERROR lines."""
+import json
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import FORM_BOUNDS, frobenius_error, row_scaled_error, transpose_slots, workload_inputs
+from workloads import WORKLOADS
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _setup(name):
+    import paper_2204_03893_amd as qxa
+    w = WORKLOADS[name]
+    print("case full size", name, "(inputs, oracle, plan)", flush=True)
+    mesh, r, u = workload_inputs(name)
+    rpo, cio, Mo, Co = oracle.assemble(mesh, r, r, w.mass_law, w.stiff_law, u, u)
+    m = qxa.Mesh(w.dim, w.order, mesh["coords"], mesh["conn"])
+    plan = qxa.Plan(m, r)
+    rp, ci = plan.pattern()
+    assert np.array_equal(rp.cpu().numpy(), rpo) and np.array_equal(ci.cpu().numpy(), cio)
+    return dict(qxa=qxa, w=w, mesh=mesh, r=r, u=u, uf=torch.tensor(u, device="cuda"), plan=plan, m=m,
+                rpo=rpo, cio=cio, Mo=Mo, Co=Co, t=None)
+
+
+@pytest.fixture(scope="module")
+def p3():
+    return _setup("p3_2d_1024")
+
+
+@pytest.fixture(scope="module")
+def heat():
+    return _setup("p1_3d_96_heat")
+
+
+def _check(S, form):
+    qxa, w, plan = S["qxa"], S["w"], S["plan"]
+    print("case", w.name, form, "full size", flush=True)
+    M, Cv = qxa.assemble(plan, w.mass_law, w.stiff_law, S["uf"], S["uf"], precision=form)
+    qxa.sync(plan)
+    Mh, Ch = M.cpu().numpy(), Cv.cpu().numpy()
+    del M, Cv
+    rpo = S["rpo"]
+    em, ec = row_scaled_error(Mh, S["Mo"], rpo), row_scaled_error(Ch, S["Co"], rpo)
+    fm, fc = frobenius_error(Mh, S["Mo"]), frobenius_error(Ch, S["Co"])
+    print("FORM_ERROR " + json.dumps({"workload": w.name, "form": form, "row_scaled": {"M": em, "C": ec},
+                                      "frobenius": {"M": fm, "C": fc}}), flush=True)
+    bound = 1e-12 if form == "fp64" else FORM_BOUNDS[form]
+    assert em <= bound and ec <= bound
+    if S["t"] is None:
+        S["t"] = transpose_slots(rpo, S["cio"])
+    t = S["t"]
+    assert np.array_equal(Mh, Mh[t]) and np.array_equal(Ch, Ch[t])   # bitwise symmetric
+    # properties at any size: the mass total with m = 1, zero conductivity row sums
+    if w.mass_law[0] == "const":
+        assert abs(Mh.sum() - 1.0) < 1e-10
+    rs = np.add.reduceat(Ch, rpo[:-1])
+    rmax = np.maximum.reduceat(np.abs(Ch), rpo[:-1])
+    assert np.all(np.abs(rs) <= (1e-12 if form == "fp64" else 1e-6) * rmax)
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32", "f16x2", "bf16x3", "bf16x2"])
+def test_p3_2d_1024_every_value(p3, form):
+    _check(p3, form)
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32"])
+def test_p1_3d_96_heat_every_value(heat, form):
+    _check(heat, form)

@@ -6,8 +6,8 @@ import numpy as np
 import pytest
 
 import oracle
-from helpers import row_scaled_error
-from workloads import WORKLOADS, make_inputs
+from helpers import row_scaled_error, workload_inputs
+from workloads import WORKLOADS
 from workloads.fields import gaussian_random_field
 
 pytestmark = pytest.mark.gpu
@@ -19,7 +19,7 @@ def setup():
     import paper_2204_03893_amd as qxa
     w = WORKLOADS["p3_2d_1024"]
     print("case next-items full size", w.name, flush=True)
-    mesh, r, u = make_inputs(w)
+    mesh, r, u = workload_inputs("p3_2d_1024")
     v = gaussian_random_field(mesh["coords"], 16, np.random.default_rng(2204), length=0.2)
     m = qxa.Mesh(w.dim, w.order, mesh["coords"], mesh["conn"])
     plan = qxa.Plan(m, r)

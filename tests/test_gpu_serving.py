@@ -196,3 +196,35 @@ def test_nonfinite_field_fails_only_its_job():
     srv.release(tb)
     plan.close()
     srv.close()
+
+
+def test_release_right_after_result_keeps_the_copied_values():
+    """result() queues the copy on the caller's stream; release() right after it, with
+    no synchronisation, must not let the next job (which takes the freed buffer, first
+    fit) overwrite the values before the copy has read them."""
+    import paper_2204_03893_amd as qxa
+    srv = qxa.Server(max_inflight=4, n_streams=2)
+    m = _mesh(2, 2, 6, seed=7)
+    mo = qxa.Mesh(2, 2, m["coords"], m["conn"])
+    r = rule(2, 4)
+    u1 = torch.tensor(_field(m, 71), device="cuda")
+    u2 = torch.tensor(_field(m, 72), device="cuda")
+    t1 = srv.submit(mo, r, r, LAW_M, LAW_C, u1, u1)
+    c1 = srv.wait(1)[0]
+    assert c1["status"] == 0
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        torch.cuda._sleep(50_000_000)     # holds back the copy queued behind it on `side`
+    M1, C1 = srv.result(t1, stream=side)
+    srv.release(t1)                       # no synchronisation of `side` before this
+    t2 = srv.submit(mo, r, r, LAW_M, LAW_C, u2, u2)
+    c2 = srv.wait(1)[0]
+    assert c2["status"] == 0 and c2["ticket"] == t2
+    side.synchronize()
+    plan, Ma, Ca = _alone(qxa, mo, r, u1)
+    torch.cuda.synchronize()
+    assert torch.equal(M1.view(torch.int64), Ma.view(torch.int64))
+    assert torch.equal(C1.view(torch.int64), Ca.view(torch.int64))
+    srv.release(t2)
+    plan.close()
+    srv.close()
