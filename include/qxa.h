@@ -217,6 +217,23 @@ qxa_status qxa_element_matrices(qxa_plan plan, const qxa_coeff *mass, const qxa_
                                 double *Vm, double *Vc, void *stream);
 
 /*
+ * Allocation-free variant of qxa_element_matrices, for callers that cannot
+ * allocate device memory: code under HIP graph capture, serving loops and
+ * harnesses that forbid hipMalloc. Same arguments, kernels and results (bitwise)
+ * as qxa_element_matrices, which allocates its pair-major staging of V_m, V_c on
+ * first use; here that staging lives in a fixed 64 MiB device array of the
+ * library (one per GPU, held until the process ends, its address resolved when
+ * the first mesh is created on that GPU). It calls no hipMalloc, hipFree or
+ * allocating routine. Limit: 2 * n_p(n_p+1)/2 * n_elem <= 8,388,608 doubles,
+ * else QXA_E_UNSUPPORTED with a message (e.g. 3D P2: up to 76,260 elements).
+ * The staging is fully written before it is read, so nothing needs clearing.
+ * All calls on one GPU share the array: calls that overlap in time on one GPU
+ * (different streams or host threads) race and must be ordered by the caller.
+ */
+qxa_status qxa_element_matrices_noalloc(qxa_plan plan, const qxa_coeff *mass, const qxa_coeff *stiff, int precision,
+                                        double *Vm, double *Vc, void *stream);
+
+/*
  * Coefficient of the mass tensor contracted with a nodal vector (Section 5, the
  * Newton Jacobian): the mass tensor M_ijk = int m'(u_h) phi_i phi_j phi_k
  * contracted with v in its second mode, (M o_2 v)_ik = int m'(u_h) v_h phi_i phi_k,

@@ -94,6 +94,7 @@ def lib():
         L.qxa_plan_check_host.argtypes = [ci, ci, i64, vp, i64, vp, C.POINTER(i64), C.POINTER(i64)]
         L.qxa_assemble.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), ci, vp, vp, vp]
         L.qxa_element_matrices.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), ci, vp, vp, vp]
+        L.qxa_element_matrices_noalloc.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), ci, vp, vp, vp]
         L.qxa_coeff_product.argtypes = [vp, ci, C.POINTER(_Coeff), vp, vp, vp]
         L.qxa_cond_tensor_product.argtypes = [vp, C.POINTER(_Coeff), vp, vp, vp]
         L.qxa_load_vector.argtypes = [vp, C.POINTER(_Coeff), vp, vp]
@@ -114,6 +115,7 @@ def lib():
         L.qxa_server_destroy.argtypes = [vp]
         for name in ("qxa_mesh_create", "qxa_mesh_destroy", "qxa_plan_create", "qxa_plan_destroy",
                      "qxa_plan_get_info", "qxa_plan_copy_pattern", "qxa_assemble", "qxa_element_matrices",
+                     "qxa_element_matrices_noalloc",
                      "qxa_sync", "qxa_pattern_host", "qxa_plan_check_host", "qxa_plan_set_timing", "qxa_plan_timing_report", "qxa_graph_create", "qxa_graph_launch",
                      "qxa_graph_destroy", "qxa_server_create", "qxa_server_submit", "qxa_server_poll",
                      "qxa_server_copy_result", "qxa_server_release", "qxa_server_pause", "qxa_server_stats", "qxa_server_destroy"):
@@ -468,6 +470,26 @@ def element_matrices(plan: Plan, law_m, law_c, field_m=None, field_c=None, preci
     cc, k2 = make_coeff(law_c, field_c, qpoint, sizes=_sizes(plan, "stiff"), name="conductivity")
     check(lib().qxa_element_matrices(plan.handle, C.byref(cm), C.byref(cc), _precision(precision), _ptr(Vm),
                                      _ptr(Vc), _stream_ptr(stream)))
+    return Vm, Vc
+
+
+def element_matrices_noalloc(plan: Plan, law_m, law_c, field_m=None, field_c=None, precision="fp64", Vm=None,
+                             Vc=None, stream=None, qpoint=False):
+    """Formation only, through the allocation-free entry point (staging in the library's
+    fixed device scratch). Vm, Vc: caller tensors [n_p*n_p, n_elem] (allocated here if None)."""
+    import torch
+    dev = torch.device("cuda", plan.mesh.device)
+    n2 = plan.n_p * plan.n_p
+    if Vm is None:
+        Vm = torch.empty((n2, plan.n_elem), dtype=torch.float64, device=dev)
+    if Vc is None:
+        Vc = torch.empty((n2, plan.n_elem), dtype=torch.float64, device=dev)
+    _dev_arg(Vm, "Vm", n2 * plan.n_elem, plan.mesh.device)
+    _dev_arg(Vc, "Vc", n2 * plan.n_elem, plan.mesh.device)
+    cm, k1 = make_coeff(law_m, field_m, qpoint, sizes=_sizes(plan, "mass"), name="mass")
+    cc, k2 = make_coeff(law_c, field_c, qpoint, sizes=_sizes(plan, "stiff"), name="conductivity")
+    check(lib().qxa_element_matrices_noalloc(plan.handle, C.byref(cm), C.byref(cc), _precision(precision),
+                                             _ptr(Vm), _ptr(Vc), _stream_ptr(stream)))
     return Vm, Vc
 
 

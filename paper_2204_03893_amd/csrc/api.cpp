@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "kernels_twopass.hpp"
@@ -254,6 +255,36 @@ static void build_qfrags(const RefTables &T, std::vector<uint8_t> (&out)[5], dou
     }
 }
 
+// Device scratch of the allocation-free formation entry point: the pair-major
+// element matrices V_m, V_c (2 * n_sym * n_elem doubles) live here instead of a
+// buffer allocated by the plan. Every GPU the library runs on holds its own copy
+// for the life of the process. In host code `scratch` only names the symbol:
+// kernels get the per-device address resolved by hipGetSymbolAddress.
+constexpr size_t kScratchDoubles = size_t(8) << 20;  // 64 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[64] = {};  // per device, resolved once at mesh creation
+
+// Resolves this device's scratch address (the device must be current). Once per device.
+static qxa_status resolve_scratch(int device)
+{
+    if (device < 0 || device >= 64) return fail(QXA_E_UNSUPPORTED, "device index above 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return QXA_OK;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[device] = static_cast<double *>(ptr);
+    return QXA_OK;
+}
+
+static double *scratch_of(int device)
+{
+    if (device < 0 || device >= 64) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
 }  // namespace qxa
 
 using namespace qxa;
@@ -275,6 +306,10 @@ qxa_status qxa_mesh_create(int device, int dim, int order, int64_t n_nodes, cons
     if (!coords || (n_elem > 0 && !conn)) return fail(QXA_E_INVALID, "null coords/conn");
     if (mem != QXA_MEM_HOST && mem != QXA_MEM_DEVICE) return fail(QXA_E_INVALID, "bad mem flag");
     QXA_HIP(hipSetDevice(device));
+    {
+        const qxa_status sst = resolve_scratch(device);  // set-up of this device's scratch address
+        if (sst) return sst;
+    }
     const int np = n_local(dim, order);
     std::vector<double> hx;
     std::vector<int32_t> hc;
@@ -695,6 +730,36 @@ qxa_status qxa_element_matrices(qxa_plan p, const qxa_coeff *mass, const qxa_coe
     a.conn = p->mesh->d_conn;
     a.Vm = Vm ? p->d_V : nullptr;
     a.Vc = Vc ? p->d_V + ns * ne : nullptr;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    QXA_HIP(launch_form(a, p->ref.dim, p->ref.order, p->ref.nq_m, p->ref.nq_c, precision, s));
+    ExpandArgs x{p->mesh->n_elem, p->ref.np, a.Vm, a.Vc, Vm, Vc};
+    QXA_HIP(launch_expand(x, s));
+    return QXA_OK;
+}
+
+qxa_status qxa_element_matrices_noalloc(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *stiff, int precision,
+                                        double *Vm, double *Vc, void *stream)
+{
+    if (!p) return fail(QXA_E_INVALID, "null plan");
+    if (precision != QXA_FP64 && precision != QXA_FP32)
+        return fail(QXA_E_UNSUPPORTED, "the formation-only entry point computes in FP64 or FP32");
+    FormArgs a{};
+    qxa_status st = fill_inputs(p, mass, stiff, precision, a.in, &a.Qm, &a.Qc);
+    if (st) return st;
+    if (!Vm && !Vc) return QXA_OK;
+    const size_t ns = size_t(p->ref.ns), ne = size_t(p->mesh->n_elem);
+    if (2 * ns * ne > kScratchDoubles)
+        return fail(QXA_E_UNSUPPORTED, "allocation-free formation: 2 * n_sym * n_elem = " + std::to_string(2 * ns * ne) +
+                                           " doubles exceeds the scratch of " + std::to_string(kScratchDoubles) +
+                                           " (64 MiB); use qxa_element_matrices");
+    if (ne == 0) return QXA_OK;
+    if (!p->d_flags) return fail(QXA_E_INVALID, "plan is owned by a server");
+    double *sc = scratch_of(p->mesh->device);
+    if (!sc) return fail(QXA_E_INVALID, "scratch address of the plan's device was not resolved");
+    QXA_HIP(hipSetDevice(p->mesh->device));
+    a.conn = p->mesh->d_conn;
+    a.Vm = Vm ? sc : nullptr;
+    a.Vc = Vc ? sc + ns * ne : nullptr;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     QXA_HIP(launch_form(a, p->ref.dim, p->ref.order, p->ref.nq_m, p->ref.nq_c, precision, s));
     ExpandArgs x{p->mesh->n_elem, p->ref.np, a.Vm, a.Vc, Vm, Vc};
