@@ -134,10 +134,16 @@ typedef struct {
     size_t device_bytes;    /* device memory held by the plan                       */
     double build_ms;        /* wall time of qxa_plan_create                         */
     int64_t n_tiles;        /* element tiles of the fused kernel                    */
-    int64_t n_shared;       /* CSR upper slots shared between tiles                 */
-    int64_t n_partials;     /* partial sums written for shared slots                */
+    int64_t n_shared;       /* CSR upper slots summed by the fix-up from partials   */
+    int64_t n_partials;     /* partial sums written for those slots                 */
+    int64_t n_outputs;      /* sums the fused kernel stores (CSR, carry, partial)   */
     int64_t n_units;        /* 16-byte output units read by the fused kernel        */
     int64_t n_pair_units;   /* of which pair units (two outputs each)               */
+    int64_t n_chains;       /* chains of tiles (workgroups of one launch)           */
+    int64_t n_carry_reads;  /* outputs that add an earlier tile's carried sum       */
+    int64_t n_fix_slots;    /* CSR slots written by the fix-up (both triangles)     */
+    int carry_cap;          /* LDS carry entries per workgroup                      */
+    int carry_used;         /* most carry entries live at once in a chain           */
 } qxa_plan_info;
 
 const char *qxa_last_error(void);
@@ -183,13 +189,19 @@ qxa_status qxa_plan_get_info(qxa_plan plan, qxa_plan_info *out);
 qxa_status qxa_pattern_host(int dim, int order, int64_t n_nodes, int64_t n_elem, const int32_t *conn,
                             int64_t *row_ptr, int32_t *col_idx, int64_t *nnz);
 
-/* Host-only build and structural self-check of the whole plan (pattern,
- * permutation, tile decomposition of the fused kernel): every index in bounds,
- * every CSR slot written exactly once. The same check runs inside
- * qxa_plan_create. Optional outputs: number of tiles and of shared-slot
- * partials. */
+/* Host-only build and check of the whole plan (pattern, permutation, tile
+ * plan of the fused kernel): the plan is executed on the host with exact
+ * integer sums (every element entry a pseudo-random 64-bit value) and each
+ * CSR slot must receive exactly its element entries; every index the kernels
+ * use is in bounds, every CSR slot and partial is written once, and carry
+ * entries are race-free within a tile. The same check runs inside
+ * qxa_plan_create. chains <= 0 and carry_cap < 0 take the values a plan on
+ * an MI355X gets (256 chains, the LDS left beside the kernel; the rules are
+ * the built-in ones of degree 2*order). Optional outputs: tiles, partials,
+ * outputs that read a carry entry. */
 qxa_status qxa_plan_check_host(int dim, int order, int64_t n_nodes, const double *coords, int64_t n_elem,
-                               const int32_t *conn, int64_t *n_tiles, int64_t *n_partials);
+                               const int32_t *conn, int64_t chains, int carry_cap, int64_t *n_tiles,
+                               int64_t *n_partials, int64_t *n_carry_reads);
 
 /* Copy the CSR pattern into caller-owned device arrays row_ptr[n_nodes+1] and
  * col_idx[nnz] (either may be NULL), asynchronously on `stream`. */

@@ -59,6 +59,7 @@ def _load():
         common = [C.c_int, C.c_int, C.c_int64, _D, C.c_int64, _I32, C.c_int, _D, _D, C.c_int, _D, _D,
                   C.POINTER(_Coeff), C.POINTER(_Coeff)]
         lib.oracle_assemble.argtypes = common + [_I64, _I32, _D, _D, C.c_int, C.POINTER(C.c_int64)]
+        lib.oracle_last_timing.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double)]
         lib.oracle_assemble_iso.argtypes = common + [_I64, _I32, _D, _D, C.c_int, C.POINTER(C.c_int64)]
         lib.oracle_assemble_rows.argtypes = common + [C.c_int64, _I64, _I64, _I32, _D, _D, C.c_int,
                                                       C.POINTER(C.c_int64)]
@@ -316,3 +317,11 @@ def assemble_iso(mesh, rule_m, rule_c, law_m, law_c, field_m=None, field_c=None,
     if rc:
         raise ValueError(f"oracle assemble_iso failed ({rc}), element {bad.value}")
     return row_ptr, col_idx, M, Cv
+
+
+def last_timing():
+    """(formation_s, assembly_s) of the last assemble() call: wall-clock seconds of the
+    element-matrix loop and of the global assembly (the paper's two timings)."""
+    f, a = C.c_double(0.0), C.c_double(0.0)
+    _load().oracle_last_timing(C.byref(f), C.byref(a))
+    return f.value, a.value

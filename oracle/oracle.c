@@ -630,6 +630,16 @@ static int assemble_rows(const refdata *R, const double *coords, int64_t n_nodes
  * then the global CSR values (parallel over rows, ascending elements per slot).
  * row_ptr/col_idx must be the oracle's own pattern (oracle_pattern_*).
  */
+/* Wall-clock seconds of the last oracle_assemble call, split as the paper times it
+ * (Section 6.1): formation of the element matrices, then their assembly into CSR.
+ * Instrumentation only: no effect on any value computed. */
+static double g_t_formation = 0.0, g_t_assembly = 0.0;
+void oracle_last_timing(double *formation_s, double *assembly_s)
+{
+    *formation_s = g_t_formation;
+    *assembly_s = g_t_assembly;
+}
+
 int oracle_assemble(int dim, int P, int64_t n_nodes, const double *coords, int64_t n_e, const int32_t *conn,
                     int nq_m, const double *pts_m, const double *w_m, int nq_c, const double *pts_c,
                     const double *w_c, const oracle_coeff *cm, const oracle_coeff *cc, const int64_t *row_ptr,
@@ -646,8 +656,10 @@ int oracle_assemble(int dim, int P, int64_t n_nodes, const double *coords, int64
         return -5;
     }
     int err = 0;
+    double t0 = 0.0, t1 = 0.0;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
+    t0 = omp_get_wtime();
 #pragma omp parallel for schedule(static)
 #endif
     for (int64_t e = 0; e < n_e; ++e) {
@@ -662,9 +674,16 @@ int oracle_assemble(int dim, int P, int64_t n_nodes, const double *coords, int64
             }
         }
     }
+#ifdef _OPENMP
+    t1 = omp_get_wtime();
+#endif
     if (!err)
         err = assemble_rows(&R, coords, n_nodes, conn, n_e, cm, cc, n_nodes, NULL, row_ptr, col_idx, Mv, Cv, Mebuf,
                             Cebuf, nthreads, bad_elem);
+#ifdef _OPENMP
+    g_t_formation = t1 - t0;
+    g_t_assembly = omp_get_wtime() - t1;
+#endif
     free(Mebuf);
     free(Cebuf);
     return err;

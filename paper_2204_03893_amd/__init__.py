@@ -46,7 +46,9 @@ class _PlanInfo(C.Structure):
                 ("n_q_stiff", C.c_int), ("n_nodes", C.c_int64), ("n_elem", C.c_int64), ("nnz", C.c_int64),
                 ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("device_bytes", C.c_size_t),
                 ("build_ms", C.c_double), ("n_tiles", C.c_int64), ("n_shared", C.c_int64),
-                ("n_partials", C.c_int64), ("n_units", C.c_int64), ("n_pair_units", C.c_int64)]
+                ("n_partials", C.c_int64), ("n_outputs", C.c_int64), ("n_units", C.c_int64), ("n_pair_units", C.c_int64),
+                ("n_chains", C.c_int64), ("n_carry_reads", C.c_int64), ("n_fix_slots", C.c_int64),
+                ("carry_cap", C.c_int), ("carry_used", C.c_int)]
 
 
 class _ServerOpts(C.Structure):
@@ -91,7 +93,8 @@ def lib():
         L.qxa_plan_copy_pattern.argtypes = [vp, vp, vp, vp]
         L.qxa_quad_builtin.argtypes = [C.c_int, C.c_int, C.POINTER(_Quad)]
         L.qxa_pattern_host.argtypes = [ci, ci, i64, i64, vp, vp, vp, C.POINTER(i64)]
-        L.qxa_plan_check_host.argtypes = [ci, ci, i64, vp, i64, vp, C.POINTER(i64), C.POINTER(i64)]
+        L.qxa_plan_check_host.argtypes = [ci, ci, i64, vp, i64, vp, i64, ci, C.POINTER(i64), C.POINTER(i64),
+                                          C.POINTER(i64)]
         L.qxa_assemble.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), ci, vp, vp, vp]
         L.qxa_element_matrices.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), ci, vp, vp, vp]
         L.qxa_element_matrices_noalloc.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), ci, vp, vp, vp]
@@ -249,8 +252,14 @@ class Plan:
         self.n_tiles = int(info.n_tiles)
         self.n_shared = int(info.n_shared)
         self.n_partials = int(info.n_partials)
+        self.n_outputs = int(info.n_outputs)
         self.n_units = int(info.n_units)
         self.n_pair_units = int(info.n_pair_units)
+        self.n_chains = int(info.n_chains)
+        self.n_carry_reads = int(info.n_carry_reads)
+        self.n_fix_slots = int(info.n_fix_slots)
+        self.carry_cap = int(info.carry_cap)
+        self.carry_used = int(info.carry_used)
 
     def pattern(self):
         """(row_ptr int64, col_idx int32) as device tensors."""
@@ -305,14 +314,15 @@ def pattern_host(dim, order, n_nodes, conn):
     return rp, ci
 
 
-def plan_check_host(dim, order, coords, conn):
-    """Host-only plan build + structural self-check; returns (n_tiles, n_partials)."""
+def plan_check_host(dim, order, coords, conn, chains=0, carry_cap=-1):
+    """Host-only plan build + check (the plan executed with exact integer sums);
+    returns (n_tiles, n_partials, n_carry_reads)."""
     X = np.ascontiguousarray(coords, dtype=np.float64)
     conn = np.ascontiguousarray(conn, dtype=np.int32)
-    nt, npart = C.c_int64(), C.c_int64()
+    nt, npart, ncr = C.c_int64(), C.c_int64(), C.c_int64()
     check(lib().qxa_plan_check_host(dim, order, X.shape[1], X.ctypes.data, conn.shape[1], conn.ctypes.data,
-                                    C.byref(nt), C.byref(npart)))
-    return nt.value, npart.value
+                                    int(chains), int(carry_cap), C.byref(nt), C.byref(npart), C.byref(ncr)))
+    return nt.value, npart.value, ncr.value
 
 
 def make_coeff(law, field=None, qpoint=False, tensor=None, tensor_q=None, sizes=None, name="coefficient"):

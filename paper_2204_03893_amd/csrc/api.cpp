@@ -387,6 +387,7 @@ qxa_status qxa_plan_destroy(qxa_plan p)
     if (!p) return QXA_OK;
     hipSetDevice(p->device);
     void *bufs[] = {p->d_row_ptr, p->d_col_idx, p->d_tconn, p->d_elem_order, p->d_rec, p->d_rec_ptr, p->d_rec_mid,
+                    p->d_chain_ptr,
                     p->d_part_ptr, p->d_fix_target, p->d_fix_mirror, p->d_sink, p->d_part, p->d_qfrag[0],
                     p->d_qfrag[1], p->d_qfrag[2], p->d_qfrag[3], p->d_qfrag[4], p->d_tables, p->d_tables_f,
                     p->d_V, p->d_flags, p->d_T, p->d_ns_ptr, p->d_ns_items, p->d_Fe, p->d_nf_ptr, p->d_nf_items, p->d_Tiso,
@@ -409,17 +410,24 @@ qxa_status plan_stage(qxa_mesh mesh, const qxa_quad &mr, const qxa_quad &cr, Pla
         return fail(QXA_E_UNSUPPORTED, "no kernel built for dim=" + std::to_string(T.dim) + " order=" +
                                            std::to_string(T.order) + " n_q(mass)=" + std::to_string(T.nq_m) +
                                            " n_q(stiffness)=" + std::to_string(T.nq_c));
-    st = build_host_plan(mesh->dim, mesh->order, mesh->n_nodes, mesh->n_elem, mesh->h_conn.data(), g.hp);
-    if (st) return st;
-    st = build_tile_plan(mesh->dim, mesh->order, mesh->n_nodes, mesh->n_elem, mesh->h_conn.data(),
-                         mesh->h_coords.data(), g.hp, tile_size(mesh->dim, mesh->order),
-                         fused_uses_mfma(mesh->dim, mesh->order), g.tp);
-    if (!st) st = check_tile_plan(T.np, mesh->n_elem, g.hp, g.tp);
-    if (st) return st;
     g.mfma = fused_uses_mfma(T.dim, T.order);
     if (g.mfma) build_qfrags(T, g.frag, g.f16_qinv);
     if (!split_ok(T.dim, T.order, T.nq_m, T.nq_c))
         for (int f = QXA_F16X2; f <= QXA_BF16X3; ++f) g.frag[f].clear();
+    st = build_host_plan(mesh->dim, mesh->order, mesh->n_nodes, mesh->n_elem, mesh->h_conn.data(), g.hp);
+    if (st) return st;
+    int cus = 256, lds = 160 * 1024;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, mesh->device) != hipSuccess) cus = 256;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, mesh->device) != hipSuccess)
+        lds = 160 * 1024;
+    (void)hipGetLastError();
+    int64_t qv16[5];
+    for (int f = 0; f < 5; ++f) qv16[f] = int64_t(g.frag[f].size() / 16);
+    const TileParams prm = fused_tile_params(T.dim, T.order, T.nq_m, T.nq_c, cus, size_t(lds), qv16);
+    st = build_tile_plan(mesh->dim, mesh->order, mesh->n_nodes, mesh->n_elem, mesh->h_conn.data(),
+                         mesh->h_coords.data(), g.hp, prm, g.tp);
+    if (!st) st = check_tile_plan(T.np, mesh->n_elem, g.hp, g.tp);
+    if (st) return st;
     // reference tables: FP64 block and an FP32 copy
     auto put = [&](const std::vector<double> &v) {
         size_t off = g.tab.size();
@@ -456,9 +464,15 @@ qxa_status plan_upload(qxa_mesh mesh, const PlanStaging &g, DevArena *arena, boo
     p->n_shared = tp.n_shared;
     p->n_fix = int64_t(tp.fix_target.size());
     p->n_partials = tp.n_partials;
+    p->n_outputs = tp.n_outputs;
     p->n_units = tp.rec_ptr.back();
-    p->n_pair_units = 0;
     for (int64_t t = 0; t < tp.n_tiles; ++t) p->n_pair_units += tp.rec_mid[t] - tp.rec_ptr[t];
+    p->n_chains = int64_t(tp.chain_ptr.size()) - 1;
+    p->n_carry_reads = tp.n_carry_reads;
+    p->carry_cap = tp.carry_cap;
+    p->carry_used = tp.carry_used;
+    p->h_chain_ptr = tp.chain_ptr;
+    for (size_t k = 0; k < tp.fix_target.size(); ++k) p->n_fix_slots += tp.fix_mirror[k] != tp.fix_target[k] ? 2 : 1;
     qxa_status st = plan_upload_buf(p, &p->d_row_ptr, hp.row_ptr.data(), hp.row_ptr.size());
     if (!st) st = plan_upload_buf(p, &p->d_col_idx, hp.col_idx.data(), hp.col_idx.size());
     if (!st) st = plan_upload_buf(p, &p->d_tconn, tp.tconn.data(), tp.tconn.size());
@@ -466,6 +480,7 @@ qxa_status plan_upload(qxa_mesh mesh, const PlanStaging &g, DevArena *arena, boo
     if (!st) st = plan_upload_buf(p, &p->d_rec, tp.rec.data(), tp.rec.size());
     if (!st) st = plan_upload_buf(p, &p->d_rec_ptr, tp.rec_ptr.data(), tp.rec_ptr.size());
     if (!st) st = plan_upload_buf(p, &p->d_rec_mid, tp.rec_mid.data(), tp.rec_mid.size());
+    if (!st) st = plan_upload_buf(p, &p->d_chain_ptr, tp.chain_ptr.data(), tp.chain_ptr.size());
     if (!st) st = plan_upload_buf(p, &p->d_part_ptr, tp.part_ptr.data(), tp.part_ptr.size());
     if (!st) st = plan_upload_buf(p, &p->d_fix_target, tp.fix_target.data(), tp.fix_target.size());
     if (!st) st = plan_upload_buf(p, &p->d_fix_mirror, tp.fix_mirror.data(), tp.fix_mirror.size());
@@ -541,8 +556,14 @@ qxa_status qxa_plan_get_info(qxa_plan p, qxa_plan_info *out)
     out->n_tiles = p->n_tiles;
     out->n_shared = p->n_shared;
     out->n_partials = p->n_partials;
+    out->n_outputs = p->n_outputs;
     out->n_units = p->n_units;
     out->n_pair_units = p->n_pair_units;
+    out->n_chains = p->n_chains;
+    out->n_carry_reads = p->n_carry_reads;
+    out->carry_cap = p->carry_cap;
+    out->carry_used = p->carry_used;
+    out->n_fix_slots = p->n_fix_slots;
     return QXA_OK;
 }
 
@@ -565,7 +586,8 @@ qxa_status qxa_pattern_host(int dim, int order, int64_t n_nodes, int64_t n_elem,
 }
 
 qxa_status qxa_plan_check_host(int dim, int order, int64_t n_nodes, const double *coords, int64_t n_elem,
-                               const int32_t *conn, int64_t *n_tiles, int64_t *n_partials)
+                               const int32_t *conn, int64_t chains, int carry_cap, int64_t *n_tiles,
+                               int64_t *n_partials, int64_t *n_carry_reads)
 {
     if (!coords || (n_elem > 0 && !conn)) return fail(QXA_E_INVALID, "null argument");
     if ((dim != 2 && dim != 3) || order < 1 || order > 3 || n_nodes < 1 || n_elem < 0)
@@ -573,16 +595,29 @@ qxa_status qxa_plan_check_host(int dim, int order, int64_t n_nodes, const double
     const int np = n_local(dim, order);
     for (size_t k = 0; k < size_t(np) * n_elem; ++k)
         if (conn[k] < 0 || conn[k] >= n_nodes) return fail(QXA_E_INDEX, "node index out of range");
+    qxa_quad rule{};
+    qxa_status st = qxa_quad_builtin(dim, 2 * order, &rule);
+    RefTables T;
+    if (!st) st = build_ref_tables(dim, order, rule, rule, T);
+    if (st) return st;
+    std::vector<uint8_t> frag[5];
+    double qinv[2];
+    if (fused_uses_mfma(dim, order)) build_qfrags(T, frag, qinv);
+    int64_t qv16[5];
+    for (int f = 0; f < 5; ++f) qv16[f] = int64_t(frag[f].size() / 16);
+    TileParams prm = fused_tile_params(dim, order, T.nq_m, T.nq_c, 256, size_t(160) * 1024, qv16);
+    if (chains > 0) prm.chains = chains;
+    if (carry_cap >= 0) prm.carry_cap = std::min(carry_cap, 65535);
     HostPlan hp;
-    qxa_status st = build_host_plan(dim, order, n_nodes, n_elem, conn, hp);
+    st = build_host_plan(dim, order, n_nodes, n_elem, conn, hp);
     if (st) return st;
     TilePlan tp;
-    st = build_tile_plan(dim, order, n_nodes, n_elem, conn, coords, hp, tile_size(dim, order),
-                         fused_uses_mfma(dim, order), tp);
+    st = build_tile_plan(dim, order, n_nodes, n_elem, conn, coords, hp, prm, tp);
     if (!st) st = check_tile_plan(np, n_elem, hp, tp);
     if (st) return st;
     if (n_tiles) *n_tiles = tp.n_tiles;
     if (n_partials) *n_partials = tp.n_partials;
+    if (n_carry_reads) *n_carry_reads = tp.n_carry_reads;
     return QXA_OK;
 }
 
@@ -658,9 +693,10 @@ qxa_status make_fused_args(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *s
     a.in.flags = flags;
     a.tconn = p->d_tconn;
     a.elem_order = p->d_elem_order;
-    a.rec = reinterpret_cast<const uint4 *>(p->d_rec);
+    a.rec = p->d_rec;
     a.rec_ptr = p->d_rec_ptr;
     a.rec_mid = p->d_rec_mid;
+    a.carry_cap = p->carry_cap;
     a.sink = p->d_sink;
     a.M = M;
     a.C = C;
@@ -702,7 +738,7 @@ qxa_status qxa_assemble(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *stif
         std::fprintf(stderr, "qxa: cleared an earlier HIP error before launching: %s\n", hipGetErrorString(stale));
     {
         TimedLaunch tl(p, "fused", s);
-        const JobTable jt{a, nullptr, nullptr, 0, p->n_tiles, a.buf_ok};
+        const JobTable jt{a, nullptr, nullptr, 0, p->n_tiles, a.buf_ok, p->d_chain_ptr, p->n_chains};
         QXA_HIP(launch_fused(jt, p->ref.dim, p->ref.order, p->ref.nq_m, p->ref.nq_c, precision, s));
     }
     TimedLaunch tl(p, "fixup", s);

@@ -7,6 +7,8 @@
 
 #include "../../include/qxa.h"
 #include "kernels_common.hpp"
+#include "plan_format.hpp"
+#include "qxa_internal.hpp"
 
 namespace qxa {
 
@@ -50,9 +52,11 @@ struct FusedArgs {
     const void *Qfrag;          // Q^T in MFMA B-operand order (matrix-core variant)
     int64_t qfrag_vec16;        // size of Qfrag in 16-byte units
     double qinv_m, qinv_c;      // inverse power-of-two scales of the FP16 Q tables (1 otherwise)
-    const uint4 *rec;           // output units: pairs {ta, a0|a1, tb, b0|b1}, then singles {t, c0|c1, c2|c3, c4|c5}
+    const uint32_t *rec;        // output units (plan_format.hpp)
     const int64_t *rec_ptr;     // [n_tiles + 1]
     const int64_t *rec_mid;     // [n_tiles] first single unit of each tile
+    int carry_cap;              // LDS carry entries of a workgroup
+    int pad0;
     double *sink;               // write target of idle lanes (at least 1024 doubles)
     double *M, *C;              // CSR values (either may be null)
     double *part;               // [n_partials][2] partials of shared slots (mass, conductivity)
@@ -65,14 +69,18 @@ struct FusedArgs {
 // (n_jobs == 0); a batch of assemblies that share a kernel (same shape,
 // rules and precision form) is a device array `jobs` with the running tile
 // count tile_end[j] (exclusive prefix). Workgroups map a global tile index
-// to (job, tile of the job).
+// to (job, tile of the job). The tiles are cut into chains (a job's chains
+// in its plan's order, jobs one after the other); a workgroup takes whole
+// chains, so that its tiles are one range of global tiles.
 struct JobTable {
     FusedArgs one;
     const FusedArgs *jobs;
     const int64_t *tile_end;
     int n_jobs;
     int64_t n_tiles;
-    int buf_stores;  // every job has buf_ok
+    int buf_stores;             // every job has buf_ok
+    const int64_t *chain_ptr;   // [n_chains + 1] first (global) tile of each chain
+    int64_t n_chains;
 };
 
 struct FixupArgs {
@@ -93,6 +101,11 @@ struct FixupTable {
 };
 
 bool form_supported(int D, int P, int nqm, int nqc);
+// Tile-plan parameters of the fused kernel of a shape: tile size, chains (the
+// workgroups of one launch on a device with `cus` compute units) and the LDS
+// carry entries left beside the kernel's other LDS (`lds_max` bytes per
+// workgroup) for every precision form with Q^T sizes qfrag_vec16[form].
+TileParams fused_tile_params(int D, int P, int nqm, int nqc, int cus, size_t lds_max, const int64_t (&qfrag_vec16)[5]);
 hipError_t launch_form(const FormArgs &a, int D, int P, int nqm, int nqc, int precision, hipStream_t st);
 hipError_t launch_fused(const JobTable &jt, int D, int P, int nqm, int nqc, int precision, hipStream_t st);
 hipError_t launch_fixup(const FixupTable &ft, hipStream_t st);

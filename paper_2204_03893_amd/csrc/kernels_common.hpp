@@ -349,6 +349,8 @@ struct TileWalk {
             step = G;
         }
     }
+    // a contiguous range of tiles [t0, t1)
+    __device__ TileWalk(int64_t t0, int64_t t1) : t(t0), hi(t1), step(1) {}
     __device__ bool valid(int64_t tt) const { return tt < hi; }
 };
 

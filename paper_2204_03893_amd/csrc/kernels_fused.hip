@@ -1,15 +1,16 @@
-// Fused assembly kernel: all of Algorithm 2 after the reference tables, in one
-// pass over the mesh.
+// Fused assembly kernels: all of Algorithm 2 after the reference tables, in
+// one pass over the mesh.
 //
-// One workgroup per tile of T consecutive elements (plan order), one lane per
-// element. Each lane computes its element's geometry and weighted coefficient
-// columns (geometry, S, Lambda, W), then for each matrix in turn forms the element
-// matrix V = Q X (symmetric-pair rows only) into LDS, and the
-// workgroup reduces every CSR slot the tile touches over the tile's
-// contributions in the plan's fixed order (the global assembly). Slots owned by the tile
-// are written directly (upper entry and its mirror); slots shared with other
-// tiles are written as partials and summed by the fix-up kernel in
-// ascending tile order. No float atomics: results are bitwise reproducible.
+// A workgroup walks the tiles of its chains (plan order). For each tile it
+// computes every element's geometry and weighted coefficient columns
+// (geometry, S, Lambda, W), forms the element matrices V = Q X (symmetric-pair
+// rows only) into LDS, and reduces the tile's outputs (the global assembly):
+// for every CSR slot the tile touches, the tile's contributions in the
+// plan's fixed order, added to a carry entry of an earlier tile of the chain
+// when there is one, and stored as the CSR value (upper slot and mirror), as
+// a carry entry for a later tile, or as a partial that the fix-up kernel sums
+// in ascending tile order. No float atomics: results are bitwise
+// reproducible.
 #include <algorithm>
 #include <type_traits>
 
@@ -18,113 +19,6 @@
 #include "kernels_common.hpp"
 
 namespace qxa {
-
-// Sums of one record's contributions (padded LDS indices, plan order) to both
-// staged matrices. Absent contributions index the zero kept at (pair 0,
-// column T), so the six reads are unconditional (adding +0.0 changes no sum).
-template <typename ST>
-__device__ __forceinline__ void record_sums(const uint4 R, const ST *sVm, const ST *sVc, double &am, double &ac)
-{
-    const uint32_t c[6] = {R.y & 0xffffu, R.y >> 16, R.z & 0xffffu, R.z >> 16, R.w & 0xffffu, R.w >> 16};
-    double vm[6], vc[6];
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        vm[q] = double(sVm[c[q]]);
-        vc[q] = double(sVc[c[q]]);
-    }
-    am = vm[0];
-    ac = vc[0];
-#pragma unroll
-    for (int q = 1; q < 6; ++q) {
-        am += vm[q];
-        ac += vc[q];
-    }
-}
-
-// The same for V_m and V_c staged interleaved, pair (V_m, V_c) of entry c at
-// sV[2 c], sV[2 c + 1]: one LDS read per contribution.
-template <typename ST>
-__device__ __forceinline__ void record_sums_pair(const uint4 R, const ST *sV, double &am, double &ac)
-{
-    using ST2 = typename std::conditional<sizeof(ST) == 8, double2, float2>::type;
-    const ST2 *v2 = reinterpret_cast<const ST2 *>(sV);
-    const uint32_t c[6] = {R.y & 0xffffu, R.y >> 16, R.z & 0xffffu, R.z >> 16, R.w & 0xffffu, R.w >> 16};
-    ST2 v[6];
-#pragma unroll
-    for (int q = 0; q < 6; ++q) v[q] = v2[c[q]];
-    am = double(v[0].x);
-    ac = double(v[0].y);
-#pragma unroll
-    for (int q = 1; q < 6; ++q) {
-        am += double(v[q].x);
-        ac += double(v[q].y);
-    }
-}
-
-// The two outputs of a pair unit {ta, a0|a1, tb, b0|b1} from the same staging.
-template <typename ST>
-__device__ __forceinline__ void pair_sums(const uint4 U, const ST *sV, double &ama, double &aca, double &amb,
-                                          double &acb)
-{
-    using ST2 = typename std::conditional<sizeof(ST) == 8, double2, float2>::type;
-    const ST2 *v2 = reinterpret_cast<const ST2 *>(sV);
-    const ST2 a0 = v2[U.y & 0xffffu], a1 = v2[U.y >> 16], b0 = v2[U.w & 0xffffu], b1 = v2[U.w >> 16];
-    ama = double(a0.x) + double(a1.x);
-    aca = double(a0.y) + double(a1.y);
-    amb = double(b0.x) + double(b1.x);
-    acb = double(b0.y) + double(b1.y);
-}
-
-// Reduction of one record into its CSR slot (target >= 0) or partial.
-template <typename ST>
-__device__ __forceinline__ void reduce_record(const uint4 R, const ST *sVm, const ST *sVc, const FusedArgs &a)
-{
-    double am, ac;
-    record_sums(R, sVm, sVc, am, ac);
-    const int32_t t = int32_t(R.x);
-    if (t >= 0) {
-        if (a.M) a.M[t] = am;
-        if (a.C) a.C[t] = ac;
-    } else {
-        a.part[2 * (-int64_t(t) - 1)] = am;
-        a.part[2 * (-int64_t(t) - 1) + 1] = ac;
-    }
-}
-
-constexpr int kPrefetch = 4;  // records per thread loaded before the contraction
-
-__device__ __forceinline__ void prefetch_records(const uint4 *__restrict__ rec, int64_t r0, int64_t r1, int stride,
-                                                 uint4 (&pf)[kPrefetch])
-{
-#pragma unroll
-    for (int i = 0; i < kPrefetch; ++i) {
-        const int64_t k = r0 + threadIdx.x + int64_t(i) * stride;
-        pf[i] = k < r1 ? rec[k] : make_uint4(0u, 0u, 0u, 0u);
-    }
-}
-
-// All records of a tile (one workgroup of `stride` threads): the prefetched
-// batch first, then the rest in groups of kPrefetch independent loads.
-template <typename ST>
-__device__ __forceinline__ void tile_reduce(const uint4 (&pf)[kPrefetch], const FusedArgs &a, int64_t tile,
-                                            const ST *sVm, const ST *sVc, int stride)
-{
-    const int64_t r0 = a.rec_ptr[tile], r1 = a.rec_ptr[tile + 1];
-#pragma unroll
-    for (int i = 0; i < kPrefetch; ++i)
-        if (r0 + threadIdx.x + int64_t(i) * stride < r1) reduce_record(pf[i], sVm, sVc, a);
-    for (int64_t k0 = r0 + threadIdx.x + int64_t(kPrefetch) * stride; k0 < r1; k0 += int64_t(kPrefetch) * stride) {
-        uint4 R[kPrefetch];
-#pragma unroll
-        for (int i = 0; i < kPrefetch; ++i) {
-            const int64_t k = k0 + int64_t(i) * stride;
-            R[i] = k < r1 ? a.rec[k] : make_uint4(0u, 0u, 0u, 0u);
-        }
-#pragma unroll
-        for (int i = 0; i < kPrefetch; ++i)
-            if (k0 + int64_t(i) * stride < r1) reduce_record(R[i], sVm, sVc, a);
-    }
-}
 
 // Job of global tile g (uniform across the workgroup) and the tile's index in
 // it; MULTI = false compiles the single-assembly launch (job carried by value).
@@ -160,41 +54,299 @@ __device__ __forceinline__ FusedArgs args_of(const JobTable &jt, int j)
     return jt.one;
 }
 
+typedef uint32_t qxa_u2 __attribute__((ext_vector_type(2)));
+
+// Raw buffer resource over [base, base + bytes) for stores: stride 0, word 3
+// as the gfx9 family takes it (32-bit data format, no swizzle, no index
+// range). A store whose offset is at or past `bytes` is dropped by the
+// hardware; bytes = 0 drops every store.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t store_rsrc(void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(base, 0, int(bytes), 0x00020000);
+}
+
+// Tiles of a workgroup: the chains jt.chain_ptr assigns it, one range of
+// global tiles. With one chain per workgroup the chains are spread
+// XCD-aware (the workgroups of one XCD take consecutive chains, which are
+// neighbouring regions of the mesh).
+__device__ __forceinline__ TileWalk chain_walk(const JobTable &jt)
+{
+    const int64_t G = gridDim.x, b = blockIdx.x, nc = jt.n_chains;
+    int64_t c0, c1;
+    if (G == nc) {
+        c0 = xcd_tile(b, nc);
+        c1 = c0 + 1;
+    } else {
+        c0 = b * nc / G;
+        c1 = (b + 1) * nc / G;
+    }
+    return TileWalk(uniform_table(jt.chain_ptr)[c0], uniform_table(jt.chain_ptr)[c1]);
+}
+
+// ---------------------------------------------------------------------------
+// Outputs of a tile (plan_format.hpp): 16-byte units, read by the consumer
+// threads in rounds (one unit per thread), CH rounds per chunk, the next
+// chunk (or the next tile's first) loaded before the current one is stored.
+// Each output sums its entries (a carry entry first, then the staged pairs
+// (V_m, V_c)) in FP64 and stores the sum: CSR values through buffer stores
+// that drop lanes without a CSR target (so every round issues the same two
+// stores and a wait for the next units leaves them in flight), a carry entry
+// (LDS) or a partial (global).
+
+// Entries of an output: staged pairs (ST2: FP64 or FP32 pairs) and, as the
+// first entry only, a carry entry (an FP64 pair).
+template <typename ST>
+struct Entries {
+    using ST2 = typename std::conditional<sizeof(ST) == 8, double2, float2>::type;
+    const ST2 *v2;
+    const double2 *carry;
+    uint32_t cb, zero;
+    __device__ __forceinline__ double2 pair(uint32_t c) const
+    {
+        const ST2 x = v2[c];
+        return make_double2(double(x.x), double(x.y));
+    }
+    // first entry: a staged pair or a carry entry; with FP64 staging one read
+    // through a selected address, else both reads (each in bounds) and a select
+    __device__ __forceinline__ double2 first(uint32_t c) const
+    {
+        if constexpr (sizeof(ST) == 8) {
+            return *(c < cb ? reinterpret_cast<const double2 *>(v2) + c : carry + (c - cb));
+        } else {
+            const bool isc = c >= cb;
+            const double2 xc = carry[isc ? c - cb : 0u];
+            const double2 xv = pair(isc ? zero : c);
+            return isc ? xc : xv;
+        }
+    }
+};
+
+// The sums of a single unit {t, c0|c1, c2|c3, c4|c5} (absent entries index the zero pair).
+template <typename ST>
+__device__ __forceinline__ void unit_sums(const uint4 U, const Entries<ST> &E, double &am, double &ac)
+{
+    const uint32_t c[6] = {U.y & 0xffffu, U.y >> 16, U.z & 0xffffu, U.z >> 16, U.w & 0xffffu, U.w >> 16};
+    double2 v[6];
+    v[0] = E.first(c[0]);
+#pragma unroll
+    for (int q = 1; q < 6; ++q) v[q] = E.pair(c[q]);
+    am = v[0].x;
+    ac = v[0].y;
+#pragma unroll
+    for (int q = 1; q < 6; ++q) {
+        am += v[q].x;
+        ac += v[q].y;
+    }
+}
+
+// The two outputs of a pair unit {ta, a0|a1, tb, b0|b1}.
+template <typename ST>
+__device__ __forceinline__ void pair_sums(const uint4 U, const Entries<ST> &E, double &ama, double &aca, double &amb,
+                                          double &acb)
+{
+    const double2 a0 = E.first(U.y & 0xffffu), a1 = E.pair(U.y >> 16);
+    const double2 b0 = E.first(U.w & 0xffffu), b1 = E.pair(U.w >> 16);
+    ama = a0.x + a1.x;
+    aca = a0.y + a1.y;
+    amb = b0.x + b1.x;
+    acb = b0.y + b1.y;
+}
+
+// Consumer threads (NCT of them, ct = 0 .. NCT - 1) of a workgroup: the units
+// of every tile of the walk. on_tile(k) is called before tile k of the walk is
+// reduced: it waits for (or stages) the tile's element matrices and returns
+// their LDS pairs.
+template <typename ST, bool MULTI, bool BUF, int CH, int NCT, class OnTile>
+__device__ __forceinline__ void consume_units(const JobTable &jt, const TileWalk &walk, int ct, double2 *carry,
+                                              uint32_t cb, uint32_t zero, OnTile &&on_tile)
+{
+    const int cw = 64 * __builtin_amdgcn_readfirstlane(ct >> 6);  // this wave's first lane (uniform)
+    uint4 R[CH], Rn[CH];
+    // unit of round q of chunk c: r0 + (c * CH + q) * NCT + ct, clamped to the tile
+    auto load_chunk = [&](const uint4 *rec, int64_t r0, int64_t r1, int64_t c, uint4(&dst)[CH]) {
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            const int64_t k = r0 + (c * CH + q) * NCT + ct;
+            dst[q] = rec[k < r1 ? k : r1 - 1];
+        }
+    };
+    // tile ranges are uniform: read them through the scalar path, so that
+    // waiting for them never waits for this wave's outstanding stores
+    auto tile_range = [&](const FusedArgs &b, int64_t t, int64_t &r0, int64_t &r1) {
+        r0 = uniform_table(b.rec_ptr)[t];
+        r1 = uniform_table(b.rec_ptr)[t + 1];
+    };
+    int64_t g = walk.t;
+    {
+        int64_t tile, r0, r1;
+        const FusedArgs a = args_of<MULTI>(jt, job_of<MULTI>(jt, g, tile));
+        tile_range(a, tile, r0, r1);
+        load_chunk(reinterpret_cast<const uint4 *>(a.rec), r0, r1, 0, R);
+    }
+    for (int64_t k = 0;; ++k, g += walk.step) {
+        const ST *bV = on_tile(k);
+        const Entries<ST> E{reinterpret_cast<const typename Entries<ST>::ST2 *>(bV), carry, cb, zero};
+        int64_t tile, r0, r1;
+        const FusedArgs a = args_of<MULTI>(jt, job_of<MULTI>(jt, g, tile));
+        tile_range(a, tile, r0, r1);
+        const int64_t rm = uniform_table(a.rec_mid)[tile];  // pair units end here
+        const int64_t nch = (r1 - r0 + int64_t(CH) * NCT - 1) / (int64_t(CH) * NCT);
+        const int64_t gn = g + walk.step;
+        const bool more = walk.valid(gn);
+        const uint4 *rec = reinterpret_cast<const uint4 *>(a.rec), *rec_n = rec;
+        int64_t r0n = r0, r1n = r1;
+        if (more) {
+            int64_t tn;
+            const FusedArgs an = args_of<MULTI>(jt, job_of<MULTI>(jt, gn, tn));
+            rec_n = reinterpret_cast<const uint4 *>(an.rec);
+            tile_range(an, tn, r0n, r1n);
+        }
+        const __amdgpu_buffer_rsrc_t rM = store_rsrc(a.M ? a.M : a.sink, a.M ? a.bytes_vals : 0u);
+        const __amdgpu_buffer_rsrc_t rC = store_rsrc(a.C ? a.C : a.sink, a.C ? a.bytes_vals : 0u);
+        double2 *part = reinterpret_cast<double2 *>(a.part);
+        for (int64_t c = 0; c < nch; ++c) {
+            // next chunk: the following one of this tile, else the next tile's first
+            const bool inner = c + 1 < nch;
+            load_chunk(inner ? rec : rec_n, inner ? r0 : r0n, inner ? r1 : r1n, inner ? c + 1 : 0, Rn);
+            const uint32_t none = zero | (zero << 16);  // no entries
+#pragma unroll
+            for (int q = 0; q < CH; ++q) {
+                const int64_t k0 = r0 + (c * CH + q) * NCT;
+                if (!BUF && k0 >= r1) continue;  // the whole round is past the tile's units (uniform)
+                const int64_t ku = k0 + ct, kw = k0 + cw;
+                const bool active = ku < r1, pair = ku < rm;  // rm <= r1: a pair unit is active
+                const uint4 U = R[q];
+                const int32_t ta = int32_t(U.x), tb = int32_t(U.z);
+                double ama = 0.0, aca = 0.0, amb = 0.0, acb = 0.0;
+                if (k0 < r1) {  // (uniform) no LDS reads for a round past the tile's units
+                    if (kw + 63 < rm) {  // the wave's units are all pairs
+                        pair_sums(U, E, ama, aca, amb, acb);
+                    } else if (kw >= rm) {  // all singles; idle lanes read the zero pair
+                        unit_sums(active ? U : make_uint4(0u, none, none, none), E, ama, aca);
+                    } else if (pair) {  // the wave that holds the boundary
+                        pair_sums(U, E, ama, aca, amb, acb);
+                    } else {
+                        unit_sums(active ? U : make_uint4(0u, none, none, none), E, ama, aca);
+                    }
+                }
+                const bool csra = active && ta >= 0 && ta < kCodeCarry, csrb = pair && tb >= 0 && tb < kCodeCarry;
+                if constexpr (BUF) {
+                    const uint32_t drop = 0x80000000u;
+                    const uint32_t oa = csra ? uint32_t(ta) * 8u : drop;
+                    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(qxa_u2, ama), rM, oa, 0, 0);
+                    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(qxa_u2, aca), rC, oa, 0, 0);
+                    if (kw < rm) {  // (uniform) second outputs of the wave's pair units
+                        const uint32_t ob = csrb ? uint32_t(tb) * 8u : drop;
+                        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(qxa_u2, amb), rM, ob, 0, 0);
+                        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(qxa_u2, acb), rC, ob, 0, 0);
+                    }
+                } else {
+                    if (csra) {
+                        if (a.M) a.M[ta] = ama;
+                        if (a.C) a.C[ta] = aca;
+                    }
+                    if (csrb) {
+                        if (a.M) a.M[tb] = amb;
+                        if (a.C) a.C[tb] = acb;
+                    }
+                }
+                // carries and partials sit at the end of each group: branches (skipped by
+                // waves without one) add stores but never remove the ones above
+                if (active && ta >= kCodeCarry) carry[ta - kCodeCarry] = make_double2(ama, aca);
+                if (active && ta < 0) part[-int64_t(ta) - 1] = make_double2(ama, aca);
+                if (pair && tb >= kCodeCarry) carry[tb - kCodeCarry] = make_double2(amb, acb);
+                if (pair && tb < 0) part[-int64_t(tb) - 1] = make_double2(amb, acb);
+            }
+#pragma unroll
+            for (int q = 0; q < CH; ++q) R[q] = Rn[q];
+        }
+        if (!more) break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Vector-ALU variant (P1): one workgroup per tile, one lane per element. The
+// lanes load their first output units, form their element's matrices into LDS
+// as (V_m, V_c) pairs, then reduce the tile's units. Every tile is a chain of
+// its own (no carries): the elements are cheap to form and many small
+// workgroups per CU hide the memory latency better than a pipeline.
+constexpr int kP1Prefetch = 4;  // units per thread loaded before the contraction
+
 template <int D, int P, int NQM, int NQC, typename CT, int T, bool MULTI>
 __global__ __launch_bounds__(T) void fused_kernel(JobTable jt)
 {
     using S = Shape<D, P>;
-    extern __shared__ double sV[];  // [2][NS][T + 1] (row stride padded against bank conflicts)
-    double *sVm = sV, *sVc = sV + S::NS * (T + 1);
-    // the padding column of row 0 is never a contribution: keep a zero there
-    if (threadIdx.x == 0) sVm[T] = sVc[T] = 0.0;
+    extern __shared__ __align__(16) double2 sP[];  // [NS][T + 1] pairs
+    double *sV = reinterpret_cast<double *>(sP);
+    if (threadIdx.x == 0) sP[T] = make_double2(0.0, 0.0);  // the zero pair: column T of pair 0
     int64_t tile;
     const FusedArgs a = args_of<MULTI>(jt, job_of<MULTI>(jt, xcd_tile(blockIdx.x, gridDim.x), tile));
-    const int64_t p0 = tile * T;
     const int64_t ne = a.in.n_elem;
-    const int lane = threadIdx.x;
-    const int64_t p = p0 + lane;
-    const bool active = p < ne;
-    uint4 pf[kPrefetch];
-    prefetch_records(a.rec, a.rec_ptr[tile], a.rec_ptr[tile + 1], T, pf);
-
-    double A[S::NG], lm[NQM], lc[NQC];
-    if (active) {
+    const int64_t r0 = a.rec_ptr[tile], r1 = a.rec_ptr[tile + 1], rm = a.rec_mid[tile];
+    const uint4 *rec = reinterpret_cast<const uint4 *>(a.rec);
+    uint4 pf[kP1Prefetch];
+#pragma unroll
+    for (int i = 0; i < kP1Prefetch; ++i) {
+        const int64_t k = r0 + threadIdx.x + int64_t(i) * T;
+        pf[i] = k < r1 ? rec[k] : make_uint4(0u, 0u, 0u, 0u);
+    }
+    const int64_t p = tile * T + threadIdx.x;
+    if (p < ne) {
+        double A[S::NG], lm[NQM], lc[NQC];
         int32_t v[S::NP];
 #pragma unroll
         for (int i = 0; i < S::NP; ++i) v[i] = a.tconn[i * ne + p];
         const int64_t eid = (a.in.cm.kind == 2 || a.in.cc.kind == 2) ? int64_t(a.elem_order[p]) : p;
         if (!element_setup<D, P, NQM, NQC>(a.in, v, eid, A, lm, lc)) atomicOr(a.in.flags, 1);
-        // a matrix that is not requested is not formed (its staged values are never stored)
+        // a matrix that is not requested is not formed (its sums are never stored)
         if (a.M)
             contract_mass<S::NS, NQM>(reinterpret_cast<const CT *>(a.Qm), lm,
-                                      [&](int s, double x) { sVm[s * (T + 1) + lane] = x; });
+                                      [&](int s, double x) { sV[2 * (s * (T + 1) + threadIdx.x)] = x; });
         if (a.C)
-            contract_stiff<P, S::NS, NQC, S::NG>(reinterpret_cast<const CT *>(a.Qc), lc, A,
-                                                 [&](int s, double x) { sVc[s * (T + 1) + lane] = x; });
+            contract_stiff<P, S::NS, NQC, S::NG>(reinterpret_cast<const CT *>(a.Qc), lc, A, [&](int s, double x) {
+                sV[2 * (s * (T + 1) + threadIdx.x) + 1] = x;
+            });
     }
     lds_barrier();
-    tile_reduce(pf, a, tile, sVm, sVc, T);
+    // no carry entries: every entry is a staged pair
+    const Entries<double> E{reinterpret_cast<const double2 *>(sP), nullptr, 0xffffu, uint32_t(T)};
+    double2 *part = reinterpret_cast<double2 *>(a.part);
+    auto put = [&](int32_t t, double am, double ac) {
+        if (t >= 0) {
+            if (a.M) a.M[t] = am;
+            if (a.C) a.C[t] = ac;
+        } else {
+            part[-int64_t(t) - 1] = make_double2(am, ac);
+        }
+    };
+    auto reduce = [&](int64_t k, const uint4 U) {
+        if (k < rm) {
+            double ama, aca, amb, acb;
+            pair_sums(U, E, ama, aca, amb, acb);
+            put(int32_t(U.x), ama, aca);
+            put(int32_t(U.z), amb, acb);
+        } else {
+            double am, ac;
+            unit_sums(U, E, am, ac);
+            put(int32_t(U.x), am, ac);
+        }
+    };
+#pragma unroll
+    for (int i = 0; i < kP1Prefetch; ++i) {
+        const int64_t k = r0 + threadIdx.x + int64_t(i) * T;
+        if (k < r1) reduce(k, pf[i]);
+    }
+    for (int64_t k0 = r0 + threadIdx.x + int64_t(kP1Prefetch) * T; k0 < r1; k0 += int64_t(kP1Prefetch) * T) {
+        uint4 U[kP1Prefetch];
+#pragma unroll
+        for (int i = 0; i < kP1Prefetch; ++i) {
+            const int64_t k = k0 + int64_t(i) * T;
+            U[i] = k < r1 ? rec[k] : make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (int i = 0; i < kP1Prefetch; ++i)
+            if (k0 + int64_t(i) * T < r1) reduce(k0 + int64_t(i) * T, U[i]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -229,17 +381,6 @@ struct Mfma<float> {
     }
 };
 
-typedef uint32_t qxa_u2 __attribute__((ext_vector_type(2)));
-typedef uint32_t qxa_u4 __attribute__((ext_vector_type(4)));
-
-// Raw buffer resource over [base, base + bytes) for stores: stride 0, word 3
-// as the gfx9 family takes it (32-bit data format, no swizzle, no index
-// range). A store whose offset is at or past `bytes` is dropped by the
-// hardware; bytes = 0 drops every store.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t store_rsrc(void *base, uint32_t bytes)
-{
-    return __builtin_amdgcn_make_buffer_rsrc(base, 0, int(bytes), 0x00020000);
-}
 
 template <typename T>
 __device__ __forceinline__ T sel4(int j, T a0, T a1, T a2, T a3)
@@ -505,7 +646,7 @@ __device__ __forceinline__ bool lane_setup(const FormInputs &in, const RawElem<D
 
 template <int PF>
 struct FormTraits {
-    using stage_t = float;  // reduced forms stage V in FP32; CSR accumulation stays FP64
+    using stage_t = float;  // reduced forms stage V in FP32; carries and the CSR accumulation stay FP64
     using qplain_t = float;
 };
 template <>
@@ -528,6 +669,7 @@ struct FormTraits<QXA_FP64> {
 // behind them in flight.
 // producer threads: 4 waves of one 16-element group each, or 8 waves for T = 16
 constexpr int ws_producers(int T) { return T == 16 ? 512 : 256; }
+// output rounds per consumer chunk (plan_format.hpp; at most 6)
 // unit rounds per consumer chunk, sized so that one chunk holds all of a
 // tile's output units on Kuhn meshes (the next tile's are then loaded a whole
 // tile ahead): 2D P2 up to ~790 units per 64-element tile on 512 consumer
@@ -800,7 +942,7 @@ struct WsLds {
     static constexpr size_t tab_doubles = size_t(NQM + NQC) * NP + NQM + NQC;
     static constexpr size_t wide_doubles =
         QLDS ? 0 : size_t(2) * T * ((D + 1) * D + 2 * NP + NQM + NQC + Shape<D, P>::NG);
-    static size_t bytes(int64_t qfrag_vec16)
+    static __host__ __device__ size_t bytes(int64_t qfrag_vec16)
     {
         return v_bytes + (QLDS ? size_t(qfrag_vec16) * 16 : 0) + (tab_doubles + wide_doubles) * 8;
     }
@@ -849,7 +991,7 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
     }
     // a zero pair in the (never written) padding column of row 0 of each buffer
     if (tid < 4) sV[(tid >> 1) * BUF_ELEMS + 2 * T + (tid & 1)] = ST(0);
-    const TileWalk walk(jt.n_tiles);
+    const TileWalk walk = chain_walk(jt);
     lds_barrier();
     if (tid < NPT) {
       if constexpr (!QLDS) {
@@ -936,127 +1078,21 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
         }
       }
     } else {
-        const int ct = tid - NPT;
-        const int cw = 64 * __builtin_amdgcn_readfirstlane(ct >> 6);  // this wave's first lane (uniform)
-        uint4 R[CH], Rn[CH];
-        // unit of round q of chunk c: r0 + (c * CH + q) * NCT + ct, clamped to the tile
-        auto load_chunk = [&](const uint4 *rec, int64_t r0, int64_t r1, int64_t c, uint4 (&dst)[CH]) {
-#pragma unroll
-            for (int q = 0; q < CH; ++q) {
-                const int64_t k = r0 + (c * CH + q) * NCT + ct;
-                dst[q] = rec[k < r1 ? k : r1 - 1];
-            }
-        };
-        // tile ranges are uniform: read them through the scalar path, so that
-        // waiting for them never waits for this wave's outstanding stores
-        auto tile_range = [&](const FusedArgs &b, int64_t t, int64_t &r0, int64_t &r1) {
-            r0 = uniform_table(b.rec_ptr)[t];
-            r1 = uniform_table(b.rec_ptr)[t + 1];
-        };
-        // BUF: the mass and conductivity stores of every round's first outputs are
-        // buffer stores; a lane without an owned slot gives an offset past the end
-        // of the buffer, which the hardware drops. With at least two memory
-        // operations per round, the wait for the next chunk's units (loaded before
-        // this chunk's stores) leaves 2 * CH stores in flight instead of draining them.
-        auto consume = [&](auto buf_tag) {
-            constexpr bool BUF = decltype(buf_tag)::value;
-            int64_t g = walk.t;
-            {
-                int64_t tile, r0, r1;
-                const FusedArgs a = args_of<MULTI>(jt, job_of<MULTI>(jt, g, tile));
-                tile_range(a, tile, r0, r1);
-                load_chunk(a.rec, r0, r1, 0, R);
-            }
+        double2 *carry = reinterpret_cast<double2 *>(smem + ((LDS::bytes(a0.qfrag_vec16) + 15) & ~size_t(15)));
+        // one barrier per tile: the producers have staged tile k, and the
+        // consumers are done with the buffer of tile k - 1 (and its carries)
+        auto on_tile = [&](int64_t k) -> const ST * {
             if constexpr (!QLDS)  // the wide producers' pipeline fill
-                for (int k = 0; k < kWidePrologueBarriers; ++k) lds_barrier();
-            lds_barrier();  // first tile staged
-            for (int it = 1;; ++it, g += walk.step) {
-                int64_t tile, r0, r1;
-                const FusedArgs a = args_of<MULTI>(jt, job_of<MULTI>(jt, g, tile));
-                tile_range(a, tile, r0, r1);
-                const int64_t rm = uniform_table(a.rec_mid)[tile];  // pair units end here
-                const int64_t nch = (r1 - r0 + int64_t(CH) * NCT - 1) / (int64_t(CH) * NCT);
-                const int64_t gn = g + walk.step;
-                const bool more = walk.valid(gn);
-                const uint4 *rec_n = a.rec;
-                int64_t r0n = r0, r1n = r1;
-                if (more) {
-                    int64_t tn;
-                    const FusedArgs an = args_of<MULTI>(jt, job_of<MULTI>(jt, gn, tn));
-                    rec_n = an.rec;
-                    tile_range(an, tn, r0n, r1n);
-                }
-                const ST *bV = sV + ((it - 1) & 1) * BUF_ELEMS;
-                const __amdgpu_buffer_rsrc_t rM = store_rsrc(a.M ? a.M : a.sink, a.M ? a.bytes_vals : 0u);
-                const __amdgpu_buffer_rsrc_t rC = store_rsrc(a.C ? a.C : a.sink, a.C ? a.bytes_vals : 0u);
-                double2 *part = reinterpret_cast<double2 *>(a.part);
-                for (int64_t c = 0; c < nch; ++c) {
-                    // next chunk: the following one of this tile, else the next tile's first
-                    const bool inner = c + 1 < nch;
-                    load_chunk(inner ? a.rec : rec_n, inner ? r0 : r0n, inner ? r1 : r1n, inner ? c + 1 : 0, Rn);
-                    const uint32_t none = uint32_t(T) | (uint32_t(T) << 16);  // absent contributions
-#pragma unroll
-                    for (int q = 0; q < CH; ++q) {
-                        const int64_t k0 = r0 + (c * CH + q) * NCT;
-                        if (!BUF && k0 >= r1) continue;  // the whole round is past the tile's units (uniform)
-                        const int64_t k = k0 + ct, kw = k0 + cw;
-                        const bool active = k < r1, pair = k < rm;  // rm <= r1: a pair unit is active
-                        const uint4 U = R[q];
-                        const int32_t ta = int32_t(U.x), tb = int32_t(U.z);
-                        double ama = 0.0, aca = 0.0, amb = 0.0, acb = 0.0;
-                        if (k0 < r1) {  // (uniform) no LDS reads for a round past the tile's units
-                            if (kw + 63 < rm) {  // the wave's units are all pairs
-                                pair_sums(U, bV, ama, aca, amb, acb);
-                            } else if (kw >= rm) {  // all singles; idle lanes read the zero pair
-                                record_sums_pair(active ? U : make_uint4(0u, none, none, none), bV, ama, aca);
-                            } else if (pair) {  // the wave that holds the boundary
-                                pair_sums(U, bV, ama, aca, amb, acb);
-                            } else {
-                                record_sums_pair(active ? U : make_uint4(0u, none, none, none), bV, ama, aca);
-                            }
-                        }
-                        if constexpr (BUF) {
-                            const uint32_t drop = 0x80000000u;
-                            const uint32_t oa = active && ta >= 0 ? uint32_t(ta) * 8u : drop;
-                            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(qxa_u2, ama), rM, oa, 0, 0);
-                            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(qxa_u2, aca), rC, oa, 0, 0);
-                            if (kw < rm) {  // (uniform) second outputs of the wave's pair units
-                                const uint32_t ob = pair && tb >= 0 ? uint32_t(tb) * 8u : drop;
-                                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(qxa_u2, amb), rM, ob, 0, 0);
-                                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(qxa_u2, acb), rC, ob, 0, 0);
-                            }
-                            // partials sit at the end of each group: branches (skipped by waves
-                            // without one) add stores but never remove the two above
-                            if (active && ta < 0) part[-int64_t(ta) - 1] = make_double2(ama, aca);
-                            if (pair && tb < 0) part[-int64_t(tb) - 1] = make_double2(amb, acb);
-                        } else {
-                            if (active) {
-                                if (ta >= 0) {
-                                    if (a.M) a.M[ta] = ama;
-                                    if (a.C) a.C[ta] = aca;
-                                } else {  // the (mass, conductivity) pair of a partial: one 16-byte store
-                                    part[-int64_t(ta) - 1] = make_double2(ama, aca);
-                                }
-                            }
-                            if (pair) {
-                                if (tb >= 0) {
-                                    if (a.M) a.M[tb] = amb;
-                                    if (a.C) a.C[tb] = acb;
-                                } else {
-                                    part[-int64_t(tb) - 1] = make_double2(amb, acb);
-                                }
-                            }
-                        }
-                    }
-#pragma unroll
-                    for (int q = 0; q < CH; ++q) R[q] = Rn[q];
-                }
-                if (!more) break;
-                lds_barrier();  // next tile staged; this buffer may be overwritten
-            }
+                if (k == 0)
+                    for (int b = 0; b < kWidePrologueBarriers; ++b) lds_barrier();
+            lds_barrier();
+            return sV + (k & 1) * BUF_ELEMS;
         };
-        if (jt.buf_stores) consume(std::true_type{});
-        else consume(std::false_type{});
+        const uint32_t cb = uint32_t(carry_base(S::NS, T));
+        if (jt.buf_stores)
+            consume_units<ST, MULTI, true, CH, NCT>(jt, walk, tid - NPT, carry, cb, uint32_t(T), on_tile);
+        else
+            consume_units<ST, MULTI, false, CH, NCT>(jt, walk, tid - NPT, carry, cb, uint32_t(T), on_tile);
     }
 }
 
@@ -1110,27 +1146,70 @@ bool fused_uses_mfma(int D, int P) { return P >= 2; }
 
 // Resident workgroups for a persistent launch: CUs x workgroups per CU.
 template <class K>
-static unsigned persistent_grid(K kernel, int block, size_t lds, int64_t n_tiles)
+static unsigned persistent_grid(K kernel, int block, size_t lds, int64_t n_chains)
 {
     int dev = 0, cus = 256, per_cu = 1;
     if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, lds) != hipSuccess || per_cu < 1)
         per_cu = 1;
     (void)hipGetLastError();  // a failed occupancy query must not be reported as a launch error
-    return unsigned(std::min<int64_t>(n_tiles, int64_t(cus) * per_cu));
+    return unsigned(std::min<int64_t>(n_chains, int64_t(cus) * per_cu));
+}
+
+// LDS bytes of a launch: the kernel's layout, then the carry entries (16 bytes each).
+static size_t with_carries(size_t bytes, int carry_cap) { return ((bytes + 15) & ~size_t(15)) + 16 * size_t(carry_cap); }
+
+constexpr int kMaxCarries = 4096;
+
+template <int D, int P>
+static size_t p1_lds_bytes()
+{
+    return size_t(tile_size(D, P) + 1) * Shape<D, P>::NS * 16;
+}
+
+TileParams fused_tile_params(int D, int P, int nqm, int nqc, int cus, size_t lds_max, const int64_t (&qv16)[5])
+{
+    TileParams tp;
+    tp.T = tile_size(D, P);
+    tp.pair_units = true;
+    if (P == 1) {  // the vector-ALU variant: a chain per tile, no carries
+        tp.chains = int64_t(1) << 40;
+        tp.carry_cap = 0;
+        return tp;
+    }
+    size_t base = 0;
+#define X(d, p, m, c)                                                                                              \
+    if (D == d && P == p && nqm == m && nqc == c) {                                                               \
+        constexpr int T = tile_size(d, p);                                                                        \
+        if constexpr (use_mfma<d, p>()) {                                                                         \
+            base = std::max(WsLds<d, p, m, c, QXA_FP64, T>::bytes(qv16[QXA_FP64]),                                \
+                            WsLds<d, p, m, c, QXA_FP32, T>::bytes(qv16[QXA_FP32]));                               \
+            if constexpr (split_ok(d, p, m, c)) {                                                                 \
+                base = std::max(base, WsLds<d, p, m, c, QXA_F16X2, T>::bytes(qv16[QXA_F16X2]));                   \
+                base = std::max(base, WsLds<d, p, m, c, QXA_BF16X2, T>::bytes(qv16[QXA_BF16X2]));                 \
+                base = std::max(base, WsLds<d, p, m, c, QXA_BF16X3, T>::bytes(qv16[QXA_BF16X3]));                 \
+            }                                                                                                     \
+        }                                                                                                         \
+    }
+    QXA_FORM_CASES(X)
+#undef X
+    const size_t room = lds_max > with_carries(base, 0) ? lds_max - with_carries(base, 0) : 0;
+    tp.carry_cap = int(std::min<size_t>(kMaxCarries, room / 16) / 16 * 16);
+    tp.chains = int64_t(std::max(1, cus));  // one workgroup per CU
+    return tp;
 }
 
 hipError_t launch_fused(const JobTable &jt, int D, int P, int nqm, int nqc, int precision, hipStream_t st)
 {
     const int64_t n_tiles = jt.n_tiles;
-    if (n_tiles == 0) return hipSuccess;
-    const FusedArgs &a = jt.one;  // the first job (Q^T fragment size is shared by all jobs)
+    if (n_tiles == 0 || jt.n_chains == 0) return hipSuccess;
+    const FusedArgs &a = jt.one;  // the first job (Q^T fragment size and carry entries are shared by all jobs)
 #define QXA_LAUNCH_MFMA(d, p, m, c, PF, MULTI)                                                            \
     {                                                                                                     \
         constexpr int T = tile_size(d, p);                                                                \
-        const size_t lds = WsLds<d, p, m, c, PF, T>::bytes(a.qfrag_vec16);                              \
+        const size_t lds = with_carries(WsLds<d, p, m, c, PF, T>::bytes(a.qfrag_vec16), a.carry_cap);    \
         auto k = fused_ws_kernel<d, p, m, c, PF, T, MULTI>;                                               \
-        k<<<persistent_grid(k, ws_threads(T), lds, n_tiles), ws_threads(T), lds, st>>>(jt);               \
+        k<<<persistent_grid(k, ws_threads(T), lds, jt.n_chains), ws_threads(T), lds, st>>>(jt);           \
     }
 #define X(d, p, m, c)                                                                                      \
     if (D == d && P == p && nqm == m && nqc == c) {                                                        \
@@ -1159,14 +1238,23 @@ hipError_t launch_fused(const JobTable &jt, int D, int P, int nqm, int nqc, int 
             }                                                                                              \
         } else {                                                                                           \
             if (precision != QXA_FP64 && precision != QXA_FP32) return hipErrorInvalidValue;               \
-            const size_t lds = 2 * size_t(T + 1) * Shape<d, p>::NS * sizeof(double);                      \
-            const unsigned grid = unsigned(n_tiles);                                                       \
+            const size_t lds = p1_lds_bytes<d, p>();                                                       \
             if (precision == QXA_FP32) {                                                                   \
-                if (multi) fused_kernel<d, p, m, c, float, T, true><<<grid, T, lds, st>>>(jt);              \
-                else fused_kernel<d, p, m, c, float, T, false><<<grid, T, lds, st>>>(jt);                  \
+                if (multi) {                                                                               \
+                    auto k = fused_kernel<d, p, m, c, float, T, true>;                                     \
+                    k<<<unsigned(n_tiles), T, lds, st>>>(jt);                        \
+                } else {                                                                                   \
+                    auto k = fused_kernel<d, p, m, c, float, T, false>;                                    \
+                    k<<<unsigned(n_tiles), T, lds, st>>>(jt);                        \
+                }                                                                                          \
             } else {                                                                                       \
-                if (multi) fused_kernel<d, p, m, c, double, T, true><<<grid, T, lds, st>>>(jt);             \
-                else fused_kernel<d, p, m, c, double, T, false><<<grid, T, lds, st>>>(jt);                 \
+                if (multi) {                                                                               \
+                    auto k = fused_kernel<d, p, m, c, double, T, true>;                                    \
+                    k<<<unsigned(n_tiles), T, lds, st>>>(jt);                        \
+                } else {                                                                                   \
+                    auto k = fused_kernel<d, p, m, c, double, T, false>;                                   \
+                    k<<<unsigned(n_tiles), T, lds, st>>>(jt);                        \
+                }                                                                                          \
             }                                                                                              \
         }                                                                                                  \
         return hipGetLastError();                                                                          \

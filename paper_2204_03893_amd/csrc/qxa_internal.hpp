@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/qxa.h"
+#include "plan_format.hpp"
 
 namespace qxa {
 
@@ -80,37 +81,43 @@ struct HostPlan {
 qxa_status build_host_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, const int32_t *conn, HostPlan &hp);
 
 // Tile decomposition for the fused kernel.
+struct TileParams {
+    int T = 64;            // elements per tile
+    int64_t chains = 256;  // chains (workgroups of one launch) the tiles are split into
+    int carry_cap = 0;     // LDS carry entries of a workgroup
+    bool pair_units = true;
+};
+
 struct TilePlan {
     int T = 0;
     int64_t n_tiles = 0;
     std::vector<int32_t> elem_order;  // tile position -> element id (Morton order of centroids)
     std::vector<int32_t> tconn;       // [np][n_elem] connectivity in tile order
-    // A tile's outputs in 16-byte units. An output has a target (>= 0: a CSR
-    // slot owned by the tile, upper and mirror entries being separate outputs
-    // with the same contributions; < 0: partial -(p + 1)) and the padded LDS
-    // indices (s*(T+1) + local element) of its contributions in summation
-    // order; T (pair 0, padding column, where the kernels keep a zero) = none.
-    // Units rec_ptr[t] .. rec_mid[t] - 1 are pair units {target a, a0|a1,
-    // target b, b0|b1} of outputs with at most two contributions (output l of
-    // that group with output l + n/2, n = 2 (rec_mid - rec_ptr)); the rest are
-    // single units {target, c0|c1, c2|c3, c4|c5} (at most six). In each group
-    // owned outputs come first in ascending CSR slot order (coalesced stores),
-    // then partials. Without pair units (P1) rec_mid[t] = rec_ptr[t].
+    // Chain c holds tiles chain_ptr[c] .. chain_ptr[c+1] - 1; a workgroup
+    // processes whole chains, so carries never cross a chain.
+    std::vector<int64_t> chain_ptr;   // [n_chains + 1]
+    int carry_cap = 0, carry_used = 0;
+    // Output units of tile t (plan_format.hpp): rec_ptr[t] .. rec_ptr[t+1] - 1,
+    // pair units up to rec_mid[t]. In each group CSR outputs come first in
+    // ascending slot order (upper and mirror entries separately), then carry
+    // outputs, then partials.
     std::vector<uint32_t> rec;        // [4 * n_units]
     std::vector<int64_t> rec_ptr;     // [n_tiles + 1] (in units)
-    std::vector<int64_t> rec_mid;     // [n_tiles] first single unit of the tile
+    std::vector<int64_t> rec_mid;     // [n_tiles]
     // Partials of shared upper slot k (CSR order) are part_ptr[k] ..
-    // part_ptr[k+1] - 1, in ascending tile order, then unit order.
+    // part_ptr[k+1] - 1, in ascending tile order, then chunk order.
     std::vector<int64_t> part_ptr;    // [n_shared + 1]
     // fix-up: shared upper slot k (ascending CSR order) and its mirror slot
     std::vector<int32_t> fix_target;  // [n_shared]
     std::vector<int32_t> fix_mirror;  // [n_shared]
     int64_t n_shared = 0;
     int64_t n_partials = 0;
+    int64_t n_outputs = 0;            // outputs of all tiles
+    int64_t n_carry_reads = 0;        // outputs that read a carry entry
 };
 
 qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, const int32_t *conn,
-                           const double *coords, const HostPlan &hp, int T, bool pair_units, TilePlan &tp);
+                           const double *coords, const HostPlan &hp, const TileParams &prm, TilePlan &tp);
 qxa_status check_tile_plan(int np, int64_t n_elem, const HostPlan &hp, const TilePlan &tp);
 
 // First-fit sub-allocator over one device allocation (256-byte granules,
@@ -139,6 +146,7 @@ private:
 // Everything of a plan that is computed on the host (reference tables, CSR
 // pattern, tile plan, operand-ordered Q^T), before any device allocation.
 struct PlanStaging {
+    int device = 0;
     RefTables ref;
     HostPlan hp;
     TilePlan tp;
@@ -181,11 +189,15 @@ struct qxa_plan_s {
     int32_t *d_col_idx = nullptr;
     // fused-path tile plan (device copies)
     int tile_T = 0;
-    int64_t n_tiles = 0, n_shared = 0, n_partials = 0, n_units = 0, n_pair_units = 0;
+    int64_t n_tiles = 0, n_shared = 0, n_partials = 0, n_outputs = 0, n_units = 0, n_pair_units = 0, n_chains = 0,
+            n_carry_reads = 0;
+    int carry_cap = 0, carry_used = 0;
+    int64_t n_fix_slots = 0;  // CSR slots the fix-up writes (shared upper slots and their mirrors)
     int32_t *d_tconn = nullptr, *d_elem_order = nullptr;
     uint32_t *d_rec = nullptr;
-    int64_t *d_rec_ptr = nullptr;
-    int64_t *d_rec_mid = nullptr;
+    int64_t *d_rec_ptr = nullptr, *d_rec_mid = nullptr;
+    int64_t *d_chain_ptr = nullptr;
+    std::vector<int64_t> h_chain_ptr;  // host copy (batched launches concatenate the chains of their jobs)
     int64_t *d_part_ptr = nullptr;
     int32_t *d_fix_target = nullptr, *d_fix_mirror = nullptr;
     int64_t n_fix = 0;

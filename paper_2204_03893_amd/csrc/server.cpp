@@ -192,13 +192,17 @@ struct qxa_server_s {
 
 namespace qxa {
 
-static size_t tab_layout(int cap, size_t &o_fix, size_t &o_te, size_t &o_fe)
+// Launch table of a batch: FusedArgs[cap] | FixupArgs[cap] | tile_end[cap] |
+// fix_end[cap] | chain_ptr[cap * max_chains + 1] (the jobs' chains, in global
+// tiles, one after the other).
+static size_t tab_layout(int cap, int64_t max_chains, size_t &o_fix, size_t &o_te, size_t &o_fe, size_t &o_cp)
 {
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
     o_fix = al(sizeof(FusedArgs) * cap);
     o_te = o_fix + al(sizeof(FixupArgs) * cap);
     o_fe = o_te + al(sizeof(int64_t) * cap);
-    return o_fe + al(sizeof(int64_t) * cap);
+    o_cp = o_fe + al(sizeof(int64_t) * cap);
+    return o_cp + al(sizeof(int64_t) * (size_t(cap) * size_t(max_chains) + 1));
 }
 
 static void finish_job(qxa_server s, Job *j, int status, const std::string &msg)
@@ -383,33 +387,39 @@ static void launch_group(qxa_server s, std::vector<Job *> &g)
     if (e == hipSuccess) e = hipMemsetAsync(sl.d_flags, 0, sizeof(int) * g.size(), st);
     if (g.size() == 1) {
         const Job *j = g[0];
-        const JobTable jt{j->fa, nullptr, nullptr, 0, j->entry->plan->n_tiles, j->fa.buf_ok};
+        const qxa_plan jp = j->entry->plan;
+        const JobTable jt{j->fa, nullptr, nullptr, 0, jp->n_tiles, j->fa.buf_ok, jp->d_chain_ptr, jp->n_chains};
         const FixupTable ft{j->xa, nullptr, nullptr, 0, j->entry->plan->n_fix};
         if (e == hipSuccess) e = launch_fused(jt, R.dim, R.order, R.nq_m, R.nq_c, prec, st);
         if (e == hipSuccess) e = launch_fixup(ft, st);
     } else {
-        size_t o_fix, o_te, o_fe;
-        tab_layout(s->o.max_inflight, o_fix, o_te, o_fe);
+        size_t o_fix, o_te, o_fe, o_cp;
+        tab_layout(s->o.max_inflight, s->o.batch_tile_limit, o_fix, o_te, o_fe, o_cp);
         char *h = static_cast<char *>(sl.h_tab);
         char *d = static_cast<char *>(sl.d_tab);
         auto *hfa = reinterpret_cast<FusedArgs *>(h);
         auto *hxa = reinterpret_cast<FixupArgs *>(h + o_fix);
         auto *hte = reinterpret_cast<int64_t *>(h + o_te);
         auto *hfe = reinterpret_cast<int64_t *>(h + o_fe);
-        int64_t nt = 0, nf = 0;
+        auto *hcp = reinterpret_cast<int64_t *>(h + o_cp);
+        int64_t nt = 0, nf = 0, nc = 0;
         int buf = 1;
+        hcp[0] = 0;
         for (size_t k = 0; k < g.size(); ++k) {
+            const qxa_plan q = g[k]->entry->plan;
             buf &= g[k]->fa.buf_ok;
             hfa[k] = g[k]->fa;
             hxa[k] = g[k]->xa;
-            nt += g[k]->entry->plan->n_tiles;
-            nf += g[k]->entry->plan->n_fix;
+            for (int64_t c = 1; c <= q->n_chains; ++c) hcp[++nc] = nt + q->h_chain_ptr[c];
+            nt += q->n_tiles;
+            nf += q->n_fix;
             hte[k] = nt;
             hfe[k] = nf;
         }
-        if (e == hipSuccess) e = hipMemcpyAsync(d, h, o_fe + sizeof(int64_t) * g.size(), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d, h, o_cp + sizeof(int64_t) * size_t(nc + 1), hipMemcpyHostToDevice, st);
         const JobTable jt{g[0]->fa, reinterpret_cast<const FusedArgs *>(d), reinterpret_cast<const int64_t *>(d + o_te),
-                          int(g.size()), nt, buf};
+                          int(g.size()), nt, buf, reinterpret_cast<const int64_t *>(d + o_cp), nc};
         const FixupTable ft{g[0]->xa, reinterpret_cast<const FixupArgs *>(d + o_fix),
                             reinterpret_cast<const int64_t *>(d + o_fe), int(g.size()), nf};
         if (e == hipSuccess) e = launch_fused(jt, R.dim, R.order, R.nq_m, R.nq_c, prec, st);
@@ -597,7 +607,8 @@ qxa_status qxa_server_create(const qxa_server_opts *opts, qxa_server *out)
     s->o = o;
     qxa_status st = s->arena.init(o.hbm_budget_bytes);
     size_t o_fix, o_te, o_fe;
-    s->tab_bytes = tab_layout(o.max_inflight, o_fix, o_te, o_fe);
+    size_t o_cp;
+    s->tab_bytes = tab_layout(o.max_inflight, o.batch_tile_limit, o_fix, o_te, o_fe, o_cp);
     for (int k = 0; k < o.n_streams && !st; ++k) {
         hipStream_t h = nullptr;
         hipError_t e = hipStreamCreateWithFlags(&h, hipStreamNonBlocking);

@@ -1,18 +1,30 @@
-// Tile plan for the fused formation + scatter kernel (Algorithm 2 after its
+// Tile plan of the fused formation + scatter kernel (Algorithm 2 after its
 // reference tables, in one pass over the mesh).
 //
 // Elements are ordered along a Morton curve of their centroids and cut into
-// tiles of T consecutive elements. One workgroup forms the element matrices
-// of a tile in LDS and reduces, for every CSR slot the tile touches, the
-// tile's contributions in a fixed order. A slot whose contributions all come
-// from one tile is written by that tile (upper slot and its mirror); a slot
-// touched by several tiles gets one partial per tile, and the fix-up kernel
-// sums the partials in ascending tile order. Every slot is written exactly
-// once, with no atomics, so results are bitwise reproducible.
+// tiles of T consecutive elements; consecutive tiles form chains, one chain
+// per workgroup of a launch. A workgroup forms the element matrices of its
+// tiles one after the other in LDS and reduces, for every CSR slot a tile
+// touches, the tile's contributions in a fixed order:
+//  - a slot touched by one tile only is written by that tile (upper slot and
+//    its mirror);
+//  - a slot touched by several tiles of one chain is carried: the first of
+//    those tiles writes its partial sum to an LDS carry entry, each later one
+//    adds the carry to its own contributions, and the last one writes the
+//    CSR value (or, for a slot that other chains touch too, a partial);
+//  - a slot touched by several chains gets one partial per chain (or per
+//    tile, when no carry entry is free), and the fix-up kernel sums the
+//    partials of each such slot in ascending tile order.
+// Every slot is written exactly once and nothing is atomic, so results are
+// bitwise reproducible.
+//
+// A tile's outputs travel in 16-byte units (plan_format.hpp).
 #include <algorithm>
 #include <array>
 #include <atomic>
 #include <cmath>
+#include <numeric>
+#include <queue>
 #include <thread>
 
 #include "qxa_internal.hpp"
@@ -44,13 +56,36 @@ static uint64_t spread_bits(uint64_t x, int dim)
     return r;
 }
 
+namespace {
+
+// Role of one tile for one upper slot it touches.
+enum Role : uint8_t {
+    R_OWNED,      // only toucher: CSR upper + mirror
+    R_CARRY_OUT,  // first tile of a carried group: carry := own
+    R_CARRY_MID,  // carry := carry + own
+    R_CARRY_CSR,  // last tile, the slot's only group: CSR := carry + own (upper + mirror)
+    R_CARRY_PART, // last tile of a group of a shared slot: partial := carry + own
+    R_PART,       // partial := own (uncarried group, or a single tile of a shared slot)
+    R_CHUNKS,     // more entries than an output holds: partials of chunks of own
+};
+
+struct Group {
+    int32_t chain, t_first, t_last, carry;  // carry index or -1
+};
+
+}  // namespace
+
 qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, const int32_t *conn,
-                           const double *coords, const HostPlan &hp, int T, bool pair_units, TilePlan &tp)
+                           const double *coords, const HostPlan &hp, const TileParams &prm, TilePlan &tp)
 {
     const int np = n_local(dim, order), ns = n_sym(np);
-    if (int64_t(T + 1) * ns >= 0xffff) return fail(QXA_E_UNSUPPORTED, "tile too large for 16-bit LDS indices");
+    const int T = prm.T;
+    if (int64_t(T) * ns >= 0xffff) return fail(QXA_E_UNSUPPORTED, "tile too large for 16-bit LDS indices");
+    tp = TilePlan{};
     tp.T = T;
     tp.n_tiles = (n_elem + T - 1) / T;
+    tp.carry_cap = std::max(0, std::min(prm.carry_cap, 0xffff - carry_base(ns, T)));
+    const int64_t nt = tp.n_tiles;
     // 1. Morton order of element centroids (vertices only: the map is affine)
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     for (int k = 0; k < dim; ++k)
@@ -58,8 +93,7 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
             lo[k] = std::min(lo[k], coords[size_t(k) * n_nodes + v]);
             hi[k] = std::max(hi[k], coords[size_t(k) * n_nodes + v]);
         }
-    const int bits = dim == 2 ? 21 : 21;
-    const double scale = double((1u << bits) - 1);
+    const double scale = double((1u << 21) - 1);
     std::vector<std::pair<uint64_t, int32_t>> key(n_elem);
     parallel_for(n_elem, [&](int64_t a, int64_t b) {
         for (int64_t e = a; e < b; ++e) {
@@ -86,10 +120,16 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
             for (int i = 0; i < np; ++i)
                 tp.tconn[size_t(i) * n_elem + p] = conn[size_t(i) * n_elem + tp.elem_order[p]];
     });
-    // 2. per tile: sorted (upper slot, local element, pair) triples
-    const int64_t nt = tp.n_tiles;
+    // 2. chains: nc balanced runs of consecutive tiles
+    const int64_t nc = nt == 0 ? 0 : std::max<int64_t>(1, std::min<int64_t>(nt, prm.chains));
+    tp.chain_ptr.assign(nc + 1, 0);
+    for (int64_t c = 1; c <= nc; ++c) tp.chain_ptr[c] = c * nt / nc;
+    std::vector<int32_t> chain_of(nt);
+    for (int64_t c = 0; c < nc; ++c)
+        for (int64_t t = tp.chain_ptr[c]; t < tp.chain_ptr[c + 1]; ++t) chain_of[t] = int32_t(c);
+    // 3. per tile: sorted (upper slot, plan order, LDS index) triples; the plan
+    //    order within a slot is ascending local element, then pair
     auto tile_entries = [&](int64_t t, std::vector<uint64_t> &buf) {
-        // key = slot (32 bits) | lds index (16 bits): lds index = s*T + local element
         buf.clear();
         const int64_t p0 = t * T, p1 = std::min<int64_t>(n_elem, p0 + T);
         for (int64_t p = p0; p < p1; ++p) {
@@ -97,148 +137,318 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
             for (int s = 0; s < ns; ++s) {
                 const uint64_t slot = hp.perm_sym[size_t(s) * n_elem + e];
                 const uint64_t lds = uint64_t(s) * (T + 1) + uint64_t(p - p0);
-                // order within a slot: ascending local element, then pair
                 const uint64_t ord = uint64_t(p - p0) * ns + s;
                 buf.push_back((slot << 32) | (ord << 16) | lds);
             }
         }
         std::sort(buf.begin(), buf.end());
     };
-    // Records hold at most 6 contributions. A slot is owned by a tile when
-    // that tile alone touches it with at most 6 contributions; otherwise
-    // (several tiles, or more than 6 contributions in one tile) every tile
-    // touching it writes ceil(k / 6) partials of its k contributions, and the
-    // fix-up sums them.
-    auto chunks = [](size_t k) { return uint32_t((k + 5) / 6); };
-    std::vector<std::atomic<uint32_t>> touch(hp.nnz), npart(hp.nnz);
-    std::vector<std::atomic<uint8_t>> big(hp.nnz);
-    for (int64_t u = 0; u < hp.nnz; ++u) {
-        touch[u].store(0, std::memory_order_relaxed);
-        npart[u].store(0, std::memory_order_relaxed);
-        big[u].store(0, std::memory_order_relaxed);
-    }
+    // 4. number of tiles touching every upper slot; slots with more own
+    //    entries in one tile than a unit holds are chunked
+    const int64_t nnz = hp.nnz;
+    std::vector<std::atomic<int32_t>> ntouch(nnz);
+    std::vector<std::atomic<uint8_t>> big(nnz), full(nnz);  // > kUnitEntries own entries in a tile; exactly
+    parallel_for(nnz, [&](int64_t a, int64_t b) {
+        for (int64_t u = a; u < b; ++u) {
+            ntouch[u].store(0, std::memory_order_relaxed);
+            big[u].store(0, std::memory_order_relaxed);
+            full[u].store(0, std::memory_order_relaxed);
+        }
+    });
+
     parallel_for(nt, [&](int64_t a, int64_t b) {
         std::vector<uint64_t> buf;
         for (int64_t t = a; t < b; ++t) {
             tile_entries(t, buf);
-            size_t k = 0;
-            while (k < buf.size()) {
+            for (size_t k = 0; k < buf.size();) {
                 const uint32_t u = uint32_t(buf[k] >> 32);
                 size_t k1 = k;
                 while (k1 < buf.size() && uint32_t(buf[k1] >> 32) == u) ++k1;
-                touch[u].fetch_add(1, std::memory_order_relaxed);
-                npart[u].fetch_add(chunks(k1 - k), std::memory_order_relaxed);
-                if (k1 - k > 6) big[u].store(1, std::memory_order_relaxed);
+                ntouch[u].fetch_add(1, std::memory_order_relaxed);
+                if (int(k1 - k) > kUnitEntries) big[u].store(1, std::memory_order_relaxed);
+                if (int(k1 - k) == kUnitEntries) full[u].store(1, std::memory_order_relaxed);
                 k = k1;
             }
         }
     });
-    // shared slots in CSR order; partials numbered by (slot, tile, chunk)
-    std::vector<int32_t> sh_id(hp.nnz, -1);
-    std::vector<uint32_t> sh_slot;
-    tp.part_ptr.assign(1, 0);
-    for (int64_t u = 0; u < hp.nnz; ++u)
-        if (touch[u].load() > 1 || big[u].load()) {
-            sh_id[u] = int32_t(sh_slot.size());
-            sh_slot.push_back(uint32_t(u));
-            tp.part_ptr.push_back(tp.part_ptr.back() + int64_t(npart[u].load()));
+    // 5. multi-tile slots: their touching tiles, sorted, and their chain groups
+    std::vector<int32_t> multi_id(nnz, -1);
+    std::vector<int64_t> mptr(1, 0);
+    std::vector<uint32_t> mslot;
+    for (int64_t u = 0; u < nnz; ++u)
+        if (ntouch[u].load() > 1 && !big[u].load()) {
+            multi_id[u] = int32_t(mslot.size());
+            mslot.push_back(uint32_t(u));
+            mptr.push_back(mptr.back() + ntouch[u].load());
         }
-    tp.n_shared = int64_t(sh_slot.size());
-    tp.n_partials = tp.part_ptr.back();
-    if (tp.n_partials >= (int64_t(1) << 31)) return fail(QXA_E_UNSUPPORTED, "too many partials");
-    // output units per tile: owned outputs (upper and mirror) sorted by CSR slot,
-    // then the tile's partials; a partial's index is fixed in a second,
-    // sequential pass over the tiles in ascending order
-    std::vector<std::vector<uint32_t>> trec(nt);
-    std::vector<int64_t> tshort(nt, 0);  // pair units at the start of each tile
-    std::vector<std::vector<std::pair<uint32_t, uint32_t>>> tpart(nt);  // (shared id, word of its target)
-    struct Out {
-        uint32_t tgt;  // CSR slot (owned) or shared id
-        bool shared;
-        int n;  // contributions
-        std::array<uint16_t, 6> c;
+    const int64_t nm = int64_t(mslot.size());
+    std::vector<int32_t> mtiles(mptr.back());
+    {
+        std::vector<std::atomic<int32_t>> cur(nm);
+        for (int64_t m = 0; m < nm; ++m) cur[m].store(0, std::memory_order_relaxed);
+        parallel_for(nt, [&](int64_t a, int64_t b) {
+            std::vector<uint64_t> buf;
+            for (int64_t t = a; t < b; ++t) {
+                tile_entries(t, buf);
+                for (size_t k = 0; k < buf.size();) {
+                    const uint32_t u = uint32_t(buf[k] >> 32);
+                    size_t k1 = k;
+                    while (k1 < buf.size() && uint32_t(buf[k1] >> 32) == u) ++k1;
+                    const int32_t m = multi_id[u];
+                    if (m >= 0) mtiles[mptr[m] + cur[m].fetch_add(1, std::memory_order_relaxed)] = int32_t(t);
+                    k = k1;
+                }
+            }
+        });
+    }
+    std::vector<int64_t> gptr(nm + 1, 0);
+    std::vector<Group> groups;
+    {
+        std::vector<int32_t> ngr(nm, 0);
+        parallel_for(nm, [&](int64_t a, int64_t b) {
+            for (int64_t m = a; m < b; ++m) {
+                std::sort(mtiles.begin() + mptr[m], mtiles.begin() + mptr[m + 1]);
+                int g = 1;
+                for (int64_t k = mptr[m] + 1; k < mptr[m + 1]; ++k) g += chain_of[mtiles[k]] != chain_of[mtiles[k - 1]];
+                ngr[m] = g;
+            }
+        });
+        for (int64_t m = 0; m < nm; ++m) gptr[m + 1] = gptr[m] + ngr[m];
+        groups.resize(gptr[nm]);
+        parallel_for(nm, [&](int64_t a, int64_t b) {
+            for (int64_t m = a; m < b; ++m) {
+                int64_t g = gptr[m];
+                for (int64_t k = mptr[m]; k < mptr[m + 1]; ++k) {
+                    const int32_t t = mtiles[k], c = chain_of[t];
+                    if (k == mptr[m] || c != chain_of[mtiles[k - 1]]) groups[g++] = Group{c, t, t, -1};
+                    else groups[g - 1].t_last = t;
+                }
+            }
+        });
+    }
+    // 6. carry entries, per chain in tile order: a group spanning tiles
+    //    t_first < t_last holds an entry from t_first to t_last; an entry read
+    //    (for the last time) in tile t is free again from tile t + 1. A group
+    //    that finds no free entry is not carried (one partial per tile).
+    // A slot with a tile holding as many entries as a unit has no room for a
+    // carry entry: its groups are not carried.
+    std::vector<std::vector<int64_t>> chain_groups(nc);  // group indices spanning > 1 tile
+    for (int64_t m = 0; m < nm; ++m)
+        if (!full[mslot[m]].load(std::memory_order_relaxed))
+            for (int64_t g = gptr[m]; g < gptr[m + 1]; ++g)
+                if (groups[g].t_first < groups[g].t_last) chain_groups[groups[g].chain].push_back(g);
+    std::vector<int32_t> chain_used(nc, 0);
+    parallel_for(nc, [&](int64_t a, int64_t b) {
+        for (int64_t c = a; c < b; ++c) {
+            auto &L = chain_groups[c];
+            std::sort(L.begin(), L.end(), [&](int64_t x, int64_t y) {
+                return groups[x].t_first != groups[y].t_first ? groups[x].t_first < groups[y].t_first : x < y;
+            });
+            std::priority_queue<int32_t, std::vector<int32_t>, std::greater<int32_t>> freeq;
+            for (int32_t k = 0; k < tp.carry_cap; ++k) freeq.push(k);
+            // live entries ordered by their last tile
+            std::priority_queue<std::pair<int32_t, int32_t>, std::vector<std::pair<int32_t, int32_t>>,
+                                std::greater<std::pair<int32_t, int32_t>>>
+                live;
+            int32_t used = 0;
+            for (int64_t g : L) {
+                Group &G = groups[g];
+                while (!live.empty() && live.top().first < G.t_first) {
+                    freeq.push(live.top().second);
+                    live.pop();
+                }
+                if (freeq.empty()) continue;
+                G.carry = freeq.top();
+                freeq.pop();
+                live.push({G.t_last, G.carry});
+                used = std::max<int32_t>(used, int32_t(live.size()));
+            }
+            chain_used[c] = used;
+        }
+    });
+    for (int64_t c = 0; c < nc; ++c) tp.carry_used = std::max(tp.carry_used, chain_used[c]);
+    // 7. shared slots (a partial at least) and their partial counts
+    auto role_of = [&](uint32_t u, int32_t t, int32_t &carry) -> Role {
+        carry = -1;
+        if (big[u].load(std::memory_order_relaxed)) return R_CHUNKS;
+        const int32_t m = multi_id[u];
+        if (m < 0) return R_OWNED;
+        const int32_t c = chain_of[t];
+        int64_t g = gptr[m];
+        while (groups[g].chain != c) ++g;
+        const Group &G = groups[g];
+        const bool single = gptr[m + 1] - gptr[m] == 1;
+        if (G.carry < 0) return R_PART;
+        carry = G.carry;
+        if (t == G.t_first) return R_CARRY_OUT;
+        if (t < G.t_last) return R_CARRY_MID;
+        return single ? R_CARRY_CSR : R_CARRY_PART;
     };
+    // partials of every shared slot: counted per tile, numbered in ascending
+    // tile order (then chunk order) by a sequential pass
+    std::vector<std::atomic<int32_t>> npart(nnz);
+    parallel_for(nnz, [&](int64_t a, int64_t b) {
+        for (int64_t u = a; u < b; ++u) npart[u].store(0, std::memory_order_relaxed);
+    });
+    std::vector<std::vector<std::pair<uint32_t, int32_t>>> tpart(nt);  // (slot, partials) per tile, slot order
     parallel_for(nt, [&](int64_t a, int64_t b) {
         std::vector<uint64_t> buf;
-        std::vector<Out> owned, shared, S, L;
         for (int64_t t = a; t < b; ++t) {
             tile_entries(t, buf);
-            owned.clear();
-            shared.clear();
-            size_t k = 0;
-            while (k < buf.size()) {
+            tpart[t].clear();
+            for (size_t k = 0; k < buf.size();) {
                 const uint32_t u = uint32_t(buf[k] >> 32);
                 size_t k1 = k;
                 while (k1 < buf.size() && uint32_t(buf[k1] >> 32) == u) ++k1;
-                for (size_t c0 = k; c0 < k1; c0 += 6) {
-                    Out o{0u, false, int(std::min(k1, c0 + 6) - c0), {}};
-                    o.c.fill(uint16_t(T));  // absent: the zero kept at (pair 0, column T)
-                    for (int q = 0; q < o.n; ++q) o.c[q] = uint16_t(buf[c0 + q] & 0xffff);
-                    if (sh_id[u] < 0) {
-                        o.tgt = u;
-                        owned.push_back(o);
-                        if (hp.mirror[u] != u) {
-                            o.tgt = hp.mirror[u];
-                            owned.push_back(o);
-                        }
-                    } else {
-                        o.tgt = uint32_t(sh_id[u]);
-                        o.shared = true;
-                        shared.push_back(o);
-                    }
+                int32_t carry;
+                const Role r = role_of(u, int32_t(t), carry);
+                int32_t n = 0;
+                if (r == R_PART || r == R_CARRY_PART) n = 1;
+                if (r == R_CHUNKS) n = int32_t((k1 - k + kUnitEntries - 1) / kUnitEntries);
+                if (n) {
+                    npart[u].fetch_add(n, std::memory_order_relaxed);
+                    tpart[t].push_back({u, n});
                 }
                 k = k1;
             }
-            std::sort(owned.begin(), owned.end(), [](const Out &x, const Out &y) { return x.tgt < y.tgt; });
-            // outputs with at most two contributions go two to a unit, the rest one
-            // to a unit; owned outputs before partials in each group
+        }
+    });
+    std::vector<int32_t> sh_id(nnz, -1);
+    std::vector<uint32_t> sh_slot;
+    tp.part_ptr.assign(1, 0);
+    for (int64_t u = 0; u < nnz; ++u)
+        if (npart[u].load() > 0) {
+            sh_id[u] = int32_t(sh_slot.size());
+            sh_slot.push_back(uint32_t(u));
+            tp.part_ptr.push_back(tp.part_ptr.back() + npart[u].load());
+        }
+    tp.n_shared = int64_t(sh_slot.size());
+    tp.n_partials = tp.part_ptr.back();
+    if (tp.n_partials >= (int64_t(1) << 30)) return fail(QXA_E_UNSUPPORTED, "too many partials");
+    if (nnz >= (int64_t(1) << 30)) return fail(QXA_E_UNSUPPORTED, "more than 2^30 CSR slots");
+    // first partial index of every (tile, shared slot): ascending tile order
+    std::vector<std::vector<int32_t>> tpart_first(nt);
+    {
+        std::vector<int64_t> fill(tp.part_ptr.begin(), tp.part_ptr.end() - 1);
+        for (int64_t t = 0; t < nt; ++t) {
+            tpart_first[t].resize(tpart[t].size());
+            for (size_t k = 0; k < tpart[t].size(); ++k) {
+                const int32_t sid = sh_id[tpart[t][k].first];
+                tpart_first[t][k] = int32_t(fill[sid]);
+                fill[sid] += tpart[t][k].second;
+            }
+        }
+    }
+    tpart.clear();
+    tpart.shrink_to_fit();
+    // 8. outputs of every tile, packed into units
+    const uint32_t cb = uint32_t(carry_base(ns, T));
+    struct Out {
+        int32_t code;
+        uint8_t kind;   // 0 CSR, 1 carry, 2 partial
+        uint8_t n;      // entries (a carry entry included)
+        std::array<uint16_t, kUnitEntries> c;
+    };
+    std::vector<std::vector<uint32_t>> trec(nt);
+    std::vector<int64_t> tpairs(nt, 0), touts(nt, 0), tcin(nt, 0);
+    parallel_for(nt, [&](int64_t a, int64_t b) {
+        std::vector<uint64_t> buf;
+        std::vector<Out> outs, S, L;
+        for (int64_t t = a; t < b; ++t) {
+            tile_entries(t, buf);
+            outs.clear();
+            size_t kp = 0;  // next of this tile's partials (slot order)
+            auto add = [&](int32_t code, uint8_t kind, int32_t cin, const uint64_t *own, size_t n_own) {
+                Out o{code, kind, uint8_t(n_own + (cin >= 0)), {}};
+                o.c.fill(uint16_t(T));  // no entry: the zero kept at (pair 0, column T)
+                int q = 0;
+                if (cin >= 0) o.c[q++] = uint16_t(cb + uint32_t(cin));
+                for (size_t m = 0; m < n_own; ++m) o.c[q++] = uint16_t(own[m] & 0xffff);
+                outs.push_back(o);
+                tcin[t] += cin >= 0;
+            };
+            for (size_t k = 0; k < buf.size();) {
+                const uint32_t u = uint32_t(buf[k] >> 32);
+                size_t k1 = k;
+                while (k1 < buf.size() && uint32_t(buf[k1] >> 32) == u) ++k1;
+                int32_t carry;
+                const Role r = role_of(u, int32_t(t), carry);
+                const uint64_t *own = buf.data() + k;
+                const size_t n_own = k1 - k;
+                const int32_t mir = int32_t(hp.mirror[u]);
+                switch (r) {
+                case R_OWNED:
+                    add(int32_t(u), 0, -1, own, n_own);
+                    if (mir != int32_t(u)) add(mir, 0, -1, own, n_own);
+                    break;
+                case R_CARRY_OUT: add(kCodeCarry | carry, 1, -1, own, n_own); break;
+                case R_CARRY_MID: add(kCodeCarry | carry, 1, carry, own, n_own); break;
+                case R_CARRY_CSR:
+                    add(int32_t(u), 0, carry, own, n_own);
+                    if (mir != int32_t(u)) add(mir, 0, carry, own, n_own);
+                    break;
+                case R_CARRY_PART:
+                case R_PART: {
+                    const int32_t p = tpart_first[t][kp++];
+                    add(-p - 1, 2, r == R_CARRY_PART ? carry : -1, own, n_own);
+                    break;
+                }
+                case R_CHUNKS: {
+                    const int32_t p = tpart_first[t][kp++];
+                    for (size_t c0 = 0, j = 0; c0 < n_own; c0 += kUnitEntries, ++j)
+                        add(-(p + int32_t(j)) - 1, 2, -1, own + c0, std::min<size_t>(kUnitEntries, n_own - c0));
+                    break;
+                }
+                }
+                k = k1;
+            }
+            // CSR outputs, then carries, then partials (partials ascending: codes descending)
+            std::sort(outs.begin(), outs.end(), [](const Out &x, const Out &y) {
+                if (x.kind != y.kind) return x.kind < y.kind;
+                return x.kind == 2 ? x.code > y.code : x.code < y.code;
+            });
             S.clear();
             L.clear();
-            for (const auto *grp : {&owned, &shared})
-                for (const Out &o : *grp) (pair_units && o.n <= 2 ? S : L).push_back(o);
+            for (const Out &o : outs) (prm.pair_units && o.n <= kPairEntries ? S : L).push_back(o);
             if (S.size() % 2) {
                 L.insert(L.begin(), S.back());
                 S.pop_back();
             }
             auto &R = trec[t];
             R.clear();
-            tpart[t].clear();
             const size_t us = S.size() / 2;
-            tshort[t] = int64_t(us);
-            auto target = [&](const Out &o) {
-                if (o.shared) tpart[t].push_back({o.tgt, uint32_t(R.size())});
-                return o.shared ? 0u : o.tgt;
-            };
+            tpairs[t] = int64_t(us);
+            touts[t] = int64_t(outs.size());
             auto pack = [](const Out &o, int q) { return uint32_t(o.c[q]) | (uint32_t(o.c[q + 1]) << 16); };
             // unit l: outputs l and l + us, so that each store of a round covers consecutive outputs
             for (size_t l = 0; l < us; ++l) {
-                R.push_back(target(S[l]));
+                R.push_back(uint32_t(S[l].code));
                 R.push_back(pack(S[l], 0));
-                R.push_back(target(S[l + us]));
+                R.push_back(uint32_t(S[l + us].code));
                 R.push_back(pack(S[l + us], 0));
             }
             for (const Out &o : L) {
-                R.push_back(target(o));
+                R.push_back(uint32_t(o.code));
                 R.push_back(pack(o, 0));
                 R.push_back(pack(o, 2));
                 R.push_back(pack(o, 4));
             }
         }
     });
-    {
-        std::vector<int64_t> fill(tp.part_ptr.begin(), tp.part_ptr.end() - 1);
-        for (int64_t t = 0; t < nt; ++t)
-            for (auto &pr : tpart[t]) trec[t][pr.second] = uint32_t(-(fill[pr.first]++) - 1);
-    }
     tp.rec_ptr.assign(nt + 1, 0);
     tp.rec_mid.assign(nt, 0);
     for (int64_t t = 0; t < nt; ++t) {
         tp.rec_ptr[t + 1] = tp.rec_ptr[t] + int64_t(trec[t].size() / 4);
-        tp.rec_mid[t] = tp.rec_ptr[t] + tshort[t];
+        tp.rec_mid[t] = tp.rec_ptr[t] + tpairs[t];
+        tp.n_outputs += touts[t];
+        tp.n_carry_reads += tcin[t];
     }
     tp.rec.resize(4 * size_t(tp.rec_ptr[nt]));
     parallel_for(nt, [&](int64_t a, int64_t b) {
-        for (int64_t t = a; t < b; ++t) std::copy(trec[t].begin(), trec[t].end(), tp.rec.begin() + 4 * tp.rec_ptr[t]);
+        for (int64_t t = a; t < b; ++t) {
+            std::copy(trec[t].begin(), trec[t].end(), tp.rec.begin() + 4 * tp.rec_ptr[t]);
+            std::vector<uint32_t>().swap(trec[t]);
+        }
     });
     // fix-up: every shared upper slot (CSR order) and its mirror
     tp.fix_target.resize(sh_slot.size());
@@ -250,83 +460,179 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
     return QXA_OK;
 }
 
-}  // namespace qxa
-
-namespace qxa {
-
-// Structural check of a tile plan against the pattern: every index the fused
-// and fix-up kernels use is in bounds, every CSR slot is written exactly once
-// (by one tile or by the fix-up), every partial is written by exactly one tile
-// and summed by exactly one shared slot, and every element entry is reduced
-// exactly once. Runs on the host before the plan is used.
+// Check of a tile plan against the pattern, by executing it on the host with
+// exact integer sums: every element entry gets a pseudo-random 64-bit value;
+// the tiles of each chain are reduced in order as the kernels reduce them
+// (decoding the units as they do), carries in a per-chain array, partials
+// written once and summed by the fix-up; the result must equal the sums of
+// the element entries of every slot through the element-entry -> slot map,
+// on both triangles. It also checks every index the kernels use, that each
+// CSR slot and partial is written exactly once, and that within a tile a
+// carry entry written by an output is read by no other output, and is read
+// only after an earlier tile of the same chain wrote it.
 qxa_status check_tile_plan(int np, int64_t n_elem, const HostPlan &hp, const TilePlan &tp)
 {
     const int ns = n_sym(np);
-    const int64_t T = tp.T, TP = T + 1;
-    std::vector<uint8_t> slot_w(hp.nnz, 0), part_w(tp.n_partials, 0), used;
-    if (int64_t(tp.rec_ptr.size()) != tp.n_tiles + 1 || tp.rec_ptr[0] != 0 ||
-        int64_t(tp.rec_mid.size()) != tp.n_tiles ||
-        int64_t(tp.rec.size()) != 4 * tp.rec_ptr[tp.n_tiles] || int64_t(tp.part_ptr.size()) != tp.n_shared + 1 ||
-        tp.part_ptr[0] != 0 || tp.part_ptr[tp.n_shared] != tp.n_partials)
+    const int64_t T = tp.T, TP = T + 1, nt = tp.n_tiles, nnz = hp.nnz;
+    const uint32_t cb = uint32_t(carry_base(ns, int(T)));
+    const int64_t nc = int64_t(tp.chain_ptr.size()) - 1;
+    if (nt > 0 && (nc < 1 || tp.chain_ptr[0] != 0 || tp.chain_ptr[nc] != nt))
+        return fail(QXA_E_INVALID, "tile plan: bad chains");
+    for (int64_t c = 0; c < nc; ++c)
+        if (tp.chain_ptr[c + 1] <= tp.chain_ptr[c]) return fail(QXA_E_INVALID, "tile plan: empty chain");
+    if (int64_t(tp.rec_ptr.size()) != nt + 1 || tp.rec_ptr[0] != 0 || int64_t(tp.rec_mid.size()) != nt ||
+        int64_t(tp.rec.size()) != 4 * tp.rec_ptr[nt] || int64_t(tp.part_ptr.size()) != tp.n_shared + 1 ||
+        tp.part_ptr[0] != 0 || tp.part_ptr[tp.n_shared] != tp.n_partials ||
+        int64_t(tp.fix_target.size()) != tp.n_shared || int64_t(tp.fix_mirror.size()) != tp.n_shared ||
+        tp.carry_used > tp.carry_cap || int64_t(cb) + tp.carry_cap > 0xffff)
         return fail(QXA_E_INVALID, "tile plan: bad sizes");
-    auto write_slot = [&](int64_t g) -> bool { return g >= 0 && g < hp.nnz && slot_w[g]++ == 0; };
-    for (int64_t t = 0; t < tp.n_tiles; ++t) {
-        const int64_t p0 = t * T, nloc = std::min<int64_t>(T, n_elem - p0);
-        used.assign(size_t(TP) * ns, 0);
-        if (tp.rec_mid[t] < tp.rec_ptr[t] || tp.rec_mid[t] > tp.rec_ptr[t + 1])
-            return fail(QXA_E_INVALID, "tile plan: bad pair-unit range");
-        // one output: target g and nc contribution indices
-        auto check_out = [&](int32_t g, const uint32_t *c, int nc) -> qxa_status {
-            int n = 0;
-            for (int q = 0; q < nc; ++q) {
-                if (c[q] == uint32_t(T)) continue;  // absent
-                if (c[q] >= uint32_t(TP * ns) || int64_t(c[q] % TP) >= nloc)
-                    return fail(QXA_E_INVALID, "tile plan: LDS index out of range");
-                used[c[q]] = 1;
-                ++n;
-            }
-            if (n == 0) return fail(QXA_E_INVALID, "tile plan: empty record");
-            if (g >= 0) {
-                if (!write_slot(g)) return fail(QXA_E_INVALID, "tile plan: slot written twice");
-            } else {
-                const int64_t pi = -int64_t(g) - 1;
-                if (pi >= tp.n_partials || part_w[pi]++) return fail(QXA_E_INVALID, "tile plan: partial written twice");
-            }
-            return QXA_OK;
-        };
-        for (int64_t r = tp.rec_ptr[t]; r < tp.rec_ptr[t + 1]; ++r) {
-            const uint32_t *R = &tp.rec[4 * r];
-            qxa_status st;
-            if (r < tp.rec_mid[t]) {  // two outputs of at most two contributions
-                const uint32_t a[2] = {R[1] & 0xffffu, R[1] >> 16}, b[2] = {R[3] & 0xffffu, R[3] >> 16};
-                st = check_out(int32_t(R[0]), a, 2);
-                if (!st) st = check_out(int32_t(R[2]), b, 2);
-            } else {
-                const uint32_t c[6] = {R[1] & 0xffffu, R[1] >> 16, R[2] & 0xffffu, R[2] >> 16, R[3] & 0xffffu, R[3] >> 16};
-                st = check_out(int32_t(R[0]), c, 6);
-            }
-            if (st) return st;
+    auto value = [](uint64_t s, uint64_t e) {
+        uint64_t x = (s << 40) ^ (e * 0x9E3779B97F4A7C15ull) ^ 0xD1B54A32D192ED03ull;
+        x ^= x >> 31;
+        x *= 0xBF58476D1CE4E5B9ull;
+        x ^= x >> 29;
+        return x;
+    };
+    std::vector<uint64_t> expect(nnz, 0), got(nnz, 0), part(tp.n_partials, 0);
+    std::vector<uint8_t> is_up(nnz, 0);
+    for (int64_t e = 0; e < n_elem; ++e)
+        for (int s = 0; s < ns; ++s) {
+            const uint32_t u = hp.perm_sym[size_t(s) * n_elem + e];
+            expect[u] += value(s, e);
+            is_up[u] = 1;
         }
-        for (int64_t k = 0; k < nloc; ++k)
-            for (int s = 0; s < ns; ++s)
-                if (!used[size_t(s) * TP + k]) return fail(QXA_E_INVALID, "tile plan: contribution never reduced");
-    }
-    for (int64_t k = 0; k < tp.n_shared; ++k)
-        if (tp.part_ptr[k + 1] - tp.part_ptr[k] < 2) return fail(QXA_E_INVALID, "tile plan: shared slot with < 2 partials");
-    if (int64_t(tp.fix_target.size()) != tp.n_shared || int64_t(tp.fix_mirror.size()) != tp.n_shared)
-        return fail(QXA_E_INVALID, "tile plan: bad fix-up sizes");
+    std::atomic<int> bad{0};
+    std::string why;
+    std::mutex why_mu;
+    auto flag = [&](const char *msg) {
+        std::lock_guard<std::mutex> lk(why_mu);
+        if (!bad.exchange(1)) why = msg;
+    };
+    std::vector<std::atomic<uint8_t>> slot_ws(nnz);
+    for (int64_t u = 0; u < nnz; ++u) slot_ws[u].store(0, std::memory_order_relaxed);
+    std::vector<std::atomic<uint8_t>> part_ws(tp.n_partials);
+    for (int64_t k = 0; k < tp.n_partials; ++k) part_ws[k].store(0, std::memory_order_relaxed);
+    // chains are independent: their CSR slots, partials and carries are disjoint
+    parallel_for(nc, [&](int64_t ca, int64_t cbd) {
+        const size_t cap = size_t(std::max(1, tp.carry_cap));
+        std::vector<uint64_t> carry(cap, 0);
+        std::vector<int64_t> wtile(cap), stamp(cap);    // tile of the last write; tile of the marks below
+        std::vector<int64_t> writer(cap), reader(cap);  // this tile's writer / reader output (-2: several readers)
+        for (int64_t c = ca; c < cbd && !bad.load(); ++c) {
+            std::fill(wtile.begin(), wtile.end(), -1);
+            std::fill(stamp.begin(), stamp.end(), -1);
+            for (int64_t t = tp.chain_ptr[c]; t < tp.chain_ptr[c + 1] && !bad.load(); ++t) {
+                const int64_t p0 = t * T, nloc = std::min<int64_t>(T, n_elem - p0);
+                if (tp.rec_mid[t] < tp.rec_ptr[t] || tp.rec_mid[t] > tp.rec_ptr[t + 1]) {
+                    flag("tile plan: bad pair-unit range");
+                    return;
+                }
+                auto mark = [&](uint32_t k) {
+                    if (stamp[k] != t) {
+                        stamp[k] = t;
+                        writer[k] = reader[k] = -1;
+                    }
+                };
+                // one output: code and entries, as a kernel lane reduces it
+                auto output = [&](int64_t oid, int32_t code, const uint32_t *c, int n) -> bool {
+                    uint64_t acc = 0;
+                    int used = 0;
+                    for (int q = 0; q < n; ++q) {
+                        const uint32_t v = c[q];
+                        if (v == uint32_t(T)) continue;
+                        ++used;
+                        if (v >= cb) {
+                            const uint32_t k = v - cb;
+                            if (q != 0 || int(k) >= tp.carry_cap || wtile[k] < 0 || wtile[k] >= t) {
+                                flag("tile plan: bad carry read");
+                                return false;
+                            }
+                            mark(k);
+                            if (writer[k] >= 0 && writer[k] != oid) {
+                                flag("tile plan: carry read and written by different outputs of a tile");
+                                return false;
+                            }
+                            reader[k] = reader[k] == -1 ? oid : -2;
+                            acc += carry[k];
+                            continue;
+                        }
+                        if (int64_t(v % TP) >= nloc || v / TP >= uint32_t(ns)) {
+                            flag("tile plan: LDS index out of range");
+                            return false;
+                        }
+                        acc += value(v / TP, tp.elem_order[p0 + v % TP]);
+                    }
+                    if (used == 0) {
+                        flag("tile plan: empty output");
+                        return false;
+                    }
+                    if (code >= 0 && code < kCodeCarry) {
+                        if (code >= nnz || slot_ws[code].fetch_add(1) != 0) {
+                            flag("tile plan: CSR slot written twice or out of range");
+                            return false;
+                        }
+                        got[code] = acc;
+                    } else if (code >= kCodeCarry) {
+                        const uint32_t k = uint32_t(code - kCodeCarry);
+                        if (int(k) >= tp.carry_cap) {
+                            flag("tile plan: carry index out of range");
+                            return false;
+                        }
+                        mark(k);
+                        if (writer[k] != -1 || (reader[k] != -1 && reader[k] != oid)) {
+                            flag("tile plan: carry written twice, or read by another output, in a tile");
+                            return false;
+                        }
+                        writer[k] = oid;
+                        carry[k] = acc;
+                        wtile[k] = t;
+                    } else {
+                        const int64_t pi = -int64_t(code) - 1;
+                        if (pi >= tp.n_partials || part_ws[pi].fetch_add(1) != 0) {
+                            flag("tile plan: partial written twice or out of range");
+                            return false;
+                        }
+                        part[pi] = acc;
+                    }
+                    return true;
+                };
+                for (int64_t r = tp.rec_ptr[t]; r < tp.rec_ptr[t + 1]; ++r) {
+                    const uint32_t *R = &tp.rec[4 * r];
+                    if (r < tp.rec_mid[t]) {
+                        const uint32_t a[2] = {R[1] & 0xffffu, R[1] >> 16}, b2[2] = {R[3] & 0xffffu, R[3] >> 16};
+                        if (!output(2 * r, int32_t(R[0]), a, 2) || !output(2 * r + 1, int32_t(R[2]), b2, 2)) return;
+                    } else {
+                        const uint32_t e6[6] = {R[1] & 0xffffu, R[1] >> 16, R[2] & 0xffffu,
+                                                R[2] >> 16,     R[3] & 0xffffu, R[3] >> 16};
+                        if (!output(2 * r, int32_t(R[0]), e6, 6)) return;
+                    }
+                }
+            }
+        }
+    });
+    if (bad.load()) return fail(QXA_E_INVALID, why);
+    for (int64_t k = 0; k < tp.n_partials; ++k)
+        if (part_ws[k].load() != 1) return fail(QXA_E_INVALID, "tile plan: partial not written exactly once");
     for (int64_t k = 0; k < tp.n_shared; ++k) {
         const int32_t u = tp.fix_target[k], m = tp.fix_mirror[k];
         if (k > 0 && u <= tp.fix_target[k - 1]) return fail(QXA_E_INVALID, "tile plan: fix-up not sorted");
-        if (u < 0 || u >= hp.nnz || m < 0 || m >= hp.nnz || hp.mirror[u] != uint32_t(m))
+        if (u < 0 || u >= nnz || m < 0 || m >= nnz || hp.mirror[u] != uint32_t(m))
             return fail(QXA_E_INVALID, "tile plan: bad fix-up slot");
-        if (!write_slot(u)) return fail(QXA_E_INVALID, "tile plan: fix-up slot written twice");
-        if (m != u && !write_slot(m)) return fail(QXA_E_INVALID, "tile plan: fix-up mirror written twice");
+        if (tp.part_ptr[k + 1] <= tp.part_ptr[k]) return fail(QXA_E_INVALID, "tile plan: shared slot without partials");
+        uint64_t acc = 0;
+        for (int64_t q = tp.part_ptr[k]; q < tp.part_ptr[k + 1]; ++q) acc += part[q];
+        if (slot_ws[u].fetch_add(1) != 0) return fail(QXA_E_INVALID, "tile plan: fix-up slot written twice");
+        got[u] = acc;
+        if (m != u) {
+            if (slot_ws[m].fetch_add(1) != 0) return fail(QXA_E_INVALID, "tile plan: fix-up mirror written twice");
+            got[m] = acc;
+        }
     }
-    for (int64_t k = 0; k < tp.n_partials; ++k)
-        if (part_w[k] != 1) return fail(QXA_E_INVALID, "tile plan: partial not written exactly once");
-    for (int64_t t = 0; t < hp.nnz; ++t)
-        if (slot_w[t] != 1) return fail(QXA_E_INVALID, "tile plan: CSR slot not written exactly once");
+    for (int64_t u = 0; u < nnz; ++u) {
+        if (slot_ws[u].load() != 1) return fail(QXA_E_INVALID, "tile plan: CSR slot not written exactly once");
+        const uint64_t want = is_up[u] ? expect[u] : expect[hp.mirror[u]];
+        if (got[u] != want) return fail(QXA_E_INVALID, "tile plan: slot sum differs from the element entries");
+    }
     return QXA_OK;
 }
 

@@ -67,10 +67,34 @@ def test_host_pattern_empty_mesh():
 @pytest.mark.parametrize("dim,order,N", [(2, 1, 64), (2, 1, 7), (2, 2, 9), (2, 3, 5), (3, 1, 5), (3, 2, 3),
                                          (3, 3, 2), (3, 2, 32)])
 def test_tile_plan_selfcheck(dim, order, N):
-    """Fused-kernel plan: every index in bounds, every CSR slot written exactly once."""
+    """Fused-kernel plan executed on the host with exact integer sums: every CSR slot gets
+    exactly its element entries, every index is in bounds, every slot written once."""
     m = structured_mesh(dim, order, N, 0.2, seed=3)
-    nt, npart = qxa.plan_check_host(dim, order, m["coords"], m["conn"])
-    assert nt >= 1 and npart >= 0
+    nt, npart, ncr = qxa.plan_check_host(dim, order, m["coords"], m["conn"])
+    assert nt >= 1 and npart >= 0 and ncr >= 0
+
+
+@pytest.mark.parametrize("dim,order,N", [(2, 1, 40), (2, 2, 20), (2, 3, 24), (3, 1, 12), (3, 2, 8), (3, 3, 4)])
+@pytest.mark.parametrize("chains,cap", [(1, 4096), (3, 4096), (4, 64), (5, 3), (2, 0)])
+def test_tile_plan_carries(dim, order, N, chains, cap):
+    """Chains of tiles with LDS carry entries (plenty, few, one tile's worth, none): the
+    plan executes exactly on the host, slots touched by several tiles of a chain are
+    carried instead of being summed from partials, and a smaller carry budget only moves
+    slots back to partials."""
+    m = structured_mesh(dim, order, N, 0.2, seed=7)
+    nt, npart, ncr = qxa.plan_check_host(dim, order, m["coords"], m["conn"], chains=chains, carry_cap=cap)
+    nt1, npart1, ncr1 = qxa.plan_check_host(dim, order, m["coords"], m["conn"], chains=nt, carry_cap=cap)
+    assert ncr1 == 0                       # one tile per chain: nothing to carry
+    if cap == 0:
+        assert ncr == 0 and npart == npart1
+    elif nt > chains:
+        assert ncr > 0 and npart < npart1  # carries replace partials
+
+
+def test_tile_plan_of_a_mesh_without_elements():
+    m = structured_mesh(2, 2, 2, 0.0)
+    assert qxa.plan_check_host(2, 2, m["coords"], np.zeros((6, 0), dtype=np.int32)) == (0, 0, 0)
+    assert qxa.plan_check_host(2, 2, m["coords"], np.zeros((6, 0), dtype=np.int32), chains=4, carry_cap=8) == (0, 0, 0)
 
 
 def test_tile_plan_selfcheck_relabelled_and_shuffled():
@@ -81,6 +105,7 @@ def test_tile_plan_selfcheck_relabelled_and_shuffled():
     X = np.empty_like(m["coords"])
     X[:, sigma] = m["coords"]
     qxa.plan_check_host(3, 2, X, conn)
+    qxa.plan_check_host(3, 2, X, conn, chains=2, carry_cap=16)
 
 
 @pytest.mark.parametrize("dim", [2, 3])
