@@ -660,7 +660,8 @@ def main():
                    "n_partials": plan.n_partials, "n_outputs": plan.n_outputs, "n_units": plan.n_units,
                    "n_pair_units": plan.n_pair_units,
                    "n_chains": plan.n_chains, "n_carry_reads": plan.n_carry_reads, "carry_cap": plan.carry_cap,
-                   "carry_used": plan.carry_used, "n_fix_slots": plan.n_fix_slots},
+                   "carry_used": plan.carry_used, "n_fix_slots": plan.n_fix_slots,
+                   "n_ext_units": plan.n_ext_units},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(dom, w.name, args.precision), "kernel": dom,

@@ -142,6 +142,8 @@ typedef struct {
     int64_t n_chains;       /* chains of tiles (workgroups of one launch)           */
     int64_t n_carry_reads;  /* outputs that add an earlier tile's carried sum       */
     int64_t n_fix_slots;    /* CSR slots written by the fix-up (both triangles)     */
+    int64_t n_ext_units;    /* units of outputs of more than six entries, continued */
+    int64_t n_empty_units;  /* units that store nothing (holes of that layout)      */
     int carry_cap;          /* LDS carry entries per workgroup                      */
     int carry_used;         /* most carry entries live at once in a chain           */
 } qxa_plan_info;
@@ -197,11 +199,11 @@ qxa_status qxa_pattern_host(int dim, int order, int64_t n_nodes, int64_t n_elem,
  * entries are race-free within a tile. The same check runs inside
  * qxa_plan_create. chains <= 0 and carry_cap < 0 take the values a plan on
  * an MI355X gets (256 chains, the LDS left beside the kernel; the rules are
- * the built-in ones of degree 2*order). Optional outputs: tiles, partials,
- * outputs that read a carry entry. */
+ * the built-in ones of degree 2*order). `out` (optional) receives the
+ * figures qxa_plan_get_info reports, without the device fields (row_ptr and
+ * col_idx NULL, device_bytes and build_ms 0). */
 qxa_status qxa_plan_check_host(int dim, int order, int64_t n_nodes, const double *coords, int64_t n_elem,
-                               const int32_t *conn, int64_t chains, int carry_cap, int64_t *n_tiles,
-                               int64_t *n_partials, int64_t *n_carry_reads);
+                               const int32_t *conn, int64_t chains, int carry_cap, qxa_plan_info *out);
 
 /* Copy the CSR pattern into caller-owned device arrays row_ptr[n_nodes+1] and
  * col_idx[nnz] (either may be NULL), asynchronously on `stream`. */

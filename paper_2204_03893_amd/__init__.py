@@ -48,7 +48,11 @@ class _PlanInfo(C.Structure):
                 ("build_ms", C.c_double), ("n_tiles", C.c_int64), ("n_shared", C.c_int64),
                 ("n_partials", C.c_int64), ("n_outputs", C.c_int64), ("n_units", C.c_int64), ("n_pair_units", C.c_int64),
                 ("n_chains", C.c_int64), ("n_carry_reads", C.c_int64), ("n_fix_slots", C.c_int64),
-                ("carry_cap", C.c_int), ("carry_used", C.c_int)]
+                ("n_ext_units", C.c_int64), ("n_empty_units", C.c_int64), ("carry_cap", C.c_int), ("carry_used", C.c_int)]
+
+
+_TILE_FIELDS = ("nnz", "n_tiles", "n_shared", "n_partials", "n_outputs", "n_units", "n_pair_units", "n_chains",
+                "n_carry_reads", "n_fix_slots", "n_ext_units", "n_empty_units", "carry_cap", "carry_used")
 
 
 class _ServerOpts(C.Structure):
@@ -93,8 +97,7 @@ def lib():
         L.qxa_plan_copy_pattern.argtypes = [vp, vp, vp, vp]
         L.qxa_quad_builtin.argtypes = [C.c_int, C.c_int, C.POINTER(_Quad)]
         L.qxa_pattern_host.argtypes = [ci, ci, i64, i64, vp, vp, vp, C.POINTER(i64)]
-        L.qxa_plan_check_host.argtypes = [ci, ci, i64, vp, i64, vp, i64, ci, C.POINTER(i64), C.POINTER(i64),
-                                          C.POINTER(i64)]
+        L.qxa_plan_check_host.argtypes = [ci, ci, i64, vp, i64, vp, i64, ci, C.POINTER(_PlanInfo)]
         L.qxa_assemble.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), ci, vp, vp, vp]
         L.qxa_element_matrices.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), ci, vp, vp, vp]
         L.qxa_element_matrices_noalloc.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), ci, vp, vp, vp]
@@ -258,6 +261,8 @@ class Plan:
         self.n_chains = int(info.n_chains)
         self.n_carry_reads = int(info.n_carry_reads)
         self.n_fix_slots = int(info.n_fix_slots)
+        self.n_ext_units = int(info.n_ext_units)
+        self.n_empty_units = int(info.n_empty_units)
         self.carry_cap = int(info.carry_cap)
         self.carry_used = int(info.carry_used)
 
@@ -316,13 +321,13 @@ def pattern_host(dim, order, n_nodes, conn):
 
 def plan_check_host(dim, order, coords, conn, chains=0, carry_cap=-1):
     """Host-only plan build + check (the plan executed with exact integer sums);
-    returns (n_tiles, n_partials, n_carry_reads)."""
+    returns the plan's figures as a dict (the tile-plan fields of qxa_plan_info)."""
     X = np.ascontiguousarray(coords, dtype=np.float64)
     conn = np.ascontiguousarray(conn, dtype=np.int32)
-    nt, npart, ncr = C.c_int64(), C.c_int64(), C.c_int64()
+    info = _PlanInfo()
     check(lib().qxa_plan_check_host(dim, order, X.shape[1], X.ctypes.data, conn.shape[1], conn.ctypes.data,
-                                    int(chains), int(carry_cap), C.byref(nt), C.byref(npart), C.byref(ncr)))
-    return nt.value, npart.value, ncr.value
+                                    int(chains), int(carry_cap), C.byref(info)))
+    return {name: int(getattr(info, name)) for name in _TILE_FIELDS}
 
 
 def make_coeff(law, field=None, qpoint=False, tensor=None, tensor_q=None, sizes=None, name="coefficient"):

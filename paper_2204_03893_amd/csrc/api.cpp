@@ -464,15 +464,10 @@ qxa_status plan_upload(qxa_mesh mesh, const PlanStaging &g, DevArena *arena, boo
     p->n_shared = tp.n_shared;
     p->n_fix = int64_t(tp.fix_target.size());
     p->n_partials = tp.n_partials;
-    p->n_outputs = tp.n_outputs;
-    p->n_units = tp.rec_ptr.back();
-    for (int64_t t = 0; t < tp.n_tiles; ++t) p->n_pair_units += tp.rec_mid[t] - tp.rec_ptr[t];
     p->n_chains = int64_t(tp.chain_ptr.size()) - 1;
-    p->n_carry_reads = tp.n_carry_reads;
     p->carry_cap = tp.carry_cap;
-    p->carry_used = tp.carry_used;
     p->h_chain_ptr = tp.chain_ptr;
-    for (size_t k = 0; k < tp.fix_target.size(); ++k) p->n_fix_slots += tp.fix_mirror[k] != tp.fix_target[k] ? 2 : 1;
+    tile_plan_stats(tp, p->stats);
     qxa_status st = plan_upload_buf(p, &p->d_row_ptr, hp.row_ptr.data(), hp.row_ptr.size());
     if (!st) st = plan_upload_buf(p, &p->d_col_idx, hp.col_idx.data(), hp.col_idx.size());
     if (!st) st = plan_upload_buf(p, &p->d_tconn, tp.tconn.data(), tp.tconn.size());
@@ -541,6 +536,7 @@ qxa_status qxa_plan_create(qxa_mesh mesh, const qxa_quad *mr, const qxa_quad *cr
 qxa_status qxa_plan_get_info(qxa_plan p, qxa_plan_info *out)
 {
     if (!p || !out) return fail(QXA_E_INVALID, "null plan or out");
+    *out = p->stats;
     out->dim = p->ref.dim;
     out->order = p->ref.order;
     out->n_p = p->ref.np;
@@ -553,17 +549,6 @@ qxa_status qxa_plan_get_info(qxa_plan p, qxa_plan_info *out)
     out->col_idx = p->d_col_idx;
     out->device_bytes = p->device_bytes;
     out->build_ms = p->build_ms;
-    out->n_tiles = p->n_tiles;
-    out->n_shared = p->n_shared;
-    out->n_partials = p->n_partials;
-    out->n_outputs = p->n_outputs;
-    out->n_units = p->n_units;
-    out->n_pair_units = p->n_pair_units;
-    out->n_chains = p->n_chains;
-    out->n_carry_reads = p->n_carry_reads;
-    out->carry_cap = p->carry_cap;
-    out->carry_used = p->carry_used;
-    out->n_fix_slots = p->n_fix_slots;
     return QXA_OK;
 }
 
@@ -586,8 +571,7 @@ qxa_status qxa_pattern_host(int dim, int order, int64_t n_nodes, int64_t n_elem,
 }
 
 qxa_status qxa_plan_check_host(int dim, int order, int64_t n_nodes, const double *coords, int64_t n_elem,
-                               const int32_t *conn, int64_t chains, int carry_cap, int64_t *n_tiles,
-                               int64_t *n_partials, int64_t *n_carry_reads)
+                               const int32_t *conn, int64_t chains, int carry_cap, qxa_plan_info *out)
 {
     if (!coords || (n_elem > 0 && !conn)) return fail(QXA_E_INVALID, "null argument");
     if ((dim != 2 && dim != 3) || order < 1 || order > 3 || n_nodes < 1 || n_elem < 0)
@@ -615,9 +599,18 @@ qxa_status qxa_plan_check_host(int dim, int order, int64_t n_nodes, const double
     st = build_tile_plan(dim, order, n_nodes, n_elem, conn, coords, hp, prm, tp);
     if (!st) st = check_tile_plan(np, n_elem, hp, tp);
     if (st) return st;
-    if (n_tiles) *n_tiles = tp.n_tiles;
-    if (n_partials) *n_partials = tp.n_partials;
-    if (n_carry_reads) *n_carry_reads = tp.n_carry_reads;
+    if (out) {
+        *out = qxa_plan_info{};
+        out->dim = dim;
+        out->order = order;
+        out->n_p = np;
+        out->n_q_mass = T.nq_m;
+        out->n_q_stiff = T.nq_c;
+        out->n_nodes = n_nodes;
+        out->n_elem = n_elem;
+        out->nnz = hp.nnz;
+        tile_plan_stats(tp, *out);
+    }
     return QXA_OK;
 }
 

@@ -152,6 +152,24 @@ __device__ __forceinline__ void pair_sums(const uint4 U, const Entries<ST> &E, d
     acb = b0.y + b1.y;
 }
 
+// Outputs of several units (plan_format.hpp): lane l of the wave adds the sum
+// of lane l - d when lanes l - d .. l - 1 all continue into the next one
+// (their bits in `ext`), for d = 1, 2, ..., 32; each segment's last lane then
+// holds the segment's sum. Called by all lanes of a wave with ext != 0.
+__device__ __forceinline__ void ext_segment_sums(uint64_t ext, double &am, double &ac)
+{
+    const int l = __lane_id();
+#pragma unroll
+    for (int d = 1; d < kSegLanes; d <<= 1) {
+        const double tm = __shfl_up(am, d), tc = __shfl_up(ac, d);
+        const uint64_t run = (uint64_t(1) << d) - 1;
+        if (l >= d && ((ext >> (l - d)) & run) == run) {
+            am += tm;
+            ac += tc;
+        }
+    }
+}
+
 // Consumer threads (NCT of them, ct = 0 .. NCT - 1) of a workgroup: the units
 // of every tile of the walk. on_tile(k) is called before tile k of the walk is
 // reduced: it waits for (or stages) the tile's element matrices and returns
@@ -176,6 +194,7 @@ __device__ __forceinline__ void consume_units(const JobTable &jt, const TileWalk
         r0 = uniform_table(b.rec_ptr)[t];
         r1 = uniform_table(b.rec_ptr)[t + 1];
     };
+    static_assert(NCT % kSegLanes == 0, "rounds of whole waves");
     int64_t g = walk.t;
     {
         int64_t tile, r0, r1;
@@ -229,6 +248,8 @@ __device__ __forceinline__ void consume_units(const JobTable &jt, const TileWalk
                         unit_sums(active ? U : make_uint4(0u, none, none, none), E, ama, aca);
                     }
                 }
+                const uint64_t ext = __builtin_amdgcn_ballot_w64(active && !pair && ta == kCodeExt);
+                if (ext) ext_segment_sums(ext, ama, aca);  // (uniform)
                 const bool csra = active && ta >= 0 && ta < kCodeCarry, csrb = pair && tb >= 0 && tb < kCodeCarry;
                 if constexpr (BUF) {
                     const uint32_t drop = 0x80000000u;
@@ -252,9 +273,9 @@ __device__ __forceinline__ void consume_units(const JobTable &jt, const TileWalk
                 }
                 // carries and partials sit at the end of each group: branches (skipped by
                 // waves without one) add stores but never remove the ones above
-                if (active && ta >= kCodeCarry) carry[ta - kCodeCarry] = make_double2(ama, aca);
+                if (active && ta >= kCodeCarry && ta < kCodeCarryEnd) carry[ta - kCodeCarry] = make_double2(ama, aca);
                 if (active && ta < 0) part[-int64_t(ta) - 1] = make_double2(ama, aca);
-                if (pair && tb >= kCodeCarry) carry[tb - kCodeCarry] = make_double2(amb, acb);
+                if (pair && tb >= kCodeCarry && tb < kCodeCarryEnd) carry[tb - kCodeCarry] = make_double2(amb, acb);
                 if (pair && tb < 0) part[-int64_t(tb) - 1] = make_double2(amb, acb);
             }
 #pragma unroll
@@ -312,31 +333,36 @@ __global__ __launch_bounds__(T) void fused_kernel(JobTable jt)
     const Entries<double> E{reinterpret_cast<const double2 *>(sP), nullptr, 0xffffu, uint32_t(T)};
     double2 *part = reinterpret_cast<double2 *>(a.part);
     auto put = [&](int32_t t, double am, double ac) {
-        if (t >= 0) {
+        if (t >= 0 && t < kCodeCarry) {
             if (a.M) a.M[t] = am;
             if (a.C) a.C[t] = ac;
-        } else {
+        } else if (t < 0) {
             part[-int64_t(t) - 1] = make_double2(am, ac);
         }
     };
+    // unit k of this lane (k >= r1: none); called by whole waves, since an
+    // output of several units is summed across lanes
     auto reduce = [&](int64_t k, const uint4 U) {
-        if (k < rm) {
-            double ama, aca, amb, acb;
+        const bool act = k < r1, pr = act && k < rm;
+        double ama = 0.0, aca = 0.0, amb = 0.0, acb = 0.0;
+        if (pr)
             pair_sums(U, E, ama, aca, amb, acb);
+        else if (act)
+            unit_sums(U, E, ama, aca);
+        const uint64_t ext = __builtin_amdgcn_ballot_w64(act && !pr && int32_t(U.x) == kCodeExt);
+        if (ext) ext_segment_sums(ext, ama, aca);
+        if (act) {
             put(int32_t(U.x), ama, aca);
-            put(int32_t(U.z), amb, acb);
-        } else {
-            double am, ac;
-            unit_sums(U, E, am, ac);
-            put(int32_t(U.x), am, ac);
+            if (pr) put(int32_t(U.z), amb, acb);
         }
     };
+    static_assert(T % kSegLanes == 0, "rounds of whole waves");
+    const int64_t wb = r0 + (threadIdx.x & ~(kSegLanes - 1));  // this wave's first unit (uniform)
 #pragma unroll
-    for (int i = 0; i < kP1Prefetch; ++i) {
-        const int64_t k = r0 + threadIdx.x + int64_t(i) * T;
-        if (k < r1) reduce(k, pf[i]);
-    }
-    for (int64_t k0 = r0 + threadIdx.x + int64_t(kP1Prefetch) * T; k0 < r1; k0 += int64_t(kP1Prefetch) * T) {
+    for (int i = 0; i < kP1Prefetch; ++i)
+        if (wb + int64_t(i) * T < r1) reduce(r0 + threadIdx.x + int64_t(i) * T, pf[i]);
+    for (int64_t w0 = wb + int64_t(kP1Prefetch) * T; w0 < r1; w0 += int64_t(kP1Prefetch) * T) {
+        const int64_t k0 = w0 + (threadIdx.x & (kSegLanes - 1));
         uint4 U[kP1Prefetch];
 #pragma unroll
         for (int i = 0; i < kP1Prefetch; ++i) {
@@ -345,7 +371,7 @@ __global__ __launch_bounds__(T) void fused_kernel(JobTable jt)
         }
 #pragma unroll
         for (int i = 0; i < kP1Prefetch; ++i)
-            if (k0 + int64_t(i) * T < r1) reduce(k0 + int64_t(i) * T, U[i]);
+            if (w0 + int64_t(i) * T < r1) reduce(k0 + int64_t(i) * T, U[i]);
     }
 }
 
@@ -669,7 +695,6 @@ struct FormTraits<QXA_FP64> {
 // behind them in flight.
 // producer threads: 4 waves of one 16-element group each, or 8 waves for T = 16
 constexpr int ws_producers(int T) { return T == 16 ? 512 : 256; }
-// output rounds per consumer chunk (plan_format.hpp; at most 6)
 // unit rounds per consumer chunk, sized so that one chunk holds all of a
 // tile's output units on Kuhn meshes (the next tile's are then loaded a whole
 // tile ahead): 2D P2 up to ~790 units per 64-element tile on 512 consumer

@@ -14,8 +14,16 @@
 // output's first entry); v = T (pair 0 of the padding column, where the
 // kernels keep a zero) is no entry.
 //
-// Target codes (int32): 0 <= code < kCodeCarry a CSR slot; kCodeCarry | k
-// carry entry k; code < 0 partial -(code + 1).
+// An output of more than six entries takes k consecutive single units that
+// lie in one block of kSegLanes units of the tile (the units one wave reads in
+// one round): all but the last have the code kCodeExt, and the last one, with
+// the output's code, adds their sums to its own (a segmented sum across the
+// wave's lanes).
+//
+// Target codes (int32): 0 <= code < kCodeCarry a CSR slot; kCodeCarry + k,
+// k < 65536, carry entry k; kCodeExt: continued in the next unit;
+// kCodeNone: a unit with no entries that stores nothing; code < 0 partial
+// -(code + 1).
 #pragma once
 
 #include <cstdint>
@@ -23,6 +31,10 @@
 namespace qxa {
 
 constexpr int32_t kCodeCarry = 0x40000000;
+constexpr int32_t kCodeCarryEnd = kCodeCarry + 0x10000;
+constexpr int32_t kCodeExt = 0x7ffffffe;
+constexpr int32_t kCodeNone = 0x7fffffff;
+constexpr int kSegLanes = 64;
 constexpr int kUnitEntries = 6;  // entries of a single unit
 constexpr int kPairEntries = 2;  // entries of each output of a pair unit
 

@@ -114,11 +114,15 @@ struct TilePlan {
     int64_t n_partials = 0;
     int64_t n_outputs = 0;            // outputs of all tiles
     int64_t n_carry_reads = 0;        // outputs that read a carry entry
+    int64_t n_ext_units = 0;          // single units continued in the thread's next unit
+    int64_t n_empty_units = 0;        // units that store nothing (holes of that layout)
 };
 
 qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, const int32_t *conn,
                            const double *coords, const HostPlan &hp, const TileParams &prm, TilePlan &tp);
 qxa_status check_tile_plan(int np, int64_t n_elem, const HostPlan &hp, const TilePlan &tp);
+// The tile-plan figures of qxa_plan_info (n_tiles .. carry_used); other fields untouched.
+void tile_plan_stats(const TilePlan &tp, qxa_plan_info &o);
 
 // First-fit sub-allocator over one device allocation (256-byte granules,
 // free ranges coalesced). Thread-safe. Serves the server's resident plans and
@@ -189,10 +193,9 @@ struct qxa_plan_s {
     int32_t *d_col_idx = nullptr;
     // fused-path tile plan (device copies)
     int tile_T = 0;
-    int64_t n_tiles = 0, n_shared = 0, n_partials = 0, n_outputs = 0, n_units = 0, n_pair_units = 0, n_chains = 0,
-            n_carry_reads = 0;
-    int carry_cap = 0, carry_used = 0;
-    int64_t n_fix_slots = 0;  // CSR slots the fix-up writes (shared upper slots and their mirrors)
+    int64_t n_tiles = 0, n_shared = 0, n_partials = 0, n_chains = 0;
+    int carry_cap = 0;
+    qxa_plan_info stats{};  // tile-plan figures reported by qxa_plan_get_info
     int32_t *d_tconn = nullptr, *d_elem_order = nullptr;
     uint32_t *d_rec = nullptr;
     int64_t *d_rec_ptr = nullptr, *d_rec_mid = nullptr;

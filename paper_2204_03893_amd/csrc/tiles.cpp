@@ -66,7 +66,6 @@ enum Role : uint8_t {
     R_CARRY_CSR,  // last tile, the slot's only group: CSR := carry + own (upper + mirror)
     R_CARRY_PART, // last tile of a group of a shared slot: partial := carry + own
     R_PART,       // partial := own (uncarried group, or a single tile of a shared slot)
-    R_CHUNKS,     // more entries than an output holds: partials of chunks of own
 };
 
 struct Group {
@@ -143,16 +142,12 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
         }
         std::sort(buf.begin(), buf.end());
     };
-    // 4. number of tiles touching every upper slot; slots with more own
-    //    entries in one tile than a unit holds are chunked
+    // 4. number of tiles touching every upper slot
     const int64_t nnz = hp.nnz;
     std::vector<std::atomic<int32_t>> ntouch(nnz);
-    std::vector<std::atomic<uint8_t>> big(nnz), full(nnz);  // > kUnitEntries own entries in a tile; exactly
     parallel_for(nnz, [&](int64_t a, int64_t b) {
         for (int64_t u = a; u < b; ++u) {
             ntouch[u].store(0, std::memory_order_relaxed);
-            big[u].store(0, std::memory_order_relaxed);
-            full[u].store(0, std::memory_order_relaxed);
         }
     });
 
@@ -165,8 +160,6 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
                 size_t k1 = k;
                 while (k1 < buf.size() && uint32_t(buf[k1] >> 32) == u) ++k1;
                 ntouch[u].fetch_add(1, std::memory_order_relaxed);
-                if (int(k1 - k) > kUnitEntries) big[u].store(1, std::memory_order_relaxed);
-                if (int(k1 - k) == kUnitEntries) full[u].store(1, std::memory_order_relaxed);
                 k = k1;
             }
         }
@@ -176,7 +169,7 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
     std::vector<int64_t> mptr(1, 0);
     std::vector<uint32_t> mslot;
     for (int64_t u = 0; u < nnz; ++u)
-        if (ntouch[u].load() > 1 && !big[u].load()) {
+        if (ntouch[u].load() > 1) {
             multi_id[u] = int32_t(mslot.size());
             mslot.push_back(uint32_t(u));
             mptr.push_back(mptr.back() + ntouch[u].load());
@@ -230,13 +223,9 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
     //    t_first < t_last holds an entry from t_first to t_last; an entry read
     //    (for the last time) in tile t is free again from tile t + 1. A group
     //    that finds no free entry is not carried (one partial per tile).
-    // A slot with a tile holding as many entries as a unit has no room for a
-    // carry entry: its groups are not carried.
     std::vector<std::vector<int64_t>> chain_groups(nc);  // group indices spanning > 1 tile
-    for (int64_t m = 0; m < nm; ++m)
-        if (!full[mslot[m]].load(std::memory_order_relaxed))
-            for (int64_t g = gptr[m]; g < gptr[m + 1]; ++g)
-                if (groups[g].t_first < groups[g].t_last) chain_groups[groups[g].chain].push_back(g);
+    for (int64_t g = 0; g < int64_t(groups.size()); ++g)
+        if (groups[g].t_first < groups[g].t_last) chain_groups[groups[g].chain].push_back(g);
     std::vector<int32_t> chain_used(nc, 0);
     parallel_for(nc, [&](int64_t a, int64_t b) {
         for (int64_t c = a; c < b; ++c) {
@@ -270,7 +259,6 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
     // 7. shared slots (a partial at least) and their partial counts
     auto role_of = [&](uint32_t u, int32_t t, int32_t &carry) -> Role {
         carry = -1;
-        if (big[u].load(std::memory_order_relaxed)) return R_CHUNKS;
         const int32_t m = multi_id[u];
         if (m < 0) return R_OWNED;
         const int32_t c = chain_of[t];
@@ -304,7 +292,6 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
                 const Role r = role_of(u, int32_t(t), carry);
                 int32_t n = 0;
                 if (r == R_PART || r == R_CARRY_PART) n = 1;
-                if (r == R_CHUNKS) n = int32_t((k1 - k + kUnitEntries - 1) / kUnitEntries);
                 if (n) {
                     npart[u].fetch_add(n, std::memory_order_relaxed);
                     tpart[t].push_back({u, n});
@@ -341,30 +328,34 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
     }
     tpart.clear();
     tpart.shrink_to_fit();
-    // 8. outputs of every tile, packed into units
+    // 8. outputs of every tile, packed into units. An output of more than six
+    //    entries takes k consecutive single units in one block of kSegLanes
+    //    units: all but the last carry the code kCodeExt, and the last one
+    //    (which has the output's code) adds their sums to its own.
     const uint32_t cb = uint32_t(carry_base(ns, T));
     struct Out {
         int32_t code;
         uint8_t kind;   // 0 CSR, 1 carry, 2 partial
-        uint8_t n;      // entries (a carry entry included)
-        std::array<uint16_t, kUnitEntries> c;
+        uint32_t n;     // entries (a carry entry included)
+        uint32_t e0;    // first entry in the tile's entry list
     };
+    std::atomic<bool> too_long{false};
     std::vector<std::vector<uint32_t>> trec(nt);
-    std::vector<int64_t> tpairs(nt, 0), touts(nt, 0), tcin(nt, 0);
+    std::vector<int64_t> tpairs(nt, 0), touts(nt, 0), tcin(nt, 0), text(nt, 0), tnone(nt, 0);
     parallel_for(nt, [&](int64_t a, int64_t b) {
         std::vector<uint64_t> buf;
         std::vector<Out> outs, S, L;
+        std::vector<uint16_t> ents;
+        std::vector<const Out *> B, O;  // single outputs of several units, of one unit
         for (int64_t t = a; t < b; ++t) {
             tile_entries(t, buf);
             outs.clear();
+            ents.clear();
             size_t kp = 0;  // next of this tile's partials (slot order)
             auto add = [&](int32_t code, uint8_t kind, int32_t cin, const uint64_t *own, size_t n_own) {
-                Out o{code, kind, uint8_t(n_own + (cin >= 0)), {}};
-                o.c.fill(uint16_t(T));  // no entry: the zero kept at (pair 0, column T)
-                int q = 0;
-                if (cin >= 0) o.c[q++] = uint16_t(cb + uint32_t(cin));
-                for (size_t m = 0; m < n_own; ++m) o.c[q++] = uint16_t(own[m] & 0xffff);
-                outs.push_back(o);
+                outs.push_back(Out{code, kind, uint32_t(n_own + (cin >= 0)), uint32_t(ents.size())});
+                if (cin >= 0) ents.push_back(uint16_t(cb + uint32_t(cin)));
+                for (size_t m = 0; m < n_own; ++m) ents.push_back(uint16_t(own[m] & 0xffff));
                 tcin[t] += cin >= 0;
             };
             for (size_t k = 0; k < buf.size();) {
@@ -393,12 +384,6 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
                     add(-p - 1, 2, r == R_CARRY_PART ? carry : -1, own, n_own);
                     break;
                 }
-                case R_CHUNKS: {
-                    const int32_t p = tpart_first[t][kp++];
-                    for (size_t c0 = 0, j = 0; c0 < n_own; c0 += kUnitEntries, ++j)
-                        add(-(p + int32_t(j)) - 1, 2, -1, own + c0, std::min<size_t>(kUnitEntries, n_own - c0));
-                    break;
-                }
                 }
                 k = k1;
             }
@@ -419,7 +404,8 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
             const size_t us = S.size() / 2;
             tpairs[t] = int64_t(us);
             touts[t] = int64_t(outs.size());
-            auto pack = [](const Out &o, int q) { return uint32_t(o.c[q]) | (uint32_t(o.c[q + 1]) << 16); };
+            auto ent = [&](const Out &o, uint32_t q) { return q < o.n ? uint32_t(ents[o.e0 + q]) : uint32_t(T); };
+            auto pack = [&](const Out &o, uint32_t q) { return ent(o, q) | (ent(o, q + 1) << 16); };
             // unit l: outputs l and l + us, so that each store of a round covers consecutive outputs
             for (size_t l = 0; l < us; ++l) {
                 R.push_back(uint32_t(S[l].code));
@@ -427,14 +413,50 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
                 R.push_back(uint32_t(S[l + us].code));
                 R.push_back(pack(S[l + us], 0));
             }
-            for (const Out &o : L) {
-                R.push_back(uint32_t(o.code));
-                R.push_back(pack(o, 0));
-                R.push_back(pack(o, 2));
-                R.push_back(pack(o, 4));
+            // singles. An output of k > 1 units takes k consecutive units inside one
+            // block of kSegLanes units of the tile (one wave's units of a round);
+            // first fit, most units first, the one-unit outputs filling in between,
+            // so a hole (a unit that stores nothing) only pads a block when no
+            // one-unit output is left.
+            auto units_of = [](const Out &o) { return (o.n + kUnitEntries - 1) / kUnitEntries; };
+            B.clear();
+            O.clear();
+            for (const Out &o : L) (units_of(o) > 1 ? B : O).push_back(&o);
+            std::stable_sort(B.begin(), B.end(),
+                             [&](const Out *x, const Out *y) { return units_of(*x) > units_of(*y); });
+            size_t b0 = 0, oi = 0;  // first unplaced multi-unit output; next one-unit output
+            auto emit = [&](const Out &o) {
+                const uint32_t k = units_of(o);
+                if (k > uint32_t(kSegLanes)) too_long = true;  // more entries than a tile can hold
+                for (uint32_t m = 0; m < k; ++m) {
+                    R.push_back(uint32_t(m + 1 == k ? o.code : kCodeExt));
+                    R.push_back(pack(o, m * kUnitEntries));
+                    R.push_back(pack(o, m * kUnitEntries + 2));
+                    R.push_back(pack(o, m * kUnitEntries + 4));
+                }
+                text[t] += k - 1;
+            };
+            while (b0 < B.size() || oi < O.size()) {
+                const uint32_t room = kSegLanes - uint32_t((R.size() / 4) % kSegLanes);
+                size_t j = b0;
+                while (j < B.size() && (!B[j] || units_of(*B[j]) > room)) ++j;
+                if (j < B.size()) {
+                    emit(*B[j]);
+                    B[j] = nullptr;
+                    while (b0 < B.size() && !B[b0]) ++b0;
+                } else if (oi < O.size()) {
+                    emit(*O[oi++]);
+                } else {
+                    ++tnone[t];
+                    R.push_back(uint32_t(kCodeNone));
+                    R.push_back(uint32_t(T) | (uint32_t(T) << 16));
+                    R.push_back(uint32_t(T) | (uint32_t(T) << 16));
+                    R.push_back(uint32_t(T) | (uint32_t(T) << 16));
+                }
             }
         }
     });
+    if (too_long) return fail(QXA_E_INVALID, "tile plan: an output of more entries than one wave's units hold");
     tp.rec_ptr.assign(nt + 1, 0);
     tp.rec_mid.assign(nt, 0);
     for (int64_t t = 0; t < nt; ++t) {
@@ -442,6 +464,8 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
         tp.rec_mid[t] = tp.rec_ptr[t] + tpairs[t];
         tp.n_outputs += touts[t];
         tp.n_carry_reads += tcin[t];
+        tp.n_ext_units += text[t];
+        tp.n_empty_units += tnone[t];
     }
     tp.rec.resize(4 * size_t(tp.rec_ptr[nt]));
     parallel_for(nt, [&](int64_t a, int64_t b) {
@@ -533,9 +557,11 @@ qxa_status check_tile_plan(int np, int64_t n_elem, const HostPlan &hp, const Til
                         writer[k] = reader[k] = -1;
                     }
                 };
-                // one output: code and entries, as a kernel lane reduces it
-                auto output = [&](int64_t oid, int32_t code, const uint32_t *c, int n) -> bool {
-                    uint64_t acc = 0;
+                // one unit: code and entries, as a kernel lane reduces it; `pend` is the
+                // sum of the output's units before (kCodeExt), oid the output
+                auto output = [&](int64_t oid, int32_t code, const uint32_t *c, int n, uint64_t pend,
+                                  bool has_pend, uint64_t &acc) -> bool {
+                    acc = has_pend ? pend : 0;
                     int used = 0;
                     for (int q = 0; q < n; ++q) {
                         const uint32_t v = c[q];
@@ -543,7 +569,7 @@ qxa_status check_tile_plan(int np, int64_t n_elem, const HostPlan &hp, const Til
                         ++used;
                         if (v >= cb) {
                             const uint32_t k = v - cb;
-                            if (q != 0 || int(k) >= tp.carry_cap || wtile[k] < 0 || wtile[k] >= t) {
+                            if (q != 0 || has_pend || int(k) >= tp.carry_cap || wtile[k] < 0 || wtile[k] >= t) {
                                 flag("tile plan: bad carry read");
                                 return false;
                             }
@@ -562,17 +588,25 @@ qxa_status check_tile_plan(int np, int64_t n_elem, const HostPlan &hp, const Til
                         }
                         acc += value(v / TP, tp.elem_order[p0 + v % TP]);
                     }
-                    if (used == 0) {
+                    if (code == kCodeNone) {
+                        if (used || has_pend) {
+                            flag("tile plan: a no-op unit with entries");
+                            return false;
+                        }
+                        return true;
+                    }
+                    if (used == 0 && !has_pend) {
                         flag("tile plan: empty output");
                         return false;
                     }
+                    if (code == kCodeExt) return true;
                     if (code >= 0 && code < kCodeCarry) {
                         if (code >= nnz || slot_ws[code].fetch_add(1) != 0) {
                             flag("tile plan: CSR slot written twice or out of range");
                             return false;
                         }
                         got[code] = acc;
-                    } else if (code >= kCodeCarry) {
+                    } else if (code >= kCodeCarry && code < kCodeCarryEnd) {
                         const uint32_t k = uint32_t(code - kCodeCarry);
                         if (int(k) >= tp.carry_cap) {
                             flag("tile plan: carry index out of range");
@@ -586,30 +620,57 @@ qxa_status check_tile_plan(int np, int64_t n_elem, const HostPlan &hp, const Til
                         writer[k] = oid;
                         carry[k] = acc;
                         wtile[k] = t;
-                    } else {
+                    } else if (code < 0) {
                         const int64_t pi = -int64_t(code) - 1;
                         if (pi >= tp.n_partials || part_ws[pi].fetch_add(1) != 0) {
                             flag("tile plan: partial written twice or out of range");
                             return false;
                         }
                         part[pi] = acc;
+                    } else {
+                        flag("tile plan: bad target code");
+                        return false;
                     }
                     return true;
                 };
+                // an extended output: the sum of the units before, and their output id
+                bool has_pend = false;
+                uint64_t pend = 0;
+                int64_t pend_oid = 0;
                 for (int64_t r = tp.rec_ptr[t]; r < tp.rec_ptr[t + 1]; ++r) {
                     const uint32_t *R = &tp.rec[4 * r];
+                    uint64_t acc;
+                    if (has_pend && (r - tp.rec_ptr[t]) % kSegLanes == 0) {
+                        flag("tile plan: an extended output crosses a block of units");
+                        return;
+                    }
                     if (r < tp.rec_mid[t]) {
                         const uint32_t a[2] = {R[1] & 0xffffu, R[1] >> 16}, b2[2] = {R[3] & 0xffffu, R[3] >> 16};
-                        if (!output(2 * r, int32_t(R[0]), a, 2) || !output(2 * r + 1, int32_t(R[2]), b2, 2)) return;
+                        if (has_pend || int32_t(R[0]) == kCodeExt || int32_t(R[2]) == kCodeExt) {
+                            flag("tile plan: a pair unit continues or extends an output");
+                            return;
+                        }
+                        if (!output(2 * r, int32_t(R[0]), a, 2, 0, false, acc) ||
+                            !output(2 * r + 1, int32_t(R[2]), b2, 2, 0, false, acc))
+                            return;
                     } else {
                         const uint32_t e6[6] = {R[1] & 0xffffu, R[1] >> 16, R[2] & 0xffffu,
                                                 R[2] >> 16,     R[3] & 0xffffu, R[3] >> 16};
-                        if (!output(2 * r, int32_t(R[0]), e6, 6)) return;
+                        const int64_t oid = has_pend ? pend_oid : 2 * r;
+                        if (!output(oid, int32_t(R[0]), e6, 6, pend, has_pend, acc)) return;
+                        has_pend = int32_t(R[0]) == kCodeExt;
+                        pend = acc;
+                        pend_oid = oid;
                     }
+                }
+                if (has_pend) {
+                    flag("tile plan: an extended output without its last unit");
+                    return;
                 }
             }
         }
     });
+
     if (bad.load()) return fail(QXA_E_INVALID, why);
     for (int64_t k = 0; k < tp.n_partials; ++k)
         if (part_ws[k].load() != 1) return fail(QXA_E_INVALID, "tile plan: partial not written exactly once");
@@ -634,6 +695,25 @@ qxa_status check_tile_plan(int np, int64_t n_elem, const HostPlan &hp, const Til
         if (got[u] != want) return fail(QXA_E_INVALID, "tile plan: slot sum differs from the element entries");
     }
     return QXA_OK;
+}
+
+void tile_plan_stats(const TilePlan &tp, qxa_plan_info &o)
+{
+    o.n_tiles = tp.n_tiles;
+    o.n_shared = tp.n_shared;
+    o.n_partials = tp.n_partials;
+    o.n_outputs = tp.n_outputs;
+    o.n_units = tp.rec_ptr.empty() ? 0 : tp.rec_ptr.back();
+    o.n_pair_units = 0;
+    for (int64_t t = 0; t < tp.n_tiles; ++t) o.n_pair_units += tp.rec_mid[t] - tp.rec_ptr[t];
+    o.n_chains = tp.chain_ptr.empty() ? 0 : int64_t(tp.chain_ptr.size()) - 1;
+    o.n_carry_reads = tp.n_carry_reads;
+    o.n_fix_slots = 0;
+    for (size_t k = 0; k < tp.fix_target.size(); ++k) o.n_fix_slots += tp.fix_mirror[k] != tp.fix_target[k] ? 2 : 1;
+    o.n_ext_units = tp.n_ext_units;
+    o.n_empty_units = tp.n_empty_units;
+    o.carry_cap = tp.carry_cap;
+    o.carry_used = tp.carry_used;
 }
 
 }  // namespace qxa

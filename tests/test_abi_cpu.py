@@ -70,8 +70,11 @@ def test_tile_plan_selfcheck(dim, order, N):
     """Fused-kernel plan executed on the host with exact integer sums: every CSR slot gets
     exactly its element entries, every index is in bounds, every slot written once."""
     m = structured_mesh(dim, order, N, 0.2, seed=3)
-    nt, npart, ncr = qxa.plan_check_host(dim, order, m["coords"], m["conn"])
-    assert nt >= 1 and npart >= 0 and ncr >= 0
+    s = qxa.plan_check_host(dim, order, m["coords"], m["conn"])
+    assert s["n_tiles"] >= 1 and s["n_units"] >= s["n_pair_units"] and s["n_outputs"] >= 2 * s["n_pair_units"]
+    # every output is a pair half or ends one single unit
+    assert s["n_outputs"] == 2 * s["n_pair_units"] + s["n_units"] - s["n_pair_units"] - s["n_ext_units"] \
+        - s["n_empty_units"]
 
 
 @pytest.mark.parametrize("dim,order,N", [(2, 1, 40), (2, 2, 20), (2, 3, 24), (3, 1, 12), (3, 2, 8), (3, 3, 4)])
@@ -82,8 +85,10 @@ def test_tile_plan_carries(dim, order, N, chains, cap):
     carried instead of being summed from partials, and a smaller carry budget only moves
     slots back to partials."""
     m = structured_mesh(dim, order, N, 0.2, seed=7)
-    nt, npart, ncr = qxa.plan_check_host(dim, order, m["coords"], m["conn"], chains=chains, carry_cap=cap)
-    nt1, npart1, ncr1 = qxa.plan_check_host(dim, order, m["coords"], m["conn"], chains=nt, carry_cap=cap)
+    s = qxa.plan_check_host(dim, order, m["coords"], m["conn"], chains=chains, carry_cap=cap)
+    nt, npart, ncr = s["n_tiles"], s["n_partials"], s["n_carry_reads"]
+    s1 = qxa.plan_check_host(dim, order, m["coords"], m["conn"], chains=nt, carry_cap=cap)
+    npart1, ncr1 = s1["n_partials"], s1["n_carry_reads"]
     assert ncr1 == 0                       # one tile per chain: nothing to carry
     if cap == 0:
         assert ncr == 0 and npart == npart1
@@ -91,10 +96,24 @@ def test_tile_plan_carries(dim, order, N, chains, cap):
         assert ncr > 0 and npart < npart1  # carries replace partials
 
 
+@pytest.mark.parametrize("dim,order,N,chains,cap", [(3, 1, 12, 0, -1), (3, 2, 8, 0, -1), (3, 2, 8, 3, 4096),
+                                                    (2, 3, 24, 2, 4096), (2, 1, 40, 0, -1)])
+def test_tile_plan_extended_outputs(dim, order, N, chains, cap):
+    """Outputs of more than six entries (a vertex diagonal summed over the elements of a
+    tile that hold the vertex, plus a carried sum) run over several units of one thread;
+    the plan still executes exactly. Kuhn meshes in 3D put up to 24 tetrahedra around a
+    vertex, so such outputs must occur there."""
+    m = structured_mesh(dim, order, N, 0.2, seed=11)
+    s = qxa.plan_check_host(dim, order, m["coords"], m["conn"], chains=chains, carry_cap=cap)
+    if dim == 3:
+        assert s["n_ext_units"] > 0
+
+
 def test_tile_plan_of_a_mesh_without_elements():
     m = structured_mesh(2, 2, 2, 0.0)
-    assert qxa.plan_check_host(2, 2, m["coords"], np.zeros((6, 0), dtype=np.int32)) == (0, 0, 0)
-    assert qxa.plan_check_host(2, 2, m["coords"], np.zeros((6, 0), dtype=np.int32), chains=4, carry_cap=8) == (0, 0, 0)
+    for kw in ({}, {"chains": 4, "carry_cap": 8}):
+        s = qxa.plan_check_host(2, 2, m["coords"], np.zeros((6, 0), dtype=np.int32), **kw)
+        assert s["n_tiles"] == s["n_units"] == s["n_partials"] == s["nnz"] == 0
 
 
 def test_tile_plan_selfcheck_relabelled_and_shuffled():
