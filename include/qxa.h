@@ -146,6 +146,8 @@ typedef struct {
     int64_t n_empty_units;  /* units that store nothing (holes of that layout)      */
     int carry_cap;          /* LDS carry entries per workgroup                      */
     int carry_used;         /* most carry entries live at once in a chain           */
+    int n_q_mass_kernel;    /* rule sizes of the kernels that run the plan: the     */
+    int n_q_stiff_kernel;   /* caller's rules padded with zero-weight nodes         */
 } qxa_plan_info;
 
 const char *qxa_last_error(void);
@@ -198,12 +200,13 @@ qxa_status qxa_pattern_host(int dim, int order, int64_t n_nodes, int64_t n_elem,
  * use is in bounds, every CSR slot and partial is written once, and carry
  * entries are race-free within a tile. The same check runs inside
  * qxa_plan_create. chains <= 0 and carry_cap < 0 take the values a plan on
- * an MI355X gets (256 chains, the LDS left beside the kernel; the rules are
- * the built-in ones of degree 2*order). `out` (optional) receives the
- * figures qxa_plan_get_info reports, without the device fields (row_ptr and
- * col_idx NULL, device_bytes and build_ms 0). */
+ * an MI355X gets (256 chains, the LDS left beside the kernel). Null rules take the built-in one of
+ * degree 2*order; the rules are checked and padded as by qxa_plan_create.
+ * `out` (optional) receives the figures qxa_plan_get_info reports, without
+ * the device fields (row_ptr and col_idx NULL, device_bytes and build_ms 0). */
 qxa_status qxa_plan_check_host(int dim, int order, int64_t n_nodes, const double *coords, int64_t n_elem,
-                               const int32_t *conn, int64_t chains, int carry_cap, qxa_plan_info *out);
+                               const int32_t *conn, const qxa_quad *mass_rule, const qxa_quad *stiff_rule,
+                               int64_t chains, int carry_cap, qxa_plan_info *out);
 
 /* Copy the CSR pattern into caller-owned device arrays row_ptr[n_nodes+1] and
  * col_idx[nnz] (either may be NULL), asynchronously on `stream`. */

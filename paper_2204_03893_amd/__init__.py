@@ -48,11 +48,13 @@ class _PlanInfo(C.Structure):
                 ("build_ms", C.c_double), ("n_tiles", C.c_int64), ("n_shared", C.c_int64),
                 ("n_partials", C.c_int64), ("n_outputs", C.c_int64), ("n_units", C.c_int64), ("n_pair_units", C.c_int64),
                 ("n_chains", C.c_int64), ("n_carry_reads", C.c_int64), ("n_fix_slots", C.c_int64),
-                ("n_ext_units", C.c_int64), ("n_empty_units", C.c_int64), ("carry_cap", C.c_int), ("carry_used", C.c_int)]
+                ("n_ext_units", C.c_int64), ("n_empty_units", C.c_int64), ("carry_cap", C.c_int),
+                ("carry_used", C.c_int), ("n_q_mass_kernel", C.c_int), ("n_q_stiff_kernel", C.c_int)]
 
 
 _TILE_FIELDS = ("nnz", "n_tiles", "n_shared", "n_partials", "n_outputs", "n_units", "n_pair_units", "n_chains",
-                "n_carry_reads", "n_fix_slots", "n_ext_units", "n_empty_units", "carry_cap", "carry_used")
+                "n_carry_reads", "n_fix_slots", "n_ext_units", "n_empty_units", "carry_cap", "carry_used",
+                "n_q_mass", "n_q_stiff", "n_q_mass_kernel", "n_q_stiff_kernel")
 
 
 class _ServerOpts(C.Structure):
@@ -97,7 +99,8 @@ def lib():
         L.qxa_plan_copy_pattern.argtypes = [vp, vp, vp, vp]
         L.qxa_quad_builtin.argtypes = [C.c_int, C.c_int, C.POINTER(_Quad)]
         L.qxa_pattern_host.argtypes = [ci, ci, i64, i64, vp, vp, vp, C.POINTER(i64)]
-        L.qxa_plan_check_host.argtypes = [ci, ci, i64, vp, i64, vp, i64, ci, C.POINTER(_PlanInfo)]
+        L.qxa_plan_check_host.argtypes = [ci, ci, i64, vp, i64, vp, C.POINTER(_Quad), C.POINTER(_Quad), i64, ci,
+                                          C.POINTER(_PlanInfo)]
         L.qxa_assemble.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), ci, vp, vp, vp]
         L.qxa_element_matrices.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), ci, vp, vp, vp]
         L.qxa_element_matrices_noalloc.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), ci, vp, vp, vp]
@@ -319,13 +322,17 @@ def pattern_host(dim, order, n_nodes, conn):
     return rp, ci
 
 
-def plan_check_host(dim, order, coords, conn, chains=0, carry_cap=-1):
+def plan_check_host(dim, order, coords, conn, chains=0, carry_cap=-1, rule_m=None, rule_c=None):
     """Host-only plan build + check (the plan executed with exact integer sums);
-    returns the plan's figures as a dict (the tile-plan fields of qxa_plan_info)."""
+    returns the plan's figures as a dict (the tile-plan fields of qxa_plan_info and the
+    rule sizes). Rules default to the built-in one of degree 2 * order."""
     X = np.ascontiguousarray(coords, dtype=np.float64)
     conn = np.ascontiguousarray(conn, dtype=np.int32)
     info = _PlanInfo()
+    qm = _quad(rule_m, dim) if rule_m is not None else None
+    qc = _quad(rule_c, dim) if rule_c is not None else None
     check(lib().qxa_plan_check_host(dim, order, X.shape[1], X.ctypes.data, conn.shape[1], conn.ctypes.data,
+                                    C.byref(qm[0]) if qm else None, C.byref(qc[0]) if qc else None,
                                     int(chains), int(carry_cap), C.byref(info)))
     return {name: int(getattr(info, name)) for name in _TILE_FIELDS}
 

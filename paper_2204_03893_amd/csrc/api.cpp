@@ -86,11 +86,12 @@ static void plan_drop(qxa_plan p, T **...ptrs)
 }
 
 // n_nodes, n_elem: the field's length for the nodal and per-(q, e) kinds (a field of
-// zero length may be null).
-static qxa_status to_coeff(const qxa_coeff *c, CoeffDev &out, const char *which, int64_t n_nodes, int64_t n_elem)
+// zero length may be null); nq: the rows of a per-(q, e) field (the caller's rule).
+static qxa_status to_coeff(const qxa_coeff *c, CoeffDev &out, const char *which, int64_t n_nodes, int64_t n_elem,
+                           int nq)
 {
     if (!c) {
-        out = CoeffDev{0, 0, 0.0, 0.0, 0.0, 0.0, nullptr};
+        out = CoeffDev{0, 0, 0.0, 0.0, 0.0, 0.0, nullptr, nq, 0};
         return QXA_OK;
     }
     if (c->kind < 0 || c->kind > 2) return fail(QXA_E_INVALID, std::string(which) + " coefficient: bad kind");
@@ -103,7 +104,7 @@ static qxa_status to_coeff(const qxa_coeff *c, CoeffDev &out, const char *which,
         return fail(QXA_E_UNSUPPORTED, std::string(which) +
                                            " coefficient: a tensor per quadrature node is taken by the "
                                            "isoparametric path (qxa_assemble_iso) only");
-    out = CoeffDev{c->kind, c->law, c->value, c->a[0], c->a[1], c->a[2], c->field};
+    out = CoeffDev{c->kind, c->law, c->value, c->a[0], c->a[1], c->a[2], c->field, nq, 0};
     return QXA_OK;
 }
 
@@ -410,7 +411,7 @@ qxa_status plan_stage(qxa_mesh mesh, const qxa_quad &mr, const qxa_quad &cr, Pla
         return fail(QXA_E_UNSUPPORTED, "no kernel built for dim=" + std::to_string(T.dim) + " order=" +
                                            std::to_string(T.order) + " n_q(mass)=" + std::to_string(T.nq_m) +
                                            " n_q(stiffness)=" + std::to_string(T.nq_c));
-    g.mfma = fused_uses_mfma(T.dim, T.order);
+    g.mfma = fused_uses_mfma(T.dim, T.order, T.nq_m, T.nq_c);
     if (g.mfma) build_qfrags(T, g.frag, g.f16_qinv);
     if (!split_ok(T.dim, T.order, T.nq_m, T.nq_c))
         for (int f = QXA_F16X2; f <= QXA_BF16X3; ++f) g.frag[f].clear();
@@ -540,8 +541,10 @@ qxa_status qxa_plan_get_info(qxa_plan p, qxa_plan_info *out)
     out->dim = p->ref.dim;
     out->order = p->ref.order;
     out->n_p = p->ref.np;
-    out->n_q_mass = p->ref.nq_m;
-    out->n_q_stiff = p->ref.nq_c;
+    out->n_q_mass = p->ref.nq_m_in;
+    out->n_q_stiff = p->ref.nq_c_in;
+    out->n_q_mass_kernel = p->ref.nq_m;
+    out->n_q_stiff_kernel = p->ref.nq_c;
     out->n_nodes = p->mesh->n_nodes;
     out->n_elem = p->mesh->n_elem;
     out->nnz = p->nnz;
@@ -571,7 +574,8 @@ qxa_status qxa_pattern_host(int dim, int order, int64_t n_nodes, int64_t n_elem,
 }
 
 qxa_status qxa_plan_check_host(int dim, int order, int64_t n_nodes, const double *coords, int64_t n_elem,
-                               const int32_t *conn, int64_t chains, int carry_cap, qxa_plan_info *out)
+                               const int32_t *conn, const qxa_quad *mass_rule, const qxa_quad *stiff_rule,
+                               int64_t chains, int carry_cap, qxa_plan_info *out)
 {
     if (!coords || (n_elem > 0 && !conn)) return fail(QXA_E_INVALID, "null argument");
     if ((dim != 2 && dim != 3) || order < 1 || order > 3 || n_nodes < 1 || n_elem < 0)
@@ -582,11 +586,11 @@ qxa_status qxa_plan_check_host(int dim, int order, int64_t n_nodes, const double
     qxa_quad rule{};
     qxa_status st = qxa_quad_builtin(dim, 2 * order, &rule);
     RefTables T;
-    if (!st) st = build_ref_tables(dim, order, rule, rule, T);
+    if (!st) st = build_ref_tables(dim, order, mass_rule ? *mass_rule : rule, stiff_rule ? *stiff_rule : rule, T);
     if (st) return st;
     std::vector<uint8_t> frag[5];
     double qinv[2];
-    if (fused_uses_mfma(dim, order)) build_qfrags(T, frag, qinv);
+    if (fused_uses_mfma(dim, order, T.nq_m, T.nq_c)) build_qfrags(T, frag, qinv);
     int64_t qv16[5];
     for (int f = 0; f < 5; ++f) qv16[f] = int64_t(frag[f].size() / 16);
     TileParams prm = fused_tile_params(dim, order, T.nq_m, T.nq_c, 256, size_t(160) * 1024, qv16);
@@ -604,8 +608,10 @@ qxa_status qxa_plan_check_host(int dim, int order, int64_t n_nodes, const double
         out->dim = dim;
         out->order = order;
         out->n_p = np;
-        out->n_q_mass = T.nq_m;
-        out->n_q_stiff = T.nq_c;
+        out->n_q_mass = T.nq_m_in;
+        out->n_q_stiff = T.nq_c_in;
+        out->n_q_mass_kernel = T.nq_m;
+        out->n_q_stiff_kernel = T.nq_c;
         out->n_nodes = n_nodes;
         out->n_elem = n_elem;
         out->nnz = hp.nnz;
@@ -647,11 +653,11 @@ static qxa_status fill_inputs(qxa_plan p, const qxa_coeff *mass, const qxa_coeff
     if (precision < QXA_FP64 || precision > QXA_BF16X3) return fail(QXA_E_INVALID, "unknown precision form");
     if (precision > QXA_FP32 && !split_ok(p->ref.dim, p->ref.order, p->ref.nq_m, p->ref.nq_c))
         return fail(QXA_E_UNSUPPORTED,
-                    "split 16-bit forms run on the matrix cores with Q staged on chip (2D P2/P3, 3D P2, at most 16 "
-                    "conductivity nodes); use QXA_FP32 as the reduced-precision form here");
+                    "split 16-bit forms run on the matrix cores with Q staged on chip (2D P2/P3 and 3D P2, with "
+                    "rules whose tables fit there); use QXA_FP32 as the reduced-precision form here");
     const int64_t nn = p->mesh->n_nodes, ne = p->mesh->n_elem;
-    qxa_status st = to_coeff(mass, in.cm, "mass", nn, ne);
-    if (!st) st = to_coeff(stiff, in.cc, "stiffness", nn, ne);
+    qxa_status st = to_coeff(mass, in.cm, "mass", nn, ne, p->ref.nq_m_in);
+    if (!st) st = to_coeff(stiff, in.cc, "stiffness", nn, ne, p->ref.nq_c_in);
     if (!st) st = to_tensor(mass, stiff, p->ref.dim, in.aniso, in.K);
     if (st) return st;
     const qxa_mesh m = p->mesh;
@@ -806,7 +812,7 @@ qxa_status qxa_coeff_product(qxa_plan p, int rule, const qxa_coeff *c, const dou
     if (c->kind != QXA_COEFF_NODAL) return fail(QXA_E_INVALID, "the first factor is a nodal field through a law");
     if (c->tensor) return fail(QXA_E_INVALID, "the first factor has no tensor");
     CoeffProductArgs a{};
-    qxa_status st = to_coeff(c, a.c, "first factor", p->mesh->n_nodes, p->mesh->n_elem);
+    qxa_status st = to_coeff(c, a.c, "first factor", p->mesh->n_nodes, p->mesh->n_elem, 0);
     if (st) return st;
     if (p->mesh->n_elem == 0) return QXA_OK;
     QXA_HIP(hipSetDevice(p->mesh->device));
@@ -817,6 +823,7 @@ qxa_status qxa_coeff_product(qxa_plan p, int rule, const qxa_coeff *c, const dou
     a.S = S;
     a.flags = p->d_flags;
     const int nq = rule == 0 ? p->ref.nq_m : p->ref.nq_c;
+    a.nq_out = rule == 0 ? p->ref.nq_m_in : p->ref.nq_c_in;
     QXA_HIP(launch_coeff_product(a, p->ref.dim, p->ref.order, nq, reinterpret_cast<hipStream_t>(stream)));
     return QXA_OK;
 }
@@ -950,6 +957,7 @@ qxa_status qxa_assemble_iso(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *
     qxa_status st = fill_inputs(p, mass, stiff ? &sc : nullptr, QXA_FP64, a.in, &qm, &qc);
     if (st) return st;
     a.Kq = stiff ? stiff->tensor_q : nullptr;
+    a.nq_kq = p->ref.nq_c_in;
     const qxa_mesh m = p->mesh;
     if ((!M_vals && !C_vals) || m->n_elem == 0) return QXA_OK;
     QXA_HIP(hipSetDevice(m->device));
@@ -1020,7 +1028,7 @@ qxa_status qxa_cond_tensor_product(qxa_plan p, const qxa_coeff *c, const double 
     if (!p->d_flags) return fail(QXA_E_INVALID, "plan is owned by a server");
     if (c->kind != QXA_COEFF_NODAL) return fail(QXA_E_INVALID, "c' is a nodal field through a law");
     CondTensorArgs a{};
-    qxa_status st = to_coeff(c, a.c, "c'", p->mesh->n_nodes, p->mesh->n_elem);
+    qxa_status st = to_coeff(c, a.c, "c'", p->mesh->n_nodes, p->mesh->n_elem, 0);
     if (!st) st = to_tensor(nullptr, c, p->ref.dim, a.aniso, a.K);
     if (st) return st;
     if (p->mesh->n_elem == 0) return QXA_OK;

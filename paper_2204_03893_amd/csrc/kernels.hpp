@@ -13,11 +13,17 @@
 namespace qxa {
 
 // (dim, order, n_q mass, n_q stiffness) combinations with compiled kernels:
-// one rule for both matrices (degree 2P), and the lower-degree stiffness rule
-// (degree 2P-2) that constant coefficients allow.
-#define QXA_FORM_CASES(X)                                                                                     \
+// one rule for both matrices (degree 2P), the lower-degree stiffness rule
+// (degree 2P-2) that constant coefficients allow, and one size per shape
+// that any other rule of at most kMaxRule2D / kMaxRule3D nodes is padded to
+// (zero-weight copies of its node 0; a rule is padded to the compiled
+// combination of least work that holds it).
+#define QXA_FORM_CASES_TUNED(X)                                                                               \
     X(2, 1, 3, 3) X(2, 2, 6, 6) X(2, 3, 12, 12) X(3, 1, 4, 4) X(3, 2, 11, 11) X(3, 3, 24, 24) X(2, 1, 3, 1)   \
         X(2, 2, 6, 3) X(2, 3, 12, 6) X(3, 1, 4, 1) X(3, 2, 11, 4) X(3, 3, 24, 11)
+#define QXA_FORM_CASES_PADDED(X) \
+    X(2, 1, 16, 16) X(2, 2, 16, 16) X(2, 3, 16, 16) X(3, 1, 32, 32) X(3, 2, 32, 32) X(3, 3, 32, 32)
+#define QXA_FORM_CASES(X) QXA_FORM_CASES_TUNED(X) QXA_FORM_CASES_PADDED(X)
 
 // Elements per tile of the fused kernels. Vector-ALU variant (P1): one lane
 // per element. Matrix-core variant (P2, P3): 4 producer waves of 16 elements
@@ -29,12 +35,41 @@ constexpr int tile_size(int D, int P)
     return (D == 3 && P == 3) ? 16 : (P >= 2) ? 64 : 256;
 }
 
-bool fused_uses_mfma(int D, int P);
+constexpr size_t kLdsBytes = 160 * 1024;  // LDS of a workgroup (gfx950)
 
-// Split 16-bit forms: Q^T staged in LDS (not the T = 16 shape).
+// LDS bytes of the matrix-core variant with Q^T staged on chip: the two
+// buffers of (V_m, V_c) in the staging type (es bytes), Q^T in K steps of
+// `kstep_bytes` per 16-row block (`ks` steps), and the basis and weight tables.
+constexpr size_t staged_lds_bytes(int D, int P, int nqm, int nqc, int es, int ks, int kstep_bytes)
+{
+    const int np = D == 2 ? (P + 1) * (P + 2) / 2 : (P + 1) * (P + 2) * (P + 3) / 6, ns = np * (np + 1) / 2;
+    return size_t(4) * es * ns * (tile_size(D, P) + 1) + size_t(ks) * ((ns + 15) / 16) * kstep_bytes +
+           (size_t(nqm + nqc) * np + nqm + nqc) * 8;
+}
+
+// Matrix-core variant of a shape and rule sizes: P >= 2, and for the shapes
+// that stage Q^T in LDS (T != 16) the FP64 form must fit a workgroup's LDS
+// (16 x 16 x 4 steps: ceil(n_q,m / 4) + d(d+1)/2 ceil(n_q,c / 4), 512 bytes
+// per 16-row block each). Larger rules run on the vector-ALU variant.
+constexpr bool mfma_variant(int D, int P, int nqm, int nqc)
+{
+    return P >= 2 && (tile_size(D, P) == 16 ||
+                      staged_lds_bytes(D, P, nqm, nqc, 8, (nqm + 3) / 4 + D * (D + 1) / 2 * ((nqc + 3) / 4), 512) <=
+                          kLdsBytes);
+}
+
+bool fused_uses_mfma(int D, int P, int nqm, int nqc);
+
+// Split 16-bit forms: Q^T staged in LDS (not the T = 16 shape), and the
+// three-term BF16 form (the largest) fits with FP32 staging: K steps of 32
+// per 16-row block, 1 KiB per term, mass steps ceil(ceil(n_q,m / 4) / 8),
+// conductivity ceil(ceil(n_q,c / 4) / floor(8 / (d(d+1)/2))).
 constexpr bool split_ok(int D, int P, int nqm, int nqc)
 {
-    return P >= 2 && tile_size(D, P) != 16 && nqm > 0 && nqc > 0;
+    return mfma_variant(D, P, nqm, nqc) && tile_size(D, P) != 16 && nqm > 0 && nqc > 0 &&
+           staged_lds_bytes(D, P, nqm, nqc, 4,
+                            ((nqm + 3) / 4 + 7) / 8 + ((nqc + 3) / 4 + 8 / (D * (D + 1) / 2) - 1) / (8 / (D * (D + 1) / 2)),
+                            3 * 1024) <= kLdsBytes;
 }
 
 struct FormArgs {

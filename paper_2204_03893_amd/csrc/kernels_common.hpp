@@ -24,7 +24,18 @@ struct CoeffDev {
     int law;   // 0 identity, 1 poly2, 2 exp
     double value, a0, a1, a2;
     const double *field;
+    int nq;    // rows of a per-(q, e) field: the nodes of the caller's rule
+    int pad0;
 };
+
+// Per-(q, e) value at node q of the compiled rule. A caller's rule shorter than
+// the compiled one is padded with zero-weight copies of its node 0, which
+// read node 0's value (finite whenever node 0's is, so its zero weight
+// cancels it exactly).
+__device__ __forceinline__ double qe_value(const CoeffDev &c, int q, int64_t n_elem, int64_t e)
+{
+    return c.field[int64_t(q < c.nq ? q : 0) * n_elem + e];
+}
 
 __device__ __forceinline__ double apply_law(const CoeffDev &c, double s)
 {
@@ -171,7 +182,7 @@ __device__ __forceinline__ bool element_setup(const FormInputs &in, const int32_
             for (int i = 0; i < NP; ++i) uh = fma(uniform_table(in.phi_m)[i * NQM + q], um[i], uh);
             s = apply_law(in.cm, uh);
         } else {
-            s = apply_law(in.cm, in.cm.field[q * in.n_elem + eid]);
+            s = apply_law(in.cm, qe_value(in.cm, q, in.n_elem, eid));
         }
         lm[q] = uniform_table(in.w_m)[q] * s * babs;
         ok &= isfinite(lm[q]);
@@ -197,7 +208,7 @@ __device__ __forceinline__ bool element_setup(const FormInputs &in, const int32_
             for (int i = 0; i < NP; ++i) uh = fma(uniform_table(in.phi_c)[i * NQC + q], uc[i], uh);
             s = apply_law(in.cc, uh);
         } else {
-            s = apply_law(in.cc, in.cc.field[q * in.n_elem + eid]);
+            s = apply_law(in.cc, qe_value(in.cc, q, in.n_elem, eid));
         }
         lc[q] = uniform_table(in.w_c)[q] * s * babs;
         ok &= isfinite(lc[q]);
@@ -286,7 +297,7 @@ __device__ __forceinline__ bool setup_from_raw(const FormInputs &in, const RawEl
             for (int i = 0; i < NP; ++i) uh = fma(uniform_table(in.phi_m)[i * NQM + q], r.u[i], uh);
             s = apply_law(in.cm, uh);
         } else {
-            s = apply_law(in.cm, in.cm.field[q * in.n_elem + eid]);
+            s = apply_law(in.cm, qe_value(in.cm, q, in.n_elem, eid));
         }
         lm[q] = uniform_table(in.w_m)[q] * s * babs;
         ok &= isfinite(lm[q]);
@@ -312,7 +323,7 @@ __device__ __forceinline__ bool setup_from_raw(const FormInputs &in, const RawEl
             for (int i = 0; i < NP; ++i) uh = fma(uniform_table(in.phi_c)[i * NQC + q], uc[i], uh);
             s = apply_law(in.cc, uh);
         } else {
-            s = apply_law(in.cc, in.cc.field[q * in.n_elem + eid]);
+            s = apply_law(in.cc, qe_value(in.cc, q, in.n_elem, eid));
         }
         lc[q] = uniform_table(in.w_c)[q] * s * babs;
         ok &= isfinite(lc[q]);

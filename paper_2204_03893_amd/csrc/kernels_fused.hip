@@ -18,6 +18,17 @@
 #include "kernels.hpp"
 #include "kernels_common.hpp"
 
+// This file is built twice: on its own (the rule sizes of QXA_FORM_CASES_TUNED,
+// the fix-up and the dispatch) and through kernels_fused_padded.hip (those of
+// QXA_FORM_CASES_PADDED), so that the two sets of kernels compile in parallel.
+#ifdef QXA_FUSED_PADDED
+#define QXA_FUSED_CASES QXA_FORM_CASES_PADDED
+#define QXA_PART(name) name##_padded
+#else
+#define QXA_FUSED_CASES QXA_FORM_CASES_TUNED
+#define QXA_PART(name) name##_tuned
+#endif
+
 namespace qxa {
 
 // Job of global tile g (uniform across the workgroup) and the tile's index in
@@ -632,7 +643,7 @@ __device__ __forceinline__ bool lane_setup(const FormInputs &in, const RawElem<D
                 for (int i = 0; i < NP; ++i) uh = fma(sPhiM[q * NP + i], r.u[i], uh);
                 s = apply_law(in.cm, uh);
             } else {
-                s = apply_law(in.cm, in.cm.field[q * in.n_elem + eid]);
+                s = apply_law(in.cm, qe_value(in.cm, q, in.n_elem, eid));
             }
             v = sWM[q] * s * babs;
         }
@@ -660,7 +671,7 @@ __device__ __forceinline__ bool lane_setup(const FormInputs &in, const RawElem<D
                 }
                 s = apply_law(in.cc, uh);
             } else {
-                s = apply_law(in.cc, in.cc.field[q * in.n_elem + eid]);
+                s = apply_law(in.cc, qe_value(in.cc, q, in.n_elem, eid));
             }
             v = sWC[q] * s * babs;
         }
@@ -829,7 +840,7 @@ struct WideProducer {
                     s = apply_law(cf, uh);
                 } else {
                     const int64_t eid = b.elem_order[p];
-                    s = apply_law(cf, cf.field[q * in.n_elem + eid]);
+                    s = apply_law(cf, qe_value(cf, q, in.n_elem, eid));
                 }
                 v = (mass ? sWM : sWC)[q] * s * babs;
                 ok &= isfinite(v);
@@ -1121,6 +1132,8 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
     }
 }
 
+#ifndef QXA_FUSED_PADDED
+
 // Shared slots: one thread per shared upper slot sums its partials (stored
 // contiguously, ascending tile order) and writes the slot and its mirror.
 __global__ __launch_bounds__(256) void fixup_kernel(FixupTable ft)
@@ -1160,14 +1173,11 @@ __global__ __launch_bounds__(256) void fixup_kernel(FixupTable ft)
         a.C[tm] = c;
     }
 }
+#endif
 
-template <int D, int P>
-constexpr bool use_mfma()
-{
-    return P >= 2;
-}
-
-bool fused_uses_mfma(int D, int P) { return P >= 2; }
+#ifndef QXA_FUSED_PADDED
+bool fused_uses_mfma(int D, int P, int nqm, int nqc) { return mfma_variant(D, P, nqm, nqc); }
+#endif
 
 // Resident workgroups for a persistent launch: CUs x workgroups per CU.
 template <class K>
@@ -1192,21 +1202,15 @@ static size_t p1_lds_bytes()
     return size_t(tile_size(D, P) + 1) * Shape<D, P>::NS * 16;
 }
 
-TileParams fused_tile_params(int D, int P, int nqm, int nqc, int cus, size_t lds_max, const int64_t (&qv16)[5])
+// LDS bytes of the matrix-core kernel of a shape (its largest precision form);
+// false if the rule sizes are not among this file's.
+bool QXA_PART(fused_base_lds)(int D, int P, int nqm, int nqc, const int64_t (&qv16)[5], size_t &base)
 {
-    TileParams tp;
-    tp.T = tile_size(D, P);
-    tp.pair_units = true;
-    if (P == 1) {  // the vector-ALU variant: a chain per tile, no carries
-        tp.chains = int64_t(1) << 40;
-        tp.carry_cap = 0;
-        return tp;
-    }
-    size_t base = 0;
+    base = 0;
 #define X(d, p, m, c)                                                                                              \
     if (D == d && P == p && nqm == m && nqc == c) {                                                               \
         constexpr int T = tile_size(d, p);                                                                        \
-        if constexpr (use_mfma<d, p>()) {                                                                         \
+        if constexpr (mfma_variant(d, p, m, c)) {                                                                         \
             base = std::max(WsLds<d, p, m, c, QXA_FP64, T>::bytes(qv16[QXA_FP64]),                                \
                             WsLds<d, p, m, c, QXA_FP32, T>::bytes(qv16[QXA_FP32]));                               \
             if constexpr (split_ok(d, p, m, c)) {                                                                 \
@@ -1215,19 +1219,43 @@ TileParams fused_tile_params(int D, int P, int nqm, int nqc, int cus, size_t lds
                 base = std::max(base, WsLds<d, p, m, c, QXA_BF16X3, T>::bytes(qv16[QXA_BF16X3]));                 \
             }                                                                                                     \
         }                                                                                                         \
+        return true;                                                                                              \
     }
-    QXA_FORM_CASES(X)
+    QXA_FUSED_CASES(X)
 #undef X
+    return false;
+}
+
+#ifndef QXA_FUSED_PADDED
+bool fused_base_lds_padded(int D, int P, int nqm, int nqc, const int64_t (&qv16)[5], size_t &base);
+hipError_t launch_fused_padded(const JobTable &jt, int D, int P, int nqm, int nqc, int precision, hipStream_t st,
+                               bool &found);
+
+TileParams fused_tile_params(int D, int P, int nqm, int nqc, int cus, size_t lds_max, const int64_t (&qv16)[5])
+{
+    TileParams tp;
+    tp.T = tile_size(D, P);
+    tp.pair_units = true;
+    if (!mfma_variant(D, P, nqm, nqc)) {  // the vector-ALU variant: a chain per tile, no carries
+        tp.chains = int64_t(1) << 40;
+        tp.carry_cap = 0;
+        return tp;
+    }
+    size_t base = 0;
+    if (!fused_base_lds_tuned(D, P, nqm, nqc, qv16, base)) fused_base_lds_padded(D, P, nqm, nqc, qv16, base);
     const size_t room = lds_max > with_carries(base, 0) ? lds_max - with_carries(base, 0) : 0;
     tp.carry_cap = int(std::min<size_t>(kMaxCarries, room / 16) / 16 * 16);
     tp.chains = int64_t(std::max(1, cus));  // one workgroup per CU
     return tp;
 }
+#endif
 
-hipError_t launch_fused(const JobTable &jt, int D, int P, int nqm, int nqc, int precision, hipStream_t st)
+// The launch of this file's rule sizes (found = false for others).
+hipError_t QXA_PART(launch_fused)(const JobTable &jt, int D, int P, int nqm, int nqc, int precision, hipStream_t st,
+                                  bool &found)
 {
     const int64_t n_tiles = jt.n_tiles;
-    if (n_tiles == 0 || jt.n_chains == 0) return hipSuccess;
+    found = true;
     const FusedArgs &a = jt.one;  // the first job (Q^T fragment size and carry entries are shared by all jobs)
 #define QXA_LAUNCH_MFMA(d, p, m, c, PF, MULTI)                                                            \
     {                                                                                                     \
@@ -1241,7 +1269,7 @@ hipError_t launch_fused(const JobTable &jt, int D, int P, int nqm, int nqc, int 
         constexpr int T = tile_size(d, p);                                                                 \
         const bool multi = jt.n_jobs > 0;                                                                  \
         if (multi && precision != QXA_FP64 && precision != QXA_FP32) return hipErrorInvalidValue;          \
-        if constexpr (use_mfma<d, p>()) {                                                                  \
+        if constexpr (mfma_variant(d, p, m, c)) {                                                                  \
             switch (precision * 2 + int(multi)) {                                                          \
             case 2 * QXA_FP64: QXA_LAUNCH_MFMA(d, p, m, c, QXA_FP64, false) break;                         \
             case 2 * QXA_FP64 + 1: QXA_LAUNCH_MFMA(d, p, m, c, QXA_FP64, true) break;                      \
@@ -1284,17 +1312,31 @@ hipError_t launch_fused(const JobTable &jt, int D, int P, int nqm, int nqc, int 
         }                                                                                                  \
         return hipGetLastError();                                                                          \
     }
-    QXA_FORM_CASES(X)
+    QXA_FUSED_CASES(X)
 #undef X
 #undef QXA_LAUNCH_MFMA
+    found = false;
     return hipErrorInvalidValue;
 }
 
+#ifndef QXA_FUSED_PADDED
+hipError_t launch_fused(const JobTable &jt, int D, int P, int nqm, int nqc, int precision, hipStream_t st)
+{
+    if (jt.n_tiles == 0 || jt.n_chains == 0) return hipSuccess;
+    bool found = false;
+    const hipError_t e = launch_fused_tuned(jt, D, P, nqm, nqc, precision, st, found);
+    if (found) return e;
+    return launch_fused_padded(jt, D, P, nqm, nqc, precision, st, found);
+}
+#endif
+
+#ifndef QXA_FUSED_PADDED
 hipError_t launch_fixup(const FixupTable &ft, hipStream_t st)
 {
     if (ft.n_fix == 0) return hipSuccess;
     fixup_kernel<<<unsigned((ft.n_fix + 255) / 256), 256, 0, st>>>(ft);
     return hipGetLastError();
 }
+#endif
 
 }  // namespace qxa

@@ -9,6 +9,18 @@
 #include "kernels_twopass.hpp"
 #include "kernels_common.hpp"
 
+// This file is built twice: on its own (the rule sizes of QXA_FORM_CASES_TUNED,
+// the rule-size choice, the gathers and the dispatch) and through
+// kernels_twopass_padded.hip (those of QXA_FORM_CASES_PADDED), so that the two
+// sets of kernels compile in parallel.
+#ifdef QXA_TWOPASS_PADDED
+#define QXA_TWOPASS_CASES QXA_FORM_CASES_PADDED
+#define QXA_PART(name) name##_padded
+#else
+#define QXA_TWOPASS_CASES QXA_FORM_CASES_TUNED
+#define QXA_PART(name) name##_tuned
+#endif
+
 namespace qxa {
 
 template <int D, int P, int NQM, int NQC, typename CT>
@@ -30,6 +42,7 @@ __global__ __launch_bounds__(256) void form_kernel(FormArgs a)
         contract_stiff<P, S::NS, NQC, S::NG>(reinterpret_cast<const CT *>(a.Qc), lc, A,
                                              [&](int s, double x) { a.Vc[s * ne + e] = x; });
 }
+#ifndef QXA_TWOPASS_PADDED
 
 // Symmetric pairs -> full n_p x n_p element matrices [(i*np+j)][n_elem].
 __global__ __launch_bounds__(256) void expand_kernel(ExpandArgs a)
@@ -51,6 +64,25 @@ __global__ __launch_bounds__(256) void expand_kernel(ExpandArgs a)
             }
         }
 }
+#endif
+#ifndef QXA_TWOPASS_PADDED
+
+bool compiled_rule_sizes(int D, int P, int nqm, int nqc, int &cm, int &cc)
+{
+    const int ng = D * (D + 1) / 2;
+    int best = -1;
+#define X(d, p, m, c)                                                           \
+    if (D == d && P == p && nqm <= m && nqc <= c && (best < 0 || m + ng * c < best)) { \
+        best = m + ng * c;                                                      \
+        cm = m;                                                                 \
+        cc = c;                                                                 \
+    }
+    QXA_FORM_CASES(X)
+#undef X
+    return best >= 0;
+}
+#endif
+#ifndef QXA_TWOPASS_PADDED
 
 bool form_supported(int D, int P, int nqm, int nqc)
 {
@@ -60,9 +92,11 @@ bool form_supported(int D, int P, int nqm, int nqc)
 #undef X
     return false;
 }
+#endif
 
-hipError_t launch_form(const FormArgs &a, int D, int P, int nqm, int nqc, int precision, hipStream_t st)
+hipError_t QXA_PART(launch_form)(const FormArgs &a, int D, int P, int nqm, int nqc, int precision, hipStream_t st, bool &found)
 {
+    found = true;
     if (a.in.n_elem == 0) return hipSuccess;
     const dim3 block(256), grid(unsigned((a.in.n_elem + 255) / 256));
 #define X(d, p, m, c)                                                                 \
@@ -71,8 +105,9 @@ hipError_t launch_form(const FormArgs &a, int D, int P, int nqm, int nqc, int pr
         else form_kernel<d, p, m, c, double><<<grid, block, 0, st>>>(a);               \
         return hipGetLastError();                                                     \
     }
-    QXA_FORM_CASES(X)
+    QXA_TWOPASS_CASES(X)
 #undef X
+    found = false;
     return hipErrorInvalidValue;
 }
 
@@ -104,14 +139,17 @@ __global__ __launch_bounds__(256) void coeff_product_kernel(CoeffProductArgs a)
             vh = fma(ph, v[i], vh);
         }
         const double s = apply_law(a.c, uh) * vh;
-        ok &= isfinite(s);
-        a.S[q * a.n_elem + e] = s;
+        if (q < a.nq_out) {  // (the caller's rule; the compiled one may be padded)
+            ok &= isfinite(s);
+            a.S[q * a.n_elem + e] = s;
+        }
     }
     if (!ok) atomicOr(a.flags, 1);
 }
 
-hipError_t launch_coeff_product(const CoeffProductArgs &a, int D, int P, int nq, hipStream_t st)
+hipError_t QXA_PART(launch_coeff_product)(const CoeffProductArgs &a, int D, int P, int nq, hipStream_t st, bool &found)
 {
+    found = true;
     if (a.n_elem == 0) return hipSuccess;
     const dim3 block(256), grid(unsigned((a.n_elem + 255) / 256));
 #define X(d, p, m, c)                                                            \
@@ -123,8 +161,9 @@ hipError_t launch_coeff_product(const CoeffProductArgs &a, int D, int P, int nq,
         coeff_product_kernel<d, p, c><<<grid, block, 0, st>>>(a);                \
         return hipGetLastError();                                                \
     }
-    QXA_FORM_CASES(X)
+    QXA_TWOPASS_CASES(X)
 #undef X
+    found = false;
     return hipErrorInvalidValue;
 }
 
@@ -248,8 +287,9 @@ __global__ __launch_bounds__(256) void cond_tensor_rows_kernel(CondTensorArgs a)
     }
 }
 
-hipError_t launch_cond_tensor(const CondTensorArgs &a, int D, int P, int nq, hipStream_t st)
+hipError_t QXA_PART(launch_cond_tensor)(const CondTensorArgs &a, int D, int P, int nq, hipStream_t st, bool &found)
 {
+    found = true;
     if (a.n_elem == 0) return hipSuccess;
     const unsigned blocks = unsigned((a.n_elem + kCtElems - 1) / kCtElems);
 #define X(d, p, m, c)                                                                                   \
@@ -257,8 +297,9 @@ hipError_t launch_cond_tensor(const CondTensorArgs &a, int D, int P, int nq, hip
         cond_tensor_rows_kernel<d, p, c><<<blocks, 256, ct_lds_doubles<d, p, c>() * sizeof(double), st>>>(a); \
         return hipGetLastError();                                                                       \
     }
-    QXA_FORM_CASES(X)
+    QXA_TWOPASS_CASES(X)
 #undef X
+    found = false;
     return hipErrorInvalidValue;
 }
 
@@ -302,7 +343,7 @@ __global__ __launch_bounds__(256) void load_elem_kernel(LoadArgs a)
             for (int i = 0; i < S::NP; ++i) uh = fma(uniform_table(a.in.phi_m)[i * NQ + q], u[i], uh);
             s = apply_law(f, uh);
         } else {
-            s = apply_law(f, f.field[q * ne + e]);
+            s = apply_law(f, qe_value(f, q, ne, e));
         }
         const double lam = uniform_table(a.in.w_m)[q] * s * babs;
         ok &= isfinite(lam);
@@ -314,8 +355,9 @@ __global__ __launch_bounds__(256) void load_elem_kernel(LoadArgs a)
     if (!ok) atomicOr(a.in.flags, 1);
 }
 
-hipError_t launch_load(const LoadArgs &a, int D, int P, int nq, hipStream_t st)
+hipError_t QXA_PART(launch_load)(const LoadArgs &a, int D, int P, int nq, hipStream_t st, bool &found)
 {
+    found = true;
     if (a.in.n_elem == 0) return hipSuccess;
     const unsigned grid = unsigned((a.in.n_elem + 255) / 256);
 #define X(d, p, m, c)                                                  \
@@ -323,8 +365,9 @@ hipError_t launch_load(const LoadArgs &a, int D, int P, int nq, hipStream_t st)
         load_elem_kernel<d, p, m><<<grid, 256, 0, st>>>(a);            \
         return hipGetLastError();                                      \
     }
-    QXA_FORM_CASES(X)
+    QXA_TWOPASS_CASES(X)
 #undef X
+    found = false;
     return hipErrorInvalidValue;
 }
 
@@ -432,7 +475,7 @@ __global__ __launch_bounds__(256) void iso_rows_kernel(IsoArgs a)
             for (int i = 0; i < NP; ++i) uh = fma(phi[i * (mass ? NQM : NQC) + q], u[i * E + lane], uh);
             sv = apply_law(cf, uh);
         } else if (cf.kind == 2) {
-            sv = live ? apply_law(cf, cf.field[q * ne + e]) : 0.0;
+            sv = live ? apply_law(cf, qe_value(cf, q, ne, e)) : 0.0;
         }
         const double lam = uniform_table(mass ? in.w_m : in.w_c)[q] * sv * adet;
         if (mass) {
@@ -446,7 +489,7 @@ __global__ __launch_bounds__(256) void iso_rows_kernel(IsoArgs a)
                 double Kl[NG];
 #pragma unroll
                 for (int g = 0; g < NG; ++g) {
-                    Kl[g] = live ? a.Kq[(int64_t(q) * NG + g) * ne + e] : 0.0;
+                    Kl[g] = live ? a.Kq[(int64_t(q < a.nq_kq ? q : 0) * NG + g) * ne + e] : 0.0;
                     ok &= isfinite(Kl[g]);
                 }
                 metric_from_inverse<D>(I, 1, Kl, Au);
@@ -500,8 +543,9 @@ __global__ __launch_bounds__(256) void iso_rows_kernel(IsoArgs a)
     }
 }
 
-hipError_t launch_iso(const IsoArgs &a, int D, int P, int nqm, int nqc, hipStream_t st)
+hipError_t QXA_PART(launch_iso)(const IsoArgs &a, int D, int P, int nqm, int nqc, hipStream_t st, bool &found)
 {
+    found = true;
     if (a.in.n_elem == 0) return hipSuccess;
     const unsigned blocks = unsigned((a.in.n_elem + kIsoElems - 1) / kIsoElems);
 #define X(d, p, m, c)                                                                                  \
@@ -509,10 +553,12 @@ hipError_t launch_iso(const IsoArgs &a, int D, int P, int nqm, int nqc, hipStrea
         iso_rows_kernel<d, p, m, c><<<blocks, 256, iso_lds_doubles<d, p, m, c>() * sizeof(double), st>>>(a); \
         return hipGetLastError();                                                                      \
     }
-    QXA_FORM_CASES(X)
+    QXA_TWOPASS_CASES(X)
 #undef X
+    found = false;
     return hipErrorInvalidValue;
 }
+#ifndef QXA_TWOPASS_PADDED
 
 // out[t] = sum of src over the entries of slot t, in their stored order (deterministic).
 __global__ __launch_bounds__(256) void slot_gather_kernel(SlotGatherArgs a)
@@ -595,5 +641,43 @@ hipError_t launch_expand(const ExpandArgs &a, hipStream_t st)
     expand_kernel<<<unsigned((a.n_elem + 255) / 256), 256, 0, st>>>(a);
     return hipGetLastError();
 }
+
+
+hipError_t launch_form_padded(const FormArgs &a, int D, int P, int nqm, int nqc, int precision, hipStream_t st, bool &found);
+hipError_t launch_form(const FormArgs &a, int D, int P, int nqm, int nqc, int precision, hipStream_t st)
+{
+    bool found = false;
+    const hipError_t e = launch_form_tuned(a, D, P, nqm, nqc, precision, st, found);
+    return found ? e : launch_form_padded(a, D, P, nqm, nqc, precision, st, found);
+}
+hipError_t launch_coeff_product_padded(const CoeffProductArgs &a, int D, int P, int nq, hipStream_t st, bool &found);
+hipError_t launch_coeff_product(const CoeffProductArgs &a, int D, int P, int nq, hipStream_t st)
+{
+    bool found = false;
+    const hipError_t e = launch_coeff_product_tuned(a, D, P, nq, st, found);
+    return found ? e : launch_coeff_product_padded(a, D, P, nq, st, found);
+}
+hipError_t launch_cond_tensor_padded(const CondTensorArgs &a, int D, int P, int nq, hipStream_t st, bool &found);
+hipError_t launch_cond_tensor(const CondTensorArgs &a, int D, int P, int nq, hipStream_t st)
+{
+    bool found = false;
+    const hipError_t e = launch_cond_tensor_tuned(a, D, P, nq, st, found);
+    return found ? e : launch_cond_tensor_padded(a, D, P, nq, st, found);
+}
+hipError_t launch_load_padded(const LoadArgs &a, int D, int P, int nq, hipStream_t st, bool &found);
+hipError_t launch_load(const LoadArgs &a, int D, int P, int nq, hipStream_t st)
+{
+    bool found = false;
+    const hipError_t e = launch_load_tuned(a, D, P, nq, st, found);
+    return found ? e : launch_load_padded(a, D, P, nq, st, found);
+}
+hipError_t launch_iso_padded(const IsoArgs &a, int D, int P, int nqm, int nqc, hipStream_t st, bool &found);
+hipError_t launch_iso(const IsoArgs &a, int D, int P, int nqm, int nqc, hipStream_t st)
+{
+    bool found = false;
+    const hipError_t e = launch_iso_tuned(a, D, P, nqm, nqc, st, found);
+    return found ? e : launch_iso_padded(a, D, P, nqm, nqc, st, found);
+}
+#endif
 
 }  // namespace qxa

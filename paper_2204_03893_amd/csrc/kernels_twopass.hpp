@@ -20,8 +20,9 @@ struct CoeffProductArgs {
     const double *phi;    // [np][nq] basis values of the rule
     CoeffDev c;           // law of the first factor; c.field = u [n_nodes]
     const double *v;      // [n_nodes]
-    double *S;            // [nq][n_elem]
+    double *S;            // [nq_out][n_elem]
     int *flags;
+    int nq_out;           // nodes of the caller's rule (the compiled rule may be padded)
 };
 
 struct CondTensorArgs {
@@ -52,7 +53,8 @@ struct IsoArgs {
     const double *dphi_c;  // [nq_c][np][dim]
     const double *Qm;      // [ns][nq_m] FP64 mass table (symmetric pair rows)
     const double *Qc;      // [ns][nq_c][ng] FP64 conductivity table
-    const double *Kq;      // [nq_c][ng][n_elem] conductivity tensor per node (or null)
+    const double *Kq;      // [nq_kq][ng][n_elem] conductivity tensor per node (or null)
+    int nq_kq;             // nodes of the caller's stiffness rule
     double *Tm, *Tc;       // [n_elem / 64][ns][64] symmetric local matrices, pair-major per block
 };
 

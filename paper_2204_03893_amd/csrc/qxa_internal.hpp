@@ -49,7 +49,8 @@ extern const int k_n_builtin_rules;
 
 struct RefTables {
     int dim = 0, order = 0, np = 0, ns = 0, ng = 0;
-    int nq_m = 0, nq_c = 0;
+    int nq_m = 0, nq_c = 0;        // nodes of the compiled rules (the tables below)
+    int nq_m_in = 0, nq_c_in = 0;  // nodes of the caller's rules (a prefix of the compiled ones)
     std::vector<double> w_m, w_c;     // quadrature weights
     std::vector<double> phi_m;        // [np][nq_m]: Phi for the mass rule
     std::vector<double> phi_c;        // [np][nq_c]: Phi at the stiffness rule (for u_h)
@@ -61,8 +62,15 @@ struct RefTables {
     bool stiff_const_grad = false;    // J_q identical for all q (P1): Q_c columns repeat
 };
 
-// Builds the tables from the rules; returns QXA_OK or an error.
+// Builds the tables from the rules, each padded to the compiled size chosen by
+// compiled_rule_sizes; returns QXA_OK or an error.
 qxa_status build_ref_tables(int dim, int order, const qxa_quad &mr, const qxa_quad &cr, RefTables &out);
+
+// Largest rules the compiled kernels take (in nodes).
+constexpr int kMaxRule2D = 16, kMaxRule3D = 32;
+// The compiled (mass, stiffness) rule sizes of least work (n_q,m + d(d+1)/2
+// n_q,c) that hold rules of nqm and nqc nodes; false if none does.
+bool compiled_rule_sizes(int dim, int order, int nqm, int nqc, int &cm, int &cc);
 
 // Lagrange basis of the reference simplex in barycentric product form.
 void lagrange_eval(int dim, int order, const double *xhat, double *phi, double *dphi /* [np][dim] */);

@@ -10,6 +10,8 @@
 // column per a <= b, so X_c = Lambda_c (.) W keeps d(d+1)/2 rows per q.
 #include <cmath>
 #include <cstring>
+#include <string>
+#include <vector>
 
 #include "qxa_internal.hpp"
 
@@ -114,11 +116,27 @@ qxa_status build_ref_tables(int dim, int order, const qxa_quad &mr, const qxa_qu
     T.np = n_local(dim, order);
     T.ns = n_sym(T.np);
     T.ng = n_geo(dim);
-    T.nq_m = mr.n_q;
-    T.nq_c = cr.n_q;
+    T.nq_m_in = mr.n_q;
+    T.nq_c_in = cr.n_q;
+    if (!compiled_rule_sizes(dim, order, mr.n_q, cr.n_q, T.nq_m, T.nq_c))
+        return fail(QXA_E_UNSUPPORTED, "no kernel takes rules of " + std::to_string(mr.n_q) + " (mass) and " +
+                                           std::to_string(cr.n_q) + " (stiffness) nodes for dim=" +
+                                           std::to_string(dim) + " order=" + std::to_string(order) + " (at most " +
+                                           std::to_string(dim == 2 ? kMaxRule2D : kMaxRule3D) + " nodes)");
+    // rules padded to the compiled sizes: zero-weight copies of node 0
+    std::vector<double> pm(size_t(T.nq_m) * dim), pc(size_t(T.nq_c) * dim);
+    for (int q = 0; q < T.nq_m; ++q)
+        std::copy(mr.points + (q < mr.n_q ? q : 0) * dim, mr.points + (q < mr.n_q ? q : 0) * dim + dim,
+                  pm.begin() + size_t(q) * dim);
+    for (int q = 0; q < T.nq_c; ++q)
+        std::copy(cr.points + (q < cr.n_q ? q : 0) * dim, cr.points + (q < cr.n_q ? q : 0) * dim + dim,
+                  pc.begin() + size_t(q) * dim);
+    const double *mpts = pm.data(), *cpts = pc.data();
     const int np = T.np, ns = T.ns, ng = T.ng;
     T.w_m.assign(mr.weights, mr.weights + mr.n_q);
     T.w_c.assign(cr.weights, cr.weights + cr.n_q);
+    T.w_m.resize(T.nq_m, 0.0);
+    T.w_c.resize(T.nq_c, 0.0);
     T.pair_a.clear();
     T.pair_b.clear();
     for (int a = 0; a < np; ++a)
@@ -142,7 +160,7 @@ qxa_status build_ref_tables(int dim, int order, const qxa_quad &mr, const qxa_qu
     T.dphi_m.assign(size_t(T.nq_m) * np * dim, 0.0);
     T.Qm.assign(size_t(ns) * T.nq_m, 0.0);
     for (int q = 0; q < T.nq_m; ++q) {
-        lagrange_eval(dim, order, mr.points + q * dim, phi, dphi);
+        lagrange_eval(dim, order, mpts + q * dim, phi, dphi);
         for (int i = 0; i < np; ++i) T.phi_m[size_t(i) * T.nq_m + q] = phi[i];
         std::copy(dphi, dphi + np * dim, T.dphi_m.begin() + size_t(q) * np * dim);
         for (int s = 0; s < ns; ++s) T.Qm[size_t(s) * T.nq_m + q] = phi[T.pair_a[s]] * phi[T.pair_b[s]];
@@ -154,7 +172,7 @@ qxa_status build_ref_tables(int dim, int order, const qxa_quad &mr, const qxa_qu
     std::vector<double> J0;
     T.stiff_const_grad = true;
     for (int q = 0; q < T.nq_c; ++q) {
-        lagrange_eval(dim, order, cr.points + q * dim, phi, dphi);
+        lagrange_eval(dim, order, cpts + q * dim, phi, dphi);
         for (int i = 0; i < np; ++i) T.phi_c[size_t(i) * T.nq_c + q] = phi[i];
         std::copy(dphi, dphi + np * dim, T.dphi_c.begin() + size_t(q) * np * dim);
         if (q == 0) J0.assign(dphi, dphi + np * dim);

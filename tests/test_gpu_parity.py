@@ -180,10 +180,11 @@ def test_error_paths():
     with pytest.raises(qxa.QxaError) as ei:
         qxa.Mesh(2, 1, X, mesh["conn"])
     assert ei.value.code == -3
-    # unsupported rule size
+    # a rule larger than every compiled size (25 nodes in 2D; smaller ones are padded)
+    from workloads.quadrature import conical
     m = qxa.Mesh(2, 1, mesh["coords"], mesh["conn"])
     with pytest.raises(qxa.QxaError) as ei:
-        qxa.Plan(m, rule(2, 4))
+        qxa.Plan(m, conical(2, 5))
     assert ei.value.code == -6
     # non-finite coefficient detected on the device, reported at sync
     plan = qxa.Plan(m, rule(2, 2))

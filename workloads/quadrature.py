@@ -188,3 +188,52 @@ def rule_degree(dim: int, degree: int) -> int:
 
 def available(dim: int):
     return sorted(dg for (dd, dg) in _SPECS if dd == dim)
+
+
+# Rules of sizes other than the built-in ones (inputs that the library pads to
+# a compiled rule size): two classical closed-form rules and a conical product.
+
+def radon7():
+    """Radon's 7-node rule of degree 5 on the triangle: the centroid and two
+    S21 orbits with a = (6 -+ sqrt 15) / 21 (weights 9/80 and (155 -+ sqrt 15) / 2400,
+    summing to the area 1/2)."""
+    s = math.sqrt(15.0)
+    pts, wts = [(1.0 / 3.0, 1.0 / 3.0)], [9.0 / 80.0]
+    for a, w in (((6.0 - s) / 21.0, (155.0 - s) / 2400.0), ((6.0 + s) / 21.0, (155.0 + s) / 2400.0)):
+        for p in ((a, a), (1.0 - 2.0 * a, a), (a, 1.0 - 2.0 * a)):
+            pts.append(p)
+            wts.append(w)
+    return np.array(pts), np.array(wts)
+
+
+def keast5():
+    """The 5-node rule of degree 3 on the tetrahedron: the centroid with weight
+    -2/15 and the S31 orbit with l = (1/2, 1/6, 1/6, 1/6), weight 3/40 each (a
+    negative weight; the total is the volume 1/6)."""
+    pts, wts = [(0.25, 0.25, 0.25)], [-2.0 / 15.0]
+    for k in range(4):
+        l = [1.0 / 6.0] * 4
+        l[k] = 0.5
+        pts.append(tuple(l[1:]))
+        wts.append(3.0 / 40.0)
+    return np.array(pts), np.array(wts)
+
+
+def conical(dim: int, n: int):
+    """Conical product rule with n Gauss-Legendre nodes per axis (n^dim nodes):
+    the square or cube mapped onto the simplex by collapsing one side at a time,
+    x = u, y = v (1 - u) (, z = t (1 - u)(1 - v)), with the Jacobian (1 - u) (1 - u)^2 (1 - v)
+    in the weights; exact up to degree 2n - 2 in 2D and 2n - 3 in 3D."""
+    g, gw = np.polynomial.legendre.leggauss(n)
+    g, gw = (g + 1.0) / 2.0, gw / 2.0
+    pts, wts = [], []
+    for idx in itertools.product(range(n), repeat=dim):
+        u = [g[i] for i in idx]
+        w = float(np.prod([gw[i] for i in idx]))
+        if dim == 2:
+            pts.append((u[0], u[1] * (1.0 - u[0])))
+            wts.append(w * (1.0 - u[0]))
+        else:
+            pts.append((u[0], u[1] * (1.0 - u[0]), u[2] * (1.0 - u[0]) * (1.0 - u[1])))
+            wts.append(w * (1.0 - u[0]) ** 2 * (1.0 - u[1]))
+    return np.array(pts), np.array(wts)
