@@ -14,22 +14,6 @@
 
 namespace qxa {
 
-template <class F>
-static void parallel_for(int64_t n, F &&f)
-{
-    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    if (n < 4096 || nt == 1) {
-        f(int64_t(0), n);
-        return;
-    }
-    std::vector<std::thread> th;
-    int64_t chunk = (n + nt - 1) / nt;
-    for (unsigned t = 0; t < nt; ++t) {
-        int64_t lo = std::min<int64_t>(n, t * chunk), hi = std::min<int64_t>(n, lo + chunk);
-        if (lo < hi) th.emplace_back([&f, lo, hi] { f(lo, hi); });
-    }
-    for (auto &x : th) x.join();
-}
 
 qxa_status build_host_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, const int32_t *conn, HostPlan &hp)
 {
@@ -39,16 +23,22 @@ qxa_status build_host_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
         return fail(QXA_E_UNSUPPORTED, "mesh too large for 32-bit element-entry indices");
     hp.n_nodes = n_nodes;
     hp.n_elem = n_elem;
-    // 1. node -> element adjacency
+    // 1. node -> element adjacency (the order within a node does not matter:
+    //    each row's columns are sorted below)
     std::vector<int64_t> astart(n_nodes + 1, 0);
-    for (int i = 0; i < np; ++i)
-        for (int64_t e = 0; e < n_elem; ++e) astart[conn[size_t(i) * n_elem + e] + 1]++;
+    parallel_for(n_elem, [&](int64_t lo, int64_t hi) {
+        for (int i = 0; i < np; ++i)
+            for (int64_t e = lo; e < hi; ++e) __atomic_fetch_add(&astart[conn[size_t(i) * n_elem + e] + 1], 1, __ATOMIC_RELAXED);
+    });
     for (int64_t v = 0; v < n_nodes; ++v) astart[v + 1] += astart[v];
-    std::vector<int32_t> aelem(astart[n_nodes]);
+    hvec<int32_t> aelem(astart[n_nodes]);
     {
         std::vector<int64_t> fill(astart.begin(), astart.end() - 1);
-        for (int64_t e = 0; e < n_elem; ++e)
-            for (int i = 0; i < np; ++i) aelem[fill[conn[size_t(i) * n_elem + e]]++] = int32_t(e);
+        parallel_for(n_elem, [&](int64_t lo, int64_t hi) {
+            for (int64_t e = lo; e < hi; ++e)
+                for (int i = 0; i < np; ++i)
+                    aelem[__atomic_fetch_add(&fill[conn[size_t(i) * n_elem + e]], 1, __ATOMIC_RELAXED)] = int32_t(e);
+        });
     }
     // 2. pattern: count, then fill
     hp.row_ptr.assign(n_nodes + 1, 0);

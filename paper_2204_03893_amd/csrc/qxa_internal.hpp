@@ -3,10 +3,14 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
+#include <type_traits>
 #include <unordered_map>
 #include <utility>
 #include <vector>
@@ -28,6 +32,82 @@ inline int n_local(int dim, int order)
 }
 inline int n_sym(int np) { return np * (np + 1) / 2; }
 inline int n_geo(int dim) { return dim * (dim + 1) / 2; }
+
+// Host plan building blocks ------------------------------------------------
+// Allocator that default-initialises (leaves trivial elements unset), for
+// large host arrays that are filled in parallel right after they are sized.
+template <class T>
+struct DefaultInit : std::allocator<T> {
+    template <class U>
+    struct rebind {
+        using other = DefaultInit<U>;
+    };
+    DefaultInit() = default;
+    template <class U>
+    DefaultInit(const DefaultInit<U> &) noexcept
+    {
+    }
+    template <class U>
+    void construct(U *p) noexcept(std::is_nothrow_default_constructible<U>::value)
+    {
+        ::new (static_cast<void *>(p)) U;
+    }
+    template <class U, class... A>
+    void construct(U *p, A &&...a)
+    {
+        ::new (static_cast<void *>(p)) U(std::forward<A>(a)...);
+    }
+};
+template <class T>
+using hvec = std::vector<T, DefaultInit<T>>;
+
+// Host threads of the plan builders (at most 16).
+inline unsigned host_threads() { return std::max(1u, std::min(16u, std::thread::hardware_concurrency())); }
+
+// f(lo, hi) over [0, n) cut into one contiguous range per host thread.
+template <class F>
+void parallel_for(int64_t n, F &&f, int64_t serial_below = 64)
+{
+    const unsigned nt = host_threads();
+    if (n < serial_below || nt == 1) {
+        f(int64_t(0), n);
+        return;
+    }
+    std::vector<std::thread> th;
+    const int64_t chunk = (n + nt - 1) / nt;
+    for (unsigned t = 0; t < nt; ++t) {
+        const int64_t lo = std::min<int64_t>(n, t * chunk), hi = std::min<int64_t>(n, lo + chunk);
+        if (lo < hi) th.emplace_back([&f, lo, hi] { f(lo, hi); });
+    }
+    for (auto &x : th) x.join();
+}
+
+// Sort of a random-access range on the host threads: ranges sorted in
+// parallel, then merged pairwise (the result equals std::sort's for a strict
+// weak order without ties).
+template <class It>
+void parallel_sort(It first, It last)
+{
+    const int64_t n = last - first;
+    const unsigned nt = host_threads();
+    if (n < (int64_t(1) << 16) || nt == 1) {
+        std::sort(first, last);
+        return;
+    }
+    int64_t w = (n + nt - 1) / nt;
+    parallel_for(nt, [&](int64_t a, int64_t b) {
+        for (int64_t k = a; k < b; ++k) std::sort(first + std::min(n, k * w), first + std::min(n, (k + 1) * w));
+    }, 0);
+    for (; w < n; w *= 2) {
+        const int64_t pairs = (n + 2 * w - 1) / (2 * w);
+        parallel_for(pairs, [&](int64_t a, int64_t b) {
+            for (int64_t k = a; k < b; ++k) {
+                const int64_t lo = k * 2 * w, mid = std::min(n, lo + w), hi = std::min(n, lo + 2 * w);
+                if (mid < hi) std::inplace_merge(first + lo, first + mid, first + hi);
+            }
+        }, 0);
+    }
+}
 
 // Error reporting ---------------------------------------------------------
 qxa_status fail(qxa_status code, const std::string &msg);
@@ -79,11 +159,11 @@ void lagrange_eval(int dim, int order, const double *xhat, double *phi, double *
 struct HostPlan {
     int64_t n_nodes = 0, n_elem = 0, nnz = 0;
     std::vector<int64_t> row_ptr;
-    std::vector<int32_t> col_idx;
+    hvec<int32_t> col_idx;
     // Element-entry -> CSR slot for every symmetric pair s of every element:
     // perm[s * n_elem + e] = slot of (min(i,j), max(i,j)) (upper triangle).
-    std::vector<uint32_t> perm_sym;
-    std::vector<uint32_t> mirror;     // [nnz]: slot of (j, i) for slot (i, j)
+    hvec<uint32_t> perm_sym;
+    hvec<uint32_t> mirror;            // [nnz]: slot of (j, i) for slot (i, j)
 };
 
 qxa_status build_host_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, const int32_t *conn, HostPlan &hp);
@@ -99,21 +179,22 @@ struct TileParams {
 struct TilePlan {
     int T = 0;
     int64_t n_tiles = 0;
-    std::vector<int32_t> elem_order;  // tile position -> element id (Morton order of centroids)
-    std::vector<int32_t> tconn;       // [np][n_elem] connectivity in tile order
+    hvec<int32_t> elem_order;         // tile position -> element id (Morton order of centroids)
+    hvec<int32_t> tconn;              // [np][n_elem] connectivity in tile order
     // Chain c holds tiles chain_ptr[c] .. chain_ptr[c+1] - 1; a workgroup
     // processes whole chains, so carries never cross a chain.
     std::vector<int64_t> chain_ptr;   // [n_chains + 1]
     int carry_cap = 0, carry_used = 0;
     // Output units of tile t (plan_format.hpp): rec_ptr[t] .. rec_ptr[t+1] - 1,
-    // pair units up to rec_mid[t]. In each group CSR outputs come first in
+    // pair units up to rec_mid[t]. Outputs are ordered CSR outputs first in
     // ascending slot order (upper and mirror entries separately), then carry
-    // outputs, then partials.
-    std::vector<uint32_t> rec;        // [4 * n_units]
+    // outputs, then partials; among single units, outputs of several units
+    // come first.
+    hvec<uint32_t> rec;               // [4 * n_units]
     std::vector<int64_t> rec_ptr;     // [n_tiles + 1] (in units)
     std::vector<int64_t> rec_mid;     // [n_tiles]
     // Partials of shared upper slot k (CSR order) are part_ptr[k] ..
-    // part_ptr[k+1] - 1, in ascending tile order, then chunk order.
+    // part_ptr[k+1] - 1, in ascending tile order.
     std::vector<int64_t> part_ptr;    // [n_shared + 1]
     // fix-up: shared upper slot k (ascending CSR order) and its mirror slot
     std::vector<int32_t> fix_target;  // [n_shared]
@@ -122,7 +203,7 @@ struct TilePlan {
     int64_t n_partials = 0;
     int64_t n_outputs = 0;            // outputs of all tiles
     int64_t n_carry_reads = 0;        // outputs that read a carry entry
-    int64_t n_ext_units = 0;          // single units continued in the thread's next unit
+    int64_t n_ext_units = 0;          // single units continued in the next unit
     int64_t n_empty_units = 0;        // units that store nothing (holes of that layout)
 };
 

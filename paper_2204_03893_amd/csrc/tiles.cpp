@@ -31,22 +31,6 @@
 
 namespace qxa {
 
-template <class F>
-static void parallel_for(int64_t n, F &&f)
-{
-    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    if (n < 64 || nt == 1) {
-        f(int64_t(0), n);
-        return;
-    }
-    std::vector<std::thread> th;
-    int64_t chunk = (n + nt - 1) / nt;
-    for (unsigned t = 0; t < nt; ++t) {
-        int64_t lo = std::min<int64_t>(n, t * chunk), hi = std::min<int64_t>(n, lo + chunk);
-        if (lo < hi) th.emplace_back([&f, lo, hi] { f(lo, hi); });
-    }
-    for (auto &x : th) x.join();
-}
 
 static uint64_t spread_bits(uint64_t x, int dim)
 {
@@ -93,7 +77,7 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
             hi[k] = std::max(hi[k], coords[size_t(k) * n_nodes + v]);
         }
     const double scale = double((1u << 21) - 1);
-    std::vector<std::pair<uint64_t, int32_t>> key(n_elem);
+    hvec<std::pair<uint64_t, int32_t>> key(n_elem);
     parallel_for(n_elem, [&](int64_t a, int64_t b) {
         for (int64_t e = a; e < b; ++e) {
             uint64_t code = 0;
@@ -108,9 +92,11 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
             key[e] = {code, int32_t(e)};
         }
     });
-    std::sort(key.begin(), key.end());
+    parallel_sort(key.begin(), key.end());  // (code, element): no ties
     tp.elem_order.resize(n_elem);
-    for (int64_t p = 0; p < n_elem; ++p) tp.elem_order[p] = key[p].second;
+    parallel_for(n_elem, [&](int64_t a, int64_t b) {
+        for (int64_t p = a; p < b; ++p) tp.elem_order[p] = key[p].second;
+    });
     key.clear();
     key.shrink_to_fit();
     tp.tconn.resize(size_t(np) * n_elem);
@@ -126,72 +112,93 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
     std::vector<int32_t> chain_of(nt);
     for (int64_t c = 0; c < nc; ++c)
         for (int64_t t = tp.chain_ptr[c]; t < tp.chain_ptr[c + 1]; ++t) chain_of[t] = int32_t(c);
-    // 3. per tile: sorted (upper slot, plan order, LDS index) triples; the plan
-    //    order within a slot is ascending local element, then pair
-    auto tile_entries = [&](int64_t t, std::vector<uint64_t> &buf) {
-        buf.clear();
-        const int64_t p0 = t * T, p1 = std::min<int64_t>(n_elem, p0 + T);
-        for (int64_t p = p0; p < p1; ++p) {
-            const int64_t e = tp.elem_order[p];
-            for (int s = 0; s < ns; ++s) {
-                const uint64_t slot = hp.perm_sym[size_t(s) * n_elem + e];
-                const uint64_t lds = uint64_t(s) * (T + 1) + uint64_t(p - p0);
-                const uint64_t ord = uint64_t(p - p0) * ns + s;
-                buf.push_back((slot << 32) | (ord << 16) | lds);
-            }
-        }
-        std::sort(buf.begin(), buf.end());
-    };
-    // 4. number of tiles touching every upper slot
-    const int64_t nnz = hp.nnz;
-    std::vector<std::atomic<int32_t>> ntouch(nnz);
-    parallel_for(nnz, [&](int64_t a, int64_t b) {
-        for (int64_t u = a; u < b; ++u) {
-            ntouch[u].store(0, std::memory_order_relaxed);
-        }
-    });
-
+    // 3. per tile: sorted (upper slot, plan order, LDS index) triples, kept for
+    //    the passes below at ent[p0 * ns ..] (p0 the tile's first position); the
+    //    plan order within a slot is ascending local element, then pair
+    hvec<uint64_t> ent(size_t(n_elem) * ns);
     parallel_for(nt, [&](int64_t a, int64_t b) {
-        std::vector<uint64_t> buf;
         for (int64_t t = a; t < b; ++t) {
-            tile_entries(t, buf);
-            for (size_t k = 0; k < buf.size();) {
-                const uint32_t u = uint32_t(buf[k] >> 32);
-                size_t k1 = k;
-                while (k1 < buf.size() && uint32_t(buf[k1] >> 32) == u) ++k1;
-                ntouch[u].fetch_add(1, std::memory_order_relaxed);
-                k = k1;
-            }
-        }
-    });
-    // 5. multi-tile slots: their touching tiles, sorted, and their chain groups
-    std::vector<int32_t> multi_id(nnz, -1);
-    std::vector<int64_t> mptr(1, 0);
-    std::vector<uint32_t> mslot;
-    for (int64_t u = 0; u < nnz; ++u)
-        if (ntouch[u].load() > 1) {
-            multi_id[u] = int32_t(mslot.size());
-            mslot.push_back(uint32_t(u));
-            mptr.push_back(mptr.back() + ntouch[u].load());
-        }
-    const int64_t nm = int64_t(mslot.size());
-    std::vector<int32_t> mtiles(mptr.back());
-    {
-        std::vector<std::atomic<int32_t>> cur(nm);
-        for (int64_t m = 0; m < nm; ++m) cur[m].store(0, std::memory_order_relaxed);
-        parallel_for(nt, [&](int64_t a, int64_t b) {
-            std::vector<uint64_t> buf;
-            for (int64_t t = a; t < b; ++t) {
-                tile_entries(t, buf);
-                for (size_t k = 0; k < buf.size();) {
-                    const uint32_t u = uint32_t(buf[k] >> 32);
-                    size_t k1 = k;
-                    while (k1 < buf.size() && uint32_t(buf[k1] >> 32) == u) ++k1;
-                    const int32_t m = multi_id[u];
-                    if (m >= 0) mtiles[mptr[m] + cur[m].fetch_add(1, std::memory_order_relaxed)] = int32_t(t);
-                    k = k1;
+            const int64_t p0 = t * T, p1 = std::min<int64_t>(n_elem, p0 + T);
+            uint64_t *out = ent.data() + size_t(p0) * ns;
+            for (int64_t p = p0; p < p1; ++p) {
+                const int64_t e = tp.elem_order[p];
+                for (int s = 0; s < ns; ++s) {
+                    const uint64_t slot = hp.perm_sym[size_t(s) * n_elem + e];
+                    const uint64_t lds = uint64_t(s) * (T + 1) + uint64_t(p - p0);
+                    const uint64_t ord = uint64_t(p - p0) * ns + s;
+                    *out++ = (slot << 32) | (ord << 16) | lds;
                 }
             }
+            std::sort(ent.data() + size_t(p0) * ns, out);
+        }
+    });
+    auto tile_span = [&](int64_t t, const uint64_t *&b, const uint64_t *&e) {
+        b = ent.data() + size_t(t) * T * ns;
+        e = ent.data() + size_t(std::min<int64_t>(n_elem, (t + 1) * T)) * ns;
+    };
+    // the distinct slots of a tile: f(slot, first entry, end of its entries)
+    auto for_slots = [&](int64_t t, auto &&f) {
+        const uint64_t *b, *e;
+        tile_span(t, b, e);
+        for (const uint64_t *k = b; k < e;) {
+            const uint32_t u = uint32_t(*k >> 32);
+            const uint64_t *k1 = k + 1;
+            while (k1 < e && uint32_t(*k1 >> 32) == u) ++k1;
+            f(u, k, k1);
+            k = k1;
+        }
+    };
+    // 4. tiles touching every upper slot; afterwards the same array holds the
+    //    slot's index among the multi-tile slots (-1: one tile)
+    const int64_t nnz = hp.nnz;
+    hvec<int32_t> mid(nnz);
+    parallel_for(nnz, [&](int64_t a, int64_t b) { std::fill(mid.begin() + a, mid.begin() + b, 0); });
+    parallel_for(nt, [&](int64_t a, int64_t b) {
+        for (int64_t t = a; t < b; ++t)
+            for_slots(t, [&](uint32_t u, const uint64_t *, const uint64_t *) {
+                __atomic_fetch_add(&mid[u], 1, __ATOMIC_RELAXED);
+            });
+    });
+    // 5. multi-tile slots (ascending slot order): their touching tiles, sorted,
+    //    and their chain groups
+    const unsigned nth = host_threads();
+    const int64_t uchunk = (nnz + nth - 1) / nth;
+    std::vector<int64_t> cbase(nth + 1, 0);
+    parallel_for(nth, [&](int64_t a, int64_t b) {
+        for (int64_t c = a; c < b; ++c) {
+            int64_t n = 0;
+            for (int64_t u = c * uchunk; u < std::min(nnz, (c + 1) * uchunk); ++u) n += mid[u] > 1;
+            cbase[c + 1] = n;
+        }
+    }, 0);
+    for (unsigned c = 0; c < nth; ++c) cbase[c + 1] += cbase[c];
+    const int64_t nm = cbase[nth];
+    std::vector<uint32_t> mslot(nm);
+    std::vector<int64_t> mptr(nm + 1, 0);
+    parallel_for(nth, [&](int64_t a, int64_t b) {
+        for (int64_t c = a; c < b; ++c) {
+            int64_t m = cbase[c];
+            for (int64_t u = c * uchunk; u < std::min(nnz, (c + 1) * uchunk); ++u) {
+                if (mid[u] > 1) {
+                    mslot[m] = uint32_t(u);
+                    mptr[m + 1] = mid[u];
+                    mid[u] = int32_t(m++);
+                } else {
+                    mid[u] = -1;
+                }
+            }
+        }
+    }, 0);
+    for (int64_t m = 0; m < nm; ++m) mptr[m + 1] += mptr[m];
+    std::vector<int32_t> mtiles(mptr[nm]);
+    {
+        std::vector<int32_t> cur(nm, 0);
+        parallel_for(nt, [&](int64_t a, int64_t b) {
+            for (int64_t t = a; t < b; ++t)
+                for_slots(t, [&](uint32_t u, const uint64_t *, const uint64_t *) {
+                    const int32_t m = mid[u];
+                    if (m >= 0) mtiles[mptr[m] + __atomic_fetch_add(&cur[m], 1, __ATOMIC_RELAXED)] = int32_t(t);
+                });
         });
     }
     std::vector<int64_t> gptr(nm + 1, 0);
@@ -256,10 +263,12 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
         }
     });
     for (int64_t c = 0; c < nc; ++c) tp.carry_used = std::max(tp.carry_used, chain_used[c]);
-    // 7. shared slots (a partial at least) and their partial counts
+    // 7. shared slots (a partial at least) and the index of every partial:
+    //    one per (tile, slot) of role R_PART or R_CARRY_PART, numbered by slot,
+    //    then ascending tile (pidx is parallel to mtiles; -1: no partial)
     auto role_of = [&](uint32_t u, int32_t t, int32_t &carry) -> Role {
         carry = -1;
-        const int32_t m = multi_id[u];
+        const int32_t m = mid[u];
         if (m < 0) return R_OWNED;
         const int32_t c = chain_of[t];
         int64_t g = gptr[m];
@@ -272,62 +281,41 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
         if (t < G.t_last) return R_CARRY_MID;
         return single ? R_CARRY_CSR : R_CARRY_PART;
     };
-    // partials of every shared slot: counted per tile, numbered in ascending
-    // tile order (then chunk order) by a sequential pass
-    std::vector<std::atomic<int32_t>> npart(nnz);
-    parallel_for(nnz, [&](int64_t a, int64_t b) {
-        for (int64_t u = a; u < b; ++u) npart[u].store(0, std::memory_order_relaxed);
-    });
-    std::vector<std::vector<std::pair<uint32_t, int32_t>>> tpart(nt);  // (slot, partials) per tile, slot order
-    parallel_for(nt, [&](int64_t a, int64_t b) {
-        std::vector<uint64_t> buf;
-        for (int64_t t = a; t < b; ++t) {
-            tile_entries(t, buf);
-            tpart[t].clear();
-            for (size_t k = 0; k < buf.size();) {
-                const uint32_t u = uint32_t(buf[k] >> 32);
-                size_t k1 = k;
-                while (k1 < buf.size() && uint32_t(buf[k1] >> 32) == u) ++k1;
-                int32_t carry;
-                const Role r = role_of(u, int32_t(t), carry);
-                int32_t n = 0;
-                if (r == R_PART || r == R_CARRY_PART) n = 1;
-                if (n) {
-                    npart[u].fetch_add(n, std::memory_order_relaxed);
-                    tpart[t].push_back({u, n});
-                }
-                k = k1;
+    std::vector<int32_t> pidx(mptr[nm]);
+    std::vector<int64_t> mpart(nm + 1, 0);
+    parallel_for(nm, [&](int64_t a, int64_t b) {
+        for (int64_t m = a; m < b; ++m) {
+            int32_t n = 0, carry;
+            for (int64_t k = mptr[m]; k < mptr[m + 1]; ++k) {
+                const Role r = role_of(mslot[m], mtiles[k], carry);
+                pidx[k] = (r == R_PART || r == R_CARRY_PART) ? n++ : -1;
             }
+            mpart[m + 1] = n;
         }
     });
-    std::vector<int32_t> sh_id(nnz, -1);
-    std::vector<uint32_t> sh_slot;
-    tp.part_ptr.assign(1, 0);
-    for (int64_t u = 0; u < nnz; ++u)
-        if (npart[u].load() > 0) {
-            sh_id[u] = int32_t(sh_slot.size());
-            sh_slot.push_back(uint32_t(u));
-            tp.part_ptr.push_back(tp.part_ptr.back() + npart[u].load());
-        }
-    tp.n_shared = int64_t(sh_slot.size());
-    tp.n_partials = tp.part_ptr.back();
+    for (int64_t m = 0; m < nm; ++m) mpart[m + 1] += mpart[m];
+    tp.n_partials = mpart[nm];
     if (tp.n_partials >= (int64_t(1) << 30)) return fail(QXA_E_UNSUPPORTED, "too many partials");
     if (nnz >= (int64_t(1) << 30)) return fail(QXA_E_UNSUPPORTED, "more than 2^30 CSR slots");
-    // first partial index of every (tile, shared slot): ascending tile order
-    std::vector<std::vector<int32_t>> tpart_first(nt);
-    {
-        std::vector<int64_t> fill(tp.part_ptr.begin(), tp.part_ptr.end() - 1);
-        for (int64_t t = 0; t < nt; ++t) {
-            tpart_first[t].resize(tpart[t].size());
-            for (size_t k = 0; k < tpart[t].size(); ++k) {
-                const int32_t sid = sh_id[tpart[t][k].first];
-                tpart_first[t][k] = int32_t(fill[sid]);
-                fill[sid] += tpart[t][k].second;
-            }
+    parallel_for(nm, [&](int64_t a, int64_t b) {
+        for (int64_t m = a; m < b; ++m)
+            for (int64_t k = mptr[m]; k < mptr[m + 1]; ++k)
+                if (pidx[k] >= 0) pidx[k] += int32_t(mpart[m]);
+    });
+    tp.part_ptr.assign(1, 0);
+    std::vector<uint32_t> sh_slot;
+    for (int64_t m = 0; m < nm; ++m)
+        if (mpart[m + 1] > mpart[m]) {
+            sh_slot.push_back(mslot[m]);
+            tp.part_ptr.push_back(mpart[m + 1]);
         }
-    }
-    tpart.clear();
-    tpart.shrink_to_fit();
+    tp.n_shared = int64_t(sh_slot.size());
+    // index of the partial of (tile t, slot u) (a multi-tile slot)
+    auto partial_of = [&](uint32_t u, int32_t t) -> int32_t {
+        const int32_t m = mid[u];
+        const int32_t *b = mtiles.data() + mptr[m], *e = mtiles.data() + mptr[m + 1];
+        return pidx[std::lower_bound(b, e, t) - mtiles.data()];
+    };
     // 8. outputs of every tile, packed into units. An output of more than six
     //    entries takes k consecutive single units in one block of kSegLanes
     //    units: all but the last carry the code kCodeExt, and the last one
@@ -343,29 +331,22 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
     std::vector<std::vector<uint32_t>> trec(nt);
     std::vector<int64_t> tpairs(nt, 0), touts(nt, 0), tcin(nt, 0), text(nt, 0), tnone(nt, 0);
     parallel_for(nt, [&](int64_t a, int64_t b) {
-        std::vector<uint64_t> buf;
         std::vector<Out> outs, S, L;
         std::vector<uint16_t> ents;
         std::vector<const Out *> B, O;  // single outputs of several units, of one unit
         for (int64_t t = a; t < b; ++t) {
-            tile_entries(t, buf);
             outs.clear();
             ents.clear();
-            size_t kp = 0;  // next of this tile's partials (slot order)
             auto add = [&](int32_t code, uint8_t kind, int32_t cin, const uint64_t *own, size_t n_own) {
                 outs.push_back(Out{code, kind, uint32_t(n_own + (cin >= 0)), uint32_t(ents.size())});
                 if (cin >= 0) ents.push_back(uint16_t(cb + uint32_t(cin)));
                 for (size_t m = 0; m < n_own; ++m) ents.push_back(uint16_t(own[m] & 0xffff));
                 tcin[t] += cin >= 0;
             };
-            for (size_t k = 0; k < buf.size();) {
-                const uint32_t u = uint32_t(buf[k] >> 32);
-                size_t k1 = k;
-                while (k1 < buf.size() && uint32_t(buf[k1] >> 32) == u) ++k1;
+            for_slots(t, [&](uint32_t u, const uint64_t *own, const uint64_t *own_end) {
                 int32_t carry;
                 const Role r = role_of(u, int32_t(t), carry);
-                const uint64_t *own = buf.data() + k;
-                const size_t n_own = k1 - k;
+                const size_t n_own = size_t(own_end - own);
                 const int32_t mir = int32_t(hp.mirror[u]);
                 switch (r) {
                 case R_OWNED:
@@ -380,13 +361,12 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
                     break;
                 case R_CARRY_PART:
                 case R_PART: {
-                    const int32_t p = tpart_first[t][kp++];
+                    const int32_t p = partial_of(u, int32_t(t));
                     add(-p - 1, 2, r == R_CARRY_PART ? carry : -1, own, n_own);
                     break;
                 }
                 }
-                k = k1;
-            }
+            });
             // CSR outputs, then carries, then partials (partials ascending: codes descending)
             std::sort(outs.begin(), outs.end(), [](const Out &x, const Out &y) {
                 if (x.kind != y.kind) return x.kind < y.kind;
@@ -477,10 +457,12 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
     // fix-up: every shared upper slot (CSR order) and its mirror
     tp.fix_target.resize(sh_slot.size());
     tp.fix_mirror.resize(sh_slot.size());
-    for (size_t k = 0; k < sh_slot.size(); ++k) {
-        tp.fix_target[k] = int32_t(sh_slot[k]);
-        tp.fix_mirror[k] = int32_t(hp.mirror[sh_slot[k]]);
-    }
+    parallel_for(int64_t(sh_slot.size()), [&](int64_t a, int64_t b) {
+        for (int64_t k = a; k < b; ++k) {
+            tp.fix_target[k] = int32_t(sh_slot[k]);
+            tp.fix_mirror[k] = int32_t(hp.mirror[sh_slot[k]]);
+        }
+    });
     return QXA_OK;
 }
 
@@ -517,14 +499,29 @@ qxa_status check_tile_plan(int np, int64_t n_elem, const HostPlan &hp, const Til
         x ^= x >> 29;
         return x;
     };
-    std::vector<uint64_t> expect(nnz, 0), got(nnz, 0), part(tp.n_partials, 0);
-    std::vector<uint8_t> is_up(nnz, 0);
-    for (int64_t e = 0; e < n_elem; ++e)
-        for (int s = 0; s < ns; ++s) {
-            const uint32_t u = hp.perm_sym[size_t(s) * n_elem + e];
-            expect[u] += value(s, e);
-            is_up[u] = 1;
-        }
+    // expected sums (wrapping 64-bit adds, so their order does not matter),
+    // write counts of every slot and partial
+    hvec<uint64_t> expect(nnz), part(tp.n_partials);
+    hvec<uint8_t> is_up(nnz), slot_ws(nnz), part_ws(tp.n_partials);
+    parallel_for(nnz, [&](int64_t a, int64_t b) {
+        std::fill(expect.begin() + a, expect.begin() + b, 0);
+        std::fill(is_up.begin() + a, is_up.begin() + b, 0);
+        std::fill(slot_ws.begin() + a, slot_ws.begin() + b, 0);
+    });
+    parallel_for(tp.n_partials, [&](int64_t a, int64_t b) {
+        std::fill(part.begin() + a, part.begin() + b, 0);
+        std::fill(part_ws.begin() + a, part_ws.begin() + b, 0);
+    });
+    parallel_for(n_elem, [&](int64_t a, int64_t b) {
+        for (int64_t e = a; e < b; ++e)
+            for (int s = 0; s < ns; ++s) {
+                const uint32_t u = hp.perm_sym[size_t(s) * n_elem + e];
+                __atomic_fetch_add(&expect[u], value(s, e), __ATOMIC_RELAXED);
+                __atomic_store_n(&is_up[u], uint8_t(1), __ATOMIC_RELAXED);
+            }
+    });
+    auto expected = [&](int64_t u) { return is_up[u] ? expect[u] : expect[hp.mirror[u]]; };
+    auto write_once = [](uint8_t &w) { return __atomic_fetch_add(&w, uint8_t(1), __ATOMIC_RELAXED) == 0; };
     std::atomic<int> bad{0};
     std::string why;
     std::mutex why_mu;
@@ -532,10 +529,6 @@ qxa_status check_tile_plan(int np, int64_t n_elem, const HostPlan &hp, const Til
         std::lock_guard<std::mutex> lk(why_mu);
         if (!bad.exchange(1)) why = msg;
     };
-    std::vector<std::atomic<uint8_t>> slot_ws(nnz);
-    for (int64_t u = 0; u < nnz; ++u) slot_ws[u].store(0, std::memory_order_relaxed);
-    std::vector<std::atomic<uint8_t>> part_ws(tp.n_partials);
-    for (int64_t k = 0; k < tp.n_partials; ++k) part_ws[k].store(0, std::memory_order_relaxed);
     // chains are independent: their CSR slots, partials and carries are disjoint
     parallel_for(nc, [&](int64_t ca, int64_t cbd) {
         const size_t cap = size_t(std::max(1, tp.carry_cap));
@@ -601,11 +594,14 @@ qxa_status check_tile_plan(int np, int64_t n_elem, const HostPlan &hp, const Til
                     }
                     if (code == kCodeExt) return true;
                     if (code >= 0 && code < kCodeCarry) {
-                        if (code >= nnz || slot_ws[code].fetch_add(1) != 0) {
+                        if (code >= nnz || !write_once(slot_ws[code])) {
                             flag("tile plan: CSR slot written twice or out of range");
                             return false;
                         }
-                        got[code] = acc;
+                        if (acc != expected(code)) {
+                            flag("tile plan: slot sum differs from the element entries");
+                            return false;
+                        }
                     } else if (code >= kCodeCarry && code < kCodeCarryEnd) {
                         const uint32_t k = uint32_t(code - kCodeCarry);
                         if (int(k) >= tp.carry_cap) {
@@ -622,7 +618,7 @@ qxa_status check_tile_plan(int np, int64_t n_elem, const HostPlan &hp, const Til
                         wtile[k] = t;
                     } else if (code < 0) {
                         const int64_t pi = -int64_t(code) - 1;
-                        if (pi >= tp.n_partials || part_ws[pi].fetch_add(1) != 0) {
+                        if (pi >= tp.n_partials || !write_once(part_ws[pi])) {
                             flag("tile plan: partial written twice or out of range");
                             return false;
                         }
@@ -673,7 +669,7 @@ qxa_status check_tile_plan(int np, int64_t n_elem, const HostPlan &hp, const Til
 
     if (bad.load()) return fail(QXA_E_INVALID, why);
     for (int64_t k = 0; k < tp.n_partials; ++k)
-        if (part_ws[k].load() != 1) return fail(QXA_E_INVALID, "tile plan: partial not written exactly once");
+        if (part_ws[k] != 1) return fail(QXA_E_INVALID, "tile plan: partial not written exactly once");
     for (int64_t k = 0; k < tp.n_shared; ++k) {
         const int32_t u = tp.fix_target[k], m = tp.fix_mirror[k];
         if (k > 0 && u <= tp.fix_target[k - 1]) return fail(QXA_E_INVALID, "tile plan: fix-up not sorted");
@@ -682,18 +678,17 @@ qxa_status check_tile_plan(int np, int64_t n_elem, const HostPlan &hp, const Til
         if (tp.part_ptr[k + 1] <= tp.part_ptr[k]) return fail(QXA_E_INVALID, "tile plan: shared slot without partials");
         uint64_t acc = 0;
         for (int64_t q = tp.part_ptr[k]; q < tp.part_ptr[k + 1]; ++q) acc += part[q];
-        if (slot_ws[u].fetch_add(1) != 0) return fail(QXA_E_INVALID, "tile plan: fix-up slot written twice");
-        got[u] = acc;
-        if (m != u) {
-            if (slot_ws[m].fetch_add(1) != 0) return fail(QXA_E_INVALID, "tile plan: fix-up mirror written twice");
-            got[m] = acc;
-        }
+        if (!write_once(slot_ws[u])) return fail(QXA_E_INVALID, "tile plan: fix-up slot written twice");
+        if (m != u && !write_once(slot_ws[m])) return fail(QXA_E_INVALID, "tile plan: fix-up mirror written twice");
+        if (acc != expected(u) || (m != u && acc != expected(m)))
+            return fail(QXA_E_INVALID, "tile plan: slot sum differs from the element entries");
     }
-    for (int64_t u = 0; u < nnz; ++u) {
-        if (slot_ws[u].load() != 1) return fail(QXA_E_INVALID, "tile plan: CSR slot not written exactly once");
-        const uint64_t want = is_up[u] ? expect[u] : expect[hp.mirror[u]];
-        if (got[u] != want) return fail(QXA_E_INVALID, "tile plan: slot sum differs from the element entries");
-    }
+    std::atomic<bool> unwritten{false};
+    parallel_for(nnz, [&](int64_t a, int64_t b) {
+        for (int64_t u = a; u < b; ++u)
+            if (slot_ws[u] != 1) unwritten = true;
+    });
+    if (unwritten) return fail(QXA_E_INVALID, "tile plan: CSR slot not written exactly once");
     return QXA_OK;
 }
 
