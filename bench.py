@@ -121,9 +121,9 @@ def cpu_baseline(w, mesh, rule, u):
 
 def serving_pool(n_pool, max_elements, seed=2204):
     """Heterogeneous request meshes: (dim, order) uniform over {2,3} x {1,2,3}, element count
-    log-uniform on [1e3, max_elements], interior vertices jittered by 0.2h; per mesh four smooth
-    random fields (16 random Fourier features), conductivity exp(g) or 1 + g^2, mass 1, and the
-    rule exact to degree 2P for both matrices."""
+    log-uniform on [1e3, max_elements] (the first mesh at max_elements), interior vertices
+    jittered by 0.2h; per mesh four smooth random fields (16 random Fourier features),
+    conductivity exp(g) or 1 + g^2, mass 1, and the rule exact to degree 2P for both matrices."""
     import numpy as np
     from workloads import rule, structured_mesh
     from workloads.fields import gaussian_random_field
@@ -132,7 +132,7 @@ def serving_pool(n_pool, max_elements, seed=2204):
     for k in range(n_pool):
         dim = int(rng.integers(2, 4))
         order = int(rng.integers(1, 4))
-        ne = float(np.exp(rng.uniform(np.log(1e3), np.log(max_elements))))
+        ne = float(np.exp(rng.uniform(np.log(1e3), np.log(max_elements)))) if k else max_elements
         N = max(2, int(round((ne / 2) ** 0.5 if dim == 2 else (ne / 6) ** (1 / 3))))
         m = structured_mesh(dim, order, N, 0.2, seed=[seed, 6, k])
         fields = [gaussian_random_field(m["coords"], 16, np.random.default_rng([seed, 7, k, j]), length=0.1)
@@ -144,10 +144,14 @@ def serving_pool(n_pool, max_elements, seed=2204):
 
 
 def serving(args):
-    """Serving run: a resident pool of meshes (plans cached by a warm-up pass), then requests
-    picking a mesh and a field at random, at saturation (all queued at once) and at Poisson
-    arrivals with 50% and 80% of the saturation rate. Latency = completion seen by the server
-    - scheduled arrival. Prints one JSON line."""
+    """Serving run: requests pick a pool geometry and one of its fields at random; a
+    fraction new_mesh_fraction of them bring a new mesh (a fresh mesh object the server has
+    no plan for, built on the server's builder thread while other jobs run, and dropped after
+    the job), the others reuse a resident mesh (plans cached by a warm-up pass). Loads:
+    saturation (all queued at once), then Poisson arrivals at 50% and 80% of the saturation
+    rate. Latency = completion seen by the server - scheduled arrival; cold (new mesh) and
+    warm requests are reported apart, with the plan-build share of the cold ones. Prints one
+    JSON line."""
     import numpy as np
     import torch
     import paper_2204_03893_amd as qxa
@@ -160,7 +164,7 @@ def serving(args):
         m = p["mesh"]
         p["obj"] = qxa.Mesh(p["dim"], p["order"], m["coords"], m["conn"])
         p["dev_fields"] = [torch.tensor(f, device=dev) for f in p["fields"]]
-    # warm-up: one job per mesh builds every plan (cold-miss cost, reported separately)
+    # warm-up: one job per resident mesh builds every plan (cold-miss cost, reported separately)
     t0 = time.perf_counter()
     for k, p in enumerate(pool):
         u = p["dev_fields"][0]
@@ -173,27 +177,38 @@ def serving(args):
     for c in warm:
         srv.release(c["ticket"])
     rng = np.random.default_rng([2204, 8])
+    frac = args.new_mesh_fraction
+
+    def pct(x, q):
+        return float(np.percentile(x, q)) if len(x) else None
 
     def run(rate):
         n = args.requests
         picks = rng.integers(0, len(pool), size=n)
         fsel = rng.integers(0, 4, size=n)
+        cold = rng.uniform(size=n) < frac
         gaps = rng.exponential(1.0 / rate, size=n) if rate else np.zeros(n)
         sched = np.cumsum(gaps)
-        lat, waits, entries, done = [], [], 0, 0
+        lat, plan_ms, is_cold, waits, entries, done = [], [], [], [], 0, 0
         paused = not rate
         if paused:
             srv.pause(True)
         t_start = time.perf_counter()
-        submit_late = {}
+        submit_late, fresh = {}, {}
         i = 0
         while done < n:
             now = time.perf_counter() - t_start
             while i < n and sched[i] <= now:
                 p = pool[picks[i]]
                 u = p["dev_fields"][fsel[i]]
-                t = srv.submit(p["obj"], p["rule"], p["rule"], ("const", 1.0), p["law_c"], u, u,
+                mo = p["obj"]
+                if cold[i]:  # the request brings its mesh: uploaded and checked now
+                    m = p["mesh"]
+                    mo = qxa.Mesh(p["dim"], p["order"], m["coords"], m["conn"])
+                t = srv.submit(mo, p["rule"], p["rule"], ("const", 1.0), p["law_c"], u, u,
                                precision=args.precision, tag=i)
+                if cold[i]:
+                    fresh[t] = mo
                 submit_late[t] = (time.perf_counter() - t_start - sched[i]) * 1e3
                 i += 1
                 now = time.perf_counter() - t_start
@@ -205,17 +220,30 @@ def serving(args):
                 if c["status"] != 0:
                     raise RuntimeError(f"serving request failed: {c}")
                 lat.append(submit_late.pop(c["ticket"]) + c["total_ms"])
+                plan_ms.append(c["plan_ms"])
+                is_cold.append(c["ticket"] in fresh)
                 waits.append(c["queue_ms"])
                 entries += pool[picks[c["tag"]]]["entries"]
                 srv.release(c["ticket"])
+                if c["ticket"] in fresh:
+                    mo = fresh.pop(c["ticket"])
+                    srv.drop_mesh(mo)
+                    mo.close()
                 done += 1
             if i == n and done < n:
                 time.sleep(0.0001)
         span = time.perf_counter() - (t_start_sat if not rate else t_start)
-        lat = np.array(lat)
-        return {"offered_jobs_per_s": rate, "jobs": n, "makespan_s": span, "jobs_per_s": n / span,
-                "entries_per_s": entries / span, "p50_ms": float(np.percentile(lat, 50)),
-                "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+        lat, plan_ms, is_cold = np.array(lat), np.array(plan_ms), np.array(is_cold, dtype=bool)
+        lc, lw = lat[is_cold], lat[~is_cold]
+        return {"offered_jobs_per_s": rate, "jobs": n, "new_meshes": int(is_cold.sum()), "makespan_s": span,
+                "jobs_per_s": n / span, "entries_per_s": entries / span,
+                "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "mean_ms": float(lat.mean()),
+                "cold": {"p50_ms": pct(lc, 50), "p99_ms": pct(lc, 99),
+                         "mean_ms": float(lc.mean()) if lc.size else None,
+                         "mean_plan_ms": float(plan_ms[is_cold].mean()) if lc.size else None,
+                         "plan_share": float(plan_ms[is_cold].sum() / lc.sum()) if lc.size else None},
+                "warm": {"p50_ms": pct(lw, 50), "p99_ms": pct(lw, 99),
+                         "mean_ms": float(lw.mean()) if lw.size else None},
                 "mean_queue_ms": float(np.mean(waits))}
 
     sat = run(0.0)
@@ -228,7 +256,7 @@ def serving(args):
            "dtype": "f64" if args.precision == "fp64" else args.precision, "vs_baseline": None,
            "config": {"workload": "serving mix", "pool_meshes": len(pool), "elements_min": min(sizes),
                       "elements_max": max(sizes), "requests_per_load": args.requests, "precision": args.precision,
-                      "budget_gib": args.budget_gib},
+                      "new_mesh_fraction": frac, "budget_gib": args.budget_gib},
            "saturation": sat, "loads": loads, "warmup_plan_builds_s": warm_s, "pool_generation_s": gen_s,
            "server": st}
     print(json.dumps(out))
@@ -525,7 +553,9 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) to calibrate HBM byte counters")
     ap.add_argument("--mode", choices=("assemble", "serving", "reassembly", "tangent", "paper"), default="assemble")
-    ap.add_argument("--requests", type=int, default=10000, help="serving: requests per offered load")
+    ap.add_argument("--requests", type=int, default=300, help="serving: requests per offered load")
+    ap.add_argument("--new-mesh-fraction", type=float, default=0.7,
+                    help="serving: share of requests that bring a mesh the server has not seen")
     ap.add_argument("--pool", type=int, default=48, help="serving: resident meshes")
     ap.add_argument("--max-elements", type=float, default=1e6, help="serving: largest mesh (elements)")
     ap.add_argument("--budget-gib", type=int, default=160, help="serving: device memory budget of the server (GiB)")

@@ -52,7 +52,7 @@ typedef enum {
     QXA_E_NOMEM = -5,       /* device or host allocation failed / over budget      */
     QXA_E_UNSUPPORTED = -6, /* (dim, order, n_q, precision) combination not built   */
     QXA_E_HIP = -7,         /* HIP runtime error                                    */
-    QXA_E_BUSY = -8         /* server queue full                                    */
+    QXA_E_BUSY = -8         /* server queue full, or a mesh still in use            */
 } qxa_status;
 
 /* Arithmetic of the contraction V = Q X. Geometry (B_e, |det B_e|, W) and the
@@ -368,7 +368,8 @@ qxa_status qxa_graph_destroy(qxa_graph graph);
  * - Plans (pattern, permutation, tiles, reference tables) stay resident in an
  *   LRU cache keyed by mesh and rule pair: only S changes between assemblies
  *   of one mesh (Section 5, summary), so a cache hit skips the plan build.
- *   Plans of new meshes are built by a second thread while other jobs run.
+ *   Plans of new meshes are built by plan_builders host threads while other
+ *   jobs run (a small mesh need not wait behind a large one).
  *   Unreferenced plans are evicted (least recently used first) when the
  *   budget is short or more than plan_cache_entries are resident.
  * - Admitted jobs with fewer than batch_tile_limit element tiles that share a
@@ -382,9 +383,10 @@ qxa_status qxa_graph_destroy(qxa_graph graph);
  * - qxa_server_poll returns completed jobs (including failed ones, with their
  *   status). Every polled ticket must be released with qxa_server_release,
  *   which returns its buffers to the budget. Results live on the device.
- * Meshes must outlive the server; coefficient fields must stay valid and
- * unchanged until the job completes. One server per device; all functions
- * are thread-safe.
+ * A mesh must outlive its jobs and resident plans: once every job on it is
+ * released, qxa_server_drop_mesh frees its plans and the mesh may be
+ * destroyed. Coefficient fields must stay valid and unchanged until the job
+ * completes. One server per device; all functions are thread-safe.
  */
 typedef struct {
     int device;
@@ -394,6 +396,7 @@ typedef struct {
     int64_t batch_tile_limit; /* jobs with fewer tiles are batched (0: 512)           */
     int queue_capacity;       /* waiting jobs beyond which submit fails (0: 65536)    */
     int plan_cache_entries;   /* resident plans kept (0: bounded by the budget only)  */
+    int plan_builders;        /* host threads building plans of new meshes (0: 4)     */
 } qxa_server_opts;
 
 typedef struct {
@@ -416,6 +419,7 @@ typedef struct {
     double queue_ms;          /* submit -> launch (host clock)                      */
     double run_ms;            /* its launch on the device (HIP events)              */
     double total_ms;          /* submit -> completion seen by the server            */
+    double plan_ms;           /* submit -> its plan resident (0 for a resident plan) */
     char message[160];        /* error text when status != QXA_OK                   */
 } qxa_completion;
 
@@ -435,6 +439,11 @@ qxa_status qxa_server_copy_result(qxa_server server, uint64_t ticket, double *M_
 qxa_status qxa_server_release(qxa_server server, uint64_t ticket);
 /* paused != 0: admit nothing (submissions still queue); 0: resume. */
 qxa_status qxa_server_pause(qxa_server server, int paused);
+/* Frees the resident plans of `mesh` (a client done with a mesh, for instance a
+ * request that brought a new one), after which the caller may destroy it.
+ * QXA_E_BUSY while a job on the mesh is queued, running or not released, or a
+ * plan of it is being built. */
+qxa_status qxa_server_drop_mesh(qxa_server server, qxa_mesh mesh);
 /* counters: [0] submitted [1] completed [2] plan-cache hits [3] plan builds
  * [4] evictions [5] launches [6] batched launches [7] most jobs in one launch
  * [8] budget bytes in use [9] peak bytes in use [10] queued [11] in flight

@@ -60,7 +60,7 @@ _TILE_FIELDS = ("nnz", "n_tiles", "n_shared", "n_partials", "n_outputs", "n_unit
 class _ServerOpts(C.Structure):
     _fields_ = [("device", C.c_int), ("hbm_budget_bytes", C.c_size_t), ("max_inflight", C.c_int),
                 ("n_streams", C.c_int), ("batch_tile_limit", C.c_int64), ("queue_capacity", C.c_int),
-                ("plan_cache_entries", C.c_int)]
+                ("plan_cache_entries", C.c_int), ("plan_builders", C.c_int)]
 
 
 class _Job(C.Structure):
@@ -72,7 +72,8 @@ class _Completion(C.Structure):
     _fields_ = [("ticket", C.c_uint64), ("user_tag", C.c_uint64), ("status", C.c_int), ("plan_cached", C.c_int),
                 ("batched", C.c_int), ("n_nodes", C.c_int64), ("nnz", C.c_int64), ("M", C.c_void_p),
                 ("C", C.c_void_p), ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("queue_ms", C.c_double),
-                ("run_ms", C.c_double), ("total_ms", C.c_double), ("message", C.c_char * 160)]
+                ("run_ms", C.c_double), ("total_ms", C.c_double), ("plan_ms", C.c_double),
+                ("message", C.c_char * 160)]
 
 
 SERVER_STATS = ("submitted", "completed", "plan_hits", "plan_builds", "evictions", "launches", "batched_launches",
@@ -120,6 +121,7 @@ def lib():
         L.qxa_server_copy_result.argtypes = [vp, C.c_uint64, vp, vp, vp]
         L.qxa_server_release.argtypes = [vp, C.c_uint64]
         L.qxa_server_pause.argtypes = [vp, ci]
+        L.qxa_server_drop_mesh.argtypes = [vp, vp]
         L.qxa_server_stats.argtypes = [vp, C.POINTER(i64), ci]
         L.qxa_server_destroy.argtypes = [vp]
         for name in ("qxa_mesh_create", "qxa_mesh_destroy", "qxa_plan_create", "qxa_plan_destroy",
@@ -127,7 +129,8 @@ def lib():
                      "qxa_element_matrices_noalloc",
                      "qxa_sync", "qxa_pattern_host", "qxa_plan_check_host", "qxa_plan_set_timing", "qxa_plan_timing_report", "qxa_graph_create", "qxa_graph_launch",
                      "qxa_graph_destroy", "qxa_server_create", "qxa_server_submit", "qxa_server_poll",
-                     "qxa_server_copy_result", "qxa_server_release", "qxa_server_pause", "qxa_server_stats", "qxa_server_destroy"):
+                     "qxa_server_copy_result", "qxa_server_release", "qxa_server_pause", "qxa_server_drop_mesh", "qxa_server_stats",
+                     "qxa_server_destroy"):
             getattr(L, name).restype = ci
         _lib = L
     return _lib
@@ -563,9 +566,9 @@ class Server:
     """
 
     def __init__(self, device=0, hbm_budget=4 << 30, max_inflight=64, n_streams=4, batch_tile_limit=512,
-                 queue_capacity=65536, plan_cache_entries=0):
+                 queue_capacity=65536, plan_cache_entries=0, plan_builders=0):
         o = _ServerOpts(int(device), int(hbm_budget), int(max_inflight), int(n_streams), int(batch_tile_limit),
-                        int(queue_capacity), int(plan_cache_entries))
+                        int(queue_capacity), int(plan_cache_entries), int(plan_builders))
         self.device = device
         self.handle = C.c_void_p()
         check(lib().qxa_server_create(C.byref(o), C.byref(self.handle)))
@@ -601,7 +604,8 @@ class Server:
             self._nnz[c.ticket] = int(c.nnz)
             out.append({"ticket": c.ticket, "tag": c.user_tag, "status": c.status, "plan_cached": bool(c.plan_cached),
                         "batched": c.batched, "n_nodes": c.n_nodes, "nnz": c.nnz, "queue_ms": c.queue_ms,
-                        "run_ms": c.run_ms, "total_ms": c.total_ms, "message": c.message.decode()})
+                        "run_ms": c.run_ms, "total_ms": c.total_ms, "plan_ms": c.plan_ms,
+                        "message": c.message.decode()})
         return out
 
     def result(self, ticket, stream=None):
@@ -617,6 +621,12 @@ class Server:
     def release(self, ticket):
         self._nnz.pop(ticket, None)
         check(lib().qxa_server_release(self.handle, C.c_uint64(ticket)))
+
+    def drop_mesh(self, mesh: Mesh):
+        """Free the server's plans of a mesh whose jobs are all released (QxaError
+        QXA_E_BUSY otherwise); the mesh may then be closed."""
+        check(lib().qxa_server_drop_mesh(self.handle, mesh.handle))
+        self._meshes.pop(id(mesh), None)
 
     def pause(self, paused=True):
         """Stop (True) or resume (False) admission; submissions keep queueing."""

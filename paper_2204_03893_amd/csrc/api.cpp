@@ -448,6 +448,15 @@ qxa_status plan_stage(qxa_mesh mesh, const qxa_quad &mr, const qxa_quad &cr, Pla
     return QXA_OK;
 }
 
+size_t plan_bytes_lower_bound(const PlanStaging &g)
+{
+    const HostPlan &hp = g.hp;
+    const TilePlan &tp = g.tp;
+    return sizeof(int64_t) * (hp.row_ptr.size() + tp.rec_ptr.size() + tp.rec_mid.size()) +
+           sizeof(int32_t) * (hp.col_idx.size() + tp.tconn.size() + tp.elem_order.size()) +
+           sizeof(uint32_t) * tp.rec.size();
+}
+
 qxa_status plan_upload(qxa_mesh mesh, const PlanStaging &g, DevArena *arena, bool own_scratch, qxa_plan *out)
 {
     *out = nullptr;

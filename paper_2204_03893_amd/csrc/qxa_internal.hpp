@@ -66,7 +66,7 @@ inline unsigned host_threads() { return std::max(1u, std::min(16u, std::thread::
 
 // f(lo, hi) over [0, n) cut into one contiguous range per host thread.
 template <class F>
-void parallel_for(int64_t n, F &&f, int64_t serial_below = 64)
+void parallel_for(int64_t n, F &&f, int64_t serial_below = 2048)
 {
     const unsigned nt = host_threads();
     if (n < serial_below || nt == 1) {
@@ -256,6 +256,8 @@ qxa_status plan_stage(qxa_mesh mesh, const qxa_quad &mr, const qxa_quad &cr, Pla
 // when it is full) and the plan keeps no scratch of its own (own_scratch =
 // false: the caller brings partial-sum and flag buffers per assembly).
 qxa_status plan_upload(qxa_mesh mesh, const PlanStaging &stg, DevArena *arena, bool own_scratch, qxa_plan *out);
+// Device bytes of a staged plan's largest arrays (a lower bound of its size).
+size_t plan_bytes_lower_bound(const PlanStaging &stg);
 
 }  // namespace qxa
 

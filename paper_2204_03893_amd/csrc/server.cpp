@@ -122,6 +122,7 @@ struct CacheEntry {
     qxa_plan plan = nullptr;
     int refs = 0;           // unreleased admitted jobs
     uint64_t last_use = 0;
+    Clock::time_point t_ready;  // when the plan became resident
 };
 
 struct Job {
@@ -132,6 +133,7 @@ struct Job {
     PlanKey key;
     CacheEntry *entry = nullptr;
     int plan_cached = -1;  // unknown until the first cache lookup
+    double plan_ms = 0.0;  // submit -> plan resident, for a job whose plan was not
     Clock::time_point t_submit, t_launch, t_done;
     void *buf = nullptr;
     double *M = nullptr, *C = nullptr;
@@ -185,9 +187,11 @@ struct qxa_server_s {
     std::deque<CacheEntry *> build_q;
     int inflight = 0;  // admitted + running
     int holders = 0;   // jobs holding job buffers
+    int uploading = 0; // builders copying a plan into the budget
     int64_t n_submitted = 0, n_completed = 0, n_hits = 0, n_builds = 0, n_evictions = 0, n_launches = 0,
             n_batched = 0, max_batch = 0;
-    std::thread worker, builder;
+    std::thread worker;
+    std::vector<std::thread> builders;
 };
 
 namespace qxa {
@@ -312,6 +316,7 @@ static bool admit(qxa_server s)
             ++it;
             continue;
         }
+        if (j->plan_cached == 0) j->plan_ms = std::max(0.0, ms_between(j->t_submit, ce->t_ready));
         qxa_plan p = ce->plan;
         const size_t need = job_bytes(p);
         void *buf = s->arena.alloc(need);
@@ -518,16 +523,20 @@ static void builder_main(qxa_server s)
         qxa_plan p = nullptr;
         lk.lock();
         while (!st && !s->stop) {
+            ++s->uploading;
             lk.unlock();
-            st = plan_upload(mesh, stg, &s->arena, false, &p);
+            st = plan_upload(mesh, stg, &s->arena, false, &p);  // frees what it took when it fails
             if (st) msg = qxa_last_error();
             lk.lock();
+            --s->uploading;
             if (st != QXA_E_NOMEM) break;
             if (evict_one(s) || (s->holders == 0 && evict_one(s, true))) {
                 st = QXA_OK;
                 continue;
             }
-            if (s->holders == 0) {
+            // nothing left to evict: wait for released results or other builders'
+            // uploads, unless the plan could not fit even in an empty budget
+            if ((s->holders == 0 && s->uploading == 0) || plan_bytes_lower_bound(stg) > s->arena.capacity()) {
                 msg = "plan exceeds the device budget";
                 break;
             }
@@ -551,11 +560,13 @@ static void builder_main(qxa_server s)
         } else {
             ce->plan = p;
             ce->ready = true;
+            ce->t_ready = Clock::now();
             ce->last_use = ++s->use_clock;
             if (s->o.plan_cache_entries > 0)
                 while (int(s->cache.size()) > s->o.plan_cache_entries && evict_one(s)) {
                 }
         }
+        s->cv_mem.notify_all();  // builders waiting for memory look again
         s->cv_work.notify_one();
     }
 }
@@ -599,8 +610,10 @@ qxa_status qxa_server_create(const qxa_server_opts *opts, qxa_server *out)
     if (o.n_streams == 0) o.n_streams = 4;
     if (o.batch_tile_limit == 0) o.batch_tile_limit = 512;
     if (o.queue_capacity == 0) o.queue_capacity = 65536;
+    if (o.plan_builders == 0) o.plan_builders = 4;
     if (o.max_inflight < 1 || o.max_inflight > 4096 || o.n_streams < 1 || o.n_streams > 32 ||
-        o.batch_tile_limit < 0 || o.queue_capacity < 1 || o.plan_cache_entries < 0)
+        o.batch_tile_limit < 0 || o.queue_capacity < 1 || o.plan_cache_entries < 0 || o.plan_builders < 1 ||
+        o.plan_builders > 64)
         return fail(QXA_E_INVALID, "server options out of range");
     QXA_HIP(hipSetDevice(o.device));
     auto *s = new qxa_server_s();
@@ -633,7 +646,7 @@ qxa_status qxa_server_create(const qxa_server_opts *opts, qxa_server *out)
         return st;
     }
     s->worker = std::thread(worker_main, s);
-    s->builder = std::thread(builder_main, s);
+    for (int k = 0; k < o.plan_builders; ++k) s->builders.emplace_back(builder_main, s);
     *out = s;
     return QXA_OK;
 }
@@ -694,6 +707,7 @@ qxa_status qxa_server_poll(qxa_server s, qxa_completion *out, int max, int *n_do
         c.user_tag = j->spec.user_tag;
         c.status = j->status;
         c.plan_cached = j->plan_cached > 0;
+        c.plan_ms = j->plan_ms;
         c.batched = j->batched;
         c.n_nodes = j->spec.mesh->n_nodes;
         if (j->status == QXA_OK) {
@@ -792,6 +806,27 @@ qxa_status qxa_server_release(qxa_server s, uint64_t ticket)
     return QXA_OK;
 }
 
+qxa_status qxa_server_drop_mesh(qxa_server s, qxa_mesh mesh)
+{
+    if (!s || !mesh) return fail(QXA_E_INVALID, "null argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (const auto &kv : s->jobs)
+        if (kv.second->spec.mesh == mesh) return fail(QXA_E_BUSY, "jobs on this mesh are not released yet");
+    for (const auto &kv : s->cache)
+        if (kv.second->mesh == mesh && !kv.second->ready) return fail(QXA_E_BUSY, "a plan of this mesh is being built");
+    for (auto it = s->cache.begin(); it != s->cache.end();) {
+        if (it->second->mesh == mesh) {
+            qxa_plan_destroy(it->second->plan);
+            it = s->cache.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    s->cv_mem.notify_all();
+    s->cv_work.notify_one();
+    return QXA_OK;
+}
+
 qxa_status qxa_server_pause(qxa_server s, int paused)
 {
     if (!s) return fail(QXA_E_INVALID, "null server");
@@ -833,7 +868,8 @@ qxa_status qxa_server_destroy(qxa_server s)
     s->cv_build.notify_all();
     s->cv_mem.notify_all();
     if (s->worker.joinable()) s->worker.join();
-    if (s->builder.joinable()) s->builder.join();
+    for (std::thread &b : s->builders)
+        if (b.joinable()) b.join();
     server_free(s);
     return QXA_OK;
 }

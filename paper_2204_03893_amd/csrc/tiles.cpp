@@ -131,7 +131,7 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
             }
             std::sort(ent.data() + size_t(p0) * ns, out);
         }
-    });
+    }, 16);
     auto tile_span = [&](int64_t t, const uint64_t *&b, const uint64_t *&e) {
         b = ent.data() + size_t(t) * T * ns;
         e = ent.data() + size_t(std::min<int64_t>(n_elem, (t + 1) * T)) * ns;
@@ -158,7 +158,7 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
             for_slots(t, [&](uint32_t u, const uint64_t *, const uint64_t *) {
                 __atomic_fetch_add(&mid[u], 1, __ATOMIC_RELAXED);
             });
-    });
+    }, 16);
     // 5. multi-tile slots (ascending slot order): their touching tiles, sorted,
     //    and their chain groups
     const unsigned nth = host_threads();
@@ -199,7 +199,7 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
                     const int32_t m = mid[u];
                     if (m >= 0) mtiles[mptr[m] + __atomic_fetch_add(&cur[m], 1, __ATOMIC_RELAXED)] = int32_t(t);
                 });
-        });
+        }, 16);
     }
     std::vector<int64_t> gptr(nm + 1, 0);
     std::vector<Group> groups;
@@ -261,7 +261,7 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
             }
             chain_used[c] = used;
         }
-    });
+    }, 2);
     for (int64_t c = 0; c < nc; ++c) tp.carry_used = std::max(tp.carry_used, chain_used[c]);
     // 7. shared slots (a partial at least) and the index of every partial:
     //    one per (tile, slot) of role R_PART or R_CARRY_PART, numbered by slot,
@@ -435,7 +435,7 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
                 }
             }
         }
-    });
+    }, 16);
     if (too_long) return fail(QXA_E_INVALID, "tile plan: an output of more entries than one wave's units hold");
     tp.rec_ptr.assign(nt + 1, 0);
     tp.rec_mid.assign(nt, 0);
@@ -453,7 +453,7 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
             std::copy(trec[t].begin(), trec[t].end(), tp.rec.begin() + 4 * tp.rec_ptr[t]);
             std::vector<uint32_t>().swap(trec[t]);
         }
-    });
+    }, 16);
     // fix-up: every shared upper slot (CSR order) and its mirror
     tp.fix_target.resize(sh_slot.size());
     tp.fix_mirror.resize(sh_slot.size());
@@ -665,7 +665,7 @@ qxa_status check_tile_plan(int np, int64_t n_elem, const HostPlan &hp, const Til
                 }
             }
         }
-    });
+    }, 2);
 
     if (bad.load()) return fail(QXA_E_INVALID, why);
     for (int64_t k = 0; k < tp.n_partials; ++k)

@@ -228,3 +228,72 @@ def test_release_right_after_result_keeps_the_copied_values():
     srv.release(t2)
     plan.close()
     srv.close()
+
+
+def test_jobs_submitted_mid_flight_match_alone_bitwise():
+    """Jobs submitted while others are queued or running (no pause), some on meshes the
+    server has not seen (their plans are built while other jobs run), in FP64 and FP32:
+    each result is bitwise equal to the same job assembled alone. A new mesh's plans are
+    freed by drop_mesh once its jobs are released (QXA_E_BUSY before)."""
+    import time
+    import paper_2204_03893_amd as qxa
+    srv = qxa.Server(max_inflight=16, n_streams=4, batch_tile_limit=512)
+    rng = np.random.default_rng(77)
+    specs = []
+    big = _mesh(3, 2, 9, seed=300)
+    specs.append((big, qxa.Mesh(3, 2, big["coords"], big["conn"]), rule(3, 4)))
+    for si, (dim, order, N) in enumerate(SHAPES):
+        m = _mesh(dim, order, N + 1, seed=310 + si)
+        specs.append((m, qxa.Mesh(dim, order, m["coords"], m["conn"]), rule(dim, 2 * order)))
+    jobs, mid_flight, new_meshes = {}, 0, []
+
+    def submit(m, mo, r, precision, seed):
+        nonlocal mid_flight
+        st = srv.stats()
+        mid_flight += (st["in_flight"] + st["queued"]) > 0
+        u = torch.tensor(_field(m, seed), device="cuda")
+        t = srv.submit(mo, r, r, LAW_M, LAW_C, u, u, precision=precision, tag=len(jobs))
+        jobs[t] = (mo, r, u, precision)
+
+    submit(*specs[0], "fp64", 400)
+    results = {}
+    for wave in range(4):
+        for k in range(len(specs)):
+            m, mo, r = specs[int(rng.integers(1, len(specs)))]
+            submit(m, mo, r, "fp64" if k % 2 == 0 else "fp32", 500 + 10 * wave + k)
+        # a mesh the server has not seen, submitted while the others run
+        dim, order, N = SHAPES[wave % len(SHAPES)]
+        m = _mesh(dim, order, N + 2, seed=600 + wave)
+        mo = qxa.Mesh(dim, order, m["coords"], m["conn"])
+        new_meshes.append(mo)
+        submit(m, mo, rule(dim, 2 * order), "fp64", 700 + wave)
+        for c in srv.poll():
+            results[c["ticket"]] = c
+        time.sleep(0.002)
+    while len(results) < len(jobs):
+        for c in srv.wait(1, timeout_s=120):
+            results[c["ticket"]] = c
+    print("mid-flight submissions", mid_flight, "of", len(jobs), srv.stats(), flush=True)
+    assert mid_flight >= len(jobs) // 2
+    cold = [c for c in results.values() if not c["plan_cached"]]
+    assert cold and all(c["plan_ms"] > 0.0 for c in cold)
+    with pytest.raises(qxa.QxaError) as ei:       # its jobs are not released yet
+        srv.drop_mesh(new_meshes[0])
+    assert ei.value.code == -8
+    plans = {}
+    for t, c in results.items():
+        assert c["status"] == 0, c
+        mo, r, u, precision = jobs[t]
+        M, Cv = srv.result(t)
+        torch.cuda.synchronize()
+        srv.release(t)
+        key = id(mo)
+        if key not in plans:
+            plans[key] = qxa.Plan(mo, r)
+        Ma, Ca = qxa.assemble(plans[key], LAW_M, LAW_C, u, u, precision=precision)
+        qxa.sync(plans[key])
+        assert torch.equal(M.view(torch.int64), Ma.view(torch.int64)), (t, precision)
+        assert torch.equal(Cv.view(torch.int64), Ca.view(torch.int64)), (t, precision)
+    for mo in new_meshes:
+        srv.drop_mesh(mo)
+    srv.close()
