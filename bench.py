@@ -550,6 +550,7 @@ def main():
     ap.add_argument("--workload", default="p3_2d_1024")
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip timing the other precision forms")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) to calibrate HBM byte counters")
     ap.add_argument("--mode", choices=("assemble", "serving", "reassembly", "tangent", "paper"), default="assemble")
@@ -667,6 +668,45 @@ def main():
     path = {"bytes": fb, "ms": ms, "achieved_gbs": fb / (ms * 1e-3) / 1e9,
             "frac": fb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
+    # every precision form of the kernel on the same workload: time per assembly and
+    # row-scaled error against this run's FP64 values (max_ij |v - v64| / max_k |v64_ik|;
+    # the FP64 path itself is held to 1e-12 of the oracle by the test suite)
+    forms = {}
+    if not args.no_forms:
+        rp, _ = plan.pattern()
+        rows = torch.repeat_interleave(torch.arange(plan.n_nodes, device=dev), torch.diff(rp))
+        M64, C64 = torch.empty_like(M), torch.empty_like(Cv)
+        qxa.assemble(plan, w.mass_law, w.stiff_law, uf, uf, precision="fp64", M=M64, Cv=C64, stream=stream)
+
+        def row_err(x, ref):
+            rmax = torch.zeros(plan.n_nodes, dtype=torch.float64, device=dev)
+            rmax.scatter_reduce_(0, rows, ref.abs(), reduce="amax")
+            rmax = torch.where(rmax == 0, torch.ones_like(rmax), rmax)
+            return float(((x - ref).abs() / rmax[rows]).max())
+
+        M2, C2 = torch.empty_like(M), torch.empty_like(Cv)
+        for form in ("fp64", "fp32", "f16x2", "bf16x3", "bf16x2"):
+            def fstep():
+                qxa.assemble(plan, w.mass_law, w.stiff_law, uf, uf, precision=form, M=M2, Cv=C2, stream=stream)
+            try:
+                fstep()
+            except qxa.QxaError as e:
+                forms[form] = {"supported": False, "reason": str(e)}
+                continue
+            n_f = max(1, min(50, args.steps))
+            for _ in range(3):
+                fstep()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(n_f):
+                fstep()
+            b.record(stream)
+            torch.cuda.synchronize()
+            qxa.sync(plan, stream)
+            forms[form] = {"supported": True, "ms": a.elapsed_time(b) / n_f, "steps": n_f,
+                           "row_scaled_err_vs_fp64": {"M": row_err(M2, M64), "C": row_err(C2, C64)}}
+        del rows, M64, C64, M2, C2
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(w, mesh, rule, u)
@@ -698,6 +738,7 @@ def main():
                      "algorithmic_bytes": ab, "kernel_ms": kern[dom], "path": path, "per_kernel": per_kernel},
         "path_floor": {"bytes": fb, "frac_of_hbm_peak": path["frac"]},
         "kernels_ms": kern,
+        "precision_forms": forms,
         "single_assembly": single,
         "plan_build_s": plan_s,
         "wall_s_timed_region": wall,
