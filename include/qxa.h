@@ -312,13 +312,12 @@ qxa_status qxa_load_vector(qxa_plan plan, const qxa_coeff *f, double *F, void *s
  * so B, |det B| and A = B^{-1} K B^{-T} are evaluated at every quadrature node (X_m and
  * X_c per (q, e); Q_m and Q_c unchanged). Same coefficients, outputs and pattern as
  * qxa_assemble, in FP64. Two passes: the local matrices of every element (X per
- * quadrature node, then V = Q X, once per symmetric pair) to a plan-owned buffer, then
- * one thread per upper CSR slot sums the slot's element entries in ascending element
- * order and writes the slot and its mirror (deterministic, bitwise symmetric). The
- * first call on a plan builds the upper slot -> entries map on the host (4 n_s n_elem
- * + 16 n_up bytes, n_s = n_p (n_p + 1) / 2, n_up upper slots) and allocates
- * 16 n_s n_elem bytes of local matrices (n_elem rounded up to a multiple of 64); later
- * calls allocate nothing. Errors as
+ * quadrature node, then V = Q X, once per symmetric pair) to a plan-owned buffer in the
+ * plan's tile order, then the reduction of the fused assembly (the plan's output units,
+ * chains and carries, and its fix-up) sums every CSR slot in the plan's fixed order
+ * (deterministic, bitwise symmetric). The first call on a plan allocates
+ * 16 n_s n_elem bytes of local matrices (n_s = n_p (n_p + 1) / 2, n_elem rounded up to
+ * a multiple of 64); later calls allocate nothing. Errors as
  * qxa_assemble, plus QXA_E_UNSUPPORTED when n_s n_elem >= 2^31 and QXA_E_INVALID for
  * tensor_q on the mass coefficient or with tensor; a non-finite coefficient or tensor
  * entry, or a map with det B_q = 0 at a quadrature node, is reported by qxa_sync as

@@ -391,8 +391,7 @@ qxa_status qxa_plan_destroy(qxa_plan p)
                     p->d_chain_ptr,
                     p->d_part_ptr, p->d_fix_target, p->d_fix_mirror, p->d_sink, p->d_part, p->d_qfrag[0],
                     p->d_qfrag[1], p->d_qfrag[2], p->d_qfrag[3], p->d_qfrag[4], p->d_tables, p->d_tables_f,
-                    p->d_V, p->d_flags, p->d_T, p->d_ns_ptr, p->d_ns_items, p->d_Fe, p->d_nf_ptr, p->d_nf_items, p->d_Tiso,
-                    p->d_nu_ptr, p->d_nu_items, p->d_nu_pos, p->d_nu_mirror};
+                    p->d_V, p->d_flags, p->d_T, p->d_ns_ptr, p->d_ns_items, p->d_Fe, p->d_nf_ptr, p->d_nf_items, p->d_Tiso};
     for (void *b : bufs) plan_free(p, b);
     delete p;
     return QXA_OK;
@@ -878,48 +877,6 @@ static qxa_status build_slot_entries(qxa_plan p)
     return st;
 }
 
-// Entries of every upper CSR slot for symmetric local matrices stored once per pair,
-// pair-major per block of kIsoElems elements: index (e / 64 * ns + s) * 64 + e % 64.
-// Counting sort in element order (a fixed summation order); each upper slot also
-// records its own and its mirror's position.
-static qxa_status build_upper_entries(qxa_plan p)
-{
-    const qxa_mesh m = p->mesh;
-    const int ns = p->ref.ns;
-    const int64_t ne = m->n_elem, ne_pad = (ne + kIsoElems - 1) / kIsoElems * kIsoElems;
-    if (int64_t(ns) * ne_pad >= (int64_t(1) << 31))
-        return fail(QXA_E_UNSUPPORTED, "isoparametric assembly: more than 2^31 element entries");
-    HostPlan hp;
-    qxa_status st = build_host_plan(m->dim, m->order, m->n_nodes, ne, m->h_conn.data(), hp);
-    if (st) return st;
-    std::vector<int64_t> cnt(hp.nnz, 0);
-    for (size_t k = 0; k < hp.perm_sym.size(); ++k) ++cnt[hp.perm_sym[k]];
-    std::vector<int32_t> pos, mir;
-    std::vector<int64_t> up_of(hp.nnz, -1);
-    for (int64_t t = 0; t < hp.nnz; ++t)
-        if (cnt[t]) {
-            up_of[t] = int64_t(pos.size());
-            pos.push_back(int32_t(t));
-            mir.push_back(int32_t(hp.mirror[t]));
-        }
-    const int64_t n_up = int64_t(pos.size());
-    std::vector<int64_t> ptr(n_up + 1, 0);
-    for (int64_t u = 0; u < n_up; ++u) ptr[u + 1] = ptr[u] + cnt[pos[u]];
-    std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
-    std::vector<int32_t> items(static_cast<size_t>(ptr[n_up]));
-    for (int64_t e = 0; e < ne; ++e)
-        for (int s = 0; s < ns; ++s) {
-            const int64_t u = up_of[hp.perm_sym[size_t(s) * ne + e]];
-            items[size_t(fill[u]++)] = int32_t((e / kIsoElems * ns + s) * kIsoElems + e % kIsoElems);
-        }
-    st = plan_upload_buf(p, &p->d_nu_ptr, ptr.data(), ptr.size());
-    if (!st) st = plan_upload_buf(p, &p->d_nu_items, items.data(), items.size());
-    if (!st) st = plan_upload_buf(p, &p->d_nu_pos, pos.data(), pos.size());
-    if (!st) st = plan_upload_buf(p, &p->d_nu_mirror, mir.data(), mir.size());
-    if (st) plan_drop(p, &p->d_nu_ptr, &p->d_nu_items, &p->d_nu_pos, &p->d_nu_mirror);
-    else p->n_up = n_up;
-    return st;
-}
 
 // Element entries of every node (a * n_elem + e with N_e(a) = node), ascending element.
 static qxa_status build_node_entries(qxa_plan p)
@@ -967,20 +924,25 @@ qxa_status qxa_assemble_iso(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *
     if (st) return st;
     a.Kq = stiff ? stiff->tensor_q : nullptr;
     a.nq_kq = p->ref.nq_c_in;
+    // the reduction: the plan's units, chains and fix-up, as the fused assembly
+    FusedArgs fa;
+    FixupArgs fx;
+    st = make_fused_args(p, mass, stiff ? &sc : nullptr, QXA_FP64, M_vals, C_vals, p->d_part, p->d_flags, fa, fx);
+    if (st) return st;
     const qxa_mesh m = p->mesh;
     if ((!M_vals && !C_vals) || m->n_elem == 0) return QXA_OK;
     QXA_HIP(hipSetDevice(m->device));
-    if (!p->d_nu_ptr) {
-        st = build_upper_entries(p);
-        if (st) return st;
-    }
-    // symmetric local matrices once per pair, pair-major per block of kIsoElems elements
-    const size_t nt = size_t(p->ref.ns) * ((m->n_elem + kIsoElems - 1) / kIsoElems) * kIsoElems;
+    // symmetric local matrices once per pair, pair-major per block of kIsoElems tile positions
+    const int64_t ne_pad = (m->n_elem + kIsoElems - 1) / kIsoElems * kIsoElems;
+    if (int64_t(p->ref.ns) * ne_pad >= (int64_t(1) << 31))
+        return fail(QXA_E_UNSUPPORTED, "isoparametric assembly: more than 2^31 element entries");
+    const size_t nt = size_t(p->ref.ns) * size_t(ne_pad);
     if (!p->d_Tiso) {
         st = plan_alloc(p, &p->d_Tiso, 2 * nt);
         if (st) return st;
     }
-    a.conn = m->d_conn;
+    a.tconn = p->d_tconn;
+    a.elem_order = p->d_elem_order;
     a.Qm = static_cast<const double *>(qm);
     a.Qc = static_cast<const double *>(qc);
     a.dphi_m = p->d_tables + p->off_dphim;
@@ -992,10 +954,14 @@ qxa_status qxa_assemble_iso(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *
         TimedLaunch tl(p, "iso_rows", s);
         QXA_HIP(launch_iso(a, m->dim, m->order, p->ref.nq_m, p->ref.nq_c, s));
     }
-    TimedLaunch tl(p, "upper_gather", s);
-    const UpperGatherArgs g{p->n_up, p->d_nu_ptr, p->d_nu_items, p->d_nu_pos, p->d_nu_mirror, a.Tm, a.Tc,
-                            M_vals, C_vals};
-    QXA_HIP(launch_upper_gather(g, s));
+    {
+        TimedLaunch tl(p, "staged_reduce", s);
+        const JobTable jt{fa, nullptr, nullptr, 0, p->n_tiles, fa.buf_ok, p->d_chain_ptr, p->n_chains};
+        QXA_HIP(launch_staged_reduce(jt, m->dim, m->order, a.Tm, a.Tc, s));
+    }
+    TimedLaunch tl(p, "fixup", s);
+    const FixupTable ft{fx, nullptr, nullptr, 0, p->n_fix};
+    QXA_HIP(launch_fixup(ft, s));
     return QXA_OK;
 }
 

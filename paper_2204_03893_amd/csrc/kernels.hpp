@@ -144,6 +144,9 @@ TileParams fused_tile_params(int D, int P, int nqm, int nqc, int cus, size_t lds
 hipError_t launch_form(const FormArgs &a, int D, int P, int nqm, int nqc, int precision, hipStream_t st);
 hipError_t launch_fused(const JobTable &jt, int D, int P, int nqm, int nqc, int precision, hipStream_t st);
 hipError_t launch_fixup(const FixupTable &ft, hipStream_t st);
+// Reduction of externally formed local matrices with the plan's units: Tm, Tc are
+// [n_elem / 64][NS][64] pair-major blocks of 64 tile positions (either may be null).
+hipError_t launch_staged_reduce(const JobTable &jt, int D, int P, const double *Tm, const double *Tc, hipStream_t st);
 
 // Argument blocks of one assembly with `plan` (validates the coefficients and
 // the precision form). part: [2][n_partials] partial sums; flags: one int.

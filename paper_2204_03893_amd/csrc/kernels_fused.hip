@@ -1331,6 +1331,84 @@ hipError_t launch_fused(const JobTable &jt, int D, int P, int nqm, int nqc, int 
 #endif
 
 #ifndef QXA_FUSED_PADDED
+// Reduction of local matrices formed elsewhere (the isoparametric path): the
+// pair-major blocks of 64 tile positions [block][pair][64] of V_m and V_c are
+// staged per tile into the LDS layout of the fused kernels ([NS][T + 1] pairs,
+// two buffers) and reduced by the same consumer code with the plan's units,
+// chains and carry entries. Every thread loads its share of the next tile into
+// registers while the current one is reduced.
+constexpr int kStageThreads = 512;
+
+template <int D, int P>
+__global__ __launch_bounds__(kStageThreads) void staged_reduce_kernel(JobTable jt, const double *Tm, const double *Tc)
+{
+    constexpr int NS = Shape<D, P>::NS, T = tile_size(D, P), BUF = NS * (T + 1);
+    constexpr int CH = P == 1 ? 2 : ws_chunk(D, P);
+    constexpr int PER = (NS * T + kStageThreads - 1) / kStageThreads;  // values per thread and tile
+    extern __shared__ __align__(16) double2 sStage[];                  // [2][NS][T + 1], then the carries
+    double2 *carry = sStage + 2 * BUF;
+    const int tid = threadIdx.x;
+    const int64_t ne = jt.one.in.n_elem;
+    if (tid == 0) {
+        sStage[T] = make_double2(0.0, 0.0);  // the zero pair of each buffer
+        sStage[BUF + T] = make_double2(0.0, 0.0);
+    }
+    const TileWalk walk = chain_walk(jt);
+    double2 reg[PER];
+    auto load = [&](int64_t tile) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int idx = tid + k * kStageThreads, s = idx / T, i = idx % T;
+            const int64_t p = tile * T + i;
+            double2 v = make_double2(0.0, 0.0);
+            if (idx < NS * T && p < ne) {
+                const size_t o = (size_t(p / 64) * NS + s) * 64 + size_t(p % 64);
+                v = make_double2(Tm ? Tm[o] : 0.0, Tc ? Tc[o] : 0.0);
+            }
+            reg[k] = v;
+        }
+    };
+    if (walk.valid(walk.t)) load(walk.t);
+    // tile k of the walk: stage it (its values arrived during tile k - 1), one barrier,
+    // then ask for tile k + 1's
+    auto on_tile = [&](int64_t k) -> const double * {
+        double2 *b = sStage + (k & 1) * BUF;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int idx = tid + j * kStageThreads;
+            if (idx < NS * T) b[(idx / T) * (T + 1) + idx % T] = reg[j];
+        }
+        lds_barrier();
+        const int64_t gn = walk.t + (k + 1) * walk.step;
+        if (walk.valid(gn)) load(gn);
+        return reinterpret_cast<const double *>(b);
+    };
+    const uint32_t cb = uint32_t(carry_base(NS, T));
+    if (jt.buf_stores)
+        consume_units<double, false, true, CH, kStageThreads>(jt, walk, tid, carry, cb, uint32_t(T), on_tile);
+    else
+        consume_units<double, false, false, CH, kStageThreads>(jt, walk, tid, carry, cb, uint32_t(T), on_tile);
+}
+
+hipError_t launch_staged_reduce(const JobTable &jt, int D, int P, const double *Tm, const double *Tc, hipStream_t st)
+{
+    if (jt.n_tiles == 0 || jt.n_chains == 0) return hipSuccess;
+#define QXA_STAGED(d, p)                                                                                \
+    if (D == d && P == p) {                                                                             \
+        constexpr int NS = Shape<d, p>::NS, T = tile_size(d, p);                                        \
+        const size_t lds = with_carries(size_t(2) * NS * (T + 1) * 16, jt.one.carry_cap);              \
+        auto k = staged_reduce_kernel<d, p>;                                                            \
+        k<<<persistent_grid(k, kStageThreads, lds, jt.n_chains), kStageThreads, lds, st>>>(jt, Tm, Tc); \
+        return hipGetLastError();                                                                       \
+    }
+    QXA_STAGED(2, 1) QXA_STAGED(2, 2) QXA_STAGED(2, 3) QXA_STAGED(3, 1) QXA_STAGED(3, 2) QXA_STAGED(3, 3)
+#undef QXA_STAGED
+    return hipErrorInvalidValue;
+}
+
+#endif
+
+#ifndef QXA_FUSED_PADDED
 hipError_t launch_fixup(const FixupTable &ft, hipStream_t st)
 {
     if (ft.n_fix == 0) return hipSuccess;

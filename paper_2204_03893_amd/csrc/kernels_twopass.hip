@@ -404,11 +404,12 @@ __device__ __forceinline__ void inverse_abs_det(const double (&B)[D][D], double 
 // A = B^{-1} K B^{-T} evaluated per quadrature node from every node's position, so X
 // holds one column per (q, e): X_m[q] = w_q m_q |det B_q| and X_c[(q, g)] = w_q c_q
 // |det B_q| A_q[g]; the contraction V = Q X with the plan's Q_m and Q_c (symmetric pair
-// rows) is unchanged. A block takes 64 elements, one per lane, in three phases through
-// LDS: the elements' node positions and nodal fields (one wave per local node), X (one
-// wave per quadrature node: B_q, |det B_q|, the coefficient, A_q), then V (one wave per
-// pair a <= b, Q read as wave-uniform scalars), stored once per pair in a pair-major
-// layout [block][pair][64] so that the lanes of a wave write 512 contiguous bytes.
+// rows) is unchanged. A block takes 64 tile positions (the plan's element order), one
+// element per lane, in three phases through LDS: the elements' node positions and nodal
+// fields (one wave per local node), X (one wave per quadrature node: B_q, |det B_q|, the
+// coefficient, A_q), then V (one wave per pair a <= b, Q read as wave-uniform scalars),
+// stored once per pair in a pair-major layout [block][pair][64] so that the lanes of a
+// wave write 512 contiguous bytes; the fused kernels' reduction then reads them per tile.
 
 template <int D, int P, int NQM, int NQC>
 constexpr size_t iso_lds_doubles()
@@ -432,10 +433,12 @@ __global__ __launch_bounds__(256) void iso_rows_kernel(IsoArgs a)
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     const int nw = int(blockDim.x >> 6);
-    const int64_t ne = in.n_elem, e = int64_t(blockIdx.x) * E + lane;
-    const bool live = e < ne;
+    // lane: tile position p (the output order the fused reduction reads), element e
+    const int64_t ne = in.n_elem, p = int64_t(blockIdx.x) * E + lane;
+    const bool live = p < ne;
+    const int64_t e = live ? int64_t(a.elem_order[p]) : 0;
     for (int i = wave; i < NP; i += nw) {
-        const int32_t node = live ? a.conn[i * ne + e] : 0;
+        const int32_t node = live ? a.tconn[i * ne + p] : 0;
 #pragma unroll
         for (int r = 0; r < D; ++r) sCrd[(i * D + r) * E + lane] = live ? in.coords[r * in.n_nodes + node] : 0.0;
         sUm[i * E + lane] = live && in.cm.kind == 1 ? in.cm.field[node] : 0.0;
@@ -583,50 +586,6 @@ __global__ __launch_bounds__(256) void slot_gather_kernel(SlotGatherArgs a)
     a.out[t] = s;
 }
 
-template <bool HM, bool HC>
-__global__ __launch_bounds__(256) void upper_gather_kernel(UpperGatherArgs a)
-{
-    const int64_t u = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (u >= a.n_up) return;
-    const int64_t lo = a.ptr[u], hi = a.ptr[u + 1];
-    const int32_t t = a.pos[u], tm = a.mirror[u];
-    double sm = 0.0, sc = 0.0;
-    for (int64_t k = lo; k < hi; k += 4) {  // four entries per step, summed in the stored order
-        int32_t i[4];
-        double vm[4], vc[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) i[j] = a.items[min(k + j, hi - 1)];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if constexpr (HM) vm[j] = a.srcM[i[j]];
-            if constexpr (HC) vc[j] = a.srcC[i[j]];
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            if (k + j < hi) {
-                if constexpr (HM) sm += vm[j];
-                if constexpr (HC) sc += vc[j];
-            }
-    }
-    if constexpr (HM) {
-        a.M[t] = sm;
-        a.M[tm] = sm;
-    }
-    if constexpr (HC) {
-        a.C[t] = sc;
-        a.C[tm] = sc;
-    }
-}
-
-hipError_t launch_upper_gather(const UpperGatherArgs &a, hipStream_t st)
-{
-    if (a.n_up == 0 || (!a.M && !a.C)) return hipSuccess;
-    const unsigned blocks = unsigned((a.n_up + 255) / 256);
-    if (a.M && a.C) upper_gather_kernel<true, true><<<blocks, 256, 0, st>>>(a);
-    else if (a.M) upper_gather_kernel<true, false><<<blocks, 256, 0, st>>>(a);
-    else upper_gather_kernel<false, true><<<blocks, 256, 0, st>>>(a);
-    return hipGetLastError();
-}
 
 hipError_t launch_slot_gather(const SlotGatherArgs &a, hipStream_t st)
 {

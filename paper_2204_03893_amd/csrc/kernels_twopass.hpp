@@ -48,14 +48,15 @@ struct LoadArgs {
 
 struct IsoArgs {
     FormInputs in;         // coefficients, tensor, rules (w, phi)
-    const int32_t *conn;   // [np][n_elem]
+    const int32_t *tconn;       // [np][n_elem] connectivity in tile order
+    const int32_t *elem_order;  // tile position -> element id (per-(q, e) inputs are in mesh order)
     const double *dphi_m;  // [nq_m][np][dim]
     const double *dphi_c;  // [nq_c][np][dim]
     const double *Qm;      // [ns][nq_m] FP64 mass table (symmetric pair rows)
     const double *Qc;      // [ns][nq_c][ng] FP64 conductivity table
     const double *Kq;      // [nq_kq][ng][n_elem] conductivity tensor per node (or null)
     int nq_kq;             // nodes of the caller's stiffness rule
-    double *Tm, *Tc;       // [n_elem / 64][ns][64] symmetric local matrices, pair-major per block
+    double *Tm, *Tc;       // [n_elem / 64][ns][64] symmetric local matrices of the tile positions, pair-major per block
 };
 
 struct SlotGatherArgs {
@@ -66,17 +67,6 @@ struct SlotGatherArgs {
     double *out;           // [n_slots]
 };
 
-// Symmetric local matrices: one thread per upper CSR slot sums its entries and writes
-// the slot and its mirror (M and C in one pass; either may be null).
-struct UpperGatherArgs {
-    int64_t n_up;
-    const int64_t *ptr;      // [n_up + 1]
-    const int32_t *items;    // indices into srcM / srcC
-    const int32_t *pos;      // [n_up] CSR position of the upper slot
-    const int32_t *mirror;   // [n_up] CSR position of its mirror
-    const double *srcM, *srcC;
-    double *M, *C;
-};
 
 // Elements per block of the isoparametric kernel and of its pair-major layout.
 constexpr int kIsoElems = 64;
@@ -85,7 +75,6 @@ hipError_t launch_expand(const ExpandArgs &a, hipStream_t st);
 hipError_t launch_coeff_product(const CoeffProductArgs &a, int D, int P, int nq, hipStream_t st);
 hipError_t launch_cond_tensor(const CondTensorArgs &a, int D, int P, int nq, hipStream_t st);
 hipError_t launch_slot_gather(const SlotGatherArgs &a, hipStream_t st);
-hipError_t launch_upper_gather(const UpperGatherArgs &a, hipStream_t st);
 hipError_t launch_load(const LoadArgs &a, int D, int P, int nq, hipStream_t st);
 hipError_t launch_iso(const IsoArgs &a, int D, int P, int nqm, int nqc, hipStream_t st);
 

@@ -305,7 +305,7 @@ struct qxa_plan_s {
     double *d_tables = nullptr;   // device copy of w, Phi, Qm, Qc (FP64)
     float *d_tables_f = nullptr;  // FP32 copy
     size_t off_wm = 0, off_wc = 0, off_phim = 0, off_phic = 0, off_qm = 0, off_qc = 0, off_dphic = 0, off_dphim = 0;
-    double *d_Tiso = nullptr;     // [2][n_elem / 64][ns][64] isoparametric local matrices (pair-major) (first use)
+    double *d_Tiso = nullptr;     // [2][n_elem / 64][ns][64] isoparametric local matrices of the tile positions (first use)
     double *d_V = nullptr;        // [2][ns][n_elem] formation-only buffer (allocated on first use)
     // conductivity tensor product (built on first use): local matrices [n_elem][np][np]
     // and, per CSR slot (both triangles), its element entries (index into d_T) in
@@ -313,13 +313,6 @@ struct qxa_plan_s {
     double *d_T = nullptr;
     int64_t *d_ns_ptr = nullptr;  // [nnz + 1]
     int32_t *d_ns_items = nullptr;
-    // isoparametric path (built on first use): per upper CSR slot, its position, its
-    // mirror's position and its element-pair entries (index into the pair-major local
-    // matrices) in ascending element order
-    int64_t n_up = 0;
-    int64_t *d_nu_ptr = nullptr;  // [n_up + 1]
-    int32_t *d_nu_items = nullptr;
-    int32_t *d_nu_pos = nullptr, *d_nu_mirror = nullptr;
     // load vector (built on first use): element vectors [np][n_elem] and, per node,
     // its element entries in ascending element order
     double *d_Fe = nullptr;
