@@ -83,6 +83,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t store_rsrc(void *base, uint32_
 __device__ __forceinline__ TileWalk chain_walk(const JobTable &jt)
 {
     const int64_t G = gridDim.x, b = blockIdx.x, nc = jt.n_chains;
+    // chains of one tile (no carries): the XCDs each walk an eighth of the tile order with
+    // their workgroups side by side, so that tiles sharing CSR lines run at the same time
+    // on one XCD and their writes meet in its L2
+    if (nc == jt.n_tiles) return TileWalk(jt.n_tiles);
     int64_t c0, c1;
     if (G == nc) {
         c0 = xcd_tile(b, nc);
@@ -1195,6 +1199,7 @@ static unsigned persistent_grid(K kernel, int block, size_t lds, int64_t n_chain
 static size_t with_carries(size_t bytes, int carry_cap) { return ((bytes + 15) & ~size_t(15)) + 16 * size_t(carry_cap); }
 
 constexpr int kMaxCarries = 4096;
+constexpr int kMinCarries = 1024;
 
 template <int D, int P>
 static size_t p1_lds_bytes()
@@ -1246,6 +1251,12 @@ TileParams fused_tile_params(int D, int P, int nqm, int nqc, int cus, size_t lds
     const size_t room = lds_max > with_carries(base, 0) ? lds_max - with_carries(base, 0) : 0;
     tp.carry_cap = int(std::min<size_t>(kMaxCarries, room / 16) / 16 * 16);
     tp.chains = int64_t(std::max(1, cus));  // one workgroup per CU
+    if (tp.carry_cap < kMinCarries) {
+        // too few carry entries to pay for walking tiles one after another (3D P2: 272,
+        // 3D P3: 896): tiles side by side instead, every shared slot through a partial
+        tp.carry_cap = 0;
+        tp.chains = int64_t(1) << 40;
+    }
     return tp;
 }
 #endif
