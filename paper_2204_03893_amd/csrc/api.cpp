@@ -932,6 +932,13 @@ qxa_status qxa_assemble_iso(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *
     const qxa_mesh m = p->mesh;
     if ((!M_vals && !C_vals) || m->n_elem == 0) return QXA_OK;
     QXA_HIP(hipSetDevice(m->device));
+    // the local-matrix kernel stages positions, fields and X of 64 elements in LDS
+    const RefTables &R = p->ref;
+    const size_t iso_lds = size_t(kIsoElems) * (R.np * R.dim + 2 * R.np + R.nq_m + R.nq_c * R.ng) * sizeof(double);
+    if (iso_lds > kLdsBytes)
+        return fail(QXA_E_UNSUPPORTED, "isoparametric assembly: rules of " + std::to_string(R.nq_m) + " and " +
+                                           std::to_string(R.nq_c) + " nodes need " + std::to_string(iso_lds) +
+                                           " bytes of LDS per workgroup (more than 160 KiB)");
     // symmetric local matrices once per pair, pair-major per block of kIsoElems tile positions
     const int64_t ne_pad = (m->n_elem + kIsoElems - 1) / kIsoElems * kIsoElems;
     if (int64_t(p->ref.ns) * ne_pad >= (int64_t(1) << 31))

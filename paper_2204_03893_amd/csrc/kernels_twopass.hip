@@ -176,7 +176,7 @@ hipError_t QXA_PART(launch_coeff_product)(const CoeffProductArgs &a, int D, int 
 // (one wave per row: r_a(q) = J_q[a] . X[q, :], then T[a][b] = sum_q phi_b(q) r_a(q)) into
 // an LDS stage that the block copies out as contiguous row segments of the element-major
 // output [n_elem][n_p][n_p].
-constexpr int kCtElems = 64, kCtRows = 4;
+constexpr int kCtElems = 64, kCtRows = 8;
 
 template <int D, int P, int NQ>
 constexpr size_t ct_lds_doubles()
@@ -186,7 +186,7 @@ constexpr size_t ct_lds_doubles()
 }
 
 template <int D, int P, int NQ>
-__global__ __launch_bounds__(256) void cond_tensor_rows_kernel(CondTensorArgs a)
+__global__ __launch_bounds__(512) void cond_tensor_rows_kernel(CondTensorArgs a)
 {
     using S = Shape<D, P>;
     constexpr int NP = S::NP, NG = S::NG, E = kCtElems, STR = kCtRows * NP + 1;
@@ -294,7 +294,7 @@ hipError_t QXA_PART(launch_cond_tensor)(const CondTensorArgs &a, int D, int P, i
     const unsigned blocks = unsigned((a.n_elem + kCtElems - 1) / kCtElems);
 #define X(d, p, m, c)                                                                                   \
     if (D == d && P == p && nq == c) {                                                                  \
-        cond_tensor_rows_kernel<d, p, c><<<blocks, 256, ct_lds_doubles<d, p, c>() * sizeof(double), st>>>(a); \
+        cond_tensor_rows_kernel<d, p, c><<<blocks, 512, ct_lds_doubles<d, p, c>() * sizeof(double), st>>>(a); \
         return hipGetLastError();                                                                       \
     }
     QXA_TWOPASS_CASES(X)
@@ -404,8 +404,8 @@ __device__ __forceinline__ void inverse_abs_det(const double (&B)[D][D], double 
 // A = B^{-1} K B^{-T} evaluated per quadrature node from every node's position, so X
 // holds one column per (q, e): X_m[q] = w_q m_q |det B_q| and X_c[(q, g)] = w_q c_q
 // |det B_q| A_q[g]; the contraction V = Q X with the plan's Q_m and Q_c (symmetric pair
-// rows) is unchanged. A block takes 64 tile positions (the plan's element order), one
-// element per lane, in three phases through LDS: the elements' node positions and nodal
+// rows) is unchanged. A block of 8 waves takes 64 tile positions (the plan's element
+// order), one element per lane, in three phases through LDS: the elements' node positions and nodal
 // fields (one wave per local node), X (one wave per quadrature node: B_q, |det B_q|, the
 // coefficient, A_q), then V (one wave per pair a <= b, Q read as wave-uniform scalars),
 // stored once per pair in a pair-major layout [block][pair][64] so that the lanes of a
@@ -419,7 +419,7 @@ constexpr size_t iso_lds_doubles()
 }
 
 template <int D, int P, int NQM, int NQC>
-__global__ __launch_bounds__(256) void iso_rows_kernel(IsoArgs a)
+__global__ __launch_bounds__(512) void iso_rows_kernel(IsoArgs a)
 {
     using S = Shape<D, P>;
     constexpr int NP = S::NP, NG = S::NG, NS = S::NS, E = kIsoElems;
@@ -553,7 +553,7 @@ hipError_t QXA_PART(launch_iso)(const IsoArgs &a, int D, int P, int nqm, int nqc
     const unsigned blocks = unsigned((a.in.n_elem + kIsoElems - 1) / kIsoElems);
 #define X(d, p, m, c)                                                                                  \
     if (D == d && P == p && nqm == m && nqc == c) {                                                    \
-        iso_rows_kernel<d, p, m, c><<<blocks, 256, iso_lds_doubles<d, p, m, c>() * sizeof(double), st>>>(a); \
+        iso_rows_kernel<d, p, m, c><<<blocks, 512, iso_lds_doubles<d, p, m, c>() * sizeof(double), st>>>(a); \
         return hipGetLastError();                                                                      \
     }
     QXA_TWOPASS_CASES(X)

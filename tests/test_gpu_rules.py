@@ -144,3 +144,22 @@ def test_iso_per_node_tensor_with_padded_rules(dim, order, N):
     rpo, cio, Mo, Co = oracle.assemble_iso(mesh, rm, rc, ("const", 1.0), law_c, None, u, tensor_q=Kq)
     assert row_scaled_error(M.cpu().numpy(), Mo, rpo) <= 1e-12
     assert row_scaled_error(Cv.cpu().numpy(), Co, rpo) <= 1e-12
+
+
+def test_iso_refuses_rules_whose_staging_exceeds_lds():
+    """3D P3 with a 27-node rule padded to 32: the isoparametric kernel would stage more than
+    160 KiB per workgroup, so the call is refused (QXA_E_UNSUPPORTED) before any launch; the
+    affine assembly of the same plan runs."""
+    import paper_2204_03893_amd as qxa
+    mesh = structured_mesh(3, 3, 2, 0.1, seed=139)
+    r = conical(3, 3)
+    m = qxa.Mesh(3, 3, mesh["coords"], mesh["conn"])
+    plan = qxa.Plan(m, r)
+    with pytest.raises(qxa.QxaError) as ei:
+        qxa.assemble_iso(plan, ("const", 1.0), ("const", 1.0))
+    assert ei.value.code == -6
+    M, Cv = qxa.assemble(plan, ("const", 1.0), ("const", 1.0))
+    qxa.sync(plan)
+    rpo, cio, Mo, Co = oracle.assemble(mesh, r, r, ("const", 1.0), ("const", 1.0))
+    assert row_scaled_error(M.cpu().numpy(), Mo, rpo) <= 1e-12
+    assert row_scaled_error(Cv.cpu().numpy(), Co, rpo) <= 1e-12
