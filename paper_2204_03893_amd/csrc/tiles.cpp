@@ -173,8 +173,9 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
     }, 0);
     for (unsigned c = 0; c < nth; ++c) cbase[c + 1] += cbase[c];
     const int64_t nm = cbase[nth];
-    std::vector<uint32_t> mslot(nm);
-    std::vector<int64_t> mptr(nm + 1, 0);
+    hvec<uint32_t> mslot(nm);
+    hvec<int64_t> mptr(nm + 1);
+    mptr[0] = 0;
     parallel_for(nth, [&](int64_t a, int64_t b) {
         for (int64_t c = a; c < b; ++c) {
             int64_t m = cbase[c];
@@ -190,9 +191,10 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
         }
     }, 0);
     for (int64_t m = 0; m < nm; ++m) mptr[m + 1] += mptr[m];
-    std::vector<int32_t> mtiles(mptr[nm]);
+    hvec<int32_t> mtiles(mptr[nm]);
     {
-        std::vector<int32_t> cur(nm, 0);
+        hvec<int32_t> cur(nm);
+        parallel_for(nm, [&](int64_t a, int64_t b) { std::fill(cur.begin() + a, cur.begin() + b, 0); });
         parallel_for(nt, [&](int64_t a, int64_t b) {
             for (int64_t t = a; t < b; ++t)
                 for_slots(t, [&](uint32_t u, const uint64_t *, const uint64_t *) {
@@ -201,13 +203,19 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
                 });
         }, 16);
     }
-    std::vector<int64_t> gptr(nm + 1, 0);
-    std::vector<Group> groups;
-    {
-        std::vector<int32_t> ngr(nm, 0);
+    // without carries (no entries, or chains of one tile) every multi-tile slot is a
+    // partial per tile and no chain groups are needed
+    const bool carries = tp.carry_cap > 0 && nc < nt;
+    hvec<int64_t> gptr(carries ? nm + 1 : 1);
+    gptr[0] = 0;
+    hvec<Group> groups;
+    parallel_for(nm, [&](int64_t a, int64_t b) {
+        for (int64_t m = a; m < b; ++m) std::sort(mtiles.begin() + mptr[m], mtiles.begin() + mptr[m + 1]);
+    });
+    if (carries) {
+        hvec<int32_t> ngr(nm);
         parallel_for(nm, [&](int64_t a, int64_t b) {
             for (int64_t m = a; m < b; ++m) {
-                std::sort(mtiles.begin() + mptr[m], mtiles.begin() + mptr[m + 1]);
                 int g = 1;
                 for (int64_t k = mptr[m] + 1; k < mptr[m + 1]; ++k) g += chain_of[mtiles[k]] != chain_of[mtiles[k - 1]];
                 ngr[m] = g;
@@ -230,11 +238,11 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
     //    t_first < t_last holds an entry from t_first to t_last; an entry read
     //    (for the last time) in tile t is free again from tile t + 1. A group
     //    that finds no free entry is not carried (one partial per tile).
-    std::vector<std::vector<int64_t>> chain_groups(nc);  // group indices spanning > 1 tile
+    std::vector<std::vector<int64_t>> chain_groups(carries ? nc : 0);  // group indices spanning > 1 tile
     for (int64_t g = 0; g < int64_t(groups.size()); ++g)
         if (groups[g].t_first < groups[g].t_last) chain_groups[groups[g].chain].push_back(g);
-    std::vector<int32_t> chain_used(nc, 0);
-    parallel_for(nc, [&](int64_t a, int64_t b) {
+    std::vector<int32_t> chain_used(carries ? nc : 0, 0);
+    parallel_for(int64_t(chain_groups.size()), [&](int64_t a, int64_t b) {
         for (int64_t c = a; c < b; ++c) {
             auto &L = chain_groups[c];
             std::sort(L.begin(), L.end(), [&](int64_t x, int64_t y) {
@@ -262,7 +270,7 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
             chain_used[c] = used;
         }
     }, 2);
-    for (int64_t c = 0; c < nc; ++c) tp.carry_used = std::max(tp.carry_used, chain_used[c]);
+    for (int32_t u : chain_used) tp.carry_used = std::max(tp.carry_used, u);
     // 7. shared slots (a partial at least) and the index of every partial:
     //    one per (tile, slot) of role R_PART or R_CARRY_PART, numbered by slot,
     //    then ascending tile (pidx is parallel to mtiles; -1: no partial)
@@ -270,6 +278,7 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
         carry = -1;
         const int32_t m = mid[u];
         if (m < 0) return R_OWNED;
+        if (!carries) return R_PART;
         const int32_t c = chain_of[t];
         int64_t g = gptr[m];
         while (groups[g].chain != c) ++g;
@@ -281,8 +290,9 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
         if (t < G.t_last) return R_CARRY_MID;
         return single ? R_CARRY_CSR : R_CARRY_PART;
     };
-    std::vector<int32_t> pidx(mptr[nm]);
-    std::vector<int64_t> mpart(nm + 1, 0);
+    hvec<int32_t> pidx(mptr[nm]);
+    hvec<int64_t> mpart(nm + 1);
+    mpart[0] = 0;
     parallel_for(nm, [&](int64_t a, int64_t b) {
         for (int64_t m = a; m < b; ++m) {
             int32_t n = 0, carry;
