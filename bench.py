@@ -446,8 +446,12 @@ def tangent(args):
     plan.set_timing(False)
     iso = {"ms_per_assembly": ms_i, "entries_per_s": 2 * entries / (ms_i * 1e-3),
            "kernels_ms": {k: v["ms"] / v["n"] for k, v in rep_i.items()},
-           "design": "X per quadrature node and V = QX through LDS, pair-major per 64 tile positions to "
-                     "HBM, then the fused reduction (the plan's units, chains, carries) and the fix-up"}
+           "design": ("one pass: the matrix-core kernel with X formed per quadrature node (B_q from every "
+                      "node's position), V = QX in LDS, the plan's units, then the fix-up"
+                      if "fused_iso" in rep_i else
+                      "two passes: X per quadrature node and V = QX through LDS, pair-major per 64 tile "
+                      "positions to HBM, then the fused reduction (the plan's units, chains, carries) and "
+                      "the fix-up")}
     out = {"metric": "mass-tensor product entries assembled/sec", "value": entries / (ms * 1e-3),
            "unit": "entries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",

@@ -311,14 +311,20 @@ qxa_status qxa_load_vector(qxa_plan plan, const qxa_coeff *f, double *F, void *s
  * basis and the positions of all of an element's nodes, x(xhat) = sum_i x_i phi_i(xhat),
  * so B, |det B| and A = B^{-1} K B^{-T} are evaluated at every quadrature node (X_m and
  * X_c per (q, e); Q_m and Q_c unchanged). Same coefficients, outputs and pattern as
- * qxa_assemble, in FP64. Two passes: the local matrices of every element (X per
- * quadrature node, then V = Q X, once per symmetric pair) to a plan-owned buffer in the
- * plan's tile order, then the reduction of the fused assembly (the plan's output units,
- * chains and carries, and its fix-up) sums every CSR slot in the plan's fixed order
- * (deterministic, bitwise symmetric). The first call on a plan allocates
+ * qxa_assemble, in FP64. One pass where the shape's matrix-core kernel stages Q^T in
+ * LDS (2D P2, 2D P3, 3D P2), the plan's mass and stiffness rules are the same rule and
+ * the reference gradients fit in LDS beside the plan's carry entries (2D P2 and 3D P2
+ * with their default rules): that kernel forms X per quadrature node from the node
+ * positions and reduces V = Q X through the plan's output units, then the fix-up.
+ * Otherwise two passes: the local matrices of every element (X per quadrature node,
+ * then V = Q X, once per symmetric pair) to a plan-owned buffer in the plan's tile
+ * order, then the reduction of the fused assembly (the plan's output units, chains and
+ * carries, and its fix-up). Either way every CSR slot is summed in the plan's fixed
+ * order (deterministic, bitwise symmetric). The first two-pass call on a plan allocates
  * 16 n_s n_elem bytes of local matrices (n_s = n_p (n_p + 1) / 2, n_elem rounded up to
- * a multiple of 64); later calls allocate nothing. Errors as
- * qxa_assemble, plus QXA_E_UNSUPPORTED when n_s n_elem >= 2^31 and QXA_E_INVALID for
+ * a multiple of 64); later calls, and one-pass calls, allocate nothing. Errors as
+ * qxa_assemble, plus, on the two-pass path, QXA_E_UNSUPPORTED when n_s n_elem >= 2^31
+ * or when the rules' staging exceeds the LDS, and QXA_E_INVALID for
  * tensor_q on the mass coefficient or with tensor; a non-finite coefficient or tensor
  * entry, or a map with det B_q = 0 at a quadrature node, is reported by qxa_sync as
  * QXA_E_NONFINITE. The stiffness coefficient may carry a per-node tensor (tensor_q).

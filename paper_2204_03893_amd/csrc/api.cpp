@@ -932,8 +932,27 @@ qxa_status qxa_assemble_iso(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *
     const qxa_mesh m = p->mesh;
     if ((!M_vals && !C_vals) || m->n_elem == 0) return QXA_OK;
     QXA_HIP(hipSetDevice(m->device));
-    // the local-matrix kernel stages positions, fields and X of 64 elements in LDS
     const RefTables &R = p->ref;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // one pass where the shape's matrix-core kernel takes it: one rule for both
+    // matrices, and the reference gradients fit in LDS beside the plan's carries
+    const bool one_rule = R.nq_m == R.nq_c && R.nq_m_in == R.nq_c_in && R.w_m == R.w_c && R.phi_m == R.phi_c &&
+                          R.dphi_m == R.dphi_c;
+    if (one_rule && fused_iso_fits(m->dim, m->order, R.nq_m, R.nq_c, fa.qfrag_vec16, fa.carry_cap)) {
+        fa.dphi = p->d_tables + p->off_dphim;
+        fa.Kq = a.Kq;
+        fa.nq_kq = a.nq_kq;
+        {
+            TimedLaunch tl(p, "fused_iso", s);
+            const JobTable jt{fa, nullptr, nullptr, 0, p->n_tiles, fa.buf_ok, p->d_chain_ptr, p->n_chains};
+            QXA_HIP(launch_fused_iso(jt, m->dim, m->order, R.nq_m, R.nq_c, s));
+        }
+        TimedLaunch tl(p, "fixup", s);
+        const FixupTable ft{fx, nullptr, nullptr, 0, p->n_fix};
+        QXA_HIP(launch_fixup(ft, s));
+        return QXA_OK;
+    }
+    // else two passes; the local-matrix kernel stages positions, fields and X of 64 elements in LDS
     const size_t iso_lds = size_t(kIsoElems) * (R.np * R.dim + 2 * R.np + R.nq_m + R.nq_c * R.ng) * sizeof(double);
     if (iso_lds > kLdsBytes)
         return fail(QXA_E_UNSUPPORTED, "isoparametric assembly: rules of " + std::to_string(R.nq_m) + " and " +
@@ -956,7 +975,6 @@ qxa_status qxa_assemble_iso(qxa_plan p, const qxa_coeff *mass, const qxa_coeff *
     a.dphi_c = p->d_tables + p->off_dphic;
     a.Tm = M_vals ? p->d_Tiso : nullptr;
     a.Tc = C_vals ? p->d_Tiso + nt : nullptr;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     {
         TimedLaunch tl(p, "iso_rows", s);
         QXA_HIP(launch_iso(a, m->dim, m->order, p->ref.nq_m, p->ref.nq_c, s));

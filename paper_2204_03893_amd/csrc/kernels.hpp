@@ -98,6 +98,11 @@ struct FusedArgs {
     uint32_t bytes_vals;        // 8 * nnz (buffer-store bound of M and C)
     uint32_t bytes_part;        // 16 * n_partials (buffer-store bound of part)
     int buf_ok;                 // both bounds below 2^31: the stores may go through buffer resources
+    // isoparametric kernels only (null otherwise)
+    const double *dphi;         // [n_q][np][dim] reference gradients at the (shared) rule's nodes
+    const double *Kq;           // [nq_kq][ng][n_elem] conductivity tensor per node, mesh order (or null)
+    int nq_kq;                  // nodes of the caller's stiffness rule
+    int pad1;
 };
 
 // Jobs of one launch: a single assembly is carried by value in `one`
@@ -144,6 +149,13 @@ TileParams fused_tile_params(int D, int P, int nqm, int nqc, int cus, size_t lds
 hipError_t launch_form(const FormArgs &a, int D, int P, int nqm, int nqc, int precision, hipStream_t st);
 hipError_t launch_fused(const JobTable &jt, int D, int P, int nqm, int nqc, int precision, hipStream_t st);
 hipError_t launch_fixup(const FixupTable &ft, hipStream_t st);
+// The isoparametric assembly in one pass (the matrix-core kernel with X formed
+// per quadrature node from every node's position): shapes whose kernel stages
+// Q^T in LDS, one rule for both matrices (nqm == nqc, identical tables), FP64.
+// fused_iso_fits: compiled, and the kernel's LDS with the plan's carry entries
+// fits a workgroup.
+bool fused_iso_fits(int D, int P, int nqm, int nqc, int64_t qfrag_vec16, int carry_cap);
+hipError_t launch_fused_iso(const JobTable &jt, int D, int P, int nqm, int nqc, hipStream_t st);
 // Reduction of externally formed local matrices with the plan's units: Tm, Tc are
 // [n_elem / 64][NS][64] pair-major blocks of 64 tile positions (either may be null).
 hipError_t launch_staged_reduce(const JobTable &jt, int D, int P, const double *Tm, const double *Tc, hipStream_t st);

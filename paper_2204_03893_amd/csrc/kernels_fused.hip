@@ -685,6 +685,163 @@ __device__ __forceinline__ bool lane_setup(const FormInputs &in, const RawElem<D
     return ok;
 }
 
+// Isoparametric elements on the matrix-core path: the four lanes of an element
+// (j = lane / 16) each gather a quarter of its node positions (items
+// it = 4 t + j of the node-major list, it = node * D + component) and of its
+// first nodal field (node 4 t + j), one tile ahead; iso_expand rebuilds the
+// whole element on every lane with cross-lane reads (the lanes of one element
+// are active together), so that no lane keeps all positions in registers
+// while the previous tile is contracted.
+template <int D, int P>
+struct IsoRaw {
+    // whole groups of four nodes (D items per lane each); items past the last node repeat a valid position
+    static constexpr int NP = Shape<D, P>::NP, NU = (NP + 3) / 4, NX = D * NU;
+    double x[NX];
+    double u[NU];
+};
+
+template <int D, int P>
+__device__ __forceinline__ void gather_iso(const FormInputs &in, const int32_t *v, int j, IsoRaw<D, P> &r)
+{
+    using R = IsoRaw<D, P>;
+    constexpr int NP = R::NP;
+    auto node = [&](int it) { return it < NP ? v[it] : v[0]; };
+#pragma unroll
+    for (int t = 0; t < R::NX; ++t) {
+        // item 4 t + j: node and component picked among the four candidates (static indices)
+        const int it0 = 4 * t;
+        const int32_t nd = sel4(j, node((it0 + 0) / D), node((it0 + 1) / D), node((it0 + 2) / D), node((it0 + 3) / D));
+        const int cp = sel4(j, (it0 + 0) % D, (it0 + 1) % D, (it0 + 2) % D, (it0 + 3) % D);
+        r.x[t] = in.coords[int64_t(cp) * in.n_nodes + nd];  // past the last item: a valid position, unused
+    }
+    if (in.cm.kind == 1 || in.cc.kind == 1) {
+        const double *f = in.cm.kind == 1 ? in.cm.field : in.cc.field;
+#pragma unroll
+        for (int t = 0; t < R::NU; ++t) r.u[t] = f[sel4(j, node(4 * t), node(4 * t + 1), node(4 * t + 2), node(4 * t + 3))];
+    }
+}
+
+// Per-lane setup of the isoparametric kernel (curved elements, Section 7:
+// the geometry is evaluated at every quadrature node from all the element's
+// node positions). For each node q = 4 m + j of this lane: B_q = sum_i
+// (x_i - x_0) grad phi_i(q)^T (the gradients sum to zero, so this is B_q
+// without the cancellation of absolute coordinates), its inverse and
+// |det B_q|; then X_m[q] = w_q m_q |det B_q| and X_c[(q, g)] = w_q c_q
+// |det B_q| A_q[g] with A_q = B_q^{-1} K_q B_q^{-T}. One rule serves both
+// matrices (sDphi: [q][i][d] in LDS); a matrix that is not requested is not
+// formed. The nodes are visited once, each node's position and field value
+// read from the lane that gathered it and added into every B_q and u_h(q) of
+// the lane. All 64 lanes must call this (cross-lane reads); live = false
+// (past the last element) gives zeros. Returns false when a value is not
+// finite or |det B_q| is not positive.
+template <int D, int P, int NQ>
+__device__ __forceinline__ bool lane_setup_iso(const FusedArgs &a, const IsoRaw<D, P> &r, bool live, int64_t pos,
+                                               int64_t eid, int j, int c16, const double *sPhi, const double *sW,
+                                               const double *sDphi, double *lm, double (*xc)[Shape<D, P>::NG])
+{
+    constexpr int NP = Shape<D, P>::NP, NG = Shape<D, P>::NG;
+    using L = LaneQ<NQ, NQ, NG>;
+    constexpr int MM = L::MM;
+    static_assert(L::MM == L::MC, "one rule for both matrices");
+    const FormInputs &in = a.in;
+    const bool field = in.cm.kind == 1 || in.cc.kind == 1;
+    const bool other = in.cc.kind == 1 && in.cm.kind == 1 && in.cc.field != in.cm.field;
+    // group k of four nodes (k = 0, 1, ...) sits in registers [D k, D k + D) of x and k of u;
+    // each pass reads group 0 and shifts the next one down, so every index is static
+    using R = IsoRaw<D, P>;
+    double rx[R::NX], ru[R::NU];
+#pragma unroll
+    for (int t = 0; t < R::NX; ++t) rx[t] = r.x[t];
+#pragma unroll
+    for (int t = 0; t < R::NU; ++t) ru[t] = r.u[t];
+    double x0[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) x0[c] = __shfl(rx[c / 4], c16 + 16 * (c % 4), 64);
+    double B[MM][D][D], uh[MM];
+#pragma unroll
+    for (int m = 0; m < MM; ++m) {
+        uh[m] = 0.0;
+#pragma unroll
+        for (int rr = 0; rr < D; ++rr)
+#pragma unroll
+            for (int c = 0; c < D; ++c) B[m][rr][c] = 0.0;
+    }
+    // q past the rule (lanes of the last node group): the last node's tables, results unused.
+    // The loop over the groups stays rolled: one group's values are live at a time.
+#pragma unroll 1
+    for (int k = 0; k < R::NU; ++k) {
+#pragma unroll
+        for (int ip = 0; ip < 4; ++ip) {
+            const int i = 4 * k + ip;
+            if (i >= NP) break;  // wave-uniform
+            double xr[D];
+#pragma unroll
+            for (int rr = 0; rr < D; ++rr) {
+                const int it = ip * D + rr;  // item within the group
+                xr[rr] = __shfl(rx[it / 4], c16 + 16 * (it % 4), 64) - x0[rr];
+            }
+            const double ui = field ? __shfl(ru[0], c16 + 16 * ip, 64) : 0.0;
+#pragma unroll
+            for (int m = 0; m < MM; ++m) {
+                const int q = min(L::q(j, m), NQ - 1);
+#pragma unroll
+                for (int rr = 0; rr < D; ++rr)
+#pragma unroll
+                    for (int c = 0; c < D; ++c) B[m][rr][c] = fma(xr[rr], sDphi[(q * NP + i) * D + c], B[m][rr][c]);
+                uh[m] = fma(sPhi[q * NP + i], ui, uh[m]);  // u_h(xhat_q) = phi_q^T u_e
+            }
+        }
+#pragma unroll
+        for (int t = 0; t + D < R::NX; ++t) rx[t] = rx[t + D];
+#pragma unroll
+        for (int t = 0; t + 1 < R::NU; ++t) ru[t] = ru[t + 1];
+    }
+    bool ok = true;
+    auto coeff = [&](const CoeffDev &cf, int q, int m, bool second) -> double {
+        if (cf.kind == 0) return cf.value;
+        if (cf.kind == 2) return apply_law(cf, qe_value(cf, q, in.n_elem, eid));
+        if (!second) return apply_law(cf, uh[m]);
+        double u2 = 0.0;  // a second nodal field, read through the element's connectivity
+#pragma unroll
+        for (int i = 0; i < NP; ++i) u2 = fma(sPhi[q * NP + i], cf.field[a.tconn[i * in.n_elem + pos]], u2);
+        return apply_law(cf, u2);
+    };
+#pragma unroll
+    for (int m = 0; m < MM; ++m) {
+        const int q = L::q(j, m);
+        lm[m] = 0.0;
+#pragma unroll
+        for (int g = 0; g < NG; ++g) xc[m][g] = 0.0;
+        if (!live || q >= NQ) continue;
+        double I[D][D], adet;
+        inverse_abs_det<D>(B[m], I, adet);
+        if (a.M) {
+            const double lam = sW[q] * coeff(in.cm, q, m, false) * adet;
+            lm[m] = lam;
+            ok &= isfinite(lam) && adet > 0.0;
+        }
+        if (a.C) {
+            const double lam = sW[q] * coeff(in.cc, q, m, other) * adet;
+            double Au[NG];
+            if (a.Kq) {  // K_qe: a tensor per quadrature node
+                double Kl[NG];
+#pragma unroll
+                for (int g = 0; g < NG; ++g) {
+                    Kl[g] = a.Kq[(int64_t(q < a.nq_kq ? q : 0) * NG + g) * in.n_elem + eid];
+                    ok &= isfinite(Kl[g]);
+                }
+                metric_from_inverse<D>(I, 1, Kl, Au);
+            } else {
+                metric_from_inverse<D>(I, in.aniso, in.K, Au);
+            }
+            ok &= isfinite(lam) && adet > 0.0;
+#pragma unroll
+            for (int g = 0; g < NG; ++g) xc[m][g] = lam * Au[g];
+        }
+    }
+    return ok;
+}
+
 template <int PF>
 struct FormTraits {
     using stage_t = float;  // reduced forms stage V in FP32; carries and the CSR accumulation stay FP64
@@ -715,9 +872,10 @@ constexpr int ws_producers(int T) { return T == 16 ? 512 : 256; }
 // tile ahead): 2D P2 up to ~790 units per 64-element tile on 512 consumer
 // threads, 2D P3 ~2,520, 3D P2 ~1,700, 3D P3 ~2,100 per 16-element tile
 constexpr int ws_chunk(int D, int P) { return D == 2 ? (P == 3 ? 5 : 2) : 4; }
-// consumer threads: 8 waves
-constexpr int ws_consumers(int T) { return 512; }
-constexpr int ws_threads(int T) { return ws_producers(T) + ws_consumers(T); }
+// consumer threads: 8 waves; 4 for the isoparametric kernel, whose producers
+// need more than the 168 registers a lane has at three waves per SIMD
+constexpr int ws_consumers(int T, bool iso = false) { return iso ? 256 : 512; }
+constexpr int ws_threads(int T, bool iso = false) { return ws_producers(T) + ws_consumers(T, iso); }
 
 // Producers of the T = 16 shape (3D P3: 210 symmetric rows, Q^T of 282 KB in
 // FP64, read from global memory where it stays cached), eight waves:
@@ -973,7 +1131,7 @@ constexpr int kWidePrologueBarriers = 2;
 // basis values and weights of both rules (q-major). With T = 16 (wide shapes:
 // 3D P3) Q^T (too large for LDS) is read from global memory, where it stays
 // cached, and the producers' staged raw values, Lambda and W follow.
-template <int D, int P, int NQM, int NQC, int PF, int T>
+template <int D, int P, int NQM, int NQC, int PF, int T, bool ISO = false>
 struct WsLds {
     using ST = typename FormTraits<PF>::stage_t;
     static constexpr bool QLDS = T != 16;
@@ -982,30 +1140,34 @@ struct WsLds {
     static constexpr size_t tab_doubles = size_t(NQM + NQC) * NP + NQM + NQC;
     static constexpr size_t wide_doubles =
         QLDS ? 0 : size_t(2) * T * ((D + 1) * D + 2 * NP + NQM + NQC + Shape<D, P>::NG);
+    static constexpr size_t iso_doubles = ISO ? size_t(NQC) * NP * D : 0;  // reference gradients [q][i][d]
     static __host__ __device__ size_t bytes(int64_t qfrag_vec16)
     {
-        return v_bytes + (QLDS ? size_t(qfrag_vec16) * 16 : 0) + (tab_doubles + wide_doubles) * 8;
+        return v_bytes + (QLDS ? size_t(qfrag_vec16) * 16 : 0) + (tab_doubles + wide_doubles + iso_doubles) * 8;
     }
 };
 
-template <int D, int P, int NQM, int NQC, int PF, int T, bool MULTI>
-__global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
+// ISO: the isoparametric assembly (X per quadrature node, lane_setup_iso) with
+// the same contraction and reduction; single assemblies in FP64 only.
+template <int D, int P, int NQM, int NQC, int PF, int T, bool MULTI, bool ISO = false>
+__global__ __launch_bounds__(ws_threads(T, ISO)) void fused_ws_kernel(JobTable jt)
 {
     constexpr int NPT = ws_producers(T);
     static_assert(T == 16 * (NPT / 64) || T == 16, "one 16-element group per producer wave, or T = 16");
     using S = Shape<D, P>;
     using ST = typename FormTraits<PF>::stage_t;
     using L = LaneQ<NQM, NQC, S::NG>;
-    using LDS = WsLds<D, P, NQM, NQC, PF, T>;
+    using LDS = WsLds<D, P, NQM, NQC, PF, T, ISO>;
     constexpr bool SPLIT = PF >= QXA_F16X2;
     constexpr bool QLDS = LDS::QLDS;  // else: T = 16, WideProducer, Q^T from global memory
     static_assert(QLDS || !SPLIT, "split forms need Q^T in LDS");
+    static_assert(!ISO || (QLDS && PF == QXA_FP64 && !MULTI && NQM == NQC), "isoparametric kernel: one rule, FP64");
     constexpr int NB = (S::NS + 15) / 16;
     constexpr int KM = NQM, KC = L::NQP * S::NG;  // conductivity K order: k = g * NQP + q
     constexpr int BUF_ELEMS = 2 * S::NS * (T + 1);  // one buffer: [NS][T + 1] pairs (V_m, V_c)
-    constexpr int NCT = ws_consumers(T);
-    constexpr int CH = ws_chunk(D, P);
-    constexpr int NTH = ws_threads(T);
+    constexpr int NCT = ws_consumers(T, ISO);
+    constexpr int CH = ws_chunk(D, P) * (512 / NCT);  // a tile's units in one chunk either way
+    constexpr int NTH = ws_threads(T, ISO);
     extern __shared__ __align__(16) unsigned char smem[];
     ST *sV = reinterpret_cast<ST *>(smem);  // [2 buffers][NS][T + 1][V_m, V_c]
     unsigned char *sQraw = smem + LDS::v_bytes;
@@ -1028,6 +1190,8 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
         }
         for (int k = tid; k < NQM; k += NTH) sWM[k] = a0.in.w_m[k];
         for (int k = tid; k < NQC; k += NTH) sWC[k] = a0.in.w_c[k];
+        if constexpr (ISO)
+            for (int k = tid; k < NQC * S::NP * D; k += NTH) sWC[NQC + k] = a0.dphi[k];
     }
     // a zero pair in the (never written) padding column of row 0 of each buffer
     if (tid < 4) sV[(tid >> 1) * BUF_ELEMS + 2 * T + (tid & 1)] = ST(0);
@@ -1041,7 +1205,7 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
       } else {
         const int j = lane >> 4, c16 = lane & 15;
         int32_t v[S::NP];
-        RawElem<D, P> raw;
+        std::conditional_t<ISO, IsoRaw<D, P>, RawElem<D, P>> raw;
         auto load_conn = [&](int64_t g) {
             int64_t lt;
             const FusedArgs b = args_of<MULTI>(jt, job_of<MULTI>(jt, g, lt));
@@ -1054,7 +1218,10 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
         auto gather = [&](int64_t g) {
             int64_t lt;
             const FusedArgs b = args_of<MULTI>(jt, job_of<MULTI>(jt, g, lt));
-            gather_raw<D, P>(b.in, v, raw);
+            if constexpr (ISO)
+                gather_iso<D, P>(b.in, v, j, raw);
+            else
+                gather_raw<D, P>(b.in, v, raw);
         };
         int64_t g = walk.t;  // every workgroup of a persistent launch has at least one tile
         load_conn(g);
@@ -1066,7 +1233,14 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
             const int64_t ne = a.in.n_elem;
             const int64_t p = tile * T + 16 * wave + c16;  // this lane's element (4 lanes each)
             double A[S::NG], lm[L::MM], lc[L::MC];
-            if (p < ne) {
+            double xiso[ISO ? L::MC : 1][S::NG];  // X_c of the isoparametric kernel
+            if constexpr (ISO) {
+                const bool live = p < ne;
+                const bool by_id = live && (a.in.cm.kind == 2 || a.in.cc.kind == 2 || a.Kq);
+                const int64_t eid = by_id ? int64_t(a.elem_order[p]) : p;
+                if (!lane_setup_iso<D, P, NQM>(a, raw, live, p, eid, j, c16, sPhiM, sWM, sWC + NQC, lm, xiso))
+                    atomicOr(a.in.flags, 1);
+            } else if (p < ne) {
                 const int64_t eid = (a.in.cm.kind == 2 || a.in.cc.kind == 2) ? int64_t(a.elem_order[p]) : p;
                 if (!lane_setup<D, P, NQM, NQC>(a.in, raw, a.tconn, p, eid, j, sPhiM, sPhiC, sWM, sWC, A, lm, lc))
                     atomicOr(a.in.flags, 1);
@@ -1090,7 +1264,12 @@ __global__ __launch_bounds__(ws_threads(T)) void fused_ws_kernel(JobTable jt)
                 const CT *q = reinterpret_cast<const CT *>(sQraw);
                 // k = 4 ks + j: mass node q = k, conductivity (g, q) = divmod(4 ks, NQP) + (0, j)
                 auto xm = [&](int ks) { return lm[ks]; };
-                auto xc = [&](int ks) { return lc[((4 * ks) % L::NQP) / 4] * A[(4 * ks) / L::NQP]; };
+                auto xc = [&](int ks) {
+                    if constexpr (ISO)
+                        return xiso[((4 * ks) % L::NQP) / 4][(4 * ks) / L::NQP];
+                    else
+                        return lc[((4 * ks) % L::NQP) / 4] * A[(4 * ks) / L::NQP];
+                };
                 // a matrix that is not requested is not formed (its staged values are never stored)
                 if (a.M) contract_group_plain<CT, KM, NB, S::NS, T, ST, 2>(q, xm, bVm, lane, 16 * wave);
                 if (a.C)
@@ -1426,6 +1605,42 @@ hipError_t launch_fixup(const FixupTable &ft, hipStream_t st)
     fixup_kernel<<<unsigned((ft.n_fix + 255) / 256), 256, 0, st>>>(ft);
     return hipGetLastError();
 }
+
+// Shapes of the one-pass isoparametric kernel: Q^T staged in LDS, one rule for
+// both matrices (the rule sizes of the default rules).
+#define QXA_ISO_CASES(X) X(2, 2, 6, 6) X(2, 3, 12, 12) X(3, 2, 11, 11)
+
+bool fused_iso_fits(int D, int P, int nqm, int nqc, int64_t qfrag_vec16, int carry_cap)
+{
+#define X(d, p, m, c)                                                                                  \
+    if (D == d && P == p && nqm == m && nqc == c) {                                                   \
+        static_assert(mfma_variant(d, p, m, c) && tile_size(d, p) != 16, "Q^T staged in LDS");        \
+        using LDS = WsLds<d, p, m, c, QXA_FP64, tile_size(d, p), true>;                               \
+        return with_carries(LDS::bytes(qfrag_vec16), carry_cap) <= kLdsBytes;                         \
+    }
+    QXA_ISO_CASES(X)
+#undef X
+    return false;
+}
+
+hipError_t launch_fused_iso(const JobTable &jt, int D, int P, int nqm, int nqc, hipStream_t st)
+{
+    const FusedArgs &a = jt.one;
+    if (jt.n_jobs != 0 || !a.dphi) return hipErrorInvalidValue;
+#define X(d, p, m, c)                                                                                  \
+    if (D == d && P == p && nqm == m && nqc == c) {                                                   \
+        constexpr int T = tile_size(d, p);                                                            \
+        const size_t lds = with_carries(WsLds<d, p, m, c, QXA_FP64, T, true>::bytes(a.qfrag_vec16), a.carry_cap); \
+        if (lds > kLdsBytes) return hipErrorInvalidValue;                                             \
+        auto k = fused_ws_kernel<d, p, m, c, QXA_FP64, T, false, true>;                               \
+        k<<<persistent_grid(k, ws_threads(T, true), lds, jt.n_chains), ws_threads(T, true), lds, st>>>(jt); \
+        return hipGetLastError();                                                                     \
+    }
+    QXA_ISO_CASES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+#undef QXA_ISO_CASES
 #endif
 
 }  // namespace qxa

@@ -371,35 +371,6 @@ hipError_t QXA_PART(launch_load)(const LoadArgs &a, int D, int P, int nq, hipStr
     return hipErrorInvalidValue;
 }
 
-// Inverse and |det| of a d x d matrix (adjugate over the determinant).
-template <int D>
-__device__ __forceinline__ void inverse_abs_det(const double (&B)[D][D], double (&I)[D][D], double &adet)
-{
-    if constexpr (D == 2) {
-        const double det = B[0][0] * B[1][1] - B[0][1] * B[1][0], r = 1.0 / det;
-        I[0][0] = B[1][1] * r;
-        I[0][1] = -B[0][1] * r;
-        I[1][0] = -B[1][0] * r;
-        I[1][1] = B[0][0] * r;
-        adet = fabs(det);
-    } else {
-        const double c00 = B[1][1] * B[2][2] - B[1][2] * B[2][1];
-        const double c01 = B[1][2] * B[2][0] - B[1][0] * B[2][2];
-        const double c02 = B[1][0] * B[2][1] - B[1][1] * B[2][0];
-        const double det = B[0][0] * c00 + B[0][1] * c01 + B[0][2] * c02, r = 1.0 / det;
-        I[0][0] = c00 * r;
-        I[1][0] = c01 * r;
-        I[2][0] = c02 * r;
-        I[0][1] = (B[0][2] * B[2][1] - B[0][1] * B[2][2]) * r;
-        I[1][1] = (B[0][0] * B[2][2] - B[0][2] * B[2][0]) * r;
-        I[2][1] = (B[0][1] * B[2][0] - B[0][0] * B[2][1]) * r;
-        I[0][2] = (B[0][1] * B[1][2] - B[0][2] * B[1][1]) * r;
-        I[1][2] = (B[0][2] * B[1][0] - B[0][0] * B[1][2]) * r;
-        I[2][2] = (B[0][0] * B[1][1] - B[0][1] * B[1][0]) * r;
-        adet = fabs(det);
-    }
-}
-
 // Isoparametric elements (curved geometry, Section 7): M_e and C_e with B, |det B| and
 // A = B^{-1} K B^{-T} evaluated per quadrature node from every node's position, so X
 // holds one column per (q, e): X_m[q] = w_q m_q |det B_q| and X_c[(q, g)] = w_q c_q

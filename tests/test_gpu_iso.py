@@ -173,3 +173,31 @@ def test_per_node_tensor_errors():
     with pytest.raises(qxa.QxaError) as ei:                       # a non-finite entry is reported
         qxa.sync(plan)
     assert ei.value.code == -4
+
+
+@pytest.mark.parametrize("dim,order,N,one_pass", [(2, 2, 13, True), (3, 2, 5, True), (2, 3, 9, False),
+                                                  (3, 3, 3, False), (3, 1, 7, False)])
+def test_iso_path_choice(dim, order, N, one_pass):
+    """One pass (the matrix-core kernel forming X per quadrature node) where the shape's
+    kernel stages Q^T in LDS, one rule serves both matrices and the reference gradients fit
+    beside the plan's carry entries (2D P2, 3D P2); two passes otherwise (2D P3: the carries
+    fill the LDS; 3D P3: Q^T read from global memory; P1: the vector-ALU kernel). Either
+    way the result meets the oracle at 1e-12."""
+    import paper_2204_03893_amd as qxa
+    print("case iso path", dim, order, N, flush=True)
+    mesh = _curved(structured_mesh(dim, order, N, 0.15, seed=[120, dim, order]), 0.02)
+    u = gaussian_random_field(mesh["coords"], 16, np.random.default_rng(121), length=0.3)
+    r = rule(dim, 2 * order)
+    m = qxa.Mesh(dim, order, mesh["coords"], mesh["conn"])
+    plan = qxa.Plan(m, r)
+    uf = torch.tensor(u, device="cuda")
+    law_m, law_c = ("poly2", 1.0, 0.3, 0.0), ("exp", 0.0, 0.5)
+    plan.set_timing(True)
+    M, Cv = qxa.assemble_iso(plan, law_m, law_c, uf, uf)
+    qxa.sync(plan)
+    rep = plan.timing_report()
+    plan.set_timing(False)
+    assert ("fused_iso" in rep) == one_pass and ("iso_rows" in rep) == (not one_pass), rep
+    rpo, _, Mo, Co = oracle.assemble_iso(mesh, r, r, law_m, law_c, u, u)
+    assert row_scaled_error(M.cpu().numpy(), Mo, rpo) <= 1e-12
+    assert row_scaled_error(Cv.cpu().numpy(), Co, rpo) <= 1e-12
