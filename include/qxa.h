@@ -313,8 +313,8 @@ qxa_status qxa_load_vector(qxa_plan plan, const qxa_coeff *f, double *F, void *s
  * X_c per (q, e); Q_m and Q_c unchanged). Same coefficients, outputs and pattern as
  * qxa_assemble, in FP64. One pass where the shape's matrix-core kernel stages Q^T in
  * LDS (2D P2, 2D P3, 3D P2), the plan's mass and stiffness rules are the same rule and
- * the reference gradients fit in LDS beside the plan's carry entries (2D P2 and 3D P2
- * with their default rules): that kernel forms X per quadrature node from the node
+ * the reference gradients fit in LDS beside the plan's carry entries (2D P2, 2D P3 and
+ * 3D P2 with their default rules): that kernel forms X per quadrature node from the node
  * positions and reduces V = Q X through the plan's output units, then the fix-up.
  * Otherwise two passes: the local matrices of every element (X per quadrature node,
  * then V = Q X, once per symmetric pair) to a plan-owned buffer in the plan's tile

@@ -1411,6 +1411,23 @@ bool QXA_PART(fused_base_lds)(int D, int P, int nqm, int nqc, const int64_t (&qv
 }
 
 #ifndef QXA_FUSED_PADDED
+// Shapes of the one-pass isoparametric kernel: Q^T staged in LDS, one rule for
+// both matrices (the rule sizes of the default rules).
+#define QXA_ISO_CASES(X) X(2, 2, 6, 6) X(2, 3, 12, 12) X(3, 2, 11, 11)
+
+// LDS bytes of the isoparametric kernel of a shape (0 if it has none)
+static size_t fused_iso_lds(int D, int P, int nqm, int nqc, int64_t qfrag_vec16)
+{
+#define X(d, p, m, c)                                                                                  \
+    if (D == d && P == p && nqm == m && nqc == c) {                                                   \
+        static_assert(mfma_variant(d, p, m, c) && tile_size(d, p) != 16, "Q^T staged in LDS");        \
+        return WsLds<d, p, m, c, QXA_FP64, tile_size(d, p), true>::bytes(qfrag_vec16);                \
+    }
+    QXA_ISO_CASES(X)
+#undef X
+    return 0;
+}
+
 bool fused_base_lds_padded(int D, int P, int nqm, int nqc, const int64_t (&qv16)[5], size_t &base);
 hipError_t launch_fused_padded(const JobTable &jt, int D, int P, int nqm, int nqc, int precision, hipStream_t st,
                                bool &found);
@@ -1427,6 +1444,10 @@ TileParams fused_tile_params(int D, int P, int nqm, int nqc, int cus, size_t lds
     }
     size_t base = 0;
     if (!fused_base_lds_tuned(D, P, nqm, nqc, qv16, base)) fused_base_lds_padded(D, P, nqm, nqc, qv16, base);
+    // the carry entries leave room for the isoparametric kernel's reference gradients, so
+    // that a plan serves both assemblies (2D P3: 1,296 entries instead of 1,408; its plans
+    // use at most about 900)
+    base = std::max(base, fused_iso_lds(D, P, nqm, nqc, qv16[QXA_FP64]));
     const size_t room = lds_max > with_carries(base, 0) ? lds_max - with_carries(base, 0) : 0;
     tp.carry_cap = int(std::min<size_t>(kMaxCarries, room / 16) / 16 * 16);
     tp.chains = int64_t(std::max(1, cus));  // one workgroup per CU
@@ -1606,21 +1627,10 @@ hipError_t launch_fixup(const FixupTable &ft, hipStream_t st)
     return hipGetLastError();
 }
 
-// Shapes of the one-pass isoparametric kernel: Q^T staged in LDS, one rule for
-// both matrices (the rule sizes of the default rules).
-#define QXA_ISO_CASES(X) X(2, 2, 6, 6) X(2, 3, 12, 12) X(3, 2, 11, 11)
-
 bool fused_iso_fits(int D, int P, int nqm, int nqc, int64_t qfrag_vec16, int carry_cap)
 {
-#define X(d, p, m, c)                                                                                  \
-    if (D == d && P == p && nqm == m && nqc == c) {                                                   \
-        static_assert(mfma_variant(d, p, m, c) && tile_size(d, p) != 16, "Q^T staged in LDS");        \
-        using LDS = WsLds<d, p, m, c, QXA_FP64, tile_size(d, p), true>;                               \
-        return with_carries(LDS::bytes(qfrag_vec16), carry_cap) <= kLdsBytes;                         \
-    }
-    QXA_ISO_CASES(X)
-#undef X
-    return false;
+    const size_t bytes = fused_iso_lds(D, P, nqm, nqc, qfrag_vec16);
+    return bytes > 0 && with_carries(bytes, carry_cap) <= kLdsBytes;
 }
 
 hipError_t launch_fused_iso(const JobTable &jt, int D, int P, int nqm, int nqc, hipStream_t st)

@@ -175,14 +175,15 @@ def test_per_node_tensor_errors():
     assert ei.value.code == -4
 
 
-@pytest.mark.parametrize("dim,order,N,one_pass", [(2, 2, 13, True), (3, 2, 5, True), (2, 3, 9, False),
-                                                  (3, 3, 3, False), (3, 1, 7, False)])
+@pytest.mark.parametrize("dim,order,N,one_pass", [(2, 2, 13, True), (3, 2, 5, True), (2, 3, 9, True),
+                                                  (3, 3, 3, False), (3, 1, 7, False), (2, 1, 23, False)])
 def test_iso_path_choice(dim, order, N, one_pass):
     """One pass (the matrix-core kernel forming X per quadrature node) where the shape's
     kernel stages Q^T in LDS, one rule serves both matrices and the reference gradients fit
-    beside the plan's carry entries (2D P2, 3D P2); two passes otherwise (2D P3: the carries
-    fill the LDS; 3D P3: Q^T read from global memory; P1: the vector-ALU kernel). Either
-    way the result meets the oracle at 1e-12."""
+    beside the plan's carry entries (2D P2, 2D P3, 3D P2); two passes otherwise (3D P3: Q^T
+    read from global memory; P1: the vector-ALU kernel; different mass and stiffness rules,
+    test_iso_qpoint_field_and_lower_degree_rule). Either way the result meets the oracle at
+    1e-12."""
     import paper_2204_03893_amd as qxa
     print("case iso path", dim, order, N, flush=True)
     mesh = _curved(structured_mesh(dim, order, N, 0.15, seed=[120, dim, order]), 0.02)
