@@ -58,6 +58,32 @@ struct Group {
 
 }  // namespace
 
+// Stable LSD radix sort of packed (slot << 32 | low) keys by the slot, in digits
+// of 11 bits over the range of slots present.
+static void radix_sort_by_slot(uint64_t *a, uint64_t *a_end, std::vector<uint64_t> &tmp)
+{
+    const size_t n = size_t(a_end - a);
+    if (n < 2) return;
+    uint32_t lo = UINT32_MAX, hi = 0;
+    for (size_t k = 0; k < n; ++k) {
+        const uint32_t u = uint32_t(a[k] >> 32);
+        lo = std::min(lo, u);
+        hi = std::max(hi, u);
+    }
+    const uint32_t range = hi - lo;
+    const int bits = range ? 32 - __builtin_clz(range) : 0;
+    tmp.resize(n);
+    uint64_t *src = a, *dst = tmp.data();
+    for (int shift = 0; shift < bits; shift += 11) {
+        uint32_t cnt[2049] = {};
+        for (size_t k = 0; k < n; ++k) ++cnt[((uint32_t(src[k] >> 32) - lo) >> shift & 2047u) + 1];
+        for (int d = 0; d < 2048; ++d) cnt[d + 1] += cnt[d];
+        for (size_t k = 0; k < n; ++k) dst[cnt[(uint32_t(src[k] >> 32) - lo) >> shift & 2047u]++] = src[k];
+        std::swap(src, dst);
+    }
+    if (src != a) std::copy(src, src + n, a);
+}
+
 qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, const int32_t *conn,
                            const double *coords, const HostPlan &hp, const TileParams &prm, TilePlan &tp)
 {
@@ -117,6 +143,7 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
     //    plan order within a slot is ascending local element, then pair
     hvec<uint64_t> ent(size_t(n_elem) * ns);
     parallel_for(nt, [&](int64_t a, int64_t b) {
+        std::vector<uint64_t> tmp;
         for (int64_t t = a; t < b; ++t) {
             const int64_t p0 = t * T, p1 = std::min<int64_t>(n_elem, p0 + T);
             uint64_t *out = ent.data() + size_t(p0) * ns;
@@ -129,7 +156,9 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
                     *out++ = (slot << 32) | (ord << 16) | lds;
                 }
             }
-            std::sort(ent.data() + size_t(p0) * ns, out);
+            // entries are written in plan order (ascending ord), so a stable sort by slot
+            // alone gives the (slot, ord) order
+            radix_sort_by_slot(ent.data() + size_t(p0) * ns, out, tmp);
         }
     }, 16);
     auto tile_span = [&](int64_t t, const uint64_t *&b, const uint64_t *&e) {
@@ -341,17 +370,23 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
     std::vector<std::vector<uint32_t>> trec(nt);
     std::vector<int64_t> tpairs(nt, 0), touts(nt, 0), tcin(nt, 0), text(nt, 0), tnone(nt, 0);
     parallel_for(nt, [&](int64_t a, int64_t b) {
-        std::vector<Out> outs, S, L;
+        // outputs by kind: CSR upper slots, CSR mirror slots, carries, partials
+        std::vector<Out> outs, up, mi, ca, pa, S, L;
         std::vector<uint16_t> ents;
         std::vector<const Out *> B, O;  // single outputs of several units, of one unit
         for (int64_t t = a; t < b; ++t) {
-            outs.clear();
+            up.clear();
+            mi.clear();
+            ca.clear();
+            pa.clear();
             ents.clear();
-            auto add = [&](int32_t code, uint8_t kind, int32_t cin, const uint64_t *own, size_t n_own) {
-                outs.push_back(Out{code, kind, uint32_t(n_own + (cin >= 0)), uint32_t(ents.size())});
+            int64_t n_cin = 0;
+            auto add_to = [&](std::vector<Out> &dst, int32_t code, uint8_t kind, int32_t cin, const uint64_t *own,
+                              size_t n_own) {
+                dst.push_back(Out{code, kind, uint32_t(n_own + (cin >= 0)), uint32_t(ents.size())});
                 if (cin >= 0) ents.push_back(uint16_t(cb + uint32_t(cin)));
                 for (size_t m = 0; m < n_own; ++m) ents.push_back(uint16_t(own[m] & 0xffff));
-                tcin[t] += cin >= 0;
+                n_cin += cin >= 0;
             };
             for_slots(t, [&](uint32_t u, const uint64_t *own, const uint64_t *own_end) {
                 int32_t carry;
@@ -360,28 +395,36 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
                 const int32_t mir = int32_t(hp.mirror[u]);
                 switch (r) {
                 case R_OWNED:
-                    add(int32_t(u), 0, -1, own, n_own);
-                    if (mir != int32_t(u)) add(mir, 0, -1, own, n_own);
+                    add_to(up, int32_t(u), 0, -1, own, n_own);
+                    if (mir != int32_t(u)) add_to(mi, mir, 0, -1, own, n_own);
                     break;
-                case R_CARRY_OUT: add(kCodeCarry | carry, 1, -1, own, n_own); break;
-                case R_CARRY_MID: add(kCodeCarry | carry, 1, carry, own, n_own); break;
+                case R_CARRY_OUT: add_to(ca, kCodeCarry | carry, 1, -1, own, n_own); break;
+                case R_CARRY_MID: add_to(ca, kCodeCarry | carry, 1, carry, own, n_own); break;
                 case R_CARRY_CSR:
-                    add(int32_t(u), 0, carry, own, n_own);
-                    if (mir != int32_t(u)) add(mir, 0, carry, own, n_own);
+                    add_to(up, int32_t(u), 0, carry, own, n_own);
+                    if (mir != int32_t(u)) add_to(mi, mir, 0, carry, own, n_own);
                     break;
                 case R_CARRY_PART:
                 case R_PART: {
                     const int32_t p = partial_of(u, int32_t(t));
-                    add(-p - 1, 2, r == R_CARRY_PART ? carry : -1, own, n_own);
+                    add_to(pa, -p - 1, 2, r == R_CARRY_PART ? carry : -1, own, n_own);
                     break;
                 }
                 }
             });
-            // CSR outputs, then carries, then partials (partials ascending: codes descending)
-            std::sort(outs.begin(), outs.end(), [](const Out &x, const Out &y) {
-                if (x.kind != y.kind) return x.kind < y.kind;
-                return x.kind == 2 ? x.code > y.code : x.code < y.code;
-            });
+            tcin[t] = n_cin;
+            // CSR outputs (ascending slot), then carries (ascending code), then partials
+            // (ascending partial index: codes descending). The slots come in ascending
+            // order, and so do the upper slots and the partials (a slot's partials are
+            // numbered in slot order); the mirror slots and the carry codes are sorted,
+            // and the mirrors merged into the upper slots. Every code is distinct.
+            auto by_code = [](const Out &x, const Out &y) { return x.code < y.code; };
+            std::sort(mi.begin(), mi.end(), by_code);
+            std::sort(ca.begin(), ca.end(), by_code);
+            outs.resize(up.size() + mi.size());
+            std::merge(up.begin(), up.end(), mi.begin(), mi.end(), outs.begin(), by_code);
+            outs.insert(outs.end(), ca.begin(), ca.end());
+            outs.insert(outs.end(), pa.begin(), pa.end());
             S.clear();
             L.clear();
             for (const Out &o : outs) (prm.pair_units && o.n <= kPairEntries ? S : L).push_back(o);
@@ -391,6 +434,7 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
             }
             auto &R = trec[t];
             R.clear();
+            R.reserve(4 * (outs.size() + ents.size() / kUnitEntries + kSegLanes));
             const size_t us = S.size() / 2;
             tpairs[t] = int64_t(us);
             touts[t] = int64_t(outs.size());
