@@ -208,6 +208,18 @@ qxa_status qxa_plan_check_host(int dim, int order, int64_t n_nodes, const double
                                const int32_t *conn, const qxa_quad *mass_rule, const qxa_quad *stiff_rule,
                                int64_t chains, int carry_cap, qxa_plan_info *out);
 
+/* Test support for the plan check above (for its callers: the tests that show it
+ * rejects broken plans): the plan qxa_plan_check_host builds (built-in rules), with one
+ * deliberate corruption, then checked. mutation 1: a CSR output retargeted to the slot
+ * of another output of its tile; 2: an entry of an output dropped; 3: an LDS index past
+ * the staged pairs (the first carry entry, which no earlier tile wrote); 4: two outputs' entries exchanged; 5: a partial written twice (and
+ * another never); 6: a fix-up mirror slot changed. Returns the check's status
+ * (QXA_E_INVALID with its message when the corruption is caught), QXA_E_UNSUPPORTED when
+ * the plan has nothing the mutation changes (no pair units, no partials), QXA_E_INVALID
+ * for a mutation outside 1..6. Host only; needs no GPU. */
+qxa_status qxa_plan_check_host_corrupted(int dim, int order, int64_t n_nodes, const double *coords, int64_t n_elem,
+                                         const int32_t *conn, int64_t chains, int carry_cap, int mutation);
+
 /* Copy the CSR pattern into caller-owned device arrays row_ptr[n_nodes+1] and
  * col_idx[nnz] (either may be NULL), asynchronously on `stream`. */
 qxa_status qxa_plan_copy_pattern(qxa_plan plan, int64_t *row_ptr, int32_t *col_idx, void *stream);

@@ -102,6 +102,7 @@ def lib():
         L.qxa_pattern_host.argtypes = [ci, ci, i64, i64, vp, vp, vp, C.POINTER(i64)]
         L.qxa_plan_check_host.argtypes = [ci, ci, i64, vp, i64, vp, C.POINTER(_Quad), C.POINTER(_Quad), i64, ci,
                                           C.POINTER(_PlanInfo)]
+        L.qxa_plan_check_host_corrupted.argtypes = [ci, ci, i64, vp, i64, vp, i64, ci, ci]
         L.qxa_assemble.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), ci, vp, vp, vp]
         L.qxa_element_matrices.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), ci, vp, vp, vp]
         L.qxa_element_matrices_noalloc.argtypes = [vp, C.POINTER(_Coeff), C.POINTER(_Coeff), ci, vp, vp, vp]
@@ -127,7 +128,7 @@ def lib():
         for name in ("qxa_mesh_create", "qxa_mesh_destroy", "qxa_plan_create", "qxa_plan_destroy",
                      "qxa_plan_get_info", "qxa_plan_copy_pattern", "qxa_assemble", "qxa_element_matrices",
                      "qxa_element_matrices_noalloc",
-                     "qxa_sync", "qxa_pattern_host", "qxa_plan_check_host", "qxa_plan_set_timing", "qxa_plan_timing_report", "qxa_graph_create", "qxa_graph_launch",
+                     "qxa_sync", "qxa_pattern_host", "qxa_plan_check_host", "qxa_plan_check_host_corrupted", "qxa_plan_set_timing", "qxa_plan_timing_report", "qxa_graph_create", "qxa_graph_launch",
                      "qxa_graph_destroy", "qxa_server_create", "qxa_server_submit", "qxa_server_poll",
                      "qxa_server_copy_result", "qxa_server_release", "qxa_server_pause", "qxa_server_drop_mesh", "qxa_server_stats",
                      "qxa_server_destroy"):
@@ -338,6 +339,18 @@ def plan_check_host(dim, order, coords, conn, chains=0, carry_cap=-1, rule_m=Non
                                     C.byref(qm[0]) if qm else None, C.byref(qc[0]) if qc else None,
                                     int(chains), int(carry_cap), C.byref(info)))
     return {name: int(getattr(info, name)) for name in _TILE_FIELDS}
+
+
+def plan_check_host_corrupted(dim, order, coords, conn, mutation, chains=0, carry_cap=-1):
+    """Test support for the plan check: the plan of plan_check_host with one deliberate
+    corruption (1 a CSR output retargeted, 2 an entry dropped, 3 an LDS index past the
+    staged pairs, 4 two outputs' entries exchanged, 5 a partial written twice, 6 a fix-up mirror
+    slot changed), then checked. Returns (status, message)."""
+    X = np.ascontiguousarray(coords, dtype=np.float64)
+    conn = np.ascontiguousarray(conn, dtype=np.int32)
+    st = lib().qxa_plan_check_host_corrupted(dim, order, X.shape[1], X.ctypes.data, conn.shape[1], conn.ctypes.data,
+                                             int(chains), int(carry_cap), int(mutation))
+    return st, (lib().qxa_last_error().decode() if st else "")
 
 
 def make_coeff(law, field=None, qpoint=False, tensor=None, tensor_q=None, sizes=None, name="coefficient"):

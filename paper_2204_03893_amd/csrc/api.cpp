@@ -581,9 +581,55 @@ qxa_status qxa_pattern_host(int dim, int order, int64_t n_nodes, int64_t n_elem,
     return QXA_OK;
 }
 
-qxa_status qxa_plan_check_host(int dim, int order, int64_t n_nodes, const double *coords, int64_t n_elem,
-                               const int32_t *conn, const qxa_quad *mass_rule, const qxa_quad *stiff_rule,
-                               int64_t chains, int carry_cap, qxa_plan_info *out)
+// One deliberate corruption of a built tile plan (tests of the plan check):
+// true if the plan has what the mutation needs.
+static bool corrupt_tile_plan(int mutation, int np, TilePlan &tp)
+{
+    const uint32_t T = uint32_t(tp.T), ns = uint32_t(n_sym(np));
+    auto is_csr = [](uint32_t c) { return int32_t(c) >= 0 && int32_t(c) < kCodeCarry; };
+    for (int64_t t = 0; t < tp.n_tiles; ++t) {
+        const int64_t r0 = tp.rec_ptr[t], rm = tp.rec_mid[t];
+        if (rm - r0 < 2) continue;
+        uint32_t *A = &tp.rec[4 * r0], *B = &tp.rec[4 * (r0 + 1)];
+        switch (mutation) {
+        case 1:  // a CSR output retargeted to the slot of another output of the tile
+            if (!is_csr(A[0]) || !is_csr(B[0])) continue;
+            A[0] = B[0];
+            return true;
+        case 2:  // an entry of an output dropped (marked absent)
+            if ((A[1] & 0xffffu) == T) continue;
+            A[1] = (A[1] & 0xffff0000u) | T;
+            return true;
+        case 3:  // an LDS index past the staged pairs
+            A[1] = (A[1] & 0xffff0000u) | (ns * (T + 1));
+            return true;
+        case 4:  // two outputs' entries exchanged
+            if ((A[1] & 0xffffu) == (B[1] & 0xffffu)) continue;
+            std::swap(A[1], B[1]);
+            return true;
+        default: break;
+        }
+    }
+    if (mutation == 5 && tp.n_partials > 1) {  // a partial written twice, another never
+        for (int64_t r = 0; r + 1 < int64_t(tp.rec.size() / 4); ++r) {
+            uint32_t *R = &tp.rec[4 * r];
+            const int32_t c = int32_t(R[0]);
+            if (c < 0) {
+                R[0] = uint32_t(c == -1 ? -2 : -1);
+                return true;
+            }
+        }
+    }
+    if (mutation == 6 && tp.n_shared > 0) {  // a fix-up mirror slot pointing elsewhere
+        tp.fix_mirror[0] = tp.fix_mirror[0] == 0 ? 1 : 0;
+        return true;
+    }
+    return false;
+}
+
+static qxa_status plan_check_host_impl(int dim, int order, int64_t n_nodes, const double *coords, int64_t n_elem,
+                                       const int32_t *conn, const qxa_quad *mass_rule, const qxa_quad *stiff_rule,
+                                       int64_t chains, int carry_cap, int mutation, qxa_plan_info *out)
 {
     if (!coords || (n_elem > 0 && !conn)) return fail(QXA_E_INVALID, "null argument");
     if ((dim != 2 && dim != 3) || order < 1 || order > 3 || n_nodes < 1 || n_elem < 0)
@@ -609,6 +655,8 @@ qxa_status qxa_plan_check_host(int dim, int order, int64_t n_nodes, const double
     if (st) return st;
     TilePlan tp;
     st = build_tile_plan(dim, order, n_nodes, n_elem, conn, coords, hp, prm, tp);
+    if (!st && mutation && !corrupt_tile_plan(mutation, np, tp))
+        return fail(QXA_E_UNSUPPORTED, "plan check: the plan has nothing this mutation changes");
     if (!st) st = check_tile_plan(np, n_elem, hp, tp);
     if (st) return st;
     if (out) {
@@ -626,6 +674,22 @@ qxa_status qxa_plan_check_host(int dim, int order, int64_t n_nodes, const double
         tile_plan_stats(tp, *out);
     }
     return QXA_OK;
+}
+
+qxa_status qxa_plan_check_host(int dim, int order, int64_t n_nodes, const double *coords, int64_t n_elem,
+                               const int32_t *conn, const qxa_quad *mass_rule, const qxa_quad *stiff_rule,
+                               int64_t chains, int carry_cap, qxa_plan_info *out)
+{
+    return plan_check_host_impl(dim, order, n_nodes, coords, n_elem, conn, mass_rule, stiff_rule, chains, carry_cap, 0,
+                                out);
+}
+
+qxa_status qxa_plan_check_host_corrupted(int dim, int order, int64_t n_nodes, const double *coords, int64_t n_elem,
+                                         const int32_t *conn, int64_t chains, int carry_cap, int mutation)
+{
+    if (mutation < 1 || mutation > 6) return fail(QXA_E_INVALID, "plan check: mutation is 1..6");
+    return plan_check_host_impl(dim, order, n_nodes, coords, n_elem, conn, nullptr, nullptr, chains, carry_cap,
+                                mutation, nullptr);
 }
 
 qxa_status qxa_quad_builtin(int dim, int degree, qxa_quad *out)

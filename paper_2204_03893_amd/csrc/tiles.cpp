@@ -722,21 +722,30 @@ qxa_status check_tile_plan(int np, int64_t n_elem, const HostPlan &hp, const Til
     }, 2);
 
     if (bad.load()) return fail(QXA_E_INVALID, why);
-    for (int64_t k = 0; k < tp.n_partials; ++k)
-        if (part_ws[k] != 1) return fail(QXA_E_INVALID, "tile plan: partial not written exactly once");
-    for (int64_t k = 0; k < tp.n_shared; ++k) {
-        const int32_t u = tp.fix_target[k], m = tp.fix_mirror[k];
-        if (k > 0 && u <= tp.fix_target[k - 1]) return fail(QXA_E_INVALID, "tile plan: fix-up not sorted");
-        if (u < 0 || u >= nnz || m < 0 || m >= nnz || hp.mirror[u] != uint32_t(m))
-            return fail(QXA_E_INVALID, "tile plan: bad fix-up slot");
-        if (tp.part_ptr[k + 1] <= tp.part_ptr[k]) return fail(QXA_E_INVALID, "tile plan: shared slot without partials");
-        uint64_t acc = 0;
-        for (int64_t q = tp.part_ptr[k]; q < tp.part_ptr[k + 1]; ++q) acc += part[q];
-        if (!write_once(slot_ws[u])) return fail(QXA_E_INVALID, "tile plan: fix-up slot written twice");
-        if (m != u && !write_once(slot_ws[m])) return fail(QXA_E_INVALID, "tile plan: fix-up mirror written twice");
-        if (acc != expected(u) || (m != u && acc != expected(m)))
-            return fail(QXA_E_INVALID, "tile plan: slot sum differs from the element entries");
-    }
+    parallel_for(tp.n_partials, [&](int64_t a, int64_t b) {
+        for (int64_t k = a; k < b; ++k)
+            if (part_ws[k] != 1) {
+                flag("tile plan: partial not written exactly once");
+                return;
+            }
+    });
+    if (bad.load()) return fail(QXA_E_INVALID, why);
+    parallel_for(tp.n_shared, [&](int64_t a, int64_t b) {
+        for (int64_t k = a; k < b && !bad.load(); ++k) {
+            const int32_t u = tp.fix_target[k], m = tp.fix_mirror[k];
+            if (k > 0 && u <= tp.fix_target[k - 1]) return flag("tile plan: fix-up not sorted");
+            if (u < 0 || u >= nnz || m < 0 || m >= nnz || hp.mirror[u] != uint32_t(m))
+                return flag("tile plan: bad fix-up slot");
+            if (tp.part_ptr[k + 1] <= tp.part_ptr[k]) return flag("tile plan: shared slot without partials");
+            uint64_t acc = 0;
+            for (int64_t q = tp.part_ptr[k]; q < tp.part_ptr[k + 1]; ++q) acc += part[q];
+            if (!write_once(slot_ws[u])) return flag("tile plan: fix-up slot written twice");
+            if (m != u && !write_once(slot_ws[m])) return flag("tile plan: fix-up mirror written twice");
+            if (acc != expected(u) || (m != u && acc != expected(m)))
+                return flag("tile plan: slot sum differs from the element entries");
+        }
+    });
+    if (bad.load()) return fail(QXA_E_INVALID, why);
     std::atomic<bool> unwritten{false};
     parallel_for(nnz, [&](int64_t a, int64_t b) {
         for (int64_t u = a; u < b; ++u)

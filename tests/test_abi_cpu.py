@@ -163,3 +163,17 @@ def test_builtin_rule_tables_are_generated():
     path = os.path.join(os.path.dirname(qxa.__file__), "csrc", "rules_builtin.cpp")
     with open(path) as f:
         assert f.read() == gen_rules.render()
+
+
+@pytest.mark.parametrize("dim,order,N,chains", [(2, 2, 12, 8), (2, 3, 10, 0), (3, 2, 4, 0), (3, 1, 6, 0)])
+@pytest.mark.parametrize("mutation", [1, 2, 3, 4, 5, 6])
+def test_plan_check_rejects_corrupted_plans(dim, order, N, chains, mutation):
+    """The host plan check (which every qxa_plan_create runs before anything reaches the
+    GPU) rejects a plan with one deliberate corruption: a doubly written slot, a dropped
+    or exchanged entry, an out-of-range LDS index, a doubly written partial, a wrong
+    fix-up mirror. The uncorrupted plan of the same mesh passes."""
+    mesh = structured_mesh(dim, order, N, 0.2, seed=[131, dim, order])
+    qxa.plan_check_host(dim, order, mesh["coords"], mesh["conn"], chains=chains)
+    st, msg = qxa.plan_check_host_corrupted(dim, order, mesh["coords"], mesh["conn"], mutation, chains=chains)
+    assert st == -1, (st, msg)  # QXA_E_INVALID
+    assert msg.startswith("tile plan:"), msg
