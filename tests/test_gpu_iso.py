@@ -202,3 +202,36 @@ def test_iso_path_choice(dim, order, N, one_pass):
     rpo, _, Mo, Co = oracle.assemble_iso(mesh, r, r, law_m, law_c, u, u)
     assert row_scaled_error(M.cpu().numpy(), Mo, rpo) <= 1e-12
     assert row_scaled_error(Cv.cpu().numpy(), Co, rpo) <= 1e-12
+
+
+@pytest.mark.parametrize("dim,order,N", [(2, 2, 11), (3, 2, 4), (2, 3, 7)])
+def test_iso_one_pass_qpoint_and_second_field(dim, order, N):
+    """The one-pass isoparametric kernel with a per-(q, e) mass coefficient, then with
+    different nodal fields for the mass and the conductivity (the second one read through
+    the element's connectivity), against the oracle at 1e-12."""
+    import paper_2204_03893_amd as qxa
+    print("case iso one pass qpoint / second field", dim, order, N, flush=True)
+    mesh = _curved(structured_mesh(dim, order, N, 0.1, seed=[140, dim, order]), 0.03)
+    r = rule(dim, 2 * order)
+    ne = mesh["conn"].shape[1]
+    m = qxa.Mesh(dim, order, mesh["coords"], mesh["conn"])
+    plan = qxa.Plan(m, r)
+    s = np.random.default_rng(141).uniform(0.5, 2.0, size=(len(r[1]), ne))
+    plan.set_timing(True)
+    M, Cv = qxa.assemble_iso(plan, ("poly2", 0.0, 1.0, 0.0), ("const", 1.7), torch.tensor(s, device="cuda"), None,
+                             qpoint=True)
+    qxa.sync(plan)
+    rep = plan.timing_report()
+    plan.set_timing(False)
+    assert "fused_iso" in rep, rep
+    rpo, _, Mo, Co = oracle.assemble_iso(mesh, r, r, ("poly2", 0.0, 1.0, 0.0), ("const", 1.7), qpoint_m=s)
+    assert row_scaled_error(M.cpu().numpy(), Mo, rpo) <= 1e-12
+    assert row_scaled_error(Cv.cpu().numpy(), Co, rpo) <= 1e-12
+    u = gaussian_random_field(mesh["coords"], 16, np.random.default_rng(142), length=0.3)
+    v = gaussian_random_field(mesh["coords"], 16, np.random.default_rng(143), length=0.2)
+    law_m, law_c = ("poly2", 1.0, 0.3, 0.0), ("exp", 0.0, 0.5)
+    M2, C2 = qxa.assemble_iso(plan, law_m, law_c, torch.tensor(u, device="cuda"), torch.tensor(v, device="cuda"))
+    qxa.sync(plan)
+    rpo, _, Mo2, Co2 = oracle.assemble_iso(mesh, r, r, law_m, law_c, u, v)
+    assert row_scaled_error(M2.cpu().numpy(), Mo2, rpo) <= 1e-12
+    assert row_scaled_error(C2.cpu().numpy(), Co2, rpo) <= 1e-12
