@@ -935,7 +935,9 @@ static qxa_status build_slot_entries(qxa_plan p)
     for (int64_t e = 0; e < ne; ++e)
         for (int a = 0; a < np; ++a)
             for (int b = 0; b < np; ++b) items[size_t(fill[slot(e, a, b)]++)] = int32_t((e * np + a) * np + b);
-    st = plan_upload_buf(p, &p->d_ns_ptr, ptr.data(), ptr.size());
+    // offsets below 2^31 (checked above): 4 bytes per slot for the gather to read
+    const std::vector<int32_t> ptr32(ptr.begin(), ptr.end());
+    st = plan_upload_buf(p, &p->d_ns_ptr, ptr32.data(), ptr32.size());
     if (!st) st = plan_upload_buf(p, &p->d_ns_items, items.data(), items.size());
     if (st) plan_drop(p, &p->d_ns_ptr, &p->d_ns_items);
     return st;
@@ -958,7 +960,8 @@ static qxa_status build_node_entries(qxa_plan p)
     std::vector<int32_t> items(static_cast<size_t>(ptr[nn]));
     for (int64_t e = 0; e < ne; ++e)
         for (int a = 0; a < np; ++a) items[size_t(fill[conn[size_t(a) * ne + e]]++)] = int32_t(a * ne + e);
-    qxa_status st = plan_upload_buf(p, &p->d_nf_ptr, ptr.data(), ptr.size());
+    const std::vector<int32_t> ptr32(ptr.begin(), ptr.end());  // below 2^31 (checked above)
+    qxa_status st = plan_upload_buf(p, &p->d_nf_ptr, ptr32.data(), ptr32.size());
     if (!st) st = plan_upload_buf(p, &p->d_nf_items, items.data(), items.size());
     if (!st) st = plan_alloc(p, &p->d_Fe, size_t(np) * ne);
     if (st) plan_drop(p, &p->d_nf_ptr, &p->d_nf_items, &p->d_Fe);

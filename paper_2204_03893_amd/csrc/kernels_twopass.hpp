@@ -61,7 +61,7 @@ struct IsoArgs {
 
 struct SlotGatherArgs {
     int64_t n_slots;
-    const int64_t *ptr;    // [n_slots + 1]
+    const int32_t *ptr;    // [n_slots + 1] (entries below 2^31)
     const int32_t *items;  // indices into src
     const double *src;
     double *out;           // [n_slots]

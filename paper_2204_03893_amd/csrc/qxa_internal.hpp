@@ -311,12 +311,12 @@ struct qxa_plan_s {
     // and, per CSR slot (both triangles), its element entries (index into d_T) in
     // ascending element order
     double *d_T = nullptr;
-    int64_t *d_ns_ptr = nullptr;  // [nnz + 1]
+    int32_t *d_ns_ptr = nullptr;  // [nnz + 1]
     int32_t *d_ns_items = nullptr;
     // load vector (built on first use): element vectors [np][n_elem] and, per node,
     // its element entries in ascending element order
     double *d_Fe = nullptr;
-    int64_t *d_nf_ptr = nullptr;  // [n_nodes + 1]
+    int32_t *d_nf_ptr = nullptr;  // [n_nodes + 1]
     int32_t *d_nf_items = nullptr;
     int *d_flags = nullptr;       // device status flags (non-finite)
     size_t device_bytes = 0;
