@@ -57,6 +57,10 @@ WORKLOADS = {
     "p1_3d_96_heat": Workload("p1_3d_96_heat", 4, 3, 1, 96, 0.2, 2, ("poly2", 1.0, 0.1, 0.0), ("poly2", 1.0, 0.0, 1.0),
                                "heat", "3D P1 Kuhn tets on 96^3 cube (5,308,416 elements), c(u)=1+u^2, "
                                "m(u)=1+0.1u, 20 reassemblies with smooth increments of size 0.05"),
+    # the 3D P3 shape (16-element tiles, Q^T read from L2): its precision forms and fix-up share
+    "p3_3d_36": Workload("p3_3d_36", 6, 3, 3, 36, 0.2, 6, ("const", 1.0), ("poly2", 1.0, 0.0, 0.5), "sinusoids8",
+                          "3D P3 Kuhn tets on 36^3 cube (279,936 elements), jitter 0.2h, 24-point rule, "
+                          "c(u)=1+0.5u^2, u = sum of 8 random-phase sinusoids"),
 }
 
 
