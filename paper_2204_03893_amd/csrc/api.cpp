@@ -648,7 +648,10 @@ static qxa_status plan_check_host_impl(int dim, int order, int64_t n_nodes, cons
     int64_t qv16[5];
     for (int f = 0; f < 5; ++f) qv16[f] = int64_t(frag[f].size() / 16);
     TileParams prm = fused_tile_params(dim, order, T.nq_m, T.nq_c, 256, size_t(160) * 1024, qv16);
-    if (chains > 0) prm.chains = chains;
+    if (chains > 0) {  // an explicit chain count: runs of consecutive tiles, no run layout
+        prm.chains = chains;
+        prm.run_len = 0;
+    }
     if (carry_cap >= 0) prm.carry_cap = std::min(carry_cap, 65535);
     HostPlan hp;
     st = build_host_plan(dim, order, n_nodes, n_elem, conn, hp);

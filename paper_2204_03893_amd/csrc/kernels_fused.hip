@@ -1379,6 +1379,7 @@ static size_t with_carries(size_t bytes, int carry_cap) { return ((bytes + 15) &
 
 constexpr int kMaxCarries = 4096;
 constexpr int kMinCarries = 1024;
+constexpr int kMinRunCarries = 128;
 
 template <int D, int P>
 static size_t p1_lds_bytes()
@@ -1452,10 +1453,15 @@ TileParams fused_tile_params(int D, int P, int nqm, int nqc, int cus, size_t lds
     tp.carry_cap = int(std::min<size_t>(kMaxCarries, room / 16) / 16 * 16);
     tp.chains = int64_t(std::max(1, cus));  // one workgroup per CU
     if (tp.carry_cap < kMinCarries) {
-        // too few carry entries to pay for walking tiles one after another (3D P2: 272,
-        // 3D P3: 896): tiles side by side instead, every shared slot through a partial
-        tp.carry_cap = 0;
-        tp.chains = int64_t(1) << 40;
+        // too few carry entries for long chains (3D P2: 272, 3D P3: 896): chains of short
+        // runs, the workgroups of one XCD on neighbouring runs at the same time
+        // (build_tile_plan), the slots a run's tiles share through carry entries
+        if (tp.carry_cap >= kMinRunCarries) {
+            tp.run_len = tp.carry_cap >= 512 ? 4 : 2;
+        } else {  // tiles side by side, every shared slot through a partial
+            tp.carry_cap = 0;
+            tp.chains = int64_t(1) << 40;
+        }
     }
     return tp;
 }

@@ -174,6 +174,9 @@ struct TileParams {
     int64_t chains = 256;  // chains (workgroups of one launch) the tiles are split into
     int carry_cap = 0;     // LDS carry entries of a workgroup
     bool pair_units = true;
+    // > 1: chains of runs of run_len consecutive tiles, one chain per workgroup, the
+    // workgroups of one XCD on neighbouring runs at the same time (build_tile_plan)
+    int run_len = 0;
 };
 
 struct TilePlan {

@@ -125,16 +125,59 @@ qxa_status build_tile_plan(int dim, int order, int64_t n_nodes, int64_t n_elem, 
     });
     key.clear();
     key.shrink_to_fit();
+    // Runs (carry entries too few for long chains: 3D P2, 3D P3). The full tiles are
+    // renumbered so that chain c = (XCD x, workgroup i) = (c / W, c % W), W = chains / 8,
+    // holds from every row of W L consecutive Morton tiles of XCD x's eighth the run of L
+    // tiles i L .. i L + L - 1. The workgroups of one XCD then work on one row at a time
+    // (neighbouring tiles at the same time, as in the side-by-side walk, so that their
+    // writes to shared CSR lines meet in that XCD's L2), and each passes the slots its
+    // run's tiles share through carry entries. A partial last tile stays last (in the
+    // last chain). Too few tiles for a run per workgroup: one-tile chains.
+    const int64_t nfull = n_elem / T;
+    const bool runs = prm.run_len > 1 && prm.chains >= 8 && prm.chains % 8 == 0 &&
+                      nfull >= prm.chains * int64_t(prm.run_len) && nt > 0;
+    std::vector<int64_t> run_chain_len;
+    if (runs) {
+        const int64_t W = prm.chains / 8, L = prm.run_len;
+        std::vector<int64_t> order;  // new tile -> Morton tile
+        order.reserve(size_t(nfull));
+        run_chain_len.assign(size_t(prm.chains), 0);
+        for (int64_t x = 0; x < 8; ++x) {
+            const int64_t x0 = x * nfull / 8, n = (x + 1) * nfull / 8 - x0;
+            for (int64_t i = 0; i < W; ++i)
+                for (int64_t r = 0; r * W * L < n; ++r)
+                    for (int64_t l = 0; l < L; ++l) {
+                        const int64_t m = r * W * L + i * L + l;
+                        if (m >= n) break;
+                        order.push_back(x0 + m);
+                        ++run_chain_len[size_t(x * W + i)];
+                    }
+        }
+        if (nt > nfull) ++run_chain_len.back();  // the partial tile
+        hvec<int32_t> eo(n_elem);
+        parallel_for(nfull, [&](int64_t a, int64_t b) {
+            for (int64_t t = a; t < b; ++t)
+                std::copy(tp.elem_order.begin() + order[t] * T, tp.elem_order.begin() + (order[t] + 1) * T,
+                          eo.begin() + t * T);
+        });
+        std::copy(tp.elem_order.begin() + nfull * T, tp.elem_order.end(), eo.begin() + nfull * T);
+        tp.elem_order.swap(eo);
+    }
     tp.tconn.resize(size_t(np) * n_elem);
     parallel_for(n_elem, [&](int64_t a, int64_t b) {
         for (int64_t p = a; p < b; ++p)
             for (int i = 0; i < np; ++i)
                 tp.tconn[size_t(i) * n_elem + p] = conn[size_t(i) * n_elem + tp.elem_order[p]];
     });
-    // 2. chains: nc balanced runs of consecutive tiles
-    const int64_t nc = nt == 0 ? 0 : std::max<int64_t>(1, std::min<int64_t>(nt, prm.chains));
+    // 2. chains: nc balanced runs of consecutive tiles (or the runs above; with run_len > 1
+    //    and too few tiles for them, one-tile chains)
+    const int64_t nc = nt == 0 ? 0
+                       : runs ? prm.chains
+                       : prm.run_len > 1 ? nt
+                              : std::max<int64_t>(1, std::min<int64_t>(nt, prm.chains));
     tp.chain_ptr.assign(nc + 1, 0);
-    for (int64_t c = 1; c <= nc; ++c) tp.chain_ptr[c] = c * nt / nc;
+    for (int64_t c = 1; c <= nc; ++c)
+        tp.chain_ptr[c] = runs ? tp.chain_ptr[c - 1] + run_chain_len[size_t(c - 1)] : c * nt / nc;
     std::vector<int32_t> chain_of(nt);
     for (int64_t c = 0; c < nc; ++c)
         for (int64_t t = tp.chain_ptr[c]; t < tp.chain_ptr[c + 1]; ++t) chain_of[t] = int32_t(c);

@@ -177,3 +177,18 @@ def test_plan_check_rejects_corrupted_plans(dim, order, N, chains, mutation):
     st, msg = qxa.plan_check_host_corrupted(dim, order, mesh["coords"], mesh["conn"], mutation, chains=chains)
     assert st == -1, (st, msg)  # QXA_E_INVALID
     assert msg.startswith("tile plan:"), msg
+
+
+def test_tile_plan_runs_on_3d_p3():
+    """3D P3 (896 carry entries, too few for long chains): one chain per workgroup made of
+    4-tile runs, the workgroups of one XCD on neighbouring runs. The plan passes the host
+    execution check, uses carries, and has fewer partials than one-tile chains; a mesh with
+    too few tiles for a run per workgroup gets one-tile chains."""
+    mesh = structured_mesh(3, 3, 14, 0.2, seed=[150, 3, 3])
+    s = qxa.plan_check_host(3, 3, mesh["coords"], mesh["conn"])
+    assert s["n_chains"] == 256 and s["carry_cap"] == 896 and s["n_carry_reads"] > 0, s
+    one = qxa.plan_check_host(3, 3, mesh["coords"], mesh["conn"], chains=s["n_tiles"], carry_cap=0)
+    assert s["n_partials"] < 0.9 * one["n_partials"], (s["n_partials"], one["n_partials"])
+    small = structured_mesh(3, 3, 6, 0.2, seed=[151, 3, 3])
+    t = qxa.plan_check_host(3, 3, small["coords"], small["conn"])
+    assert t["n_chains"] == t["n_tiles"] and t["n_carry_reads"] == 0, t

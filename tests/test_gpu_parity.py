@@ -43,6 +43,36 @@ def _run(w, precision="fp64", reps=1, stream_id=0):
     return mesh, r, u, plan, rp.cpu().numpy(), ci.cpu().numpy(), outs
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_3d_p3_run_chains_against_oracle(precision):
+    """3D P3 on a mesh with enough tiles for the run layout (one chain of 4-tile runs per
+    workgroup, carries between a run's tiles): against the oracle, run-to-run bitwise,
+    bitwise symmetric."""
+    qxa = _qxa()
+    from workloads.fields import gaussian_random_field
+    dim, order, N = 3, 3, 14
+    _say("case 3D P3 runs", N, precision)
+    mesh = structured_mesh(dim, order, N, 0.2, seed=[9, dim, order])
+    u = gaussian_random_field(mesh["coords"], 16, np.random.default_rng([10, dim, order]), length=0.3)
+    r = rule(dim, 2 * order)
+    law_m, law_c = ("poly2", 1.0, 0.1, 0.0), ("exp", 0.0, 1.0)
+    plan = qxa.Plan(qxa.Mesh(dim, order, mesh["coords"], mesh["conn"]), r)
+    assert plan.n_chains == 256 and plan.n_carry_reads > 0
+    uf = torch.tensor(u, device="cuda")
+    M, Cv = qxa.assemble(plan, law_m, law_c, uf, uf, precision=precision)
+    M2, C2 = qxa.assemble(plan, law_m, law_c, uf, uf, precision=precision)
+    qxa.sync(plan)
+    rpo, cio, Mo, Co = oracle.assemble(mesh, r, r, law_m, law_c, u, u)
+    tol = 1e-12 if precision == "fp64" else FORM_BOUNDS["fp32"]
+    assert row_scaled_error(M.cpu().numpy(), Mo, rpo) <= tol
+    assert row_scaled_error(Cv.cpu().numpy(), Co, rpo) <= tol
+    assert torch.equal(M.view(torch.int64), M2.view(torch.int64))
+    assert torch.equal(Cv.view(torch.int64), C2.view(torch.int64))
+    t = transpose_slots(rpo, cio)
+    Mh, Ch = M.cpu().numpy(), Cv.cpu().numpy()
+    assert np.array_equal(Mh, Mh[t]) and np.array_equal(Ch, Ch[t])
+
+
 SMALL = [("p1_2d_64", None), ("p2_3d_32", 6), ("p3_2d_1024", 24), ("p1_3d_96_heat", 10)]
 
 
