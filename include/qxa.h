@@ -381,7 +381,9 @@ qxa_status qxa_graph_destroy(qxa_graph graph);
  *   the resident plans. The budget is one device allocation made at creation;
  *   nothing in the serving loop allocates or frees device memory. A job that
  *   does not fit waits until released results or evicted plans make room;
- *   QXA_E_NOMEM only when it cannot fit even in an otherwise empty budget.
+ *   when only its own plan is left and the plan's buffers split the free
+ *   space, the plan is rebuilt into the empty budget; QXA_E_NOMEM only when it
+ *   cannot fit even in an otherwise empty budget.
  * - Plans (pattern, permutation, tiles, reference tables) stay resident in an
  *   LRU cache keyed by mesh and rule pair: only S changes between assemblies
  *   of one mesh (Section 5, summary), so a cache hit skips the plan build.

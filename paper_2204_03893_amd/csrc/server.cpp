@@ -144,6 +144,7 @@ struct Job {
     int batched = 0;
     double run_ms = 0.0;
     bool polled = false;
+    int replans = 0;  // times its plan was rebuilt to free a contiguous range
     // copies of the result queued by qxa_server_copy_result on callers' streams:
     // release waits for them before the buffer returns to the budget
     std::vector<hipEvent_t> copies;
@@ -324,8 +325,23 @@ static bool admit(qxa_server s)
         // nothing will be released: plans that other waiting jobs need go too
         while (!buf && s->holders == 0 && evict_one(s, true, ce)) buf = s->arena.alloc(need);
         if (!buf) {
-            // it can never fit if no job holds memory and its plan is all that is left
+            // no job holds memory and its plan is all that is left
             if (s->holders == 0 && s->arena.used() <= p->device_bytes) {
+                // It would fit an empty budget, but the plan's buffers split the free space:
+                // the plan goes and is rebuilt into the empty budget, where its buffers lie
+                // together and leave one free range (a few times per job: another plan
+                // built meanwhile can split the space again).
+                if (j->replans < 4 && ce->refs == 0 && DevArena::granule(need) + p->device_bytes <= s->arena.capacity()) {
+                    ++j->replans;
+                    for (Job *q : s->queue)
+                        if (q->entry == ce) q->entry = nullptr;
+                    qxa_plan_destroy(ce->plan);
+                    s->cache.erase(ce->key);
+                    ++s->n_evictions;
+                    s->cv_mem.notify_all();
+                    progress = true;
+                    continue;  // the job looks its plan up again and waits for the rebuild
+                }
                 finish_job(s, j, QXA_E_NOMEM, "job buffers exceed the device budget");
                 it = s->queue.erase(it);
                 progress = true;

@@ -297,3 +297,40 @@ def test_jobs_submitted_mid_flight_match_alone_bitwise():
     for mo in new_meshes:
         srv.drop_mesh(mo)
     srv.close()
+
+
+def test_run_plans_batched_match_alone_bitwise():
+    """3D P3 plans with runs (one chain of 4-tile runs per workgroup) batched into one
+    launch: 768 chains on 256 workgroups, each walking three chains one after another.
+    Every job is bitwise equal to the same job assembled alone, and matches the oracle."""
+    import paper_2204_03893_amd as qxa
+    srv = qxa.Server(max_inflight=8, n_streams=1, batch_tile_limit=1 << 20, hbm_budget=8 << 30)
+    srv.pause(True)
+    m = _mesh(3, 3, 14, seed=160)
+    mo = qxa.Mesh(3, 3, m["coords"], m["conn"])
+    r = rule(3, 6)
+    jobs = {}
+    for k in range(3):
+        u = torch.tensor(_field(m, 161 + k), device="cuda")
+        jobs[srv.submit(mo, r, r, LAW_M, LAW_C, u, u, precision="fp64", tag=k)] = u
+    print("submitted 3D P3 run-plan jobs", flush=True)
+    srv.pause(False)
+    done = srv.wait(len(jobs))
+    assert all(c["status"] == 0 for c in done), [c["message"] for c in done if c["status"]]
+    assert srv.stats()["max_batch"] > 1
+    for i, c in enumerate(done):
+        u = jobs[c["ticket"]]
+        Ms, Cs = srv.result(c["ticket"])
+        plan, Ma, Ca = _alone(qxa, mo, r, u)
+        assert plan.n_chains == 256 and plan.n_carry_reads > 0
+        torch.cuda.synchronize()
+        assert torch.equal(Ms.view(torch.int64), Ma.view(torch.int64))
+        assert torch.equal(Cs.view(torch.int64), Ca.view(torch.int64))
+        if i == 0:
+            uh = u.cpu().numpy()
+            rp, ci, Mo, Co = oracle.assemble(m, r, r, LAW_M, LAW_C, uh, uh)
+            assert row_scaled_error(Ms.cpu().numpy(), Mo, rp) <= 1e-12
+            assert row_scaled_error(Cs.cpu().numpy(), Co, rp) <= 1e-12
+        srv.release(c["ticket"])
+        plan.close()
+    srv.close()
